@@ -1,0 +1,323 @@
+"""CPU oracle for the CountSketch -> multisketch -> sketch-and-solve path.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark are the only callers.  The product library never imports,
+links or runs anything in this directory, and this directory imports nothing
+from the product package.
+
+The arithmetic lives in ``oracle.c`` (plain C, built with
+``-O2 -ffp-contract=off -fno-fast-math``); this module only marshals NumPy
+arrays (column-major, i.e. Fortran order) into it.  Each wrapper names the
+passage of the paper (Higgins, Boman, Yamazaki, arXiv 2508.14209) it follows.
+
+Parity pins: every function here is pinned by ``tests/test_oracle_*.py``
+against values fixed by the paper's definitions and by mathematics (dense-S
+brute force, invariants, closed forms, special cases, LAPACK cross-checks);
+nothing here is "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+# A test that plants a mistake in the oracle points this at a mutant build.
+_LIB_PATH = os.environ.get("MSKETCH_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+
+OK, ERR_ARG, ERR_RANGE, ERR_NOMEM, ERR_SINGULAR = 0, 1, 2, 3, 4
+
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99", "-fPIC",
+          "-shared"]
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so next to it (gcc, no FMA contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", *CFLAGS, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+_i64 = ctypes.c_int64
+_p = ctypes.c_void_p
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        sig = {
+            "or_countsketch_f64": [_i64, _i64, _i64, _p, _i64, _p, _p, _p, _i64],
+            "or_countsketch_f32": [_i64, _i64, _i64, _p, _i64, _p, _p, _p, _i64],
+            "or_countsketch_f32_acc64": [_i64, _i64, _i64, _p, _i64, _p, _p, _p, _i64],
+            "or_bucket_hist": [_i64, _i64, _p, _p],
+            "or_bucket_plan": [_i64, _i64, _p, _p, _p],
+            "or_gemm_f64": [_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64],
+            "or_householder_qr": [_i64, _i64, _p, _i64, _p],
+            "or_apply_qt": [_i64, _i64, _i64, _p, _i64, _p, _p, _i64],
+            "or_trsv_upper": [_i64, _i64, _p, _i64, _p, _i64],
+            "or_qr_solve": [_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64],
+            "or_normal_equations": [_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64],
+            "or_sketch_lstsq_f64": [_i64, _i64, _i64, _i64, _i64, _p, _i64, _p,
+                                    _i64, _p, _p, _p, _i64, _p, _i64, _p, _p],
+            "or_sketch_lstsq_f32": [_i64, _i64, _i64, _i64, _i64, _p, _i64, _p,
+                                    _i64, _p, _p, _p, _i64, ctypes.c_int, _p,
+                                    _i64, _p, _p],
+            "or_round_bf16": [ctypes.c_float],
+        }
+        for name, args in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        lib.or_gemm_f64.restype = None
+        lib.or_householder_qr.restype = None
+        lib.or_apply_qt.restype = None
+        lib.or_round_bf16.restype = ctypes.c_float
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _fortran(a, dtype):
+    a = np.asarray(a)
+    if a.ndim == 1:
+        a = a.reshape(-1, 1)
+    return np.asfortranarray(a, dtype=dtype)
+
+
+def _ld(a: np.ndarray) -> int:
+    return max(1, a.shape[0])
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__("%s failed with oracle status %d" % (what, code))
+        self.code = code
+
+
+def _check(code: int, what: str):
+    if code != OK:
+        raise OracleError(code, what)
+
+
+# --------------------------------------------------------------------------
+# CountSketch: Def. 3, Eq. (2), Alg. 2
+# --------------------------------------------------------------------------
+
+def countsketch(A, h, s, k: int, acc: str | None = None) -> np.ndarray:
+    """Y = S A, S the CountSketch with buckets h (0-based) and signs s (+-1).
+
+    Canonical fold: for each bucket, rows are added in ascending row order
+    starting from +0.0, in the accumulation precision (A's own precision unless
+    ``acc='f64'`` for an FP32 A).  Def. 3 and Eq. (2); the add-or-subtract form
+    of Alg. 2.
+    """
+    A = np.asarray(A)
+    lib = _load()
+    h = np.ascontiguousarray(h, dtype=np.int32)
+    s = np.ascontiguousarray(s, dtype=np.int8)
+    if A.dtype == np.float64:
+        A = _fortran(A, np.float64)
+        d, n = A.shape
+        Y = np.zeros((k, n), dtype=np.float64, order="F")
+        rc = lib.or_countsketch_f64(d, n, k, _ptr(A), _ld(A), _ptr(h), _ptr(s),
+                                    _ptr(Y), max(1, k))
+    elif A.dtype == np.float32 and acc == "f64":
+        A = _fortran(A, np.float32)
+        d, n = A.shape
+        Y = np.zeros((k, n), dtype=np.float64, order="F")
+        rc = lib.or_countsketch_f32_acc64(d, n, k, _ptr(A), _ld(A), _ptr(h),
+                                          _ptr(s), _ptr(Y), max(1, k))
+    elif A.dtype == np.float32:
+        A = _fortran(A, np.float32)
+        d, n = A.shape
+        Y = np.zeros((k, n), dtype=np.float32, order="F")
+        rc = lib.or_countsketch_f32(d, n, k, _ptr(A), _ld(A), _ptr(h), _ptr(s),
+                                    _ptr(Y), max(1, k))
+    else:
+        raise TypeError("countsketch oracle takes float64 or float32 A")
+    if h.shape[0] != d or s.shape[0] != d:
+        raise ValueError("h and s must have one entry per row of A")
+    _check(rc, "countsketch")
+    return Y
+
+
+def bucket_hist(h, k: int) -> np.ndarray:
+    """cnt[m] = #{i : h[i] = m} (the row counts of the buckets of Def. 3)."""
+    h = np.ascontiguousarray(h, dtype=np.int32)
+    cnt = np.zeros(k, dtype=np.int64)
+    _check(_load().or_bucket_hist(h.shape[0], k, _ptr(h), _ptr(cnt)),
+           "bucket_hist")
+    return cnt
+
+
+def bucket_plan(h, k: int):
+    """(off, perm): exclusive scan of the bucket counts (k+1 entries) and the
+    stable counting-sort permutation (rows of each bucket in ascending order)."""
+    h = np.ascontiguousarray(h, dtype=np.int32)
+    off = np.zeros(k + 1, dtype=np.int64)
+    perm = np.zeros(max(1, h.shape[0]), dtype=np.int64)
+    _check(_load().or_bucket_plan(h.shape[0], k, _ptr(h), _ptr(off), _ptr(perm)),
+           "bucket_plan")
+    return off, perm[: h.shape[0]]
+
+
+# --------------------------------------------------------------------------
+# Gaussian stage: Sec. 1 (multisketch S2(S1 x)), Table 1
+# --------------------------------------------------------------------------
+
+def gemm(G, Y) -> np.ndarray:
+    """Z = G Y in FP64, each entry folded in ascending inner index from +0.0."""
+    G = _fortran(G, np.float64)
+    Y = _fortran(Y, np.float64)
+    M, K = G.shape
+    K2, N = Y.shape
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    Z = np.zeros((M, N), dtype=np.float64, order="F")
+    _load().or_gemm_f64(M, N, K, _ptr(G), _ld(G), _ptr(Y), _ld(Y), _ptr(Z),
+                        max(1, M))
+    return Z
+
+
+# --------------------------------------------------------------------------
+# Householder QR, Q^T application, triangular solve: Alg. 1 steps 2-3;
+# GeQRF + OrMQR + TRSV as the paper runs them (Sec. 6.1, 6.3)
+# --------------------------------------------------------------------------
+
+def householder_qr(W):
+    """Return (F, tau): F holds R in its upper triangle and the Householder
+    vectors (unit leading entry implied) below it, LAPACK geqr2 convention."""
+    F = np.array(_fortran(W, np.float64), order="F", copy=True)
+    m, n = F.shape
+    tau = np.zeros(max(1, n), dtype=np.float64)
+    _load().or_householder_qr(m, n, _ptr(F), _ld(F), _ptr(tau))
+    return F, tau[:n]
+
+
+def apply_qt(F, tau, B) -> np.ndarray:
+    """Q^T B using the reflectors stored in F (what OrMQR computes)."""
+    F = _fortran(F, np.float64)
+    m, n = F.shape
+    Bc = np.array(_fortran(B, np.float64), order="F", copy=True)
+    tau = np.ascontiguousarray(tau, dtype=np.float64)
+    _load().or_apply_qt(m, n, Bc.shape[1], _ptr(F), _ld(F), _ptr(tau), _ptr(Bc),
+                        _ld(Bc))
+    return Bc
+
+
+def trsv_upper(R, B) -> np.ndarray:
+    """X with R X = B for the upper triangle of R (n x n); B is n x nrhs."""
+    R = _fortran(R, np.float64)
+    X = np.array(_fortran(B, np.float64), order="F", copy=True)
+    rc = _load().or_trsv_upper(R.shape[1], X.shape[1], _ptr(R), _ld(R), _ptr(X),
+                               _ld(X))
+    _check(rc, "trsv_upper")
+    return X
+
+
+def qr_solve(W, B) -> np.ndarray:
+    """X = R^{-1} (Q^T B)_{0:n} with [Q,R] = qr(W,0) (Alg. 1 steps 2-3)."""
+    W = _fortran(W, np.float64)
+    B = _fortran(B, np.float64)
+    m, n = W.shape
+    X = np.zeros((n, B.shape[1]), dtype=np.float64, order="F")
+    rc = _load().or_qr_solve(m, n, B.shape[1], _ptr(W), _ld(W), _ptr(B), _ld(B),
+                             _ptr(X), max(1, n))
+    _check(rc, "qr_solve")
+    return X
+
+
+def lstsq_qr(A, B) -> np.ndarray:
+    """The FP64 least-squares optimum x_t = argmin ||B - A x|| by Householder
+    QR of the full A (comparator for the residual ratio)."""
+    return qr_solve(A, B)
+
+
+def normal_equations(A, B) -> np.ndarray:
+    """FP64 normal equations (Sec. 6.3): Gram A^T A, A^T b, Cholesky R^T R,
+    then R^T y = A^T b and R x = y.  Raises OracleError(ERR_SINGULAR) when the
+    Cholesky factorisation breaks down."""
+    A = _fortran(A, np.float64)
+    B = _fortran(B, np.float64)
+    d, n = A.shape
+    X = np.zeros((n, B.shape[1]), dtype=np.float64, order="F")
+    rc = _load().or_normal_equations(d, n, B.shape[1], _ptr(A), _ld(A), _ptr(B),
+                                     _ld(B), _ptr(X), max(1, n))
+    _check(rc, "normal_equations")
+    return X
+
+
+# --------------------------------------------------------------------------
+# Composite multisketch sketch-and-solve (Alg. 1 with S = G C)
+# --------------------------------------------------------------------------
+
+def sketch_lstsq(A, B, h, s, G, k: int, y_bf16: bool = False):
+    """X = argmin ||G C (B - A X)|| via Alg. 1 with the multisketch S = G C.
+
+    FP64 A: CountSketch in FP64.  FP32 A: CountSketch in FP32, optional RNE
+    rounding of the sketch to BF16 (``y_bf16``), Gaussian stage and QR in
+    FP64 on the exact FP64 images of the stored values.  G is passed as its
+    stored values (float64, float32 or BF16 values held in float32/float64).
+    Returns (X, Y, Z): solution n x nrhs, CountSketch k x (n+nrhs) and the
+    Gaussian-stage output k2 x (n+nrhs).
+    """
+    A = np.asarray(A)
+    lib = _load()
+    h = np.ascontiguousarray(h, dtype=np.int32)
+    s = np.ascontiguousarray(s, dtype=np.int8)
+    Gd = _fortran(G, np.float64)
+    k2 = Gd.shape[0]
+    if Gd.shape[1] != k:
+        raise ValueError("G must be k2 x k")
+    if A.dtype == np.float64:
+        A = _fortran(A, np.float64)
+        B = _fortran(B, np.float64)
+        d, n = A.shape
+        nrhs = B.shape[1]
+        X = np.zeros((n, nrhs), dtype=np.float64, order="F")
+        Y = np.zeros((k, n + nrhs), dtype=np.float64, order="F")
+        Z = np.zeros((k2, n + nrhs), dtype=np.float64, order="F")
+        rc = lib.or_sketch_lstsq_f64(d, n, nrhs, k, k2, _ptr(A), _ld(A), _ptr(B),
+                                     _ld(B), _ptr(h), _ptr(s), _ptr(Gd), _ld(Gd),
+                                     _ptr(X), max(1, n), _ptr(Y), _ptr(Z))
+    elif A.dtype == np.float32:
+        A = _fortran(A, np.float32)
+        B = _fortran(B, np.float32)
+        d, n = A.shape
+        nrhs = B.shape[1]
+        X = np.zeros((n, nrhs), dtype=np.float64, order="F")
+        Y = np.zeros((k, n + nrhs), dtype=np.float32, order="F")
+        Z = np.zeros((k2, n + nrhs), dtype=np.float64, order="F")
+        rc = lib.or_sketch_lstsq_f32(d, n, nrhs, k, k2, _ptr(A), _ld(A), _ptr(B),
+                                     _ld(B), _ptr(h), _ptr(s), _ptr(Gd), _ld(Gd),
+                                     1 if y_bf16 else 0, _ptr(X), max(1, n),
+                                     _ptr(Y), _ptr(Z))
+    else:
+        raise TypeError("sketch_lstsq oracle takes float64 or float32 A")
+    if rc == ERR_SINGULAR:
+        return X, Y, Z
+    _check(rc, "sketch_lstsq")
+    return X, Y, Z
+
+
+def round_bf16(x) -> np.ndarray:
+    """Round FP32 values to BF16 (RNE), returned as the FP32 values they are."""
+    lib = _load()
+    x = np.asarray(x, dtype=np.float32)
+    flat = x.reshape(-1)
+    out = np.empty_like(flat)
+    for i in range(flat.shape[0]):
+        out[i] = lib.or_round_bf16(float(flat[i]))
+    return out.reshape(x.shape)

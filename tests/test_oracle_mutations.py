@@ -1,0 +1,91 @@
+"""Planted mistakes in the oracle must be caught by its pins.
+
+Each case copies ``oracle/oracle.c``, plants one plausible mistake (a dropped
+sign, a wrong index, a transposed operand, a reversed fold, a broken sign
+convention, ...), builds the mutant on the CPU and runs the oracle pin suite
+against it in a subprocess: the suite has to fail.  This checks that the pins
+are strong enough to tell a wrong oracle from the right one.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+# (name, original text, mutated text, which occurrence (0-based) to change)
+MUTANTS = [
+    ("cs64_sign_dropped", "Y[m + c * ldy] = Y[m + c * ldy] + (s[i] > 0 ? a : -a);",
+     "Y[m + c * ldy] = Y[m + c * ldy] + a;", 0),
+    ("cs32_sign_flipped", "Y[m + c * ldy] = Y[m + c * ldy] + (s[i] > 0 ? a : -a);",
+     "Y[m + c * ldy] = Y[m + c * ldy] + (s[i] < 0 ? a : -a);", 1),
+    ("cs64_fold_reversed", "for (int64_t i = 0; i < d; ++i) {\n    const int64_t m = h[i];",
+     "for (int64_t i = d - 1; i >= 0; --i) {\n    const int64_t m = h[i];", 0),
+    ("cs64_bucket_shift", "const int64_t m = h[i];", "const int64_t m = (h[i] + 1) % k;", 0),
+    ("cs64_init_neg_zero", "for (int64_t m = 0; m < k; ++m) Y[m + c * ldy] = +0.0;",
+     "for (int64_t m = 0; m < k; ++m) Y[m + c * ldy] = -0.0;", 0),
+    ("hist_skip_first_row", "for (int64_t i = 0; i < d; ++i) cnt[h[i]] += 1;",
+     "for (int64_t i = 1; i < d; ++i) cnt[h[i]] += 1;", 0),
+    ("plan_unstable", "for (int64_t i = 0; i < d; ++i) perm[cnt[h[i]]++] = i;",
+     "for (int64_t i = d - 1; i >= 0; --i) perm[cnt[h[i]]++] = i;", 0),
+    ("gemm_transposed_G", "acc = acc + G[p + m * ldg] * Y[m + c * ldy];",
+     "acc = acc + G[m + p * ldg] * Y[m + c * ldy];", 0),
+    ("gemm_dropped_term", "for (int64_t m = 0; m < K; ++m)\n        acc = acc + G",
+     "for (int64_t m = 1; m < K; ++m)\n        acc = acc + G", 0),
+    ("qr_sign_convention", "const double beta = alpha >= 0.0 ? -norm : norm;",
+     "const double beta = alpha >= 0.0 ? norm : -norm;", 0),
+    ("qr_update_without_tau", "      w = w * tau[j];\n      cc[j] = cc[j] - w;",
+     "      cc[j] = cc[j] - w;", 0),
+    ("qt_skips_leading_one", "double w = bc[j];", "double w = 0.0;", 0),
+    ("trsv_transposed", "acc = acc - R[i + j * ldr] * x[j];", "acc = acc - R[j + i * ldr] * x[j];", 0),
+    ("ne_forward_wrong_index", "acc = acc - Gm[t + i * n] * x[t];", "acc = acc - Gm[i + t * n] * x[t];", 0),
+    ("composite_rhs_offset", "st = or_countsketch_f64(d, nrhs, k, B, ldb, h, s, Y + n * k, k);",
+     "st = or_countsketch_f64(d, nrhs, k, B, ldb, h, s, Y + (n - 1) * k, k);", 0),
+    ("bf16_ties_away", "u = u + 0x7fffu + lsb;", "u = u + 0x8000u + 0 * lsb;", 0),
+]
+
+
+def _mutate(src: str, old: str, new: str, occ: int) -> str:
+    idx = -1
+    for _ in range(occ + 1):
+        idx = src.find(old, idx + 1)
+        assert idx >= 0, "mutation anchor not found: %r" % old
+    return src[:idx] + new + src[idx + len(old):]
+
+
+def _run_mutant(args):
+    name, old, new, occ, tmp = args
+    src = open(SRC).read()
+    mdir = os.path.join(tmp, name)
+    os.makedirs(mdir)
+    mc = os.path.join(mdir, "oracle.c")
+    with open(mc, "w") as f:
+        f.write(_mutate(src, old, new, occ))
+    with open(os.path.join(mdir, "oracle.h"), "w") as f:
+        f.write(open(os.path.join(ROOT, "oracle", "oracle.h")).read())
+    lib = os.path.join(mdir, "liboracle.so")
+    subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
+                           "-fPIC", "-shared", mc, "-o", lib, "-lm"])
+    env = dict(os.environ, MSKETCH_ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_countsketch.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_solve.py")],
+                       env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    return name, r.returncode, r.stdout[-600:]
+
+
+def test_every_planted_mistake_is_caught():
+    src = open(SRC).read()
+    for name, old, new, occ in MUTANTS:
+        assert src.count(old) > occ, name
+    with tempfile.TemporaryDirectory() as tmp:
+        jobs = [(n, o, w, k, tmp) for (n, o, w, k) in MUTANTS]
+        with ThreadPoolExecutor(max(1, min(6, (os.cpu_count() or 2) - 1))) as ex:
+            results = list(ex.map(_run_mutant, jobs))
+    survivors = [(n, out) for (n, rc, out) in results if rc == 0]
+    assert not survivors, "mutants not caught by the oracle pins: %s" % survivors
+    assert all(rc == 1 for (_, rc, _) in results), [(n, rc) for (n, rc, _) in results]
