@@ -1,0 +1,234 @@
+/*
+ * msketch.h -- C ABI of the MI355X (gfx950) CountSketch / multisketch /
+ * sketch-and-solve least-squares library (libmsketch.so).
+ *
+ * Method: Higgins, Boman, Yamazaki, "A High Performance GPU CountSketch
+ * Implementation and Its Application to Multisketching and Least Squares
+ * Problems" (arXiv 2508.14209).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers owned by the caller.  The library
+ *    allocates no memory on any call; scratch space comes from the caller's
+ *    workspace `ws` of `ws_bytes` bytes, sized by ms_workspace_size() and
+ *    aligned to 256 bytes.
+ *  - Matrices are column-major with a leading dimension (LAPACK style):
+ *    element (i, j) of M is M[i + j*ldm], ldm >= number of rows.
+ *  - The CountSketch S (k x d) of Def. 3 is given by a bucket map h (int32,
+ *    0-based, h[i] in [0,k); the paper numbers buckets 1..k) and a sign s
+ *    (int8, +1 or -1; the paper's boolean of Alg. 2 with true meaning +1).
+ *    Column i of S is s[i] * e_{h[i]}.  S is never scaled.
+ *  - The Gaussian stage matrix G (k2 x k) has N(0, 1/k2) entries (Sec. 1,
+ *    variance 1/k2) and is passed in; h, s and G are data, so every result is
+ *    reproducible from the seed that drew them.
+ *  - Outputs are overwritten (accumulation starts from +0.0).
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL is the null stream)
+ *    and runs asynchronously.  Argument errors are returned before anything
+ *    is enqueued.  Errors found on the device (a bucket index outside [0,k),
+ *    a sign that is not +-1, a zero or non-finite diagonal of R, a sorted-mode
+ *    bucket longer than MS_SORTED_MAX_SEGMENT rows) are recorded in a status
+ *    word at the start of `ws` and returned by ms_check_status().  After such
+ *    an error the outputs' contents are unspecified, except that a singular
+ *    R leaves X filled with NaN.
+ *  - Calls that share a workspace must be ordered (same stream or explicit
+ *    synchronisation): the workspace is overwritten by every call.
+ *  - Nothing throws across the ABI.
+ */
+#ifndef MSKETCH_H
+#define MSKETCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MS_OK = 0,
+  MS_ERR_ARG = 1,         /* invalid argument, detected on the host */
+  MS_ERR_RANGE = 2,       /* h outside [0,k) or s not in {+1,-1} (device) */
+  MS_ERR_NOMEM = 3,       /* workspace smaller than ms_workspace_size() */
+  MS_ERR_SINGULAR = 4,    /* R has a zero or non-finite diagonal (device) */
+  MS_ERR_DEVICE = 5,      /* a HIP runtime call or kernel launch failed */
+  MS_ERR_UNSUPPORTED = 6  /* valid but unsupported combination or size */
+} ms_status;
+
+typedef enum { MS_F64 = 0, MS_F32 = 1, MS_BF16 = 2 } ms_dtype;
+
+/* How the CountSketch sum of Eq. (2) is formed on the device. */
+typedef enum {
+  MS_CS_AUTO = 0,   /* MS_CS_LDS */
+  MS_CS_ATOMIC = 1, /* Alg. 2 as written: one global atomic add per element.
+                       Measured baseline only. */
+  MS_CS_LDS = 2,    /* coalesced streaming of A, per-workgroup bucket partial
+                       sums in LDS, one flush per workgroup.  Summation order
+                       varies from run to run. */
+  MS_CS_SORTED = 3  /* deterministic: rows grouped by bucket by a stable
+                       counting sort, each bucket folded in ascending row order
+                       from +0.0 -- bit-identical to the sequential reading of
+                       Alg. 2 */
+} ms_cs_mode;
+
+/* Longest bucket (rows sharing one h value) MS_CS_SORTED accepts. */
+#define MS_SORTED_MAX_SEGMENT 16384
+
+typedef struct {
+  int32_t cs_mode;      /* ms_cs_mode */
+  int32_t refine_steps; /* sketch_lstsq: FP64-residual refinement steps */
+  int32_t reserved0;
+  int32_t reserved1;
+} ms_opts;
+
+/* op codes of ms_workspace_size() */
+#define MS_OP_BUCKET_PLAN 0
+#define MS_OP_COUNTSKETCH 1
+#define MS_OP_GAUSSIAN 2
+#define MS_OP_MULTISKETCH 3
+#define MS_OP_QR_SOLVE 4
+#define MS_OP_LSTSQ 5
+
+/*
+ * Bytes of workspace the operation needs (a multiple of 256, at least 256).
+ * Arguments not used by `op` are ignored.  opts may be NULL (defaults).
+ * Returns 0 for invalid arguments.
+ */
+size_t ms_workspace_size(int op, int64_t d, int64_t n, int64_t nrhs, int64_t k,
+                         int64_t k2, ms_dtype a_dtype, ms_dtype g_dtype,
+                         const ms_opts *opts);
+
+/*
+ * Synchronises `stream` and returns the device-side status recorded by the
+ * last call that used `ws` (MS_OK if none).  The only entry point that blocks.
+ */
+ms_status ms_check_status(const void *ws, void *stream);
+
+/* Human-readable name of a status code (static string). */
+const char *ms_status_string(ms_status st);
+
+/*
+ * Sketch plan (bucket histogram, exclusive scan, stable counting sort).
+ * The paper notes that the parallel fold of Alg. 2 needs atomic row
+ * additions (Sec. 4); the plan instead groups rows by bucket.
+ *   cnt[m]  = #{i : h[i] = m}                      (k entries, int32)
+ *   off[m]  = cnt[0] + ... + cnt[m-1], off[k] = d  (k+1 entries, int32)
+ *   perm    = the rows of bucket 0, then of bucket 1, ..., each group in
+ *             ascending row order                  (d entries, int32)
+ * Requires 0 <= d < 2^31, 1 <= k < 2^31.  h out of range -> MS_ERR_RANGE on
+ * the device.  ws: ms_workspace_size(MS_OP_BUCKET_PLAN, d, 0, 0, k, ...).
+ */
+ms_status ms_bucket_plan(int64_t d, int64_t k, const int32_t *h, int32_t *cnt,
+                         int32_t *off, int32_t *perm, void *ws, size_t ws_bytes,
+                         void *stream);
+
+/*
+ * Packed sketch: validates (h, s) and stores one 32-bit word per row,
+ *   code[i] = h[i] | (s[i] == -1 ? 0x80000000 : 0),
+ * reusable by every countsketch_accumulate() call with the same sketch (the
+ * CountSketch of Def. 3 is fixed once r and sigma are drawn).  Requires
+ * 1 <= k < 2^31.  A row with h outside [0,k) or s not +-1 records
+ * MS_ERR_RANGE on the device and is packed as bucket 0 with sign +1.
+ * ws: any workspace of at least 256 bytes (only the status word is used).
+ */
+ms_status ms_pack_sketch(int64_t d, int64_t k, const int32_t *h, const int8_t *s,
+                         uint32_t *code, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Streaming accumulation Y += S A with a packed sketch (code from
+ * ms_pack_sketch).  Y is NOT cleared, so a sketch of a tall matrix can be
+ * built block of rows by block of rows, as the row-block sum
+ * C A = sum_i C^(i) A^(i) of Sec. 7 (pass the codes of each block's rows).
+ *   A: d x n (F64 or F32), lda >= max(1,d); Y: k x n (same dtype), ldy >= k.
+ * opts->cs_mode: MS_CS_AUTO/MS_CS_LDS or MS_CS_ATOMIC; MS_CS_SORTED returns
+ * MS_ERR_UNSUPPORTED (its fixed fold order starts from +0.0).  A code whose
+ * bucket is >= k is skipped and recorded as MS_ERR_RANGE.
+ * ws: ms_workspace_size(MS_OP_COUNTSKETCH, ...) suffices.
+ */
+ms_status countsketch_accumulate(int64_t d, int64_t n, int64_t k, ms_dtype a_dtype,
+                                 const void *A, int64_t lda, const uint32_t *code, void *Y,
+                                 int64_t ldy, const ms_opts *opts, void *ws,
+                                 size_t ws_bytes, void *stream);
+
+/*
+ * CountSketch Y = S A (Def. 3, Eq. (2), Alg. 2).
+ *   A: d x n, a_dtype MS_F64 or MS_F32, lda >= max(1,d).
+ *   Y: k x n, same dtype as A, ldy >= k.  Accumulation is in A's precision.
+ *   h, s: d entries each (see the conventions above).
+ * opts->cs_mode selects the variant; MS_CS_SORTED reproduces the ascending
+ * row fold bit for bit.  d may be 0 (Y = 0).  n may be 0 (no-op).
+ */
+ms_status countsketch_apply(int64_t d, int64_t n, int64_t k, ms_dtype a_dtype,
+                            const void *A, int64_t lda, const int32_t *h,
+                            const int8_t *s, void *Y, int64_t ldy,
+                            const ms_opts *opts, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/*
+ * Gaussian stage alone: Z = G Y (the second sketch of the multisketch
+ * S2(S1 x), Sec. 1; k2 x k times k x ncols).
+ *   (g_dtype, y_dtype) = (F64, F64): FP64 MFMA, Z is FP64.
+ *                        (F32, F32): FP32 MFMA, Z is FP32.
+ *                        (BF16, F32): Y rounded to BF16 (round to nearest
+ *                        even), BF16 MFMA with FP32 accumulation, Z is FP32.
+ *   G: k2 x k (BF16 is passed as its 16-bit patterns), ldg >= k2.
+ *   Y: k x ncols, ldy >= k.   Z: k2 x ncols, ldz >= k2.
+ */
+ms_status ms_gaussian_apply(int64_t k, int64_t ncols, int64_t k2,
+                            ms_dtype g_dtype, const void *G, int64_t ldg,
+                            ms_dtype y_dtype, const void *Y, int64_t ldy,
+                            void *Z, int64_t ldz, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/*
+ * Multisketch Z = G (S A) (Sec. 1; Table 1 "MultiSketch"), always in that
+ * association: the CountSketch first, then the Gaussian stage.
+ *   a_dtype F64 -> g_dtype F64, Z FP64;  a_dtype F32 -> g_dtype F32 or BF16,
+ *   Z FP32.  Z: k2 x n, ldz >= k2.  Requires k2 >= 1.
+ */
+ms_status multisketch_apply(int64_t d, int64_t n, int64_t k, int64_t k2,
+                            ms_dtype a_dtype, const void *A, int64_t lda,
+                            const int32_t *h, const int8_t *s, ms_dtype g_dtype,
+                            const void *G, int64_t ldg, void *Z, int64_t ldz,
+                            const ms_opts *opts, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/*
+ * Householder QR least squares of a small system (Alg. 1 steps 2-3, done in
+ * the paper with GeQRF + OrMQR + a triangular solve, Sec. 6.1 and 6.3):
+ *   [Q,R] = qr(W,0) with W m x n (m >= n), X = R^{-1} (Q^T Bm)_{0:n}.
+ * FP64 throughout, LAPACK geqr2 reflector convention.
+ *   W: m x n, ldw >= m.  Bm: m x nrhs, ldb >= m.  X: n x nrhs, ldx >= n.
+ *   R: optional (may be NULL) n x n output of the triangular factor, ldr >= n
+ *   (its strictly lower part is set to 0).
+ * A zero or non-finite R diagonal -> MS_ERR_SINGULAR (device) and X = NaN.
+ */
+ms_status ms_qr_solve(int64_t m, int64_t n, int64_t nrhs, const double *W,
+                      int64_t ldw, const double *Bm, int64_t ldb, double *X,
+                      int64_t ldx, double *R, int64_t ldr, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/*
+ * Multisketch sketch-and-solve least squares (Alg. 1 with S = G C):
+ *   X = argmin || G C (B - A X) ||,  A d x n, B d x nrhs, X n x nrhs (FP64).
+ * Steps: Y = C [A | B] (CountSketch, A's precision); Z = G Y (Gaussian stage,
+ * MFMA in the precision of g_dtype); Householder QR of Z_A (k2 x n, FP64);
+ * Q^T applied to Z_B; back substitution.
+ *   a_dtype F64: g_dtype F64.   a_dtype F32: g_dtype F32 or BF16.
+ *   Requires d >= 1, n >= 1, nrhs >= 1, k >= 1, k2 >= n.
+ * opts->refine_steps > 0 (FP32 A only) then repeats, in FP64,
+ *   r = B - A X;  X += R^{-1} Q^T G (C r)
+ * with the Q and R of the first pass.
+ */
+ms_status sketch_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k,
+                       int64_t k2, ms_dtype a_dtype, const void *A, int64_t lda,
+                       const void *B, int64_t ldb, const int32_t *h,
+                       const int8_t *s, ms_dtype g_dtype, const void *G,
+                       int64_t ldg, double *X, int64_t ldx,
+                       const ms_opts *opts, void *ws, size_t ws_bytes,
+                       void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSKETCH_H */

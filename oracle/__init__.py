@@ -72,6 +72,7 @@ def _load():
                                     _i64, _p, _p, _p, _i64, ctypes.c_int, _p,
                                     _i64, _p, _p],
             "or_round_bf16": [ctypes.c_float],
+            "or_round_bf16_array": [_i64, _p, _p],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -81,6 +82,7 @@ def _load():
         lib.or_householder_qr.restype = None
         lib.or_apply_qt.restype = None
         lib.or_round_bf16.restype = ctypes.c_float
+        lib.or_round_bf16_array.restype = None
         _lib = lib
     return _lib
 
@@ -316,8 +318,8 @@ def round_bf16(x) -> np.ndarray:
     """Round FP32 values to BF16 (RNE), returned as the FP32 values they are."""
     lib = _load()
     x = np.asarray(x, dtype=np.float32)
-    flat = x.reshape(-1)
+    order = "F" if x.flags.f_contiguous and not x.flags.c_contiguous else "C"
+    flat = np.ascontiguousarray(x.reshape(-1, order=order))
     out = np.empty_like(flat)
-    for i in range(flat.shape[0]):
-        out[i] = lib.or_round_bf16(float(flat[i]))
-    return out.reshape(x.shape)
+    lib.or_round_bf16_array(flat.shape[0], _ptr(flat), _ptr(out))
+    return out.reshape(x.shape, order=order)

@@ -392,6 +392,11 @@ float or_round_bf16(float x) {
   return r;
 }
 
+/* Element-wise or_round_bf16 over an array. */
+void or_round_bf16_array(int64_t count, const float *x, float *out) {
+  for (int64_t i = 0; i < count; ++i) out[i] = or_round_bf16(x[i]);
+}
+
 /*
  * FP32 data path of the same composite: Y = C [A | B] folded in FP32; when
  * y_bf16 is non-zero Y is rounded to BF16 (RNE) before the Gaussian stage;

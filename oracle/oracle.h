@@ -45,6 +45,7 @@ int or_sketch_lstsq_f64(int64_t d, int64_t n, int64_t nrhs, int64_t k,
                         const int8_t *s, const double *G, int64_t ldg,
                         double *X, int64_t ldx, double *Ys, double *Zs);
 float or_round_bf16(float x);
+void or_round_bf16_array(int64_t count, const float *x, float *out);
 int or_sketch_lstsq_f32(int64_t d, int64_t n, int64_t nrhs, int64_t k,
                         int64_t k2, const float *A, int64_t lda,
                         const float *B, int64_t ldb, const int32_t *h,

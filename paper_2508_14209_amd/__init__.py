@@ -1,0 +1,337 @@
+"""msketch: MI355X-native CountSketch, multisketch and sketch-and-solve least
+squares (Higgins, Boman, Yamazaki, arXiv 2508.14209).
+
+Thin Python binding of the C ABI in ``include/msketch.h`` (``libmsketch.so``):
+every function here only checks shapes, takes device pointers, leading
+dimensions and the current HIP stream from torch tensors, and calls the entry
+point of the same name.  All arithmetic runs in the library's HIP kernels.
+There is no CPU fallback: importing this module without the built library
+raises.
+
+Matrices are column-major (``t.stride(0) == 1``); ``empty_colmajor`` makes
+such tensors.  BF16 Gaussian matrices are ``torch.bfloat16`` tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+__all__ = [
+    "MS_OK", "MS_ERR_ARG", "MS_ERR_RANGE", "MS_ERR_NOMEM", "MS_ERR_SINGULAR",
+    "MS_ERR_DEVICE", "MS_ERR_UNSUPPORTED", "MsketchError", "LIB_PATH",
+    "empty_colmajor", "colmajor", "workspace", "workspace_size", "check_status",
+    "bucket_plan", "pack_sketch", "countsketch_accumulate", "countsketch_apply",
+    "gaussian_apply", "multisketch_apply", "qr_solve", "sketch_lstsq",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmsketch.so")
+
+MS_OK, MS_ERR_ARG, MS_ERR_RANGE, MS_ERR_NOMEM, MS_ERR_SINGULAR, MS_ERR_DEVICE, \
+    MS_ERR_UNSUPPORTED = range(7)
+MS_F64, MS_F32, MS_BF16 = 0, 1, 2
+MODES = {"auto": 0, "atomic": 1, "lds": 2, "sorted": 3}
+OPS = {"bucket_plan": 0, "countsketch": 1, "gaussian": 2, "multisketch": 3,
+       "qr_solve": 4, "lstsq": 5}
+MS_SORTED_MAX_SEGMENT = 16384
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libmsketch.so is not built (%s); run `python paper_2508_14209_amd/build.py` "
+        "or __graft_entry__.build()" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+_i64, _p, _sz, _i32 = ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+
+
+class MsOpts(ctypes.Structure):
+    _fields_ = [("cs_mode", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+
+
+_SIGS = {
+    "ms_workspace_size": ([_i32, _i64, _i64, _i64, _i64, _i64, _i32, _i32, _p], _sz),
+    "ms_check_status": ([_p, _p], _i32),
+    "ms_status_string": ([_i32], ctypes.c_char_p),
+    "ms_bucket_plan": ([_i64, _i64, _p, _p, _p, _p, _p, _sz, _p], _i32),
+    "ms_pack_sketch": ([_i64, _i64, _p, _p, _p, _p, _sz, _p], _i32),
+    "countsketch_accumulate": ([_i64, _i64, _i64, _i32, _p, _i64, _p, _p, _i64, _p, _p, _sz,
+                                _p], _i32),
+    "countsketch_apply": ([_i64, _i64, _i64, _i32, _p, _i64, _p, _p, _p, _i64, _p, _p,
+                           _sz, _p], _i32),
+    "ms_gaussian_apply": ([_i64, _i64, _i64, _i32, _p, _i64, _i32, _p, _i64, _p, _i64,
+                           _p, _sz, _p], _i32),
+    "multisketch_apply": ([_i64, _i64, _i64, _i64, _i32, _p, _i64, _p, _p, _i32, _p,
+                           _i64, _p, _i64, _p, _p, _sz, _p], _i32),
+    "ms_qr_solve": ([_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _sz,
+                     _p], _i32),
+    "sketch_lstsq": ([_i64, _i64, _i64, _i64, _i64, _i32, _p, _i64, _p, _i64, _p, _p,
+                      _i32, _p, _i64, _p, _i64, _p, _p, _sz, _p], _i32),
+}
+for _name, (_args, _ret) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _ret
+
+
+class MsketchError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.ms_status_string(code).decode()
+        super().__init__("%s: %s" % (where, msg))
+        self.code = code
+
+
+def _ok(code: int, where: str):
+    if code != MS_OK:
+        raise MsketchError(code, where)
+
+
+def _dt(t: torch.Tensor) -> int:
+    if t.dtype == torch.float64:
+        return MS_F64
+    if t.dtype == torch.float32:
+        return MS_F32
+    if t.dtype == torch.bfloat16:
+        return MS_BF16
+    raise TypeError("unsupported dtype %s" % t.dtype)
+
+
+_TORCH_DT = {MS_F64: torch.float64, MS_F32: torch.float32, MS_BF16: torch.bfloat16}
+
+
+def empty_colmajor(rows: int, cols: int, dtype, device="cuda") -> torch.Tensor:
+    """A rows x cols tensor in column-major storage (leading dimension rows)."""
+    return torch.empty((cols, rows), dtype=dtype, device=device).t()
+
+
+def colmajor(t: torch.Tensor, name: str):
+    """(pointer, leading dimension) of a 2-D column-major device tensor."""
+    if t.dim() == 1:
+        t = t.unsqueeze(1)
+    if t.dim() != 2:
+        raise ValueError("%s must be 2-D" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    rows, cols = t.shape
+    if rows > 1 and t.stride(0) != 1:
+        raise ValueError("%s must be column-major (stride(0) == 1)" % name)
+    ld = t.stride(1) if cols > 1 else max(1, rows)
+    return t.data_ptr(), max(ld, rows, 1)
+
+
+def _vec(t: torch.Tensor, dtype, name: str):
+    if not t.is_cuda or t.dtype != dtype or t.dim() != 1 or (t.numel() > 1 and t.stride(0) != 1):
+        raise ValueError("%s must be a contiguous 1-D %s device tensor" % (name, dtype))
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _opts(mode: str = "auto", refine_steps: int = 0):
+    return MsOpts(MODES[mode], int(refine_steps), 0, 0)
+
+
+def workspace_size(op: str, d=0, n=0, nrhs=0, k=0, k2=0, a_dtype=MS_F64, g_dtype=MS_F64,
+                   mode: str = "auto", refine_steps: int = 0) -> int:
+    o = _opts(mode, refine_steps)
+    sz = _lib.ms_workspace_size(OPS[op], d, n, nrhs, k, k2, a_dtype, g_dtype, ctypes.byref(o))
+    if sz == 0:
+        raise MsketchError(MS_ERR_ARG, "ms_workspace_size")
+    return sz
+
+
+def workspace(nbytes: int, device="cuda") -> torch.Tensor:
+    """A device byte buffer usable as a workspace (256-byte aligned)."""
+    return torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+
+
+def _ws_ptr(ws: torch.Tensor, need: int):
+    p = ws.data_ptr()
+    aligned = (p + 255) // 256 * 256
+    have = ws.numel() - (aligned - p)
+    if have < need:
+        raise MsketchError(MS_ERR_NOMEM, "workspace")
+    return aligned, have
+
+
+def check_status(ws: torch.Tensor, stream=None, where: str = "device status"):
+    """Synchronise and raise MsketchError if the last call that used ``ws``
+    recorded a device-side error."""
+    p = (ws.data_ptr() + 255) // 256 * 256
+    _ok(_lib.ms_check_status(ctypes.c_void_p(p), _stream(stream)), where)
+
+
+def bucket_plan(h: torch.Tensor, k: int, ws: torch.Tensor | None = None, stream=None):
+    """(cnt, off, perm) of the stable counting sort of rows by bucket."""
+    d = h.numel()
+    need = workspace_size("bucket_plan", d=d, k=k)
+    ws = workspace(need, h.device) if ws is None else ws
+    wp, have = _ws_ptr(ws, need)
+    cnt = torch.empty(k, dtype=torch.int32, device=h.device)
+    off = torch.empty(k + 1, dtype=torch.int32, device=h.device)
+    perm = torch.empty(max(d, 1), dtype=torch.int32, device=h.device)
+    _ok(_lib.ms_bucket_plan(d, k, _vec(h, torch.int32, "h") if d else None, cnt.data_ptr(),
+                            off.data_ptr(), perm.data_ptr(), wp, have, _stream(stream)),
+        "ms_bucket_plan")
+    return cnt, off, perm[:d], ws
+
+
+def pack_sketch(h: torch.Tensor, s: torch.Tensor, k: int, code: torch.Tensor | None = None,
+                ws: torch.Tensor | None = None, stream=None):
+    """Validated packed sketch: one int32 word per row, h | (s == -1) << 31.
+    Returns (code, ws)."""
+    d = h.numel()
+    if code is None:
+        code = torch.empty(max(d, 1), dtype=torch.int32, device=h.device)
+    ws = workspace(256, h.device) if ws is None else ws
+    wp, have = _ws_ptr(ws, 256)
+    _ok(_lib.ms_pack_sketch(d, k, _vec(h, torch.int32, "h") if d else None,
+                            _vec(s, torch.int8, "s") if d else None,
+                            code.data_ptr(), wp, have, _stream(stream)), "ms_pack_sketch")
+    return code[:d], ws
+
+
+def countsketch_accumulate(A: torch.Tensor, code: torch.Tensor, k: int, Y: torch.Tensor,
+                           mode: str = "auto", ws: torch.Tensor | None = None, stream=None):
+    """Y += S A with a packed sketch (no clearing of Y).  Returns (Y, ws)."""
+    d, n = A.shape
+    a_dt = _dt(A)
+    Ap, lda = colmajor(A, "A")
+    Yp, ldy = colmajor(Y, "Y")
+    if Y.shape != (k, n) or Y.dtype != A.dtype:
+        raise ValueError("Y must be k x n with A's dtype")
+    ws = workspace(256, A.device) if ws is None else ws
+    wp, have = _ws_ptr(ws, 256)
+    o = _opts(mode)
+    _ok(_lib.countsketch_accumulate(d, n, k, a_dt, Ap, lda,
+                                    _vec(code, torch.int32, "code") if d else None, Yp, ldy,
+                                    ctypes.byref(o), wp, have, _stream(stream)),
+        "countsketch_accumulate")
+    return Y, ws
+
+
+def countsketch_apply(A: torch.Tensor, h: torch.Tensor, s: torch.Tensor, k: int,
+                      Y: torch.Tensor | None = None, mode: str = "auto",
+                      ws: torch.Tensor | None = None, stream=None):
+    """Y = S A (k x n, A's dtype).  Returns (Y, ws)."""
+    d, n = A.shape
+    a_dt = _dt(A)
+    Ap, lda = colmajor(A, "A")
+    if Y is None:
+        Y = empty_colmajor(k, n, A.dtype, A.device)
+    Yp, ldy = colmajor(Y, "Y")
+    if Y.shape != (k, n) or Y.dtype != A.dtype:
+        raise ValueError("Y must be k x n with A's dtype")
+    need = workspace_size("countsketch", d=d, n=n, k=k, a_dtype=a_dt, mode=mode)
+    ws = workspace(need, A.device) if ws is None else ws
+    wp, have = _ws_ptr(ws, need)
+    o = _opts(mode)
+    _ok(_lib.countsketch_apply(d, n, k, a_dt, Ap, lda,
+                               _vec(h, torch.int32, "h") if d else None,
+                               _vec(s, torch.int8, "s") if d else None, Yp, ldy,
+                               ctypes.byref(o), wp, have, _stream(stream)), "countsketch_apply")
+    return Y, ws
+
+
+def gaussian_apply(G: torch.Tensor, Y: torch.Tensor, Z: torch.Tensor | None = None,
+                   ws: torch.Tensor | None = None, stream=None):
+    """Z = G Y (k2 x ncols).  Returns (Z, ws)."""
+    k2, k = G.shape
+    k_, nc = Y.shape
+    if k_ != k:
+        raise ValueError("G is k2 x k and Y is k x ncols")
+    g_dt, y_dt = _dt(G), _dt(Y)
+    zdtype = torch.float64 if g_dt == MS_F64 else torch.float32
+    if Z is None:
+        Z = empty_colmajor(k2, nc, zdtype, Y.device)
+    Gp, ldg = colmajor(G, "G")
+    Yp, ldy = colmajor(Y, "Y")
+    Zp, ldz = colmajor(Z, "Z")
+    need = workspace_size("gaussian", n=nc, k=k, k2=k2, a_dtype=y_dt, g_dtype=g_dt)
+    ws = workspace(need, Y.device) if ws is None else ws
+    wp, have = _ws_ptr(ws, need)
+    _ok(_lib.ms_gaussian_apply(k, nc, k2, g_dt, Gp, ldg, y_dt, Yp, ldy, Zp, ldz, wp, have,
+                               _stream(stream)), "ms_gaussian_apply")
+    return Z, ws
+
+
+def multisketch_apply(A: torch.Tensor, h: torch.Tensor, s: torch.Tensor, G: torch.Tensor,
+                      k: int, Z: torch.Tensor | None = None, mode: str = "auto",
+                      ws: torch.Tensor | None = None, stream=None):
+    """Z = G (S A) (k2 x n).  Returns (Z, ws)."""
+    d, n = A.shape
+    k2 = G.shape[0]
+    a_dt, g_dt = _dt(A), _dt(G)
+    zdtype = torch.float64 if a_dt == MS_F64 else torch.float32
+    if Z is None:
+        Z = empty_colmajor(k2, n, zdtype, A.device)
+    Ap, lda = colmajor(A, "A")
+    Gp, ldg = colmajor(G, "G")
+    Zp, ldz = colmajor(Z, "Z")
+    need = workspace_size("multisketch", d=d, n=n, k=k, k2=k2, a_dtype=a_dt, g_dtype=g_dt,
+                          mode=mode)
+    ws = workspace(need, A.device) if ws is None else ws
+    wp, have = _ws_ptr(ws, need)
+    o = _opts(mode)
+    _ok(_lib.multisketch_apply(d, n, k, k2, a_dt, Ap, lda,
+                               _vec(h, torch.int32, "h") if d else None,
+                               _vec(s, torch.int8, "s") if d else None, g_dt, Gp, ldg, Zp, ldz,
+                               ctypes.byref(o), wp, have, _stream(stream)), "multisketch_apply")
+    return Z, ws
+
+
+def qr_solve(W: torch.Tensor, B: torch.Tensor, X: torch.Tensor | None = None,
+             R: torch.Tensor | None = None, want_r: bool = False,
+             ws: torch.Tensor | None = None, stream=None):
+    """X = R^{-1} (Q^T B)_{0:n} with [Q, R] = qr(W, 0), FP64.  Returns (X, R, ws)."""
+    m, n = W.shape
+    nrhs = B.shape[1] if B.dim() == 2 else 1
+    if X is None:
+        X = empty_colmajor(n, nrhs, torch.float64, W.device)
+    if want_r and R is None:
+        R = empty_colmajor(n, n, torch.float64, W.device)
+    Wp, ldw = colmajor(W, "W")
+    Bp, ldb = colmajor(B, "B")
+    Xp, ldx = colmajor(X, "X")
+    Rp, ldr = colmajor(R, "R") if R is not None else (None, n)
+    need = workspace_size("qr_solve", n=n, nrhs=nrhs, k2=m)
+    ws = workspace(need, W.device) if ws is None else ws
+    wp, have = _ws_ptr(ws, need)
+    _ok(_lib.ms_qr_solve(m, n, nrhs, Wp, ldw, Bp, ldb, Xp, ldx, Rp, ldr, wp, have,
+                         _stream(stream)), "ms_qr_solve")
+    return X, R, ws
+
+
+def sketch_lstsq(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torch.Tensor,
+                 G: torch.Tensor, k: int, refine_steps: int = 0, mode: str = "auto",
+                 X: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None):
+    """X = argmin || G C (B - A X) || (n x nrhs, FP64).  Returns (X, ws)."""
+    d, n = A.shape
+    if B.dim() == 1:
+        B = B.unsqueeze(1)
+    nrhs = B.shape[1]
+    k2 = G.shape[0]
+    a_dt, g_dt = _dt(A), _dt(G)
+    if B.dtype != A.dtype:
+        raise ValueError("B must have A's dtype")
+    if X is None:
+        X = empty_colmajor(n, nrhs, torch.float64, A.device)
+    Ap, lda = colmajor(A, "A")
+    Bp, ldb = colmajor(B, "B")
+    Gp, ldg = colmajor(G, "G")
+    Xp, ldx = colmajor(X, "X")
+    need = workspace_size("lstsq", d=d, n=n, nrhs=nrhs, k=k, k2=k2, a_dtype=a_dt,
+                          g_dtype=g_dt, mode=mode, refine_steps=refine_steps)
+    ws = workspace(need, A.device) if ws is None else ws
+    wp, have = _ws_ptr(ws, need)
+    o = _opts(mode, refine_steps)
+    _ok(_lib.sketch_lstsq(d, n, nrhs, k, k2, a_dt, Ap, lda, Bp, ldb, _vec(h, torch.int32, "h"),
+                          _vec(s, torch.int8, "s"), g_dt, Gp, ldg, Xp, ldx, ctypes.byref(o), wp,
+                          have, _stream(stream)), "sketch_lstsq")
+    return X, ws

@@ -1,0 +1,504 @@
+// api.hip -- the C ABI of libmsketch (include/msketch.h): argument checks,
+// workspace layout and the order of launches for each entry point.  Every
+// step of the path runs in this library's kernels; this file only validates,
+// carves the caller's workspace and enqueues.
+#include <mutex>
+
+#include "ms_internal.h"
+
+namespace ms {
+
+// ------------------------------------------------------------------ device info
+namespace {
+std::mutex g_mu;
+constexpr int kMaxDev = 64;
+DevInfo g_info[kMaxDev];
+bool g_have[kMaxDev];
+struct LdsKey {
+  const void *fn;
+  int dev;
+  int bytes;
+};
+LdsKey g_lds[256];
+int g_nlds = 0;
+}  // namespace
+
+const DevInfo &dev_info() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) dev = 0;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_have[dev]) {
+    DevInfo d;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess) d.cus = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+      d.lds_per_block = v;
+    if (d.cus <= 0) d.cus = 256;
+    if (d.lds_per_block <= 0) d.lds_per_block = 65536;
+    g_info[dev] = d;
+    g_have[dev] = true;
+  }
+  return g_info[dev];
+}
+
+hipError_t allow_dynamic_lds(const void *kernel, int bytes) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (int i = 0; i < g_nlds; ++i)
+      if (g_lds[i].fn == kernel && g_lds[i].dev == dev && g_lds[i].bytes >= bytes) return hipSuccess;
+  }
+  if (bytes <= 65536) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (g_nlds < 256) g_lds[g_nlds++] = LdsKey{kernel, dev, bytes};
+  return hipSuccess;
+}
+
+// refine.hip
+hipError_t launch_residual_f32(int64_t d, int64_t n, int64_t nrhs, const float *A, int64_t lda,
+                               const float *B, int64_t ldb, const double *X, int64_t ldx,
+                               double *r, int64_t ldr, hipStream_t st);
+hipError_t launch_residual_f64(int64_t d, int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                               const double *B, int64_t ldb, const double *X, int64_t ldx,
+                               double *r, int64_t ldr, hipStream_t st);
+hipError_t launch_axpy_update(int64_t n, int64_t nrhs, const double *dX, double *X, int64_t ldx,
+                              hipStream_t st);
+
+// ------------------------------------------------------------------ layouts
+
+namespace {
+
+constexpr int64_t kMax31 = 0x7ffffffe;
+
+int resolve_mode(const ms_opts *o) {
+  const int m = o ? o->cs_mode : MS_CS_AUTO;
+  return m == MS_CS_AUTO ? MS_CS_LDS : m;
+}
+
+struct CsLayout {
+  size_t code = 0, cnt = 0, off = 0, cursor = 0, sperm = 0;
+};
+
+void carve_cs(Carve &cv, CsLayout &L, int64_t d, int64_t k, int mode) {
+  if (mode == MS_CS_SORTED) {
+    L.cnt = cv.take((size_t)k * 4);
+    L.off = cv.take((size_t)(k + 1) * 4);
+    L.cursor = cv.take((size_t)k * 4);
+    L.sperm = cv.take((size_t)d * 4);
+  } else {
+    L.code = cv.take((size_t)d * 4);
+  }
+}
+
+struct LstsqLayout {
+  CsLayout cs;
+  size_t y = 0, partials = 0, z64 = 0, qr = 0, fact = 0, tau = 0;
+  size_t r = 0, yr = 0, zr = 0, gv = 0, dx = 0;
+  size_t total = 0;
+};
+
+LstsqLayout lstsq_layout(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64_t k2,
+                         ms_dtype a_dtype, ms_dtype g_dtype, int mode, int refine) {
+  LstsqLayout L;
+  Carve cv;
+  const int64_t nc = n + nrhs;
+  carve_cs(cv, L.cs, d, k, mode);
+  L.y = cv.take((size_t)k * nc * dtype_size(a_dtype));
+  L.partials = cv.take(plan_gemm(k2, nc, k, g_dtype).partial_bytes);
+  L.z64 = cv.take((size_t)k2 * nc * 8);
+  L.qr = cv.take(qr_workspace_bytes(k2, n, nrhs));
+  L.fact = cv.take((size_t)k2 * n * 8);
+  L.tau = cv.take((size_t)n * 8);
+  if (refine > 0) {
+    L.r = cv.take((size_t)d * nrhs * 8);
+    L.yr = cv.take((size_t)k * nrhs * 8);
+    L.zr = cv.take((size_t)k2 * nrhs * 8);
+    L.gv = cv.take(gemv64_partial_bytes(k2, nrhs, k));
+    L.dx = cv.take((size_t)n * nrhs * 8);
+  }
+  L.total = cv.off;
+  return L;
+}
+
+template <typename P>
+P *at(void *ws, size_t off) {
+  return reinterpret_cast<P *>(static_cast<unsigned char *>(ws) + off);
+}
+
+ms_status from_hip(hipError_t e) { return e == hipSuccess ? MS_OK : MS_ERR_DEVICE; }
+
+// CountSketch of the column set `c` into Y (k x c.ncols, ldy).
+template <typename T>
+hipError_t run_countsketch(int64_t d, int64_t k, const Cols<T> &c, const int32_t *h,
+                           const int8_t *s, T *Y, int64_t ldy, int mode, void *ws,
+                           const CsLayout &L, int *status, hipStream_t st) {
+  if (c.ncols <= 0) return hipSuccess;
+  if (d == 0) return launch_fill_zero<T>(Y, k, c.ncols, ldy, st);
+  hipError_t e;
+  if (mode == MS_CS_SORTED) {
+    e = launch_plan(d, k, h, s, at<int32_t>(ws, L.cnt), at<int32_t>(ws, L.off),
+                    at<int32_t>(ws, L.cursor), at<uint32_t>(ws, L.sperm), status, st);
+    if (e != hipSuccess) return e;
+    // a sign outside {+1,-1} is reported through the pack check as well
+    return launch_cs_sorted<T>(k, c, at<int32_t>(ws, L.off), at<uint32_t>(ws, L.sperm), Y, ldy, st);
+  }
+  e = launch_pack_codes(d, k, h, s, at<uint32_t>(ws, L.code), status, st);
+  if (e != hipSuccess) return e;
+  if (mode == MS_CS_ATOMIC)
+    return launch_cs_atomic<T>(d, k, c, at<uint32_t>(ws, L.code), Y, ldy, true, status, st);
+  return launch_cs_lds<T>(d, k, c, at<uint32_t>(ws, L.code), Y, ldy, true, status, st);
+}
+
+// Sorted mode validates s with a separate pass (the plan only reads h).
+__global__ void k_check_signs(int64_t d, const int8_t *__restrict__ s, int *status) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d;
+       i += (int64_t)gridDim.x * blockDim.x)
+    bad |= !(s[i] == 1 || s[i] == -1);
+  if (bad) record_status(status, MS_ERR_RANGE);
+}
+
+hipError_t launch_check_signs(int64_t d, const int8_t *s, int *status, hipStream_t st) {
+  if (d <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((d + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_check_signs, dim3((unsigned)blocks), dim3(256), 0, st, d, s, status);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t run_countsketch_checked(int64_t d, int64_t k, const Cols<T> &c, const int32_t *h,
+                                   const int8_t *s, T *Y, int64_t ldy, int mode, void *ws,
+                                   const CsLayout &L, int *status, hipStream_t st) {
+  if (mode == MS_CS_SORTED && d > 0) {
+    hipError_t e = launch_check_signs(d, s, status, st);
+    if (e != hipSuccess) return e;
+  }
+  return run_countsketch<T>(d, k, c, h, s, Y, ldy, mode, ws, L, status, st);
+}
+
+bool valid_mode(const ms_opts *o) {
+  const int m = o ? o->cs_mode : MS_CS_AUTO;
+  return m >= MS_CS_AUTO && m <= MS_CS_SORTED;
+}
+
+}  // namespace
+}  // namespace ms
+
+using namespace ms;
+
+extern "C" {
+
+const char *ms_status_string(ms_status st) {
+  switch (st) {
+    case MS_OK: return "MS_OK";
+    case MS_ERR_ARG: return "MS_ERR_ARG: invalid argument";
+    case MS_ERR_RANGE: return "MS_ERR_RANGE: bucket index outside [0,k) or sign not +-1";
+    case MS_ERR_NOMEM: return "MS_ERR_NOMEM: workspace too small";
+    case MS_ERR_SINGULAR: return "MS_ERR_SINGULAR: zero or non-finite diagonal of R";
+    case MS_ERR_DEVICE: return "MS_ERR_DEVICE: HIP runtime or launch failure";
+    case MS_ERR_UNSUPPORTED: return "MS_ERR_UNSUPPORTED: unsupported combination or size";
+  }
+  return "unknown status";
+}
+
+size_t ms_workspace_size(int op, int64_t d, int64_t n, int64_t nrhs, int64_t k, int64_t k2,
+                         ms_dtype a_dtype, ms_dtype g_dtype, const ms_opts *opts) {
+  if (d < 0 || n < 0 || nrhs < 0 || k < 0 || k2 < 0 || !valid_mode(opts)) return 0;
+  const int mode = resolve_mode(opts);
+  Carve cv;
+  CsLayout L;
+  switch (op) {
+    case MS_OP_BUCKET_PLAN:
+      cv.take((size_t)k * 4);
+      cv.take((size_t)d * 4);
+      return cv.off;
+    case MS_OP_COUNTSKETCH:
+      carve_cs(cv, L, d, k, mode);
+      return cv.off;
+    case MS_OP_GAUSSIAN:
+      cv.take(plan_gemm(k2, n, k, g_dtype).partial_bytes);
+      return cv.off;
+    case MS_OP_MULTISKETCH:
+      carve_cs(cv, L, d, k, mode);
+      cv.take((size_t)k * n * dtype_size(a_dtype));
+      cv.take(plan_gemm(k2, n, k, g_dtype).partial_bytes);
+      return cv.off;
+    case MS_OP_QR_SOLVE:
+      cv.take(qr_workspace_bytes(k2, n, nrhs));
+      return cv.off;
+    case MS_OP_LSTSQ: {
+      const int refine = opts ? opts->refine_steps : 0;
+      return lstsq_layout(d, n, nrhs, k, k2, a_dtype, g_dtype, mode, refine).total;
+    }
+    default:
+      return 0;
+  }
+}
+
+ms_status ms_check_status(const void *ws, void *stream) {
+  if (!ws) return MS_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  int v = 0;
+  if (hipMemcpyAsync(&v, ws, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return MS_ERR_DEVICE;
+  if (hipStreamSynchronize(st) != hipSuccess) return MS_ERR_DEVICE;
+  return (ms_status)v;
+}
+
+ms_status ms_bucket_plan(int64_t d, int64_t k, const int32_t *h, int32_t *cnt, int32_t *off,
+                         int32_t *perm, void *ws, size_t ws_bytes, void *stream) {
+  if (d < 0 || d > kMax31 || k < 1 || k > kMax31) return MS_ERR_ARG;
+  if ((d > 0 && (!h || !perm)) || !cnt || !off || !ws) return MS_ERR_ARG;
+  const size_t need = ms_workspace_size(MS_OP_BUCKET_PLAN, d, 0, 0, k, 0, MS_F64, MS_F64, nullptr);
+  if (ws_bytes < need) return MS_ERR_NOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  Carve cv;
+  const size_t o_cursor = cv.take((size_t)k * 4);
+  const size_t o_sperm = cv.take((size_t)d * 4);
+  int *status = static_cast<int *>(ws);
+  hipError_t e = launch_zero_status(status, st);
+  if (e == hipSuccess)
+    e = launch_plan(d, k, h, nullptr, cnt, off, at<int32_t>(ws, o_cursor),
+                    at<uint32_t>(ws, o_sperm), status, st);
+  if (e == hipSuccess) e = launch_strip_sign(d, at<uint32_t>(ws, o_sperm), perm, st);
+  return from_hip(e);
+}
+
+ms_status ms_pack_sketch(int64_t d, int64_t k, const int32_t *h, const int8_t *s, uint32_t *code,
+                         void *ws, size_t ws_bytes, void *stream) {
+  if (d < 0 || k < 1 || k > kMax31) return MS_ERR_ARG;
+  if (!ws || ws_bytes < kAlign || (d > 0 && (!h || !s || !code))) return MS_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  int *status = static_cast<int *>(ws);
+  hipError_t e = launch_zero_status(status, st);
+  if (e == hipSuccess) e = launch_pack_codes(d, k, h, s, code, status, st);
+  return from_hip(e);
+}
+
+ms_status countsketch_accumulate(int64_t d, int64_t n, int64_t k, ms_dtype a_dtype, const void *A,
+                                 int64_t lda, const uint32_t *code, void *Y, int64_t ldy,
+                                 const ms_opts *opts, void *ws, size_t ws_bytes, void *stream) {
+  if (d < 0 || n < 0 || k < 1 || k > kMax31 || n > (int64_t)1 << 30) return MS_ERR_ARG;
+  if (a_dtype != MS_F64 && a_dtype != MS_F32) return MS_ERR_ARG;
+  if (!valid_mode(opts)) return MS_ERR_ARG;
+  const int mode = resolve_mode(opts);
+  if (mode == MS_CS_SORTED) return MS_ERR_UNSUPPORTED;
+  if (lda < (d > 1 ? d : 1) || ldy < k) return MS_ERR_ARG;
+  if (!ws || ws_bytes < kAlign || (n > 0 && !Y) || (d > 0 && n > 0 && (!A || !code)))
+    return MS_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  int *status = static_cast<int *>(ws);
+  hipError_t e = launch_zero_status(status, st);
+  if (e != hipSuccess || n == 0 || d == 0) return from_hip(e);
+  if (a_dtype == MS_F64) {
+    Cols<double> c{static_cast<const double *>(A), lda, nullptr, 0, (int)n, (int)n};
+    e = mode == MS_CS_ATOMIC
+            ? launch_cs_atomic<double>(d, k, c, code, static_cast<double *>(Y), ldy, false, status, st)
+            : launch_cs_lds<double>(d, k, c, code, static_cast<double *>(Y), ldy, false, status, st);
+  } else {
+    Cols<float> c{static_cast<const float *>(A), lda, nullptr, 0, (int)n, (int)n};
+    e = mode == MS_CS_ATOMIC
+            ? launch_cs_atomic<float>(d, k, c, code, static_cast<float *>(Y), ldy, false, status, st)
+            : launch_cs_lds<float>(d, k, c, code, static_cast<float *>(Y), ldy, false, status, st);
+  }
+  return from_hip(e);
+}
+
+ms_status countsketch_apply(int64_t d, int64_t n, int64_t k, ms_dtype a_dtype, const void *A,
+                            int64_t lda, const int32_t *h, const int8_t *s, void *Y, int64_t ldy,
+                            const ms_opts *opts, void *ws, size_t ws_bytes, void *stream) {
+  if (d < 0 || n < 0 || k < 1 || k > kMax31 || n > (int64_t)1 << 30) return MS_ERR_ARG;
+  if (a_dtype != MS_F64 && a_dtype != MS_F32) return MS_ERR_ARG;
+  if (!valid_mode(opts)) return MS_ERR_ARG;
+  const int mode = resolve_mode(opts);
+  if (mode == MS_CS_SORTED && d > kMax31) return MS_ERR_UNSUPPORTED;
+  if (lda < (d > 1 ? d : 1) || ldy < k) return MS_ERR_ARG;
+  if (!ws || (n > 0 && !Y) || (d > 0 && n > 0 && (!A || !h || !s))) return MS_ERR_ARG;
+  if (ws_bytes < ms_workspace_size(MS_OP_COUNTSKETCH, d, n, 0, k, 0, a_dtype, a_dtype, opts))
+    return MS_ERR_NOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  int *status = static_cast<int *>(ws);
+  hipError_t e = launch_zero_status(status, st);
+  if (e != hipSuccess || n == 0) return from_hip(e);
+  Carve cv;
+  CsLayout L;
+  carve_cs(cv, L, d, k, mode);
+  if (a_dtype == MS_F64) {
+    Cols<double> c{static_cast<const double *>(A), lda, nullptr, 0, (int)n, (int)n};
+    e = run_countsketch_checked<double>(d, k, c, h, s, static_cast<double *>(Y), ldy, mode, ws, L,
+                                        status, st);
+  } else {
+    Cols<float> c{static_cast<const float *>(A), lda, nullptr, 0, (int)n, (int)n};
+    e = run_countsketch_checked<float>(d, k, c, h, s, static_cast<float *>(Y), ldy, mode, ws, L,
+                                       status, st);
+  }
+  return from_hip(e);
+}
+
+ms_status ms_gaussian_apply(int64_t k, int64_t ncols, int64_t k2, ms_dtype g_dtype, const void *G,
+                            int64_t ldg, ms_dtype y_dtype, const void *Y, int64_t ldy, void *Z,
+                            int64_t ldz, void *ws, size_t ws_bytes, void *stream) {
+  if (k < 1 || ncols < 0 || k2 < 1 || k2 > (1 << 24) || ncols > (1 << 24)) return MS_ERR_ARG;
+  const bool ok = (g_dtype == MS_F64 && y_dtype == MS_F64) ||
+                  (g_dtype == MS_F32 && y_dtype == MS_F32) ||
+                  (g_dtype == MS_BF16 && y_dtype == MS_F32);
+  if (!ok) return MS_ERR_ARG;
+  if (ldg < k2 || ldy < k || ldz < k2) return MS_ERR_ARG;
+  if (!ws || (ncols > 0 && (!G || !Y || !Z))) return MS_ERR_ARG;
+  if (ws_bytes < ms_workspace_size(MS_OP_GAUSSIAN, 0, ncols, 0, k, k2, y_dtype, g_dtype, nullptr))
+    return MS_ERR_NOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  hipError_t e = launch_zero_status(static_cast<int *>(ws), st);
+  if (e != hipSuccess || ncols == 0) return from_hip(e);
+  Carve cv;
+  const GemmPlan p = plan_gemm(k2, ncols, k, g_dtype);
+  const size_t o_part = cv.take(p.partial_bytes);
+  e = launch_gemm(p, g_dtype, G, ldg, Y, ldy, Z, ldz, nullptr, at<void>(ws, o_part), nullptr, st);
+  return from_hip(e);
+}
+
+ms_status multisketch_apply(int64_t d, int64_t n, int64_t k, int64_t k2, ms_dtype a_dtype,
+                            const void *A, int64_t lda, const int32_t *h, const int8_t *s,
+                            ms_dtype g_dtype, const void *G, int64_t ldg, void *Z, int64_t ldz,
+                            const ms_opts *opts, void *ws, size_t ws_bytes, void *stream) {
+  if (d < 0 || n < 0 || k < 1 || k > kMax31 || k2 < 1 || k2 > (1 << 24) || n > (1 << 24))
+    return MS_ERR_ARG;
+  const bool ok = (a_dtype == MS_F64 && g_dtype == MS_F64) ||
+                  (a_dtype == MS_F32 && (g_dtype == MS_F32 || g_dtype == MS_BF16));
+  if (!ok || !valid_mode(opts)) return MS_ERR_ARG;
+  const int mode = resolve_mode(opts);
+  if (mode == MS_CS_SORTED && d > kMax31) return MS_ERR_UNSUPPORTED;
+  if (lda < (d > 1 ? d : 1) || ldg < k2 || ldz < k2) return MS_ERR_ARG;
+  if (!ws || (n > 0 && (!Z || !G)) || (d > 0 && n > 0 && (!A || !h || !s))) return MS_ERR_ARG;
+  if (ws_bytes < ms_workspace_size(MS_OP_MULTISKETCH, d, n, 0, k, k2, a_dtype, g_dtype, opts))
+    return MS_ERR_NOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  int *status = static_cast<int *>(ws);
+  hipError_t e = launch_zero_status(status, st);
+  if (e != hipSuccess || n == 0) return from_hip(e);
+  Carve cv;
+  CsLayout L;
+  carve_cs(cv, L, d, k, mode);
+  const size_t o_y = cv.take((size_t)k * n * dtype_size(a_dtype));
+  const GemmPlan p = plan_gemm(k2, n, k, g_dtype);
+  const size_t o_part = cv.take(p.partial_bytes);
+  if (a_dtype == MS_F64) {
+    Cols<double> c{static_cast<const double *>(A), lda, nullptr, 0, (int)n, (int)n};
+    e = run_countsketch_checked<double>(d, k, c, h, s, at<double>(ws, o_y), k, mode, ws, L, status,
+                                        st);
+  } else {
+    Cols<float> c{static_cast<const float *>(A), lda, nullptr, 0, (int)n, (int)n};
+    e = run_countsketch_checked<float>(d, k, c, h, s, at<float>(ws, o_y), k, mode, ws, L, status,
+                                       st);
+  }
+  if (e == hipSuccess)
+    e = launch_gemm(p, g_dtype, G, ldg, at<void>(ws, o_y), k, Z, ldz, nullptr,
+                    at<void>(ws, o_part), nullptr, st);
+  return from_hip(e);
+}
+
+ms_status ms_qr_solve(int64_t m, int64_t n, int64_t nrhs, const double *W, int64_t ldw,
+                      const double *Bm, int64_t ldb, double *X, int64_t ldx, double *R,
+                      int64_t ldr, void *ws, size_t ws_bytes, void *stream) {
+  if (n < 1 || m < n || nrhs < 0 || m > (1 << 24) || n > (1 << 16) || nrhs > (1 << 16))
+    return MS_ERR_ARG;
+  if (ldw < m || (nrhs > 0 && ldb < m) || ldx < n || (R && ldr < n)) return MS_ERR_ARG;
+  if (!W || !ws || (nrhs > 0 && (!Bm || !X))) return MS_ERR_ARG;
+  if (ws_bytes < ms_workspace_size(MS_OP_QR_SOLVE, 0, n, nrhs, 0, m, MS_F64, MS_F64, nullptr))
+    return MS_ERR_NOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  int *status = static_cast<int *>(ws);
+  hipError_t e = launch_zero_status(status, st);
+  Carve cv;
+  const size_t o_qr = cv.take(qr_workspace_bytes(m, n, nrhs));
+  if (e == hipSuccess)
+    e = launch_qr_solve(m, n, nrhs, W, ldw, Bm, ldb, X, ldx, R, ldr, nullptr, nullptr,
+                        at<void>(ws, o_qr), status, st);
+  return from_hip(e);
+}
+
+ms_status sketch_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64_t k2,
+                       ms_dtype a_dtype, const void *A, int64_t lda, const void *B, int64_t ldb,
+                       const int32_t *h, const int8_t *s, ms_dtype g_dtype, const void *G,
+                       int64_t ldg, double *X, int64_t ldx, const ms_opts *opts, void *ws,
+                       size_t ws_bytes, void *stream) {
+  if (d < 1 || n < 1 || nrhs < 1 || k < 1 || k > kMax31 || k2 < n || k2 > (1 << 24) ||
+      n > (1 << 16) || nrhs > (1 << 16))
+    return MS_ERR_ARG;
+  const bool ok = (a_dtype == MS_F64 && g_dtype == MS_F64) ||
+                  (a_dtype == MS_F32 && (g_dtype == MS_F32 || g_dtype == MS_BF16));
+  if (!ok || !valid_mode(opts)) return MS_ERR_ARG;
+  const int mode = resolve_mode(opts);
+  const int refine = opts ? opts->refine_steps : 0;
+  if (refine < 0 || refine > 64) return MS_ERR_ARG;
+  if (refine > 0 && nrhs > 8) return MS_ERR_UNSUPPORTED;
+  if (mode == MS_CS_SORTED && d > kMax31) return MS_ERR_UNSUPPORTED;
+  if (lda < d || ldb < d || ldg < k2 || ldx < n) return MS_ERR_ARG;
+  if (!A || !B || !h || !s || !G || !X || !ws) return MS_ERR_ARG;
+  const LstsqLayout L = lstsq_layout(d, n, nrhs, k, k2, a_dtype, g_dtype, mode, refine);
+  if (ws_bytes < L.total) return MS_ERR_NOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  int *status = static_cast<int *>(ws);
+  const int64_t nc = n + nrhs;
+  hipError_t e = launch_zero_status(status, st);
+  // 1. Y = C [A | B]
+  if (e == hipSuccess) {
+    if (a_dtype == MS_F64) {
+      Cols<double> c{static_cast<const double *>(A), lda, static_cast<const double *>(B), ldb,
+                     (int)n, (int)nc};
+      e = run_countsketch_checked<double>(d, k, c, h, s, at<double>(ws, L.y), k, mode, ws, L.cs,
+                                          status, st);
+    } else {
+      Cols<float> c{static_cast<const float *>(A), lda, static_cast<const float *>(B), ldb, (int)n,
+                    (int)nc};
+      e = run_countsketch_checked<float>(d, k, c, h, s, at<float>(ws, L.y), k, mode, ws, L.cs,
+                                         status, st);
+    }
+  }
+  // 2. Z = G Y (FP64 copy for the factorisation)
+  const GemmPlan p = plan_gemm(k2, nc, k, g_dtype);
+  if (e == hipSuccess)
+    e = launch_gemm(p, g_dtype, G, ldg, at<void>(ws, L.y), k, nullptr, k2, at<double>(ws, L.z64),
+                    at<void>(ws, L.partials), nullptr, st);
+  // 3. Householder QR of Z_A, Q^T Z_B, back substitution
+  double *z64 = at<double>(ws, L.z64);
+  if (e == hipSuccess)
+    e = launch_qr_solve(k2, n, nrhs, z64, k2, z64 + n * k2, k2, X, ldx, nullptr, 0,
+                        at<double>(ws, L.tau), at<double>(ws, L.fact), at<void>(ws, L.qr), status,
+                        st);
+  // 4. refinement: r = B - A X (FP64); X += R^{-1} Q^T G (C r)
+  for (int it = 0; it < refine && e == hipSuccess; ++it) {
+    double *r = at<double>(ws, L.r);
+    if (a_dtype == MS_F32)
+      e = launch_residual_f32(d, n, nrhs, static_cast<const float *>(A), lda,
+                              static_cast<const float *>(B), ldb, X, ldx, r, d, st);
+    else
+      e = launch_residual_f64(d, n, nrhs, static_cast<const double *>(A), lda,
+                              static_cast<const double *>(B), ldb, X, ldx, r, d, st);
+    if (e != hipSuccess) break;
+    Cols<double> cr{r, d, nullptr, 0, (int)nrhs, (int)nrhs};
+    if (mode == MS_CS_SORTED)
+      e = launch_cs_sorted<double>(k, cr, at<int32_t>(ws, L.cs.off), at<uint32_t>(ws, L.cs.sperm),
+                                   at<double>(ws, L.yr), k, st);
+    else if (mode == MS_CS_ATOMIC)
+      e = launch_cs_atomic<double>(d, k, cr, at<uint32_t>(ws, L.cs.code), at<double>(ws, L.yr), k,
+                                   true, status, st);
+    else
+      e = launch_cs_lds<double>(d, k, cr, at<uint32_t>(ws, L.cs.code), at<double>(ws, L.yr), k,
+                                true, status, st);
+    if (e != hipSuccess) break;
+    e = launch_gemv64(k2, nrhs, k, g_dtype, G, ldg, at<double>(ws, L.yr), k, at<double>(ws, L.zr),
+                      at<double>(ws, L.gv), st);
+    if (e != hipSuccess) break;
+    e = launch_qr_apply_solve(k2, n, nrhs, at<double>(ws, L.fact), at<double>(ws, L.tau),
+                              at<double>(ws, L.zr), at<double>(ws, L.dx), n, status, st);
+    if (e != hipSuccess) break;
+    e = launch_axpy_update(n, nrhs, at<double>(ws, L.dx), X, ldx, st);
+  }
+  return from_hip(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,568 @@
+// countsketch.hip -- CountSketch Y = S [A | B] on gfx950 (Def. 3, Eq. (2),
+// Alg. 2 of Higgins, Boman, Yamazaki, arXiv 2508.14209) and the sketch plan
+// (bucket histogram, scan, stable counting sort) that its deterministic mode
+// uses.
+//
+// A is column-major, so a column is a contiguous stream.  Three ways of
+// forming the bucket sums of Eq. (2):
+//   * atomic  -- Alg. 2 as written, one device-scope atomic add per element
+//                (kept as the measured baseline);
+//   * lds     -- each workgroup streams a row chunk of one column tile with
+//                16-byte loads and accumulates bucket partial sums in LDS
+//                (LDS atomics), then adds its partials to Y once;
+//   * sorted  -- rows grouped by bucket by a stable counting sort, each
+//                (bucket, column) folded sequentially in ascending row order
+//                from +0.0: bit-identical to the sequential reading of Alg. 2.
+#include <algorithm>
+
+#include "ms_internal.h"
+
+namespace ms {
+
+// ------------------------------------------------------------------ helpers
+
+__global__ void k_zero_status(int *status) {
+  if (threadIdx.x == 0) *status = MS_OK;
+}
+
+hipError_t launch_zero_status(int *status, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_status, dim3(1), dim3(64), 0, st, status);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_fill_zero(T *Y, int64_t rows, int64_t cols, int64_t ld) {
+  const int64_t total = rows * cols;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = t / rows;
+    Y[(t - c * rows) + c * ld] = T(0);
+  }
+}
+
+template <typename T>
+hipError_t launch_fill_zero(T *Y, int64_t rows, int64_t cols, int64_t ld, hipStream_t st) {
+  const int64_t total = rows * cols;
+  if (total <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_fill_zero<T>, dim3((unsigned)blocks), dim3(256), 0, st, Y, rows, cols, ld);
+  return hipGetLastError();
+}
+template hipError_t launch_fill_zero<double>(double *, int64_t, int64_t, int64_t, hipStream_t);
+template hipError_t launch_fill_zero<float>(float *, int64_t, int64_t, int64_t, hipStream_t);
+template hipError_t launch_fill_zero<int32_t>(int32_t *, int64_t, int64_t, int64_t, hipStream_t);
+
+// Validate (h, s) and pack them: code = h | (s == -1 ? sign bit : 0).  A row
+// with h outside [0,k) or s not in {+1,-1} records MS_ERR_RANGE and is
+// packed as bucket 0 so no later kernel leaves its bounds.
+__global__ void k_pack_codes(int64_t d, int64_t k, const int32_t *__restrict__ h,
+                             const int8_t *__restrict__ s, uint32_t *__restrict__ code,
+                             int *status) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t b = h[i];
+    const int8_t sg = s[i];
+    const bool ok = b >= 0 && (int64_t)b < k && (sg == 1 || sg == -1);
+    code[i] = ok ? ((uint32_t)b | (sg < 0 ? kSignBit : 0u)) : 0u;
+    bad |= !ok;
+  }
+  if (bad) record_status(status, MS_ERR_RANGE);
+}
+
+hipError_t launch_pack_codes(int64_t d, int64_t k, const int32_t *h, const int8_t *s,
+                             uint32_t *code, int *status, hipStream_t st) {
+  if (d <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((d + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_pack_codes, dim3((unsigned)blocks), dim3(256), 0, st, d, k, h, s, code,
+                     status);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ plan
+
+// cnt[m] += 1 per row with h = m (integer atomics: the counts are exact and
+// independent of order).
+__global__ void k_hist(int64_t d, int64_t k, const int32_t *__restrict__ h,
+                       int32_t *__restrict__ cnt, int *status) {
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t b = h[i];
+    if (b >= 0 && (int64_t)b < k)
+      atomicAdd(&cnt[b], 1);
+    else
+      bad = true;
+  }
+  if (bad) record_status(status, MS_ERR_RANGE);
+}
+
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan of cnt into off (k+1 entries) by one workgroup of 1024
+// threads, 4096 entries per pass with a running carry; also seeds the
+// scatter cursors with the bucket offsets.
+__global__ __launch_bounds__(1024) void k_scan(int64_t k, const int32_t *__restrict__ cnt,
+                                               int32_t *__restrict__ off,
+                                               int32_t *__restrict__ cursor) {
+  __shared__ int32_t wave_tot[16];
+  __shared__ int32_t carry_s;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) carry_s = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < k; base += 4096) {
+    int32_t v[4];
+    int32_t local = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t idx = base + tid * 4 + q;
+      v[q] = idx < k ? cnt[idx] : 0;
+      local += v[q];
+    }
+    const int32_t incl = wave_incl_scan(local);
+    if (lane == 63) wave_tot[wave] = incl;
+    __syncthreads();
+    int32_t wave_off = 0;
+    for (int w = 0; w < wave; ++w) wave_off += wave_tot[w];
+    int32_t run = carry_s + wave_off + incl - local;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t idx = base + tid * 4 + q;
+      if (idx < k) {
+        off[idx] = run;
+        cursor[idx] = run;
+      }
+      run += v[q];
+    }
+    __syncthreads();
+    if (tid == 1023) carry_s = run;
+    __syncthreads();
+  }
+  if (tid == 0) off[k] = carry_s;
+}
+
+// Scatter each row to a free slot of its bucket (order inside a bucket is
+// arbitrary here and is fixed by the per-bucket sort that follows).
+__global__ void k_scatter(int64_t d, int64_t k, const int32_t *__restrict__ h,
+                          const int8_t *__restrict__ s, int32_t *__restrict__ cursor,
+                          uint32_t *__restrict__ sperm) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t b = h[i];
+    if (b < 0 || (int64_t)b >= k) continue;
+    const int32_t pos = atomicAdd(&cursor[b], 1);
+    sperm[pos] = (uint32_t)i | ((s != nullptr && s[i] < 0) ? kSignBit : 0u);
+  }
+}
+
+// Sort one bucket's entries by row index (bits 0..30) with a bitonic network
+// in LDS.  Buckets of length <= CAP handled here; longer ones by the larger
+// instantiation; lengths beyond MS_SORTED_MAX_SEGMENT are reported.
+template <int CAP, int NTHREADS>
+__global__ __launch_bounds__(NTHREADS) void k_segsort(int64_t k, int lo_exclusive,
+                                                      const int32_t *__restrict__ off,
+                                                      uint32_t *__restrict__ sperm,
+                                                      int *status) {
+  __shared__ uint32_t key[CAP];
+  const int64_t b = blockIdx.x;
+  if (b >= k) return;
+  const int32_t o0 = off[b];
+  const int len = off[b + 1] - o0;
+  if (len <= lo_exclusive || len < 2) return;
+  if (len > CAP) {
+    if (CAP >= MS_SORTED_MAX_SEGMENT && threadIdx.x == 0) record_status(status, MS_ERR_UNSUPPORTED);
+    return;
+  }
+  int P = 2;
+  while (P < len) P <<= 1;
+  for (int t = threadIdx.x; t < P; t += NTHREADS) key[t] = t < len ? sperm[o0 + t] : 0xffffffffu;
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < (P >> 1); t += NTHREADS) {
+        const int lo = 2 * t - (t & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const uint32_t a = key[lo], c = key[hi];
+        if (((a & kIdxMask) > (c & kIdxMask)) == up) {
+          key[lo] = c;
+          key[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = threadIdx.x; t < len; t += NTHREADS) sperm[o0 + t] = key[t];
+}
+
+hipError_t launch_plan(int64_t d, int64_t k, const int32_t *h, const int8_t *s, int32_t *cnt,
+                       int32_t *off, int32_t *cursor, uint32_t *sperm, int *status,
+                       hipStream_t st) {
+  hipError_t e = launch_fill_zero<int32_t>(cnt, k, 1, k, st);
+  if (e != hipSuccess) return e;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((d + 255) / 256, 8192));
+  if (d > 0) hipLaunchKernelGGL(k_hist, dim3((unsigned)blocks), dim3(256), 0, st, d, k, h, cnt, status);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, k, cnt, off, cursor);
+  if (d > 0)
+    hipLaunchKernelGGL(k_scatter, dim3((unsigned)blocks), dim3(256), 0, st, d, k, h, s, cursor,
+                       sperm);
+  // buckets of length 2..1024, then 1025..MS_SORTED_MAX_SEGMENT
+  hipLaunchKernelGGL((k_segsort<1024, 256>), dim3((unsigned)k), dim3(256), 0, st, k, 0, off,
+                     sperm, status);
+  hipLaunchKernelGGL((k_segsort<MS_SORTED_MAX_SEGMENT, 1024>), dim3((unsigned)k), dim3(1024), 0,
+                     st, k, 1024, off, sperm, status);
+  return hipGetLastError();
+}
+
+__global__ void k_strip_sign(int64_t d, const uint32_t *__restrict__ sperm,
+                             int32_t *__restrict__ perm) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d;
+       i += (int64_t)gridDim.x * blockDim.x)
+    perm[i] = (int32_t)(sperm[i] & kIdxMask);
+}
+
+hipError_t launch_strip_sign(int64_t d, const uint32_t *sperm, int32_t *perm, hipStream_t st) {
+  if (d <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((d + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_strip_sign, dim3((unsigned)blocks), dim3(256), 0, st, d, sperm, perm);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ column access
+
+template <typename T>
+__device__ __forceinline__ const T *col_ptr(const Cols<T> &c, int j) {
+  return j < c.n_a ? c.A + (int64_t)j * c.lda : c.B + (int64_t)(j - c.n_a) * c.ldb;
+}
+
+// ------------------------------------------------------------------ atomic (Alg. 2)
+
+// One thread per (row, column): Y[h[i], c] += +-A[i, c] with a device-scope
+// floating-point atomic add.  Y must be zero on entry.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cs_atomic(int64_t d, int64_t k, Cols<T> cols,
+                                                   const uint32_t *__restrict__ code,
+                                                   T *__restrict__ Y, int64_t ldy, int *status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= d) return;
+  const uint32_t cd = code[i];
+  const int64_t b = (int64_t)(cd & kIdxMask);
+  if (b >= k) {
+    record_status(status, MS_ERR_RANGE);
+    return;
+  }
+  const T a = col_ptr(cols, c)[i];
+  unsafeAtomicAdd(&Y[b + (int64_t)c * ldy], apply_sign(a, cd));
+}
+
+template <typename T>
+hipError_t launch_cs_atomic(int64_t d, int64_t k, const Cols<T> &c, const uint32_t *code, T *Y,
+                            int64_t ldy, bool zero_first, int *status, hipStream_t st) {
+  hipError_t e = zero_first ? launch_fill_zero<T>(Y, k, c.ncols, ldy, st) : hipSuccess;
+  if (e != hipSuccess || d <= 0 || c.ncols <= 0) return e;
+  for (int c0 = 0; c0 < c.ncols; c0 += 65535) {
+    Cols<T> sub = c;
+    const int nc = std::min(65535, c.ncols - c0);
+    // shift the column window: columns c0.. of [A | B]
+    if (c0 < c.n_a) {
+      sub.A = c.A + (int64_t)c0 * c.lda;
+      sub.n_a = c.n_a - c0;
+    } else {
+      sub.A = nullptr;
+      sub.B = c.B + (int64_t)(c0 - c.n_a) * c.ldb;
+      sub.n_a = 0;
+    }
+    sub.ncols = nc;
+    hipLaunchKernelGGL(k_cs_atomic<T>, dim3((unsigned)((d + 255) / 256), nc), dim3(256), 0, st, d,
+                       k, sub, code, Y + (int64_t)c0 * ldy, ldy, status);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_cs_atomic<double>(int64_t, int64_t, const Cols<double> &,
+                                             const uint32_t *, double *, int64_t, bool, int *,
+                                             hipStream_t);
+template hipError_t launch_cs_atomic<float>(int64_t, int64_t, const Cols<float> &,
+                                            const uint32_t *, float *, int64_t, bool, int *,
+                                            hipStream_t);
+
+// ------------------------------------------------------------------ LDS-binned
+
+// 16-byte vector types for the streaming loads.
+template <typename T>
+struct Vec16;
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef uint32_t uvec2 __attribute__((ext_vector_type(2)));
+typedef uint32_t uvec4 __attribute__((ext_vector_type(4)));
+template <>
+struct Vec16<double> {
+  using type = dvec2;
+  static constexpr int N = 2;
+  using code_t = uvec2;
+};
+template <>
+struct Vec16<float> {
+  using type = fvec4;
+  static constexpr int N = 4;
+  using code_t = uvec4;
+};
+
+template <typename T>
+__device__ __forceinline__ T lane_of(const typename Vec16<T>::type &v, int q) {
+  return v[q];
+}
+template <typename CV>
+__device__ __forceinline__ uint32_t code_of(const CV &v, int q) {
+  return v[q];
+}
+
+// Workgroup (chunk, column tile, bucket tile): rows [r0, r1) of NT columns
+// starting at c0, buckets [b0, b0 + kt).  Partial sums live in LDS as
+// acc[b + j*kt]; rows whose bucket is outside the tile are skipped (only
+// when the buckets of a column do not fit in LDS at once).  Y must be zero
+// on entry; the flush adds each non-zero partial with one atomic.
+template <typename T, int NT, bool VEC>
+__global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
+                                                 const uint32_t *__restrict__ code, int64_t k,
+                                                 int64_t ktile, int64_t rows_per_chunk,
+                                                 T *__restrict__ Y, int64_t ldy, int *status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *acc = reinterpret_cast<T *>(smem_raw);
+  const int64_t b0 = (int64_t)blockIdx.z * ktile;
+  const uint32_t kt = (uint32_t)min(ktile, k - b0);
+  const int c0 = blockIdx.y * NT;
+  const int nc = min(NT, cols.ncols - c0);
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t r1 = min(d, r0 + rows_per_chunk);
+
+  for (uint32_t t = threadIdx.x; t < kt * NT; t += blockDim.x) acc[t] = T(0);
+  const T *cp[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) cp[j] = col_ptr(cols, min(c0 + j, cols.ncols - 1));
+  __syncthreads();
+
+  if (VEC) {
+    using V = typename Vec16<T>::type;
+    using CV = typename Vec16<T>::code_t;
+    constexpr int W = Vec16<T>::N;
+    const int64_t step = (int64_t)blockDim.x * W;
+    int64_t i = r0 + (int64_t)threadIdx.x * W;
+    // two vectors in flight per thread per iteration
+    for (; i + step + W <= r1; i += 2 * step) {
+      const CV cd0 = *reinterpret_cast<const CV *>(code + i);
+      const CV cd1 = *reinterpret_cast<const CV *>(code + i + step);
+      V a0[NT], a1[NT];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        a0[j] = __builtin_nontemporal_load(reinterpret_cast<const V *>(cp[j] + i));
+        a1[j] = __builtin_nontemporal_load(reinterpret_cast<const V *>(cp[j] + i + step));
+      }
+#pragma unroll
+      for (int q = 0; q < W; ++q) {
+        const uint32_t e0 = code_of(cd0, q), e1 = code_of(cd1, q);
+        const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
+        const uint32_t l1 = (e1 & kIdxMask) - (uint32_t)b0;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+          if (j < nc) {
+            if (l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(lane_of<T>(a0[j], q), e0));
+            if (l1 < kt) atomicAdd(&acc[l1 + j * kt], apply_sign(lane_of<T>(a1[j], q), e1));
+          }
+        }
+      }
+    }
+    for (; i < r1; i += step) {
+      if (i + W <= r1) {
+        const CV cd0 = *reinterpret_cast<const CV *>(code + i);
+        V a0[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) a0[j] = *reinterpret_cast<const V *>(cp[j] + i);
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+          const uint32_t e0 = code_of(cd0, q);
+          const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
+#pragma unroll
+          for (int j = 0; j < NT; ++j)
+            if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(lane_of<T>(a0[j], q), e0));
+        }
+      } else {
+        for (int64_t r = i; r < r1; ++r) {
+          const uint32_t e0 = code[r];
+          const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
+#pragma unroll
+          for (int j = 0; j < NT; ++j)
+            if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(cp[j][r], e0));
+        }
+      }
+    }
+  } else {
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+      const uint32_t e0 = code[r];
+      const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
+#pragma unroll
+      for (int j = 0; j < NT; ++j)
+        if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(cp[j][r], e0));
+    }
+  }
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < kt * (uint32_t)nc; t += blockDim.x) {
+    const uint32_t j = t / kt, b = t - j * kt;
+    const T v = acc[t];
+    if (v != T(0)) unsafeAtomicAdd(&Y[(b0 + b) + (int64_t)(c0 + j) * ldy], v);
+  }
+  // codes with a bucket >= k (only possible for codes not made by the pack
+  // kernel) were skipped above; the last bucket tile's first column tile
+  // reports them
+  if (blockIdx.z == gridDim.z - 1 && blockIdx.y == 0) {
+    bool bad = false;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) bad |= (int64_t)(code[r] & kIdxMask) >= k;
+    if (bad) record_status(status, MS_ERR_RANGE);
+  }
+}
+
+template <typename T, int NT>
+static hipError_t launch_cs_lds_nt(bool vec, dim3 grid, size_t lds, hipStream_t st, int64_t d,
+                                   const Cols<T> &c, const uint32_t *code, int64_t k,
+                                   int64_t ktile, int64_t rows, T *Y, int64_t ldy, int *status) {
+  const void *fn = vec ? (const void *)k_cs_lds<T, NT, true> : (const void *)k_cs_lds<T, NT, false>;
+  hipError_t e = allow_dynamic_lds(fn, (int)lds);
+  if (e != hipSuccess) return e;
+  if (vec)
+    hipLaunchKernelGGL((k_cs_lds<T, NT, true>), grid, dim3(1024), lds, st, d, c, code, k, ktile,
+                       rows, Y, ldy, status);
+  else
+    hipLaunchKernelGGL((k_cs_lds<T, NT, false>), grid, dim3(1024), lds, st, d, c, code, k, ktile,
+                       rows, Y, ldy, status);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t *code, T *Y,
+                         int64_t ldy, bool zero_first, int *status, hipStream_t st) {
+  hipError_t e = zero_first ? launch_fill_zero<T>(Y, k, c.ncols, ldy, st) : hipSuccess;
+  if (e != hipSuccess || d <= 0 || c.ncols <= 0) return e;
+  const DevInfo &di = dev_info();
+  const int64_t w = sizeof(T);
+  const int64_t cap = std::min<int64_t>(di.lds_per_block, 128 * 1024);
+  // bucket tile: all k buckets when one column fits, else the largest
+  // power-of-two tile that does
+  int64_t ktile = k;
+  if (k * w > cap) {
+    ktile = 1;
+    while (ktile * 2 * w <= cap) ktile *= 2;
+  }
+  const int64_t nbt = (k + ktile - 1) / ktile;
+  const int64_t lds1 = ktile * w;
+  const int64_t per_cu1 = std::max<int64_t>(1, std::min<int64_t>(2, di.lds_per_block / lds1));
+  // rows per chunk never below 2048; columns per workgroup (nt) as many as
+  // LDS holds while there is still at least one workgroup per slot
+  const int64_t c_hi = std::max<int64_t>(1, d / 2048);
+  int nt = 1;
+  while (nt < 8 && lds1 * nt * 2 <= cap && nt * 2 <= c.ncols) {
+    const int64_t units2 = ((c.ncols + nt * 2 - 1) / (nt * 2)) * nbt;
+    const int64_t per_cu2 = std::max<int64_t>(1, std::min<int64_t>(2, di.lds_per_block / (lds1 * nt * 2)));
+    if (units2 * c_hi < (int64_t)di.cus * per_cu2) break;
+    nt *= 2;
+  }
+  (void)per_cu1;
+  const int64_t nct = (c.ncols + nt - 1) / nt;
+  const int64_t lds = lds1 * nt;
+  const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(2, di.lds_per_block / lds));
+  const int64_t slots = (int64_t)di.cus * per_cu;
+  // enough chunks to fill every slot, more while the LDS flush (ktile
+  // partials per chunk) stays under 1/16 of the streamed rows; then rounded
+  // to whole rounds of resident workgroups
+  const int64_t units = nct * nbt;
+  const int64_t c_flush = std::max<int64_t>(1, d / (16 * ktile));
+  int64_t chunks = std::min(c_hi, std::max(c_flush, (slots + units - 1) / units));
+  const int64_t rounds = std::max<int64_t>(1, (units * chunks + slots / 2) / slots);
+  chunks = std::max<int64_t>(1, std::min(c_hi, rounds * slots / units));
+  int64_t rows = (d + chunks - 1) / chunks;
+  rows = (rows + 255) / 256 * 256;
+  chunks = (d + rows - 1) / rows;
+  const uintptr_t mis = (reinterpret_cast<uintptr_t>(c.A) | reinterpret_cast<uintptr_t>(c.B) |
+                         (uintptr_t)(c.lda * w) | (uintptr_t)(c.B ? c.ldb * w : 0));
+  const bool vec = (mis & 15) == 0;
+  const dim3 grid((unsigned)chunks, (unsigned)nct, (unsigned)nbt);
+  switch (nt) {
+    case 8: return launch_cs_lds_nt<T, 8>(vec, grid, lds, st, d, c, code, k, ktile, rows, Y, ldy, status);
+    case 4: return launch_cs_lds_nt<T, 4>(vec, grid, lds, st, d, c, code, k, ktile, rows, Y, ldy, status);
+    case 2: return launch_cs_lds_nt<T, 2>(vec, grid, lds, st, d, c, code, k, ktile, rows, Y, ldy, status);
+    default: return launch_cs_lds_nt<T, 1>(vec, grid, lds, st, d, c, code, k, ktile, rows, Y, ldy, status);
+  }
+}
+template hipError_t launch_cs_lds<double>(int64_t, int64_t, const Cols<double> &, const uint32_t *,
+                                          double *, int64_t, bool, int *, hipStream_t);
+template hipError_t launch_cs_lds<float>(int64_t, int64_t, const Cols<float> &, const uint32_t *,
+                                         float *, int64_t, bool, int *, hipStream_t);
+
+// ------------------------------------------------------------------ sorted (deterministic)
+
+// One thread per (bucket, column): the bucket's rows, in ascending row order
+// (sperm from the stable plan), are folded into +0.0 one after the other --
+// exactly the sequential order of Alg. 2, so the result is bit-identical to
+// it.  Loads are issued four ahead of the dependent adds.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cs_sorted(int64_t k, Cols<T> cols,
+                                                   const int32_t *__restrict__ off,
+                                                   const uint32_t *__restrict__ sperm,
+                                                   T *__restrict__ Y, int64_t ldy) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (b >= k) return;
+  const T *cp = col_ptr(cols, c);
+  const int32_t j0 = off[b], j1 = off[b + 1];
+  T y = T(0);
+  int32_t j = j0;
+  for (; j + 4 <= j1; j += 4) {
+    const uint32_t e0 = sperm[j], e1 = sperm[j + 1], e2 = sperm[j + 2], e3 = sperm[j + 3];
+    const T a0 = cp[e0 & kIdxMask], a1 = cp[e1 & kIdxMask], a2 = cp[e2 & kIdxMask],
+            a3 = cp[e3 & kIdxMask];
+    y = y + apply_sign(a0, e0);
+    y = y + apply_sign(a1, e1);
+    y = y + apply_sign(a2, e2);
+    y = y + apply_sign(a3, e3);
+  }
+  for (; j < j1; ++j) {
+    const uint32_t e = sperm[j];
+    y = y + apply_sign(cp[e & kIdxMask], e);
+  }
+  Y[b + (int64_t)c * ldy] = y;
+}
+
+template <typename T>
+hipError_t launch_cs_sorted(int64_t k, const Cols<T> &c, const int32_t *off,
+                            const uint32_t *sperm, T *Y, int64_t ldy, hipStream_t st) {
+  if (c.ncols <= 0) return hipSuccess;
+  for (int c0 = 0; c0 < c.ncols; c0 += 65535) {
+    Cols<T> sub = c;
+    const int nc = std::min(65535, c.ncols - c0);
+    if (c0 < c.n_a) {
+      sub.A = c.A + (int64_t)c0 * c.lda;
+      sub.n_a = c.n_a - c0;
+    } else {
+      sub.A = nullptr;
+      sub.B = c.B + (int64_t)(c0 - c.n_a) * c.ldb;
+      sub.n_a = 0;
+    }
+    sub.ncols = nc;
+    hipLaunchKernelGGL(k_cs_sorted<T>, dim3((unsigned)((k + 255) / 256), nc), dim3(256), 0, st, k,
+                       sub, off, sperm, Y + (int64_t)c0 * ldy, ldy);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_cs_sorted<double>(int64_t, const Cols<double> &, const int32_t *,
+                                             const uint32_t *, double *, int64_t, hipStream_t);
+template hipError_t launch_cs_sorted<float>(int64_t, const Cols<float> &, const int32_t *,
+                                            const uint32_t *, float *, int64_t, hipStream_t);
+
+}  // namespace ms

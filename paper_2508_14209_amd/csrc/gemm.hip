@@ -1,0 +1,332 @@
+// gemm.hip -- the Gaussian stage Z = G Y of the multisketch S2(S1 x)
+// (Sec. 1 of Higgins, Boman, Yamazaki, arXiv 2508.14209; Table 1), on the
+// gfx950 matrix cores.
+//
+// Shapes are short and wide in K: M = k2 (2n), N = n + nrhs, K = k (2n^2).
+// The K dimension is split across workgroups; each writes a partial M x N
+// block and a second kernel adds the partials in split order (fixed, so the
+// result does not depend on scheduling).
+//
+// Matrix-core instructions (one 16x16 output block per instruction):
+//   FP64: v_mfma_f64_16x16x4_f64       (K step 4)
+//   FP32: v_mfma_f32_16x16x4_f32       (K step 4)
+//   BF16: v_mfma_f32_16x16x32_bf16     (K step 32, FP32 accumulation)
+// Operand layout per lane l (64 lanes): A element (row l%16, k-group l/16),
+// B element (k-group l/16, column l%16).  The four accumulator values r of
+// lane l belong to column l%16 and to row 4*(l/16)+r for the FP32 and BF16
+// instructions, but to row (l/16)+4*r for the FP64 one (measured).
+#include <algorithm>
+
+#include "ms_internal.h"
+
+namespace ms {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef unsigned short v8u16 __attribute__((ext_vector_type(8)));
+
+// FP32 -> BF16 bits, round to nearest, ties to even (NaN kept quiet).
+__device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu) != 0u)
+    return (unsigned short)((u | 0x00400000u) >> 16);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
+
+template <int DT>
+struct Mf;
+template <>
+struct Mf<DT_F64> {
+  using TG = double;
+  using TY = double;
+  using Acc = double;
+  using Frag = double;
+  using AccV = v4d;
+  static constexpr int KS = 4;
+  __device__ static AccV mma(Frag a, Frag b, AccV c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int out_row(int lk, int r) { return lk + 4 * r; }
+};
+template <>
+struct Mf<DT_F32> {
+  using TG = float;
+  using TY = float;
+  using Acc = float;
+  using Frag = float;
+  using AccV = v4f;
+  static constexpr int KS = 4;
+  __device__ static AccV mma(Frag a, Frag b, AccV c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int out_row(int lk, int r) { return 4 * lk + r; }
+};
+template <>
+struct Mf<DT_BF16> {
+  using TG = unsigned short;  // BF16 bit patterns
+  using TY = float;           // rounded to BF16 on load
+  using Acc = float;
+  using Frag = v8bf;
+  using AccV = v4f;
+  static constexpr int KS = 32;
+  __device__ static AccV mma(Frag a, Frag b, AccV c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+  __device__ static int out_row(int lk, int r) { return 4 * lk + r; }
+};
+
+// A fragment: G rows [row], k-group starting at kq (KS/4 consecutive k).
+template <int DT>
+__device__ __forceinline__ typename Mf<DT>::Frag load_a(const typename Mf<DT>::TG *G, int64_t ldg,
+                                                        int M, int row, int64_t kq, int64_t ke);
+template <>
+__device__ __forceinline__ double load_a<DT_F64>(const double *G, int64_t ldg, int M, int row,
+                                                 int64_t kq, int64_t ke) {
+  return (row < M && kq < ke) ? G[row + kq * ldg] : 0.0;
+}
+template <>
+__device__ __forceinline__ float load_a<DT_F32>(const float *G, int64_t ldg, int M, int row,
+                                                int64_t kq, int64_t ke) {
+  return (row < M && kq < ke) ? G[row + kq * ldg] : 0.0f;
+}
+template <>
+__device__ __forceinline__ v8bf load_a<DT_BF16>(const unsigned short *G, int64_t ldg, int M,
+                                                int row, int64_t kq, int64_t ke) {
+  v8u16 u;
+#pragma unroll
+  for (int t = 0; t < 8; ++t) u[t] = (row < M && kq + t < ke) ? G[row + (kq + t) * ldg] : 0;
+  return __builtin_bit_cast(v8bf, u);
+}
+
+// B fragment: Y column [col], k-group starting at kq.
+template <int DT>
+__device__ __forceinline__ typename Mf<DT>::Frag load_b(const typename Mf<DT>::TY *Y, int64_t ldy,
+                                                        int N, int col, int64_t kq, int64_t ke);
+template <>
+__device__ __forceinline__ double load_b<DT_F64>(const double *Y, int64_t ldy, int N, int col,
+                                                 int64_t kq, int64_t ke) {
+  return (col < N && kq < ke) ? Y[kq + (int64_t)col * ldy] : 0.0;
+}
+template <>
+__device__ __forceinline__ float load_b<DT_F32>(const float *Y, int64_t ldy, int N, int col,
+                                                int64_t kq, int64_t ke) {
+  return (col < N && kq < ke) ? Y[kq + (int64_t)col * ldy] : 0.0f;
+}
+template <>
+__device__ __forceinline__ v8bf load_b<DT_BF16>(const float *Y, int64_t ldy, int N, int col,
+                                                int64_t kq, int64_t ke) {
+  v8u16 u;
+#pragma unroll
+  for (int t = 0; t < 8; ++t)
+    u[t] = (col < N && kq + t < ke) ? f32_to_bf16_rne(Y[kq + t + (int64_t)col * ldy]) : 0;
+  return __builtin_bit_cast(v8bf, u);
+}
+
+// Workgroup = 4 waves over a 64 x 64 output tile (each wave 32 x 32, i.e.
+// 2 x 2 matrix-core blocks), one K chunk per blockIdx.z.
+template <int DT>
+__global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
+                                                     const typename Mf<DT>::TG *__restrict__ G,
+                                                     int64_t ldg,
+                                                     const typename Mf<DT>::TY *__restrict__ Y,
+                                                     int64_t ldy,
+                                                     typename Mf<DT>::Acc *__restrict__ part,
+                                                     int64_t kchunk) {
+  using F = Mf<DT>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int m_base = blockIdx.x * 64 + (wave & 1) * 32;
+  const int n_base = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = min(K, kb + kchunk);
+  constexpr int KPL = F::KS / 4;  // k values per lane per instruction
+  typename F::AccV acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = typename F::AccV{};
+  for (int64_t kk = kb; kk < ke; kk += F::KS) {
+    const int64_t kq = kk + (int64_t)lk * KPL;
+    typename F::Frag a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = load_a<DT>(G, ldg, M, m_base + 16 * i + li, kq, ke);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = load_b<DT>(Y, ldy, N, n_base + 16 * j + li, kq, ke);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = F::mma(a[i], b[j], acc[i][j]);
+  }
+  typename F::Acc *P = part + (int64_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n_base + 16 * j + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m_base + 16 * i + F::out_row(lk, r);
+        if (row < M && col < N) P[row + (int64_t)col * M] = acc[i][j][r];
+      }
+    }
+}
+
+// Z[p, c] = sum over splits (in split order) of the partials; written to Z
+// (its own dtype and leading dimension) and/or to an FP64 copy z64 (ld = M).
+template <typename Acc, typename TZ>
+__global__ void k_reduce_splits(int M, int N, int nsplit, const Acc *__restrict__ part,
+                                TZ *__restrict__ Z, int64_t ldz, double *__restrict__ z64) {
+  const int64_t MN = (int64_t)M * N;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < MN;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    Acc s = part[t];
+    for (int z = 1; z < nsplit; ++z) s = s + part[t + z * MN];
+    const int64_t c = t / M, p = t - c * M;
+    if (Z) Z[p + c * ldz] = (TZ)s;
+    if (z64) z64[t] = (double)s;
+  }
+}
+
+GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K, ms_dtype g_dtype) {
+  GemmPlan p{};
+  p.M = (int)M;
+  p.N = (int)N;
+  p.K = K;
+  p.tiles_m = (int)((M + 63) / 64);
+  p.tiles_n = (int)((N + 63) / 64);
+  const int64_t ks = g_dtype == MS_BF16 ? 32 : 4;
+  const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
+  // aim for ~1024 workgroups but keep at least 256 K values per workgroup
+  int64_t ns = std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, (K + 255) / 256));
+  ns = std::min<int64_t>(ns, 65535);
+  int64_t kc = (K + ns - 1) / ns;
+  kc = (kc + ks - 1) / ks * ks;
+  if (kc < ks) kc = ks;
+  p.kchunk = kc;
+  p.nsplit = (int)((K + kc - 1) / kc);
+  if (p.nsplit < 1) p.nsplit = 1;
+  const size_t acc = g_dtype == MS_F64 ? 8 : 4;
+  p.partial_bytes = (size_t)p.nsplit * (size_t)M * (size_t)N * acc;
+  p.ybf16_bytes = 0;
+  return p;
+}
+
+hipError_t launch_gemm(const GemmPlan &p, ms_dtype g_dtype, const void *G, int64_t ldg,
+                       const void *Y, int64_t ldy, void *Z, int64_t ldz, double *z64,
+                       void *partials, void *ybf16, hipStream_t st) {
+  (void)ybf16;
+  if (p.M <= 0 || p.N <= 0) return hipSuccess;
+  const int64_t MN = (int64_t)p.M * p.N;
+  const unsigned rblocks = (unsigned)std::min<int64_t>((MN + 255) / 256, 4096);
+  if (p.K <= 0) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)p.tiles_m, (unsigned)p.tiles_n, (unsigned)p.nsplit);
+  switch (g_dtype) {
+    case MS_F64:
+      hipLaunchKernelGGL(k_gemm_splitk<DT_F64>, grid, dim3(256), 0, st, p.M, p.N, p.K,
+                         (const double *)G, ldg, (const double *)Y, ldy, (double *)partials,
+                         p.kchunk);
+      hipLaunchKernelGGL((k_reduce_splits<double, double>), dim3(rblocks), dim3(256), 0, st, p.M,
+                         p.N, p.nsplit, (const double *)partials, (double *)Z, ldz, z64);
+      break;
+    case MS_F32:
+      hipLaunchKernelGGL(k_gemm_splitk<DT_F32>, grid, dim3(256), 0, st, p.M, p.N, p.K,
+                         (const float *)G, ldg, (const float *)Y, ldy, (float *)partials,
+                         p.kchunk);
+      hipLaunchKernelGGL((k_reduce_splits<float, float>), dim3(rblocks), dim3(256), 0, st, p.M,
+                         p.N, p.nsplit, (const float *)partials, (float *)Z, ldz, z64);
+      break;
+    case MS_BF16:
+      hipLaunchKernelGGL(k_gemm_splitk<DT_BF16>, grid, dim3(256), 0, st, p.M, p.N, p.K,
+                         (const unsigned short *)G, ldg, (const float *)Y, ldy, (float *)partials,
+                         p.kchunk);
+      hipLaunchKernelGGL((k_reduce_splits<float, float>), dim3(rblocks), dim3(256), 0, st, p.M,
+                         p.N, p.nsplit, (const float *)partials, (float *)Z, ldz, z64);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ FP64-accumulating GEMV
+// Z64 (M x N, ld M) = G Y64 for a narrow FP64 right operand (N <= 8), G of
+// any stored dtype, all products and sums in FP64.  Used by the refinement
+// correction, where the sketched residual must keep FP64 accuracy.  Thread p
+// owns row p of Z; workgroup z takes a K chunk; partials are reduced in order.
+template <typename TG>
+__device__ __forceinline__ double g_as_f64(TG v);
+template <>
+__device__ __forceinline__ double g_as_f64<double>(double v) { return v; }
+template <>
+__device__ __forceinline__ double g_as_f64<float>(float v) { return (double)v; }
+template <>
+__device__ __forceinline__ double g_as_f64<unsigned short>(unsigned short v) {
+  return (double)__uint_as_float((uint32_t)v << 16);
+}
+
+template <typename TG>
+__global__ __launch_bounds__(256) void k_gemv64_splitk(int M, int N, int64_t K,
+                                                       const TG *__restrict__ G, int64_t ldg,
+                                                       const double *__restrict__ Y, int64_t ldy,
+                                                       double *__restrict__ part, int64_t kchunk) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t kb = (int64_t)blockIdx.y * kchunk;
+  const int64_t ke = min(K, kb + kchunk);
+  double acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  if (p < M) {
+    for (int64_t m = kb; m < ke; ++m) {
+      const double g = g_as_f64<TG>(G[p + m * ldg]);
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < N) acc[c] += g * Y[m + (int64_t)c * ldy];
+    }
+    double *P = part + (int64_t)blockIdx.y * M * N;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (c < N) P[p + (int64_t)c * M] = acc[c];
+  }
+}
+
+size_t gemv64_partial_bytes(int64_t M, int64_t N, int64_t K) {
+  const int64_t ns = std::max<int64_t>(1, std::min<int64_t>(1024, (K + 511) / 512));
+  return (size_t)ns * (size_t)M * (size_t)N * 8;
+}
+
+hipError_t launch_gemv64(int64_t M, int64_t N, int64_t K, ms_dtype g_dtype, const void *G,
+                         int64_t ldg, const double *Y, int64_t ldy, double *z64, double *part,
+                         hipStream_t st) {
+  if (N > 8 || M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
+  int64_t ns = std::max<int64_t>(1, std::min<int64_t>(1024, (K + 511) / 512));
+  const int64_t kc = (K + ns - 1) / ns;
+  ns = (K + kc - 1) / kc;
+  const dim3 grid((unsigned)((M + 255) / 256), (unsigned)ns);
+  switch (g_dtype) {
+    case MS_F64:
+      hipLaunchKernelGGL(k_gemv64_splitk<double>, grid, dim3(256), 0, st, (int)M, (int)N, K,
+                         (const double *)G, ldg, Y, ldy, part, kc);
+      break;
+    case MS_F32:
+      hipLaunchKernelGGL(k_gemv64_splitk<float>, grid, dim3(256), 0, st, (int)M, (int)N, K,
+                         (const float *)G, ldg, Y, ldy, part, kc);
+      break;
+    case MS_BF16:
+      hipLaunchKernelGGL(k_gemv64_splitk<unsigned short>, grid, dim3(256), 0, st, (int)M, (int)N,
+                         K, (const unsigned short *)G, ldg, Y, ldy, part, kc);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  const int64_t MN = M * N;
+  const unsigned rblocks = (unsigned)std::min<int64_t>((MN + 255) / 256, 4096);
+  hipLaunchKernelGGL((k_reduce_splits<double, double>), dim3(rblocks), dim3(256), 0, st, (int)M,
+                     (int)N, (int)ns, (const double *)part, (double *)nullptr, (int64_t)M, z64);
+  return hipGetLastError();
+}
+
+}  // namespace ms

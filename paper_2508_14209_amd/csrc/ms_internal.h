@@ -1,0 +1,141 @@
+// ms_internal.h -- shared declarations of libmsketch's HIP translation units.
+//
+// Device helpers, the workspace layout and the host-side launchers each
+// kernel file exports to the C-ABI layer (api.hip).  Nothing here is part of
+// the public ABI (include/msketch.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "msketch.h"
+
+namespace ms {
+
+// ---------------------------------------------------------------- device info
+struct DevInfo {
+  int cus = 0;            // compute units
+  int lds_per_block = 0;  // bytes of LDS one workgroup may allocate
+  int xcds = 8;           // accelerator complex dies (L2 domains)
+};
+// Properties of the current device, queried once per device and cached.
+const DevInfo &dev_info();
+// Raise a kernel's dynamic-LDS limit once per (kernel, device).
+hipError_t allow_dynamic_lds(const void *kernel, int bytes);
+
+// ---------------------------------------------------------------- status word
+// The first 256 bytes of every workspace hold an int32 status; kernels record
+// the first device-side error with a compare-and-swap from MS_OK.
+__device__ inline void record_status(int *st, int code) {
+  atomicCAS(st, (int)MS_OK, code);
+}
+
+// ---------------------------------------------------------------- sign codes
+// A row's bucket and sign packed in one word: bits 0..30 hold h[i], bit 31 is
+// set when s[i] = -1.  The same packing carries a row index and its sign in
+// the sorted plan.
+constexpr uint32_t kSignBit = 0x80000000u;
+constexpr uint32_t kIdxMask = 0x7fffffffu;
+
+// +-a selected by the sign bit of `code`: flipping the IEEE sign bit is exact
+// negation, so this is the add-or-subtract of Alg. 2 with no multiply.
+__device__ __forceinline__ float apply_sign(float a, uint32_t code) {
+  return __uint_as_float(__float_as_uint(a) ^ (code & kSignBit));
+}
+__device__ __forceinline__ double apply_sign(double a, uint32_t code) {
+  uint64_t u = (uint64_t)__double_as_longlong(a) ^ ((uint64_t)(code & kSignBit) << 32);
+  return __longlong_as_double((long long)u);
+}
+
+// ---------------------------------------------------------------- workspace
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+inline size_t dtype_size(ms_dtype t) {
+  return t == MS_F64 ? 8 : t == MS_F32 ? 4 : 2;
+}
+
+// Bump allocator over the caller's workspace (offsets only; no allocation).
+struct Carve {
+  size_t off = kAlign;  // the status word occupies the first block
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes ? bytes : 1);
+    return o;
+  }
+};
+
+// ---------------------------------------------------------------- launchers
+// Columns of the sketched operand [A | B]: column c < n_a is A's column c,
+// the rest are B's.  B may be null when n_a == ncols.
+template <typename T>
+struct Cols {
+  const T *A;
+  int64_t lda;
+  const T *B;
+  int64_t ldb;
+  int n_a;
+  int ncols;
+};
+
+// countsketch.hip
+hipError_t launch_zero_status(int *status, hipStream_t st);
+template <typename T>
+hipError_t launch_fill_zero(T *Y, int64_t rows, int64_t cols, int64_t ld, hipStream_t st);
+hipError_t launch_pack_codes(int64_t d, int64_t k, const int32_t *h, const int8_t *s,
+                             uint32_t *code, int *status, hipStream_t st);
+// Plan: cnt (k), off (k+1), cursor (k), sperm (d) -- row index | sign bit
+// (sign bit only when s is non-null).
+hipError_t launch_plan(int64_t d, int64_t k, const int32_t *h, const int8_t *s,
+                       int32_t *cnt, int32_t *off, int32_t *cursor, uint32_t *sperm,
+                       int *status, hipStream_t st);
+hipError_t launch_strip_sign(int64_t d, const uint32_t *sperm, int32_t *perm, hipStream_t st);
+
+// zero_first: clear Y before accumulating (false: Y += S [A | B]).  status
+// receives MS_ERR_RANGE for a code whose bucket is >= k (such rows are skipped).
+template <typename T>
+hipError_t launch_cs_atomic(int64_t d, int64_t k, const Cols<T> &c, const uint32_t *code,
+                            T *Y, int64_t ldy, bool zero_first, int *status, hipStream_t st);
+template <typename T>
+hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t *code,
+                         T *Y, int64_t ldy, bool zero_first, int *status, hipStream_t st);
+template <typename T>
+hipError_t launch_cs_sorted(int64_t k, const Cols<T> &c, const int32_t *off,
+                            const uint32_t *sperm, T *Y, int64_t ldy, hipStream_t st);
+
+// gemm.hip -- Z = G Y through split-K partial sums reduced in a fixed order.
+struct GemmPlan {
+  int M, N;
+  int64_t K;
+  int tiles_m, tiles_n, nsplit;
+  int64_t kchunk;
+  size_t partial_bytes;  // workspace for the split-K partials
+  size_t ybf16_bytes;    // workspace for the BF16 copy of Y (BF16 path)
+};
+GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K, ms_dtype g_dtype);
+// z64 (optional) receives an FP64 copy of Z (ldz64 = M).
+hipError_t launch_gemm(const GemmPlan &p, ms_dtype g_dtype, const void *G, int64_t ldg,
+                       const void *Y, int64_t ldy, void *Z, int64_t ldz, double *z64,
+                       void *partials, void *ybf16, hipStream_t st);
+
+// Z64 (M x N, ld M) = G Y64 in FP64 for N <= 8 (refinement correction).
+size_t gemv64_partial_bytes(int64_t M, int64_t N, int64_t K);
+hipError_t launch_gemv64(int64_t M, int64_t N, int64_t K, ms_dtype g_dtype, const void *G,
+                         int64_t ldg, const double *Y, int64_t ldy, double *z64, double *part,
+                         hipStream_t st);
+
+// qr.hip -- Householder QR least squares of a small FP64 system.
+size_t qr_workspace_bytes(int64_t m, int64_t n, int64_t nrhs);
+hipError_t launch_qr_solve(int64_t m, int64_t n, int64_t nrhs, const double *W, int64_t ldw,
+                           const double *Bm, int64_t ldb, double *X, int64_t ldx, double *R,
+                           int64_t ldr, double *tau_out, double *fact_out, void *qr_ws,
+                           int *status, hipStream_t st);
+// X = R^{-1} (Q^T Bm)_{0:n} from factors kept by launch_qr_solve (fact: m x n
+// with R on and above the diagonal and the reflector tails below, ld m; tau:
+// n).  Bm (m x nrhs, ld m) is overwritten.
+hipError_t launch_qr_apply_solve(int64_t m, int64_t n, int64_t nrhs, const double *fact,
+                                 const double *tau, double *Bm, double *X, int64_t ldx,
+                                 int *status, hipStream_t st);
+
+}  // namespace ms

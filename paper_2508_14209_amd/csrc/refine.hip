@@ -1,0 +1,72 @@
+// refine.hip -- FP64 residual of the mixed-precision least-squares path.
+//
+// r = B - A X in FP64: A (d x n, FP32 or FP64, column-major) is promoted exactly,
+// X (n x nrhs) and B are FP64/FP32, every product and sum is FP64.  One
+// thread per row; for each column j of A the threads of a wave read 64
+// consecutive rows (coalesced) and X[j, :] is a broadcast load.
+#include <algorithm>
+
+#include "ms_internal.h"
+
+namespace ms {
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(256) void k_residual(int64_t d, int n, int nrhs,
+                                                  const TA *__restrict__ A, int64_t lda,
+                                                  const TB *__restrict__ B, int64_t ldb,
+                                                  const double *__restrict__ X, int64_t ldx,
+                                                  double *__restrict__ r, int64_t ldr) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d) return;
+  double acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  for (int j = 0; j < n; ++j) {
+    const double a = (double)A[i + (int64_t)j * lda];
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (c < nrhs) acc[c] += a * X[j + (int64_t)c * ldx];
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    if (c < nrhs) r[i + (int64_t)c * ldr] = (double)B[i + (int64_t)c * ldb] - acc[c];
+}
+
+hipError_t launch_residual_f32(int64_t d, int64_t n, int64_t nrhs, const float *A, int64_t lda,
+                               const float *B, int64_t ldb, const double *X, int64_t ldx,
+                               double *r, int64_t ldr, hipStream_t st) {
+  if (nrhs > 8) return hipErrorInvalidValue;
+  if (d <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_residual<float, float>), dim3((unsigned)((d + 255) / 256)), dim3(256), 0,
+                     st, d, (int)n, (int)nrhs, A, lda, B, ldb, X, ldx, r, ldr);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_f64(int64_t d, int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                               const double *B, int64_t ldb, const double *X, int64_t ldx,
+                               double *r, int64_t ldr, hipStream_t st) {
+  if (nrhs > 8) return hipErrorInvalidValue;
+  if (d <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_residual<double, double>), dim3((unsigned)((d + 255) / 256)), dim3(256),
+                     0, st, d, (int)n, (int)nrhs, A, lda, B, ldb, X, ldx, r, ldr);
+  return hipGetLastError();
+}
+
+// X += dX (n x nrhs).
+__global__ void k_axpy_update(int n, int nrhs, const double *__restrict__ dX, double *X,
+                              int64_t ldx) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * nrhs) return;
+  const int c = (int)(t / n), i = (int)(t - (int64_t)c * n);
+  X[i + (int64_t)c * ldx] += dX[t];
+}
+
+hipError_t launch_axpy_update(int64_t n, int64_t nrhs, const double *dX, double *X, int64_t ldx,
+                              hipStream_t st) {
+  const int64_t t = n * nrhs;
+  hipLaunchKernelGGL(k_axpy_update, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, (int)n,
+                     (int)nrhs, dX, X, ldx);
+  return hipGetLastError();
+}
+
+}  // namespace ms

@@ -1,0 +1,95 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point ``include/msketch.h`` declares, sizes workspaces, and
+rejects invalid arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "msketch.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w]*\s*\**\s+\**([A-Za-z_]\w*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+@pytest.fixture(scope="module")
+def ms():
+    import paper_2508_14209_amd as ms
+    return ms
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ["countsketch_apply", "multisketch_apply", "sketch_lstsq", "ms_bucket_plan",
+              "ms_gaussian_apply", "ms_qr_solve", "ms_workspace_size", "ms_check_status",
+              "ms_status_string"]:
+        assert n in names, n
+
+
+def test_library_exports_every_declared_symbol(ms):
+    lib = ctypes.CDLL(ms.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_workspace_sizes(ms):
+    for op, kw in [("bucket_plan", dict(d=1000, k=64)),
+                   ("countsketch", dict(d=1000, n=3, k=64)),
+                   ("countsketch", dict(d=1000, n=3, k=64, mode="sorted")),
+                   ("gaussian", dict(n=9, k=128, k2=16)),
+                   ("multisketch", dict(d=1000, n=8, k=128, k2=16)),
+                   ("qr_solve", dict(n=64, nrhs=1, k2=128)),
+                   ("lstsq", dict(d=4194304, n=64, nrhs=1, k=8192, k2=128)),
+                   ("lstsq", dict(d=1 << 20, n=32, nrhs=4, k=2048, k2=64, a_dtype=1, g_dtype=2,
+                                  refine_steps=3))]:
+        sz = ms.workspace_size(op, **kw)
+        assert sz >= 256 and sz % 256 == 0, (op, kw, sz)
+    # the sorted plan needs more room than the packed codes
+    assert ms.workspace_size("countsketch", d=10 ** 6, n=3, k=64, mode="sorted") > \
+        ms.workspace_size("countsketch", d=10 ** 6, n=3, k=64, mode="lds")
+    # refinement buffers are only carved when asked for
+    a = ms.workspace_size("lstsq", d=1 << 20, n=32, nrhs=4, k=2048, k2=64, a_dtype=1, g_dtype=2)
+    b = ms.workspace_size("lstsq", d=1 << 20, n=32, nrhs=4, k=2048, k2=64, a_dtype=1, g_dtype=2,
+                          refine_steps=1)
+    assert b > a + (1 << 20) * 4 * 8
+
+
+def test_invalid_arguments_rejected_on_host(ms):
+    lib = ms._lib
+    ws = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+    o = ms.MsOpts(0, 0, 0, 0)
+    P = ctypes.c_void_p(0x2000)
+    # negative sizes, k < 1, lda < d, unknown dtype, unknown mode, null workspace
+    assert lib.countsketch_apply(-1, 1, 4, 0, P, 1, P, P, P, 4, ctypes.byref(o), ws, 1 << 20, None) == ms.MS_ERR_ARG
+    assert lib.countsketch_apply(10, 1, 0, 0, P, 10, P, P, P, 4, ctypes.byref(o), ws, 1 << 20, None) == ms.MS_ERR_ARG
+    assert lib.countsketch_apply(10, 1, 4, 0, P, 9, P, P, P, 4, ctypes.byref(o), ws, 1 << 20, None) == ms.MS_ERR_ARG
+    assert lib.countsketch_apply(10, 1, 4, 7, P, 10, P, P, P, 4, ctypes.byref(o), ws, 1 << 20, None) == ms.MS_ERR_ARG
+    assert lib.countsketch_apply(10, 1, 4, 0, P, 10, P, P, P, 4, ctypes.byref(o), None, 1 << 20, None) == ms.MS_ERR_ARG
+    bad = ms.MsOpts(9, 0, 0, 0)
+    assert lib.countsketch_apply(10, 1, 4, 0, P, 10, P, P, P, 4, ctypes.byref(bad), ws, 1 << 20, None) == ms.MS_ERR_ARG
+    # workspace too small
+    assert lib.countsketch_apply(10, 1, 4, 0, P, 10, P, P, P, 4, ctypes.byref(o), ws, 16, None) == ms.MS_ERR_NOMEM
+    # dtype combinations the Gaussian stage does not support
+    assert lib.ms_gaussian_apply(8, 2, 4, 0, P, 4, 1, P, 8, P, 4, ws, 1 << 20, None) == ms.MS_ERR_ARG
+    assert lib.ms_gaussian_apply(8, 2, 4, 2, P, 4, 0, P, 8, P, 4, ws, 1 << 20, None) == ms.MS_ERR_ARG
+    # k2 < n for least squares; refinement with too many right-hand sides
+    assert lib.sketch_lstsq(100, 8, 1, 32, 4, 0, P, 100, P, 100, P, P, 0, P, 4, P, 8,
+                            ctypes.byref(o), ws, 1 << 30, None) == ms.MS_ERR_ARG
+    r = ms.MsOpts(0, 2, 0, 0)
+    assert lib.sketch_lstsq(100, 8, 9, 32, 16, 1, P, 100, P, 100, P, P, 1, P, 16, P, 8,
+                            ctypes.byref(r), ws, 1 << 30, None) == ms.MS_ERR_UNSUPPORTED
+    # QR: m < n
+    assert lib.ms_qr_solve(4, 8, 1, P, 4, P, 4, P, 8, None, 8, ws, 1 << 20, None) == ms.MS_ERR_ARG
+    assert lib.ms_check_status(None, None) == ms.MS_ERR_ARG
+    assert lib.ms_workspace_size(99, 1, 1, 1, 1, 1, 0, 0, None) == 0
+
+
+def test_status_strings(ms):
+    for code in range(7):
+        assert ms._lib.ms_status_string(code).decode().startswith("MS_")

@@ -1,0 +1,242 @@
+"""GPU parity: Gaussian stage (MFMA), multisketch, Householder QR solve and
+the composite sketch-and-solve, against the oracle through the C ABI.
+
+Bar: normwise relative 1e-12 for FP64 results and 1e-5 for FP32 results
+(the Gaussian stage in FP32, or BF16 products with FP32 accumulation against
+the oracle's FP64 sum of the same BF16 operands).  The least-squares solution
+of a well-conditioned FP64 problem is held to 1e-12; ill-conditioned FP32
+problems are judged by their residual ratio, since their forward error is of
+order kappa * u32 on both sides.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import bf16_dev, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ms():
+    import paper_2508_14209_amd as ms
+    return ms
+
+
+# ------------------------------------------------------------------- Gaussian stage
+GEMM_CASES = [
+    # k2, k, ncols
+    (16, 128, 9),
+    (37, 1000, 13),     # ragged in every dimension
+    (128, 8192, 65),    # the 128 x 8192 stage of the FP64 workload
+    (64, 2048, 1),
+    (256, 32768, 129),  # the 256 x 32768 stage of the FP32 workload
+]
+
+
+@pytest.mark.parametrize("k2,k,nc", GEMM_CASES)
+@pytest.mark.parametrize("gd", ["f64", "f32", "bf16"])
+def test_gaussian_stage_parity(ms, orc, k2, k, nc, gd):
+    print("gaussian %s k2=%d k=%d nc=%d" % (gd, k2, k, nc), flush=True)
+    G = synth.gaussian_sketch(k2, k, seed=k2 + k, dtype=gd)
+    ydt = np.float64 if gd == "f64" else np.float32
+    Y = synth.normal_matrix(k, nc, seed=nc + 7, dtype=ydt)
+    Gd = bf16_dev(G) if gd == "bf16" else to_dev(G)
+    Z, ws = ms.gaussian_apply(Gd, to_dev(Y))
+    ms.check_status(ws)
+    Yref = orc.round_bf16(Y) if gd == "bf16" else Y
+    Zr = orc.gemm(G, Yref)
+    assert rel(to_host(Z), Zr) <= (1e-12 if gd == "f64" else 1e-5)
+
+
+def test_gaussian_stage_bf16_full_width_sampled(ms, orc):
+    # the 512 x 131072 BF16 stage on 260 columns; the oracle checks 4 of them
+    k2, k, nc = 512, 131072, 260
+    G = synth.gaussian_sketch(k2, k, seed=3, dtype="bf16")
+    Y = synth.normal_matrix(k, nc, seed=4, dtype=np.float32)
+    Z, ws = ms.gaussian_apply(bf16_dev(G), to_dev(Y))
+    ms.check_status(ws)
+    cols = [0, 131, 258, 259]
+    Zr = orc.gemm(G, orc.round_bf16(Y[:, cols]))
+    assert rel(to_host(Z)[:, cols], Zr) <= 1e-5
+
+
+def test_gaussian_identity_exact(ms):
+    # G = I (k2 = k): Z = Y bit for bit in FP64
+    k, nc = 64, 5
+    Y = synth.normal_matrix(k, nc, seed=5)
+    Z, ws = ms.gaussian_apply(to_dev(np.eye(k)), to_dev(Y))
+    ms.check_status(ws)
+    assert np.array_equal(to_host(Z), Y)
+
+
+@pytest.mark.parametrize("mode", ["lds", "sorted"])
+@pytest.mark.parametrize("d,n,k,k2,gd", [(20000, 8, 128, 16, "f64"), (100003, 16, 512, 32, "f32"),
+                                         (100003, 16, 512, 32, "bf16")])
+def test_multisketch_parity(ms, orc, mode, d, n, k, k2, gd):
+    dt = np.float64 if gd == "f64" else np.float32
+    A = synth.normal_matrix(d, n, seed=d, dtype=dt)
+    h = synth.bucket_map(d, k, seed=d)
+    s = synth.signs(d, seed=d)
+    G = synth.gaussian_sketch(k2, k, seed=d, dtype=gd)
+    Gd = bf16_dev(G) if gd == "bf16" else to_dev(G)
+    Z, ws = ms.multisketch_apply(to_dev(A), to_dev(h), to_dev(s), Gd, k, mode=mode)
+    ms.check_status(ws)
+    Y = orc.countsketch(A, h, s, k)
+    Zr = orc.gemm(G, orc.round_bf16(Y) if gd == "bf16" else Y)
+    # BF16 with the LDS sketch: the GPU's FP32 sketch differs from the
+    # oracle's in its last bits (association order), so the few entries that
+    # sit next to a BF16 rounding boundary may round to the neighbouring BF16
+    # value (a 2^-8 relative change of those entries)
+    tol = {"f64": 1e-12, "f32": 1e-5, "bf16": 1e-5 if mode == "sorted" else 1e-3}[gd]
+    assert rel(to_host(Z), Zr) <= tol
+
+
+# ------------------------------------------------------------------- QR solve
+QR_CASES = [(1, 1, 1), (16, 8, 1), (37, 19, 3), (128, 64, 1), (64, 64, 2), (256, 128, 1),
+            (512, 256, 4)]
+
+
+@pytest.mark.parametrize("m,n,nrhs", QR_CASES)
+def test_qr_solve_parity(ms, orc, m, n, nrhs):
+    print("qr m=%d n=%d nrhs=%d" % (m, n, nrhs), flush=True)
+    W = synth.normal_matrix(m, n, seed=m + n)
+    B = synth.normal_matrix(m, nrhs, seed=m + n + 1)
+    X, R, ws = ms.qr_solve(to_dev(W), to_dev(B), want_r=True)
+    ms.check_status(ws)
+    Xr = orc.qr_solve(W, B)
+    F, _ = orc.householder_qr(W)
+    Rr = np.triu(F[:n, :n])
+    kappa = np.linalg.cond(W)
+    assert rel(to_host(X), Xr) <= max(1e-12, 10 * kappa * 1e-16 * n)
+    assert rel(to_host(R), Rr) <= 1e-13 * n
+
+
+def test_qr_solve_singular(ms):
+    W = synth.normal_matrix(20, 4, seed=7)
+    W[:, 2] = 0.0
+    X, _, ws = ms.qr_solve(to_dev(W), to_dev(np.ones((20, 1))))
+    with pytest.raises(ms.MsketchError) as e:
+        ms.check_status(ws)
+    assert e.value.code == ms.MS_ERR_SINGULAR
+    assert np.isnan(to_host(X)).all()
+
+
+# ------------------------------------------------------------------- sketch-and-solve
+def _lstsq_inputs(d, n, nrhs, k, k2, seed, dtype=np.float64, gd="f64", kappa=None, noise=1e-6):
+    if kappa is None:
+        A = synth.normal_matrix(d, n, seed=seed, dtype=dtype)
+    else:
+        A = synth.conditioned_matrix(d, n, kappa, seed=seed, dtype=dtype)
+    B, xs = synth.lstsq_rhs(A, nrhs, seed=seed, noise=noise)
+    h = synth.bucket_map(d, k, seed=seed)
+    s = synth.signs(d, seed=seed)
+    G = synth.gaussian_sketch(k2, k, seed=seed, dtype=gd)
+    return A, B, xs, h, s, G
+
+
+def _gpu_lstsq(ms, A, B, h, s, G, k, gd="f64", **kw):
+    Gd = bf16_dev(G) if gd == "bf16" else to_dev(G)
+    X, ws = ms.sketch_lstsq(to_dev(A), to_dev(B), to_dev(h), to_dev(s), Gd, k, **kw)
+    ms.check_status(ws)
+    return to_host(X)
+
+
+@pytest.mark.parametrize("mode", ["lds", "sorted", "atomic"])
+@pytest.mark.parametrize("d,n,nrhs", [(4096, 4, 1), (50001, 8, 3), (200000, 16, 8)])
+def test_lstsq_fp64_parity(ms, orc, mode, d, n, nrhs):
+    k, k2 = 2 * n * n, 2 * n
+    A, B, xs, h, s, G = _lstsq_inputs(d, n, nrhs, k, k2, seed=d + n)
+    X = _gpu_lstsq(ms, A, B, h, s, G, k, mode=mode)
+    Xr, _, _ = orc.sketch_lstsq(A, B, h, s, G, k)
+    assert rel(X, Xr) <= 1e-12
+
+
+def test_lstsq_fp64_full_workload(ms, orc):
+    # A 4,194,304 x 64 FP64, b = A x* + 1e-6 N(0,1), k = 8192, G 128 x 8192
+    d, n, nrhs, k, k2 = 4194304, 64, 1, 8192, 128
+    print("lstsq full d=%d n=%d" % (d, n), flush=True)
+    A, B, xs, h, s, G = _lstsq_inputs(d, n, nrhs, k, k2, seed=14209)
+    X = _gpu_lstsq(ms, A, B, h, s, G, k)
+    Xr, _, _ = orc.sketch_lstsq(A, B, h, s, G, k)
+    assert rel(X, Xr) <= 1e-12
+    # residual ratio against the full least-squares optimum (LAPACK)
+    xt = np.linalg.lstsq(A, B, rcond=None)[0]
+    rho = np.linalg.norm(B - A @ X) / np.linalg.norm(B - A @ xt)
+    print("rho =", rho)
+    assert 1.0 - 1e-9 <= rho <= 2.0
+
+
+@pytest.mark.parametrize("d,n,nrhs,k", [(3000, 16, 2, 512), (100, 8, 1, 128), (5000, 8, 1, 128)])
+def test_lstsq_edge_shapes(ms, orc, d, n, nrhs, k):
+    # k > d (sketch does not shrink rows) and a square Gaussian stage (k2 = n)
+    k2 = n if d == 5000 else 2 * n
+    A, B, xs, h, s, G = _lstsq_inputs(d, n, nrhs, k, k2, seed=d + 1)
+    X = _gpu_lstsq(ms, A, B, h, s, G, k)
+    Xr, _, _ = orc.sketch_lstsq(A, B, h, s, G, k)
+    assert rel(X, Xr) <= 1e-11
+
+
+def test_lstsq_consistent_exact_recovery(ms):
+    d, n, k, k2 = 100000, 16, 512, 32
+    A, B, xs, h, s, G = _lstsq_inputs(d, n, 2, k, k2, seed=3, noise=0.0)
+    X = _gpu_lstsq(ms, A, B, h, s, G, k)
+    assert rel(X, xs) <= 1e-12
+
+
+def test_lstsq_fp32_well_conditioned(ms, orc):
+    d, n, nrhs, k, k2 = 1 << 20, 32, 1, 2048, 64
+    A, B, xs, h, s, G = _lstsq_inputs(d, n, nrhs, k, k2, seed=11, dtype=np.float32, gd="f32")
+    X = _gpu_lstsq(ms, A, B, h, s, G, k, gd="f32")
+    Xr, _, _ = orc.sketch_lstsq(A, B, h, s, G, k)
+    assert rel(X, Xr) <= 1e-4
+
+
+def test_lstsq_fp32_ill_conditioned_residual(ms, orc):
+    # A = Z D Q with kappa 1e6, FP32: judged by the residual ratio
+    d, n, nrhs, k, k2 = 1 << 20, 32, 1, 2048, 64
+    A, B, xs, h, s, G = _lstsq_inputs(d, n, nrhs, k, k2, seed=12, dtype=np.float32, gd="f32",
+                                      kappa=1e6)
+    X = _gpu_lstsq(ms, A, B, h, s, G, k, gd="f32")
+    Xr, _, _ = orc.sketch_lstsq(A, B, h, s, G, k)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    xt = np.linalg.lstsq(A64, B64, rcond=None)[0]
+    rt = np.linalg.norm(B64 - A64 @ xt)
+    rho_g = np.linalg.norm(B64 - A64 @ X) / rt
+    rho_o = np.linalg.norm(B64 - A64 @ Xr) / rt
+    print("rho gpu %.4f oracle %.4f" % (rho_g, rho_o))
+    assert rho_g <= 1.05 * rho_o + 1e-3
+
+
+@pytest.mark.parametrize("refine", [0, 1, 3])
+def test_lstsq_bf16_refinement(ms, orc, refine):
+    # FP32 A with column scales down to 1e-4, BF16 Gaussian stage, FP64 QR,
+    # FP64-residual refinement steps
+    d, n, nrhs, k, k2 = 1 << 19, 32, 4, 2048, 64
+    seed = 21
+    Z = synth.normal_matrix(d, n, seed=seed, dtype=np.float64)
+    A = np.asfortranarray((Z * np.logspace(0, -4, n)[None, :]).astype(np.float32))
+    B, xs = synth.lstsq_rhs(A, nrhs, seed=seed)
+    h = synth.bucket_map(d, k, seed=seed)
+    s = synth.signs(d, seed=seed)
+    G = synth.gaussian_sketch(k2, k, seed=seed, dtype="bf16")
+    X = _gpu_lstsq(ms, A, B, h, s, G, k, gd="bf16", refine_steps=refine)
+    # the FP64 sketch-and-solve solution with the same (h, s, G)
+    X64, _, _ = orc.sketch_lstsq(A.astype(np.float64), B.astype(np.float64), h, s,
+                                 G.astype(np.float64), k)
+    err = rel(X, X64)
+    print("refine=%d err vs FP64 sketch-and-solve = %.3e" % (refine, err))
+    bound = {0: 5e-2, 1: 1e-3, 3: 1e-6}[refine]
+    assert err <= bound
+
+
+def test_lstsq_range_error(ms):
+    d, n, k, k2 = 1000, 4, 32, 8
+    A, B, xs, h, s, G = _lstsq_inputs(d, n, 1, k, k2, seed=2)
+    h[10] = -1
+    Gd = to_dev(G)
+    X, ws = ms.sketch_lstsq(to_dev(A), to_dev(B), to_dev(h), to_dev(s), Gd, k)
+    with pytest.raises(ms.MsketchError) as e:
+        ms.check_status(ws)
+    assert e.value.code == ms.MS_ERR_RANGE
