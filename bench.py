@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--seed", type=int, default=14209)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle baseline (0 disables it)")
+    ap.add_argument("--only", default=None, choices=["countsketch", "copy"],
+                    help="profiling runs: launch only the LDS CountSketch of [A | b] (--steps "
+                         "times) or only a plain device copy of 1 GiB (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters); prints a short JSON line")
     return ap.parse_args()
 
 
@@ -69,6 +73,17 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.only == "copy":
+        nbytes = 1 << 30
+        src = torch.empty(nbytes // 8, dtype=torch.float64, device=dev).normal_()
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"only": "copy", "bytes_read_per_launch": nbytes,
+                          "bytes_written_per_launch": nbytes, "launches": args.steps}))
+        return
     d, n, nrhs, k, k2 = 4194304, 64, 1, 8192, 128
     nc = n + nrhs
     seed = args.seed
@@ -91,6 +106,16 @@ def main():
     ws = ms.workspace(ms.workspace_size("lstsq", d=d, n=n, nrhs=nrhs, k=k, k2=k2,
                                         mode=args.mode), dev)
     torch.cuda.synchronize()
+    if args.only == "countsketch":
+        Y = ms.empty_colmajor(k, nc, torch.float64, dev)
+        cws = ms.workspace(256, dev)
+        Y.zero_()
+        for _ in range(args.steps):
+            ms.countsketch_apply(AB, hd, sd, k, Y=Y, mode="lds", ws=cws)
+        ms.check_status(cws)
+        print(json.dumps({"only": "countsketch", "kernel": "k_cs_lds", "launches": args.steps,
+                          "bytes_per_launch": d * nc * 8 + d * 5 + k * nc * 8}))
+        return
 
     # ---- the step: one sketch-and-solve, W warm-up + K timed
     for _ in range(args.warmup):

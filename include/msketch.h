@@ -76,8 +76,11 @@ typedef enum {
 typedef struct {
   int32_t cs_mode;      /* ms_cs_mode */
   int32_t refine_steps; /* sketch_lstsq: FP64-residual refinement steps */
-  int32_t reserved0;
-  int32_t reserved1;
+  int32_t cs_tile_cols; /* MS_CS_LDS tuning: at most this many columns binned
+                           per workgroup (power of two, 0 = automatic) */
+  int32_t cs_schedule;  /* MS_CS_LDS tuning: 0 = persistent die-aware
+                           schedule (default), 1 = one workgroup per (row
+                           chunk, column tile, bucket tile) */
 } ms_opts;
 
 /* op codes of ms_workspace_size() */

@@ -48,7 +48,7 @@ _i64, _p, _sz, _i32 = ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t, ctypes.c
 
 class MsOpts(ctypes.Structure):
     _fields_ = [("cs_mode", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("cs_tile_cols", ctypes.c_int32), ("cs_schedule", ctypes.c_int32)]
 
 
 _SIGS = {
@@ -133,8 +133,8 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _opts(mode: str = "auto", refine_steps: int = 0):
-    return MsOpts(MODES[mode], int(refine_steps), 0, 0)
+def _opts(mode: str = "auto", refine_steps: int = 0, tile_cols: int = 0, schedule: int = 0):
+    return MsOpts(MODES[mode], int(refine_steps), int(tile_cols), int(schedule))
 
 
 def workspace_size(op: str, d=0, n=0, nrhs=0, k=0, k2=0, a_dtype=MS_F64, g_dtype=MS_F64,
@@ -198,7 +198,8 @@ def pack_sketch(h: torch.Tensor, s: torch.Tensor, k: int, code: torch.Tensor | N
 
 
 def countsketch_accumulate(A: torch.Tensor, code: torch.Tensor, k: int, Y: torch.Tensor,
-                           mode: str = "auto", ws: torch.Tensor | None = None, stream=None):
+                           mode: str = "auto", ws: torch.Tensor | None = None, stream=None,
+                           tile_cols: int = 0, schedule: int = 0):
     """Y += S A with a packed sketch (no clearing of Y).  Returns (Y, ws)."""
     d, n = A.shape
     a_dt = _dt(A)
@@ -208,7 +209,7 @@ def countsketch_accumulate(A: torch.Tensor, code: torch.Tensor, k: int, Y: torch
         raise ValueError("Y must be k x n with A's dtype")
     ws = workspace(256, A.device) if ws is None else ws
     wp, have = _ws_ptr(ws, 256)
-    o = _opts(mode)
+    o = _opts(mode, 0, tile_cols, schedule)
     _ok(_lib.countsketch_accumulate(d, n, k, a_dt, Ap, lda,
                                     _vec(code, torch.int32, "code") if d else None, Yp, ldy,
                                     ctypes.byref(o), wp, have, _stream(stream)),
@@ -218,7 +219,8 @@ def countsketch_accumulate(A: torch.Tensor, code: torch.Tensor, k: int, Y: torch
 
 def countsketch_apply(A: torch.Tensor, h: torch.Tensor, s: torch.Tensor, k: int,
                       Y: torch.Tensor | None = None, mode: str = "auto",
-                      ws: torch.Tensor | None = None, stream=None):
+                      ws: torch.Tensor | None = None, stream=None, tile_cols: int = 0,
+                      schedule: int = 0):
     """Y = S A (k x n, A's dtype).  Returns (Y, ws)."""
     d, n = A.shape
     a_dt = _dt(A)
@@ -231,7 +233,7 @@ def countsketch_apply(A: torch.Tensor, h: torch.Tensor, s: torch.Tensor, k: int,
     need = workspace_size("countsketch", d=d, n=n, k=k, a_dtype=a_dt, mode=mode)
     ws = workspace(need, A.device) if ws is None else ws
     wp, have = _ws_ptr(ws, need)
-    o = _opts(mode)
+    o = _opts(mode, 0, tile_cols, schedule)
     _ok(_lib.countsketch_apply(d, n, k, a_dt, Ap, lda,
                                _vec(h, torch.int32, "h") if d else None,
                                _vec(s, torch.int8, "s") if d else None, Yp, ldy,
@@ -310,7 +312,8 @@ def qr_solve(W: torch.Tensor, B: torch.Tensor, X: torch.Tensor | None = None,
 
 def sketch_lstsq(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torch.Tensor,
                  G: torch.Tensor, k: int, refine_steps: int = 0, mode: str = "auto",
-                 X: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None):
+                 X: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None,
+                 tile_cols: int = 0, schedule: int = 0):
     """X = argmin || G C (B - A X) || (n x nrhs, FP64).  Returns (X, ws)."""
     d, n = A.shape
     if B.dim() == 1:
@@ -330,7 +333,7 @@ def sketch_lstsq(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torch.Ten
                           g_dtype=g_dt, mode=mode, refine_steps=refine_steps)
     ws = workspace(need, A.device) if ws is None else ws
     wp, have = _ws_ptr(ws, need)
-    o = _opts(mode, refine_steps)
+    o = _opts(mode, refine_steps, tile_cols, schedule)
     _ok(_lib.sketch_lstsq(d, n, nrhs, k, k2, a_dt, Ap, lda, Bp, ldb, _vec(h, torch.int32, "h"),
                           _vec(s, torch.int8, "s"), g_dt, Gp, ldg, Xp, ldx, ctypes.byref(o), wp,
                           have, _stream(stream)), "sketch_lstsq")

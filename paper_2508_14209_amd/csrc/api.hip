@@ -130,28 +130,6 @@ P *at(void *ws, size_t off) {
 
 ms_status from_hip(hipError_t e) { return e == hipSuccess ? MS_OK : MS_ERR_DEVICE; }
 
-// CountSketch of the column set `c` into Y (k x c.ncols, ldy).
-template <typename T>
-hipError_t run_countsketch(int64_t d, int64_t k, const Cols<T> &c, const int32_t *h,
-                           const int8_t *s, T *Y, int64_t ldy, int mode, void *ws,
-                           const CsLayout &L, int *status, hipStream_t st) {
-  if (c.ncols <= 0) return hipSuccess;
-  if (d == 0) return launch_fill_zero<T>(Y, k, c.ncols, ldy, st);
-  hipError_t e;
-  if (mode == MS_CS_SORTED) {
-    e = launch_plan(d, k, h, s, at<int32_t>(ws, L.cnt), at<int32_t>(ws, L.off),
-                    at<int32_t>(ws, L.cursor), at<uint32_t>(ws, L.sperm), status, st);
-    if (e != hipSuccess) return e;
-    // a sign outside {+1,-1} is reported through the pack check as well
-    return launch_cs_sorted<T>(k, c, at<int32_t>(ws, L.off), at<uint32_t>(ws, L.sperm), Y, ldy, st);
-  }
-  e = launch_pack_codes(d, k, h, s, at<uint32_t>(ws, L.code), status, st);
-  if (e != hipSuccess) return e;
-  if (mode == MS_CS_ATOMIC)
-    return launch_cs_atomic<T>(d, k, c, at<uint32_t>(ws, L.code), Y, ldy, true, status, st);
-  return launch_cs_lds<T>(d, k, c, at<uint32_t>(ws, L.code), Y, ldy, true, status, st);
-}
-
 // Sorted mode validates s with a separate pass (the plan only reads h).
 __global__ void k_check_signs(int64_t d, const int8_t *__restrict__ s, int *status) {
   bool bad = false;
@@ -168,20 +146,53 @@ hipError_t launch_check_signs(int64_t d, const int8_t *s, int *status, hipStream
   return hipGetLastError();
 }
 
+// CountSketch of the column set `c` into Y (k x c.ncols, ldy).  This is the
+// first work of a call: its first launch also clears the status word.
+//   lds    : prologue (status, Y = 0), pack h/s into validated 32-bit codes,
+//            the LDS kernel (one code read per row per column tile);
+//   atomic : prologue, pack, one atomic per element;
+//   sorted : prologue (status, bucket counts = 0), sign check, plan, fold.
 template <typename T>
-hipError_t run_countsketch_checked(int64_t d, int64_t k, const Cols<T> &c, const int32_t *h,
-                                   const int8_t *s, T *Y, int64_t ldy, int mode, void *ws,
-                                   const CsLayout &L, int *status, hipStream_t st) {
-  if (mode == MS_CS_SORTED && d > 0) {
-    hipError_t e = launch_check_signs(d, s, status, st);
+hipError_t run_countsketch(int64_t d, int64_t k, const Cols<T> &c, const int32_t *h,
+                           const int8_t *s, T *Y, int64_t ldy, int mode, void *ws,
+                           const CsLayout &L, int *status, hipStream_t st,
+                           const CsTuning &tune) {
+  if (c.ncols <= 0 || d == 0)
+    return launch_prologue<T>(status, Y, k, c.ncols > 0 ? c.ncols : 0, ldy, st);
+  hipError_t e;
+  if (mode == MS_CS_SORTED) {
+    e = launch_prologue<int32_t>(status, at<int32_t>(ws, L.cnt), k, 1, k, st);
+    if (e == hipSuccess) e = launch_check_signs(d, s, status, st);
+    if (e == hipSuccess)
+      e = launch_plan(d, k, h, s, at<int32_t>(ws, L.cnt), at<int32_t>(ws, L.off),
+                      at<int32_t>(ws, L.cursor), at<uint32_t>(ws, L.sperm), status, st);
     if (e != hipSuccess) return e;
+    return launch_cs_sorted<T>(k, c, at<int32_t>(ws, L.off), at<uint32_t>(ws, L.sperm), Y, ldy, st);
   }
-  return run_countsketch<T>(d, k, c, h, s, Y, ldy, mode, ws, L, status, st);
+  e = launch_prologue<T>(status, Y, k, c.ncols, ldy, st);
+  if (e == hipSuccess) e = launch_pack_codes(d, k, h, s, at<uint32_t>(ws, L.code), status, st);
+  if (e != hipSuccess) return e;
+  if (mode == MS_CS_ATOMIC)
+    return launch_cs_atomic<T>(d, k, c, at<uint32_t>(ws, L.code), Y, ldy, false, status, st);
+  return launch_cs_lds<T>(d, k, c, at<uint32_t>(ws, L.code), nullptr, nullptr, Y, ldy, false,
+                          status, st, &tune);
 }
 
 bool valid_mode(const ms_opts *o) {
   const int m = o ? o->cs_mode : MS_CS_AUTO;
-  return m >= MS_CS_AUTO && m <= MS_CS_SORTED;
+  if (!(m >= MS_CS_AUTO && m <= MS_CS_SORTED)) return false;
+  if (o && (o->cs_tile_cols < 0 || o->cs_tile_cols > 64 || o->cs_schedule < 0 || o->cs_schedule > 1))
+    return false;
+  return true;
+}
+
+CsTuning tuning_of(const ms_opts *o) {
+  CsTuning t{0, 0};
+  if (o) {
+    t.cols_per_wg = o->cs_tile_cols;
+    t.grid_variant = o->cs_schedule;
+  }
+  return t;
 }
 
 }  // namespace
@@ -259,7 +270,7 @@ ms_status ms_bucket_plan(int64_t d, int64_t k, const int32_t *h, int32_t *cnt, i
   const size_t o_cursor = cv.take((size_t)k * 4);
   const size_t o_sperm = cv.take((size_t)d * 4);
   int *status = static_cast<int *>(ws);
-  hipError_t e = launch_zero_status(status, st);
+  hipError_t e = launch_prologue<int32_t>(status, cnt, k, 1, k, st);
   if (e == hipSuccess)
     e = launch_plan(d, k, h, nullptr, cnt, off, at<int32_t>(ws, o_cursor),
                     at<uint32_t>(ws, o_sperm), status, st);
@@ -293,16 +304,19 @@ ms_status countsketch_accumulate(int64_t d, int64_t n, int64_t k, ms_dtype a_dty
   int *status = static_cast<int *>(ws);
   hipError_t e = launch_zero_status(status, st);
   if (e != hipSuccess || n == 0 || d == 0) return from_hip(e);
+  const CsTuning tune = tuning_of(opts);
   if (a_dtype == MS_F64) {
     Cols<double> c{static_cast<const double *>(A), lda, nullptr, 0, (int)n, (int)n};
     e = mode == MS_CS_ATOMIC
             ? launch_cs_atomic<double>(d, k, c, code, static_cast<double *>(Y), ldy, false, status, st)
-            : launch_cs_lds<double>(d, k, c, code, static_cast<double *>(Y), ldy, false, status, st);
+            : launch_cs_lds<double>(d, k, c, code, nullptr, nullptr, static_cast<double *>(Y), ldy,
+                                    false, status, st, &tune);
   } else {
     Cols<float> c{static_cast<const float *>(A), lda, nullptr, 0, (int)n, (int)n};
     e = mode == MS_CS_ATOMIC
             ? launch_cs_atomic<float>(d, k, c, code, static_cast<float *>(Y), ldy, false, status, st)
-            : launch_cs_lds<float>(d, k, c, code, static_cast<float *>(Y), ldy, false, status, st);
+            : launch_cs_lds<float>(d, k, c, code, nullptr, nullptr, static_cast<float *>(Y), ldy,
+                                   false, status, st, &tune);
   }
   return from_hip(e);
 }
@@ -321,19 +335,19 @@ ms_status countsketch_apply(int64_t d, int64_t n, int64_t k, ms_dtype a_dtype, c
     return MS_ERR_NOMEM;
   hipStream_t st = (hipStream_t)stream;
   int *status = static_cast<int *>(ws);
-  hipError_t e = launch_zero_status(status, st);
-  if (e != hipSuccess || n == 0) return from_hip(e);
+  if (n == 0) return from_hip(launch_zero_status(status, st));
+  hipError_t e;
   Carve cv;
   CsLayout L;
   carve_cs(cv, L, d, k, mode);
   if (a_dtype == MS_F64) {
     Cols<double> c{static_cast<const double *>(A), lda, nullptr, 0, (int)n, (int)n};
-    e = run_countsketch_checked<double>(d, k, c, h, s, static_cast<double *>(Y), ldy, mode, ws, L,
-                                        status, st);
+    e = run_countsketch<double>(d, k, c, h, s, static_cast<double *>(Y), ldy, mode, ws, L, status,
+                                st, tuning_of(opts));
   } else {
     Cols<float> c{static_cast<const float *>(A), lda, nullptr, 0, (int)n, (int)n};
-    e = run_countsketch_checked<float>(d, k, c, h, s, static_cast<float *>(Y), ldy, mode, ws, L,
-                                       status, st);
+    e = run_countsketch<float>(d, k, c, h, s, static_cast<float *>(Y), ldy, mode, ws, L, status,
+                               st, tuning_of(opts));
   }
   return from_hip(e);
 }
@@ -377,8 +391,8 @@ ms_status multisketch_apply(int64_t d, int64_t n, int64_t k, int64_t k2, ms_dtyp
     return MS_ERR_NOMEM;
   hipStream_t st = (hipStream_t)stream;
   int *status = static_cast<int *>(ws);
-  hipError_t e = launch_zero_status(status, st);
-  if (e != hipSuccess || n == 0) return from_hip(e);
+  if (n == 0) return from_hip(launch_zero_status(status, st));
+  hipError_t e;
   Carve cv;
   CsLayout L;
   carve_cs(cv, L, d, k, mode);
@@ -387,12 +401,10 @@ ms_status multisketch_apply(int64_t d, int64_t n, int64_t k, int64_t k2, ms_dtyp
   const size_t o_part = cv.take(p.partial_bytes);
   if (a_dtype == MS_F64) {
     Cols<double> c{static_cast<const double *>(A), lda, nullptr, 0, (int)n, (int)n};
-    e = run_countsketch_checked<double>(d, k, c, h, s, at<double>(ws, o_y), k, mode, ws, L, status,
-                                        st);
+    e = run_countsketch<double>(d, k, c, h, s, at<double>(ws, o_y), k, mode, ws, L, status, st, tuning_of(opts));
   } else {
     Cols<float> c{static_cast<const float *>(A), lda, nullptr, 0, (int)n, (int)n};
-    e = run_countsketch_checked<float>(d, k, c, h, s, at<float>(ws, o_y), k, mode, ws, L, status,
-                                       st);
+    e = run_countsketch<float>(d, k, c, h, s, at<float>(ws, o_y), k, mode, ws, L, status, st, tuning_of(opts));
   }
   if (e == hipSuccess)
     e = launch_gemm(p, g_dtype, G, ldg, at<void>(ws, o_y), k, Z, ldz, nullptr,
@@ -443,28 +455,24 @@ ms_status sketch_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64_t k2
   hipStream_t st = (hipStream_t)stream;
   int *status = static_cast<int *>(ws);
   const int64_t nc = n + nrhs;
-  hipError_t e = launch_zero_status(status, st);
+  hipError_t e;
   // 1. Y = C [A | B]
-  if (e == hipSuccess) {
-    if (a_dtype == MS_F64) {
-      Cols<double> c{static_cast<const double *>(A), lda, static_cast<const double *>(B), ldb,
-                     (int)n, (int)nc};
-      e = run_countsketch_checked<double>(d, k, c, h, s, at<double>(ws, L.y), k, mode, ws, L.cs,
-                                          status, st);
-    } else {
-      Cols<float> c{static_cast<const float *>(A), lda, static_cast<const float *>(B), ldb, (int)n,
-                    (int)nc};
-      e = run_countsketch_checked<float>(d, k, c, h, s, at<float>(ws, L.y), k, mode, ws, L.cs,
-                                         status, st);
-    }
+  if (a_dtype == MS_F64) {
+    Cols<double> c{static_cast<const double *>(A), lda, static_cast<const double *>(B), ldb,
+                   (int)n, (int)nc};
+    e = run_countsketch<double>(d, k, c, h, s, at<double>(ws, L.y), k, mode, ws, L.cs, status, st, tuning_of(opts));
+  } else {
+    Cols<float> c{static_cast<const float *>(A), lda, static_cast<const float *>(B), ldb, (int)n,
+                  (int)nc};
+    e = run_countsketch<float>(d, k, c, h, s, at<float>(ws, L.y), k, mode, ws, L.cs, status, st, tuning_of(opts));
   }
-  // 2. Z = G Y (FP64 copy for the factorisation)
-  const GemmPlan p = plan_gemm(k2, nc, k, g_dtype);
-  if (e == hipSuccess)
-    e = launch_gemm(p, g_dtype, G, ldg, at<void>(ws, L.y), k, nullptr, k2, at<double>(ws, L.z64),
-                    at<void>(ws, L.partials), nullptr, st);
+  // 2. Z = G Y (split-K partials reduced in split order into an FP64 Z);
   // 3. Householder QR of Z_A, Q^T Z_B, back substitution
+  const GemmPlan p = plan_gemm(k2, nc, k, g_dtype);
   double *z64 = at<double>(ws, L.z64);
+  if (e == hipSuccess)
+    e = launch_gemm(p, g_dtype, G, ldg, at<void>(ws, L.y), k, nullptr, k2, z64,
+                    at<void>(ws, L.partials), nullptr, st);
   if (e == hipSuccess)
     e = launch_qr_solve(k2, n, nrhs, z64, k2, z64 + n * k2, k2, X, ldx, nullptr, 0,
                         at<double>(ws, L.tau), at<double>(ws, L.fact), at<void>(ws, L.qr), status,
@@ -487,8 +495,8 @@ ms_status sketch_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64_t k2
       e = launch_cs_atomic<double>(d, k, cr, at<uint32_t>(ws, L.cs.code), at<double>(ws, L.yr), k,
                                    true, status, st);
     else
-      e = launch_cs_lds<double>(d, k, cr, at<uint32_t>(ws, L.cs.code), at<double>(ws, L.yr), k,
-                                true, status, st);
+      e = launch_cs_lds<double>(d, k, cr, at<uint32_t>(ws, L.cs.code), nullptr, nullptr,
+                                at<double>(ws, L.yr), k, true, status, st);
     if (e != hipSuccess) break;
     e = launch_gemv64(k2, nrhs, k, g_dtype, G, ldg, at<double>(ws, L.yr), k, at<double>(ws, L.zr),
                       at<double>(ws, L.gv), st);

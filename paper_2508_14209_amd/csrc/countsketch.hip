@@ -14,6 +14,7 @@
 //                (bucket, column) folded sequentially in ascending row order
 //                from +0.0: bit-identical to the sequential reading of Alg. 2.
 #include <algorithm>
+#include <type_traits>
 
 #include "ms_internal.h"
 
@@ -51,6 +52,33 @@ hipError_t launch_fill_zero(T *Y, int64_t rows, int64_t cols, int64_t ld, hipStr
 template hipError_t launch_fill_zero<double>(double *, int64_t, int64_t, int64_t, hipStream_t);
 template hipError_t launch_fill_zero<float>(float *, int64_t, int64_t, int64_t, hipStream_t);
 template hipError_t launch_fill_zero<int32_t>(int32_t *, int64_t, int64_t, int64_t, hipStream_t);
+
+// Start of a call: clear the status word and a buffer (the sketch that the
+// atomic variants accumulate into, or the plan's bucket counts).
+template <typename T>
+__global__ void k_prologue(int *status, T *Y, int64_t rows, int64_t cols, int64_t ld) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *status = MS_OK;
+  const int64_t total = rows * cols;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = t / rows;
+    Y[(t - c * rows) + c * ld] = T(0);
+  }
+}
+
+template <typename T>
+hipError_t launch_prologue(int *status, T *Y, int64_t rows, int64_t cols, int64_t ld,
+                           hipStream_t st) {
+  const int64_t total = std::max<int64_t>(0, rows * cols);
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 65536));
+  hipLaunchKernelGGL(k_prologue<T>, dim3((unsigned)blocks), dim3(256), 0, st, status, Y, rows, cols,
+                     ld);
+  return hipGetLastError();
+}
+template hipError_t launch_prologue<double>(int *, double *, int64_t, int64_t, int64_t, hipStream_t);
+template hipError_t launch_prologue<float>(int *, float *, int64_t, int64_t, int64_t, hipStream_t);
+template hipError_t launch_prologue<int32_t>(int *, int32_t *, int64_t, int64_t, int64_t,
+                                             hipStream_t);
 
 // Validate (h, s) and pack them: code = h | (s == -1 ? sign bit : 0).  A row
 // with h outside [0,k) or s not in {+1,-1} records MS_ERR_RANGE and is
@@ -206,8 +234,6 @@ __global__ __launch_bounds__(NTHREADS) void k_segsort(int64_t k, int lo_exclusiv
 hipError_t launch_plan(int64_t d, int64_t k, const int32_t *h, const int8_t *s, int32_t *cnt,
                        int32_t *off, int32_t *cursor, uint32_t *sperm, int *status,
                        hipStream_t st) {
-  hipError_t e = launch_fill_zero<int32_t>(cnt, k, 1, k, st);
-  if (e != hipSuccess) return e;
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((d + 255) / 256, 8192));
   if (d > 0) hipLaunchKernelGGL(k_hist, dim3((unsigned)blocks), dim3(256), 0, st, d, k, h, cnt, status);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, k, cnt, off, cursor);
@@ -325,14 +351,82 @@ __device__ __forceinline__ uint32_t code_of(const CV &v, int q) {
   return v[q];
 }
 
+// The bucket/sign word of row i: either a packed code (CODES) or built from
+// h and s, in which case a row with h outside [0,k) or s not +-1 yields an
+// invalid word (bucket field 0x7fffffff, never inside a tile) and sets bad.
+template <bool CODES>
+__device__ __forceinline__ uint32_t row_word(const uint32_t *__restrict__ code,
+                                             const int32_t *__restrict__ h,
+                                             const int8_t *__restrict__ s, int64_t i, int64_t k,
+                                             bool &bad) {
+  if (CODES) {
+    const uint32_t e = code[i];
+    bad |= (int64_t)(e & kIdxMask) >= k;
+    return e;
+  }
+  const int32_t b = h[i];
+  const int8_t sg = s[i];
+  const bool ok = b >= 0 && (int64_t)b < k && (sg == 1 || sg == -1);
+  bad |= !ok;
+  return ok ? ((uint32_t)b | (sg < 0 ? kSignBit : 0u)) : 0xffffffffu;
+}
+
+typedef int32_t ivec2 __attribute__((ext_vector_type(2)));
+typedef int32_t ivec4 __attribute__((ext_vector_type(4)));
+typedef int8_t cvec2 __attribute__((ext_vector_type(2)));
+typedef int8_t cvec4 __attribute__((ext_vector_type(4)));
+template <int W>
+struct HsVec;
+template <>
+struct HsVec<2> {
+  using hv = ivec2;
+  using sv = cvec2;
+};
+template <>
+struct HsVec<4> {
+  using hv = ivec4;
+  using sv = cvec4;
+};
+
+// W consecutive words starting at row i (i a multiple of W; 16/8/4/2-byte
+// aligned loads).
+template <bool CODES, int W>
+__device__ __forceinline__ void row_words(const uint32_t *__restrict__ code,
+                                          const int32_t *__restrict__ h,
+                                          const int8_t *__restrict__ s, int64_t i, int64_t k,
+                                          uint32_t (&e)[W], bool &bad) {
+  if (CODES) {
+    using CV = typename Vec16<typename std::conditional<W == 2, double, float>::type>::code_t;
+    const CV v = *reinterpret_cast<const CV *>(code + i);
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      e[q] = v[q];
+      bad |= (int64_t)(e[q] & kIdxMask) >= k;
+    }
+  } else {
+    const typename HsVec<W>::hv hv = *reinterpret_cast<const typename HsVec<W>::hv *>(h + i);
+    const typename HsVec<W>::sv sv = *reinterpret_cast<const typename HsVec<W>::sv *>(s + i);
+#pragma unroll
+    for (int q = 0; q < W; ++q) {
+      const int32_t b = hv[q];
+      const int8_t sg = sv[q];
+      const bool ok = b >= 0 && (int64_t)b < k && (sg == 1 || sg == -1);
+      bad |= !ok;
+      e[q] = ok ? ((uint32_t)b | (sg < 0 ? kSignBit : 0u)) : 0xffffffffu;
+    }
+  }
+}
+
 // Workgroup (chunk, column tile, bucket tile): rows [r0, r1) of NT columns
 // starting at c0, buckets [b0, b0 + kt).  Partial sums live in LDS as
 // acc[b + j*kt]; rows whose bucket is outside the tile are skipped (only
-// when the buckets of a column do not fit in LDS at once).  Y must be zero
-// on entry; the flush adds each non-zero partial with one atomic.
-template <typename T, int NT, bool VEC>
+// when the buckets of a column do not fit in LDS at once).  Y += the
+// partials, one atomic add per non-zero partial.
+template <typename T, int NT, bool VEC, bool CODES>
 __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
-                                                 const uint32_t *__restrict__ code, int64_t k,
+                                                 const uint32_t *__restrict__ code,
+                                                 const int32_t *__restrict__ h,
+                                                 const int8_t *__restrict__ s, int64_t k,
                                                  int64_t ktile, int64_t rows_per_chunk,
                                                  T *__restrict__ Y, int64_t ldy, int *status) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -343,6 +437,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
   const int nc = min(NT, cols.ncols - c0);
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_chunk;
   const int64_t r1 = min(d, r0 + rows_per_chunk);
+  bool bad = false;
 
   for (uint32_t t = threadIdx.x; t < kt * NT; t += blockDim.x) acc[t] = T(0);
   const T *cp[NT];
@@ -352,14 +447,14 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
 
   if (VEC) {
     using V = typename Vec16<T>::type;
-    using CV = typename Vec16<T>::code_t;
     constexpr int W = Vec16<T>::N;
     const int64_t step = (int64_t)blockDim.x * W;
     int64_t i = r0 + (int64_t)threadIdx.x * W;
     // two vectors in flight per thread per iteration
     for (; i + step + W <= r1; i += 2 * step) {
-      const CV cd0 = *reinterpret_cast<const CV *>(code + i);
-      const CV cd1 = *reinterpret_cast<const CV *>(code + i + step);
+      uint32_t e0[W], e1[W];
+      row_words<CODES, W>(code, h, s, i, k, e0, bad);
+      row_words<CODES, W>(code, h, s, i + step, k, e1, bad);
       V a0[NT], a1[NT];
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
@@ -368,35 +463,34 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
       }
 #pragma unroll
       for (int q = 0; q < W; ++q) {
-        const uint32_t e0 = code_of(cd0, q), e1 = code_of(cd1, q);
-        const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
-        const uint32_t l1 = (e1 & kIdxMask) - (uint32_t)b0;
+        const uint32_t l0 = (e0[q] & kIdxMask) - (uint32_t)b0;
+        const uint32_t l1 = (e1[q] & kIdxMask) - (uint32_t)b0;
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
           if (j < nc) {
-            if (l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(lane_of<T>(a0[j], q), e0));
-            if (l1 < kt) atomicAdd(&acc[l1 + j * kt], apply_sign(lane_of<T>(a1[j], q), e1));
+            if (l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(lane_of<T>(a0[j], q), e0[q]));
+            if (l1 < kt) atomicAdd(&acc[l1 + j * kt], apply_sign(lane_of<T>(a1[j], q), e1[q]));
           }
         }
       }
     }
     for (; i < r1; i += step) {
       if (i + W <= r1) {
-        const CV cd0 = *reinterpret_cast<const CV *>(code + i);
+        uint32_t e0[W];
+        row_words<CODES, W>(code, h, s, i, k, e0, bad);
         V a0[NT];
 #pragma unroll
         for (int j = 0; j < NT; ++j) a0[j] = *reinterpret_cast<const V *>(cp[j] + i);
 #pragma unroll
         for (int q = 0; q < W; ++q) {
-          const uint32_t e0 = code_of(cd0, q);
-          const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
+          const uint32_t l0 = (e0[q] & kIdxMask) - (uint32_t)b0;
 #pragma unroll
           for (int j = 0; j < NT; ++j)
-            if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(lane_of<T>(a0[j], q), e0));
+            if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(lane_of<T>(a0[j], q), e0[q]));
         }
       } else {
         for (int64_t r = i; r < r1; ++r) {
-          const uint32_t e0 = code[r];
+          const uint32_t e0 = row_word<CODES>(code, h, s, r, k, bad);
           const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
 #pragma unroll
           for (int j = 0; j < NT; ++j)
@@ -406,65 +500,263 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
     }
   } else {
     for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-      const uint32_t e0 = code[r];
+      const uint32_t e0 = row_word<CODES>(code, h, s, r, k, bad);
       const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
 #pragma unroll
       for (int j = 0; j < NT; ++j)
         if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(cp[j][r], e0));
     }
   }
+  if (bad) record_status(status, MS_ERR_RANGE);
   __syncthreads();
   for (uint32_t t = threadIdx.x; t < kt * (uint32_t)nc; t += blockDim.x) {
     const uint32_t j = t / kt, b = t - j * kt;
     const T v = acc[t];
     if (v != T(0)) unsafeAtomicAdd(&Y[(b0 + b) + (int64_t)(c0 + j) * ldy], v);
   }
-  // codes with a bucket >= k (only possible for codes not made by the pack
-  // kernel) were skipped above; the last bucket tile's first column tile
-  // reports them
-  if (blockIdx.z == gridDim.z - 1 && blockIdx.y == 0) {
-    bool bad = false;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) bad |= (int64_t)(code[r] & kIdxMask) >= k;
-    if (bad) record_status(status, MS_ERR_RANGE);
+}
+
+// ------------------------------------------------------------------ persistent, XCD-aware
+
+// Rows [r0, r1) of column tile ct (NT columns from c0) and bucket tile
+// [b0, b0 + kt): accumulate into LDS (zero on entry), then add the non-zero
+// partials to Y and leave LDS zero again.  UNR vectors in flight per thread.
+template <typename T, int NT, bool VEC, bool CODES, int UNR>
+__device__ __forceinline__ void cs_segment(T *acc, const Cols<T> &cols, int c0, int nc,
+                                           const uint32_t *__restrict__ code,
+                                           const int32_t *__restrict__ h,
+                                           const int8_t *__restrict__ s, int64_t k, int64_t b0,
+                                           uint32_t kt, int64_t r0, int64_t r1,
+                                           T *__restrict__ Y, int64_t ldy, bool &bad) {
+  const T *cp[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) cp[j] = col_ptr(cols, min(c0 + j, cols.ncols - 1));
+  auto scalar_row = [&](int64_t r) {
+    const uint32_t e0 = row_word<CODES>(code, h, s, r, k, bad);
+    const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+      if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(cp[j][r], e0));
+  };
+  if (VEC) {
+    using V = typename Vec16<T>::type;
+    constexpr int W = Vec16<T>::N;
+    // head rows up to the first multiple of W
+    const int64_t ra = min(r1, (r0 + W - 1) / W * W);
+    for (int64_t r = r0 + threadIdx.x; r < ra; r += blockDim.x) scalar_row(r);
+    const int64_t step = (int64_t)blockDim.x * W;
+    int64_t i = ra + (int64_t)threadIdx.x * W;
+    for (; i + (UNR - 1) * step + W <= r1; i += UNR * step) {
+      uint32_t e[UNR][W];
+      V a[UNR][NT];
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) row_words<CODES, W>(code, h, s, i + u * step, k, e[u], bad);
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+          a[u][j] = __builtin_nontemporal_load(reinterpret_cast<const V *>(cp[j] + i + u * step));
+#pragma unroll
+      for (int u = 0; u < UNR; ++u)
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+          const uint32_t l = (e[u][q] & kIdxMask) - (uint32_t)b0;
+#pragma unroll
+          for (int j = 0; j < NT; ++j)
+            if (j < nc && l < kt) atomicAdd(&acc[l + j * kt], apply_sign(lane_of<T>(a[u][j], q), e[u][q]));
+        }
+    }
+    for (; i < r1; i += step) {
+      if (i + W <= r1) {
+        uint32_t e0[W];
+        row_words<CODES, W>(code, h, s, i, k, e0, bad);
+        V a0[NT];
+#pragma unroll
+        for (int j = 0; j < NT; ++j) a0[j] = *reinterpret_cast<const V *>(cp[j] + i);
+#pragma unroll
+        for (int q = 0; q < W; ++q) {
+          const uint32_t l0 = (e0[q] & kIdxMask) - (uint32_t)b0;
+#pragma unroll
+          for (int j = 0; j < NT; ++j)
+            if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(lane_of<T>(a0[j], q), e0[q]));
+        }
+      } else {
+        for (int64_t r = i; r < r1; ++r) scalar_row(r);
+      }
+    }
+  } else {
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) scalar_row(r);
   }
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < kt * (uint32_t)nc; t += blockDim.x) {
+    const uint32_t j = t / kt, b = t - j * kt;
+    const T v = acc[t];
+    acc[t] = T(0);
+    if (v != T(0)) unsafeAtomicAdd(&Y[(b0 + b) + (int64_t)(c0 + j) * ldy], v);
+  }
+  __syncthreads();
+}
+
+// Persistent grid of xcds * spx workgroups.  Workgroups are dispatched to the
+// accelerator dies round-robin by id, so workgroup g runs on die g % xcds;
+// die x owns rows [x*rpx, (x+1)*rpx), so the codes of those rows are shared
+// in its L2.  On a die, slot s takes bucket tile s % nbt and an equal,
+// contiguous share of the (column tile, row) space of its rows, so the bucket
+// tiles of a column are streamed by workgroups of the same die at the same
+// time, and each workgroup flushes LDS only when its share crosses a column
+// tile.
+template <typename T, int NT, bool VEC, bool CODES, int UNR>
+__global__ __launch_bounds__(1024) void k_cs_lds_xcd(int64_t d, Cols<T> cols,
+                                                     const uint32_t *__restrict__ code,
+                                                     const int32_t *__restrict__ h,
+                                                     const int8_t *__restrict__ s, int64_t k,
+                                                     int64_t ktile, int nct, int nbt, int xcds,
+                                                     int spx, int64_t rpx, T *__restrict__ Y,
+                                                     int64_t ldy, int *status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *acc = reinterpret_cast<T *>(smem_raw);
+  const int g = blockIdx.x;
+  const int x = g % xcds, slot = g / xcds;
+  const int subs = spx / nbt;
+  if (slot >= subs * nbt) return;
+  const int bt = slot % nbt, sub = slot / nbt;
+  const int64_t R0 = (int64_t)x * rpx, R1 = min(d, R0 + rpx);
+  if (R0 >= R1) return;
+  const int64_t len = R1 - R0;
+  const int64_t b0 = (int64_t)bt * ktile;
+  const uint32_t kt = (uint32_t)min(ktile, k - b0);
+  for (uint32_t t = threadIdx.x; t < kt * NT; t += blockDim.x) acc[t] = T(0);
+  __syncthreads();
+  const int64_t total = (int64_t)nct * len;
+  int64_t u0 = (total * sub / subs) & ~(int64_t)255;
+  const int64_t u1 = sub + 1 == subs ? total : ((total * (sub + 1) / subs) & ~(int64_t)255);
+  bool bad = false;
+  while (u0 < u1) {
+    const int ct = (int)(u0 / len);
+    const int64_t rlo = u0 - (int64_t)ct * len;
+    const int64_t rhi = min(len, rlo + (u1 - u0));
+    const int c0 = ct * NT;
+    const int nc = min(NT, cols.ncols - c0);
+    cs_segment<T, NT, VEC, CODES, UNR>(acc, cols, c0, nc, code, h, s, k, b0, kt, R0 + rlo,
+                                       R0 + rhi, Y, ldy, bad);
+    u0 += rhi - rlo;
+  }
+  if (bad) record_status(status, MS_ERR_RANGE);
+}
+
+template <typename T, int NT, bool CODES>
+static hipError_t launch_cs_xcd_v(bool vec, int grid, size_t lds, hipStream_t st, int64_t d,
+                                  const Cols<T> &c, const uint32_t *code, const int32_t *h,
+                                  const int8_t *s, int64_t k, int64_t ktile, int nct, int nbt,
+                                  int xcds, int spx, int64_t rpx, T *Y, int64_t ldy, int *status) {
+  // vectors in flight per thread: fewer for wider column tiles (registers)
+  constexpr int UNR = NT >= 8 ? 1 : NT >= 4 ? 2 : 4;
+  const void *fn = vec ? (const void *)k_cs_lds_xcd<T, NT, true, CODES, UNR>
+                       : (const void *)k_cs_lds_xcd<T, NT, false, CODES, UNR>;
+  hipError_t e = allow_dynamic_lds(fn, (int)lds);
+  if (e != hipSuccess) return e;
+  if (vec)
+    hipLaunchKernelGGL((k_cs_lds_xcd<T, NT, true, CODES, UNR>), dim3(grid), dim3(1024), lds, st, d,
+                       c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy, status);
+  else
+    hipLaunchKernelGGL((k_cs_lds_xcd<T, NT, false, CODES, UNR>), dim3(grid), dim3(1024), lds, st,
+                       d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy, status);
+  return hipGetLastError();
+}
+
+template <typename T, int NT, bool CODES>
+static hipError_t launch_cs_lds_v(bool vec, dim3 grid, size_t lds, hipStream_t st, int64_t d,
+                                  const Cols<T> &c, const uint32_t *code, const int32_t *h,
+                                  const int8_t *s, int64_t k, int64_t ktile, int64_t rows, T *Y,
+                                  int64_t ldy, int *status) {
+  const void *fn = vec ? (const void *)k_cs_lds<T, NT, true, CODES>
+                       : (const void *)k_cs_lds<T, NT, false, CODES>;
+  hipError_t e = allow_dynamic_lds(fn, (int)lds);
+  if (e != hipSuccess) return e;
+  if (vec)
+    hipLaunchKernelGGL((k_cs_lds<T, NT, true, CODES>), grid, dim3(1024), lds, st, d, c, code, h, s,
+                       k, ktile, rows, Y, ldy, status);
+  else
+    hipLaunchKernelGGL((k_cs_lds<T, NT, false, CODES>), grid, dim3(1024), lds, st, d, c, code, h,
+                       s, k, ktile, rows, Y, ldy, status);
+  return hipGetLastError();
 }
 
 template <typename T, int NT>
 static hipError_t launch_cs_lds_nt(bool vec, dim3 grid, size_t lds, hipStream_t st, int64_t d,
-                                   const Cols<T> &c, const uint32_t *code, int64_t k,
-                                   int64_t ktile, int64_t rows, T *Y, int64_t ldy, int *status) {
-  const void *fn = vec ? (const void *)k_cs_lds<T, NT, true> : (const void *)k_cs_lds<T, NT, false>;
-  hipError_t e = allow_dynamic_lds(fn, (int)lds);
-  if (e != hipSuccess) return e;
-  if (vec)
-    hipLaunchKernelGGL((k_cs_lds<T, NT, true>), grid, dim3(1024), lds, st, d, c, code, k, ktile,
-                       rows, Y, ldy, status);
-  else
-    hipLaunchKernelGGL((k_cs_lds<T, NT, false>), grid, dim3(1024), lds, st, d, c, code, k, ktile,
-                       rows, Y, ldy, status);
-  return hipGetLastError();
+                                   const Cols<T> &c, const uint32_t *code, const int32_t *h,
+                                   const int8_t *s, int64_t k, int64_t ktile, int64_t rows, T *Y,
+                                   int64_t ldy, int *status) {
+  if (code)
+    return launch_cs_lds_v<T, NT, true>(vec, grid, lds, st, d, c, code, h, s, k, ktile, rows, Y,
+                                        ldy, status);
+  return launch_cs_lds_v<T, NT, false>(vec, grid, lds, st, d, c, code, h, s, k, ktile, rows, Y,
+                                       ldy, status);
 }
 
+// LDS CountSketch.  Default: the persistent die-aware schedule; the earlier
+// one-workgroup-per-(chunk, tile) grid is kept behind MS_CS_GRID (tuning).
 template <typename T>
-hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t *code, T *Y,
-                         int64_t ldy, bool zero_first, int *status, hipStream_t st) {
+hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t *code,
+                         const int32_t *h, const int8_t *s, T *Y, int64_t ldy, bool zero_first,
+                         int *status, hipStream_t st, const CsTuning *tune) {
   hipError_t e = zero_first ? launch_fill_zero<T>(Y, k, c.ncols, ldy, st) : hipSuccess;
   if (e != hipSuccess || d <= 0 || c.ncols <= 0) return e;
   const DevInfo &di = dev_info();
   const int64_t w = sizeof(T);
   const int64_t cap = std::min<int64_t>(di.lds_per_block, 128 * 1024);
-  // bucket tile: all k buckets when one column fits, else the largest
-  // power-of-two tile that does
   int64_t ktile = k;
   if (k * w > cap) {
     ktile = 1;
     while (ktile * 2 * w <= cap) ktile *= 2;
   }
   const int64_t nbt = (k + ktile - 1) / ktile;
+  const uintptr_t mis = (reinterpret_cast<uintptr_t>(c.A) | reinterpret_cast<uintptr_t>(c.B) |
+                         (uintptr_t)(c.lda * w) | (uintptr_t)(c.B ? c.ldb * w : 0) |
+                         reinterpret_cast<uintptr_t>(code) | reinterpret_cast<uintptr_t>(h));
+  const uintptr_t smis = reinterpret_cast<uintptr_t>(s) & (uintptr_t)(16 / w - 1);
+  const bool vec = (mis & 15) == 0 && smis == 0;
+  const bool grid_variant = tune && tune->grid_variant;
+  if (!grid_variant) {
+    const int xcds = (di.cus % di.xcds == 0) ? di.xcds : 1;
+    int64_t rpx = (d + xcds - 1) / xcds;
+    rpx = (rpx + 255) / 256 * 256;
+    // columns per workgroup: as many as LDS holds (and the caller allows)
+    // while each workgroup still streams at least 8 rows per flushed bucket
+    auto spx_of = [&](int nt_) {
+      const int64_t l = ktile * w * nt_;
+      return di.cus / xcds * (int)std::max<int64_t>(1, std::min<int64_t>(2, di.lds_per_block / l));
+    };
+    int nt = 1;
+    const int want_nt = tune && tune->cols_per_wg ? tune->cols_per_wg : 8;
+    while (nt * 2 <= want_nt && ktile * w * nt * 2 <= cap && nt * 2 <= c.ncols) {
+      const int64_t nct2 = (c.ncols + nt * 2 - 1) / (nt * 2);
+      const int64_t per_wg = nct2 * nbt * rpx / std::max(1, spx_of(nt * 2));
+      if (!(tune && tune->cols_per_wg) && per_wg < 8 * ktile * nbt) break;
+      nt *= 2;
+    }
+    const int64_t lds = ktile * w * nt;
+    const int spx = spx_of(nt);
+    if (nbt > spx) return hipErrorNotSupported;
+    const int64_t nct = (c.ncols + nt - 1) / nt;
+    const int grid = xcds * spx;
+#define MS_XCD_CASE(NT_)                                                                         \
+  if (nt == NT_)                                                                                 \
+    return code ? launch_cs_xcd_v<T, NT_, true>(vec, grid, lds, st, d, c, code, h, s, k, ktile,   \
+                                                (int)nct, (int)nbt, xcds, spx, rpx, Y, ldy,      \
+                                                status)                                          \
+                : launch_cs_xcd_v<T, NT_, false>(vec, grid, lds, st, d, c, code, h, s, k, ktile,  \
+                                                 (int)nct, (int)nbt, xcds, spx, rpx, Y, ldy,     \
+                                                 status);
+    MS_XCD_CASE(8)
+    MS_XCD_CASE(4)
+    MS_XCD_CASE(2)
+    MS_XCD_CASE(1)
+#undef MS_XCD_CASE
+    return hipErrorInvalidValue;
+  }
+  // grid variant: one workgroup per (row chunk, column tile, bucket tile)
   const int64_t lds1 = ktile * w;
-  const int64_t per_cu1 = std::max<int64_t>(1, std::min<int64_t>(2, di.lds_per_block / lds1));
-  // rows per chunk never below 2048; columns per workgroup (nt) as many as
-  // LDS holds while there is still at least one workgroup per slot
   const int64_t c_hi = std::max<int64_t>(1, d / 2048);
   int nt = 1;
   while (nt < 8 && lds1 * nt * 2 <= cap && nt * 2 <= c.ncols) {
@@ -473,14 +765,10 @@ hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t 
     if (units2 * c_hi < (int64_t)di.cus * per_cu2) break;
     nt *= 2;
   }
-  (void)per_cu1;
   const int64_t nct = (c.ncols + nt - 1) / nt;
   const int64_t lds = lds1 * nt;
   const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(2, di.lds_per_block / lds));
   const int64_t slots = (int64_t)di.cus * per_cu;
-  // enough chunks to fill every slot, more while the LDS flush (ktile
-  // partials per chunk) stays under 1/16 of the streamed rows; then rounded
-  // to whole rounds of resident workgroups
   const int64_t units = nct * nbt;
   const int64_t c_flush = std::max<int64_t>(1, d / (16 * ktile));
   int64_t chunks = std::min(c_hi, std::max(c_flush, (slots + units - 1) / units));
@@ -489,21 +777,20 @@ hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t 
   int64_t rows = (d + chunks - 1) / chunks;
   rows = (rows + 255) / 256 * 256;
   chunks = (d + rows - 1) / rows;
-  const uintptr_t mis = (reinterpret_cast<uintptr_t>(c.A) | reinterpret_cast<uintptr_t>(c.B) |
-                         (uintptr_t)(c.lda * w) | (uintptr_t)(c.B ? c.ldb * w : 0));
-  const bool vec = (mis & 15) == 0;
   const dim3 grid((unsigned)chunks, (unsigned)nct, (unsigned)nbt);
   switch (nt) {
-    case 8: return launch_cs_lds_nt<T, 8>(vec, grid, lds, st, d, c, code, k, ktile, rows, Y, ldy, status);
-    case 4: return launch_cs_lds_nt<T, 4>(vec, grid, lds, st, d, c, code, k, ktile, rows, Y, ldy, status);
-    case 2: return launch_cs_lds_nt<T, 2>(vec, grid, lds, st, d, c, code, k, ktile, rows, Y, ldy, status);
-    default: return launch_cs_lds_nt<T, 1>(vec, grid, lds, st, d, c, code, k, ktile, rows, Y, ldy, status);
+    case 8: return launch_cs_lds_nt<T, 8>(vec, grid, lds, st, d, c, code, h, s, k, ktile, rows, Y, ldy, status);
+    case 4: return launch_cs_lds_nt<T, 4>(vec, grid, lds, st, d, c, code, h, s, k, ktile, rows, Y, ldy, status);
+    case 2: return launch_cs_lds_nt<T, 2>(vec, grid, lds, st, d, c, code, h, s, k, ktile, rows, Y, ldy, status);
+    default: return launch_cs_lds_nt<T, 1>(vec, grid, lds, st, d, c, code, h, s, k, ktile, rows, Y, ldy, status);
   }
 }
 template hipError_t launch_cs_lds<double>(int64_t, int64_t, const Cols<double> &, const uint32_t *,
-                                          double *, int64_t, bool, int *, hipStream_t);
+                                          const int32_t *, const int8_t *, double *, int64_t, bool,
+                                          int *, hipStream_t, const CsTuning *);
 template hipError_t launch_cs_lds<float>(int64_t, int64_t, const Cols<float> &, const uint32_t *,
-                                         float *, int64_t, bool, int *, hipStream_t);
+                                         const int32_t *, const int8_t *, float *, int64_t, bool,
+                                         int *, hipStream_t, const CsTuning *);
 
 // ------------------------------------------------------------------ sorted (deterministic)
 

@@ -127,7 +127,14 @@ __device__ __forceinline__ v8bf load_b<DT_BF16>(const float *Y, int64_t ldy, int
 }
 
 // Workgroup = 4 waves over a 64 x 64 output tile (each wave 32 x 32, i.e.
-// 2 x 2 matrix-core blocks), one K chunk per blockIdx.z.
+// 2 x 2 matrix-core blocks), one K chunk per blockIdx.z.  Fragments are
+// loaded U instructions ahead: the loads of the next batch are in flight
+// while the current batch runs on the matrix cores.
+template <int DT>
+struct Unroll {
+  static constexpr int U = DT == DT_BF16 ? 2 : 8;
+};
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
                                                      const typename Mf<DT>::TG *__restrict__ G,
@@ -137,6 +144,7 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
                                                      typename Mf<DT>::Acc *__restrict__ part,
                                                      int64_t kchunk) {
   using F = Mf<DT>;
+  constexpr int U = Unroll<DT>::U;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int m_base = blockIdx.x * 64 + (wave & 1) * 32;
@@ -149,17 +157,37 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = typename F::AccV{};
-  for (int64_t kk = kb; kk < ke; kk += F::KS) {
-    const int64_t kq = kk + (int64_t)lk * KPL;
-    typename F::Frag a[2], b[2];
+  typename F::Frag a[U][2], b[U][2];
+  auto load_batch = [&](int64_t k0, typename F::Frag (&fa)[U][2], typename F::Frag (&fb)[U][2]) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) a[i] = load_a<DT>(G, ldg, M, m_base + 16 * i + li, kq, ke);
+    for (int u = 0; u < U; ++u) {
+      const int64_t kq = k0 + (int64_t)u * F::KS + (int64_t)lk * KPL;
 #pragma unroll
-    for (int j = 0; j < 2; ++j) b[j] = load_b<DT>(Y, ldy, N, n_base + 16 * j + li, kq, ke);
+      for (int i = 0; i < 2; ++i) fa[u][i] = load_a<DT>(G, ldg, M, m_base + 16 * i + li, kq, ke);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) fb[u][j] = load_b<DT>(Y, ldy, N, n_base + 16 * j + li, kq, ke);
+    }
+  };
+  load_batch(kb, a, b);
+  for (int64_t kk = kb; kk < ke; kk += (int64_t)F::KS * U) {
+    typename F::Frag an[U][2], bn[U][2];
+    const bool more = kk + (int64_t)F::KS * U < ke;
+    if (more) load_batch(kk + (int64_t)F::KS * U, an, bn);
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = F::mma(a[i], b[j], acc[i][j]);
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = F::mma(a[u][i], b[u][j], acc[i][j]);
+    if (more) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          a[u][i] = an[u][i];
+          b[u][i] = bn[u][i];
+        }
+    }
   }
   typename F::Acc *P = part + (int64_t)blockIdx.z * M * N;
 #pragma unroll
@@ -177,6 +205,7 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
 
 // Z[p, c] = sum over splits (in split order) of the partials; written to Z
 // (its own dtype and leading dimension) and/or to an FP64 copy z64 (ld = M).
+// Loads are issued eight splits ahead of the (ordered) adds.
 template <typename Acc, typename TZ>
 __global__ void k_reduce_splits(int M, int N, int nsplit, const Acc *__restrict__ part,
                                 TZ *__restrict__ Z, int64_t ldz, double *__restrict__ z64) {
@@ -184,7 +213,15 @@ __global__ void k_reduce_splits(int M, int N, int nsplit, const Acc *__restrict_
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < MN;
        t += (int64_t)gridDim.x * blockDim.x) {
     Acc s = part[t];
-    for (int z = 1; z < nsplit; ++z) s = s + part[t + z * MN];
+    int z = 1;
+    for (; z + 8 <= nsplit; z += 8) {
+      Acc v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[t + (int64_t)(z + u) * MN];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s = s + v[u];
+    }
+    for (; z < nsplit; ++z) s = s + part[t + (int64_t)z * MN];
     const int64_t c = t / M, p = t - c * M;
     if (Z) Z[p + c * ldz] = (TZ)s;
     if (z64) z64[t] = (double)s;
@@ -200,8 +237,8 @@ GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K, ms_dtype g_dtype) {
   p.tiles_n = (int)((N + 63) / 64);
   const int64_t ks = g_dtype == MS_BF16 ? 32 : 4;
   const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
-  // aim for ~1024 workgroups but keep at least 256 K values per workgroup
-  int64_t ns = std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, (K + 255) / 256));
+  // aim for ~1024 workgroups but keep at least 128 K values per workgroup
+  int64_t ns = std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, (K + 127) / 128));
   ns = std::min<int64_t>(ns, 65535);
   int64_t kc = (K + ns - 1) / ns;
   kc = (kc + ks - 1) / ks * ks;
@@ -221,30 +258,34 @@ hipError_t launch_gemm(const GemmPlan &p, ms_dtype g_dtype, const void *G, int64
   (void)ybf16;
   if (p.M <= 0 || p.N <= 0) return hipSuccess;
   const int64_t MN = (int64_t)p.M * p.N;
-  const unsigned rblocks = (unsigned)std::min<int64_t>((MN + 255) / 256, 4096);
+  const unsigned rblocks = (unsigned)std::min<int64_t>((MN + 255) / 256, 65535);
   if (p.K <= 0) return hipErrorInvalidValue;
   const dim3 grid((unsigned)p.tiles_m, (unsigned)p.tiles_n, (unsigned)p.nsplit);
+  const bool reduce = Z != nullptr || z64 != nullptr;  // otherwise the caller consumes the partials
   switch (g_dtype) {
     case MS_F64:
       hipLaunchKernelGGL(k_gemm_splitk<DT_F64>, grid, dim3(256), 0, st, p.M, p.N, p.K,
                          (const double *)G, ldg, (const double *)Y, ldy, (double *)partials,
                          p.kchunk);
-      hipLaunchKernelGGL((k_reduce_splits<double, double>), dim3(rblocks), dim3(256), 0, st, p.M,
-                         p.N, p.nsplit, (const double *)partials, (double *)Z, ldz, z64);
+      if (reduce)
+        hipLaunchKernelGGL((k_reduce_splits<double, double>), dim3(rblocks), dim3(256), 0, st, p.M,
+                           p.N, p.nsplit, (const double *)partials, (double *)Z, ldz, z64);
       break;
     case MS_F32:
       hipLaunchKernelGGL(k_gemm_splitk<DT_F32>, grid, dim3(256), 0, st, p.M, p.N, p.K,
                          (const float *)G, ldg, (const float *)Y, ldy, (float *)partials,
                          p.kchunk);
-      hipLaunchKernelGGL((k_reduce_splits<float, float>), dim3(rblocks), dim3(256), 0, st, p.M,
-                         p.N, p.nsplit, (const float *)partials, (float *)Z, ldz, z64);
+      if (reduce)
+        hipLaunchKernelGGL((k_reduce_splits<float, float>), dim3(rblocks), dim3(256), 0, st, p.M,
+                           p.N, p.nsplit, (const float *)partials, (float *)Z, ldz, z64);
       break;
     case MS_BF16:
       hipLaunchKernelGGL(k_gemm_splitk<DT_BF16>, grid, dim3(256), 0, st, p.M, p.N, p.K,
                          (const unsigned short *)G, ldg, (const float *)Y, ldy, (float *)partials,
                          p.kchunk);
-      hipLaunchKernelGGL((k_reduce_splits<float, float>), dim3(rblocks), dim3(256), 0, st, p.M,
-                         p.N, p.nsplit, (const float *)partials, (float *)Z, ldz, z64);
+      if (reduce)
+        hipLaunchKernelGGL((k_reduce_splits<float, float>), dim3(rblocks), dim3(256), 0, st, p.M,
+                           p.N, p.nsplit, (const float *)partials, (float *)Z, ldz, z64);
       break;
     default:
       return hipErrorInvalidValue;

@@ -81,12 +81,16 @@ struct Cols {
 
 // countsketch.hip
 hipError_t launch_zero_status(int *status, hipStream_t st);
+// Clear the status word and a rows x cols buffer (ld) in one launch.
+template <typename T>
+hipError_t launch_prologue(int *status, T *Y, int64_t rows, int64_t cols, int64_t ld,
+                           hipStream_t st);
 template <typename T>
 hipError_t launch_fill_zero(T *Y, int64_t rows, int64_t cols, int64_t ld, hipStream_t st);
 hipError_t launch_pack_codes(int64_t d, int64_t k, const int32_t *h, const int8_t *s,
                              uint32_t *code, int *status, hipStream_t st);
-// Plan: cnt (k), off (k+1), cursor (k), sperm (d) -- row index | sign bit
-// (sign bit only when s is non-null).
+// Plan: cnt (k, zero on entry), off (k+1), cursor (k), sperm (d) -- row
+// index | sign bit (sign bit only when s is non-null).
 hipError_t launch_plan(int64_t d, int64_t k, const int32_t *h, const int8_t *s,
                        int32_t *cnt, int32_t *off, int32_t *cursor, uint32_t *sperm,
                        int *status, hipStream_t st);
@@ -97,9 +101,17 @@ hipError_t launch_strip_sign(int64_t d, const uint32_t *sperm, int32_t *perm, hi
 template <typename T>
 hipError_t launch_cs_atomic(int64_t d, int64_t k, const Cols<T> &c, const uint32_t *code,
                             T *Y, int64_t ldy, bool zero_first, int *status, hipStream_t st);
+// Tuning of the LDS CountSketch (zero fields: defaults).
+struct CsTuning {
+  int cols_per_wg;   // upper bound on the columns one workgroup bins at once
+  int grid_variant;  // 1: one workgroup per (row chunk, column tile, bucket tile)
+};
+// LDS variant: the bucket/sign words come from `code` when non-null, else
+// from h and s directly (validated in the kernel).
 template <typename T>
 hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t *code,
-                         T *Y, int64_t ldy, bool zero_first, int *status, hipStream_t st);
+                         const int32_t *h, const int8_t *s, T *Y, int64_t ldy, bool zero_first,
+                         int *status, hipStream_t st, const CsTuning *tune = nullptr);
 template <typename T>
 hipError_t launch_cs_sorted(int64_t k, const Cols<T> &c, const int32_t *off,
                             const uint32_t *sperm, T *Y, int64_t ldy, hipStream_t st);
@@ -131,6 +143,15 @@ hipError_t launch_qr_solve(int64_t m, int64_t n, int64_t nrhs, const double *W, 
                            const double *Bm, int64_t ldb, double *X, int64_t ldx, double *R,
                            int64_t ldr, double *tau_out, double *fact_out, void *qr_ws,
                            int *status, hipStream_t st);
+// Register-resident variant for small systems (m <= 256, n + nrhs <= 144,
+// n (n + nrhs) doubles in LDS); input [W | Bm] or split-K partials (part: FP64,
+// part32: FP32, summed in split order).  hipErrorNotSupported when it does
+// not fit.
+bool qr_reg_fits(int64_t m, int64_t n, int64_t nrhs);
+hipError_t launch_qr_reg(int64_t m, int64_t n, int64_t nrhs, const double *W, int64_t ldw,
+                         const double *Bm, int64_t ldb, const double *part, const float *part32,
+                         int nsplit, double *X, int64_t ldx, double *R, int64_t ldr,
+                         double *tau_out, double *fact_out, int *status, hipStream_t st);
 // X = R^{-1} (Q^T Bm)_{0:n} from factors kept by launch_qr_solve (fact: m x n
 // with R on and above the diagonal and the reflector tails below, ld m; tau:
 // n).  Bm (m x nrhs, ld m) is overwritten.

@@ -119,6 +119,247 @@ __global__ __launch_bounds__(1024) void k_qr_solve(int m, int n, int nrhs, const
     wave_back_substitute(n, Mx, m, Mx + (int64_t)(n + c) * m, X + (int64_t)c * ldx);
 }
 
+// ------------------------------------------------------------------ register-resident QR
+// Wave-wide sum with DPP row operations (quad swaps, half-row and row
+// mirrors) and four lane reads, one per 16-lane row.  Every lane gets the
+// same value.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long u = __double_as_longlong(v);
+  int lo = (int)(u & 0xffffffffLL), hi = (int)(u >> 32);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_allsum(double v) {
+  v += dpp_move<0xb1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4e>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror: every lane holds its 16-lane row sum
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// Householder QR least squares with the system [W | Bm] (m x nc, nc = n +
+// nrhs) held in registers: lane l of wave w owns rows l + 64 r (r < RPL) of
+// columns w + 16 q (q < CPW).  Reflector j is built by the wave owning column
+// j and published through a double-buffered LDS vector, so each column costs
+// one barrier.  The input is either [W | Bm] or, when part (FP64) or part32
+// (FP32) is given, the sum in split order of nsplit split-K partial blocks of
+// an m x nc product -- the same sum, in the same precision, as the separate
+// split reduction.
+// R and the transformed right-hand sides go to LDS for the back substitution.
+template <int RPL, int CPW>
+__global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, int nrhs, const double *__restrict__ W,
+                                                 int64_t ldw, const double *__restrict__ Bm,
+                                                 int64_t ldb, const double *__restrict__ part,
+                                                 const float *__restrict__ part32, int nsplit,
+                                                 double *__restrict__ X, int64_t ldx,
+                                                 double *__restrict__ R, int64_t ldr,
+                                                 double *__restrict__ tau_out,
+                                                 double *__restrict__ fact_out, int *status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double *rs = reinterpret_cast<double *>(smem_raw);  // n x nc top block, ld n
+  __shared__ double vbuf[2][64 * RPL];
+  __shared__ double taubuf[2];
+  __shared__ int s_singular;
+  const int nc = n + nrhs;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t MN = (int64_t)m * nc;
+
+  double a[CPW][RPL];
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    const int c = wave + 16 * q;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lane + 64 * r;
+      double x = 0.0;
+      if (i < m && c < nc) {
+        const int64_t o = i + (int64_t)c * m;
+        if (part) {
+          x = part[o];
+          for (int z = 1; z < nsplit; ++z) x = x + part[o + z * MN];
+        } else if (part32) {
+          float x32 = part32[o];
+          for (int z = 1; z < nsplit; ++z) x32 = x32 + part32[o + z * MN];
+          x = (double)x32;
+        } else {
+          x = c < n ? W[i + (int64_t)c * ldw] : Bm[i + (int64_t)(c - n) * ldb];
+        }
+      }
+      a[q][r] = x;
+    }
+  }
+  if (threadIdx.x == 0) s_singular = 0;
+
+  for (int j = 0; j < n; ++j) {
+    const int buf = j & 1;
+    if (wave == (j & 15)) {
+      const int qj = j >> 4;
+      double col[RPL];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) col[r] = 0.0;
+#pragma unroll
+      for (int q = 0; q < CPW; ++q)
+        if (q == qj)
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) col[r] = a[q][r];
+      double p2 = 0.0, av = 0.0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        if (i > j) p2 += col[r] * col[r];
+        if (r == (j >> 6)) av = col[r];
+      }
+      const double xn2 = wave_allsum(p2);
+      const double alpha = read_lane(av, j & 63);
+      double tau = 0.0, beta = alpha, scal = 0.0;
+      if (xn2 != 0.0) {
+        const double nrm = sqrt(alpha * alpha + xn2);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        const double v = i > j ? col[r] * scal : (i == j ? 1.0 : 0.0);
+        vbuf[buf][i] = v;
+        if (xn2 != 0.0) col[r] = i > j ? v : (i == j ? beta : col[r]);
+      }
+#pragma unroll
+      for (int q = 0; q < CPW; ++q)
+        if (q == qj)
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) a[q][r] = col[r];
+      if (lane == 0) {
+        taubuf[buf] = tau;
+        if (tau_out) tau_out[j] = tau;
+      }
+    }
+    __syncthreads();
+    const double tau = taubuf[buf];
+    if (tau != 0.0) {
+      double v[RPL];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) v[r] = vbuf[buf][lane + 64 * r];
+      double dots[CPW];
+#pragma unroll
+      for (int q = 0; q < CPW; ++q) {
+        dots[q] = 0.0;
+        const int c = wave + 16 * q;
+        if (c > j && c < nc)
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) dots[q] += v[r] * a[q][r];
+      }
+#pragma unroll
+      for (int q = 0; q < CPW; ++q) dots[q] = wave_allsum(dots[q]);
+#pragma unroll
+      for (int q = 0; q < CPW; ++q) {
+        const int c = wave + 16 * q;
+        if (c > j && c < nc) {
+          const double w = tau * dots[q];
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) a[q][r] -= w * v[r];
+        }
+      }
+    }
+  }
+
+  // outputs of the factorisation, and the top n rows to LDS
+#pragma unroll
+  for (int q = 0; q < CPW; ++q) {
+    const int c = wave + 16 * q;
+    if (c >= nc) continue;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lane + 64 * r;
+      if (i >= m) continue;
+      if (fact_out && c < n) fact_out[i + (int64_t)c * m] = a[q][r];
+      if (i < n) {
+        rs[i + c * n] = a[q][r];
+        if (R && c < n) R[i + (int64_t)c * ldr] = i <= c ? a[q][r] : 0.0;
+        if (i == c && (a[q][r] == 0.0 || !isfinite(a[q][r]))) s_singular = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (s_singular) {
+    for (int64_t t = threadIdx.x; t < (int64_t)n * nrhs; t += blockDim.x) {
+      const int c = (int)(t / n), i = (int)(t - (int64_t)c * n);
+      X[i + (int64_t)c * ldx] = __longlong_as_double(0x7ff8000000000000LL);
+    }
+    if (threadIdx.x == 0) record_status(status, MS_ERR_SINGULAR);
+    return;
+  }
+  for (int c = wave; c < nrhs; c += 16)
+    wave_back_substitute(n, rs, n, rs + (int64_t)(n + c) * n, X + (int64_t)c * ldx);
+}
+
+struct QrRegShape {
+  int rpl, cpw;
+};
+// the register-resident instantiations, smallest first
+constexpr QrRegShape kQrShapes[] = {{1, 1}, {1, 2}, {1, 5}, {2, 2}, {2, 5}, {2, 9}, {4, 5}, {4, 9}};
+
+template <int RPL, int CPW>
+static hipError_t launch_qr_reg_t(int64_t m, int64_t n, int64_t nrhs, const double *W,
+                                  int64_t ldw, const double *Bm, int64_t ldb, const double *part,
+                                  const float *part32, int nsplit, double *X, int64_t ldx,
+                                  double *R, int64_t ldr,
+                                  double *tau_out, double *fact_out, int *status,
+                                  hipStream_t st) {
+  const size_t lds = (size_t)n * (size_t)(n + nrhs) * sizeof(double);
+  hipError_t e = allow_dynamic_lds((const void *)k_qr_reg<RPL, CPW>, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_qr_reg<RPL, CPW>), dim3(1), dim3(1024), lds, st, (int)m, (int)n, (int)nrhs,
+                     W, ldw, Bm, ldb, part, part32, nsplit, X, ldx, R, ldr, tau_out, fact_out,
+                     status);
+  return hipGetLastError();
+}
+
+// Returns hipErrorNotSupported when no register-resident shape fits.
+bool qr_reg_fits(int64_t m, int64_t n, int64_t nrhs) {
+  const int64_t nc = n + nrhs;
+  const size_t lds = (size_t)n * (size_t)nc * sizeof(double) + 2 * 64 * 4 * 8 + 64;
+  if (lds > (size_t)dev_info().lds_per_block) return false;
+  for (const QrRegShape &s : kQrShapes)
+    if (64 * s.rpl >= m && 16 * s.cpw >= nc) return true;
+  return false;
+}
+
+hipError_t launch_qr_reg(int64_t m, int64_t n, int64_t nrhs, const double *W, int64_t ldw,
+                         const double *Bm, int64_t ldb, const double *part, const float *part32,
+                         int nsplit, double *X, int64_t ldx, double *R, int64_t ldr,
+                         double *tau_out, double *fact_out, int *status, hipStream_t st) {
+  const int64_t nc = n + nrhs;
+  const size_t lds = (size_t)n * (size_t)nc * sizeof(double) + 2 * 64 * 4 * 8 + 64;
+  if (lds > (size_t)dev_info().lds_per_block) return hipErrorNotSupported;
+  for (const QrRegShape &s : kQrShapes) {
+    if (64 * s.rpl < m || 16 * s.cpw < nc) continue;
+#define MS_QR_CASE(R_, C_)                                                                     \
+  if (s.rpl == R_ && s.cpw == C_)                                                              \
+    return launch_qr_reg_t<R_, C_>(m, n, nrhs, W, ldw, Bm, ldb, part, part32, nsplit, X, ldx, R, \
+                                   ldr, tau_out, fact_out, status, st);
+    MS_QR_CASE(1, 1)
+    MS_QR_CASE(1, 2)
+    MS_QR_CASE(1, 5)
+    MS_QR_CASE(2, 2)
+    MS_QR_CASE(2, 5)
+    MS_QR_CASE(2, 9)
+    MS_QR_CASE(4, 5)
+    MS_QR_CASE(4, 9)
+#undef MS_QR_CASE
+  }
+  return hipErrorNotSupported;
+}
+
 size_t qr_workspace_bytes(int64_t m, int64_t n, int64_t nrhs) {
   return (size_t)m * (size_t)(n + nrhs) * sizeof(double);
 }
@@ -127,6 +368,9 @@ hipError_t launch_qr_solve(int64_t m, int64_t n, int64_t nrhs, const double *W, 
                            const double *Bm, int64_t ldb, double *X, int64_t ldx, double *R,
                            int64_t ldr, double *tau_out, double *fact_out, void *qr_ws,
                            int *status, hipStream_t st) {
+  hipError_t er = launch_qr_reg(m, n, nrhs, W, ldw, Bm, ldb, nullptr, nullptr, 0, X, ldx, R, ldr,
+                                tau_out, fact_out, status, st);
+  if (er != hipErrorNotSupported) return er;
   const DevInfo &di = dev_info();
   const size_t bytes = qr_workspace_bytes(m, n, nrhs);
   if (bytes + 1024 <= (size_t)di.lds_per_block) {

@@ -209,10 +209,17 @@ def test_lstsq_fp32_ill_conditioned_residual(ms, orc):
     assert rho_g <= 1.05 * rho_o + 1e-3
 
 
-@pytest.mark.parametrize("refine", [0, 1, 3])
+@pytest.mark.parametrize("refine", [0, 1, 2, 3])
 def test_lstsq_bf16_refinement(ms, orc, refine):
     # FP32 A with column scales down to 1e-4, BF16 Gaussian stage, FP64 QR,
-    # FP64-residual refinement steps
+    # FP64-residual refinement steps.  Without refinement the BF16 rounding of
+    # the sketched right-hand side costs about u_bf16 * (column scale ratio)
+    # in the small-scale components of x (relative error O(1)); each step
+    # contracts the error by about u_bf16 * kappa(column-scaled sketch)
+    # (~1e-3); the fixed point differs from the FP64 sketch-and-solve solution
+    # by a term proportional to the sketched residual (~1e-6 here, set by the
+    # 1e-6 noise of b).  The same iteration on the CPU oracle gives
+    # 1.31, 3.6e-3, 4.2e-6, 1.24e-6 for 0..3 steps on this problem.
     d, n, nrhs, k, k2 = 1 << 19, 32, 4, 2048, 64
     seed = 21
     Z = synth.normal_matrix(d, n, seed=seed, dtype=np.float64)
@@ -223,12 +230,16 @@ def test_lstsq_bf16_refinement(ms, orc, refine):
     G = synth.gaussian_sketch(k2, k, seed=seed, dtype="bf16")
     X = _gpu_lstsq(ms, A, B, h, s, G, k, gd="bf16", refine_steps=refine)
     # the FP64 sketch-and-solve solution with the same (h, s, G)
-    X64, _, _ = orc.sketch_lstsq(A.astype(np.float64), B.astype(np.float64), h, s,
-                                 G.astype(np.float64), k)
+    A64, B64 = A.astype(np.float64), B.astype(np.float64)
+    X64, _, _ = orc.sketch_lstsq(A64, B64, h, s, G.astype(np.float64), k)
     err = rel(X, X64)
-    print("refine=%d err vs FP64 sketch-and-solve = %.3e" % (refine, err))
-    bound = {0: 5e-2, 1: 1e-3, 3: 1e-6}[refine]
-    assert err <= bound
+    xt = np.linalg.lstsq(A64, B64, rcond=None)[0]
+    rho = np.linalg.norm(B64 - A64 @ X) / np.linalg.norm(B64 - A64 @ xt)
+    print("refine=%d err vs FP64 sketch-and-solve = %.3e, rho = %.4f" % (refine, err, rho))
+    bound = {0: 5.0, 1: 1e-2, 2: 1e-4, 3: 1e-5}[refine]
+    assert np.isfinite(X).all() and err <= bound
+    if refine >= 2:
+        assert rho <= 2.0
 
 
 def test_lstsq_range_error(ms):
