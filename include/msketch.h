@@ -81,6 +81,14 @@ typedef struct {
   int32_t cs_schedule;  /* MS_CS_LDS tuning: 0 = persistent die-aware
                            schedule (default), 1 = one workgroup per (row
                            chunk, column tile, bucket tile) */
+  int32_t batch_rows_log2;   /* sketch_lstsq_batched tuning: rows per
+                                CountSketch work item = 2^x (0 = automatic,
+                                else 8..24) */
+  int32_t batch_kchunk_log2; /* sketch_lstsq_batched tuning: K per Gaussian-
+                                stage work item = 2^x (0 = automatic, else
+                                5..20) */
+  int32_t reserved0;
+  int32_t reserved1;
 } ms_opts;
 
 /* op codes of ms_workspace_size() */
@@ -229,6 +237,67 @@ ms_status sketch_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k,
                        int64_t ldg, double *X, int64_t ldx,
                        const ms_opts *opts, void *ws, size_t ws_bytes,
                        void *stream);
+
+/*
+ * One problem of a batched multisketch sketch-and-solve (all device
+ * pointers; the meaning of every field is that of the sketch_lstsq argument
+ * of the same name).
+ */
+typedef struct {
+  int64_t d, n, nrhs, k, k2;
+  const void *A;
+  int64_t lda;
+  const void *B;
+  int64_t ldb;
+  const int32_t *h;
+  const int8_t *s;
+  const void *G;
+  int64_t ldg;
+  double *X;
+  int64_t ldx;
+} ms_problem;
+
+/* Largest sketched system a batched problem may have (register-resident QR). */
+#define MS_BATCH_MAX_K2 256
+#define MS_BATCH_MAX_COLS 144
+
+/*
+ * Workspace bytes of sketch_lstsq_batched for these problems (host array).
+ * 0 for invalid arguments.  A workspace sized for one set of problems serves
+ * any other set with the same count whose problems are no larger in k,
+ * k2 and n + nrhs (d does not enter).
+ */
+size_t ms_batch_workspace_size(int count, const ms_problem *probs,
+                               ms_dtype a_dtype, ms_dtype g_dtype,
+                               const ms_opts *opts);
+
+/*
+ * Batched multisketch sketch-and-solve: every problem p is solved as
+ * sketch_lstsq would solve it (same association G (C [A | B]), same
+ * Householder QR and back substitution), all problems together in a fixed
+ * sequence of six launches whose grids do not depend on the problems'
+ * contents -- so the sequence can be captured once in a HIP graph and
+ * replayed after the descriptors in device memory are rewritten.
+ *   count      number of problems (1 .. 65535);
+ *   probs_host host copy of the descriptors: validated, and used for the
+ *              launch shapes (LDS size, QR register tile);
+ *   probs_dev  the same descriptors in device memory (read by the kernels);
+ *   a_dtype    MS_F32 or MS_F64 (all problems); g_dtype as for sketch_lstsq.
+ * Limits per problem: k2 <= MS_BATCH_MAX_K2, n + nrhs <= MS_BATCH_MAX_COLS,
+ * k2 >= n >= 1, nrhs >= 1, 1 <= d < 2^31, 1 <= k < 2^31.  The CountSketch is the
+ * LDS variant (opts->cs_mode MS_CS_SORTED -> MS_ERR_UNSUPPORTED); no
+ * refinement (opts->refine_steps must be 0).  Device errors are recorded per
+ * problem (ms_batch_status) and in the workspace status word.
+ */
+ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
+                               const ms_problem *probs_dev, ms_dtype a_dtype,
+                               ms_dtype g_dtype, const ms_opts *opts, void *ws,
+                               size_t ws_bytes, void *stream);
+
+/* Synchronises `stream` and copies the per-problem status codes of the last
+ * sketch_lstsq_batched call on `ws` into status_host (count entries). */
+ms_status ms_batch_status(const void *ws, int count, int32_t *status_host,
+                          void *stream);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,8 @@ __all__ = [
     "MS_ERR_DEVICE", "MS_ERR_UNSUPPORTED", "MsketchError", "LIB_PATH",
     "empty_colmajor", "colmajor", "workspace", "workspace_size", "check_status",
     "bucket_plan", "pack_sketch", "countsketch_accumulate", "countsketch_apply",
-    "gaussian_apply", "multisketch_apply", "qr_solve", "sketch_lstsq",
+    "gaussian_apply", "multisketch_apply", "qr_solve", "sketch_lstsq", "MsProblem",
+    "batch_workspace_size", "sketch_lstsq_batched", "batch_status", "BatchRunner",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -48,7 +49,19 @@ _i64, _p, _sz, _i32 = ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t, ctypes.c
 
 class MsOpts(ctypes.Structure):
     _fields_ = [("cs_mode", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
-                ("cs_tile_cols", ctypes.c_int32), ("cs_schedule", ctypes.c_int32)]
+                ("cs_tile_cols", ctypes.c_int32), ("cs_schedule", ctypes.c_int32),
+                ("batch_rows_log2", ctypes.c_int32), ("batch_kchunk_log2", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+
+
+class MsProblem(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int64), ("n", ctypes.c_int64), ("nrhs", ctypes.c_int64),
+                ("k", ctypes.c_int64), ("k2", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("h", ctypes.c_void_p), ("s", ctypes.c_void_p),
+                ("G", ctypes.c_void_p), ("ldg", ctypes.c_int64),
+                ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64)]
 
 
 _SIGS = {
@@ -69,6 +82,9 @@ _SIGS = {
                      _p], _i32),
     "sketch_lstsq": ([_i64, _i64, _i64, _i64, _i64, _i32, _p, _i64, _p, _i64, _p, _p,
                       _i32, _p, _i64, _p, _i64, _p, _p, _sz, _p], _i32),
+    "ms_batch_workspace_size": ([_i32, _p, _i32, _i32, _p], _sz),
+    "sketch_lstsq_batched": ([_i32, _p, _p, _i32, _i32, _p, _p, _sz, _p], _i32),
+    "ms_batch_status": ([_p, _i32, _p, _p], _i32),
 }
 for _name, (_args, _ret) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -133,8 +149,10 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def _opts(mode: str = "auto", refine_steps: int = 0, tile_cols: int = 0, schedule: int = 0):
-    return MsOpts(MODES[mode], int(refine_steps), int(tile_cols), int(schedule))
+def _opts(mode: str = "auto", refine_steps: int = 0, tile_cols: int = 0, schedule: int = 0,
+          rows_log2: int = 0, kchunk_log2: int = 0):
+    return MsOpts(MODES[mode], int(refine_steps), int(tile_cols), int(schedule), int(rows_log2),
+                  int(kchunk_log2), 0, 0)
 
 
 def workspace_size(op: str, d=0, n=0, nrhs=0, k=0, k2=0, a_dtype=MS_F64, g_dtype=MS_F64,
@@ -338,3 +356,128 @@ def sketch_lstsq(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torch.Ten
                           _vec(s, torch.int8, "s"), g_dt, Gp, ldg, Xp, ldx, ctypes.byref(o), wp,
                           have, _stream(stream)), "sketch_lstsq")
     return X, ws
+
+
+# --------------------------------------------------------------------------
+# Batched sketch-and-solve
+# --------------------------------------------------------------------------
+
+def _describe(prob: dict) -> MsProblem:
+    """ms_problem of a dict with tensors A, B, h, s, G, X and the int k."""
+    A, B, G, X = prob["A"], prob["B"], prob["G"], prob["X"]
+    if B.dim() == 1:
+        B = B.unsqueeze(1)
+    Ap, lda = colmajor(A, "A")
+    Bp, ldb = colmajor(B, "B")
+    Gp, ldg = colmajor(G, "G")
+    Xp, ldx = colmajor(X, "X")
+    return MsProblem(A.shape[0], A.shape[1], B.shape[1], int(prob["k"]), G.shape[0],
+                     Ap, lda, Bp, ldb, _vec(prob["h"], torch.int32, "h"),
+                     _vec(prob["s"], torch.int8, "s"), Gp, ldg, Xp, ldx)
+
+
+def _host_array(problems):
+    arr = (MsProblem * len(problems))()
+    for i, pr in enumerate(problems):
+        arr[i] = _describe(pr)
+    return arr
+
+
+def batch_workspace_size(problems, a_dtype: int, g_dtype: int, rows_log2: int = 0,
+                         kchunk_log2: int = 0) -> int:
+    arr = _host_array(problems)
+    o = _opts("auto", 0, 0, 0, rows_log2, kchunk_log2)
+    sz = _lib.ms_batch_workspace_size(len(problems), arr, a_dtype, g_dtype, ctypes.byref(o))
+    if sz == 0:
+        raise MsketchError(MS_ERR_ARG, "ms_batch_workspace_size")
+    return sz
+
+
+def batch_status(ws: torch.Tensor, count: int, stream=None):
+    """(batch status, per-problem status list) of the last batched call on ws."""
+    out = (ctypes.c_int32 * count)()
+    p = (ws.data_ptr() + 255) // 256 * 256
+    st = _lib.ms_batch_status(ctypes.c_void_p(p), count, out, _stream(stream))
+    return st, list(out)
+
+
+class BatchRunner:
+    """A batched multisketch sketch-and-solve with its workspace and device
+    descriptors, reusable across calls and capturable in a HIP graph.
+
+    ``problems``: list of dicts with device tensors A (d x n), B (d x nrhs),
+    h (int32, d), s (int8, d), G (k2 x k), X (n x nrhs, FP64) and int k.
+    ``capacity``: problems that bound later ones (same count, each no larger
+    in k, k2, n + nrhs); defaults to ``problems``.
+    """
+
+    def __init__(self, problems, capacity=None, rows_log2: int = 0, kchunk_log2: int = 0):
+        if not problems:
+            raise ValueError("empty batch")
+        self.count = len(problems)
+        self.a_dtype = _dt(problems[0]["A"])
+        self.g_dtype = _dt(problems[0]["G"])
+        self.opts = _opts("auto", 0, 0, 0, rows_log2, kchunk_log2)
+        cap = capacity if capacity is not None else problems
+        cap_arr = _host_array(cap)
+        need = _lib.ms_batch_workspace_size(self.count, cap_arr, self.a_dtype, self.g_dtype,
+                                            ctypes.byref(self.opts))
+        if need == 0:
+            raise MsketchError(MS_ERR_ARG, "ms_batch_workspace_size")
+        dev = problems[0]["A"].device
+        self.ws = workspace(need, dev)
+        self.ws_ptr, self.ws_bytes = _ws_ptr(self.ws, need)
+        self.cap_host = cap_arr          # launch shapes come from the capacity set
+        nbytes = ctypes.sizeof(MsProblem) * self.count
+        self.desc_host = torch.empty(nbytes, dtype=torch.uint8).pin_memory()
+        self.desc_dev = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.graph = None
+        self.set_problems(problems)
+
+    def set_problems(self, problems, stream=None):
+        """Rewrite the device descriptors (stream-ordered copy)."""
+        if len(problems) != self.count:
+            raise ValueError("a runner keeps its problem count")
+        arr = _host_array(problems)
+        ctypes.memmove(self.desc_host.data_ptr(), arr, ctypes.sizeof(arr))
+        s = stream if stream is not None else torch.cuda.current_stream()
+        with torch.cuda.stream(s):
+            self.desc_dev.copy_(self.desc_host, non_blocking=True)
+        self.problems = problems
+
+    def launch(self, stream=None):
+        _ok(_lib.sketch_lstsq_batched(self.count, self.cap_host,
+                                      ctypes.c_void_p(self.desc_dev.data_ptr()), self.a_dtype,
+                                      self.g_dtype, ctypes.byref(self.opts),
+                                      ctypes.c_void_p(self.ws_ptr), self.ws_bytes,
+                                      _stream(stream)), "sketch_lstsq_batched")
+
+    def capture(self):
+        """Capture one launch sequence in a graph (torch.cuda.CUDAGraph)."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.launch(s)          # warm-up outside the capture
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.launch(torch.cuda.current_stream())
+        self.graph = g
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            raise RuntimeError("capture() first")
+        self.graph.replay()
+
+    def status(self, stream=None):
+        return batch_status(self.ws, self.count, stream)
+
+
+def sketch_lstsq_batched(problems, rows_log2: int = 0, kchunk_log2: int = 0, stream=None):
+    """Solve a list of problems (dicts as for BatchRunner) in one batched call;
+    returns the runner (its problems' X tensors hold the solutions)."""
+    r = BatchRunner(problems, rows_log2=rows_log2, kchunk_log2=kchunk_log2)
+    r.launch(stream)
+    return r

@@ -430,7 +430,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
                                                  int64_t ktile, int64_t rows_per_chunk,
                                                  T *__restrict__ Y, int64_t ldy, int *status) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *acc = reinterpret_cast<T *>(smem_raw);
+  double *acc = reinterpret_cast<double *>(smem_raw);
   const int64_t b0 = (int64_t)blockIdx.z * ktile;
   const uint32_t kt = (uint32_t)min(ktile, k - b0);
   const int c0 = blockIdx.y * NT;
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
   const int64_t r1 = min(d, r0 + rows_per_chunk);
   bool bad = false;
 
-  for (uint32_t t = threadIdx.x; t < kt * NT; t += blockDim.x) acc[t] = T(0);
+  for (uint32_t t = threadIdx.x; t < kt * NT; t += blockDim.x) acc[t] = 0.0;
   const T *cp[NT];
 #pragma unroll
   for (int j = 0; j < NT; ++j) cp[j] = col_ptr(cols, min(c0 + j, cols.ncols - 1));
@@ -468,8 +468,8 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
           if (j < nc) {
-            if (l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(lane_of<T>(a0[j], q), e0[q]));
-            if (l1 < kt) atomicAdd(&acc[l1 + j * kt], apply_sign(lane_of<T>(a1[j], q), e1[q]));
+            if (l0 < kt) atomicAdd(&acc[l0 + j * kt], (double)apply_sign(lane_of<T>(a0[j], q), e0[q]));
+            if (l1 < kt) atomicAdd(&acc[l1 + j * kt], (double)apply_sign(lane_of<T>(a1[j], q), e1[q]));
           }
         }
       }
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
           const uint32_t l0 = (e0[q] & kIdxMask) - (uint32_t)b0;
 #pragma unroll
           for (int j = 0; j < NT; ++j)
-            if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(lane_of<T>(a0[j], q), e0[q]));
+            if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], (double)apply_sign(lane_of<T>(a0[j], q), e0[q]));
         }
       } else {
         for (int64_t r = i; r < r1; ++r) {
@@ -494,7 +494,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
           const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
 #pragma unroll
           for (int j = 0; j < NT; ++j)
-            if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(cp[j][r], e0));
+            if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], (double)apply_sign(cp[j][r], e0));
         }
       }
     }
@@ -504,15 +504,15 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
       const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
 #pragma unroll
       for (int j = 0; j < NT; ++j)
-        if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(cp[j][r], e0));
+        if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], (double)apply_sign(cp[j][r], e0));
     }
   }
   if (bad) record_status(status, MS_ERR_RANGE);
   __syncthreads();
   for (uint32_t t = threadIdx.x; t < kt * (uint32_t)nc; t += blockDim.x) {
     const uint32_t j = t / kt, b = t - j * kt;
-    const T v = acc[t];
-    if (v != T(0)) unsafeAtomicAdd(&Y[(b0 + b) + (int64_t)(c0 + j) * ldy], v);
+    const double v = acc[t];
+    if (v != 0.0) unsafeAtomicAdd(&Y[(b0 + b) + (int64_t)(c0 + j) * ldy], (T)v);
   }
 }
 
@@ -521,8 +521,8 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
 // Rows [r0, r1) of column tile ct (NT columns from c0) and bucket tile
 // [b0, b0 + kt): accumulate into LDS (zero on entry), then add the non-zero
 // partials to Y and leave LDS zero again.  UNR vectors in flight per thread.
-template <typename T, int NT, bool VEC, bool CODES, int UNR>
-__device__ __forceinline__ void cs_segment(T *acc, const Cols<T> &cols, int c0, int nc,
+template <typename T, int NT, bool VEC, bool CODES, int UNR, bool NTL>
+__device__ __forceinline__ void cs_segment(double *acc, const Cols<T> &cols, int c0, int nc,
                                            const uint32_t *__restrict__ code,
                                            const int32_t *__restrict__ h,
                                            const int8_t *__restrict__ s, int64_t k, int64_t b0,
@@ -536,7 +536,7 @@ __device__ __forceinline__ void cs_segment(T *acc, const Cols<T> &cols, int c0, 
     const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
 #pragma unroll
     for (int j = 0; j < NT; ++j)
-      if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(cp[j][r], e0));
+      if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], (double)apply_sign(cp[j][r], e0));
   };
   if (VEC) {
     using V = typename Vec16<T>::type;
@@ -555,7 +555,8 @@ __device__ __forceinline__ void cs_segment(T *acc, const Cols<T> &cols, int c0, 
       for (int u = 0; u < UNR; ++u)
 #pragma unroll
         for (int j = 0; j < NT; ++j)
-          a[u][j] = __builtin_nontemporal_load(reinterpret_cast<const V *>(cp[j] + i + u * step));
+          a[u][j] = NTL ? __builtin_nontemporal_load(reinterpret_cast<const V *>(cp[j] + i + u * step))
+                        : *reinterpret_cast<const V *>(cp[j] + i + u * step);
 #pragma unroll
       for (int u = 0; u < UNR; ++u)
 #pragma unroll
@@ -563,7 +564,7 @@ __device__ __forceinline__ void cs_segment(T *acc, const Cols<T> &cols, int c0, 
           const uint32_t l = (e[u][q] & kIdxMask) - (uint32_t)b0;
 #pragma unroll
           for (int j = 0; j < NT; ++j)
-            if (j < nc && l < kt) atomicAdd(&acc[l + j * kt], apply_sign(lane_of<T>(a[u][j], q), e[u][q]));
+            if (j < nc && l < kt) atomicAdd(&acc[l + j * kt], (double)apply_sign(lane_of<T>(a[u][j], q), e[u][q]));
         }
     }
     for (; i < r1; i += step) {
@@ -578,7 +579,7 @@ __device__ __forceinline__ void cs_segment(T *acc, const Cols<T> &cols, int c0, 
           const uint32_t l0 = (e0[q] & kIdxMask) - (uint32_t)b0;
 #pragma unroll
           for (int j = 0; j < NT; ++j)
-            if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], apply_sign(lane_of<T>(a0[j], q), e0[q]));
+            if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], (double)apply_sign(lane_of<T>(a0[j], q), e0[q]));
         }
       } else {
         for (int64_t r = i; r < r1; ++r) scalar_row(r);
@@ -590,9 +591,9 @@ __device__ __forceinline__ void cs_segment(T *acc, const Cols<T> &cols, int c0, 
   __syncthreads();
   for (uint32_t t = threadIdx.x; t < kt * (uint32_t)nc; t += blockDim.x) {
     const uint32_t j = t / kt, b = t - j * kt;
-    const T v = acc[t];
-    acc[t] = T(0);
-    if (v != T(0)) unsafeAtomicAdd(&Y[(b0 + b) + (int64_t)(c0 + j) * ldy], v);
+    const double v = acc[t];
+    acc[t] = 0.0;
+    if (v != 0.0) unsafeAtomicAdd(&Y[(b0 + b) + (int64_t)(c0 + j) * ldy], (T)v);
   }
   __syncthreads();
 }
@@ -605,7 +606,7 @@ __device__ __forceinline__ void cs_segment(T *acc, const Cols<T> &cols, int c0, 
 // tiles of a column are streamed by workgroups of the same die at the same
 // time, and each workgroup flushes LDS only when its share crosses a column
 // tile.
-template <typename T, int NT, bool VEC, bool CODES, int UNR>
+template <typename T, int NT, bool VEC, bool CODES, int UNR, bool NTL>
 __global__ __launch_bounds__(1024) void k_cs_lds_xcd(int64_t d, Cols<T> cols,
                                                      const uint32_t *__restrict__ code,
                                                      const int32_t *__restrict__ h,
@@ -614,7 +615,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds_xcd(int64_t d, Cols<T> cols,
                                                      int spx, int64_t rpx, T *__restrict__ Y,
                                                      int64_t ldy, int *status) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *acc = reinterpret_cast<T *>(smem_raw);
+  double *acc = reinterpret_cast<double *>(smem_raw);
   const int g = blockIdx.x;
   const int x = g % xcds, slot = g / xcds;
   const int subs = spx / nbt;
@@ -625,7 +626,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds_xcd(int64_t d, Cols<T> cols,
   const int64_t len = R1 - R0;
   const int64_t b0 = (int64_t)bt * ktile;
   const uint32_t kt = (uint32_t)min(ktile, k - b0);
-  for (uint32_t t = threadIdx.x; t < kt * NT; t += blockDim.x) acc[t] = T(0);
+  for (uint32_t t = threadIdx.x; t < kt * NT; t += blockDim.x) acc[t] = 0.0;
   __syncthreads();
   const int64_t total = (int64_t)nct * len;
   int64_t u0 = (total * sub / subs) & ~(int64_t)255;
@@ -637,12 +638,93 @@ __global__ __launch_bounds__(1024) void k_cs_lds_xcd(int64_t d, Cols<T> cols,
     const int64_t rhi = min(len, rlo + (u1 - u0));
     const int c0 = ct * NT;
     const int nc = min(NT, cols.ncols - c0);
-    cs_segment<T, NT, VEC, CODES, UNR>(acc, cols, c0, nc, code, h, s, k, b0, kt, R0 + rlo,
-                                       R0 + rhi, Y, ldy, bad);
+    cs_segment<T, NT, VEC, CODES, UNR, NTL>(acc, cols, c0, nc, code, h, s, k, b0, kt, R0 + rlo,
+                                            R0 + rhi, Y, ldy, bad);
     u0 += rhi - rlo;
   }
   if (bad) record_status(status, MS_ERR_RANGE);
 }
+
+// ------------------------------------------------------------------ batched
+
+__device__ __forceinline__ int batch_find(const BatchEntry *__restrict__ E, int count, int64_t it,
+                                          bool gemm) {
+  // last problem whose first item is <= it (problems without items share the
+  // next problem's start and so are never selected)
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t st = gemm ? E[mid].gemm_start : E[mid].cs_start;
+    if (st <= it)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Persistent workgroups over the CountSketch items of all problems: item =
+// (problem, column tile, row segment, bucket tile).  h and s are read and
+// validated in the kernel; a problem's Y must be zero on entry.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_batch_cs(int count, const ms_problem *__restrict__ P,
+                                                   const BatchEntry *__restrict__ E,
+                                                   const BatchTotals *__restrict__ tot,
+                                                   unsigned char *__restrict__ yarea,
+                                                   int *__restrict__ pstatus, int *status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double *acc = reinterpret_cast<double *>(smem_raw);
+  for (int t = threadIdx.x; t < kBatchLdsSlots; t += blockDim.x) acc[t] = 0.0;
+  __syncthreads();
+  const int64_t total = tot->cs_items;
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const int p = batch_find(E, count, it, false);
+    const ms_problem &Q = P[p];
+    const BatchEntry &e = E[p];
+    int64_t local = it - e.cs_start;
+    const int bt = (int)(local % e.nbt);
+    local /= e.nbt;
+    const int seg = (int)(local % e.nsegs);
+    const int tile = (int)(local / e.nsegs);
+    const int64_t r0 = (int64_t)seg * e.rows, r1 = min(Q.d, r0 + e.rows);
+    const int64_t b0 = (int64_t)bt * e.ktile;
+    const uint32_t kt = (uint32_t)min(e.ktile, Q.k - b0);
+    const Cols<T> cols{static_cast<const T *>(Q.A), Q.lda, static_cast<const T *>(Q.B), Q.ldb,
+                       (int)Q.n, e.nc};
+    const int c0 = tile * e.nt;
+    const int ncur = min(e.nt, e.nc - c0);
+    T *Y = reinterpret_cast<T *>(yarea + e.y_off);
+    bool bad = false;
+    if (e.vec)
+      cs_segment<T, 4, true, false, 2, false>(acc, cols, c0, ncur, nullptr, Q.h, Q.s, Q.k, b0, kt,
+                                              r0, r1, Y, Q.k, bad);
+    else
+      cs_segment<T, 4, false, false, 2, false>(acc, cols, c0, ncur, nullptr, Q.h, Q.s, Q.k, b0, kt,
+                                               r0, r1, Y, Q.k, bad);
+    if (bad) {
+      record_status(&pstatus[p], MS_ERR_RANGE);
+      record_status(status, MS_ERR_RANGE);
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_batch_cs(int count, const ms_problem *P, const BatchEntry *E,
+                           const BatchTotals *tot, unsigned char *yarea, int *pstatus, int *status,
+                           int grid, hipStream_t st) {
+  const size_t lds = (size_t)kBatchLdsSlots * sizeof(double);
+  hipError_t e = allow_dynamic_lds((const void *)k_batch_cs<T>, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_cs<T>, dim3(grid), dim3(1024), lds, st, count, P, E, tot, yarea,
+                     pstatus, status);
+  return hipGetLastError();
+}
+template hipError_t launch_batch_cs<double>(int, const ms_problem *, const BatchEntry *,
+                                            const BatchTotals *, unsigned char *, int *, int *,
+                                            int, hipStream_t);
+template hipError_t launch_batch_cs<float>(int, const ms_problem *, const BatchEntry *,
+                                           const BatchTotals *, unsigned char *, int *, int *, int,
+                                           hipStream_t);
 
 template <typename T, int NT, bool CODES>
 static hipError_t launch_cs_xcd_v(bool vec, int grid, size_t lds, hipStream_t st, int64_t d,
@@ -651,16 +733,31 @@ static hipError_t launch_cs_xcd_v(bool vec, int grid, size_t lds, hipStream_t st
                                   int xcds, int spx, int64_t rpx, T *Y, int64_t ldy, int *status) {
   // vectors in flight per thread: fewer for wider column tiles (registers)
   constexpr int UNR = NT >= 8 ? 1 : NT >= 4 ? 2 : 4;
-  const void *fn = vec ? (const void *)k_cs_lds_xcd<T, NT, true, CODES, UNR>
-                       : (const void *)k_cs_lds_xcd<T, NT, false, CODES, UNR>;
+  if (nbt > 1) {  // bucket tiles re-read A: ordinary loads, so the die's L2 keeps it
+    const void *fn = vec ? (const void *)k_cs_lds_xcd<T, NT, true, CODES, UNR, false>
+                         : (const void *)k_cs_lds_xcd<T, NT, false, CODES, UNR, false>;
+    hipError_t e = allow_dynamic_lds(fn, (int)lds);
+    if (e != hipSuccess) return e;
+    if (vec)
+      hipLaunchKernelGGL((k_cs_lds_xcd<T, NT, true, CODES, UNR, false>), dim3(grid), dim3(1024),
+                         lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy,
+                         status);
+    else
+      hipLaunchKernelGGL((k_cs_lds_xcd<T, NT, false, CODES, UNR, false>), dim3(grid), dim3(1024),
+                         lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy,
+                         status);
+    return hipGetLastError();
+  }
+  const void *fn = vec ? (const void *)k_cs_lds_xcd<T, NT, true, CODES, UNR, true>
+                       : (const void *)k_cs_lds_xcd<T, NT, false, CODES, UNR, true>;
   hipError_t e = allow_dynamic_lds(fn, (int)lds);
   if (e != hipSuccess) return e;
   if (vec)
-    hipLaunchKernelGGL((k_cs_lds_xcd<T, NT, true, CODES, UNR>), dim3(grid), dim3(1024), lds, st, d,
-                       c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy, status);
+    hipLaunchKernelGGL((k_cs_lds_xcd<T, NT, true, CODES, UNR, true>), dim3(grid), dim3(1024), lds,
+                       st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy, status);
   else
-    hipLaunchKernelGGL((k_cs_lds_xcd<T, NT, false, CODES, UNR>), dim3(grid), dim3(1024), lds, st,
-                       d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy, status);
+    hipLaunchKernelGGL((k_cs_lds_xcd<T, NT, false, CODES, UNR, true>), dim3(grid), dim3(1024), lds,
+                       st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy, status);
   return hipGetLastError();
 }
 
@@ -703,7 +800,8 @@ hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t 
   hipError_t e = zero_first ? launch_fill_zero<T>(Y, k, c.ncols, ldy, st) : hipSuccess;
   if (e != hipSuccess || d <= 0 || c.ncols <= 0) return e;
   const DevInfo &di = dev_info();
-  const int64_t w = sizeof(T);
+  const int64_t w = 8;  // bytes of an LDS partial-sum slot (FP64 for both data types)
+  const int64_t wd = sizeof(T);
   const int64_t cap = std::min<int64_t>(di.lds_per_block, 128 * 1024);
   int64_t ktile = k;
   if (k * w > cap) {
@@ -712,9 +810,9 @@ hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t 
   }
   const int64_t nbt = (k + ktile - 1) / ktile;
   const uintptr_t mis = (reinterpret_cast<uintptr_t>(c.A) | reinterpret_cast<uintptr_t>(c.B) |
-                         (uintptr_t)(c.lda * w) | (uintptr_t)(c.B ? c.ldb * w : 0) |
+                         (uintptr_t)(c.lda * wd) | (uintptr_t)(c.B ? c.ldb * wd : 0) |
                          reinterpret_cast<uintptr_t>(code) | reinterpret_cast<uintptr_t>(h));
-  const uintptr_t smis = reinterpret_cast<uintptr_t>(s) & (uintptr_t)(16 / w - 1);
+  const uintptr_t smis = reinterpret_cast<uintptr_t>(s) & (uintptr_t)(16 / wd - 1);
   const bool vec = (mis & 15) == 0 && smis == 0;
   const bool grid_variant = tune && tune->grid_variant;
   if (!grid_variant) {

@@ -127,30 +127,26 @@ __device__ __forceinline__ v8bf load_b<DT_BF16>(const float *Y, int64_t ldy, int
 }
 
 // Workgroup = 4 waves over a 64 x 64 output tile (each wave 32 x 32, i.e.
-// 2 x 2 matrix-core blocks), one K chunk per blockIdx.z.  Fragments are
-// loaded U instructions ahead: the loads of the next batch are in flight
-// while the current batch runs on the matrix cores.
+// 2 x 2 matrix-core blocks), one K chunk per workgroup.  Fragments are loaded U instructions ahead: the loads of the next batch are
+// in flight while the current batch runs on the matrix cores.
 template <int DT>
 struct Unroll {
   static constexpr int U = DT == DT_BF16 ? 2 : 8;
 };
 
+// One 64 x 64 output tile (m_tile, n_tile) of G[:, kb:ke] Y[kb:ke, :], written
+// to P (ld M) -- the body shared by the single-problem and batched kernels.
 template <int DT>
-__global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
-                                                     const typename Mf<DT>::TG *__restrict__ G,
-                                                     int64_t ldg,
-                                                     const typename Mf<DT>::TY *__restrict__ Y,
-                                                     int64_t ldy,
-                                                     typename Mf<DT>::Acc *__restrict__ part,
-                                                     int64_t kchunk) {
+__device__ __forceinline__ void gemm_tile(int M, int N, const typename Mf<DT>::TG *__restrict__ G,
+                                          int64_t ldg, const typename Mf<DT>::TY *__restrict__ Y,
+                                          int64_t ldy, typename Mf<DT>::Acc *__restrict__ P,
+                                          int64_t kb, int64_t ke, int m_tile, int n_tile) {
   using F = Mf<DT>;
   constexpr int U = Unroll<DT>::U;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int m_base = blockIdx.x * 64 + (wave & 1) * 32;
-  const int n_base = blockIdx.y * 64 + (wave >> 1) * 32;
-  const int64_t kb = (int64_t)blockIdx.z * kchunk;
-  const int64_t ke = min(K, kb + kchunk);
+  const int m_base = m_tile * 64 + (wave & 1) * 32;
+  const int n_base = n_tile * 64 + (wave >> 1) * 32;
   constexpr int KPL = F::KS / 4;  // k values per lane per instruction
   typename F::AccV acc[2][2];
 #pragma unroll
@@ -189,7 +185,6 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
         }
     }
   }
-  typename F::Acc *P = part + (int64_t)blockIdx.z * M * N;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -201,6 +196,20 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
         if (row < M && col < N) P[row + (int64_t)col * M] = acc[i][j][r];
       }
     }
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
+                                                     const typename Mf<DT>::TG *__restrict__ G,
+                                                     int64_t ldg,
+                                                     const typename Mf<DT>::TY *__restrict__ Y,
+                                                     int64_t ldy,
+                                                     typename Mf<DT>::Acc *__restrict__ part,
+                                                     int64_t kchunk) {
+  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+  const int64_t ke = min(K, kb + kchunk);
+  gemm_tile<DT>(M, N, G, ldg, Y, ldy, part + (int64_t)blockIdx.z * M * N, kb, ke, blockIdx.x,
+                blockIdx.y);
 }
 
 // Z[p, c] = sum over splits (in split order) of the partials; written to Z
@@ -226,6 +235,110 @@ __global__ void k_reduce_splits(int M, int N, int nsplit, const Acc *__restrict_
     if (Z) Z[p + c * ldz] = (TZ)s;
     if (z64) z64[t] = (double)s;
   }
+}
+
+// ------------------------------------------------------------------ batched
+
+__device__ __forceinline__ int batch_find_gemm(const BatchEntry *__restrict__ E, int count,
+                                               int64_t it) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (E[mid].gemm_start <= it)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Persistent workgroups over the Gaussian-stage items of all problems: item
+// = (problem, 64-row tile, 64-column tile, K split); each writes its partial
+// block into the problem's partials area.
+template <int DT>
+__global__ __launch_bounds__(256) void k_batch_gemm(int count, const ms_problem *__restrict__ P,
+                                                    const BatchEntry *__restrict__ E,
+                                                    const BatchTotals *__restrict__ tot,
+                                                    const unsigned char *__restrict__ yarea,
+                                                    unsigned char *__restrict__ parea) {
+  using F = Mf<DT>;
+  const int64_t total = tot->gemm_items;
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const int p = batch_find_gemm(E, count, it);
+    const ms_problem &Q = P[p];
+    const BatchEntry &e = E[p];
+    int64_t local = it - e.gemm_start;
+    const int split = (int)(local % e.nsplit);
+    local /= e.nsplit;
+    const int tn = (int)(local % e.tiles_n);
+    const int tm = (int)(local / e.tiles_n);
+    const int M = (int)Q.k2, N = e.nc;
+    const int64_t kb = (int64_t)split * e.kchunk, ke = min(Q.k, kb + e.kchunk);
+    const auto *Y = reinterpret_cast<const typename F::TY *>(yarea + e.y_off);
+    auto *Pz = reinterpret_cast<typename F::Acc *>(parea + e.part_off) + (int64_t)split * M * N;
+    gemm_tile<DT>(M, N, static_cast<const typename F::TG *>(Q.G), Q.ldg, Y, Q.k, Pz, kb, ke, tm, tn);
+  }
+}
+
+hipError_t launch_batch_gemm(int count, ms_dtype g_dtype, const ms_problem *P, const BatchEntry *E,
+                             const BatchTotals *tot, const unsigned char *yarea,
+                             unsigned char *parea, int grid, hipStream_t st) {
+  switch (g_dtype) {
+    case MS_F64:
+      hipLaunchKernelGGL(k_batch_gemm<DT_F64>, dim3(grid), dim3(256), 0, st, count, P, E, tot,
+                         yarea, parea);
+      break;
+    case MS_F32:
+      hipLaunchKernelGGL(k_batch_gemm<DT_F32>, dim3(grid), dim3(256), 0, st, count, P, E, tot,
+                         yarea, parea);
+      break;
+    case MS_BF16:
+      hipLaunchKernelGGL(k_batch_gemm<DT_BF16>, dim3(grid), dim3(256), 0, st, count, P, E, tot,
+                         yarea, parea);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Z_p = sum over splits (in split order) of problem p's partials, as FP64.
+template <typename Acc>
+__global__ void k_batch_reduce(int count, const ms_problem *__restrict__ P,
+                               const BatchEntry *__restrict__ E,
+                               const unsigned char *__restrict__ parea,
+                               unsigned char *__restrict__ zarea) {
+  const int p = blockIdx.y;
+  const BatchEntry &e = E[p];
+  if (!e.valid) return;
+  const int64_t MN = P[p].k2 * e.nc;
+  const Acc *part = reinterpret_cast<const Acc *>(parea + e.part_off);
+  double *Z = reinterpret_cast<double *>(zarea + e.z_off);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < MN;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    Acc s = part[t];
+    int z = 1;
+    for (; z + 8 <= e.nsplit; z += 8) {
+      Acc v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[t + (int64_t)(z + u) * MN];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s = s + v[u];
+    }
+    for (; z < e.nsplit; ++z) s = s + part[t + (int64_t)z * MN];
+    Z[t] = (double)s;
+  }
+}
+
+hipError_t launch_batch_reduce(int count, ms_dtype g_dtype, const ms_problem *P,
+                               const BatchEntry *E, const unsigned char *parea,
+                               unsigned char *zarea, int max_mn, hipStream_t st) {
+  const dim3 grid((unsigned)std::max(1, (max_mn + 255) / 256), (unsigned)count);
+  if (g_dtype == MS_F64)
+    hipLaunchKernelGGL(k_batch_reduce<double>, grid, dim3(256), 0, st, count, P, E, parea, zarea);
+  else
+    hipLaunchKernelGGL(k_batch_reduce<float>, grid, dim3(256), 0, st, count, P, E, parea, zarea);
+  return hipGetLastError();
 }
 
 GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K, ms_dtype g_dtype) {

@@ -159,4 +159,96 @@ hipError_t launch_qr_apply_solve(int64_t m, int64_t n, int64_t nrhs, const doubl
                                  const double *tau, double *Bm, double *X, int64_t ldx,
                                  int *status, hipStream_t st);
 
+// ---------------------------------------------------------------- batched
+// Per-problem plan of a batched call, computed identically on the host (to
+// size the workspace) and on the device (so graph replays with rewritten
+// descriptors need no host work).
+struct BatchEntry {
+  int64_t cs_start;    // first CountSketch work item of the problem
+  int64_t gemm_start;  // first Gaussian-stage work item
+  int64_t y_off;       // byte offsets into the Y / partials / Z areas
+  int64_t part_off;
+  int64_t z_off;
+  int64_t rows;        // rows per CountSketch item
+  int64_t kchunk;      // K per Gaussian-stage item
+  int64_t ktile;       // buckets per LDS tile
+  int32_t nc, nt, ntiles, nsegs, nbt, tiles_m, tiles_n, nsplit;
+  int32_t valid, vec, pad0, pad1;
+};
+
+constexpr int64_t kBatchLdsSlots = 16384;  // FP64 partial sums per workgroup (128 KB)
+constexpr int kBatchMaxK2 = 256;
+constexpr int kBatchMaxCols = 144;
+
+__host__ __device__ inline int64_t batch_align(int64_t x) { return (x + 255) / 256 * 256; }
+
+// Sizes of one problem's items and areas.  wdata: bytes of A; accw: bytes of
+// a Gaussian-stage partial; rows_item, kchunk: tuning (powers of two).
+__host__ __device__ inline void batch_entry(const ms_problem &P, int wdata, int accw,
+                                            int64_t rows_item, int64_t kchunk, BatchEntry &E) {
+  E = BatchEntry{};
+  E.valid = P.d >= 1 && P.d < 0x7fffffffLL && P.n >= 1 && P.nrhs >= 1 && P.k >= 1 &&
+            P.k < 0x7fffffffLL && P.k2 >= P.n && P.k2 <= kBatchMaxK2 &&
+            P.n + P.nrhs <= kBatchMaxCols && P.lda >= P.d && P.ldb >= P.d && P.ldg >= P.k2 &&
+            P.ldx >= P.n && P.A && P.B && P.h && P.s && P.G && P.X;
+  if (!E.valid) return;
+  E.nc = (int32_t)(P.n + P.nrhs);
+  E.ktile = P.k;
+  if (E.ktile > kBatchLdsSlots) {
+    E.ktile = 1;
+    while (E.ktile * 2 <= kBatchLdsSlots) E.ktile *= 2;
+  }
+  E.nbt = (int32_t)((P.k + E.ktile - 1) / E.ktile);
+  E.nt = 1;
+  while (E.nt < 4 && E.ktile * E.nt * 2 <= kBatchLdsSlots && E.nt * 2 <= E.nc) E.nt *= 2;
+  E.ntiles = (E.nc + E.nt - 1) / E.nt;
+  E.rows = rows_item;
+  E.nsegs = (int32_t)((P.d + rows_item - 1) / rows_item);
+  E.tiles_m = (int32_t)((P.k2 + 63) / 64);
+  E.tiles_n = (E.nc + 63) / 64;
+  E.kchunk = kchunk;
+  E.nsplit = (int32_t)((P.k + kchunk - 1) / kchunk);
+  const uintptr_t mis = (uintptr_t)P.A | (uintptr_t)P.B | (uintptr_t)(P.lda * wdata) |
+                        (uintptr_t)(P.ldb * wdata) | (uintptr_t)P.h;
+  E.vec = (mis & 15) == 0 && ((uintptr_t)P.s & (uintptr_t)(16 / wdata - 1)) == 0;
+}
+
+__host__ __device__ inline int64_t batch_cs_items(const BatchEntry &E) {
+  return E.valid ? (int64_t)E.ntiles * E.nsegs * E.nbt : 0;
+}
+__host__ __device__ inline int64_t batch_gemm_items(const BatchEntry &E) {
+  return E.valid ? (int64_t)E.tiles_m * E.tiles_n * E.nsplit : 0;
+}
+__host__ __device__ inline int64_t batch_y_bytes(const ms_problem &P, const BatchEntry &E, int wdata) {
+  return E.valid ? batch_align(P.k * E.nc * wdata) : 0;
+}
+__host__ __device__ inline int64_t batch_part_bytes(const ms_problem &P, const BatchEntry &E, int accw) {
+  return E.valid ? batch_align((int64_t)E.nsplit * P.k2 * E.nc * accw) : 0;
+}
+__host__ __device__ inline int64_t batch_z_bytes(const ms_problem &P, const BatchEntry &E) {
+  return E.valid ? batch_align(P.k2 * E.nc * 8) : 0;
+}
+
+// Totals written by the setup kernel (device) next to the entries.
+struct BatchTotals {
+  int64_t cs_items, gemm_items, y_bytes, part_bytes, z_bytes, max_mn;
+  int64_t pad[2];
+};
+
+// countsketch.hip / gemm.hip / qr.hip batched launchers
+template <typename T>
+hipError_t launch_batch_cs(int count, const ms_problem *P, const BatchEntry *E,
+                           const BatchTotals *tot, unsigned char *yarea, int *pstatus,
+                           int *status, int grid, hipStream_t st);
+hipError_t launch_batch_gemm(int count, ms_dtype g_dtype, const ms_problem *P,
+                             const BatchEntry *E, const BatchTotals *tot,
+                             const unsigned char *yarea, unsigned char *parea, int grid,
+                             hipStream_t st);
+hipError_t launch_batch_reduce(int count, ms_dtype g_dtype, const ms_problem *P,
+                               const BatchEntry *E, const unsigned char *parea,
+                               unsigned char *zarea, int max_mn, hipStream_t st);
+hipError_t launch_batch_qr(int count, int max_k2, int max_n, int max_nc, const ms_problem *P,
+                           const BatchEntry *E, const unsigned char *zarea, int *pstatus,
+                           int *status, hipStream_t st);
+
 }  // namespace ms

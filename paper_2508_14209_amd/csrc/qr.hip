@@ -154,20 +154,29 @@ __device__ __forceinline__ double wave_allsum(double v) {
 // an m x nc product -- the same sum, in the same precision, as the separate
 // split reduction.
 // R and the transformed right-hand sides go to LDS for the back substitution.
+template <int RPL>
+struct QrShared {
+  double vbuf[2][64 * RPL];
+  double taubuf[2];
+  int singular;
+};
+
+// The body shared by the single-problem and batched kernels; rs is dynamic
+// LDS of n x (n + nrhs) doubles.  status2 (may be null) also receives a
+// singular-R report.
 template <int RPL, int CPW>
-__global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, int nrhs, const double *__restrict__ W,
-                                                 int64_t ldw, const double *__restrict__ Bm,
-                                                 int64_t ldb, const double *__restrict__ part,
-                                                 const float *__restrict__ part32, int nsplit,
-                                                 double *__restrict__ X, int64_t ldx,
-                                                 double *__restrict__ R, int64_t ldr,
-                                                 double *__restrict__ tau_out,
-                                                 double *__restrict__ fact_out, int *status) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double *rs = reinterpret_cast<double *>(smem_raw);  // n x nc top block, ld n
-  __shared__ double vbuf[2][64 * RPL];
-  __shared__ double taubuf[2];
-  __shared__ int s_singular;
+__device__ __forceinline__ void qr_reg_body(int m, int n, int nrhs, const double *__restrict__ W,
+                                            int64_t ldw, const double *__restrict__ Bm,
+                                            int64_t ldb, const double *__restrict__ part,
+                                            const float *__restrict__ part32, int nsplit,
+                                            double *__restrict__ X, int64_t ldx,
+                                            double *__restrict__ R, int64_t ldr,
+                                            double *__restrict__ tau_out,
+                                            double *__restrict__ fact_out, int *status,
+                                            int *status2, double *rs, QrShared<RPL> &sh) {
+  auto &vbuf = sh.vbuf;
+  auto &taubuf = sh.taubuf;
+  int &s_singular = sh.singular;
   const int nc = n + nrhs;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t MN = (int64_t)m * nc;
@@ -295,11 +304,57 @@ __global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, int nrhs, const d
       const int c = (int)(t / n), i = (int)(t - (int64_t)c * n);
       X[i + (int64_t)c * ldx] = __longlong_as_double(0x7ff8000000000000LL);
     }
-    if (threadIdx.x == 0) record_status(status, MS_ERR_SINGULAR);
+    if (threadIdx.x == 0) {
+      record_status(status, MS_ERR_SINGULAR);
+      if (status2) record_status(status2, MS_ERR_SINGULAR);
+    }
     return;
   }
   for (int c = wave; c < nrhs; c += 16)
     wave_back_substitute(n, rs, n, rs + (int64_t)(n + c) * n, X + (int64_t)c * ldx);
+}
+
+template <int RPL, int CPW>
+__global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, int nrhs, const double *__restrict__ W,
+                                                 int64_t ldw, const double *__restrict__ Bm,
+                                                 int64_t ldb, const double *__restrict__ part,
+                                                 const float *__restrict__ part32, int nsplit,
+                                                 double *__restrict__ X, int64_t ldx,
+                                                 double *__restrict__ R, int64_t ldr,
+                                                 double *__restrict__ tau_out,
+                                                 double *__restrict__ fact_out, int *status) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ QrShared<RPL> sh;
+  qr_reg_body<RPL, CPW>(m, n, nrhs, W, ldw, Bm, ldb, part, part32, nsplit, X, ldx, R, ldr, tau_out,
+                        fact_out, status, nullptr, reinterpret_cast<double *>(smem_raw), sh);
+}
+
+// One workgroup per problem of a batch: Z_p (FP64, k2 x (n + nrhs)) -> X_p.
+template <int RPL, int CPW>
+__global__ __launch_bounds__(1024) void k_batch_qr(int count, const ms_problem *__restrict__ P,
+                                                   const BatchEntry *__restrict__ E,
+                                                   const unsigned char *__restrict__ zarea,
+                                                   int *__restrict__ pstatus, int *status,
+                                                   int64_t lds_doubles) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ QrShared<RPL> sh;
+  const int p = blockIdx.x;
+  const BatchEntry &e = E[p];
+  if (!e.valid) return;
+  const ms_problem &Q = P[p];
+  const double *Z = reinterpret_cast<const double *>(zarea + e.z_off);
+  const int m = (int)Q.k2, n = (int)Q.n;
+  // descriptors rewritten after the launch shape was chosen must still fit it
+  if (m > 64 * RPL || e.nc > 16 * CPW || (int64_t)n * e.nc > lds_doubles) {
+    if (threadIdx.x == 0) {
+      record_status(&pstatus[p], MS_ERR_NOMEM);
+      record_status(status, MS_ERR_NOMEM);
+    }
+    return;
+  }
+  qr_reg_body<RPL, CPW>(m, n, (int)Q.nrhs, Z, m, Z + (int64_t)n * m, m, nullptr, nullptr, 0, Q.X,
+                        Q.ldx, nullptr, 0, nullptr, nullptr, &pstatus[p], status,
+                        reinterpret_cast<double *>(smem_raw), sh);
 }
 
 struct QrRegShape {
@@ -385,6 +440,33 @@ hipError_t launch_qr_solve(int64_t m, int64_t n, int64_t nrhs, const double *W, 
                        status);
   }
   return hipGetLastError();
+}
+
+hipError_t launch_batch_qr(int count, int max_k2, int max_n, int max_nc, const ms_problem *P,
+                           const BatchEntry *E, const unsigned char *zarea, int *pstatus,
+                           int *status, hipStream_t st) {
+  const size_t lds = (size_t)max_n * (size_t)max_nc * sizeof(double);
+  for (const QrRegShape &s : kQrShapes) {
+    if (64 * s.rpl < max_k2 || 16 * s.cpw < max_nc) continue;
+#define MS_BQR_CASE(R_, C_)                                                                    \
+  if (s.rpl == R_ && s.cpw == C_) {                                                           \
+    hipError_t e = allow_dynamic_lds((const void *)k_batch_qr<R_, C_>, (int)lds);            \
+    if (e != hipSuccess) return e;                                                            \
+    hipLaunchKernelGGL((k_batch_qr<R_, C_>), dim3(count), dim3(1024), lds, st, count, P, E,  \
+                       zarea, pstatus, status, (int64_t)max_n * max_nc);                      \
+    return hipGetLastError();                                                                 \
+  }
+    MS_BQR_CASE(1, 1)
+    MS_BQR_CASE(1, 2)
+    MS_BQR_CASE(1, 5)
+    MS_BQR_CASE(2, 2)
+    MS_BQR_CASE(2, 5)
+    MS_BQR_CASE(2, 9)
+    MS_BQR_CASE(4, 5)
+    MS_BQR_CASE(4, 9)
+#undef MS_BQR_CASE
+  }
+  return hipErrorNotSupported;
 }
 
 // Apply H_0 ... H_{n-1} (stored in fact/tau) to each right-hand side, one

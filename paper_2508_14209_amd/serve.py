@@ -1,0 +1,254 @@
+"""Continuous-batching least-squares serving loop over the batched C-ABI call.
+
+Requests (least-squares problems of uneven d, n and right-hand-side count)
+arrive over time.  Each is generated into device memory when it arrives, on a
+generator stream; it is admitted when its HBM footprint fits the budget next
+to the requests already in flight and a slot is free; admitted requests wait
+in a ready list until a solver stream is free, and then every ready request
+(up to ``max_batch``) is solved by one batched multisketch sketch-and-solve
+call (``sketch_lstsq_batched``) on that stream.  Several solver streams run
+batches concurrently, and arrivals keep being generated and admitted while
+batches run, so work of requests that arrived at different times overlaps on
+the device (continuous batching).  A request's latency runs from its
+scheduled arrival to the moment the host observes its batch's completion
+event.
+
+The solver is the library's; this module only schedules.  Inputs follow the
+serving workload: A = Z diag(logspace(0, -log10 kappa, n)) (FP32), B = A x* +
+1e-6 N(0,1), h uniform, s Rademacher, G ~ N(0, 1/k2), k = 2 n^2, k2 = 2 n.
+"""
+from __future__ import annotations
+
+import math
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import torch
+
+import paper_2508_14209_amd as ms
+
+
+@dataclass
+class Request:
+    id: int
+    d: int
+    n: int
+    nrhs: int
+    kappa: float
+    k: int
+    k2: int
+    seed: int
+    arrival: float = 0.0            # scheduled arrival, seconds from the start
+    tensors: dict | None = None
+    footprint: int = 0
+    gen_event: object = None
+    t_admit: float = math.nan
+    t_launch: float = math.nan
+    t_done: float = math.nan
+    status: int = -1
+    batch: int = -1
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.arrival
+
+
+def footprint_bytes(d: int, n: int, nrhs: int, k: int, k2: int, w: int = 4) -> int:
+    """HBM a request holds while in flight: its inputs and output plus its
+    share of the batched workspace (sketch, split-K partials, Z)."""
+    data = d * (n + nrhs) * w + d * 5 + k2 * k * w + n * nrhs * 8
+    nsplit = (k + 1023) // 1024
+    work = k * (n + nrhs) * w + nsplit * k2 * (n + nrhs) * 4 + k2 * (n + nrhs) * 8 + 1024
+    return data + work
+
+
+def generate(req: Request, device, g_dtype: str = "f32") -> dict:
+    """Seeded synthetic inputs of one request, on the current stream."""
+    g = torch.Generator(device=device)
+    g.manual_seed(int(req.seed))
+    d, n, nrhs, k, k2 = req.d, req.n, req.nrhs, req.k, req.k2
+    scales = torch.logspace(0.0, -math.log10(req.kappa), n, device=device, dtype=torch.float32)
+    A = torch.randn((n, d), generator=g, device=device, dtype=torch.float32).t()
+    A.mul_(scales)                                   # column scaling: condition ~ kappa
+    xs = torch.randn((n, nrhs), generator=g, device=device, dtype=torch.float32)
+    B = ms.empty_colmajor(d, nrhs, torch.float32, device)
+    B.copy_(A @ xs)
+    B.add_(torch.randn((nrhs, d), generator=g, device=device, dtype=torch.float32).t(), alpha=1e-6)
+    h = torch.randint(0, k, (d,), generator=g, device=device, dtype=torch.int32)
+    s = (torch.randint(0, 2, (d,), generator=g, device=device, dtype=torch.int8) * 2 - 1)
+    Gm = torch.randn((k, k2), generator=g, device=device, dtype=torch.float32).t()
+    Gm.mul_(1.0 / math.sqrt(k2))
+    if g_dtype == "bf16":
+        Gb = torch.empty((k, k2), device=device, dtype=torch.bfloat16).t()
+        Gb.copy_(Gm)
+        Gm = Gb
+    X = ms.empty_colmajor(n, nrhs, torch.float64, device)
+    return dict(A=A, B=B, h=h, s=s.to(torch.int8), G=Gm, X=X, k=k, xstar=xs)
+
+
+class Admission:
+    """HBM-budget admission: a request is admitted when a slot is free and its
+    footprint fits the budget next to the requests in flight (a request larger
+    than the whole budget is admitted alone, when nothing else is in flight).
+    Host logic only."""
+
+    def __init__(self, hbm_budget: int, max_inflight: int):
+        self.hbm_budget = int(hbm_budget)
+        self.max_inflight = int(max_inflight)
+        self.bytes = 0
+        self.count = 0
+        self.peak_bytes = 0
+
+    def try_admit(self, footprint: int) -> bool:
+        if self.count >= self.max_inflight:
+            return False
+        if self.count and self.bytes + footprint > self.hbm_budget:
+            return False
+        self.count += 1
+        self.bytes += footprint
+        self.peak_bytes = max(self.peak_bytes, self.bytes)
+        return True
+
+    def release(self, footprint: int):
+        self.count -= 1
+        self.bytes -= footprint
+
+
+class Server:
+    """Continuous-batching scheduler (see the module docstring).
+
+    hbm_budget: bytes the in-flight requests may hold together.
+    max_inflight: request slots.  max_batch: requests per batched call.
+    streams: solver streams running batches concurrently.
+    """
+
+    def __init__(self, hbm_budget: int = 64 << 30, max_inflight: int = 256, max_batch: int = 64,
+                 streams: int = 4, g_dtype: str = "f32", rows_log2: int = 0,
+                 kchunk_log2: int = 0, device="cuda"):
+        self.device = torch.device(device)
+        self.admission = Admission(hbm_budget, max_inflight)
+        self.max_batch = max_batch
+        self.g_dtype = g_dtype
+        self.rows_log2 = rows_log2
+        self.kchunk_log2 = kchunk_log2
+        self.gen_stream = torch.cuda.Stream(device=self.device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
+        self.busy = {}                # stream index -> (event, runner, requests)
+        self.waiting = deque()        # arrived, not yet admitted (budget / slots)
+        self.ready = deque()          # admitted, inputs being / been generated
+        self.done = []
+        self.nbatches = 0
+        self.t0 = None
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    # -- arrivals and admission ------------------------------------------------
+    def arrive(self, req: Request):
+        req.footprint = footprint_bytes(req.d, req.n, req.nrhs, req.k, req.k2)
+        self.waiting.append(req)
+        self._admit()
+
+    def _admit(self):
+        while self.waiting:
+            req = self.waiting[0]
+            if not self.admission.try_admit(req.footprint):
+                return
+            self.waiting.popleft()
+            req.t_admit = self.now()
+            with torch.cuda.stream(self.gen_stream):
+                req.tensors = generate(req, self.device, self.g_dtype)
+                ev = torch.cuda.Event()
+                ev.record(self.gen_stream)
+            req.gen_event = ev
+            self.ready.append(req)
+
+    # -- batches -----------------------------------------------------------------
+    def _launch(self):
+        for si, st in enumerate(self.streams):
+            if si in self.busy or not self.ready:
+                continue
+            batch = []
+            while self.ready and len(batch) < self.max_batch:
+                batch.append(self.ready.popleft())
+            probs = [r.tensors for r in batch]
+            st.wait_stream(self.gen_stream)     # inputs generated before the solve
+            for pr in probs:                    # memory of the generator stream used here
+                for key in ("A", "B", "h", "s", "G", "X"):
+                    pr[key].record_stream(st)
+            with torch.cuda.stream(st):
+                runner = ms.BatchRunner(probs, rows_log2=self.rows_log2,
+                                        kchunk_log2=self.kchunk_log2)
+                runner.launch(st)
+                ev = torch.cuda.Event()
+                ev.record(st)
+            tl = self.now()
+            for r in batch:
+                r.t_launch = tl
+                r.batch = self.nbatches
+            self.nbatches += 1
+            self.busy[si] = (ev, runner, batch)
+
+    def _complete(self):
+        for si in list(self.busy):
+            ev, runner, batch = self.busy[si]
+            if not ev.query():
+                continue
+            t = self.now()
+            st, per = runner.status(self.streams[si])
+            for r, code in zip(batch, per):
+                r.t_done = t
+                r.status = code
+                self.admission.release(r.footprint)
+                self.done.append(r)
+            del self.busy[si]
+        self._admit()
+
+    def step(self):
+        self._complete()
+        self._launch()
+
+    def idle(self) -> bool:
+        return not (self.busy or self.ready or self.waiting)
+
+    # -- drivers -------------------------------------------------------------------
+    def run(self, requests, keep_tensors: bool = False):
+        """Open loop: request r arrives at r.arrival seconds after the start."""
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        self.t0 = time.perf_counter()
+        while pending or not self.idle():
+            t = self.now()
+            while pending and pending[0].arrival <= t:
+                self.arrive(pending.popleft())
+            self.step()
+            if not keep_tensors:
+                for r in self.done:
+                    if r.tensors is not None and not r.extra.get("kept"):
+                        r.tensors = None
+            if pending and self.idle():
+                time.sleep(max(0.0, min(pending[0].arrival - self.now(), 1e-3)))
+        torch.cuda.synchronize(self.device)
+        return self.done
+
+
+def make_requests(count: int, rate: float, seed: int = 14209, **kw):
+    """The serving stream: synth's request descriptors with Poisson arrivals."""
+    import synth
+    desc = synth.serving_requests(count, seed, **kw)
+    times = synth.poisson_arrivals(count, rate, seed) if rate > 0 else [0.0] * count
+    return [Request(id=dd["id"], d=dd["d"], n=dd["n"], nrhs=dd["nrhs"], kappa=dd["kappa"],
+                    k=dd["k"], k2=dd["k2"], seed=dd["seed"], arrival=float(t))
+            for dd, t in zip(desc, times)]
+
+
+def summarize(done, wall: float) -> dict:
+    import numpy as np
+    lat = np.array([r.latency for r in done if r.status == ms.MS_OK]) * 1e3
+    ok = len(lat)
+    return {"requests": len(done), "ok": ok,
+            "solves_per_s": ok / wall if wall > 0 else 0.0,
+            "p50_ms": float(np.percentile(lat, 50)) if ok else None,
+            "p99_ms": float(np.percentile(lat, 99)) if ok else None,
+            "mean_ms": float(lat.mean()) if ok else None}

@@ -63,7 +63,7 @@ def test_workspace_sizes(ms):
 def test_invalid_arguments_rejected_on_host(ms):
     lib = ms._lib
     ws = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
-    o = ms.MsOpts(0, 0, 0, 0)
+    o = ms.MsOpts(0, 0, 0, 0, 0, 0, 0, 0)
     P = ctypes.c_void_p(0x2000)
     # negative sizes, k < 1, lda < d, unknown dtype, unknown mode, null workspace
     assert lib.countsketch_apply(-1, 1, 4, 0, P, 1, P, P, P, 4, ctypes.byref(o), ws, 1 << 20, None) == ms.MS_ERR_ARG
@@ -71,7 +71,7 @@ def test_invalid_arguments_rejected_on_host(ms):
     assert lib.countsketch_apply(10, 1, 4, 0, P, 9, P, P, P, 4, ctypes.byref(o), ws, 1 << 20, None) == ms.MS_ERR_ARG
     assert lib.countsketch_apply(10, 1, 4, 7, P, 10, P, P, P, 4, ctypes.byref(o), ws, 1 << 20, None) == ms.MS_ERR_ARG
     assert lib.countsketch_apply(10, 1, 4, 0, P, 10, P, P, P, 4, ctypes.byref(o), None, 1 << 20, None) == ms.MS_ERR_ARG
-    bad = ms.MsOpts(9, 0, 0, 0)
+    bad = ms.MsOpts(9, 0, 0, 0, 0, 0, 0, 0)
     assert lib.countsketch_apply(10, 1, 4, 0, P, 10, P, P, P, 4, ctypes.byref(bad), ws, 1 << 20, None) == ms.MS_ERR_ARG
     # workspace too small
     assert lib.countsketch_apply(10, 1, 4, 0, P, 10, P, P, P, 4, ctypes.byref(o), ws, 16, None) == ms.MS_ERR_NOMEM
@@ -81,7 +81,7 @@ def test_invalid_arguments_rejected_on_host(ms):
     # k2 < n for least squares; refinement with too many right-hand sides
     assert lib.sketch_lstsq(100, 8, 1, 32, 4, 0, P, 100, P, 100, P, P, 0, P, 4, P, 8,
                             ctypes.byref(o), ws, 1 << 30, None) == ms.MS_ERR_ARG
-    r = ms.MsOpts(0, 2, 0, 0)
+    r = ms.MsOpts(0, 2, 0, 0, 0, 0, 0, 0)
     assert lib.sketch_lstsq(100, 8, 9, 32, 16, 1, P, 100, P, 100, P, P, 1, P, 16, P, 8,
                             ctypes.byref(r), ws, 1 << 30, None) == ms.MS_ERR_UNSUPPORTED
     # QR: m < n
@@ -93,3 +93,40 @@ def test_invalid_arguments_rejected_on_host(ms):
 def test_status_strings(ms):
     for code in range(7):
         assert ms._lib.ms_status_string(code).decode().startswith("MS_")
+
+
+def test_struct_layouts_match_binding(ms, tmp_path):
+    # the C compiler's view of the ABI structs equals the ctypes mirrors
+    src = tmp_path / "sz.c"
+    src.write_text('#include "msketch.h"\n#include <stdio.h>\n#include <stddef.h>\n'
+                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(ms_opts), sizeof(ms_problem),'
+                   ' offsetof(ms_problem, X), offsetof(ms_opts, batch_kchunk_log2));return 0;}\n')
+    exe = tmp_path / "sz"
+    import subprocess
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = subprocess.check_output([str(exe)]).decode().split()
+    assert int(out[0]) == ctypes.sizeof(ms.MsOpts)
+    assert int(out[1]) == ctypes.sizeof(ms.MsProblem)
+    assert int(out[2]) == ms.MsProblem.X.offset
+    assert int(out[3]) == ms.MsOpts.batch_kchunk_log2.offset
+
+
+def test_batch_workspace_size_host_only(ms):
+    import torch
+    # descriptors are only inspected on the host here: fake device pointers
+    P = ms.MsProblem(1000, 8, 2, 128, 16, 0x10000, 1000, 0x20000, 1000, 0x30000, 0x40000,
+                     0x50000, 16, 0x60000, 8)
+    arr = (ms.MsProblem * 2)(P, P)
+    o = ms.MsOpts(0, 0, 0, 0, 0, 0, 0, 0)
+    sz = ms._lib.ms_batch_workspace_size(2, arr, 1, 1, ctypes.byref(o))
+    assert sz >= 256 and sz % 256 == 0
+    # k2 above the batched limit, refinement requested, bad tuning: refused
+    Pbig = ms.MsProblem(1000, 8, 2, 128, 512, 0x10000, 1000, 0x20000, 1000, 0x30000, 0x40000,
+                        0x50000, 512, 0x60000, 8)
+    assert ms._lib.ms_batch_workspace_size(1, (ms.MsProblem * 1)(Pbig), 1, 1, ctypes.byref(o)) == 0
+    r = ms.MsOpts(0, 1, 0, 0, 0, 0, 0, 0)
+    assert ms._lib.ms_batch_workspace_size(1, (ms.MsProblem * 1)(P), 1, 1, ctypes.byref(r)) == 0
+    bad = ms.MsOpts(0, 0, 0, 0, 30, 0, 0, 0)
+    assert ms._lib.ms_batch_workspace_size(1, (ms.MsProblem * 1)(P), 1, 1, ctypes.byref(bad)) == 0
+    assert ms._lib.sketch_lstsq_batched(0, arr, arr, 1, 1, None, ctypes.c_void_p(0x1000), 1 << 30,
+                                        None) == ms.MS_ERR_ARG

@@ -1,0 +1,118 @@
+"""GPU parity of the batched multisketch sketch-and-solve: every problem of a
+mixed batch against the oracle, each result the same alone and in the mix,
+HIP-graph capture and replay with rewritten descriptors, per-problem errors.
+
+Bar: FP64 problems 1e-12 normwise relative against the oracle (and against
+the same problem solved alone); FP32 problems 1e-4 (well-conditioned, FP32
+sketch); BF16 Gaussian stage against the oracle's BF16 path 1e-2 (the
+sketch's last-bit differences may move entries across a BF16 rounding
+boundary, each such entry changing by 2^-8 relative).
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import bf16_dev, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ms():
+    import paper_2508_14209_amd as ms
+    return ms
+
+
+def make_problem(ms, d, n, nrhs, seed, dtype=np.float64, gd="f64", noise=1e-6):
+    k, k2 = 2 * n * n, 2 * n
+    A = synth.normal_matrix(d, n, seed=seed, dtype=dtype)
+    B, _ = synth.lstsq_rhs(A, nrhs, seed=seed, noise=noise)
+    h = synth.bucket_map(d, k, seed=seed)
+    s = synth.signs(d, seed=seed)
+    G = synth.gaussian_sketch(k2, k, seed=seed, dtype=gd)
+    host = dict(A=A, B=B, h=h, s=s, G=G, k=k)
+    dev = dict(A=to_dev(A), B=to_dev(B), h=to_dev(h), s=to_dev(s),
+               G=bf16_dev(G) if gd == "bf16" else to_dev(G), k=k,
+               X=ms.empty_colmajor(n, nrhs, torch.float64, "cuda"))
+    return host, dev
+
+
+SHAPES = [(5000, 4, 1), (20000, 8, 3), (70001, 16, 2), (3000, 16, 8), (40000, 32, 1),
+          (100, 8, 1), (65536, 64, 4), (30000, 128, 1)]
+
+
+def test_batched_fp64_mixed_matches_oracle_and_alone(ms, orc):
+    probs = [make_problem(ms, d, n, r, seed=100 + i) for i, (d, n, r) in enumerate(SHAPES)]
+    runner = ms.sketch_lstsq_batched([p[1] for p in probs])
+    st, per = runner.status()
+    assert st == ms.MS_OK and all(v == ms.MS_OK for v in per)
+    for (host, dev), (d, n, r) in zip(probs, SHAPES):
+        Xb = to_host(dev["X"])
+        Xr, _, _ = orc.sketch_lstsq(host["A"], host["B"], host["h"], host["s"], host["G"], host["k"])
+        assert rel(Xb, Xr) <= 1e-12, (d, n, r, rel(Xb, Xr))
+        Xa, ws = ms.sketch_lstsq(dev["A"], dev["B"], dev["h"], dev["s"], dev["G"], host["k"])
+        ms.check_status(ws)
+        assert rel(Xb, to_host(Xa)) <= 1e-12
+
+
+@pytest.mark.parametrize("gd", ["f32", "bf16"])
+def test_batched_fp32(ms, orc, gd):
+    shapes = [(30000, 8, 2), (50000, 16, 1), (20000, 32, 4)]
+    probs = [make_problem(ms, d, n, r, seed=200 + i, dtype=np.float32, gd=gd)
+             for i, (d, n, r) in enumerate(shapes)]
+    runner = ms.sketch_lstsq_batched([p[1] for p in probs])
+    st, per = runner.status()
+    assert st == ms.MS_OK
+    for host, dev in probs:
+        Xr, _, _ = orc.sketch_lstsq(host["A"], host["B"], host["h"], host["s"], host["G"],
+                                    host["k"], y_bf16=(gd == "bf16"))
+        assert rel(to_host(dev["X"]), Xr) <= (1e-4 if gd == "f32" else 1e-2)
+
+
+def test_batched_graph_replay_with_new_problems(ms, orc):
+    shapes = [(20000, 8, 2), (30000, 16, 1), (10000, 8, 3)]
+    set1 = [make_problem(ms, d, n, r, seed=300 + i) for i, (d, n, r) in enumerate(shapes)]
+    set2 = [make_problem(ms, d + 777, n, r, seed=400 + i) for i, (d, n, r) in enumerate(shapes)]
+    runner = ms.BatchRunner([p[1] for p in set1])
+    runner.capture()
+    for rep in range(3):
+        for which in (set1, set2):
+            runner.set_problems([p[1] for p in which])
+            for _, dev in which:
+                dev["X"].fill_(float("nan"))
+            runner.replay()
+            torch.cuda.synchronize()
+            # eager work between replays
+            torch.ones(1024, device="cuda").sum().item()
+            st, per = runner.status()
+            assert st == ms.MS_OK, (rep, st, per)
+            for host, dev in which:
+                Xr, _, _ = orc.sketch_lstsq(host["A"], host["B"], host["h"], host["s"],
+                                            host["G"], host["k"])
+                assert rel(to_host(dev["X"]), Xr) <= 1e-12
+
+
+def test_batched_per_problem_range_error(ms, orc):
+    probs = [make_problem(ms, 5000, 8, 1, seed=500 + i) for i in range(3)]
+    bad_h = probs[1][0]["h"].copy()
+    bad_h[17] = probs[1][0]["k"]  # out of range
+    probs[1][1]["h"] = to_dev(bad_h)
+    runner = ms.sketch_lstsq_batched([p[1] for p in probs])
+    st, per = runner.status()
+    assert st == ms.MS_ERR_RANGE
+    assert per == [ms.MS_OK, ms.MS_ERR_RANGE, ms.MS_OK]
+    for i in (0, 2):
+        host, dev = probs[i]
+        Xr, _, _ = orc.sketch_lstsq(host["A"], host["B"], host["h"], host["s"], host["G"], host["k"])
+        assert rel(to_host(dev["X"]), Xr) <= 1e-12
+
+
+def test_batched_replay_larger_than_capacity_is_refused(ms):
+    small = [make_problem(ms, 4000, 8, 1, seed=600 + i) for i in range(2)]
+    big = [make_problem(ms, 4000, 16, 1, seed=700 + i) for i in range(2)]
+    runner = ms.BatchRunner([p[1] for p in small])
+    runner.set_problems([p[1] for p in big])
+    runner.launch()
+    st, per = runner.status()
+    assert st == ms.MS_ERR_NOMEM and per == [ms.MS_ERR_NOMEM] * 2
