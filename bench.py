@@ -14,7 +14,12 @@ Also measured, each over its own timed loop on the launch stream:
   * the global-atomic CountSketch (the Alg. 2 baseline) and the deterministic
     sorted CountSketch, for comparison;
   * the Gaussian stage alone (matrix cores, FP64);
-  * the CPU oracle on the host, for the cpu_baseline entry.
+  * the CPU oracle on the host, for the cpu_baseline entry;
+  * the continuous-batching serving loop over a stream of uneven requests
+    (open loop at 2,000/s and closed loop), p50/p99 latency and solves/s;
+  * a batch of such problems solved by the plain FP64 path one by one and by
+    the batched mixed-precision path (BF16 Gaussian stage, FP64 QR and
+    refinement), with solves/s and residual ratios against the FP64 QR optimum.
 
 Prints ONE JSON line.  Usage: python bench.py [--steps K] [--warmup W]
 """
@@ -46,6 +51,12 @@ def parse():
     ap.add_argument("--seed", type=int, default=14209)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU time budget of the oracle baseline (0 disables it)")
+    ap.add_argument("--serve-requests", type=int, default=4096,
+                    help="requests of the serving stream legs (0 skips them)")
+    ap.add_argument("--compare-problems", type=int, default=64,
+                    help="problems of the batched mixed-precision vs plain FP64 leg (0 skips it)")
+    ap.add_argument("--refine", type=int, default=2,
+                    help="FP64-residual refinement steps of the mixed-precision legs")
     ap.add_argument("--only", default=None, choices=["countsketch", "copy"],
                     help="profiling runs: launch only the LDS CountSketch of [A | b] (--steps "
                          "times) or only a plain device copy of 1 GiB (calibrates the "
@@ -53,8 +64,159 @@ def parse():
     return ap.parse_args()
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles",
+                               "k_cs_lds_xcd_multisketch_lstsq_4194304x65_f64_traffic.md")
+
+
+def measured_traffic():
+    """HBM bytes per CountSketch launch from the committed counter profile,
+    or None once the kernel's source differs from the profiled one."""
+    import hashlib
+    import re
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m_t = re.search(r"traffic_bytes_per_launch:\s*(\d+)", text)
+    m_h = re.search(r"kernel_source_sha256:\s*([0-9a-f]{64})", text)
+    if not (m_t and m_h):
+        return None
+    return int(m_t.group(1)) if countsketch_source_hash() == m_h.group(1) else None
+
+
+def countsketch_source_hash():
+    """sha256 of the single-problem CountSketch sources: countsketch.hip and
+    ms_internal.h up to their batched sections (which the profiled kernel
+    does not use)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f, mark in (("countsketch.hip", "// " + "-" * 66 + " batched"),
+                    ("ms_internal.h", "// " + "-" * 64 + " batched")):
+        with open(os.path.join(ROOT, "paper_2508_14209_amd", "csrc", f)) as fh:
+            text = fh.read()
+        h.update(text[:text.index(mark)].encode())
+    return h.hexdigest()
+
+
 def event_pair(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+SERVE_WORKLOAD = ("Poisson arrivals at 2,000/s; d log-uniform in [2^14, 2^20], n uniform in "
+                  "{8,16,32,64,128}, 1-8 right-hand sides, FP32 A = N(0,1) diag(logspace(0, "
+                  "-log10 kappa, n)), kappa log-uniform in [1e1, 1e5]; k = 2n^2, k2 = 2n")
+
+
+def serving_leg(ms, torch, np, count, seed, refine, dev):
+    """Continuous-batching serving loop over the request stream: open loop at
+    2,000 requests/s and closed loop (all requests at t = 0, saturation)."""
+    from paper_2508_14209_amd import serve
+    out = {"workload": SERVE_WORKLOAD, "requests": count, "g_dtype": "bf16",
+           "refine_steps": refine, "max_batch": 64, "streams": 4}
+    # warm-up: load every kernel of the batched path once
+    warm = serve.make_requests(16, 0.0, seed=seed + 7)
+    serve.Server(max_batch=8, streams=2, g_dtype="bf16", refine_steps=refine, device=dev).run(warm)
+    for name, rate in (("open_loop_2000_per_s", 2000.0), ("closed_loop", 0.0)):
+        reqs = serve.make_requests(count, rate, seed=seed)
+        srv = serve.Server(hbm_budget=96 << 30, max_inflight=512, max_batch=64, streams=4,
+                           g_dtype="bf16", refine_steps=refine, device=dev)
+        t0 = time.perf_counter()
+        done = srv.run(reqs)
+        wall = time.perf_counter() - t0
+        summ = serve.summarize(done, wall)
+        summ.update({"wall_s": wall, "batches": srv.nbatches,
+                     "peak_inflight_bytes": srv.admission.peak_bytes,
+                     "failed": sum(1 for r in done if r.status != ms.MS_OK)})
+        out[name] = summ
+    return out
+
+
+def mixed_vs_fp64_leg(ms, torch, np, count, seed, refine, dev, reps=3):
+    """The same batch of serving-stream problems solved (a) one by one by the
+    plain FP64 multisketch path (A and G promoted exactly to FP64), (b) in
+    one batched FP64 call, (c) in one batched mixed-precision call (FP32
+    CountSketch, BF16 Gaussian stage, FP64 QR and `refine` FP64-residual
+    refinement steps) and (d) the same without refinement; solves/s of each
+    and the residual ratio ||b - A x|| / ||b - A x_opt|| against the FP64 QR
+    optimum x_opt (library QR in FP64 on the device, measurement only)."""
+    from paper_2508_14209_amd import serve
+    reqs = serve.make_requests(count, 0.0, seed=seed)
+    p32, p64, pbf = [], [], []
+    for r in reqs:
+        t = serve.generate(r, dev, "f32")
+        d, n, nrhs, k, k2 = r.d, r.n, r.nrhs, r.k, r.k2
+        A64 = ms.empty_colmajor(d, n, torch.float64, dev)
+        A64.copy_(t["A"])
+        B64 = ms.empty_colmajor(d, nrhs, torch.float64, dev)
+        B64.copy_(t["B"])
+        Gb = torch.empty((k, k2), device=dev, dtype=torch.bfloat16).t()
+        Gb.copy_(t["G"])
+        G64 = ms.empty_colmajor(k2, k, torch.float64, dev)
+        G64.copy_(Gb)                      # the BF16 values, exactly
+        common = dict(h=t["h"], s=t["s"], k=k)
+        p64.append(dict(A=A64, B=B64, G=G64, X=ms.empty_colmajor(n, nrhs, torch.float64, dev),
+                        **common))
+        pbf.append(dict(A=t["A"], B=t["B"], G=Gb, X=ms.empty_colmajor(n, nrhs, torch.float64, dev),
+                        **common))
+        p32.append(pbf[-1])
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return count * reps / (time.perf_counter() - t0)
+
+    wmax = max(ms.workspace_size("lstsq", d=p["A"].shape[0], n=p["A"].shape[1],
+                                 nrhs=p["B"].shape[1], k=p["k"], k2=p["G"].shape[0])
+               for p in p64)
+    ws = ms.workspace(wmax, dev)
+
+    def plain():
+        for p in p64:
+            ms.sketch_lstsq(p["A"], p["B"], p["h"], p["s"], p["G"], p["k"], X=p["X"], ws=ws)
+
+    res = {}
+    res["plain_fp64_solves_per_s"] = timed(plain)
+    ms.check_status(ws)
+    X_plain = [p["X"].clone() for p in p64]
+    r64 = ms.BatchRunner(p64)
+    res["batched_fp64_solves_per_s"] = timed(lambda: r64.launch())
+    assert r64.status()[0] == ms.MS_OK
+    X_b64 = [p["X"].clone() for p in p64]
+    r0 = ms.BatchRunner(pbf, refine_steps=0)
+    res["batched_mixed_norefine_solves_per_s"] = timed(lambda: r0.launch())
+    assert r0.status()[0] == ms.MS_OK
+    X_m0 = [p["X"].clone() for p in pbf]
+    rr = ms.BatchRunner(pbf, refine_steps=refine)
+    res["batched_mixed_solves_per_s"] = timed(lambda: rr.launch())
+    assert rr.status()[0] == ms.MS_OK
+    X_mr = [p["X"].clone() for p in pbf]
+
+    def rho(Xs):
+        vals = []
+        for p, X, xo in zip(p64, Xs, x_opt):
+            num = torch.linalg.norm(p["B"] - p["A"] @ X)
+            den = torch.linalg.norm(p["B"] - p["A"] @ xo)
+            vals.append(float(num / den))
+        return {"max": max(vals), "median": float(np.median(vals))}
+
+    x_opt = []
+    for p in p64:
+        Q, R = torch.linalg.qr(p["A"], mode="reduced")
+        x_opt.append(torch.linalg.solve_triangular(R, Q.t() @ p["B"], upper=True))
+        del Q, R
+    res["rho_vs_fp64_qr_optimum"] = {"plain_fp64": rho(X_plain), "batched_fp64": rho(X_b64),
+                                     "batched_mixed_norefine": rho(X_m0),
+                                     "batched_mixed": rho(X_mr)}
+    res["speedup_batched_mixed_over_plain_fp64"] = (res["batched_mixed_solves_per_s"]
+                                                    / res["plain_fp64_solves_per_s"])
+    res.update({"problems": count, "refine_steps": refine, "workload": SERVE_WORKLOAD,
+                "g_dtype_mixed": "bf16", "reps": reps})
+    return res
 
 
 def main():
@@ -218,9 +380,25 @@ def main():
         "gaussian_stage": {"avg_us": gs_ms * 1e3, "TFLOPs": gs_flops / (gs_ms * 1e-3) / 1e12,
                            "pct_fp64_peak": 100.0 * gs_flops / (gs_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS},
         "roofline": {"bound": "hbm", "achieved": cs_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": cs_gbps / HBM_PEAK_GBPS, "traffic": None},
+                     "frac": cs_gbps / HBM_PEAK_GBPS, "traffic": measured_traffic()},
         "cpu_baseline": cpu,
     }
+    # beyond the headline: the serving loop and the batched mixed-precision
+    # solver against the plain FP64 one (each leg reports its own error)
+    del AB, Gd, Y, Ys, Z, ws, sws, gws
+    torch.cuda.empty_cache()
+    if args.serve_requests > 0:
+        try:
+            out["serving"] = serving_leg(ms, torch, np, args.serve_requests, seed, args.refine,
+                                         dev)
+        except Exception as e:  # reported in the line, not hidden
+            out["serving"] = {"error": repr(e)}
+    if args.compare_problems > 0:
+        try:
+            out["batched_mixed_vs_plain_fp64"] = mixed_vs_fp64_leg(
+                ms, torch, np, args.compare_problems, seed + 1, args.refine, dev)
+        except Exception as e:
+            out["batched_mixed_vs_plain_fp64"] = {"error": repr(e)}
     print(json.dumps(out))
 
 

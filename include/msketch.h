@@ -226,7 +226,7 @@ ms_status ms_qr_solve(int64_t m, int64_t n, int64_t nrhs, const double *W,
  * Q^T applied to Z_B; back substitution.
  *   a_dtype F64: g_dtype F64.   a_dtype F32: g_dtype F32 or BF16.
  *   Requires d >= 1, n >= 1, nrhs >= 1, k >= 1, k2 >= n.
- * opts->refine_steps > 0 (FP32 A only) then repeats, in FP64,
+ * opts->refine_steps > 0 (requires nrhs <= 8) then repeats, in FP64,
  *   r = B - A X;  X += R^{-1} Q^T G (C r)
  * with the Q and R of the first pass.
  */
@@ -265,7 +265,8 @@ typedef struct {
  * Workspace bytes of sketch_lstsq_batched for these problems (host array).
  * 0 for invalid arguments.  A workspace sized for one set of problems serves
  * any other set with the same count whose problems are no larger in k,
- * k2 and n + nrhs (d does not enter).
+ * k2 and n + nrhs (and, with refinement, in d * nrhs): d does not enter
+ * without refinement.
  */
 size_t ms_batch_workspace_size(int count, const ms_problem *probs,
                                ms_dtype a_dtype, ms_dtype g_dtype,
@@ -274,10 +275,11 @@ size_t ms_batch_workspace_size(int count, const ms_problem *probs,
 /*
  * Batched multisketch sketch-and-solve: every problem p is solved as
  * sketch_lstsq would solve it (same association G (C [A | B]), same
- * Householder QR and back substitution), all problems together in a fixed
- * sequence of six launches whose grids do not depend on the problems'
- * contents -- so the sequence can be captured once in a HIP graph and
- * replayed after the descriptors in device memory are rewritten.
+ * Householder QR and back substitution, same FP64-residual refinement), all
+ * problems together in a fixed sequence of launches (six, plus five per
+ * refinement step) whose grids do not depend on the problems' contents -- so
+ * the sequence can be captured once in a HIP graph and replayed after the
+ * descriptors in device memory are rewritten.
  *   count      number of problems (1 .. 65535);
  *   probs_host host copy of the descriptors: validated, and used for the
  *              launch shapes (LDS size, QR register tile);
@@ -285,9 +287,12 @@ size_t ms_batch_workspace_size(int count, const ms_problem *probs,
  *   a_dtype    MS_F32 or MS_F64 (all problems); g_dtype as for sketch_lstsq.
  * Limits per problem: k2 <= MS_BATCH_MAX_K2, n + nrhs <= MS_BATCH_MAX_COLS,
  * k2 >= n >= 1, nrhs >= 1, 1 <= d < 2^31, 1 <= k < 2^31.  The CountSketch is the
- * LDS variant (opts->cs_mode MS_CS_SORTED -> MS_ERR_UNSUPPORTED); no
- * refinement (opts->refine_steps must be 0).  Device errors are recorded per
- * problem (ms_batch_status) and in the workspace status word.
+ * LDS variant (opts->cs_mode MS_CS_SORTED or MS_CS_ATOMIC ->
+ * MS_ERR_UNSUPPORTED).  opts->refine_steps (0 .. 64) refinement steps
+ * x <- x + R^{-1} Q^T G C (b - A x) with the FP64 residual, as in
+ * sketch_lstsq; with refinement every problem needs nrhs <= 8 (else
+ * MS_ERR_UNSUPPORTED).  Device errors are recorded per problem
+ * (ms_batch_status) and in the workspace status word.
  */
 ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
                                const ms_problem *probs_dev, ms_dtype a_dtype,

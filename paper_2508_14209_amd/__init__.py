@@ -384,9 +384,9 @@ def _host_array(problems):
 
 
 def batch_workspace_size(problems, a_dtype: int, g_dtype: int, rows_log2: int = 0,
-                         kchunk_log2: int = 0) -> int:
+                         kchunk_log2: int = 0, refine_steps: int = 0) -> int:
     arr = _host_array(problems)
-    o = _opts("auto", 0, 0, 0, rows_log2, kchunk_log2)
+    o = _opts("auto", refine_steps, 0, 0, rows_log2, kchunk_log2)
     sz = _lib.ms_batch_workspace_size(len(problems), arr, a_dtype, g_dtype, ctypes.byref(o))
     if sz == 0:
         raise MsketchError(MS_ERR_ARG, "ms_batch_workspace_size")
@@ -408,16 +408,19 @@ class BatchRunner:
     ``problems``: list of dicts with device tensors A (d x n), B (d x nrhs),
     h (int32, d), s (int8, d), G (k2 x k), X (n x nrhs, FP64) and int k.
     ``capacity``: problems that bound later ones (same count, each no larger
-    in k, k2, n + nrhs); defaults to ``problems``.
+    in k, k2, n + nrhs, and with refinement in d * nrhs); defaults to
+    ``problems``.  ``refine_steps``: FP64-residual refinement steps (each
+    problem then needs nrhs <= 8).
     """
 
-    def __init__(self, problems, capacity=None, rows_log2: int = 0, kchunk_log2: int = 0):
+    def __init__(self, problems, capacity=None, rows_log2: int = 0, kchunk_log2: int = 0,
+                 refine_steps: int = 0):
         if not problems:
             raise ValueError("empty batch")
         self.count = len(problems)
         self.a_dtype = _dt(problems[0]["A"])
         self.g_dtype = _dt(problems[0]["G"])
-        self.opts = _opts("auto", 0, 0, 0, rows_log2, kchunk_log2)
+        self.opts = _opts("auto", refine_steps, 0, 0, rows_log2, kchunk_log2)
         cap = capacity if capacity is not None else problems
         cap_arr = _host_array(cap)
         need = _lib.ms_batch_workspace_size(self.count, cap_arr, self.a_dtype, self.g_dtype,
@@ -475,9 +478,11 @@ class BatchRunner:
         return batch_status(self.ws, self.count, stream)
 
 
-def sketch_lstsq_batched(problems, rows_log2: int = 0, kchunk_log2: int = 0, stream=None):
+def sketch_lstsq_batched(problems, rows_log2: int = 0, kchunk_log2: int = 0,
+                         refine_steps: int = 0, stream=None):
     """Solve a list of problems (dicts as for BatchRunner) in one batched call;
     returns the runner (its problems' X tensors hold the solutions)."""
-    r = BatchRunner(problems, rows_log2=rows_log2, kchunk_log2=kchunk_log2)
+    r = BatchRunner(problems, rows_log2=rows_log2, kchunk_log2=kchunk_log2,
+                    refine_steps=refine_steps)
     r.launch(stream)
     return r

@@ -11,6 +11,11 @@
 //   gemm    persistent Gaussian stage over (problem, row tile, column tile, K)
 //   reduce  split-K partials summed in split order, per problem, into FP64 Z
 //   qr      one workgroup per problem: Householder QR, Q^T Z_B, back solve
+//
+// and, for each refinement step, five more: clear the residual sketches,
+// residuals r = B - A X (FP64), their CountSketch, G (C r) in FP64 split-K
+// partials, and one workgroup per problem that sums the partials and applies
+// the kept Q and R to update X.
 #include <algorithm>
 
 #include "ms_internal.h"
@@ -22,11 +27,12 @@ namespace {
 constexpr int kSetupThreads = 1024;
 
 struct BatchCaps {
-  int64_t y_bytes, part_bytes, z_bytes;
+  int64_t y_bytes, part_bytes, z_bytes;       // first pass
+  int64_t f_bytes, r_bytes, yr_bytes, gv_bytes;  // refinement (0 without)
 };
 
 struct BatchLayout {
-  size_t pstatus, entries, totals, yarea, parea, zarea, total;
+  size_t pstatus, entries, totals, yarea, parea, zarea, farea, rarea, yrarea, gvarea, total;
 };
 
 BatchLayout batch_layout(int count, const BatchCaps &caps) {
@@ -38,8 +44,32 @@ BatchLayout batch_layout(int count, const BatchCaps &caps) {
   L.yarea = cv.take((size_t)caps.y_bytes);
   L.parea = cv.take((size_t)caps.part_bytes);
   L.zarea = cv.take((size_t)caps.z_bytes);
+  L.farea = cv.take((size_t)caps.f_bytes);
+  L.rarea = cv.take((size_t)caps.r_bytes);
+  L.yrarea = cv.take((size_t)caps.yr_bytes);
+  L.gvarea = cv.take((size_t)caps.gv_bytes);
   L.total = cv.off;
   return L;
+}
+
+// The per-problem quantities the setup scans: work items of each persistent
+// launch and bytes of each workspace area.
+enum BatchQ { QCS, QGEMM, QRES, QRCS, QGV, QY, QPART, QZ, QF, QR, QYR, QGVB, NQ };
+
+__host__ __device__ inline void batch_quantities(const ms_problem &P, const BatchEntry &e,
+                                                 int wdata, int accw, int64_t q[NQ]) {
+  q[QCS] = batch_cs_items(e);
+  q[QGEMM] = batch_gemm_items(e);
+  q[QRES] = batch_res_items(P, e);
+  q[QRCS] = batch_rcs_items(e);
+  q[QGV] = batch_gv_items(e);
+  q[QY] = batch_y_bytes(P, e, wdata);
+  q[QPART] = batch_part_bytes(P, e, accw);
+  q[QZ] = batch_z_bytes(P, e);
+  q[QF] = batch_f_bytes(P, e);
+  q[QR] = batch_r_bytes(P, e);
+  q[QYR] = batch_yr_bytes(P, e);
+  q[QGVB] = batch_gv_bytes(P, e);
 }
 
 __device__ __forceinline__ int64_t wave_excl_scan64(int64_t v, int64_t &wave_total) {
@@ -74,51 +104,57 @@ __device__ int64_t block_excl_scan64(int64_t v, int64_t *sh, int64_t &total) {
 
 __global__ __launch_bounds__(kSetupThreads) void k_batch_setup(
     int count, const ms_problem *__restrict__ P, int wdata, int accw, int64_t rows_item,
-    int64_t kchunk, BatchCaps caps, BatchEntry *__restrict__ E, BatchTotals *__restrict__ tot,
-    int *__restrict__ pstatus, int *status) {
+    int64_t kchunk, int refine, BatchCaps caps, BatchEntry *__restrict__ E,
+    BatchTotals *__restrict__ tot, int *__restrict__ pstatus, int *status) {
   __shared__ int64_t sh[16];
   if (threadIdx.x == 0) *status = MS_OK;
   const int per = (count + (int)blockDim.x - 1) / (int)blockDim.x;
   const int p0 = min(count, (int)threadIdx.x * per), p1 = min(count, p0 + per);
-  int64_t s_cs = 0, s_gm = 0, s_y = 0, s_pt = 0, s_z = 0, mx = 0;
+  int64_t sum[NQ] = {}, mx = 0;
   for (int p = p0; p < p1; ++p) {
     BatchEntry e;
-    batch_entry(P[p], wdata, accw, rows_item, kchunk, e);
-    s_cs += batch_cs_items(e);
-    s_gm += batch_gemm_items(e);
-    s_y += batch_y_bytes(P[p], e, wdata);
-    s_pt += batch_part_bytes(P[p], e, accw);
-    s_z += batch_z_bytes(P[p], e);
+    batch_entry(P[p], wdata, accw, rows_item, kchunk, refine, e);
+    int64_t q[NQ];
+    batch_quantities(P[p], e, wdata, accw, q);
+    for (int j = 0; j < NQ; ++j) sum[j] += q[j];
     if (e.valid) mx = max(mx, P[p].k2 * (int64_t)e.nc);
     pstatus[p] = e.valid ? MS_OK : MS_ERR_ARG;
   }
   __syncthreads();
-  int64_t t_cs, t_gm, t_y, t_pt, t_z;
-  int64_t o_cs = block_excl_scan64(s_cs, sh, t_cs);
-  int64_t o_gm = block_excl_scan64(s_gm, sh, t_gm);
-  int64_t o_y = block_excl_scan64(s_y, sh, t_y);
-  int64_t o_pt = block_excl_scan64(s_pt, sh, t_pt);
-  int64_t o_z = block_excl_scan64(s_z, sh, t_z);
+  int64_t off[NQ], total[NQ];
+  for (int j = 0; j < NQ; ++j) off[j] = block_excl_scan64(sum[j], sh, total[j]);
   // the workspace areas were sized on the host; descriptors rewritten for a
   // graph replay must not need more
-  const bool fits = t_y <= caps.y_bytes && t_pt <= caps.part_bytes && t_z <= caps.z_bytes;
+  const bool fits = total[QY] <= caps.y_bytes && total[QPART] <= caps.part_bytes &&
+                    total[QZ] <= caps.z_bytes && total[QF] <= caps.f_bytes &&
+                    total[QR] <= caps.r_bytes && total[QYR] <= caps.yr_bytes &&
+                    total[QGVB] <= caps.gv_bytes;
   for (int p = p0; p < p1; ++p) {
     BatchEntry e;
-    batch_entry(P[p], wdata, accw, rows_item, kchunk, e);
+    batch_entry(P[p], wdata, accw, rows_item, kchunk, refine, e);
+    const bool valid = e.valid != 0;
     if (!fits) e.valid = 0;
-    e.cs_start = o_cs;
-    e.gemm_start = o_gm;
-    e.y_off = o_y;
-    e.part_off = o_pt;
-    e.z_off = o_z;
-    o_cs += batch_cs_items(e);
-    o_gm += batch_gemm_items(e);
-    o_y += batch_y_bytes(P[p], e, wdata);
-    o_pt += batch_part_bytes(P[p], e, accw);
-    o_z += batch_z_bytes(P[p], e);
+    int64_t q[NQ];
+    batch_quantities(P[p], e, wdata, accw, q);
+    e.cs_start = off[QCS];
+    e.gemm_start = off[QGEMM];
+    e.res_start = off[QRES];
+    e.rcs_start = off[QRCS];
+    e.gv_start = off[QGV];
+    e.y_off = off[QY];
+    e.part_off = off[QPART];
+    e.z_off = off[QZ];
+    e.f_off = off[QF];
+    e.r_off = off[QR];
+    e.yr_off = off[QYR];
+    e.gv_off = off[QGVB];
+    for (int j = 0; j < NQ; ++j) off[j] += q[j];
     E[p] = e;
-    if (!e.valid) record_status(status, fits ? MS_ERR_ARG : MS_ERR_NOMEM);
-    if (!fits) pstatus[p] = MS_ERR_NOMEM;
+    if (!valid) record_status(status, MS_ERR_ARG);
+    if (!fits) {
+      record_status(status, MS_ERR_NOMEM);
+      pstatus[p] = MS_ERR_NOMEM;
+    }
   }
   __shared__ int64_t mx_sh[16];
   int64_t m = mx;
@@ -130,20 +166,26 @@ __global__ __launch_bounds__(kSetupThreads) void k_batch_setup(
     int64_t mm = 0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) mm = max(mm, mx_sh[w]);
     BatchTotals T{};
-    T.cs_items = fits ? t_cs : 0;
-    T.gemm_items = fits ? t_gm : 0;
-    T.y_bytes = fits ? t_y : 0;
-    T.part_bytes = t_pt;
-    T.z_bytes = t_z;
+    T.cs_items = fits ? total[QCS] : 0;
+    T.gemm_items = fits ? total[QGEMM] : 0;
+    T.res_items = fits ? total[QRES] : 0;
+    T.rcs_items = fits ? total[QRCS] : 0;
+    T.gv_items = fits ? total[QGV] : 0;
+    T.y_bytes = fits ? total[QY] : 0;
+    T.yr_bytes = fits ? total[QYR] : 0;
+    T.part_bytes = total[QPART];
+    T.z_bytes = total[QZ];
     T.max_mn = mm;
     *tot = T;
   }
 }
 
-// Clear the accumulators of all problems (the first y_bytes of the area).
-__global__ void k_batch_zero(const BatchTotals *__restrict__ tot, unsigned char *__restrict__ yarea) {
+// Clear the accumulators of all problems (the first y_bytes of the area, or
+// yr_bytes for the residual sketches).
+__global__ void k_batch_zero(const BatchTotals *__restrict__ tot, int residual,
+                             unsigned char *__restrict__ yarea) {
   typedef uint32_t u4 __attribute__((ext_vector_type(4)));
-  const int64_t n16 = tot->y_bytes / 16;
+  const int64_t n16 = (residual ? tot->yr_bytes : tot->y_bytes) / 16;
   u4 *y = reinterpret_cast<u4 *>(yarea);
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n16;
        t += (int64_t)gridDim.x * blockDim.x)
@@ -162,10 +204,11 @@ int64_t kchunk_of(const ms_opts *o) {
   const int r = o ? o->batch_kchunk_log2 : 0;
   return (int64_t)1 << (r ? r : 10);
 }
+int refine_of(const ms_opts *o) { return o ? o->refine_steps : 0; }
 bool valid_batch_opts(const ms_opts *o) {
   if (!o) return true;
   if (o->cs_mode != MS_CS_AUTO && o->cs_mode != MS_CS_LDS) return false;
-  if (o->refine_steps != 0) return false;
+  if (o->refine_steps < 0 || o->refine_steps > 64) return false;
   if (o->batch_rows_log2 != 0 && (o->batch_rows_log2 < 8 || o->batch_rows_log2 > 24)) return false;
   if (o->batch_kchunk_log2 != 0 && (o->batch_kchunk_log2 < 5 || o->batch_kchunk_log2 > 20))
     return false;
@@ -174,8 +217,8 @@ bool valid_batch_opts(const ms_opts *o) {
 
 // Host pass over the descriptors: validity, area sizes and launch maxima.
 struct HostBatch {
-  bool ok = true;
-  BatchCaps caps{0, 0, 0};
+  bool ok = true, refine_rhs_ok = true;
+  BatchCaps caps{0, 0, 0, 0, 0, 0, 0};
   int max_k2 = 1, max_n = 1, max_nc = 2;
   int64_t max_mn = 1;
 };
@@ -185,16 +228,27 @@ HostBatch host_batch(int count, const ms_problem *probs, ms_dtype a, ms_dtype g,
   HostBatch H;
   const int wdata = (int)dtype_size(a);
   const int accw = g == MS_F64 ? 8 : 4;
+  const int refine = refine_of(o) > 0;
   for (int p = 0; p < count; ++p) {
+    if (refine && probs[p].nrhs > kBatchMaxRefineRhs) {
+      H.refine_rhs_ok = false;
+      return H;
+    }
     BatchEntry e;
-    batch_entry(probs[p], wdata, accw, rows_item_of(o), kchunk_of(o), e);
+    batch_entry(probs[p], wdata, accw, rows_item_of(o), kchunk_of(o), refine, e);
     if (!e.valid) {
       H.ok = false;
       return H;
     }
-    H.caps.y_bytes += batch_y_bytes(probs[p], e, wdata);
-    H.caps.part_bytes += batch_part_bytes(probs[p], e, accw);
-    H.caps.z_bytes += batch_z_bytes(probs[p], e);
+    int64_t q[NQ];
+    batch_quantities(probs[p], e, wdata, accw, q);
+    H.caps.y_bytes += q[QY];
+    H.caps.part_bytes += q[QPART];
+    H.caps.z_bytes += q[QZ];
+    H.caps.f_bytes += q[QF];
+    H.caps.r_bytes += q[QR];
+    H.caps.yr_bytes += q[QYR];
+    H.caps.gv_bytes += q[QGVB];
     H.max_k2 = std::max<int>(H.max_k2, (int)probs[p].k2);
     H.max_n = std::max<int>(H.max_n, (int)probs[p].n);
     H.max_nc = std::max<int>(H.max_nc, e.nc);
@@ -216,7 +270,7 @@ size_t ms_batch_workspace_size(int count, const ms_problem *probs, ms_dtype a_dt
       !valid_batch_opts(opts))
     return 0;
   const HostBatch H = host_batch(count, probs, a_dtype, g_dtype, opts);
-  if (!H.ok) return 0;
+  if (!H.ok || !H.refine_rhs_ok) return 0;
   return batch_layout(count, H.caps).total;
 }
 
@@ -225,11 +279,11 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
                                const ms_opts *opts, void *ws, size_t ws_bytes, void *stream) {
   if (count < 1 || count > 65535 || !probs_host || !probs_dev || !ws) return MS_ERR_ARG;
   if (!valid_dtypes(a_dtype, g_dtype)) return MS_ERR_ARG;
-  if (opts && (opts->refine_steps != 0 || opts->cs_mode == MS_CS_SORTED ||
-               opts->cs_mode == MS_CS_ATOMIC))
+  if (opts && (opts->cs_mode == MS_CS_SORTED || opts->cs_mode == MS_CS_ATOMIC))
     return MS_ERR_UNSUPPORTED;
   if (!valid_batch_opts(opts)) return MS_ERR_ARG;
   const HostBatch H = host_batch(count, probs_host, a_dtype, g_dtype, opts);
+  if (!H.refine_rhs_ok) return MS_ERR_UNSUPPORTED;
   if (!H.ok) return MS_ERR_ARG;
   const BatchLayout L = batch_layout(count, H.caps);
   if (ws_bytes < L.total) return MS_ERR_NOMEM;
@@ -240,19 +294,24 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
   BatchEntry *E = reinterpret_cast<BatchEntry *>(base + L.entries);
   BatchTotals *tot = reinterpret_cast<BatchTotals *>(base + L.totals);
   unsigned char *yarea = base + L.yarea, *parea = base + L.parea, *zarea = base + L.zarea;
+  unsigned char *farea = base + L.farea, *rarea = base + L.rarea, *yrarea = base + L.yrarea,
+                *gvarea = base + L.gvarea;
   const DevInfo &di = dev_info();
   const int wdata = (int)dtype_size(a_dtype);
   const int accw = g_dtype == MS_F64 ? 8 : 4;
+  const int refine = refine_of(opts);
 
   hipLaunchKernelGGL(k_batch_setup, dim3(1), dim3(kSetupThreads), 0, st, count, probs_dev, wdata,
-                     accw, rows_item_of(opts), kchunk_of(opts), H.caps, E, tot, pstatus, status);
+                     accw, rows_item_of(opts), kchunk_of(opts), refine > 0 ? 1 : 0, H.caps, E,
+                     tot, pstatus, status);
   hipError_t e = hipGetLastError();
-  if (e == hipSuccess) {
-    const int64_t n16 = H.caps.y_bytes / 16;
+  auto zero = [&](int residual, int64_t cap, unsigned char *area) {
+    const int64_t n16 = cap / 16;
     const unsigned zb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n16 + 255) / 256, 8192));
-    hipLaunchKernelGGL(k_batch_zero, dim3(zb), dim3(256), 0, st, tot, yarea);
-    e = hipGetLastError();
-  }
+    hipLaunchKernelGGL(k_batch_zero, dim3(zb), dim3(256), 0, st, tot, residual, area);
+    return hipGetLastError();
+  };
+  if (e == hipSuccess) e = zero(0, H.caps.y_bytes, yarea);
   if (e == hipSuccess) {
     const int grid = di.cus;  // one 1024-thread workgroup per CU (128 KB of LDS each)
     e = a_dtype == MS_F64
@@ -264,8 +323,23 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
   if (e == hipSuccess)
     e = launch_batch_reduce(count, g_dtype, probs_dev, E, parea, zarea, (int)H.max_mn, st);
   if (e == hipSuccess)
-    e = launch_batch_qr(count, H.max_k2, H.max_n, H.max_nc, probs_dev, E, zarea, pstatus, status,
-                        st);
+    e = launch_batch_qr(count, H.max_k2, H.max_n, H.max_nc, probs_dev, E, zarea, farea, pstatus,
+                        status, st);
+  // refinement: r = B - A X (FP64); X += R^{-1} Q^T G (C r)
+  for (int it = 0; it < refine && e == hipSuccess; ++it) {
+    e = zero(1, H.caps.yr_bytes, yrarea);
+    if (e == hipSuccess)
+      e = a_dtype == MS_F64
+              ? launch_batch_residual<double>(count, probs_dev, E, tot, rarea, di.cus * 8, st)
+              : launch_batch_residual<float>(count, probs_dev, E, tot, rarea, di.cus * 8, st);
+    if (e == hipSuccess)
+      e = launch_batch_cs_res(count, probs_dev, E, tot, rarea, yrarea, pstatus, status, di.cus,
+                              st);
+    if (e == hipSuccess)
+      e = launch_batch_gemv(count, g_dtype, probs_dev, E, tot, yrarea, gvarea, di.cus * 4, st);
+    if (e == hipSuccess)
+      e = launch_batch_apply_solve(count, probs_dev, E, gvarea, farea, pstatus, status, st);
+  }
   return e == hipSuccess ? MS_OK : MS_ERR_DEVICE;
 }
 

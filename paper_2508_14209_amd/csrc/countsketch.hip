@@ -647,55 +647,56 @@ __global__ __launch_bounds__(1024) void k_cs_lds_xcd(int64_t d, Cols<T> cols,
 
 // ------------------------------------------------------------------ batched
 
-__device__ __forceinline__ int batch_find(const BatchEntry *__restrict__ E, int count, int64_t it,
-                                          bool gemm) {
-  // last problem whose first item is <= it (problems without items share the
-  // next problem's start and so are never selected)
-  int lo = 0, hi = count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    const int64_t st = gemm ? E[mid].gemm_start : E[mid].cs_start;
-    if (st <= it)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
 // Persistent workgroups over the CountSketch items of all problems: item =
 // (problem, column tile, row segment, bucket tile).  h and s are read and
-// validated in the kernel; a problem's Y must be zero on entry.
-template <typename T>
+// validated in the kernel; a problem's Y must be zero on entry.  RES: the
+// CountSketch of the FP64 residual columns (refinement) instead of [A | B].
+template <typename T, bool RES>
 __global__ __launch_bounds__(1024) void k_batch_cs(int count, const ms_problem *__restrict__ P,
                                                    const BatchEntry *__restrict__ E,
                                                    const BatchTotals *__restrict__ tot,
+                                                   const unsigned char *__restrict__ rarea,
                                                    unsigned char *__restrict__ yarea,
                                                    int *__restrict__ pstatus, int *status) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double *acc = reinterpret_cast<double *>(smem_raw);
   for (int t = threadIdx.x; t < kBatchLdsSlots; t += blockDim.x) acc[t] = 0.0;
   __syncthreads();
-  const int64_t total = tot->cs_items;
+  const int64_t total = RES ? tot->rcs_items : tot->cs_items;
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
-    const int p = batch_find(E, count, it, false);
+    const int p = RES ? batch_find_m<&BatchEntry::rcs_start>(E, count, it)
+                      : batch_find_m<&BatchEntry::cs_start>(E, count, it);
     const ms_problem &Q = P[p];
     const BatchEntry &e = E[p];
-    int64_t local = it - e.cs_start;
-    const int bt = (int)(local % e.nbt);
-    local /= e.nbt;
+    const int nbt = RES ? e.rnbt : e.nbt, nt = RES ? e.rnt : e.nt;
+    const int64_t ktile = RES ? e.rktile : e.ktile;
+    int64_t local = it - (RES ? e.rcs_start : e.cs_start);
+    const int bt = (int)(local % nbt);
+    local /= nbt;
     const int seg = (int)(local % e.nsegs);
     const int tile = (int)(local / e.nsegs);
     const int64_t r0 = (int64_t)seg * e.rows, r1 = min(Q.d, r0 + e.rows);
-    const int64_t b0 = (int64_t)bt * e.ktile;
-    const uint32_t kt = (uint32_t)min(e.ktile, Q.k - b0);
-    const Cols<T> cols{static_cast<const T *>(Q.A), Q.lda, static_cast<const T *>(Q.B), Q.ldb,
-                       (int)Q.n, e.nc};
-    const int c0 = tile * e.nt;
-    const int ncur = min(e.nt, e.nc - c0);
-    T *Y = reinterpret_cast<T *>(yarea + e.y_off);
+    const int64_t b0 = (int64_t)bt * ktile;
+    const uint32_t kt = (uint32_t)min(ktile, Q.k - b0);
+    Cols<T> cols;
+    bool vec;
+    T *Y;
+    if (RES) {
+      const T *r = reinterpret_cast<const T *>(rarea + e.r_off);
+      cols = Cols<T>{r, Q.d, nullptr, 0, (int)Q.nrhs, (int)Q.nrhs};
+      vec = ((Q.d * (int64_t)sizeof(T)) & 15) == 0 && ((uintptr_t)Q.h & 15) == 0 &&
+            ((uintptr_t)Q.s & (uintptr_t)(16 / sizeof(T) - 1)) == 0;
+      Y = reinterpret_cast<T *>(yarea + e.yr_off);
+    } else {
+      cols = Cols<T>{static_cast<const T *>(Q.A), Q.lda, static_cast<const T *>(Q.B), Q.ldb,
+                     (int)Q.n, e.nc};
+      vec = e.vec != 0;
+      Y = reinterpret_cast<T *>(yarea + e.y_off);
+    }
+    const int c0 = tile * nt;
+    const int ncur = min(nt, cols.ncols - c0);
     bool bad = false;
-    if (e.vec)
+    if (vec)
       cs_segment<T, 4, true, false, 2, false>(acc, cols, c0, ncur, nullptr, Q.h, Q.s, Q.k, b0, kt,
                                               r0, r1, Y, Q.k, bad);
     else
@@ -713,10 +714,10 @@ hipError_t launch_batch_cs(int count, const ms_problem *P, const BatchEntry *E,
                            const BatchTotals *tot, unsigned char *yarea, int *pstatus, int *status,
                            int grid, hipStream_t st) {
   const size_t lds = (size_t)kBatchLdsSlots * sizeof(double);
-  hipError_t e = allow_dynamic_lds((const void *)k_batch_cs<T>, (int)lds);
+  hipError_t e = allow_dynamic_lds((const void *)k_batch_cs<T, false>, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batch_cs<T>, dim3(grid), dim3(1024), lds, st, count, P, E, tot, yarea,
-                     pstatus, status);
+  hipLaunchKernelGGL((k_batch_cs<T, false>), dim3(grid), dim3(1024), lds, st, count, P, E, tot,
+                     (const unsigned char *)nullptr, yarea, pstatus, status);
   return hipGetLastError();
 }
 template hipError_t launch_batch_cs<double>(int, const ms_problem *, const BatchEntry *,
@@ -725,6 +726,18 @@ template hipError_t launch_batch_cs<double>(int, const ms_problem *, const Batch
 template hipError_t launch_batch_cs<float>(int, const ms_problem *, const BatchEntry *,
                                            const BatchTotals *, unsigned char *, int *, int *, int,
                                            hipStream_t);
+
+hipError_t launch_batch_cs_res(int count, const ms_problem *P, const BatchEntry *E,
+                               const BatchTotals *tot, const unsigned char *rarea,
+                               unsigned char *yrarea, int *pstatus, int *status, int grid,
+                               hipStream_t st) {
+  const size_t lds = (size_t)kBatchLdsSlots * sizeof(double);
+  hipError_t e = allow_dynamic_lds((const void *)k_batch_cs<double, true>, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_batch_cs<double, true>), dim3(grid), dim3(1024), lds, st, count, P, E,
+                     tot, rarea, yrarea, pstatus, status);
+  return hipGetLastError();
+}
 
 template <typename T, int NT, bool CODES>
 static hipError_t launch_cs_xcd_v(bool vec, int grid, size_t lds, hipStream_t st, int64_t d,

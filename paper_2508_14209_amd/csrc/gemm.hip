@@ -239,19 +239,6 @@ __global__ void k_reduce_splits(int M, int N, int nsplit, const Acc *__restrict_
 
 // ------------------------------------------------------------------ batched
 
-__device__ __forceinline__ int batch_find_gemm(const BatchEntry *__restrict__ E, int count,
-                                               int64_t it) {
-  int lo = 0, hi = count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (E[mid].gemm_start <= it)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
 // Persistent workgroups over the Gaussian-stage items of all problems: item
 // = (problem, 64-row tile, 64-column tile, K split); each writes its partial
 // block into the problem's partials area.
@@ -264,7 +251,7 @@ __global__ __launch_bounds__(256) void k_batch_gemm(int count, const ms_problem 
   using F = Mf<DT>;
   const int64_t total = tot->gemm_items;
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
-    const int p = batch_find_gemm(E, count, it);
+    const int p = batch_find_m<&BatchEntry::gemm_start>(E, count, it);
     const ms_problem &Q = P[p];
     const BatchEntry &e = E[p];
     int64_t local = it - e.gemm_start;
@@ -445,6 +432,65 @@ __global__ __launch_bounds__(256) void k_gemv64_splitk(int M, int N, int64_t K,
     for (int c = 0; c < 8; ++c)
       if (c < N) P[p + (int64_t)c * M] = acc[c];
   }
+}
+
+// Refinement of a batch: partials of G Yr in FP64 (G's values promoted
+// exactly), item = (problem, K split); one thread per row of G (k2 <= 256).
+template <typename TG>
+__global__ __launch_bounds__(256) void k_batch_gemv(int count, const ms_problem *__restrict__ P,
+                                                    const BatchEntry *__restrict__ E,
+                                                    const BatchTotals *__restrict__ tot,
+                                                    const unsigned char *__restrict__ yrarea,
+                                                    unsigned char *__restrict__ gvarea) {
+  const int64_t total = tot->gv_items;
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const int p = batch_find_m<&BatchEntry::gv_start>(E, count, it);
+    const ms_problem &Q = P[p];
+    const BatchEntry &e = E[p];
+    const int split = (int)(it - e.gv_start);
+    const int M = (int)Q.k2, N = (int)Q.nrhs;
+    const int64_t kb = (int64_t)split * e.kchunk, ke = min(Q.k, kb + e.kchunk);
+    const double *Yr = reinterpret_cast<const double *>(yrarea + e.yr_off);
+    double *part = reinterpret_cast<double *>(gvarea + e.gv_off) + (int64_t)split * M * N;
+    const TG *G = static_cast<const TG *>(Q.G);
+    for (int row = threadIdx.x; row < M; row += blockDim.x) {
+      double acc[kBatchMaxRefineRhs];
+#pragma unroll
+      for (int c = 0; c < kBatchMaxRefineRhs; ++c) acc[c] = 0.0;
+      for (int64_t m = kb; m < ke; ++m) {
+        const double g = g_as_f64<TG>(G[row + m * Q.ldg]);
+#pragma unroll
+        for (int c = 0; c < kBatchMaxRefineRhs; ++c)
+          if (c < N) acc[c] += g * Yr[m + (int64_t)c * Q.k];
+      }
+#pragma unroll
+      for (int c = 0; c < kBatchMaxRefineRhs; ++c)
+        if (c < N) part[row + (int64_t)c * M] = acc[c];
+    }
+  }
+}
+
+hipError_t launch_batch_gemv(int count, ms_dtype g_dtype, const ms_problem *P,
+                             const BatchEntry *E, const BatchTotals *tot,
+                             const unsigned char *yrarea, unsigned char *gvarea, int grid,
+                             hipStream_t st) {
+  switch (g_dtype) {
+    case MS_F64:
+      hipLaunchKernelGGL(k_batch_gemv<double>, dim3(grid), dim3(256), 0, st, count, P, E, tot,
+                         yrarea, gvarea);
+      break;
+    case MS_F32:
+      hipLaunchKernelGGL(k_batch_gemv<float>, dim3(grid), dim3(256), 0, st, count, P, E, tot,
+                         yrarea, gvarea);
+      break;
+    case MS_BF16:
+      hipLaunchKernelGGL(k_batch_gemv<unsigned short>, dim3(grid), dim3(256), 0, st, count, P, E,
+                         tot, yrarea, gvarea);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 size_t gemv64_partial_bytes(int64_t M, int64_t N, int64_t K) {

@@ -173,8 +173,18 @@ struct BatchEntry {
   int64_t kchunk;      // K per Gaussian-stage item
   int64_t ktile;       // buckets per LDS tile
   int32_t nc, nt, ntiles, nsegs, nbt, tiles_m, tiles_n, nsplit;
-  int32_t valid, vec, pad0, pad1;
+  int32_t valid, vec, refine, pad0;
+  // refinement (refine != 0): residual r = B - A X (FP64, d x nrhs), its
+  // CountSketch Yr (k x nrhs, FP64), G Yr split-K partials, and the QR
+  // factors (k2 x n reflectors and R, then n values of tau)
+  int64_t res_start, rcs_start, gv_start;
+  int64_t f_off, r_off, yr_off, gv_off;
+  int64_t rktile;
+  int32_t rnt, rntiles, rnbt, pad1;
 };
+
+constexpr int64_t kBatchResRows = 256;  // rows per residual work item
+constexpr int kBatchMaxRefineRhs = 8;
 
 constexpr int64_t kBatchLdsSlots = 16384;  // FP64 partial sums per workgroup (128 KB)
 constexpr int kBatchMaxK2 = 256;
@@ -184,24 +194,34 @@ __host__ __device__ inline int64_t batch_align(int64_t x) { return (x + 255) / 2
 
 // Sizes of one problem's items and areas.  wdata: bytes of A; accw: bytes of
 // a Gaussian-stage partial; rows_item, kchunk: tuning (powers of two).
+// Buckets per LDS tile and columns per tile for a CountSketch of nc columns.
+__host__ __device__ inline void batch_cs_geom(int64_t k, int nc, int64_t &ktile, int32_t &nbt,
+                                              int32_t &nt, int32_t &ntiles) {
+  ktile = k;
+  if (ktile > kBatchLdsSlots) {
+    ktile = 1;
+    while (ktile * 2 <= kBatchLdsSlots) ktile *= 2;
+  }
+  nbt = (int32_t)((k + ktile - 1) / ktile);
+  nt = 1;
+  while (nt < 4 && ktile * nt * 2 <= kBatchLdsSlots && nt * 2 <= nc) nt *= 2;
+  ntiles = (nc + nt - 1) / nt;
+}
+
 __host__ __device__ inline void batch_entry(const ms_problem &P, int wdata, int accw,
-                                            int64_t rows_item, int64_t kchunk, BatchEntry &E) {
+                                            int64_t rows_item, int64_t kchunk, int refine,
+                                            BatchEntry &E) {
   E = BatchEntry{};
   E.valid = P.d >= 1 && P.d < 0x7fffffffLL && P.n >= 1 && P.nrhs >= 1 && P.k >= 1 &&
             P.k < 0x7fffffffLL && P.k2 >= P.n && P.k2 <= kBatchMaxK2 &&
             P.n + P.nrhs <= kBatchMaxCols && P.lda >= P.d && P.ldb >= P.d && P.ldg >= P.k2 &&
-            P.ldx >= P.n && P.A && P.B && P.h && P.s && P.G && P.X;
+            P.ldx >= P.n && P.A && P.B && P.h && P.s && P.G && P.X &&
+            (!refine || P.nrhs <= kBatchMaxRefineRhs);
   if (!E.valid) return;
   E.nc = (int32_t)(P.n + P.nrhs);
-  E.ktile = P.k;
-  if (E.ktile > kBatchLdsSlots) {
-    E.ktile = 1;
-    while (E.ktile * 2 <= kBatchLdsSlots) E.ktile *= 2;
-  }
-  E.nbt = (int32_t)((P.k + E.ktile - 1) / E.ktile);
-  E.nt = 1;
-  while (E.nt < 4 && E.ktile * E.nt * 2 <= kBatchLdsSlots && E.nt * 2 <= E.nc) E.nt *= 2;
-  E.ntiles = (E.nc + E.nt - 1) / E.nt;
+  batch_cs_geom(P.k, E.nc, E.ktile, E.nbt, E.nt, E.ntiles);
+  E.refine = refine ? 1 : 0;
+  if (refine) batch_cs_geom(P.k, (int)P.nrhs, E.rktile, E.rnbt, E.rnt, E.rntiles);
   E.rows = rows_item;
   E.nsegs = (int32_t)((P.d + rows_item - 1) / rows_item);
   E.tiles_m = (int32_t)((P.k2 + 63) / 64);
@@ -228,12 +248,52 @@ __host__ __device__ inline int64_t batch_part_bytes(const ms_problem &P, const B
 __host__ __device__ inline int64_t batch_z_bytes(const ms_problem &P, const BatchEntry &E) {
   return E.valid ? batch_align(P.k2 * E.nc * 8) : 0;
 }
+// refinement items and areas (zero without refinement)
+__host__ __device__ inline bool batch_ref(const BatchEntry &E) { return E.valid && E.refine; }
+__host__ __device__ inline int64_t batch_res_items(const ms_problem &P, const BatchEntry &E) {
+  return batch_ref(E) ? (P.d + kBatchResRows - 1) / kBatchResRows : 0;
+}
+__host__ __device__ inline int64_t batch_rcs_items(const BatchEntry &E) {
+  return batch_ref(E) ? (int64_t)E.rntiles * E.nsegs * E.rnbt : 0;
+}
+__host__ __device__ inline int64_t batch_gv_items(const BatchEntry &E) {
+  return batch_ref(E) ? (int64_t)E.nsplit : 0;
+}
+__host__ __device__ inline int64_t batch_f_bytes(const ms_problem &P, const BatchEntry &E) {
+  return batch_ref(E) ? batch_align((P.k2 * P.n + P.n) * 8) : 0;
+}
+__host__ __device__ inline int64_t batch_r_bytes(const ms_problem &P, const BatchEntry &E) {
+  return batch_ref(E) ? batch_align(P.d * P.nrhs * 8) : 0;
+}
+__host__ __device__ inline int64_t batch_yr_bytes(const ms_problem &P, const BatchEntry &E) {
+  return batch_ref(E) ? batch_align(P.k * P.nrhs * 8) : 0;
+}
+__host__ __device__ inline int64_t batch_gv_bytes(const ms_problem &P, const BatchEntry &E) {
+  return batch_ref(E) ? batch_align((int64_t)E.nsplit * P.k2 * P.nrhs * 8) : 0;
+}
 
 // Totals written by the setup kernel (device) next to the entries.
 struct BatchTotals {
   int64_t cs_items, gemm_items, y_bytes, part_bytes, z_bytes, max_mn;
+  int64_t res_items, rcs_items, gv_items, yr_bytes;
   int64_t pad[2];
 };
+
+// Last problem whose first item (member M of its entry) is <= it; problems
+// without items share the next problem's start and so are never selected.
+template <int64_t BatchEntry::*M>
+__device__ __forceinline__ int batch_find_m(const BatchEntry *__restrict__ E, int count,
+                                            int64_t it) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (E[mid].*M <= it)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
 
 // countsketch.hip / gemm.hip / qr.hip batched launchers
 template <typename T>
@@ -248,7 +308,23 @@ hipError_t launch_batch_reduce(int count, ms_dtype g_dtype, const ms_problem *P,
                                const BatchEntry *E, const unsigned char *parea,
                                unsigned char *zarea, int max_mn, hipStream_t st);
 hipError_t launch_batch_qr(int count, int max_k2, int max_n, int max_nc, const ms_problem *P,
-                           const BatchEntry *E, const unsigned char *zarea, int *pstatus,
-                           int *status, hipStream_t st);
+                           const BatchEntry *E, const unsigned char *zarea, unsigned char *farea,
+                           int *pstatus, int *status, hipStream_t st);
+// refinement: r = B - A X; Yr = C r; partials of G Yr; X += R^{-1} Q^T (G Yr)
+template <typename TA>
+hipError_t launch_batch_residual(int count, const ms_problem *P, const BatchEntry *E,
+                                 const BatchTotals *tot, unsigned char *rarea, int grid,
+                                 hipStream_t st);
+hipError_t launch_batch_cs_res(int count, const ms_problem *P, const BatchEntry *E,
+                               const BatchTotals *tot, const unsigned char *rarea,
+                               unsigned char *yrarea, int *pstatus, int *status, int grid,
+                               hipStream_t st);
+hipError_t launch_batch_gemv(int count, ms_dtype g_dtype, const ms_problem *P,
+                             const BatchEntry *E, const BatchTotals *tot,
+                             const unsigned char *yrarea, unsigned char *gvarea, int grid,
+                             hipStream_t st);
+hipError_t launch_batch_apply_solve(int count, const ms_problem *P, const BatchEntry *E,
+                                    const unsigned char *gvarea, const unsigned char *farea,
+                                    int *pstatus, int *status, hipStream_t st);
 
 }  // namespace ms

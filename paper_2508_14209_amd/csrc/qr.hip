@@ -137,12 +137,23 @@ __device__ __forceinline__ double read_lane(double v, int lane) {
   const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+// DPP broadcast into the rows selected by ROWMASK; other rows get 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_bcast(double v) {
+  const long long u = __double_as_longlong(v);
+  int lo = (int)(u & 0xffffffffLL), hi = (int)(u >> 32);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 __device__ __forceinline__ double wave_allsum(double v) {
-  v += dpp_move<0xb1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_move<0x4e>(v);   // quad_perm [2,3,0,1]
-  v += dpp_move<0x141>(v);  // row_half_mirror
-  v += dpp_move<0x140>(v);  // row_mirror: every lane holds its 16-lane row sum
-  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+  v += dpp_move<0xb1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_move<0x4e>(v);        // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);       // row_half_mirror
+  v += dpp_move<0x140>(v);       // row_mirror: every lane holds its 16-lane row sum
+  v += dpp_bcast<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3: rows (0+1), (2+3)
+  v += dpp_bcast<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3: lane 63 holds the total
+  return read_lane(v, 63);
 }
 
 // Householder QR least squares with the system [W | Bm] (m x nc, nc = n +
@@ -154,6 +165,33 @@ __device__ __forceinline__ double wave_allsum(double v) {
 // an m x nc product -- the same sum, in the same precision, as the separate
 // split reduction.
 // R and the transformed right-hand sides go to LDS for the back substitution.
+// Back substitution R x = y by one wave, y held in registers (lane l owns
+// rows l + 64 r): per row a lane read, one division and one update per lane.
+template <int RPL>
+__device__ __forceinline__ void wave_back_substitute_reg(int n, const double *R, int ldr,
+                                                         const double *ysrc, double *X) {
+  const int lane = threadIdx.x & 63;
+  double y[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int t = lane + 64 * r;
+    y[r] = t < n ? ysrc[t] : 0.0;
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double yl = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)
+      if (r == (i >> 6)) yl = y[r];
+    const double xi = read_lane(yl, i & 63) / R[i + i * ldr];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int t = lane + 64 * r;
+      if (t < i) y[r] -= R[t + i * ldr] * xi;
+    }
+    if (lane == 0) X[i] = xi;
+  }
+}
+
 template <int RPL>
 struct QrShared {
   double vbuf[2][64 * RPL];
@@ -268,7 +306,10 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, int nrhs, const double
           for (int r = 0; r < RPL; ++r) dots[q] += v[r] * a[q][r];
       }
 #pragma unroll
-      for (int q = 0; q < CPW; ++q) dots[q] = wave_allsum(dots[q]);
+      for (int q = 0; q < CPW; ++q) {
+        const int c = wave + 16 * q;
+        if (c > j && c < nc) dots[q] = wave_allsum(dots[q]);
+      }
 #pragma unroll
       for (int q = 0; q < CPW; ++q) {
         const int c = wave + 16 * q;
@@ -311,7 +352,7 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, int nrhs, const double
     return;
   }
   for (int c = wave; c < nrhs; c += 16)
-    wave_back_substitute(n, rs, n, rs + (int64_t)(n + c) * n, X + (int64_t)c * ldx);
+    wave_back_substitute_reg<RPL>(n, rs, n, rs + (int64_t)(n + c) * n, X + (int64_t)c * ldx);
 }
 
 template <int RPL, int CPW>
@@ -334,6 +375,7 @@ template <int RPL, int CPW>
 __global__ __launch_bounds__(1024) void k_batch_qr(int count, const ms_problem *__restrict__ P,
                                                    const BatchEntry *__restrict__ E,
                                                    const unsigned char *__restrict__ zarea,
+                                                   unsigned char *__restrict__ farea,
                                                    int *__restrict__ pstatus, int *status,
                                                    int64_t lds_doubles) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -352,8 +394,10 @@ __global__ __launch_bounds__(1024) void k_batch_qr(int count, const ms_problem *
     }
     return;
   }
+  double *fact = batch_ref(e) ? reinterpret_cast<double *>(farea + e.f_off) : nullptr;
+  double *tau = fact ? fact + (int64_t)m * n : nullptr;
   qr_reg_body<RPL, CPW>(m, n, (int)Q.nrhs, Z, m, Z + (int64_t)n * m, m, nullptr, nullptr, 0, Q.X,
-                        Q.ldx, nullptr, 0, nullptr, nullptr, &pstatus[p], status,
+                        Q.ldx, nullptr, 0, tau, fact, &pstatus[p], status,
                         reinterpret_cast<double *>(smem_raw), sh);
 }
 
@@ -443,8 +487,8 @@ hipError_t launch_qr_solve(int64_t m, int64_t n, int64_t nrhs, const double *W, 
 }
 
 hipError_t launch_batch_qr(int count, int max_k2, int max_n, int max_nc, const ms_problem *P,
-                           const BatchEntry *E, const unsigned char *zarea, int *pstatus,
-                           int *status, hipStream_t st) {
+                           const BatchEntry *E, const unsigned char *zarea, unsigned char *farea,
+                           int *pstatus, int *status, hipStream_t st) {
   const size_t lds = (size_t)max_n * (size_t)max_nc * sizeof(double);
   for (const QrRegShape &s : kQrShapes) {
     if (64 * s.rpl < max_k2 || 16 * s.cpw < max_nc) continue;
@@ -453,7 +497,7 @@ hipError_t launch_batch_qr(int count, int max_k2, int max_n, int max_nc, const m
     hipError_t e = allow_dynamic_lds((const void *)k_batch_qr<R_, C_>, (int)lds);            \
     if (e != hipSuccess) return e;                                                            \
     hipLaunchKernelGGL((k_batch_qr<R_, C_>), dim3(count), dim3(1024), lds, st, count, P, E,  \
-                       zarea, pstatus, status, (int64_t)max_n * max_nc);                      \
+                       zarea, farea, pstatus, status, (int64_t)max_n * max_nc);               \
     return hipGetLastError();                                                                 \
   }
     MS_BQR_CASE(1, 1)
@@ -467,6 +511,57 @@ hipError_t launch_batch_qr(int count, int max_k2, int max_n, int max_nc, const m
 #undef MS_BQR_CASE
   }
   return hipErrorNotSupported;
+}
+
+// Refinement of a batch, one workgroup per problem: zr = the G Yr partials
+// summed in split order; dx = R^{-1} (Q^T zr)_{0:n} with the reflectors, tau
+// and R the first pass kept; X += dx.  One wave per right-hand side.
+__global__ __launch_bounds__(64 * kBatchMaxRefineRhs) void k_batch_apply_solve(
+    int count, const ms_problem *__restrict__ P, const BatchEntry *__restrict__ E,
+    const unsigned char *__restrict__ gvarea, const unsigned char *__restrict__ farea) {
+  __shared__ double zb[kBatchMaxK2 * kBatchMaxRefineRhs];
+  const int p = blockIdx.x;
+  const BatchEntry &e = E[p];
+  if (!batch_ref(e)) return;
+  const ms_problem &Q = P[p];
+  const int m = (int)Q.k2, n = (int)Q.n, nrhs = (int)Q.nrhs;
+  if (m > kBatchMaxK2 || nrhs > kBatchMaxRefineRhs) return;  // excluded by the setup
+  const int64_t MN = (int64_t)m * nrhs;
+  const double *part = reinterpret_cast<const double *>(gvarea + e.gv_off);
+  for (int t = threadIdx.x; t < MN; t += blockDim.x) {
+    double s = part[t];
+    for (int z = 1; z < e.nsplit; ++z) s = s + part[t + (int64_t)z * MN];
+    zb[t] = s;
+  }
+  __syncthreads();
+  const double *fact = reinterpret_cast<const double *>(farea + e.f_off);
+  const double *tau = fact + (int64_t)m * n;
+  const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
+  if (c >= nrhs) return;
+  double *b = zb + (int64_t)c * m;
+  for (int j = 0; j < n; ++j) {
+    const double tj = tau[j];
+    if (tj == 0.0) continue;
+    const double *v = fact + (int64_t)j * m;
+    double s = lane == 0 ? b[j] : 0.0;
+    for (int i = j + 1 + lane; i < m; i += 64) s += v[i] * b[i];
+    const double w = wave_sum(s) * tj;
+    if (lane == 0) b[j] -= w;
+    for (int i = j + 1 + lane; i < m; i += 64) b[i] -= w * v[i];
+    __threadfence_block();
+  }
+  wave_back_substitute(n, fact, m, b, b);  // in place: b[0:n) = dx
+  for (int i = lane; i < n; i += 64) Q.X[i + (int64_t)c * Q.ldx] += b[i];
+}
+
+hipError_t launch_batch_apply_solve(int count, const ms_problem *P, const BatchEntry *E,
+                                    const unsigned char *gvarea, const unsigned char *farea,
+                                    int *pstatus, int *status, hipStream_t st) {
+  (void)pstatus;
+  (void)status;
+  hipLaunchKernelGGL(k_batch_apply_solve, dim3(count), dim3(64 * kBatchMaxRefineRhs), 0, st,
+                     count, P, E, gvarea, farea);
+  return hipGetLastError();
 }
 
 // Apply H_0 ... H_{n-1} (stored in fact/tau) to each right-hand side, one

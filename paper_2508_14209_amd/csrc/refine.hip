@@ -52,6 +52,54 @@ hipError_t launch_residual_f64(int64_t d, int64_t n, int64_t nrhs, const double 
   return hipGetLastError();
 }
 
+// Residuals of a batch: item = (problem, kBatchResRows rows), one thread per
+// row; B has A's type.  r_p is d x nrhs, column-major, ld d.
+template <typename TA>
+__global__ __launch_bounds__(kBatchResRows) void k_batch_residual(
+    int count, const ms_problem *__restrict__ P, const BatchEntry *__restrict__ E,
+    const BatchTotals *__restrict__ tot, unsigned char *__restrict__ rarea) {
+  const int64_t total = tot->res_items;
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const int p = batch_find_m<&BatchEntry::res_start>(E, count, it);
+    const ms_problem &Q = P[p];
+    const BatchEntry &e = E[p];
+    const int64_t i = (it - e.res_start) * kBatchResRows + threadIdx.x;
+    if (i >= Q.d) continue;
+    const TA *A = static_cast<const TA *>(Q.A);
+    const TA *B = static_cast<const TA *>(Q.B);
+    const int n = (int)Q.n, nrhs = (int)Q.nrhs;
+    double acc[kBatchMaxRefineRhs];
+#pragma unroll
+    for (int c = 0; c < kBatchMaxRefineRhs; ++c) acc[c] = 0.0;
+#pragma unroll 4
+    for (int j = 0; j < n; ++j) {
+      const double a = (double)A[i + (int64_t)j * Q.lda];
+#pragma unroll
+      for (int c = 0; c < kBatchMaxRefineRhs; ++c)
+        if (c < nrhs) acc[c] += a * Q.X[j + (int64_t)c * Q.ldx];
+    }
+    double *r = reinterpret_cast<double *>(rarea + e.r_off);
+#pragma unroll
+    for (int c = 0; c < kBatchMaxRefineRhs; ++c)
+      if (c < nrhs) r[i + (int64_t)c * Q.d] = (double)B[i + (int64_t)c * Q.ldb] - acc[c];
+  }
+}
+
+template <typename TA>
+hipError_t launch_batch_residual(int count, const ms_problem *P, const BatchEntry *E,
+                                 const BatchTotals *tot, unsigned char *rarea, int grid,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_residual<TA>, dim3(grid), dim3(kBatchResRows), 0, st, count, P, E,
+                     tot, rarea);
+  return hipGetLastError();
+}
+template hipError_t launch_batch_residual<float>(int, const ms_problem *, const BatchEntry *,
+                                                 const BatchTotals *, unsigned char *, int,
+                                                 hipStream_t);
+template hipError_t launch_batch_residual<double>(int, const ms_problem *, const BatchEntry *,
+                                                  const BatchTotals *, unsigned char *, int,
+                                                  hipStream_t);
+
 // X += dX (n x nrhs).
 __global__ void k_axpy_update(int n, int nrhs, const double *__restrict__ dX, double *X,
                               int64_t ldx) {

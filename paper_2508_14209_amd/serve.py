@@ -55,12 +55,17 @@ class Request:
         return self.t_done - self.arrival
 
 
-def footprint_bytes(d: int, n: int, nrhs: int, k: int, k2: int, w: int = 4) -> int:
+def footprint_bytes(d: int, n: int, nrhs: int, k: int, k2: int, w: int = 4,
+                    refine: bool = False) -> int:
     """HBM a request holds while in flight: its inputs and output plus its
-    share of the batched workspace (sketch, split-K partials, Z)."""
+    share of the batched workspace (sketch, split-K partials, Z; with
+    refinement also the QR factors, the FP64 residual, its sketch and the
+    Gaussian-stage partials of the residual)."""
     data = d * (n + nrhs) * w + d * 5 + k2 * k * w + n * nrhs * 8
     nsplit = (k + 1023) // 1024
     work = k * (n + nrhs) * w + nsplit * k2 * (n + nrhs) * 4 + k2 * (n + nrhs) * 8 + 1024
+    if refine:
+        work += (k2 * n + n) * 8 + d * nrhs * 8 + k * nrhs * 8 + nsplit * k2 * nrhs * 8 + 1024
     return data + work
 
 
@@ -126,13 +131,14 @@ class Server:
 
     def __init__(self, hbm_budget: int = 64 << 30, max_inflight: int = 256, max_batch: int = 64,
                  streams: int = 4, g_dtype: str = "f32", rows_log2: int = 0,
-                 kchunk_log2: int = 0, device="cuda"):
+                 kchunk_log2: int = 0, refine_steps: int = 0, device="cuda"):
         self.device = torch.device(device)
         self.admission = Admission(hbm_budget, max_inflight)
         self.max_batch = max_batch
         self.g_dtype = g_dtype
         self.rows_log2 = rows_log2
         self.kchunk_log2 = kchunk_log2
+        self.refine_steps = refine_steps
         self.gen_stream = torch.cuda.Stream(device=self.device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self.busy = {}                # stream index -> (event, runner, requests)
@@ -147,7 +153,8 @@ class Server:
 
     # -- arrivals and admission ------------------------------------------------
     def arrive(self, req: Request):
-        req.footprint = footprint_bytes(req.d, req.n, req.nrhs, req.k, req.k2)
+        req.footprint = footprint_bytes(req.d, req.n, req.nrhs, req.k, req.k2,
+                                        refine=self.refine_steps > 0)
         self.waiting.append(req)
         self._admit()
 
@@ -180,7 +187,8 @@ class Server:
                     pr[key].record_stream(st)
             with torch.cuda.stream(st):
                 runner = ms.BatchRunner(probs, rows_log2=self.rows_log2,
-                                        kchunk_log2=self.kchunk_log2)
+                                        kchunk_log2=self.kchunk_log2,
+                                        refine_steps=self.refine_steps)
                 runner.launch(st)
                 ev = torch.cuda.Event()
                 ev.record(st)

@@ -120,12 +120,29 @@ def test_batch_workspace_size_host_only(ms):
     o = ms.MsOpts(0, 0, 0, 0, 0, 0, 0, 0)
     sz = ms._lib.ms_batch_workspace_size(2, arr, 1, 1, ctypes.byref(o))
     assert sz >= 256 and sz % 256 == 0
-    # k2 above the batched limit, refinement requested, bad tuning: refused
+    # k2 above the batched limit, bad tuning: refused
     Pbig = ms.MsProblem(1000, 8, 2, 128, 512, 0x10000, 1000, 0x20000, 1000, 0x30000, 0x40000,
                         0x50000, 512, 0x60000, 8)
     assert ms._lib.ms_batch_workspace_size(1, (ms.MsProblem * 1)(Pbig), 1, 1, ctypes.byref(o)) == 0
+    # refinement adds the QR factors, the FP64 residual (d x nrhs), its sketch
+    # (k x nrhs) and the residual's Gaussian-stage partials, each 256-aligned
+    # (without refinement each of the four areas is one empty 256-byte block)
     r = ms.MsOpts(0, 1, 0, 0, 0, 0, 0, 0)
-    assert ms._lib.ms_batch_workspace_size(1, (ms.MsProblem * 1)(P), 1, 1, ctypes.byref(r)) == 0
+    one = ms._lib.ms_batch_workspace_size(1, (ms.MsProblem * 1)(P), 1, 1, ctypes.byref(o))
+    one_r = ms._lib.ms_batch_workspace_size(1, (ms.MsProblem * 1)(P), 1, 1, ctypes.byref(r))
+    al = lambda x: (x + 255) // 256 * 256
+    assert one_r - one == (al((16 * 8 + 8) * 8) + al(1000 * 2 * 8) + al(128 * 2 * 8)
+                           + al(1 * 16 * 2 * 8) - 4 * 256)
+    # refinement needs nrhs <= 8; at most 64 steps
+    P9 = ms.MsProblem(1000, 8, 9, 128, 16, 0x10000, 1000, 0x20000, 1000, 0x30000, 0x40000,
+                      0x50000, 16, 0x60000, 8)
+    assert ms._lib.ms_batch_workspace_size(1, (ms.MsProblem * 1)(P9), 1, 1, ctypes.byref(o)) > 0
+    assert ms._lib.ms_batch_workspace_size(1, (ms.MsProblem * 1)(P9), 1, 1, ctypes.byref(r)) == 0
+    assert ms._lib.sketch_lstsq_batched(1, (ms.MsProblem * 1)(P9), (ms.MsProblem * 1)(P9), 1, 1,
+                                        ctypes.byref(r), ctypes.c_void_p(0x1000), 1 << 30,
+                                        None) == ms.MS_ERR_UNSUPPORTED
+    r65 = ms.MsOpts(0, 65, 0, 0, 0, 0, 0, 0)
+    assert ms._lib.ms_batch_workspace_size(1, (ms.MsProblem * 1)(P), 1, 1, ctypes.byref(r65)) == 0
     bad = ms.MsOpts(0, 0, 0, 0, 30, 0, 0, 0)
     assert ms._lib.ms_batch_workspace_size(1, (ms.MsProblem * 1)(P), 1, 1, ctypes.byref(bad)) == 0
     assert ms._lib.sketch_lstsq_batched(0, arr, arr, 1, 1, None, ctypes.c_void_p(0x1000), 1 << 30,

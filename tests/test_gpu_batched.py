@@ -116,3 +116,94 @@ def test_batched_replay_larger_than_capacity_is_refused(ms):
     runner.launch()
     st, per = runner.status()
     assert st == ms.MS_ERR_NOMEM and per == [ms.MS_ERR_NOMEM] * 2
+
+
+def make_scaled_problem(ms, d, n, nrhs, seed, gd="bf16", decades=4.0):
+    """FP32 A = Z diag(logspace(0, -decades, n)), BF16 (or FP32) Gaussian stage."""
+    k, k2 = 2 * n * n, 2 * n
+    Z = synth.normal_matrix(d, n, seed=seed, dtype=np.float64)
+    A = np.asfortranarray((Z * np.logspace(0, -decades, n)[None, :]).astype(np.float32))
+    B, _ = synth.lstsq_rhs(A, nrhs, seed=seed)
+    h = synth.bucket_map(d, k, seed=seed)
+    s = synth.signs(d, seed=seed)
+    G = synth.gaussian_sketch(k2, k, seed=seed, dtype=gd)
+    host = dict(A=A, B=B, h=h, s=s, G=G, k=k)
+    dev = dict(A=to_dev(A), B=to_dev(B), h=to_dev(h), s=to_dev(s),
+               G=bf16_dev(G) if gd == "bf16" else to_dev(G), k=k,
+               X=ms.empty_colmajor(n, nrhs, torch.float64, "cuda"))
+    return host, dev
+
+
+REFINE_SHAPES = [(1 << 17, 8, 1), (100003, 16, 4), (1 << 16, 32, 8)]
+
+
+@pytest.mark.parametrize("refine", [0, 1, 3])
+def test_batched_bf16_refinement(ms, orc, refine):
+    # Mixed precision in one batched call: FP32 CountSketch, BF16 Gaussian
+    # stage, FP64 QR, then FP64-residual refinement steps per problem.  Each
+    # X is compared with the FP64 sketch-and-solve solution for the same
+    # (h, s, G) (oracle) and with the single-problem path at the same step
+    # count.  The error bound per step count is the one the single-problem
+    # path meets (each step contracts the BF16 error by about u_bf16 times
+    # the conditioning of the column-scaled sketch).
+    probs = [make_scaled_problem(ms, d, n, r, seed=800 + i)
+             for i, (d, n, r) in enumerate(REFINE_SHAPES)]
+    runner = ms.sketch_lstsq_batched([p[1] for p in probs], refine_steps=refine)
+    st, per = runner.status()
+    assert st == ms.MS_OK and all(v == ms.MS_OK for v in per)
+    bound = {0: 5.0, 1: 1e-2, 3: 1e-5}[refine]
+    for (host, dev), shape in zip(probs, REFINE_SHAPES):
+        Xb = to_host(dev["X"])
+        A64, B64 = host["A"].astype(np.float64), host["B"].astype(np.float64)
+        X64, _, _ = orc.sketch_lstsq(A64, B64, host["h"], host["s"],
+                                     host["G"].astype(np.float64), host["k"])
+        err = rel(Xb, X64)
+        Xa, ws = ms.sketch_lstsq(dev["A"], dev["B"], dev["h"], dev["s"], dev["G"], host["k"],
+                                 refine_steps=refine)
+        ms.check_status(ws)
+        ea = rel(to_host(Xa), X64)
+        print(shape, "refine=%d batched %.3e alone %.3e" % (refine, err, ea))
+        assert np.isfinite(Xb).all() and err <= bound, (shape, err)
+        if refine == 3:
+            assert rel(Xb, to_host(Xa)) <= 2 * bound
+
+
+def test_batched_fp64_refinement_keeps_parity(ms, orc):
+    # FP64 throughout: the first pass already is the sketch-and-solve
+    # solution to rounding, so refinement steps leave it within 1e-12.
+    shapes = [(20000, 8, 2), (30001, 16, 1)]
+    probs = [make_problem(ms, d, n, r, seed=900 + i) for i, (d, n, r) in enumerate(shapes)]
+    runner = ms.sketch_lstsq_batched([p[1] for p in probs], refine_steps=2)
+    st, per = runner.status()
+    assert st == ms.MS_OK
+    for host, dev in probs:
+        Xr, _, _ = orc.sketch_lstsq(host["A"], host["B"], host["h"], host["s"], host["G"], host["k"])
+        assert rel(to_host(dev["X"]), Xr) <= 1e-12
+
+
+def test_batched_refinement_graph_replay(ms, orc):
+    # the refinement launches are captured with the rest; replays with new
+    # descriptors (same count, no larger) reproduce the eager results
+    set1 = [make_scaled_problem(ms, d, n, r, seed=1000 + i)
+            for i, (d, n, r) in enumerate([(40000, 8, 2), (30000, 16, 1)])]
+    set2 = [make_scaled_problem(ms, d, n, r, seed=1100 + i)
+            for i, (d, n, r) in enumerate([(35000, 8, 2), (20000, 16, 1)])]
+    eager = {}
+    for name, which in (("1", set1), ("2", set2)):
+        r = ms.sketch_lstsq_batched([p[1] for p in which], refine_steps=2)
+        assert r.status()[0] == ms.MS_OK
+        eager[name] = [to_host(p[1]["X"]).copy() for p in which]
+    runner = ms.BatchRunner([p[1] for p in set1], refine_steps=2)
+    runner.capture()
+    for rep in range(3):
+        for name, which in (("1", set1), ("2", set2)):
+            runner.set_problems([p[1] for p in which])
+            for _, dev in which:
+                dev["X"].fill_(float("nan"))
+            runner.replay()
+            torch.cuda.synchronize()
+            torch.ones(1024, device="cuda").sum().item()
+            st, per = runner.status()
+            assert st == ms.MS_OK, (rep, st, per)
+            for (host, dev), Xe in zip(which, eager[name]):
+                assert rel(to_host(dev["X"]), Xe) <= 1e-6, (rep, name)
