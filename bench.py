@@ -57,10 +57,14 @@ def parse():
                     help="problems of the batched mixed-precision vs plain FP64 leg (0 skips it)")
     ap.add_argument("--refine", type=int, default=2,
                     help="FP64-residual refinement steps of the mixed-precision legs")
-    ap.add_argument("--only", default=None, choices=["countsketch", "copy"],
+    ap.add_argument("--only", default=None,
+                    choices=["countsketch", "copy", "gaussian_f64", "gaussian_bf16"],
                     help="profiling runs: launch only the LDS CountSketch of [A | b] (--steps "
-                         "times) or only a plain device copy of 1 GiB (calibrates the "
-                         "FETCH_SIZE / WRITE_SIZE counters); prints a short JSON line")
+                         "times), only a plain device copy of 1 GiB (calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters), or only the Gaussian stage of the "
+                         "FP64 workload (128 x 8192 times 8192 x 65) or of the mixed-precision "
+                         "workload (BF16 512 x 131,072 times 131,072 x 260); prints a short "
+                         "JSON line")
     return ap.parse_args()
 
 
@@ -245,6 +249,27 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"only": "copy", "bytes_read_per_launch": nbytes,
                           "bytes_written_per_launch": nbytes, "launches": args.steps}))
+        return
+    if args.only in ("gaussian_f64", "gaussian_bf16"):
+        # Gaussian stage alone on device-generated inputs of the workload's shape
+        bf = args.only == "gaussian_bf16"
+        k2_, k_, nc_ = (512, 131072, 260) if bf else (128, 8192, 65)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(args.seed)
+        G32 = torch.randn((k_, k2_), generator=gen, device=dev, dtype=torch.float64).t()
+        G32.mul_(1.0 / math.sqrt(k2_))
+        Gx = ms.empty_colmajor(k2_, k_, torch.bfloat16 if bf else torch.float64, dev)
+        Gx.copy_(G32)
+        Yx = ms.empty_colmajor(k_, nc_, torch.float32 if bf else torch.float64, dev)
+        Yx.copy_(torch.randn((nc_, k_), generator=gen, device=dev, dtype=torch.float64).t())
+        del G32
+        Zx, gws_ = ms.gaussian_apply(Gx, Yx)
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            ms.gaussian_apply(Gx, Yx, Z=Zx, ws=gws_)
+        torch.cuda.synchronize()
+        print(json.dumps({"only": args.only, "k2": k2_, "k": k_, "ncols": nc_,
+                          "flops_per_call": 2 * k2_ * k_ * nc_, "launches": args.steps}))
         return
     d, n, nrhs, k, k2 = 4194304, 64, 1, 8192, 128
     nc = n + nrhs

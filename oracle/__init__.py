@@ -323,3 +323,30 @@ def round_bf16(x) -> np.ndarray:
     out = np.empty_like(flat)
     lib.or_round_bf16_array(flat.shape[0], _ptr(flat), _ptr(out))
     return out.reshape(x.shape, order=order)
+
+
+def lstsq_tsqr(A, B, block_rows: int = 1 << 18):
+    """The FP64 least-squares optimum of min ||B - A X|| for tall A that need
+    not fit in memory twice: Householder QR of [A | B] taken over blocks of
+    rows (each block stacked under the running triangular factor and
+    re-factored, LAPACK's QR as the step), giving
+        [A | B] = Q [[R11, R12], [0, R22]],  X = R11^{-1} R12,
+        ||B[:, j] - A X[:, j]|| = ||R22[:, j]||.
+    A is promoted to FP64 block by block.  Returns (X, residual norms)."""
+    A = np.asarray(A)
+    B = np.asarray(B)
+    if B.ndim == 1:
+        B = B[:, None]
+    d, n = A.shape
+    nrhs = B.shape[1]
+    R = np.zeros((0, n + nrhs))
+    for r0 in range(0, d, block_rows):
+        blk = np.empty((min(d, r0 + block_rows) - r0, n + nrhs))
+        blk[:, :n] = A[r0:r0 + block_rows]
+        blk[:, n:] = B[r0:r0 + block_rows]
+        R = np.linalg.qr(np.vstack([R, blk]), mode="r")
+    R11, R12 = R[:n, :n], R[:n, n:]
+    R22 = R[n:, n:]
+    X = np.linalg.solve(np.triu(R11), R12) if n else np.zeros((0, nrhs))
+    res = np.array([np.linalg.norm(R22[:, j]) for j in range(nrhs)])
+    return X, res

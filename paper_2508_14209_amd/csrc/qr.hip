@@ -120,9 +120,10 @@ __global__ __launch_bounds__(1024) void k_qr_solve(int m, int n, int nrhs, const
 }
 
 // ------------------------------------------------------------------ register-resident QR
-// Wave-wide sum with DPP row operations (quad swaps, half-row and row
-// mirrors) and four lane reads, one per 16-lane row.  Every lane gets the
-// same value.
+// Wave-wide sum with DPP: quad swaps, half-row and row mirrors give every
+// lane its 16-lane row sum, two row broadcasts (lane 15 into rows 1 and 3,
+// lane 31 into rows 2 and 3) leave the total in lane 63, and one lane read
+// (a pair, for the two halves of the double) hands it to every lane.
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
   const long long u = __double_as_longlong(v);

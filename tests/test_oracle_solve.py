@@ -231,3 +231,25 @@ def test_round_bf16_definition(orc):
     x = synth.normal_matrix(1000, 1, seed=14, dtype=np.float32)[:, 0]
     assert np.array_equal(orc.round_bf16(x), synth.to_bf16_values(x))
     assert np.all(np.abs(orc.round_bf16(x) - x) <= np.abs(x) * 2.0 ** -8)
+
+
+def test_lstsq_tsqr_matches_lapack_and_exact_cases(orc):
+    # the blocked QR optimum equals LAPACK's least squares (SVD driver) on a
+    # problem split over several row blocks, including a ragged last block
+    rng = np.random.default_rng(5)
+    d, n, nrhs = 1000, 7, 3
+    A = rng.standard_normal((d, n)) * np.logspace(0, -3, n)
+    B = rng.standard_normal((d, nrhs))
+    X, res = orc.lstsq_tsqr(A, B, block_rows=96)
+    Xl, _, _, _ = np.linalg.lstsq(A, B, rcond=None)
+    assert np.allclose(X, Xl, rtol=1e-10, atol=1e-12)
+    assert np.allclose(res, np.linalg.norm(B - A @ Xl, axis=0), rtol=1e-10)
+    # consistent system: zero residual, exact solution
+    xs = rng.standard_normal((n, 1))
+    X2, res2 = orc.lstsq_tsqr(A, A @ xs, block_rows=128)
+    assert np.allclose(X2, xs, rtol=1e-9) and res2[0] <= 1e-10 * np.linalg.norm(A @ xs)
+    # b orthogonal to range(A): x = 0 and the residual is ||b||
+    q, _ = np.linalg.qr(np.hstack([A, rng.standard_normal((d, 1))]))
+    b = q[:, -1:]
+    X3, res3 = orc.lstsq_tsqr(A, b, block_rows=300)
+    assert np.abs(X3).max() <= 1e-10 and abs(res3[0] - 1.0) <= 1e-12
