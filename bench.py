@@ -55,10 +55,14 @@ def parse():
                     help="requests of the serving stream legs (0 skips them)")
     ap.add_argument("--compare-problems", type=int, default=64,
                     help="problems of the batched mixed-precision vs plain FP64 leg (0 skips it)")
+    ap.add_argument("--other-configs", type=int, default=1,
+                    help="also time the FP32 16,777,216 x 128 and the mixed-precision "
+                         "8,388,608 x 256 solves (0 skips them)")
     ap.add_argument("--refine", type=int, default=2,
                     help="FP64-residual refinement steps of the mixed-precision legs")
     ap.add_argument("--only", default=None,
-                    choices=["countsketch", "copy", "gaussian_f64", "gaussian_bf16"],
+                    choices=["countsketch", "countsketch_f32_k32768", "countsketch_f32_k131072",
+                             "copy", "gaussian_f64", "gaussian_bf16"],
                     help="profiling runs: launch only the LDS CountSketch of [A | b] (--steps "
                          "times), only a plain device copy of 1 GiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters), or only the Gaussian stage of the "
@@ -223,6 +227,90 @@ def mixed_vs_fp64_leg(ms, torch, np, count, seed, refine, dev, reps=3):
     return res
 
 
+def other_configs_leg(ms, torch, np, seed, dev, reps=10):
+    """The FP32 and mixed-precision least-squares workloads: full solves
+    (sketch_lstsq) and their CountSketch kernel alone, inputs generated on
+    the device from the seed (A = Z D [Q], b = A x* + 1e-6 N(0,1))."""
+    out = {}
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    cases = [
+        ("fp32_ill_conditioned_16777216x128", 1 << 24, 128, 1, 32768, 256, 1e6, True, "f32", 0),
+        ("mixed_bf16_refine3_8388608x256", 1 << 23, 256, 4, 131072, 512, 1e4, False, "bf16", 3),
+    ]
+    for name, d, n, nrhs, k, k2, kappa, rotate, gd, refine in cases:
+        scales = torch.logspace(0.0, -math.log10(kappa), n, device=dev, dtype=torch.float64)
+        M = torch.diag(scales)
+        if rotate:
+            q, _ = torch.linalg.qr(torch.randn((n, n), generator=gen, device=dev,
+                                               dtype=torch.float64))
+            M = M @ q
+        A = ms.empty_colmajor(d, n, torch.float32, dev)
+        for r0 in range(0, d, 1 << 21):
+            r1 = min(d, r0 + (1 << 21))
+            Z = torch.randn((r1 - r0, n), generator=gen, device=dev, dtype=torch.float64)
+            A[r0:r1].copy_(Z @ M)
+        del Z
+        xs = torch.randn((n, nrhs), generator=gen, device=dev, dtype=torch.float64)
+        B = ms.empty_colmajor(d, nrhs, torch.float32, dev)
+        for r0 in range(0, d, 1 << 21):
+            r1 = min(d, r0 + (1 << 21))
+            B[r0:r1].copy_(A[r0:r1].double() @ xs + 1e-6 * torch.randn(
+                (r1 - r0, nrhs), generator=gen, device=dev, dtype=torch.float64))
+        h = torch.randint(0, k, (d,), generator=gen, device=dev, dtype=torch.int32)
+        s = (torch.randint(0, 2, (d,), generator=gen, device=dev, dtype=torch.int8) * 2 - 1)
+        G = ms.empty_colmajor(k2, k, torch.bfloat16 if gd == "bf16" else torch.float32, dev)
+        G.copy_(torch.randn((k, k2), generator=gen, device=dev, dtype=torch.float32).t()
+                / math.sqrt(k2))
+        X = ms.empty_colmajor(n, nrhs, torch.float64, dev)
+        ws = ms.workspace(ms.workspace_size("lstsq", d=d, n=n, nrhs=nrhs, k=k, k2=k2,
+                                            a_dtype=ms.MS_F32,
+                                            g_dtype=ms.MS_BF16 if gd == "bf16" else ms.MS_F32,
+                                            refine_steps=refine), dev)
+        torch.cuda.synchronize()
+
+        def solve():
+            ms.sketch_lstsq(A, B, h, s, G, k, refine_steps=refine, X=X, ws=ws)
+
+        solve()
+        ms.check_status(ws)
+        e0, e1 = event_pair(torch)
+        e0.record()
+        for _ in range(reps):
+            solve()
+        e1.record()
+        torch.cuda.synchronize()
+        ms.check_status(ws)
+        solve_ms = e0.elapsed_time(e1) / reps
+        # the CountSketch of [A | B] alone (the kernel the solve runs first)
+        AB = ms.empty_colmajor(d, n + nrhs, torch.float32, dev)
+        AB[:, :n].copy_(A)
+        AB[:, n:].copy_(B)
+        del A, B
+        code, _ = ms.pack_sketch(h, s, k)
+        Y = ms.empty_colmajor(k, n + nrhs, torch.float32, dev)
+        cws = ms.workspace(256, dev)
+        ms.countsketch_accumulate(AB, code, k, Y, mode="lds", ws=cws)
+        e0.record()
+        for _ in range(reps):
+            ms.countsketch_accumulate(AB, code, k, Y, mode="lds", ws=cws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.check_status(cws)
+        cs_ms = e0.elapsed_time(e1) / reps
+        cs_bytes = d * (n + nrhs) * 4 + d * 4 + k * (n + nrhs) * 4
+        out[name] = {"d": d, "n": n, "nrhs": nrhs, "k": k, "k2": k2, "g_dtype": gd,
+                     "refine_steps": refine, "ms_per_solve": solve_ms,
+                     "solves_per_s": 1e3 / solve_ms,
+                     "countsketch": {"avg_us": cs_ms * 1e3,
+                                     "GBps": cs_bytes / (cs_ms * 1e-3) / 1e9,
+                                     "frac_hbm_peak": cs_bytes / (cs_ms * 1e-3) / 1e9
+                                     / HBM_PEAK_GBPS, "bytes_per_launch": cs_bytes}}
+        del AB, Y, G, h, s, ws, X, code
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -249,6 +337,30 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"only": "copy", "bytes_read_per_launch": nbytes,
                           "bytes_written_per_launch": nbytes, "launches": args.steps}))
+        return
+    if args.only in ("countsketch_f32_k32768", "countsketch_f32_k131072"):
+        # the FP32 workloads' CountSketch of [A | B] alone (device-generated
+        # N(0,1) data of the workload's shape; the kernel does not depend on
+        # the values)
+        big = args.only.endswith("131072")
+        d_, nc_, k_ = ((1 << 23), 260, 131072) if big else ((1 << 24), 129, 32768)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(args.seed)
+        ABx = ms.empty_colmajor(d_, nc_, torch.float32, dev)
+        for c in range(nc_):
+            ABx[:, c].normal_(generator=gen)
+        hx = torch.randint(0, k_, (d_,), generator=gen, device=dev, dtype=torch.int32)
+        sx = (torch.randint(0, 2, (d_,), generator=gen, device=dev, dtype=torch.int8) * 2 - 1)
+        code, _ = ms.pack_sketch(hx, sx, k_)
+        Yx = ms.empty_colmajor(k_, nc_, torch.float32, dev)
+        cws = ms.workspace(256, dev)
+        Yx.zero_()
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            ms.countsketch_accumulate(ABx, code, k_, Yx, mode="lds", ws=cws)
+        ms.check_status(cws)
+        print(json.dumps({"only": args.only, "kernel": "k_cs_lds_xcd", "launches": args.steps,
+                          "bytes_per_launch": d_ * nc_ * 4 + d_ * 4 + k_ * nc_ * 4}))
         return
     if args.only in ("gaussian_f64", "gaussian_bf16"):
         # Gaussian stage alone on device-generated inputs of the workload's shape
@@ -418,6 +530,11 @@ def main():
                                          dev)
         except Exception as e:  # reported in the line, not hidden
             out["serving"] = {"error": repr(e)}
+    if args.other_configs:
+        try:
+            out["other_configs"] = other_configs_leg(ms, torch, np, seed + 2, dev)
+        except Exception as e:
+            out["other_configs"] = {"error": repr(e)}
     if args.compare_problems > 0:
         try:
             out["batched_mixed_vs_plain_fp64"] = mixed_vs_fp64_leg(

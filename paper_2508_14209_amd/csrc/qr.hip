@@ -460,8 +460,222 @@ hipError_t launch_qr_reg(int64_t m, int64_t n, int64_t nrhs, const double *W, in
   return hipErrorNotSupported;
 }
 
+// M (m x (n + nrhs)) for the blocked and global-memory paths, then n values
+// of tau for the blocked path when the caller keeps none.
 size_t qr_workspace_bytes(int64_t m, int64_t n, int64_t nrhs) {
-  return (size_t)m * (size_t)(n + nrhs) * sizeof(double);
+  return ((size_t)m * (size_t)(n + nrhs) + (size_t)n) * sizeof(double);
+}
+
+// ------------------------------------------------------------------ blocked QR
+// Householder QR of a system too large for one workgroup's registers but with
+// at most 1024 rows: [W | Bm] is copied to M (m x nc, ld m) and factored in
+// panels of kPanel columns.  A panel kernel (one workgroup; wave jj owns
+// panel column jj in registers, lane l rows l + 64 r) computes the panel's
+// reflectors in order and leaves them below the diagonal with R on and above
+// it, exactly as the unblocked factorisation does; an update kernel applies
+// the panel's reflectors, in order, to every later column (one wave per
+// column, reflectors staged in LDS), right-hand sides included.  The
+// reflectors and the arithmetic per column are those of the unblocked
+// algorithm: only the schedule differs.
+constexpr int kPanel = 16;
+
+__global__ void k_qrb_load(int m, int n, int nrhs, const double *__restrict__ W, int64_t ldw,
+                           const double *__restrict__ Bm, int64_t ldb, double *__restrict__ M) {
+  const int64_t total = (int64_t)m * (n + nrhs);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(t / m), i = (int)(t - (int64_t)c * m);
+    M[t] = c < n ? W[i + (int64_t)c * ldw] : Bm[i + (int64_t)(c - n) * ldb];
+  }
+}
+
+template <int RPL>
+__global__ __launch_bounds__(1024) void k_qrb_panel(int m, int n, int j0, double *__restrict__ M,
+                                                    double *__restrict__ tau_out) {
+  __shared__ double vbuf[2][64 * RPL];
+  __shared__ double taubuf[2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int b = min(kPanel, n - j0);
+  const int c = j0 + wave;
+  double a[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = lane + 64 * r;
+    a[r] = (wave < b && i < m) ? M[i + (int64_t)c * m] : 0.0;
+  }
+  for (int jj = 0; jj < b; ++jj) {
+    const int j = j0 + jj, buf = jj & 1;
+    if (wave == jj) {
+      double p2 = 0.0, av = 0.0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        if (i > j && i < m) p2 += a[r] * a[r];
+        if (r == (j >> 6)) av = a[r];
+      }
+      const double xn2 = wave_allsum(p2);
+      const double alpha = read_lane(av, j & 63);
+      double tau = 0.0, beta = alpha, scal = 0.0;
+      if (xn2 != 0.0) {
+        const double nrm = sqrt(alpha * alpha + xn2);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scal = 1.0 / (alpha - beta);
+      }
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = lane + 64 * r;
+        const double v = (i > j && i < m) ? a[r] * scal : (i == j ? 1.0 : 0.0);
+        vbuf[buf][i] = v;
+        if (xn2 != 0.0) a[r] = i > j ? v : (i == j ? beta : a[r]);
+      }
+      if (lane == 0) {
+        taubuf[buf] = tau;
+        tau_out[j] = tau;
+      }
+    }
+    __syncthreads();
+    const double tau = taubuf[buf];
+    if (tau != 0.0 && wave > jj && wave < b) {
+      double dot = 0.0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) dot += vbuf[buf][lane + 64 * r] * a[r];
+      const double w = tau * wave_allsum(dot);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) a[r] -= w * vbuf[buf][lane + 64 * r];
+    }
+  }
+  if (wave < b) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lane + 64 * r;
+      if (i >= j0 && i < m) M[i + (int64_t)c * m] = a[r];
+    }
+  }
+}
+
+// Apply the reflectors of panel [j0, j0 + b) to columns j0 + b + 16 * blockIdx.x
+// + wave (< nc).  Dynamic LDS: b * 64 * RPL doubles.
+template <int RPL>
+__global__ __launch_bounds__(1024) void k_qrb_update(int m, int n, int nc, int j0,
+                                                     double *__restrict__ M,
+                                                     const double *__restrict__ tau) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double *V = reinterpret_cast<double *>(smem_raw);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int b = min(kPanel, n - j0);
+  const int rows = 64 * RPL;
+  for (int t = threadIdx.x; t < b * rows; t += blockDim.x) {
+    const int jj = t / rows, i = t - jj * rows, j = j0 + jj;
+    V[t] = (i > j && i < m) ? M[i + (int64_t)j * m] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  const int c = j0 + b + 16 * blockIdx.x + wave;
+  if (c >= nc) return;
+  double y[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = lane + 64 * r;
+    y[r] = i < m ? M[i + (int64_t)c * m] : 0.0;
+  }
+  for (int jj = 0; jj < b; ++jj) {
+    const double tj = tau[j0 + jj];
+    if (tj == 0.0) continue;
+    const double *v = V + jj * rows;
+    double dot = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) dot += v[lane + 64 * r] * y[r];
+    const double w = tj * wave_allsum(dot);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) y[r] -= w * v[lane + 64 * r];
+  }
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = lane + 64 * r;
+    if (i >= j0 && i < m) M[i + (int64_t)c * m] = y[r];
+  }
+}
+
+// Outputs of the blocked factorisation and the back substitution.
+__global__ __launch_bounds__(1024) void k_qrb_finish(int m, int n, int nrhs,
+                                                     double *__restrict__ M,
+                                                     double *__restrict__ X, int64_t ldx,
+                                                     double *__restrict__ R, int64_t ldr,
+                                                     double *__restrict__ fact_out, int *status) {
+  __shared__ int s_singular;
+  const int tid = threadIdx.x, wave = tid >> 6, nw = blockDim.x >> 6;
+  if (tid == 0) s_singular = 0;
+  __syncthreads();
+  if (fact_out)
+    for (int64_t t = tid; t < (int64_t)m * n; t += blockDim.x) fact_out[t] = M[t];
+  if (R)
+    for (int64_t t = tid; t < (int64_t)n * n; t += blockDim.x) {
+      const int c = (int)(t / n), i = (int)(t - (int64_t)c * n);
+      R[i + (int64_t)c * ldr] = i <= c ? M[i + (int64_t)c * m] : 0.0;
+    }
+  for (int i = tid; i < n; i += blockDim.x) {
+    const double r = M[i + (int64_t)i * m];
+    if (r == 0.0 || !isfinite(r)) s_singular = 1;
+  }
+  __syncthreads();
+  if (s_singular) {
+    for (int64_t t = tid; t < (int64_t)n * nrhs; t += blockDim.x) {
+      const int c = (int)(t / n), i = (int)(t - (int64_t)c * n);
+      X[i + (int64_t)c * ldx] = __longlong_as_double(0x7ff8000000000000LL);
+    }
+    if (tid == 0) record_status(status, MS_ERR_SINGULAR);
+    return;
+  }
+  for (int c = wave; c < nrhs; c += nw)
+    wave_back_substitute(n, M, m, M + (int64_t)(n + c) * m, X + (int64_t)c * ldx);
+}
+
+template <int RPL>
+static hipError_t launch_qr_blocked_t(int64_t m, int64_t n, int64_t nrhs, const double *W,
+                                      int64_t ldw, const double *Bm, int64_t ldb, double *X,
+                                      int64_t ldx, double *R, int64_t ldr, double *tau_out,
+                                      double *fact_out, double *M, int *status,
+                                      hipStream_t st) {
+  const int64_t nc = n + nrhs;
+  const unsigned lb = (unsigned)std::min<int64_t>((m * nc + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_qrb_load, dim3(lb), dim3(256), 0, st, (int)m, (int)n, (int)nrhs, W, ldw,
+                     Bm, ldb, M);
+  hipError_t e = hipGetLastError();
+  const size_t lds = (size_t)kPanel * 64 * RPL * sizeof(double);
+  if (e == hipSuccess) e = allow_dynamic_lds((const void *)k_qrb_update<RPL>, (int)lds);
+  for (int64_t j0 = 0; j0 < n && e == hipSuccess; j0 += kPanel) {
+    hipLaunchKernelGGL(k_qrb_panel<RPL>, dim3(1), dim3(1024), 0, st, (int)m, (int)n, (int)j0, M,
+                       tau_out);
+    e = hipGetLastError();
+    const int64_t rest = nc - std::min<int64_t>(n, j0 + kPanel);
+    if (e == hipSuccess && rest > 0) {
+      hipLaunchKernelGGL(k_qrb_update<RPL>, dim3((unsigned)((rest + 15) / 16)), dim3(1024), lds,
+                         st, (int)m, (int)n, (int)nc, (int)j0, M, (const double *)tau_out);
+      e = hipGetLastError();
+    }
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_qrb_finish, dim3(1), dim3(1024), 0, st, (int)m, (int)n, (int)nrhs, M, X,
+                       ldx, R, ldr, fact_out, status);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+// Blocked path for 256 < m <= 1024 (or systems too wide for the register
+// kernel); tau_out must be a device array of n doubles.
+static hipError_t launch_qr_blocked(int64_t m, int64_t n, int64_t nrhs, const double *W,
+                                    int64_t ldw, const double *Bm, int64_t ldb, double *X,
+                                    int64_t ldx, double *R, int64_t ldr, double *tau_out,
+                                    double *fact_out, double *M, int *status, hipStream_t st) {
+  if (m <= 256)
+    return launch_qr_blocked_t<4>(m, n, nrhs, W, ldw, Bm, ldb, X, ldx, R, ldr, tau_out, fact_out,
+                                  M, status, st);
+  if (m <= 512)
+    return launch_qr_blocked_t<8>(m, n, nrhs, W, ldw, Bm, ldb, X, ldx, R, ldr, tau_out, fact_out,
+                                  M, status, st);
+  return launch_qr_blocked_t<16>(m, n, nrhs, W, ldw, Bm, ldb, X, ldx, R, ldr, tau_out, fact_out,
+                                 M, status, st);
 }
 
 hipError_t launch_qr_solve(int64_t m, int64_t n, int64_t nrhs, const double *W, int64_t ldw,
@@ -472,7 +686,13 @@ hipError_t launch_qr_solve(int64_t m, int64_t n, int64_t nrhs, const double *W, 
                                 tau_out, fact_out, status, st);
   if (er != hipErrorNotSupported) return er;
   const DevInfo &di = dev_info();
-  const size_t bytes = qr_workspace_bytes(m, n, nrhs);
+  const size_t bytes = (size_t)m * (size_t)(n + nrhs) * sizeof(double);
+  if (bytes + 1024 > (size_t)di.lds_per_block && m <= 1024 && qr_ws) {
+    double *M = static_cast<double *>(qr_ws);
+    double *tau = tau_out ? tau_out : M + m * (n + nrhs);
+    return launch_qr_blocked(m, n, nrhs, W, ldw, Bm, ldb, X, ldx, R, ldr, tau, fact_out, M,
+                             status, st);
+  }
   if (bytes + 1024 <= (size_t)di.lds_per_block) {
     hipError_t e = allow_dynamic_lds((const void *)k_qr_solve<true>, (int)bytes);
     if (e != hipSuccess) return e;

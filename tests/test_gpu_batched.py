@@ -141,17 +141,18 @@ REFINE_SHAPES = [(1 << 17, 8, 1), (100003, 16, 4), (1 << 16, 32, 8)]
 def test_batched_bf16_refinement(ms, orc, refine):
     # Mixed precision in one batched call: FP32 CountSketch, BF16 Gaussian
     # stage, FP64 QR, then FP64-residual refinement steps per problem.  Each
-    # X is compared with the FP64 sketch-and-solve solution for the same
-    # (h, s, G) (oracle) and with the single-problem path at the same step
-    # count.  The error bound per step count is the one the single-problem
-    # path meets (each step contracts the BF16 error by about u_bf16 times
-    # the conditioning of the column-scaled sketch).
+    # X's error against the FP64 sketch-and-solve solution for the same
+    # (h, s, G) (oracle) must equal, to association-order effects, the error
+    # of the single-problem path at the same step count (whose contraction is
+    # pinned against the oracle's own iteration elsewhere); and three steps
+    # must have removed the BF16 error (O(1) without refinement; each step
+    # contracts it by about u_bf16 times the conditioning of the
+    # column-equilibrated sketch, ~1e-2 for k2 = 2n).
     probs = [make_scaled_problem(ms, d, n, r, seed=800 + i)
              for i, (d, n, r) in enumerate(REFINE_SHAPES)]
     runner = ms.sketch_lstsq_batched([p[1] for p in probs], refine_steps=refine)
     st, per = runner.status()
     assert st == ms.MS_OK and all(v == ms.MS_OK for v in per)
-    bound = {0: 5.0, 1: 1e-2, 3: 1e-5}[refine]
     for (host, dev), shape in zip(probs, REFINE_SHAPES):
         Xb = to_host(dev["X"])
         A64, B64 = host["A"].astype(np.float64), host["B"].astype(np.float64)
@@ -163,9 +164,10 @@ def test_batched_bf16_refinement(ms, orc, refine):
         ms.check_status(ws)
         ea = rel(to_host(Xa), X64)
         print(shape, "refine=%d batched %.3e alone %.3e" % (refine, err, ea))
-        assert np.isfinite(Xb).all() and err <= bound, (shape, err)
+        assert np.isfinite(Xb).all() and err <= 5.0, (shape, err)
+        assert err <= 1.2 * ea + 1e-7, (shape, err, ea)
         if refine == 3:
-            assert rel(Xb, to_host(Xa)) <= 2 * bound
+            assert err <= 1e-4, (shape, err)
 
 
 def test_batched_fp64_refinement_keeps_parity(ms, orc):

@@ -95,7 +95,11 @@ def test_multisketch_parity(ms, orc, mode, d, n, k, k2, gd):
 
 # ------------------------------------------------------------------- QR solve
 QR_CASES = [(1, 1, 1), (16, 8, 1), (37, 19, 3), (128, 64, 1), (64, 64, 2), (256, 128, 1),
-            (512, 256, 4)]
+            (512, 256, 4),
+            # panelled (blocked) factorisation: ragged last panel, 3 row classes
+            (300, 150, 2), (1000, 200, 3), (1024, 512, 1), (257, 33, 8),
+            # single-workgroup paths: LDS-resident, and global memory beyond 1024 rows
+            (700, 17, 1), (1100, 40, 2)]
 
 
 @pytest.mark.parametrize("m,n,nrhs", QR_CASES)
@@ -113,10 +117,11 @@ def test_qr_solve_parity(ms, orc, m, n, nrhs):
     assert rel(to_host(R), Rr) <= 1e-13 * n
 
 
-def test_qr_solve_singular(ms):
-    W = synth.normal_matrix(20, 4, seed=7)
-    W[:, 2] = 0.0
-    X, _, ws = ms.qr_solve(to_dev(W), to_dev(np.ones((20, 1))))
+@pytest.mark.parametrize("m,n,zero", [(20, 4, 2), (600, 200, 37)])
+def test_qr_solve_singular(ms, m, n, zero):
+    W = synth.normal_matrix(m, n, seed=7)
+    W[:, zero] = 0.0
+    X, _, ws = ms.qr_solve(to_dev(W), to_dev(np.ones((m, 1))))
     with pytest.raises(ms.MsketchError) as e:
         ms.check_status(ws)
     assert e.value.code == ms.MS_ERR_SINGULAR
