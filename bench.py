@@ -62,7 +62,7 @@ def parse():
                     help="FP64-residual refinement steps of the mixed-precision legs")
     ap.add_argument("--only", default=None,
                     choices=["countsketch", "countsketch_f32_k32768", "countsketch_f32_k131072",
-                             "copy", "gaussian_f64", "gaussian_bf16"],
+                             "copy", "gaussian_f64", "gaussian_bf16", "batched_mixed"],
                     help="profiling runs: launch only the LDS CountSketch of [A | b] (--steps "
                          "times), only a plain device copy of 1 GiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters), or only the Gaussian stage of the "
@@ -139,17 +139,12 @@ def serving_leg(ms, torch, np, count, seed, refine, dev):
     return out
 
 
-def mixed_vs_fp64_leg(ms, torch, np, count, seed, refine, dev, reps=3):
-    """The same batch of serving-stream problems solved (a) one by one by the
-    plain FP64 multisketch path (A and G promoted exactly to FP64), (b) in
-    one batched FP64 call, (c) in one batched mixed-precision call (FP32
-    CountSketch, BF16 Gaussian stage, FP64 QR and `refine` FP64-residual
-    refinement steps) and (d) the same without refinement; solves/s of each
-    and the residual ratio ||b - A x|| / ||b - A x_opt|| against the FP64 QR
-    optimum x_opt (library QR in FP64 on the device, measurement only)."""
+def compare_problems(ms, torch, count, seed, dev):
+    """A batch of serving-stream problems on the device, twice: FP64 A, B and
+    G (the BF16 values promoted exactly) and FP32 A, B with BF16 G."""
     from paper_2508_14209_amd import serve
     reqs = serve.make_requests(count, 0.0, seed=seed)
-    p32, p64, pbf = [], [], []
+    p64, pbf = [], []
     for r in reqs:
         t = serve.generate(r, dev, "f32")
         d, n, nrhs, k, k2 = r.d, r.n, r.nrhs, r.k, r.k2
@@ -166,7 +161,18 @@ def mixed_vs_fp64_leg(ms, torch, np, count, seed, refine, dev, reps=3):
                         **common))
         pbf.append(dict(A=t["A"], B=t["B"], G=Gb, X=ms.empty_colmajor(n, nrhs, torch.float64, dev),
                         **common))
-        p32.append(pbf[-1])
+    return p64, pbf
+
+
+def mixed_vs_fp64_leg(ms, torch, np, count, seed, refine, dev, reps=3):
+    """The same batch of serving-stream problems solved (a) one by one by the
+    plain FP64 multisketch path (A and G promoted exactly to FP64), (b) in
+    one batched FP64 call, (c) in one batched mixed-precision call (FP32
+    CountSketch, BF16 Gaussian stage, FP64 QR and `refine` FP64-residual
+    refinement steps) and (d) the same without refinement; solves/s of each
+    and the residual ratio ||b - A x|| / ||b - A x_opt|| against the FP64 QR
+    optimum x_opt (library QR in FP64 on the device, measurement only)."""
+    p64, pbf = compare_problems(ms, torch, count, seed, dev)
     torch.cuda.synchronize()
 
     def timed(fn):
@@ -337,6 +343,16 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"only": "copy", "bytes_read_per_launch": nbytes,
                           "bytes_written_per_launch": nbytes, "launches": args.steps}))
+        return
+    if args.only == "batched_mixed":
+        # the batched mixed-precision solve of the comparison batch, alone
+        _, pbf = compare_problems(ms, torch, args.compare_problems, args.seed + 1, dev)
+        r = ms.BatchRunner(pbf, refine_steps=args.refine)
+        for _ in range(args.steps):
+            r.launch()
+        torch.cuda.synchronize()
+        print(json.dumps({"only": args.only, "problems": len(pbf), "refine_steps": args.refine,
+                          "status": r.status()[0], "launches": args.steps}))
         return
     if args.only in ("countsketch_f32_k32768", "countsketch_f32_k131072"):
         # the FP32 workloads' CountSketch of [A | B] alone (device-generated

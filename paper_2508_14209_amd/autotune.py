@@ -121,17 +121,27 @@ def tune_countsketch(A: torch.Tensor, h: torch.Tensor, s: torch.Tensor, k: int,
 
 
 def batch_key(problems, device) -> str:
-    n = sorted({int(p["A"].shape[1]) for p in problems})
+    """Shape class of a batch: dtypes, largest n (rounded up to a power of
+    two) and mean d (nearest power of two).  The count is not part of it, so
+    batches of a serving stream with similar requests share one entry."""
+    n = max(int(p["A"].shape[1]) for p in problems)
     d = sum(int(p["A"].shape[0]) for p in problems) // len(problems)
-    return "batch|%s|%s|%s|cnt%d|d2^%d|n%s" % (
+    return "batch|%s|%s|%s|d2^%d|n<=%d" % (
         _device_name(device), str(problems[0]["A"].dtype).replace("torch.", ""),
-        str(problems[0]["G"].dtype).replace("torch.", ""), len(problems),
-        max(0, round(math.log2(max(1, d)))), ",".join(map(str, n)))
+        str(problems[0]["G"].dtype).replace("torch.", ""),
+        max(0, round(math.log2(max(1, d)))), 1 << max(0, math.ceil(math.log2(max(1, n)))))
 
 
 def lookup_batch(problems, device="cuda"):
+    """(rows_log2, kchunk_log2) cached for the batch's shape class, or None."""
     v = _load().get(batch_key(problems, torch.device(device)))
     return (v["rows_log2"], v["kchunk_log2"]) if v else None
+
+
+def batch_params(problems, device="cuda"):
+    """Tuning for BatchRunner: the cached choice, else (0, 0) (library
+    defaults)."""
+    return lookup_batch(problems, device) or (0, 0)
 
 
 def tune_batch(problems, reps: int = 3, store: bool = True,

@@ -648,7 +648,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds_xcd(int64_t d, Cols<T> cols,
 // ------------------------------------------------------------------ batched
 
 // Persistent workgroups over the CountSketch items of all problems: item =
-// (problem, column tile, row segment, bucket tile).  h and s are read and
+// (problem, row segment, column tile, bucket tile).  h and s are read and
 // validated in the kernel; a problem's Y must be zero on entry.  RES: the
 // CountSketch of the FP64 residual columns (refinement) instead of [A | B].
 template <typename T, bool RES>
@@ -670,11 +670,15 @@ __global__ __launch_bounds__(1024) void k_batch_cs(int count, const ms_problem *
     const BatchEntry &e = E[p];
     const int nbt = RES ? e.rnbt : e.nbt, nt = RES ? e.rnt : e.nt;
     const int64_t ktile = RES ? e.rktile : e.ktile;
+    // the column tiles and bucket tiles of a row segment are consecutive
+    // items, so h and s of the segment are read from each die's L2 once
+    // rather than once per column tile
+    const int ntl = RES ? e.rntiles : e.ntiles;
     int64_t local = it - (RES ? e.rcs_start : e.cs_start);
     const int bt = (int)(local % nbt);
     local /= nbt;
-    const int seg = (int)(local % e.nsegs);
-    const int tile = (int)(local / e.nsegs);
+    const int tile = (int)(local % ntl);
+    const int seg = (int)(local / ntl);
     const int64_t r0 = (int64_t)seg * e.rows, r1 = min(Q.d, r0 + e.rows);
     const int64_t b0 = (int64_t)bt * ktile;
     const uint32_t kt = (uint32_t)min(ktile, Q.k - b0);

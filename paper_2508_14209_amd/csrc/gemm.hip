@@ -435,13 +435,33 @@ __global__ __launch_bounds__(256) void k_gemv64_splitk(int M, int N, int64_t K,
 }
 
 // Refinement of a batch: partials of G Yr in FP64 (G's values promoted
-// exactly), item = (problem, K split); one thread per row of G (k2 <= 256).
+// exactly), item = (problem, K split).  Each thread owns four rows of G; the
+// 256 threads form 256 / L slots (L = ceil(k2 / 4) threads per column of G)
+// that take the split's columns round-robin; Yr is staged in LDS 1024 rows at
+// a time, and the slots' sums are added in slot order at the end.
+template <typename TG>
+__device__ __forceinline__ void g_rows4(const TG *g, bool vec, int nvalid, double v[4]) {
+  if (vec) {
+    typedef TG V __attribute__((ext_vector_type(4)));
+    const V a = *reinterpret_cast<const V *>(g);
+    v[0] = g_as_f64<TG>(a.x);
+    v[1] = g_as_f64<TG>(a.y);
+    v[2] = g_as_f64<TG>(a.z);
+    v[3] = g_as_f64<TG>(a.w);
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = q < nvalid ? g_as_f64<TG>(g[q]) : 0.0;
+  }
+}
+
 template <typename TG>
 __global__ __launch_bounds__(256) void k_batch_gemv(int count, const ms_problem *__restrict__ P,
                                                     const BatchEntry *__restrict__ E,
                                                     const BatchTotals *__restrict__ tot,
                                                     const unsigned char *__restrict__ yrarea,
                                                     unsigned char *__restrict__ gvarea) {
+  constexpr int RH = kBatchMaxRefineRhs, CH = 1024;
+  __shared__ double buf[CH * RH];
   const int64_t total = tot->gv_items;
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
     const int p = batch_find_m<&BatchEntry::gv_start>(E, count, it);
@@ -449,23 +469,56 @@ __global__ __launch_bounds__(256) void k_batch_gemv(int count, const ms_problem 
     const BatchEntry &e = E[p];
     const int split = (int)(it - e.gv_start);
     const int M = (int)Q.k2, N = (int)Q.nrhs;
+    const int L = (M + 3) / 4, S = (int)blockDim.x / L;
+    const int rg = (int)threadIdx.x % L, slot = (int)threadIdx.x / L;
+    const int row0 = 4 * rg, nvalid = min(4, M - row0);
+    const bool active = slot < S;
     const int64_t kb = (int64_t)split * e.kchunk, ke = min(Q.k, kb + e.kchunk);
     const double *Yr = reinterpret_cast<const double *>(yrarea + e.yr_off);
-    double *part = reinterpret_cast<double *>(gvarea + e.gv_off) + (int64_t)split * M * N;
     const TG *G = static_cast<const TG *>(Q.G);
-    for (int row = threadIdx.x; row < M; row += blockDim.x) {
-      double acc[kBatchMaxRefineRhs];
+    const bool vec = nvalid == 4 && (Q.ldg & 3) == 0 &&
+                     ((uintptr_t)G & (4 * sizeof(TG) - 1)) == 0;
+    double acc[4][RH];
 #pragma unroll
-      for (int c = 0; c < kBatchMaxRefineRhs; ++c) acc[c] = 0.0;
-      for (int64_t m = kb; m < ke; ++m) {
-        const double g = g_as_f64<TG>(G[row + m * Q.ldg]);
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int c = 0; c < kBatchMaxRefineRhs; ++c)
-          if (c < N) acc[c] += g * Yr[m + (int64_t)c * Q.k];
+      for (int c = 0; c < RH; ++c) acc[q][c] = 0.0;
+    for (int64_t c0 = kb; c0 < ke; c0 += CH) {
+      const int len = (int)min((int64_t)CH, ke - c0);
+      __syncthreads();  // earlier readers of buf are done
+      for (int t = threadIdx.x; t < len * N; t += blockDim.x) {
+        const int c = t / len, m = t - c * len;
+        buf[m * RH + c] = Yr[c0 + m + (int64_t)c * Q.k];
       }
+      __syncthreads();
+      if (active)
+        for (int m = slot; m < len; m += S) {
+          double g[4];
+          g_rows4<TG>(G + row0 + (c0 + m) * Q.ldg, vec, nvalid, g);
 #pragma unroll
-      for (int c = 0; c < kBatchMaxRefineRhs; ++c)
-        if (c < N) part[row + (int64_t)c * M] = acc[c];
+          for (int c = 0; c < RH; ++c)
+            if (c < N) {
+              const double y = buf[m * RH + c];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) acc[q][c] += g[q] * y;
+            }
+        }
+    }
+    // slot sums in slot order: buf[(slot * 4L + row) * RH + c]
+    __syncthreads();
+    if (active)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < RH; ++c)
+          if (c < N) buf[((int64_t)slot * 4 * L + row0 + q) * RH + c] = acc[q][c];
+    __syncthreads();
+    double *part = reinterpret_cast<double *>(gvarea + e.gv_off) + (int64_t)split * M * N;
+    for (int t = threadIdx.x; t < M * N; t += blockDim.x) {
+      const int c = t / M, row = t - c * M;
+      double s = buf[row * RH + c];
+      for (int z = 1; z < S; ++z) s += buf[((int64_t)z * 4 * L + row) * RH + c];
+      part[row + (int64_t)c * M] = s;
     }
   }
 }

@@ -183,7 +183,7 @@ struct BatchEntry {
   int32_t rnt, rntiles, rnbt, pad1;
 };
 
-constexpr int64_t kBatchResRows = 256;  // rows per residual work item
+constexpr int64_t kBatchResRows = 1024;  // rows per residual work item (4 per thread)
 constexpr int kBatchMaxRefineRhs = 8;
 
 constexpr int64_t kBatchLdsSlots = 16384;  // FP64 partial sums per workgroup (128 KB)
@@ -222,8 +222,11 @@ __host__ __device__ inline void batch_entry(const ms_problem &P, int wdata, int 
   batch_cs_geom(P.k, E.nc, E.ktile, E.nbt, E.nt, E.ntiles);
   E.refine = refine ? 1 : 0;
   if (refine) batch_cs_geom(P.k, (int)P.nrhs, E.rktile, E.rnbt, E.rnt, E.rntiles);
+  // rows per item: at least 8 rows per bucket of the tile on average, so the
+  // flush of a tile's partial sums stays small next to the adds
   E.rows = rows_item;
-  E.nsegs = (int32_t)((P.d + rows_item - 1) / rows_item);
+  while (E.rows < 8 * E.ktile && E.rows < ((int64_t)1 << 30)) E.rows *= 2;
+  E.nsegs = (int32_t)((P.d + E.rows - 1) / E.rows);
   E.tiles_m = (int32_t)((P.k2 + 63) / 64);
   E.tiles_n = (E.nc + 63) / 64;
   E.kchunk = kchunk;

@@ -736,10 +736,14 @@ hipError_t launch_batch_qr(int count, int max_k2, int max_n, int max_nc, const m
 
 // Refinement of a batch, one workgroup per problem: zr = the G Yr partials
 // summed in split order; dx = R^{-1} (Q^T zr)_{0:n} with the reflectors, tau
-// and R the first pass kept; X += dx.  One wave per right-hand side.
+// and R the first pass kept; X += dx.  One wave per right-hand side, which
+// holds its column in registers (lane l rows l + 64 r); the next reflector
+// (and, in the back substitution, the next column of R) is loaded while the
+// current one is applied.
 __global__ __launch_bounds__(64 * kBatchMaxRefineRhs) void k_batch_apply_solve(
     int count, const ms_problem *__restrict__ P, const BatchEntry *__restrict__ E,
     const unsigned char *__restrict__ gvarea, const unsigned char *__restrict__ farea) {
+  constexpr int RPL = kBatchMaxK2 / 64;
   __shared__ double zb[kBatchMaxK2 * kBatchMaxRefineRhs];
   const int p = blockIdx.x;
   const BatchEntry &e = E[p];
@@ -759,20 +763,68 @@ __global__ __launch_bounds__(64 * kBatchMaxRefineRhs) void k_batch_apply_solve(
   const double *tau = fact + (int64_t)m * n;
   const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
   if (c >= nrhs) return;
-  double *b = zb + (int64_t)c * m;
-  for (int j = 0; j < n; ++j) {
-    const double tj = tau[j];
-    if (tj == 0.0) continue;
-    const double *v = fact + (int64_t)j * m;
-    double s = lane == 0 ? b[j] : 0.0;
-    for (int i = j + 1 + lane; i < m; i += 64) s += v[i] * b[i];
-    const double w = wave_sum(s) * tj;
-    if (lane == 0) b[j] -= w;
-    for (int i = j + 1 + lane; i < m; i += 64) b[i] -= w * v[i];
-    __threadfence_block();
+  double y[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int i = lane + 64 * r;
+    y[r] = i < m ? zb[c * m + i] : 0.0;
   }
-  wave_back_substitute(n, fact, m, b, b);  // in place: b[0:n) = dx
-  for (int i = lane; i < n; i += 64) Q.X[i + (int64_t)c * Q.ldx] += b[i];
+  // y <- Q^T y, reflector j: v_i = fact[i, j] below the diagonal, 1 on it
+  auto load_v = [&](int j, double v[RPL]) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lane + 64 * r;
+      v[r] = (i > j && i < m) ? fact[i + (int64_t)j * m] : (i == j ? 1.0 : 0.0);
+    }
+  };
+  double vn[RPL], tn = n > 0 ? tau[0] : 0.0;
+  if (n > 0) load_v(0, vn);
+  for (int j = 0; j < n; ++j) {
+    double v[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) v[r] = vn[r];
+    const double tj = tn;
+    if (j + 1 < n) {
+      load_v(j + 1, vn);
+      tn = tau[j + 1];
+    }
+    double dot = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) dot += v[r] * y[r];
+    const double w = tj * wave_allsum(dot);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) y[r] -= w * v[r];
+  }
+  // R dx = y[0:n): column i of R is fact[0:i, i] (on and above the diagonal)
+  auto load_r = [&](int i, double col[RPL]) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int t = lane + 64 * r;
+      col[r] = t <= i ? fact[t + (int64_t)i * m] : 0.0;
+    }
+  };
+  double rn[RPL];
+  if (n > 0) load_r(n - 1, rn);
+  for (int i = n - 1; i >= 0; --i) {
+    double col[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) col[r] = rn[r];
+    if (i > 0) load_r(i - 1, rn);
+    double yl = 0.0, dl = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r)
+      if (r == (i >> 6)) {
+        yl = y[r];
+        dl = col[r];
+      }
+    const double xi = read_lane(yl, i & 63) / read_lane(dl, i & 63);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int t = lane + 64 * r;
+      if (t < i) y[r] -= col[r] * xi;
+    }
+    if (lane == 0) Q.X[i + (int64_t)c * Q.ldx] += xi;
+  }
 }
 
 hipError_t launch_batch_apply_solve(int count, const ms_problem *P, const BatchEntry *E,

@@ -52,36 +52,117 @@ hipError_t launch_residual_f64(int64_t d, int64_t n, int64_t nrhs, const double 
   return hipGetLastError();
 }
 
-// Residuals of a batch: item = (problem, kBatchResRows rows), one thread per
-// row; B has A's type.  r_p is d x nrhs, column-major, ld d.
+// Residuals of a batch: item = (problem, kBatchResRows rows), four rows per
+// thread (16-byte loads of A and B when aligned), X staged in LDS; B has A's
+// type.  r_p is d x nrhs, column-major, ld d.
 template <typename TA>
-__global__ __launch_bounds__(kBatchResRows) void k_batch_residual(
+struct Rows4 {
+  static __device__ __forceinline__ void load(const TA *p, double v[4]) {
+    typedef TA V __attribute__((ext_vector_type(4)));
+    const V a = *reinterpret_cast<const V *>(p);
+    v[0] = (double)a.x;
+    v[1] = (double)a.y;
+    v[2] = (double)a.z;
+    v[3] = (double)a.w;
+  }
+};
+template <>
+struct Rows4<double> {
+  static __device__ __forceinline__ void load(const double *p, double v[4]) {
+    typedef double V __attribute__((ext_vector_type(2)));
+    const V a = *reinterpret_cast<const V *>(p);
+    const V b = *reinterpret_cast<const V *>(p + 2);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+    v[3] = b.y;
+  }
+};
+
+template <typename TA>
+__global__ __launch_bounds__(kBatchResRows / 4) void k_batch_residual(
     int count, const ms_problem *__restrict__ P, const BatchEntry *__restrict__ E,
     const BatchTotals *__restrict__ tot, unsigned char *__restrict__ rarea) {
+  constexpr int RH = kBatchMaxRefineRhs;
+  __shared__ double xs[kBatchMaxCols * RH];  // xs[j * RH + c] = X[j, c]
   const int64_t total = tot->res_items;
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
     const int p = batch_find_m<&BatchEntry::res_start>(E, count, it);
     const ms_problem &Q = P[p];
     const BatchEntry &e = E[p];
-    const int64_t i = (it - e.res_start) * kBatchResRows + threadIdx.x;
-    if (i >= Q.d) continue;
+    const int n = (int)Q.n, nrhs = (int)Q.nrhs;
+    __syncthreads();  // the previous item's reads of xs are done
+    for (int t = threadIdx.x; t < n * nrhs; t += blockDim.x) {
+      const int c = t / n, j = t - c * n;
+      xs[j * RH + c] = Q.X[j + (int64_t)c * Q.ldx];
+    }
+    __syncthreads();
+    const int64_t i0 = (it - e.res_start) * kBatchResRows + (int64_t)threadIdx.x * 4;
+    if (i0 >= Q.d) continue;
     const TA *A = static_cast<const TA *>(Q.A);
     const TA *B = static_cast<const TA *>(Q.B);
-    const int n = (int)Q.n, nrhs = (int)Q.nrhs;
-    double acc[kBatchMaxRefineRhs];
-#pragma unroll
-    for (int c = 0; c < kBatchMaxRefineRhs; ++c) acc[c] = 0.0;
-#pragma unroll 4
-    for (int j = 0; j < n; ++j) {
-      const double a = (double)A[i + (int64_t)j * Q.lda];
-#pragma unroll
-      for (int c = 0; c < kBatchMaxRefineRhs; ++c)
-        if (c < nrhs) acc[c] += a * Q.X[j + (int64_t)c * Q.ldx];
-    }
     double *r = reinterpret_cast<double *>(rarea + e.r_off);
+    const bool vec = i0 + 4 <= Q.d && ((Q.lda | Q.ldb) & 3) == 0 &&
+                     (((uintptr_t)A | (uintptr_t)B) & 15) == 0;
+    const int rows = (int)min((int64_t)4, Q.d - i0);
+    double acc[4][RH];
 #pragma unroll
-    for (int c = 0; c < kBatchMaxRefineRhs; ++c)
-      if (c < nrhs) r[i + (int64_t)c * Q.d] = (double)B[i + (int64_t)c * Q.ldb] - acc[c];
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < RH; ++c) acc[q][c] = 0.0;
+    if (vec) {
+      int j = 0;
+      for (; j + 4 <= n; j += 4) {
+        double a[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) Rows4<TA>::load(A + i0 + (int64_t)(j + u) * Q.lda, a[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < RH; ++c)
+            if (c < nrhs) {
+              const double x = xs[(j + u) * RH + c];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) acc[q][c] += a[u][q] * x;
+            }
+      }
+      for (; j < n; ++j) {
+        double a[4];
+        Rows4<TA>::load(A + i0 + (int64_t)j * Q.lda, a);
+#pragma unroll
+        for (int c = 0; c < RH; ++c)
+          if (c < nrhs) {
+            const double x = xs[j * RH + c];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q][c] += a[q] * x;
+          }
+      }
+#pragma unroll
+      for (int c = 0; c < RH; ++c)
+        if (c < nrhs) {
+          double b[4];
+          Rows4<TA>::load(B + i0 + (int64_t)c * Q.ldb, b);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) r[i0 + q + (int64_t)c * Q.d] = b[q] - acc[q][c];
+        }
+    } else {
+      for (int j = 0; j < n; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q < rows) {
+            const double a = (double)A[i0 + q + (int64_t)j * Q.lda];
+#pragma unroll
+            for (int c = 0; c < RH; ++c)
+              if (c < nrhs) acc[q][c] += a * xs[j * RH + c];
+          }
+#pragma unroll
+      for (int c = 0; c < RH; ++c)
+        if (c < nrhs)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (q < rows)
+              r[i0 + q + (int64_t)c * Q.d] = (double)B[i0 + q + (int64_t)c * Q.ldb] - acc[q][c];
+    }
   }
 }
 
@@ -89,8 +170,8 @@ template <typename TA>
 hipError_t launch_batch_residual(int count, const ms_problem *P, const BatchEntry *E,
                                  const BatchTotals *tot, unsigned char *rarea, int grid,
                                  hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_residual<TA>, dim3(grid), dim3(kBatchResRows), 0, st, count, P, E,
-                     tot, rarea);
+  hipLaunchKernelGGL(k_batch_residual<TA>, dim3(grid), dim3(kBatchResRows / 4), 0, st, count, P,
+                     E, tot, rarea);
   return hipGetLastError();
 }
 template hipError_t launch_batch_residual<float>(int, const ms_problem *, const BatchEntry *,

@@ -131,7 +131,8 @@ class Server:
 
     def __init__(self, hbm_budget: int = 64 << 30, max_inflight: int = 256, max_batch: int = 64,
                  streams: int = 4, g_dtype: str = "f32", rows_log2: int = 0,
-                 kchunk_log2: int = 0, refine_steps: int = 0, device="cuda"):
+                 kchunk_log2: int = 0, refine_steps: int = 0, tuned: bool = False,
+                 device="cuda"):
         self.device = torch.device(device)
         self.admission = Admission(hbm_budget, max_inflight)
         self.max_batch = max_batch
@@ -139,6 +140,7 @@ class Server:
         self.rows_log2 = rows_log2
         self.kchunk_log2 = kchunk_log2
         self.refine_steps = refine_steps
+        self.tuned = tuned              # take rows/K per item from the autotuner's cache
         self.gen_stream = torch.cuda.Stream(device=self.device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self.busy = {}                # stream index -> (event, runner, requests)
@@ -185,9 +187,12 @@ class Server:
             for pr in probs:                    # memory of the generator stream used here
                 for key in ("A", "B", "h", "s", "G", "X"):
                     pr[key].record_stream(st)
+            rl, kl = self.rows_log2, self.kchunk_log2
+            if self.tuned and not (rl or kl):
+                from paper_2508_14209_amd import autotune
+                rl, kl = autotune.batch_params(probs, self.device)
             with torch.cuda.stream(st):
-                runner = ms.BatchRunner(probs, rows_log2=self.rows_log2,
-                                        kchunk_log2=self.kchunk_log2,
+                runner = ms.BatchRunner(probs, rows_log2=rl, kchunk_log2=kl,
                                         refine_steps=self.refine_steps)
                 runner.launch(st)
                 ev = torch.cuda.Event()
