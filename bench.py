@@ -62,7 +62,8 @@ def parse():
                     help="FP64-residual refinement steps of the mixed-precision legs")
     ap.add_argument("--only", default=None,
                     choices=["countsketch", "countsketch_f32_k32768", "countsketch_f32_k131072",
-                             "copy", "gaussian_f64", "gaussian_bf16", "batched_mixed"],
+                             "copy", "gaussian_f64", "gaussian_bf16", "batched_mixed",
+                             "solve_fp32", "solve_mixed"],
                     help="profiling runs: launch only the LDS CountSketch of [A | b] (--steps "
                          "times), only a plain device copy of 1 GiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters), or only the Gaussian stage of the "
@@ -233,7 +234,7 @@ def mixed_vs_fp64_leg(ms, torch, np, count, seed, refine, dev, reps=3):
     return res
 
 
-def other_configs_leg(ms, torch, np, seed, dev, reps=10):
+def other_configs_leg(ms, torch, np, seed, dev, reps=10, only=None):
     """The FP32 and mixed-precision least-squares workloads: full solves
     (sketch_lstsq) and their CountSketch kernel alone, inputs generated on
     the device from the seed (A = Z D [Q], b = A x* + 1e-6 N(0,1))."""
@@ -245,6 +246,8 @@ def other_configs_leg(ms, torch, np, seed, dev, reps=10):
         ("mixed_bf16_refine3_8388608x256", 1 << 23, 256, 4, 131072, 512, 1e4, False, "bf16", 3),
     ]
     for name, d, n, nrhs, k, k2, kappa, rotate, gd, refine in cases:
+        if only and not name.startswith(only):
+            continue
         scales = torch.logspace(0.0, -math.log10(kappa), n, device=dev, dtype=torch.float64)
         M = torch.diag(scales)
         if rotate:
@@ -295,7 +298,9 @@ def other_configs_leg(ms, torch, np, seed, dev, reps=10):
         del A, B
         code, _ = ms.pack_sketch(h, s, k)
         Y = ms.empty_colmajor(k, n + nrhs, torch.float32, dev)
-        cws = ms.workspace(256, dev)
+        # a workspace with room for the per-die partial sums, as in the solve
+        cws = ms.workspace(ms.workspace_size("countsketch", d=d, n=n + nrhs, k=k,
+                                             a_dtype=ms.MS_F32), dev)
         ms.countsketch_accumulate(AB, code, k, Y, mode="lds", ws=cws)
         e0.record()
         for _ in range(reps):
@@ -344,6 +349,12 @@ def main():
         print(json.dumps({"only": "copy", "bytes_read_per_launch": nbytes,
                           "bytes_written_per_launch": nbytes, "launches": args.steps}))
         return
+    if args.only in ("solve_fp32", "solve_mixed"):
+        # one of the FP32 / mixed-precision solves alone (3 timed solves)
+        res = other_configs_leg(ms, torch, np, args.seed + 2, dev, reps=3,
+                                only="fp32" if args.only == "solve_fp32" else "mixed")
+        print(json.dumps(res))
+        return
     if args.only == "batched_mixed":
         # the batched mixed-precision solve of the comparison batch, alone
         _, pbf = compare_problems(ms, torch, args.compare_problems, args.seed + 1, dev)
@@ -369,7 +380,8 @@ def main():
         sx = (torch.randint(0, 2, (d_,), generator=gen, device=dev, dtype=torch.int8) * 2 - 1)
         code, _ = ms.pack_sketch(hx, sx, k_)
         Yx = ms.empty_colmajor(k_, nc_, torch.float32, dev)
-        cws = ms.workspace(256, dev)
+        cws = ms.workspace(ms.workspace_size("countsketch", d=d_, n=nc_, k=k_,
+                                             a_dtype=ms.MS_F32), dev)
         Yx.zero_()
         torch.cuda.synchronize()
         for _ in range(args.steps):

@@ -153,7 +153,12 @@ ms_status ms_pack_sketch(int64_t d, int64_t k, const int32_t *h, const int8_t *s
  * opts->cs_mode: MS_CS_AUTO/MS_CS_LDS or MS_CS_ATOMIC; MS_CS_SORTED returns
  * MS_ERR_UNSUPPORTED (its fixed fold order starts from +0.0).  A code whose
  * bucket is >= k is skipped and recorded as MS_ERR_RANGE.
- * ws: ms_workspace_size(MS_OP_COUNTSKETCH, ...) suffices.
+ * ws: at least 256 bytes (the status word).  A workspace of
+ * ms_workspace_size(MS_OP_COUNTSKETCH, d, n, 0, k, 0, a_dtype, ...) bytes
+ * also holds, after the status block, the per-die partial sums that the LDS
+ * variant uses instead of atomic flushes when k is large next to d (then
+ * 8 k n elements); with a smaller workspace that variant flushes with
+ * atomics.
  */
 ms_status countsketch_accumulate(int64_t d, int64_t n, int64_t k, ms_dtype a_dtype,
                                  const void *A, int64_t lda, const uint32_t *code, void *Y,
@@ -163,7 +168,9 @@ ms_status countsketch_accumulate(int64_t d, int64_t n, int64_t k, ms_dtype a_dty
 /*
  * CountSketch Y = S A (Def. 3, Eq. (2), Alg. 2).
  *   A: d x n, a_dtype MS_F64 or MS_F32, lda >= max(1,d).
- *   Y: k x n, same dtype as A, ldy >= k.  Accumulation is in A's precision.
+ *   Y: k x n, same dtype as A, ldy >= k.  The atomic and sorted variants
+ *   accumulate in A's precision; the LDS variant sums each workgroup's rows
+ *   in FP64 and adds that partial sum to Y in Y's precision.
  *   h, s: d entries each (see the conventions above).
  * opts->cs_mode selects the variant; MS_CS_SORTED reproduces the ascending
  * row fold bit for bit.  d may be 0 (Y = 0).  n may be 0 (no-op).

@@ -80,9 +80,12 @@ int resolve_mode(const ms_opts *o) {
 
 struct CsLayout {
   size_t code = 0, cnt = 0, off = 0, cursor = 0, sperm = 0;
+  size_t part = 0, part_bytes = 0;
 };
 
-void carve_cs(Carve &cv, CsLayout &L, int64_t d, int64_t k, int mode) {
+// ncols, wd: columns and element bytes of the sketched operand (the LDS
+// variant's per-die partial buffer, when its schedule pays for the shape).
+void carve_cs(Carve &cv, CsLayout &L, int64_t d, int64_t k, int mode, int64_t ncols, int64_t wd) {
   if (mode == MS_CS_SORTED) {
     L.cnt = cv.take((size_t)k * 4);
     L.off = cv.take((size_t)(k + 1) * 4);
@@ -90,6 +93,10 @@ void carve_cs(Carve &cv, CsLayout &L, int64_t d, int64_t k, int mode) {
     L.sperm = cv.take((size_t)d * 4);
   } else {
     L.code = cv.take((size_t)d * 4);
+    if (mode == MS_CS_LDS) {
+      L.part_bytes = cs_part_bytes(d, k, ncols, wd);
+      if (L.part_bytes) L.part = cv.take(L.part_bytes);
+    }
   }
 }
 
@@ -105,7 +112,7 @@ LstsqLayout lstsq_layout(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64_t 
   LstsqLayout L;
   Carve cv;
   const int64_t nc = n + nrhs;
-  carve_cs(cv, L.cs, d, k, mode);
+  carve_cs(cv, L.cs, d, k, mode, nc, dtype_size(a_dtype));
   L.y = cv.take((size_t)k * nc * dtype_size(a_dtype));
   L.partials = cv.take(plan_gemm(k2, nc, k, g_dtype).partial_bytes);
   L.z64 = cv.take((size_t)k2 * nc * 8);
@@ -175,7 +182,8 @@ hipError_t run_countsketch(int64_t d, int64_t k, const Cols<T> &c, const int32_t
   if (mode == MS_CS_ATOMIC)
     return launch_cs_atomic<T>(d, k, c, at<uint32_t>(ws, L.code), Y, ldy, false, status, st);
   return launch_cs_lds<T>(d, k, c, at<uint32_t>(ws, L.code), nullptr, nullptr, Y, ldy, false,
-                          status, st, &tune);
+                          status, st, &tune, L.part_bytes ? at<void>(ws, L.part) : nullptr,
+                          L.part_bytes);
 }
 
 bool valid_mode(const ms_opts *o) {
@@ -227,13 +235,13 @@ size_t ms_workspace_size(int op, int64_t d, int64_t n, int64_t nrhs, int64_t k, 
       cv.take((size_t)d * 4);
       return cv.off;
     case MS_OP_COUNTSKETCH:
-      carve_cs(cv, L, d, k, mode);
+      carve_cs(cv, L, d, k, mode, n, dtype_size(a_dtype));
       return cv.off;
     case MS_OP_GAUSSIAN:
       cv.take(plan_gemm(k2, n, k, g_dtype).partial_bytes);
       return cv.off;
     case MS_OP_MULTISKETCH:
-      carve_cs(cv, L, d, k, mode);
+      carve_cs(cv, L, d, k, mode, n, dtype_size(a_dtype));
       cv.take((size_t)k * n * dtype_size(a_dtype));
       cv.take(plan_gemm(k2, n, k, g_dtype).partial_bytes);
       return cv.off;
@@ -305,18 +313,21 @@ ms_status countsketch_accumulate(int64_t d, int64_t n, int64_t k, ms_dtype a_dty
   hipError_t e = launch_zero_status(status, st);
   if (e != hipSuccess || n == 0 || d == 0) return from_hip(e);
   const CsTuning tune = tuning_of(opts);
+  // a workspace beyond the status block holds the per-die partial buffer
+  const size_t pneed = cs_part_bytes(d, k, n, dtype_size(a_dtype));
+  void *part = (pneed && ws_bytes >= kAlign + pneed) ? at<void>(ws, kAlign) : nullptr;
   if (a_dtype == MS_F64) {
     Cols<double> c{static_cast<const double *>(A), lda, nullptr, 0, (int)n, (int)n};
     e = mode == MS_CS_ATOMIC
             ? launch_cs_atomic<double>(d, k, c, code, static_cast<double *>(Y), ldy, false, status, st)
             : launch_cs_lds<double>(d, k, c, code, nullptr, nullptr, static_cast<double *>(Y), ldy,
-                                    false, status, st, &tune);
+                                    false, status, st, &tune, part, part ? pneed : 0);
   } else {
     Cols<float> c{static_cast<const float *>(A), lda, nullptr, 0, (int)n, (int)n};
     e = mode == MS_CS_ATOMIC
             ? launch_cs_atomic<float>(d, k, c, code, static_cast<float *>(Y), ldy, false, status, st)
             : launch_cs_lds<float>(d, k, c, code, nullptr, nullptr, static_cast<float *>(Y), ldy,
-                                   false, status, st, &tune);
+                                   false, status, st, &tune, part, part ? pneed : 0);
   }
   return from_hip(e);
 }
@@ -339,7 +350,7 @@ ms_status countsketch_apply(int64_t d, int64_t n, int64_t k, ms_dtype a_dtype, c
   hipError_t e;
   Carve cv;
   CsLayout L;
-  carve_cs(cv, L, d, k, mode);
+  carve_cs(cv, L, d, k, mode, n, dtype_size(a_dtype));
   if (a_dtype == MS_F64) {
     Cols<double> c{static_cast<const double *>(A), lda, nullptr, 0, (int)n, (int)n};
     e = run_countsketch<double>(d, k, c, h, s, static_cast<double *>(Y), ldy, mode, ws, L, status,
@@ -395,7 +406,7 @@ ms_status multisketch_apply(int64_t d, int64_t n, int64_t k, int64_t k2, ms_dtyp
   hipError_t e;
   Carve cv;
   CsLayout L;
-  carve_cs(cv, L, d, k, mode);
+  carve_cs(cv, L, d, k, mode, n, dtype_size(a_dtype));
   const size_t o_y = cv.take((size_t)k * n * dtype_size(a_dtype));
   const GemmPlan p = plan_gemm(k2, n, k, g_dtype);
   const size_t o_part = cv.take(p.partial_bytes);

@@ -520,8 +520,9 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
 
 // Rows [r0, r1) of column tile ct (NT columns from c0) and bucket tile
 // [b0, b0 + kt): accumulate into LDS (zero on entry), then add the non-zero
-// partials to Y and leave LDS zero again.  UNR vectors in flight per thread.
-template <typename T, int NT, bool VEC, bool CODES, int UNR, bool NTL>
+// partials to Y (PST: store every partial, zeros included, into a buffer the
+// workgroup owns) and leave LDS zero again.  UNR vectors in flight per thread.
+template <typename T, int NT, bool VEC, bool CODES, int UNR, bool NTL, bool PST = false>
 __device__ __forceinline__ void cs_segment(double *acc, const Cols<T> &cols, int c0, int nc,
                                            const uint32_t *__restrict__ code,
                                            const int32_t *__restrict__ h,
@@ -593,7 +594,10 @@ __device__ __forceinline__ void cs_segment(double *acc, const Cols<T> &cols, int
     const uint32_t j = t / kt, b = t - j * kt;
     const double v = acc[t];
     acc[t] = 0.0;
-    if (v != 0.0) unsafeAtomicAdd(&Y[(b0 + b) + (int64_t)(c0 + j) * ldy], (T)v);
+    if (PST)
+      Y[(b0 + b) + (int64_t)(c0 + j) * ldy] = (T)v;
+    else if (v != 0.0)
+      unsafeAtomicAdd(&Y[(b0 + b) + (int64_t)(c0 + j) * ldy], (T)v);
   }
   __syncthreads();
 }
@@ -605,8 +609,12 @@ __device__ __forceinline__ void cs_segment(double *acc, const Cols<T> &cols, int
 // contiguous share of the (column tile, row) space of its rows, so the bucket
 // tiles of a column are streamed by workgroups of the same die at the same
 // time, and each workgroup flushes LDS only when its share crosses a column
-// tile.
-template <typename T, int NT, bool VEC, bool CODES, int UNR, bool NTL>
+// tile.  PART: the die's groups split its column tiles instead (whole tiles,
+// all of the die's rows), so each (column, bucket) of a die has one owner,
+// which stores its partial sum into the die's slice of a partial buffer (Y,
+// ld k, slices of k x ncols) with plain stores; k_cs_part_reduce adds the
+// slices to the output.
+template <typename T, int NT, bool VEC, bool CODES, int UNR, bool NTL, bool PART>
 __global__ __launch_bounds__(1024) void k_cs_lds_xcd(int64_t d, Cols<T> cols,
                                                      const uint32_t *__restrict__ code,
                                                      const int32_t *__restrict__ h,
@@ -628,10 +636,22 @@ __global__ __launch_bounds__(1024) void k_cs_lds_xcd(int64_t d, Cols<T> cols,
   const uint32_t kt = (uint32_t)min(ktile, k - b0);
   for (uint32_t t = threadIdx.x; t < kt * NT; t += blockDim.x) acc[t] = 0.0;
   __syncthreads();
+  bool bad = false;
+  if (PART) {
+    const int ct0 = (int)((int64_t)nct * sub / subs), ct1 = (int)((int64_t)nct * (sub + 1) / subs);
+    T *Px = Y + (int64_t)x * k * cols.ncols;
+    for (int ct = ct0; ct < ct1; ++ct) {
+      const int c0 = ct * NT;
+      const int nc = min(NT, cols.ncols - c0);
+      cs_segment<T, NT, VEC, CODES, UNR, NTL, true>(acc, cols, c0, nc, code, h, s, k, b0, kt, R0,
+                                                    R1, Px, k, bad);
+    }
+    if (bad) record_status(status, MS_ERR_RANGE);
+    return;
+  }
   const int64_t total = (int64_t)nct * len;
   int64_t u0 = (total * sub / subs) & ~(int64_t)255;
   const int64_t u1 = sub + 1 == subs ? total : ((total * (sub + 1) / subs) & ~(int64_t)255);
-  bool bad = false;
   while (u0 < u1) {
     const int ct = (int)(u0 / len);
     const int64_t rlo = u0 - (int64_t)ct * len;
@@ -643,6 +663,40 @@ __global__ __launch_bounds__(1024) void k_cs_lds_xcd(int64_t d, Cols<T> cols,
     u0 += rhi - rlo;
   }
   if (bad) record_status(status, MS_ERR_RANGE);
+}
+
+// Y += the sum over dies (in die order, in FP64) of the per-die partial
+// slices written by the PART schedule (slice x: k x ncols, ld k).
+template <typename T>
+__global__ void k_cs_part_reduce(int64_t k, int ncols, int ndies, const T *__restrict__ part,
+                                 T *__restrict__ Y, int64_t ldy) {
+  const int64_t total = k * ncols;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = t / k, b = t - c * k;
+    double s = 0.0;
+    for (int x = 0; x < ndies; ++x) s += (double)part[t + (int64_t)x * total];
+    T *y = Y + b + c * ldy;
+    *y = (T)((double)*y + s);
+  }
+}
+
+// Bytes of the per-die partial buffer when the PART schedule pays: the
+// bucket range needs several LDS tiles (one column per tile), the atomic
+// flushes of the die-row schedule (every bucket of every column once per
+// die, 8 k per column) would exceed 1/16 of the data, and the columns split
+// over a die's groups to within 25%.  0 otherwise.  Assumes 8 dies of 32
+// compute units and 128 KB of LDS per workgroup (FP64 slots); the launch
+// checks the device matches.
+size_t cs_part_bytes(int64_t d, int64_t k, int64_t ncols, int64_t wd) {
+  const int64_t ktile = (128 * 1024) / 8;
+  if (k <= ktile || ncols < 1 || d < 1) return 0;
+  const int64_t nbt = (k + ktile - 1) / ktile;
+  const int64_t subs = 32 / nbt;
+  if (subs < 1 || 128 * k < d) return 0;
+  const int64_t per = (ncols + subs - 1) / subs;
+  if (ncols < subs || per * subs * 4 > ncols * 5) return 0;
+  return (size_t)(8 * k * ncols * wd);
 }
 
 // ------------------------------------------------------------------ batched
@@ -700,12 +754,23 @@ __global__ __launch_bounds__(1024) void k_batch_cs(int count, const ms_problem *
     const int c0 = tile * nt;
     const int ncur = min(nt, cols.ncols - c0);
     bool bad = false;
-    if (vec)
-      cs_segment<T, 4, true, false, 2, false>(acc, cols, c0, ncur, nullptr, Q.h, Q.s, Q.k, b0, kt,
-                                              r0, r1, Y, Q.k, bad);
-    else
-      cs_segment<T, 4, false, false, 2, false>(acc, cols, c0, ncur, nullptr, Q.h, Q.s, Q.k, b0, kt,
-                                               r0, r1, Y, Q.k, bad);
+    // the tile width is a template argument, so narrow tiles issue no
+    // loads for columns they do not have
+#define MS_BCS(NT_, UNR_)                                                                         \
+  if (vec)                                                                                        \
+    cs_segment<T, NT_, true, false, UNR_, false>(acc, cols, c0, ncur, nullptr, Q.h, Q.s, Q.k, b0,  \
+                                                 kt, r0, r1, Y, Q.k, bad);                        \
+  else                                                                                            \
+    cs_segment<T, NT_, false, false, UNR_, false>(acc, cols, c0, ncur, nullptr, Q.h, Q.s, Q.k, b0, \
+                                                  kt, r0, r1, Y, Q.k, bad);
+    if (nt >= 4) {
+      MS_BCS(4, 2)
+    } else if (nt == 2) {
+      MS_BCS(2, 4)
+    } else {
+      MS_BCS(1, 4)
+    }
+#undef MS_BCS
     if (bad) {
       record_status(&pstatus[p], MS_ERR_RANGE);
       record_status(status, MS_ERR_RANGE);
@@ -743,39 +808,62 @@ hipError_t launch_batch_cs_res(int count, const ms_problem *P, const BatchEntry 
   return hipGetLastError();
 }
 
+template <typename T, int NT, bool VEC, bool CODES, int UNR, bool NTL, bool PART>
+static hipError_t launch_cs_xcd_k(int grid, size_t lds, hipStream_t st, int64_t d,
+                                  const Cols<T> &c, const uint32_t *code, const int32_t *h,
+                                  const int8_t *s, int64_t k, int64_t ktile, int nct, int nbt,
+                                  int xcds, int spx, int64_t rpx, T *Y, int64_t ldy, int *status) {
+  const void *fn = (const void *)k_cs_lds_xcd<T, NT, VEC, CODES, UNR, NTL, PART>;
+  hipError_t e = allow_dynamic_lds(fn, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_cs_lds_xcd<T, NT, VEC, CODES, UNR, NTL, PART>), dim3(grid), dim3(1024),
+                     lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy,
+                     status);
+  return hipGetLastError();
+}
+
+// part (may be null): per-die partial buffer of xcds * k * ncols elements;
+// when given (one column per tile only), the PART schedule stores into it and
+// k_cs_part_reduce adds it to Y.
 template <typename T, int NT, bool CODES>
 static hipError_t launch_cs_xcd_v(bool vec, int grid, size_t lds, hipStream_t st, int64_t d,
                                   const Cols<T> &c, const uint32_t *code, const int32_t *h,
                                   const int8_t *s, int64_t k, int64_t ktile, int nct, int nbt,
-                                  int xcds, int spx, int64_t rpx, T *Y, int64_t ldy, int *status) {
+                                  int xcds, int spx, int64_t rpx, T *Y, int64_t ldy, T *part,
+                                  int *status) {
   // vectors in flight per thread: fewer for wider column tiles (registers)
   constexpr int UNR = NT >= 8 ? 1 : NT >= 4 ? 2 : 4;
-  if (nbt > 1) {  // bucket tiles re-read A: ordinary loads, so the die's L2 keeps it
-    const void *fn = vec ? (const void *)k_cs_lds_xcd<T, NT, true, CODES, UNR, false>
-                         : (const void *)k_cs_lds_xcd<T, NT, false, CODES, UNR, false>;
-    hipError_t e = allow_dynamic_lds(fn, (int)lds);
+  if constexpr (NT == 1) {
+  if (part && nbt > 1) {
+    hipError_t e =
+        vec ? launch_cs_xcd_k<T, NT, true, CODES, UNR, false, true>(
+                  grid, lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, part, k,
+                  status)
+            : launch_cs_xcd_k<T, NT, false, CODES, UNR, false, true>(
+                  grid, lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, part, k,
+                  status);
     if (e != hipSuccess) return e;
-    if (vec)
-      hipLaunchKernelGGL((k_cs_lds_xcd<T, NT, true, CODES, UNR, false>), dim3(grid), dim3(1024),
-                         lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy,
-                         status);
-    else
-      hipLaunchKernelGGL((k_cs_lds_xcd<T, NT, false, CODES, UNR, false>), dim3(grid), dim3(1024),
-                         lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy,
-                         status);
+    const int ndies = (int)std::min<int64_t>(xcds, (d + rpx - 1) / rpx);
+    const int64_t total = k * c.ncols;
+    const unsigned rb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 8192));
+    hipLaunchKernelGGL(k_cs_part_reduce<T>, dim3(rb), dim3(256), 0, st, k, c.ncols, ndies,
+                       (const T *)part, Y, ldy);
     return hipGetLastError();
   }
-  const void *fn = vec ? (const void *)k_cs_lds_xcd<T, NT, true, CODES, UNR, true>
-                       : (const void *)k_cs_lds_xcd<T, NT, false, CODES, UNR, true>;
-  hipError_t e = allow_dynamic_lds(fn, (int)lds);
-  if (e != hipSuccess) return e;
-  if (vec)
-    hipLaunchKernelGGL((k_cs_lds_xcd<T, NT, true, CODES, UNR, true>), dim3(grid), dim3(1024), lds,
-                       st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy, status);
-  else
-    hipLaunchKernelGGL((k_cs_lds_xcd<T, NT, false, CODES, UNR, true>), dim3(grid), dim3(1024), lds,
-                       st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy, status);
-  return hipGetLastError();
+  }
+  if (nbt > 1)  // bucket tiles re-read A: ordinary loads, so the die's L2 keeps it
+    return vec ? launch_cs_xcd_k<T, NT, true, CODES, UNR, false, false>(
+                     grid, lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy,
+                     status)
+               : launch_cs_xcd_k<T, NT, false, CODES, UNR, false, false>(
+                     grid, lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy,
+                     status);
+  return vec ? launch_cs_xcd_k<T, NT, true, CODES, UNR, true, false>(
+                   grid, lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy,
+                   status)
+             : launch_cs_xcd_k<T, NT, false, CODES, UNR, true, false>(
+                   grid, lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy,
+                   status);
 }
 
 template <typename T, int NT, bool CODES>
@@ -813,7 +901,8 @@ static hipError_t launch_cs_lds_nt(bool vec, dim3 grid, size_t lds, hipStream_t 
 template <typename T>
 hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t *code,
                          const int32_t *h, const int8_t *s, T *Y, int64_t ldy, bool zero_first,
-                         int *status, hipStream_t st, const CsTuning *tune) {
+                         int *status, hipStream_t st, const CsTuning *tune, void *part,
+                         size_t part_bytes) {
   hipError_t e = zero_first ? launch_fill_zero<T>(Y, k, c.ncols, ldy, st) : hipSuccess;
   if (e != hipSuccess || d <= 0 || c.ncols <= 0) return e;
   const DevInfo &di = dev_info();
@@ -855,13 +944,19 @@ hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t 
     if (nbt > spx) return hipErrorNotSupported;
     const int64_t nct = (c.ncols + nt - 1) / nt;
     const int grid = xcds * spx;
+    // the per-die partial schedule, when the caller's buffer holds it and the
+    // device is the one its shape was chosen for
+    const size_t need = cs_part_bytes(d, k, c.ncols, wd);
+    T *pb = (part && need && part_bytes >= need && xcds == 8 && spx == 32 && nt == 1)
+                ? static_cast<T *>(part)
+                : nullptr;
 #define MS_XCD_CASE(NT_)                                                                         \
   if (nt == NT_)                                                                                 \
     return code ? launch_cs_xcd_v<T, NT_, true>(vec, grid, lds, st, d, c, code, h, s, k, ktile,   \
-                                                (int)nct, (int)nbt, xcds, spx, rpx, Y, ldy,      \
+                                                (int)nct, (int)nbt, xcds, spx, rpx, Y, ldy, pb,  \
                                                 status)                                          \
                 : launch_cs_xcd_v<T, NT_, false>(vec, grid, lds, st, d, c, code, h, s, k, ktile,  \
-                                                 (int)nct, (int)nbt, xcds, spx, rpx, Y, ldy,     \
+                                                 (int)nct, (int)nbt, xcds, spx, rpx, Y, ldy, pb, \
                                                  status);
     MS_XCD_CASE(8)
     MS_XCD_CASE(4)
@@ -902,10 +997,10 @@ hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t 
 }
 template hipError_t launch_cs_lds<double>(int64_t, int64_t, const Cols<double> &, const uint32_t *,
                                           const int32_t *, const int8_t *, double *, int64_t, bool,
-                                          int *, hipStream_t, const CsTuning *);
+                                          int *, hipStream_t, const CsTuning *, void *, size_t);
 template hipError_t launch_cs_lds<float>(int64_t, int64_t, const Cols<float> &, const uint32_t *,
                                          const int32_t *, const int8_t *, float *, int64_t, bool,
-                                         int *, hipStream_t, const CsTuning *);
+                                         int *, hipStream_t, const CsTuning *, void *, size_t);
 
 // ------------------------------------------------------------------ sorted (deterministic)
 

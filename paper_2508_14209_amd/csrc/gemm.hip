@@ -198,6 +198,132 @@ __device__ __forceinline__ void gemm_tile(int M, int N, const typename Mf<DT>::T
     }
 }
 
+// BF16 tile staged through LDS.  G is stored with its rows contiguous, but a
+// matrix-core fragment holds 8 consecutive k of one row, so G's tile (64 rows
+// x 64 k) is loaded with 16-byte loads along the rows and written to LDS
+// transposed (row-major, k contiguous); Y's tile (64 k x 64 columns, FP32,
+// k contiguous) is rounded to BF16 and written as is.  Two LDS buffers: the
+// next stage's global loads are in flight while the current stage runs on
+// the matrix cores.  The k steps (32 each) run in the same order as in
+// gemm_tile, so the partial sums are the same.
+constexpr int kStK = 64, kStPad = 72;  // k per stage; LDS row stride (BF16 elements)
+
+__device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned short *__restrict__ G,
+                                                   int64_t ldg, const float *__restrict__ Y,
+                                                   int64_t ldy, float *__restrict__ P, int64_t kb,
+                                                   int64_t ke, int m_tile, int n_tile) {
+  __shared__ __align__(16) unsigned short As[2][64 * kStPad];
+  __shared__ __align__(16) unsigned short Bs[2][64 * kStPad];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int m0 = m_tile * 64, n0 = n_tile * 64;
+  // global-load roles: G column kk, rows gr .. gr+15; Y column yc, k yk .. yk+15
+  const int kk = tid >> 2, gr = (tid & 3) * 16;
+  const int yc = tid >> 2, yk = (tid & 3) * 16;
+  const bool gvec = (ldg & 7) == 0 && ((uintptr_t)G & 15) == 0 && m0 + gr + 16 <= M;
+  const bool yvec = (ldy & 3) == 0 && ((uintptr_t)Y & 15) == 0 && n0 + yc < N;
+  unsigned short gv[16];
+  float yv[16];
+  auto gload = [&](int64_t k0) {
+    const int64_t kc = k0 + kk;
+    if (kc < ke && gvec) {
+      const v8u16 a = *reinterpret_cast<const v8u16 *>(G + (m0 + gr) + kc * ldg);
+      const v8u16 b = *reinterpret_cast<const v8u16 *>(G + (m0 + gr + 8) + kc * ldg);
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        gv[r] = a[r];
+        gv[8 + r] = b[r];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        gv[r] = (kc < ke && m0 + gr + r < M) ? G[(m0 + gr + r) + kc * ldg] : (unsigned short)0;
+    }
+    const int64_t kq = k0 + yk;
+    if (yvec && kq + 16 <= ke) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const v4f v = *reinterpret_cast<const v4f *>(Y + kq + 4 * q + (int64_t)(n0 + yc) * ldy);
+        yv[4 * q] = v[0];
+        yv[4 * q + 1] = v[1];
+        yv[4 * q + 2] = v[2];
+        yv[4 * q + 3] = v[3];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        yv[u] = (n0 + yc < N && kq + u < ke) ? Y[kq + u + (int64_t)(n0 + yc) * ldy] : 0.0f;
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) As[buf][(gr + r) * kStPad + kk] = gv[r];
+    v8u16 b0, b1;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      b0[u] = f32_to_bf16_rne(yv[u]);
+      b1[u] = f32_to_bf16_rne(yv[8 + u]);
+    }
+    *reinterpret_cast<v8u16 *>(&Bs[buf][yc * kStPad + yk]) = b0;
+    *reinterpret_cast<v8u16 *>(&Bs[buf][yc * kStPad + yk + 8]) = b1;
+  };
+  const int m_base = (wave & 1) * 32, n_base = (wave >> 1) * 32;
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{};
+  gload(kb);
+  lstore(0);
+  __syncthreads();
+  int buf = 0;
+  for (int64_t k0 = kb; k0 < ke; k0 += kStK) {
+    const bool more = k0 + kStK < ke;
+    if (more) gload(k0 + kStK);
+#pragma unroll
+    for (int ks = 0; ks < kStK / 32; ++ks) {
+      v8bf a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        a[i] = *reinterpret_cast<const v8bf *>(&As[buf][(m_base + 16 * i + li) * kStPad + ks * 32 + lk * 8]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        b[j] = *reinterpret_cast<const v8bf *>(&Bs[buf][(n_base + 16 * j + li) * kStPad + ks * 32 + lk * 8]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) lstore(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + n_base + 16 * j + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + m_base + 16 * i + 4 * lk + r;
+        if (row < M && col < N) P[row + (int64_t)col * M] = acc[i][j][r];
+      }
+    }
+}
+
+// The tile of either kind: LDS-staged for BF16, direct fragment loads else.
+template <int DT>
+__device__ __forceinline__ void gemm_tile_any(int M, int N, const typename Mf<DT>::TG *__restrict__ G,
+                                              int64_t ldg, const typename Mf<DT>::TY *__restrict__ Y,
+                                              int64_t ldy, typename Mf<DT>::Acc *__restrict__ P,
+                                              int64_t kb, int64_t ke, int m_tile, int n_tile) {
+  if constexpr (DT == DT_BF16)
+    gemm_tile_lds_bf16(M, N, G, ldg, Y, ldy, P, kb, ke, m_tile, n_tile);
+  else
+    gemm_tile<DT>(M, N, G, ldg, Y, ldy, P, kb, ke, m_tile, n_tile);
+}
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
                                                      const typename Mf<DT>::TG *__restrict__ G,
@@ -208,8 +334,8 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
                                                      int64_t kchunk) {
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = min(K, kb + kchunk);
-  gemm_tile<DT>(M, N, G, ldg, Y, ldy, part + (int64_t)blockIdx.z * M * N, kb, ke, blockIdx.x,
-                blockIdx.y);
+  gemm_tile_any<DT>(M, N, G, ldg, Y, ldy, part + (int64_t)blockIdx.z * M * N, kb, ke, blockIdx.x,
+                    blockIdx.y);
 }
 
 // Z[p, c] = sum over splits (in split order) of the partials; written to Z
@@ -263,7 +389,8 @@ __global__ __launch_bounds__(256) void k_batch_gemm(int count, const ms_problem 
     const int64_t kb = (int64_t)split * e.kchunk, ke = min(Q.k, kb + e.kchunk);
     const auto *Y = reinterpret_cast<const typename F::TY *>(yarea + e.y_off);
     auto *Pz = reinterpret_cast<typename F::Acc *>(parea + e.part_off) + (int64_t)split * M * N;
-    gemm_tile<DT>(M, N, static_cast<const typename F::TG *>(Q.G), Q.ldg, Y, Q.k, Pz, kb, ke, tm, tn);
+    gemm_tile_any<DT>(M, N, static_cast<const typename F::TG *>(Q.G), Q.ldg, Y, Q.k, Pz, kb, ke, tm,
+                      tn);
   }
 }
 
@@ -410,36 +537,6 @@ __device__ __forceinline__ double g_as_f64<unsigned short>(unsigned short v) {
 }
 
 template <typename TG>
-__global__ __launch_bounds__(256) void k_gemv64_splitk(int M, int N, int64_t K,
-                                                       const TG *__restrict__ G, int64_t ldg,
-                                                       const double *__restrict__ Y, int64_t ldy,
-                                                       double *__restrict__ part, int64_t kchunk) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t kb = (int64_t)blockIdx.y * kchunk;
-  const int64_t ke = min(K, kb + kchunk);
-  double acc[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-  if (p < M) {
-    for (int64_t m = kb; m < ke; ++m) {
-      const double g = g_as_f64<TG>(G[p + m * ldg]);
-#pragma unroll
-      for (int c = 0; c < 8; ++c)
-        if (c < N) acc[c] += g * Y[m + (int64_t)c * ldy];
-    }
-    double *P = part + (int64_t)blockIdx.y * M * N;
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-      if (c < N) P[p + (int64_t)c * M] = acc[c];
-  }
-}
-
-// Refinement of a batch: partials of G Yr in FP64 (G's values promoted
-// exactly), item = (problem, K split).  Each thread owns four rows of G; the
-// 256 threads form 256 / L slots (L = ceil(k2 / 4) threads per column of G)
-// that take the split's columns round-robin; Yr is staged in LDS 1024 rows at
-// a time, and the slots' sums are added in slot order at the end.
-template <typename TG>
 __device__ __forceinline__ void g_rows4(const TG *g, bool vec, int nvalid, double v[4]) {
   if (vec) {
     typedef TG V __attribute__((ext_vector_type(4)));
@@ -454,6 +551,74 @@ __device__ __forceinline__ void g_rows4(const TG *g, bool vec, int nvalid, doubl
   }
 }
 
+// Split-K partials of G Y in FP64 for narrow Y (N <= 8 columns; G's values
+// promoted exactly): block (row tile of 256 rows, K split).  Each thread owns
+// four rows; the block's threads form 256 / L slots (L threads per column of
+// the tile) that take the split's columns round-robin, Y's rows staged in LDS
+// 1024 at a time; the slots' sums are added in slot order.
+template <typename TG>
+__global__ __launch_bounds__(256) void k_gemv64_splitk(int M, int N, int64_t K,
+                                                       const TG *__restrict__ G, int64_t ldg,
+                                                       const double *__restrict__ Y, int64_t ldy,
+                                                       double *__restrict__ part, int64_t kchunk) {
+  constexpr int RH = 8, CH = 1024;
+  __shared__ double buf[CH * RH];
+  const int mt0 = blockIdx.x * 256;
+  const int rows = min(256, M - mt0);
+  const int L = (rows + 3) / 4, S = (int)blockDim.x / L;
+  const int rg = (int)threadIdx.x % L, slot = (int)threadIdx.x / L;
+  const int row0 = mt0 + 4 * rg, nvalid = min(4, M - row0);
+  const bool active = slot < S;
+  const int64_t kb = (int64_t)blockIdx.y * kchunk, ke = min(K, kb + kchunk);
+  const bool vec = nvalid == 4 && (ldg & 3) == 0 && ((uintptr_t)G & (4 * sizeof(TG) - 1)) == 0;
+  double acc[4][RH];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < RH; ++c) acc[q][c] = 0.0;
+  for (int64_t c0 = kb; c0 < ke; c0 += CH) {
+    const int len = (int)min((int64_t)CH, ke - c0);
+    __syncthreads();
+    for (int t = threadIdx.x; t < len * N; t += blockDim.x) {
+      const int c = t / len, m = t - c * len;
+      buf[m * RH + c] = Y[c0 + m + (int64_t)c * ldy];
+    }
+    __syncthreads();
+    if (active)
+      for (int m = slot; m < len; m += S) {
+        double g[4];
+        g_rows4<TG>(G + row0 + (c0 + m) * ldg, vec, nvalid, g);
+#pragma unroll
+        for (int c = 0; c < RH; ++c)
+          if (c < N) {
+            const double y = buf[m * RH + c];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q][c] += g[q] * y;
+          }
+      }
+  }
+  __syncthreads();
+  if (active)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < RH; ++c)
+        if (c < N) buf[((int64_t)slot * 4 * L + 4 * rg + q) * RH + c] = acc[q][c];
+  __syncthreads();
+  double *P = part + (int64_t)blockIdx.y * M * N;
+  for (int t = threadIdx.x; t < rows * N; t += blockDim.x) {
+    const int c = t / rows, rr = t - c * rows;
+    double s = buf[rr * RH + c];
+    for (int z = 1; z < S; ++z) s += buf[((int64_t)z * 4 * L + rr) * RH + c];
+    P[mt0 + rr + (int64_t)c * M] = s;
+  }
+}
+
+// Refinement of a batch: partials of G Yr in FP64 (G's values promoted
+// exactly), item = (problem, K split).  Each thread owns four rows of G; the
+// 256 threads form 256 / L slots (L = ceil(k2 / 4) threads per column of G)
+// that take the split's columns round-robin; Yr is staged in LDS 1024 rows at
+// a time, and the slots' sums are added in slot order at the end.
 template <typename TG>
 __global__ __launch_bounds__(256) void k_batch_gemv(int count, const ms_problem *__restrict__ P,
                                                     const BatchEntry *__restrict__ E,

@@ -111,7 +111,11 @@ struct CsTuning {
 template <typename T>
 hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t *code,
                          const int32_t *h, const int8_t *s, T *Y, int64_t ldy, bool zero_first,
-                         int *status, hipStream_t st, const CsTuning *tune = nullptr);
+                         int *status, hipStream_t st, const CsTuning *tune = nullptr,
+                         void *part = nullptr, size_t part_bytes = 0);
+// Bytes of the optional per-die partial buffer of launch_cs_lds (0 when the
+// per-die partial schedule does not pay for this shape); wd = element bytes.
+size_t cs_part_bytes(int64_t d, int64_t k, int64_t ncols, int64_t wd);
 template <typename T>
 hipError_t launch_cs_sorted(int64_t k, const Cols<T> &c, const int32_t *off,
                             const uint32_t *sperm, T *Y, int64_t ldy, hipStream_t st);
@@ -183,7 +187,7 @@ struct BatchEntry {
   int32_t rnt, rntiles, rnbt, pad1;
 };
 
-constexpr int64_t kBatchResRows = 1024;  // rows per residual work item (4 per thread)
+constexpr int64_t kBatchResRows = 2048;  // rows per residual work item
 constexpr int kBatchMaxRefineRhs = 8;
 
 constexpr int64_t kBatchLdsSlots = 16384;  // FP64 partial sums per workgroup (128 KB)

@@ -217,7 +217,9 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, int nrhs, const double
   auto &taubuf = sh.taubuf;
   int &s_singular = sh.singular;
   const int nc = n + nrhs;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  // uniform across a wave; saying so keeps the per-column conditions scalar
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t MN = (int64_t)m * nc;
 
   double a[CPW][RPL];
@@ -878,9 +880,116 @@ __global__ __launch_bounds__(1024) void k_qr_apply_solve(int m, int n, int nrhs,
   }
 }
 
+// The same for m <= 64 * RPL with each right-hand side in one wave's
+// registers (lane l rows l + 64 r); the next reflector, and in the back
+// substitution the next column of R, are loaded while the current one is
+// applied.  Bm is left unchanged.
+template <int RPL>
+__global__ __launch_bounds__(512) void k_qr_apply_solve_reg(int m, int n, int nrhs,
+                                                             const double *__restrict__ fact,
+                                                             const double *__restrict__ tau,
+                                                             const double *__restrict__ Bm,
+                                                             double *__restrict__ X, int64_t ldx,
+                                                             int *status) {
+  __shared__ int s_singular;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (threadIdx.x == 0) s_singular = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double r = fact[i + (int64_t)i * m];
+    if (r == 0.0 || !isfinite(r)) s_singular = 1;
+  }
+  __syncthreads();
+  if (s_singular) {
+    for (int64_t t = threadIdx.x; t < (int64_t)n * nrhs; t += blockDim.x) {
+      const int c = (int)(t / n), i = (int)(t - (int64_t)c * n);
+      X[i + (int64_t)c * ldx] = __longlong_as_double(0x7ff8000000000000LL);
+    }
+    if (threadIdx.x == 0) record_status(status, MS_ERR_SINGULAR);
+    return;
+  }
+  auto load_v = [&](int j, double v[RPL]) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lane + 64 * r;
+      v[r] = (i > j && i < m) ? fact[i + (int64_t)j * m] : (i == j ? 1.0 : 0.0);
+    }
+  };
+  auto load_r = [&](int i, double col[RPL]) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int t = lane + 64 * r;
+      col[r] = t <= i ? fact[t + (int64_t)i * m] : 0.0;
+    }
+  };
+  for (int c = wave; c < nrhs; c += nw) {
+    double y[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = lane + 64 * r;
+      y[r] = i < m ? Bm[i + (int64_t)c * m] : 0.0;
+    }
+    double vn[RPL], tn = tau[0];
+    load_v(0, vn);
+    for (int j = 0; j < n; ++j) {
+      double v[RPL];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) v[r] = vn[r];
+      const double tj = tn;
+      if (j + 1 < n) {
+        load_v(j + 1, vn);
+        tn = tau[j + 1];
+      }
+      if (tj == 0.0) continue;
+      double dot = 0.0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) dot += v[r] * y[r];
+      const double w = tj * wave_allsum(dot);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) y[r] -= w * v[r];
+    }
+    double rn[RPL];
+    load_r(n - 1, rn);
+    for (int i = n - 1; i >= 0; --i) {
+      double col[RPL];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) col[r] = rn[r];
+      if (i > 0) load_r(i - 1, rn);
+      double yl = 0.0, dl = 0.0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r)
+        if (r == (i >> 6)) {
+          yl = y[r];
+          dl = col[r];
+        }
+      const double xi = read_lane(yl, i & 63) / read_lane(dl, i & 63);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int t = lane + 64 * r;
+        if (t < i) y[r] -= col[r] * xi;
+      }
+      if (lane == 0) X[i + (int64_t)c * ldx] = xi;
+    }
+  }
+}
+
 hipError_t launch_qr_apply_solve(int64_t m, int64_t n, int64_t nrhs, const double *fact,
                                  const double *tau, double *Bm, double *X, int64_t ldx,
                                  int *status, hipStream_t st) {
+  if (n < 1 || nrhs < 1) return hipSuccess;
+  const unsigned threads = (unsigned)(64 * std::min<int64_t>(nrhs, 8));
+#define MS_AS_CASE(R_)                                                                         \
+  if (m <= 64 * R_) {                                                                         \
+    hipLaunchKernelGGL(k_qr_apply_solve_reg<R_>, dim3(1), dim3(threads), 0, st, (int)m, (int)n, \
+                       (int)nrhs, fact, tau, (const double *)Bm, X, ldx, status);              \
+    return hipGetLastError();                                                                 \
+  }
+  MS_AS_CASE(1)
+  MS_AS_CASE(2)
+  MS_AS_CASE(4)
+  MS_AS_CASE(8)
+  MS_AS_CASE(16)
+#undef MS_AS_CASE
   hipLaunchKernelGGL(k_qr_apply_solve, dim3(1), dim3(1024), 0, st, (int)m, (int)n, (int)nrhs,
                      fact, tau, Bm, X, ldx, status);
   return hipGetLastError();

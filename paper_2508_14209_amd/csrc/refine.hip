@@ -1,60 +1,17 @@
 // refine.hip -- FP64 residual of the mixed-precision least-squares path.
 //
-// r = B - A X in FP64: A (d x n, FP32 or FP64, column-major) is promoted exactly,
-// X (n x nrhs) and B are FP64/FP32, every product and sum is FP64.  One
-// thread per row; for each column j of A the threads of a wave read 64
-// consecutive rows (coalesced) and X[j, :] is a broadcast load.
+// r = B - A X in FP64: A (d x n, FP32 or FP64, column-major) is promoted
+// exactly, X (n x nrhs) is FP64, B has A's type, every product and sum is
+// FP64.  Each thread takes four consecutive rows with one 16-byte load per
+// column of A (a wave reads 1 KB of a column at a time) and keeps the 4 x
+// nrhs sums in registers; X is staged in LDS.
 #include <algorithm>
 
 #include "ms_internal.h"
 
 namespace ms {
 
-template <typename TA, typename TB>
-__global__ __launch_bounds__(256) void k_residual(int64_t d, int n, int nrhs,
-                                                  const TA *__restrict__ A, int64_t lda,
-                                                  const TB *__restrict__ B, int64_t ldb,
-                                                  const double *__restrict__ X, int64_t ldx,
-                                                  double *__restrict__ r, int64_t ldr) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d) return;
-  double acc[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
-  for (int j = 0; j < n; ++j) {
-    const double a = (double)A[i + (int64_t)j * lda];
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-      if (c < nrhs) acc[c] += a * X[j + (int64_t)c * ldx];
-  }
-#pragma unroll
-  for (int c = 0; c < 8; ++c)
-    if (c < nrhs) r[i + (int64_t)c * ldr] = (double)B[i + (int64_t)c * ldb] - acc[c];
-}
-
-hipError_t launch_residual_f32(int64_t d, int64_t n, int64_t nrhs, const float *A, int64_t lda,
-                               const float *B, int64_t ldb, const double *X, int64_t ldx,
-                               double *r, int64_t ldr, hipStream_t st) {
-  if (nrhs > 8) return hipErrorInvalidValue;
-  if (d <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_residual<float, float>), dim3((unsigned)((d + 255) / 256)), dim3(256), 0,
-                     st, d, (int)n, (int)nrhs, A, lda, B, ldb, X, ldx, r, ldr);
-  return hipGetLastError();
-}
-
-hipError_t launch_residual_f64(int64_t d, int64_t n, int64_t nrhs, const double *A, int64_t lda,
-                               const double *B, int64_t ldb, const double *X, int64_t ldx,
-                               double *r, int64_t ldr, hipStream_t st) {
-  if (nrhs > 8) return hipErrorInvalidValue;
-  if (d <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_residual<double, double>), dim3((unsigned)((d + 255) / 256)), dim3(256),
-                     0, st, d, (int)n, (int)nrhs, A, lda, B, ldb, X, ldx, r, ldr);
-  return hipGetLastError();
-}
-
-// Residuals of a batch: item = (problem, kBatchResRows rows), four rows per
-// thread (16-byte loads of A and B when aligned), X staged in LDS; B has A's
-// type.  r_p is d x nrhs, column-major, ld d.
+// Four consecutive rows of a column, promoted to FP64 (16-byte aligned).
 template <typename TA>
 struct Rows4 {
   static __device__ __forceinline__ void load(const TA *p, double v[4]) {
@@ -79,8 +36,123 @@ struct Rows4<double> {
   }
 };
 
+constexpr int kResXlds = 8192;  // doubles of X staged in LDS (64 KB)
+
+template <typename TA, bool XLDS>
+__global__ __launch_bounds__(256) void k_residual(int64_t d, int n, int nrhs,
+                                                  const TA *__restrict__ A, int64_t lda,
+                                                  const TA *__restrict__ B, int64_t ldb,
+                                                  const double *__restrict__ X, int64_t ldx,
+                                                  double *__restrict__ r, int64_t ldr) {
+  constexpr int RH = 8;
+  __shared__ double xs[XLDS ? kResXlds : 1];  // xs[j * RH + c] = X[j, c]
+  if (XLDS) {
+    for (int t = threadIdx.x; t < n * nrhs; t += blockDim.x) {
+      const int c = t / n, j = t - c * n;
+      xs[j * RH + c] = X[j + (int64_t)c * ldx];
+    }
+    __syncthreads();
+  }
+  auto xv = [&](int j, int c) { return XLDS ? xs[j * RH + c] : X[j + (int64_t)c * ldx]; };
+  const bool aligned = ((lda | ldb) & 3) == 0 && (((uintptr_t)A | (uintptr_t)B) & 15) == 0;
+  for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i0 < d;
+       i0 += (int64_t)gridDim.x * blockDim.x * 4) {
+    const bool vec = aligned && i0 + 4 <= d;
+    const int rows = (int)min((int64_t)4, d - i0);
+    double acc[4][RH];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < RH; ++c) acc[q][c] = 0.0;
+    if (vec) {
+      int j = 0;
+      for (; j + 4 <= n; j += 4) {
+        double a[4][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) Rows4<TA>::load(A + i0 + (int64_t)(j + u) * lda, a[u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int c = 0; c < RH; ++c)
+            if (c < nrhs) {
+              const double x = xv(j + u, c);
+#pragma unroll
+              for (int q = 0; q < 4; ++q) acc[q][c] += a[u][q] * x;
+            }
+      }
+      for (; j < n; ++j) {
+        double a[4];
+        Rows4<TA>::load(A + i0 + (int64_t)j * lda, a);
+#pragma unroll
+        for (int c = 0; c < RH; ++c)
+          if (c < nrhs) {
+            const double x = xv(j, c);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q][c] += a[q] * x;
+          }
+      }
+#pragma unroll
+      for (int c = 0; c < RH; ++c)
+        if (c < nrhs) {
+          double b[4];
+          Rows4<TA>::load(B + i0 + (int64_t)c * ldb, b);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) r[i0 + q + (int64_t)c * ldr] = b[q] - acc[q][c];
+        }
+    } else {
+      for (int j = 0; j < n; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q < rows) {
+            const double a = (double)A[i0 + q + (int64_t)j * lda];
+#pragma unroll
+            for (int c = 0; c < RH; ++c)
+              if (c < nrhs) acc[q][c] += a * xv(j, c);
+          }
+#pragma unroll
+      for (int c = 0; c < RH; ++c)
+        if (c < nrhs)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (q < rows) r[i0 + q + (int64_t)c * ldr] = (double)B[i0 + q + (int64_t)c * ldb] - acc[q][c];
+    }
+  }
+}
+
 template <typename TA>
-__global__ __launch_bounds__(kBatchResRows / 4) void k_batch_residual(
+static hipError_t launch_residual_t(int64_t d, int64_t n, int64_t nrhs, const TA *A, int64_t lda,
+                                    const TA *B, int64_t ldb, const double *X, int64_t ldx,
+                                    double *r, int64_t ldr, hipStream_t st) {
+  if (nrhs > 8) return hipErrorInvalidValue;
+  if (d <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>((d + 1023) / 1024, (int64_t)dev_info().cus * 8);
+  if (n * 8 <= kResXlds)
+    hipLaunchKernelGGL((k_residual<TA, true>), dim3(grid), dim3(256), 0, st, d, (int)n, (int)nrhs,
+                       A, lda, B, ldb, X, ldx, r, ldr);
+  else
+    hipLaunchKernelGGL((k_residual<TA, false>), dim3(grid), dim3(256), 0, st, d, (int)n,
+                       (int)nrhs, A, lda, B, ldb, X, ldx, r, ldr);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_f32(int64_t d, int64_t n, int64_t nrhs, const float *A, int64_t lda,
+                               const float *B, int64_t ldb, const double *X, int64_t ldx,
+                               double *r, int64_t ldr, hipStream_t st) {
+  return launch_residual_t<float>(d, n, nrhs, A, lda, B, ldb, X, ldx, r, ldr, st);
+}
+
+hipError_t launch_residual_f64(int64_t d, int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                               const double *B, int64_t ldb, const double *X, int64_t ldx,
+                               double *r, int64_t ldr, hipStream_t st) {
+  return launch_residual_t<double>(d, n, nrhs, A, lda, B, ldb, X, ldx, r, ldr, st);
+}
+
+// Residuals of a batch: item = (problem, kBatchResRows rows) taken in
+// sub-blocks of 1024 rows, four rows per thread (16-byte loads of A and B
+// when aligned), X staged in LDS once per item; B has A's type.  r_p is
+// d x nrhs, column-major, ld d.
+template <typename TA>
+__global__ __launch_bounds__(256) void k_batch_residual(
     int count, const ms_problem *__restrict__ P, const BatchEntry *__restrict__ E,
     const BatchTotals *__restrict__ tot, unsigned char *__restrict__ rarea) {
   constexpr int RH = kBatchMaxRefineRhs;
@@ -97,71 +169,73 @@ __global__ __launch_bounds__(kBatchResRows / 4) void k_batch_residual(
       xs[j * RH + c] = Q.X[j + (int64_t)c * Q.ldx];
     }
     __syncthreads();
-    const int64_t i0 = (it - e.res_start) * kBatchResRows + (int64_t)threadIdx.x * 4;
-    if (i0 >= Q.d) continue;
-    const TA *A = static_cast<const TA *>(Q.A);
-    const TA *B = static_cast<const TA *>(Q.B);
-    double *r = reinterpret_cast<double *>(rarea + e.r_off);
-    const bool vec = i0 + 4 <= Q.d && ((Q.lda | Q.ldb) & 3) == 0 &&
-                     (((uintptr_t)A | (uintptr_t)B) & 15) == 0;
-    const int rows = (int)min((int64_t)4, Q.d - i0);
-    double acc[4][RH];
+    for (int64_t sub = 0; sub < kBatchResRows; sub += 4 * (int64_t)blockDim.x) {
+      const int64_t i0 = (it - e.res_start) * kBatchResRows + sub + (int64_t)threadIdx.x * 4;
+      if (i0 >= Q.d) break;
+      const TA *A = static_cast<const TA *>(Q.A);
+      const TA *B = static_cast<const TA *>(Q.B);
+      double *r = reinterpret_cast<double *>(rarea + e.r_off);
+      const bool vec = i0 + 4 <= Q.d && ((Q.lda | Q.ldb) & 3) == 0 &&
+                       (((uintptr_t)A | (uintptr_t)B) & 15) == 0;
+      const int rows = (int)min((int64_t)4, Q.d - i0);
+      double acc[4][RH];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int c = 0; c < RH; ++c) acc[q][c] = 0.0;
-    if (vec) {
-      int j = 0;
-      for (; j + 4 <= n; j += 4) {
-        double a[4][4];
+        for (int c = 0; c < RH; ++c) acc[q][c] = 0.0;
+      if (vec) {
+        int j = 0;
+        for (; j + 4 <= n; j += 4) {
+          double a[4][4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) Rows4<TA>::load(A + i0 + (int64_t)(j + u) * Q.lda, a[u]);
+          for (int u = 0; u < 4; ++u) Rows4<TA>::load(A + i0 + (int64_t)(j + u) * Q.lda, a[u]);
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+          for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < RH; ++c)
+              if (c < nrhs) {
+                const double x = xs[(j + u) * RH + c];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q][c] += a[u][q] * x;
+              }
+        }
+        for (; j < n; ++j) {
+          double a[4];
+          Rows4<TA>::load(A + i0 + (int64_t)j * Q.lda, a);
 #pragma unroll
           for (int c = 0; c < RH; ++c)
             if (c < nrhs) {
-              const double x = xs[(j + u) * RH + c];
+              const double x = xs[j * RH + c];
 #pragma unroll
-              for (int q = 0; q < 4; ++q) acc[q][c] += a[u][q] * x;
+              for (int q = 0; q < 4; ++q) acc[q][c] += a[q] * x;
             }
-      }
-      for (; j < n; ++j) {
-        double a[4];
-        Rows4<TA>::load(A + i0 + (int64_t)j * Q.lda, a);
+        }
 #pragma unroll
         for (int c = 0; c < RH; ++c)
           if (c < nrhs) {
-            const double x = xs[j * RH + c];
+            double b[4];
+            Rows4<TA>::load(B + i0 + (int64_t)c * Q.ldb, b);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q][c] += a[q] * x;
+            for (int q = 0; q < 4; ++q) r[i0 + q + (int64_t)c * Q.d] = b[q] - acc[q][c];
           }
-      }
-#pragma unroll
-      for (int c = 0; c < RH; ++c)
-        if (c < nrhs) {
-          double b[4];
-          Rows4<TA>::load(B + i0 + (int64_t)c * Q.ldb, b);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) r[i0 + q + (int64_t)c * Q.d] = b[q] - acc[q][c];
-        }
-    } else {
-      for (int j = 0; j < n; ++j)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (q < rows) {
-            const double a = (double)A[i0 + q + (int64_t)j * Q.lda];
-#pragma unroll
-            for (int c = 0; c < RH; ++c)
-              if (c < nrhs) acc[q][c] += a * xs[j * RH + c];
-          }
-#pragma unroll
-      for (int c = 0; c < RH; ++c)
-        if (c < nrhs)
+      } else {
+        for (int j = 0; j < n; ++j)
 #pragma unroll
           for (int q = 0; q < 4; ++q)
-            if (q < rows)
-              r[i0 + q + (int64_t)c * Q.d] = (double)B[i0 + q + (int64_t)c * Q.ldb] - acc[q][c];
+            if (q < rows) {
+              const double a = (double)A[i0 + q + (int64_t)j * Q.lda];
+#pragma unroll
+              for (int c = 0; c < RH; ++c)
+                if (c < nrhs) acc[q][c] += a * xs[j * RH + c];
+            }
+#pragma unroll
+        for (int c = 0; c < RH; ++c)
+          if (c < nrhs)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              if (q < rows)
+                r[i0 + q + (int64_t)c * Q.d] = (double)B[i0 + q + (int64_t)c * Q.ldb] - acc[q][c];
+      }
     }
   }
 }
@@ -170,8 +244,8 @@ template <typename TA>
 hipError_t launch_batch_residual(int count, const ms_problem *P, const BatchEntry *E,
                                  const BatchTotals *tot, unsigned char *rarea, int grid,
                                  hipStream_t st) {
-  hipLaunchKernelGGL(k_batch_residual<TA>, dim3(grid), dim3(kBatchResRows / 4), 0, st, count, P,
-                     E, tot, rarea);
+  hipLaunchKernelGGL(k_batch_residual<TA>, dim3(grid), dim3(256), 0, st, count, P, E, tot,
+                     rarea);
   return hipGetLastError();
 }
 template hipError_t launch_batch_residual<float>(int, const ms_problem *, const BatchEntry *,

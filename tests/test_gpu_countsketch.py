@@ -110,6 +110,25 @@ def test_countsketch_bucket_tiles(ms, orc, dtype, k):
     assert rel(to_host(Y), orc.countsketch(A, h, s, k)) <= (1e-12 if dtype == np.float64 else 1e-5)
 
 
+@pytest.mark.parametrize("d,n,k,dtype", [(300001, 20, 65536, np.float32),
+                                         (200000, 32, 32768, np.float64),
+                                         (1000, 8, 131072, np.float32)])
+def test_countsketch_die_partials(ms, orc, d, n, k, dtype):
+    # many buckets, few rows per bucket: each die stores its partial sums
+    # (one owner per column and bucket) and a second kernel adds the dies'
+    # slices; with 1000 rows only some dies hold rows
+    wd = np.dtype(dtype).itemsize
+    a_dt = ms.MS_F64 if dtype == np.float64 else ms.MS_F32
+    assert (ms.workspace_size("countsketch", d=d, n=n, k=k, a_dtype=a_dt, mode="lds")
+            - ms.workspace_size("countsketch", d=d, n=n, k=k, a_dtype=a_dt, mode="atomic")
+            >= 8 * k * n * wd)
+    print("countsketch die partials d=%d n=%d k=%d" % (d, n, k), flush=True)
+    A, h, s = _inputs(d, n, k, seed=9, dtype=dtype)
+    Y, ws = ms.countsketch_apply(to_dev(A), to_dev(h), to_dev(s), k, mode="lds")
+    ms.check_status(ws)
+    assert rel(to_host(Y), orc.countsketch(A, h, s, k)) <= (1e-12 if dtype == np.float64 else 1e-5)
+
+
 @pytest.mark.parametrize("mode", ["sorted", "lds", "atomic"])
 def test_countsketch_strided_lda(ms, orc, mode):
     # leading dimension not a multiple of the vector width: scalar path

