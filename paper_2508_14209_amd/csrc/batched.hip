@@ -180,16 +180,24 @@ __global__ __launch_bounds__(kSetupThreads) void k_batch_setup(
   }
 }
 
-// Clear the accumulators of all problems (the first y_bytes of the area, or
-// yr_bytes for the residual sketches).
-__global__ void k_batch_zero(const BatchTotals *__restrict__ tot, int residual,
-                             unsigned char *__restrict__ yarea) {
+// Clear the CountSketch outputs (Y, or Yr for the residual sketches) that
+// are accumulated with atomic adds: those of problems whose rows are split
+// over several items.  A problem of one row segment has each slot of its
+// output stored exactly once by the owner of its (column tile, bucket tile),
+// so it needs no clearing.  Workgroup row y takes problems y, y + gridDim.y, ...
+__global__ void k_batch_zero(int count, const ms_problem *__restrict__ P,
+                             const BatchEntry *__restrict__ E, int residual, int wdata,
+                             unsigned char *__restrict__ area) {
   typedef uint32_t u4 __attribute__((ext_vector_type(4)));
-  const int64_t n16 = (residual ? tot->yr_bytes : tot->y_bytes) / 16;
-  u4 *y = reinterpret_cast<u4 *>(yarea);
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n16;
-       t += (int64_t)gridDim.x * blockDim.x)
-    y[t] = u4{0u, 0u, 0u, 0u};
+  for (int p = blockIdx.y; p < count; p += gridDim.y) {
+    const BatchEntry &e = E[p];
+    if (!e.valid || e.nsegs <= 1) continue;
+    const int64_t bytes = residual ? batch_yr_bytes(P[p], e) : batch_y_bytes(P[p], e, wdata);
+    u4 *y = reinterpret_cast<u4 *>(area + (residual ? e.yr_off : e.y_off));
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < bytes / 16;
+         t += (int64_t)gridDim.x * blockDim.x)
+      y[t] = u4{0u, 0u, 0u, 0u};
+  }
 }
 
 bool valid_dtypes(ms_dtype a, ms_dtype g) {
@@ -305,13 +313,12 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
                      accw, rows_item_of(opts), kchunk_of(opts), refine > 0 ? 1 : 0, H.caps, E,
                      tot, pstatus, status);
   hipError_t e = hipGetLastError();
-  auto zero = [&](int residual, int64_t cap, unsigned char *area) {
-    const int64_t n16 = cap / 16;
-    const unsigned zb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n16 + 255) / 256, 8192));
-    hipLaunchKernelGGL(k_batch_zero, dim3(zb), dim3(256), 0, st, tot, residual, area);
+  auto zero = [&](int residual, unsigned char *area) {
+    hipLaunchKernelGGL(k_batch_zero, dim3(32, (unsigned)std::min(count, 2048)), dim3(256), 0, st,
+                       count, probs_dev, E, residual, wdata, area);
     return hipGetLastError();
   };
-  if (e == hipSuccess) e = zero(0, H.caps.y_bytes, yarea);
+  if (e == hipSuccess) e = zero(0, yarea);
   if (e == hipSuccess) {
     const int grid = di.cus;  // one 1024-thread workgroup per CU (128 KB of LDS each)
     e = a_dtype == MS_F64
@@ -327,7 +334,7 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
                         status, st);
   // refinement: r = B - A X (FP64); X += R^{-1} Q^T G (C r)
   for (int it = 0; it < refine && e == hipSuccess; ++it) {
-    e = zero(1, H.caps.yr_bytes, yrarea);
+    e = zero(1, yrarea);
     if (e == hipSuccess)
       e = a_dtype == MS_F64
               ? launch_batch_residual<double>(count, probs_dev, E, tot, rarea, di.cus * 8, st)

@@ -322,11 +322,15 @@ template hipError_t launch_cs_atomic<float>(int64_t, int64_t, const Cols<float> 
 
 // ------------------------------------------------------------------ LDS-binned
 
-// 16-byte vector types for the streaming loads.
+// 16-byte vector types for the streaming loads of the data columns, aligned
+// only to their element: a column of leading dimension d starts at any
+// element, and a dword-aligned multi-dword global load is legal on CDNA, so
+// every d takes the vector path (a wave's 1 KB then spans one more cache
+// line when the column start is not 16-byte aligned).
 template <typename T>
 struct Vec16;
-typedef double dvec2 __attribute__((ext_vector_type(2)));
-typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef double dvec2 __attribute__((ext_vector_type(2), aligned(8)));
+typedef float fvec4 __attribute__((ext_vector_type(4), aligned(4)));
 typedef uint32_t uvec2 __attribute__((ext_vector_type(2)));
 typedef uint32_t uvec4 __attribute__((ext_vector_type(4)));
 template <>
@@ -360,13 +364,15 @@ __device__ __forceinline__ uint32_t row_word(const uint32_t *__restrict__ code,
                                              const int8_t *__restrict__ s, int64_t i, int64_t k,
                                              bool &bad) {
   if (CODES) {
-    const uint32_t e = code[i];
+    const uint32_t e = gload(code + i);
     bad |= (int64_t)(e & kIdxMask) >= k;
     return e;
   }
-  const int32_t b = h[i];
-  const int8_t sg = s[i];
-  const bool ok = b >= 0 && (int64_t)b < k && (sg == 1 || sg == -1);
+  const int32_t b = gload(h + i);
+  const int8_t sg = gload(s + i);
+  // bitwise, not short-circuit: no branch per row (k < 2^31 is checked by
+  // every caller, so one unsigned compare covers 0 <= b < k)
+  const bool ok = ((uint32_t)b < (uint32_t)k) & ((sg == 1) | (sg == -1));
   bad |= !ok;
   return ok ? ((uint32_t)b | (sg < 0 ? kSignBit : 0u)) : 0xffffffffu;
 }
@@ -397,20 +403,20 @@ __device__ __forceinline__ void row_words(const uint32_t *__restrict__ code,
                                           uint32_t (&e)[W], bool &bad) {
   if (CODES) {
     using CV = typename Vec16<typename std::conditional<W == 2, double, float>::type>::code_t;
-    const CV v = *reinterpret_cast<const CV *>(code + i);
+    const CV v = gload(reinterpret_cast<const CV *>(code + i));
 #pragma unroll
     for (int q = 0; q < W; ++q) {
       e[q] = v[q];
       bad |= (int64_t)(e[q] & kIdxMask) >= k;
     }
   } else {
-    const typename HsVec<W>::hv hv = *reinterpret_cast<const typename HsVec<W>::hv *>(h + i);
-    const typename HsVec<W>::sv sv = *reinterpret_cast<const typename HsVec<W>::sv *>(s + i);
+    const typename HsVec<W>::hv hv = gload(reinterpret_cast<const typename HsVec<W>::hv *>(h + i));
+    const typename HsVec<W>::sv sv = gload(reinterpret_cast<const typename HsVec<W>::sv *>(s + i));
 #pragma unroll
     for (int q = 0; q < W; ++q) {
       const int32_t b = hv[q];
       const int8_t sg = sv[q];
-      const bool ok = b >= 0 && (int64_t)b < k && (sg == 1 || sg == -1);
+      const bool ok = ((uint32_t)b < (uint32_t)k) & ((sg == 1) | (sg == -1));
       bad |= !ok;
       e[q] = ok ? ((uint32_t)b | (sg < 0 ? kSignBit : 0u)) : 0xffffffffu;
     }
@@ -458,8 +464,8 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
       V a0[NT], a1[NT];
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
-        a0[j] = __builtin_nontemporal_load(reinterpret_cast<const V *>(cp[j] + i));
-        a1[j] = __builtin_nontemporal_load(reinterpret_cast<const V *>(cp[j] + i + step));
+        a0[j] = gload_nt(reinterpret_cast<const V *>(cp[j] + i));
+        a1[j] = gload_nt(reinterpret_cast<const V *>(cp[j] + i + step));
       }
 #pragma unroll
       for (int q = 0; q < W; ++q) {
@@ -480,7 +486,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
         row_words<CODES, W>(code, h, s, i, k, e0, bad);
         V a0[NT];
 #pragma unroll
-        for (int j = 0; j < NT; ++j) a0[j] = *reinterpret_cast<const V *>(cp[j] + i);
+        for (int j = 0; j < NT; ++j) a0[j] = gload(reinterpret_cast<const V *>(cp[j] + i));
 #pragma unroll
         for (int q = 0; q < W; ++q) {
           const uint32_t l0 = (e0[q] & kIdxMask) - (uint32_t)b0;
@@ -494,7 +500,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
           const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
 #pragma unroll
           for (int j = 0; j < NT; ++j)
-            if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], (double)apply_sign(cp[j][r], e0));
+            if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], (double)apply_sign(gload(cp[j] + r), e0));
         }
       }
     }
@@ -504,7 +510,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
       const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
 #pragma unroll
       for (int j = 0; j < NT; ++j)
-        if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], (double)apply_sign(cp[j][r], e0));
+        if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], (double)apply_sign(gload(cp[j] + r), e0));
     }
   }
   if (bad) record_status(status, MS_ERR_RANGE);
@@ -537,7 +543,7 @@ __device__ __forceinline__ void cs_segment(double *acc, const Cols<T> &cols, int
     const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
 #pragma unroll
     for (int j = 0; j < NT; ++j)
-      if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], (double)apply_sign(cp[j][r], e0));
+      if (j < nc && l0 < kt) atomicAdd(&acc[l0 + j * kt], (double)apply_sign(gload(cp[j] + r), e0));
   };
   if (VEC) {
     using V = typename Vec16<T>::type;
@@ -556,8 +562,8 @@ __device__ __forceinline__ void cs_segment(double *acc, const Cols<T> &cols, int
       for (int u = 0; u < UNR; ++u)
 #pragma unroll
         for (int j = 0; j < NT; ++j)
-          a[u][j] = NTL ? __builtin_nontemporal_load(reinterpret_cast<const V *>(cp[j] + i + u * step))
-                        : *reinterpret_cast<const V *>(cp[j] + i + u * step);
+          a[u][j] = NTL ? gload_nt(reinterpret_cast<const V *>(cp[j] + i + u * step))
+                        : gload(reinterpret_cast<const V *>(cp[j] + i + u * step));
 #pragma unroll
       for (int u = 0; u < UNR; ++u)
 #pragma unroll
@@ -574,7 +580,7 @@ __device__ __forceinline__ void cs_segment(double *acc, const Cols<T> &cols, int
         row_words<CODES, W>(code, h, s, i, k, e0, bad);
         V a0[NT];
 #pragma unroll
-        for (int j = 0; j < NT; ++j) a0[j] = *reinterpret_cast<const V *>(cp[j] + i);
+        for (int j = 0; j < NT; ++j) a0[j] = gload(reinterpret_cast<const V *>(cp[j] + i));
 #pragma unroll
         for (int q = 0; q < W; ++q) {
           const uint32_t l0 = (e0[q] & kIdxMask) - (uint32_t)b0;
@@ -739,10 +745,12 @@ __global__ __launch_bounds__(1024) void k_batch_cs(int count, const ms_problem *
     Cols<T> cols;
     bool vec;
     T *Y;
+    const int32_t *hq = Q.h;
+    const int8_t *sq = Q.s;
     if (RES) {
       const T *r = reinterpret_cast<const T *>(rarea + e.r_off);
       cols = Cols<T>{r, Q.d, nullptr, 0, (int)Q.nrhs, (int)Q.nrhs};
-      vec = ((Q.d * (int64_t)sizeof(T)) & 15) == 0 && ((uintptr_t)Q.h & 15) == 0 &&
+      vec = ((uintptr_t)Q.h & 15) == 0 &&
             ((uintptr_t)Q.s & (uintptr_t)(16 / sizeof(T) - 1)) == 0;
       Y = reinterpret_cast<T *>(yarea + e.yr_off);
     } else {
@@ -756,13 +764,30 @@ __global__ __launch_bounds__(1024) void k_batch_cs(int count, const ms_problem *
     bool bad = false;
     // the tile width is a template argument, so narrow tiles issue no
     // loads for columns they do not have
-#define MS_BCS(NT_, UNR_)                                                                         \
+#define MS_BCS_W(NT_, UNR_, NTL_, PST_)                                                          \
   if (vec)                                                                                        \
-    cs_segment<T, NT_, true, false, UNR_, false>(acc, cols, c0, ncur, nullptr, Q.h, Q.s, Q.k, b0,  \
-                                                 kt, r0, r1, Y, Q.k, bad);                        \
+    cs_segment<T, NT_, true, false, UNR_, NTL_, PST_>(acc, cols, c0, ncur, nullptr, hq, sq, Q.k,   \
+                                                      b0, kt, r0, r1, Y, Q.k, bad);               \
   else                                                                                            \
-    cs_segment<T, NT_, false, false, UNR_, false>(acc, cols, c0, ncur, nullptr, Q.h, Q.s, Q.k, b0, \
-                                                  kt, r0, r1, Y, Q.k, bad);
+    cs_segment<T, NT_, false, false, UNR_, false, PST_>(acc, cols, c0, ncur, nullptr, hq, sq,      \
+                                                        Q.k, b0, kt, r0, r1, Y, Q.k, bad);
+    // with one bucket tile each column value is read once: nontemporal loads
+    // keep it from evicting the h and s of the segment, which the other
+    // column tiles read from L2.  With one row segment the item is the only
+    // writer of its tile of the output: plain stores, and the output needs
+    // no clearing beforehand.
+#define MS_BCS_V(NT_, UNR_, NTL_)         \
+  if (e.nsegs == 1) {                     \
+    MS_BCS_W(NT_, UNR_, NTL_, true)       \
+  } else {                                \
+    MS_BCS_W(NT_, UNR_, NTL_, false)      \
+  }
+#define MS_BCS(NT_, UNR_)            \
+  if (nbt == 1) {                    \
+    MS_BCS_V(NT_, UNR_, true)        \
+  } else {                           \
+    MS_BCS_V(NT_, UNR_, false)       \
+  }
     if (nt >= 4) {
       MS_BCS(4, 2)
     } else if (nt == 2) {
@@ -771,6 +796,8 @@ __global__ __launch_bounds__(1024) void k_batch_cs(int count, const ms_problem *
       MS_BCS(1, 4)
     }
 #undef MS_BCS
+#undef MS_BCS_V
+#undef MS_BCS_W
     if (bad) {
       record_status(&pstatus[p], MS_ERR_RANGE);
       record_status(status, MS_ERR_RANGE);
@@ -915,9 +942,9 @@ hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t 
     while (ktile * 2 * w <= cap) ktile *= 2;
   }
   const int64_t nbt = (k + ktile - 1) / ktile;
-  const uintptr_t mis = (reinterpret_cast<uintptr_t>(c.A) | reinterpret_cast<uintptr_t>(c.B) |
-                         (uintptr_t)(c.lda * wd) | (uintptr_t)(c.B ? c.ldb * wd : 0) |
-                         reinterpret_cast<uintptr_t>(code) | reinterpret_cast<uintptr_t>(h));
+  // the data columns need only element alignment (Vec16); the codes, or h
+  // and s, are loaded W rows at a time at multiples of W
+  const uintptr_t mis = reinterpret_cast<uintptr_t>(code) | reinterpret_cast<uintptr_t>(h);
   const uintptr_t smis = reinterpret_cast<uintptr_t>(s) & (uintptr_t)(16 / wd - 1);
   const bool vec = (mis & 15) == 0 && smis == 0;
   const bool grid_variant = tune && tune->grid_variant;

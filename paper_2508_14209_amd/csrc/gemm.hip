@@ -86,19 +86,19 @@ __device__ __forceinline__ typename Mf<DT>::Frag load_a(const typename Mf<DT>::T
 template <>
 __device__ __forceinline__ double load_a<DT_F64>(const double *G, int64_t ldg, int M, int row,
                                                  int64_t kq, int64_t ke) {
-  return (row < M && kq < ke) ? G[row + kq * ldg] : 0.0;
+  return (row < M && kq < ke) ? gload(G + row + kq * ldg) : 0.0;
 }
 template <>
 __device__ __forceinline__ float load_a<DT_F32>(const float *G, int64_t ldg, int M, int row,
                                                 int64_t kq, int64_t ke) {
-  return (row < M && kq < ke) ? G[row + kq * ldg] : 0.0f;
+  return (row < M && kq < ke) ? gload(G + row + kq * ldg) : 0.0f;
 }
 template <>
 __device__ __forceinline__ v8bf load_a<DT_BF16>(const unsigned short *G, int64_t ldg, int M,
                                                 int row, int64_t kq, int64_t ke) {
   v8u16 u;
 #pragma unroll
-  for (int t = 0; t < 8; ++t) u[t] = (row < M && kq + t < ke) ? G[row + (kq + t) * ldg] : 0;
+  for (int t = 0; t < 8; ++t) u[t] = (row < M && kq + t < ke) ? gload(G + row + (kq + t) * ldg) : 0;
   return __builtin_bit_cast(v8bf, u);
 }
 
@@ -224,11 +224,11 @@ __device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned 
   const bool yvec = (ldy & 3) == 0 && ((uintptr_t)Y & 15) == 0 && n0 + yc < N;
   unsigned short gv[16];
   float yv[16];
-  auto gload = [&](int64_t k0) {
+  auto fetch = [&](int64_t k0) {
     const int64_t kc = k0 + kk;
     if (kc < ke && gvec) {
-      const v8u16 a = *reinterpret_cast<const v8u16 *>(G + (m0 + gr) + kc * ldg);
-      const v8u16 b = *reinterpret_cast<const v8u16 *>(G + (m0 + gr + 8) + kc * ldg);
+      const v8u16 a = gload(reinterpret_cast<const v8u16 *>(G + (m0 + gr) + kc * ldg));
+      const v8u16 b = gload(reinterpret_cast<const v8u16 *>(G + (m0 + gr + 8) + kc * ldg));
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         gv[r] = a[r];
@@ -237,13 +237,13 @@ __device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned 
     } else {
 #pragma unroll
       for (int r = 0; r < 16; ++r)
-        gv[r] = (kc < ke && m0 + gr + r < M) ? G[(m0 + gr + r) + kc * ldg] : (unsigned short)0;
+        gv[r] = (kc < ke && m0 + gr + r < M) ? gload(G + (m0 + gr + r) + kc * ldg) : (unsigned short)0;
     }
     const int64_t kq = k0 + yk;
     if (yvec && kq + 16 <= ke) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const v4f v = *reinterpret_cast<const v4f *>(Y + kq + 4 * q + (int64_t)(n0 + yc) * ldy);
+        const v4f v = gload(reinterpret_cast<const v4f *>(Y + kq + 4 * q + (int64_t)(n0 + yc) * ldy));
         yv[4 * q] = v[0];
         yv[4 * q + 1] = v[1];
         yv[4 * q + 2] = v[2];
@@ -252,7 +252,7 @@ __device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned 
     } else {
 #pragma unroll
       for (int u = 0; u < 16; ++u)
-        yv[u] = (n0 + yc < N && kq + u < ke) ? Y[kq + u + (int64_t)(n0 + yc) * ldy] : 0.0f;
+        yv[u] = (n0 + yc < N && kq + u < ke) ? gload(Y + kq + u + (int64_t)(n0 + yc) * ldy) : 0.0f;
     }
   };
   auto lstore = [&](int buf) {
@@ -273,13 +273,13 @@ __device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned 
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{};
-  gload(kb);
+  fetch(kb);
   lstore(0);
   __syncthreads();
   int buf = 0;
   for (int64_t k0 = kb; k0 < ke; k0 += kStK) {
     const bool more = k0 + kStK < ke;
-    if (more) gload(k0 + kStK);
+    if (more) fetch(k0 + kStK);
 #pragma unroll
     for (int ks = 0; ks < kStK / 32; ++ks) {
       v8bf a[2], b[2];
@@ -540,14 +540,14 @@ template <typename TG>
 __device__ __forceinline__ void g_rows4(const TG *g, bool vec, int nvalid, double v[4]) {
   if (vec) {
     typedef TG V __attribute__((ext_vector_type(4)));
-    const V a = *reinterpret_cast<const V *>(g);
+    const V a = gload(reinterpret_cast<const V *>(g));
     v[0] = g_as_f64<TG>(a.x);
     v[1] = g_as_f64<TG>(a.y);
     v[2] = g_as_f64<TG>(a.z);
     v[3] = g_as_f64<TG>(a.w);
   } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = q < nvalid ? g_as_f64<TG>(g[q]) : 0.0;
+    for (int q = 0; q < 4; ++q) v[q] = q < nvalid ? g_as_f64<TG>(gload(g + q)) : 0.0;
   }
 }
 

@@ -66,6 +66,21 @@ struct Carve {
   }
 };
 
+// Loads through a global-address-space pointer.  A pointer read from memory
+// (a batch descriptor) is generic to the compiler, and loads through it are
+// flat loads, which also count against the LDS wait counter: every wait for
+// an LDS operation then waits for the outstanding memory loads too.  Every
+// device pointer handed to this library addresses global memory, so the
+// cast at the load is exact; the compiler then issues global loads.
+template <typename T>
+__device__ __forceinline__ T gload(const T *p) {
+  return *(const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ T gload_nt(const T *p) {
+  return __builtin_nontemporal_load((const __attribute__((address_space(1))) T *)p);
+}
+
 // ---------------------------------------------------------------- launchers
 // Columns of the sketched operand [A | B]: column c < n_a is A's column c,
 // the rest are B's.  B may be null when n_a == ncols.
@@ -226,18 +241,19 @@ __host__ __device__ inline void batch_entry(const ms_problem &P, int wdata, int 
   batch_cs_geom(P.k, E.nc, E.ktile, E.nbt, E.nt, E.ntiles);
   E.refine = refine ? 1 : 0;
   if (refine) batch_cs_geom(P.k, (int)P.nrhs, E.rktile, E.rnbt, E.rnt, E.rntiles);
-  // rows per item: at least 8 rows per bucket of the tile on average, so the
-  // flush of a tile's partial sums stays small next to the adds
+  // rows per item: an item adds rows * ktile / k values into a tile of ktile
+  // slots and flushes the tile once, so at least 8 k rows keep the flush
+  // (global atomics) under an eighth of the adds
   E.rows = rows_item;
-  while (E.rows < 8 * E.ktile && E.rows < ((int64_t)1 << 30)) E.rows *= 2;
+  while (E.rows < 8 * P.k && E.rows < ((int64_t)1 << 30)) E.rows *= 2;
   E.nsegs = (int32_t)((P.d + E.rows - 1) / E.rows);
   E.tiles_m = (int32_t)((P.k2 + 63) / 64);
   E.tiles_n = (E.nc + 63) / 64;
   E.kchunk = kchunk;
   E.nsplit = (int32_t)((P.k + kchunk - 1) / kchunk);
-  const uintptr_t mis = (uintptr_t)P.A | (uintptr_t)P.B | (uintptr_t)(P.lda * wdata) |
-                        (uintptr_t)(P.ldb * wdata) | (uintptr_t)P.h;
-  E.vec = (mis & 15) == 0 && ((uintptr_t)P.s & (uintptr_t)(16 / wdata - 1)) == 0;
+  // data columns need element alignment only; h and s are loaded 16 / wdata
+  // rows at a time
+  E.vec = ((uintptr_t)P.h & 15) == 0 && ((uintptr_t)P.s & (uintptr_t)(16 / wdata - 1)) == 0;
 }
 
 __host__ __device__ inline int64_t batch_cs_items(const BatchEntry &E) {

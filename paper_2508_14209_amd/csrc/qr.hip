@@ -157,15 +157,6 @@ __device__ __forceinline__ double wave_allsum(double v) {
   return read_lane(v, 63);
 }
 
-// Householder QR least squares with the system [W | Bm] (m x nc, nc = n +
-// nrhs) held in registers: lane l of wave w owns rows l + 64 r (r < RPL) of
-// columns w + 16 q (q < CPW).  Reflector j is built by the wave owning column
-// j and published through a double-buffered LDS vector, so each column costs
-// one barrier.  The input is either [W | Bm] or, when part (FP64) or part32
-// (FP32) is given, the sum in split order of nsplit split-K partial blocks of
-// an m x nc product -- the same sum, in the same precision, as the separate
-// split reduction.
-// R and the transformed right-hand sides go to LDS for the back substitution.
 // Back substitution R x = y by one wave, y held in registers (lane l owns
 // rows l + 64 r): per row a lane read, one division and one update per lane.
 template <int RPL>
@@ -193,26 +184,71 @@ __device__ __forceinline__ void wave_back_substitute_reg(int n, const double *R,
   }
 }
 
-template <int RPL>
+// Sum over the 16 lanes of a DPP row (quad swaps, half-row and row mirrors);
+// every lane of the row receives the same bits, since each step adds the same
+// two partial sums in either order.
+__device__ __forceinline__ double row_allsum(double v) {
+  v += dpp_move<0xb1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4e>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
+  return v;
+}
+// The value of lane i ^ 16 (ds_swizzle in bit-mask mode: and 0x1f, xor 0x10).
+__device__ __forceinline__ double swap_rows(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)(u & 0xffffffffLL), 0x401f);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(u >> 32), 0x401f);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// Sum over a group of GW (16 or 32) lanes, the same bits in every lane of it.
+template <int GW>
+__device__ __forceinline__ double group_allsum(double v) {
+  v = row_allsum(v);
+  if (GW == 32) v += swap_rows(v);
+  return v;
+}
+
+template <int ROWS>
 struct QrShared {
-  double vbuf[2][64 * RPL];
+  double vbuf[2][ROWS];
   double taubuf[2];
   int singular;
 };
 
-// The body shared by the single-problem and batched kernels; rs is dynamic
-// LDS of n x (n + nrhs) doubles.  status2 (may be null) also receives a
-// singular-R report.
-template <int RPL, int CPW>
+// Householder QR least squares (the factorisation of the sketched system,
+// Section 2 and Algorithm 1's final solve) with [W | Bm] (m x nc, nc = n +
+// nrhs) held in registers.  The NW waves form NG = 64 NW / GW groups of GW
+// lanes (one or two DPP rows): group g owns columns g + NG s (s < S), and lane
+// l of a group rows l + GW r (r < R).  A column's inner product with a
+// reflector is R fused multiply-adds per lane (in up to four independent
+// chains) and a sum over the group that DPP steps (and, for 32 lanes, one
+// swizzle) give to every lane of it.  Reflector j is built by the group
+// owning column j and published through a double-buffered LDS vector: one
+// barrier per column.  Look-ahead: after the barrier that publishes
+// reflector j, the wave owning column j + 1 applies reflector j to that
+// column first, builds and publishes reflector j + 1, and only then updates
+// its other columns, so the serial part of a step (norm, square root,
+// division) overlaps the other waves' updates.  The input is either [W | Bm]
+// or, when part (FP64) or part32 (FP32) is given, the sum in split order of
+// nsplit split-K partial blocks of an m x nc product -- the same sum, in the
+// same precision, as the separate split reduction.  R and the transformed
+// right-hand sides go to LDS (rs: dynamic LDS of n x nc doubles) for the back
+// substitution; status2 (may be null) also receives a singular-R report.
+template <int NW, int GW, int R, int S>
 __device__ __forceinline__ void qr_reg_body(int m, int n, int nrhs, const double *__restrict__ W,
                                             int64_t ldw, const double *__restrict__ Bm,
                                             int64_t ldb, const double *__restrict__ part,
                                             const float *__restrict__ part32, int nsplit,
                                             double *__restrict__ X, int64_t ldx,
-                                            double *__restrict__ R, int64_t ldr,
+                                            double *__restrict__ Rout, int64_t ldr,
                                             double *__restrict__ tau_out,
                                             double *__restrict__ fact_out, int *status,
-                                            int *status2, double *rs, QrShared<RPL> &sh) {
+                                            int *status2, double *rs, QrShared<GW * R> &sh) {
+  constexpr int NG = NW * 64 / GW;   // groups
+  constexpr int GPW = 64 / GW;       // groups per wave
+  // independent partial sums (two when the columns leave few registers)
+  constexpr int NP = R >= 4 && S <= 3 ? 4 : (R >= 2 ? 2 : 1);
   auto &vbuf = sh.vbuf;
   auto &taubuf = sh.taubuf;
   int &s_singular = sh.singular;
@@ -220,15 +256,17 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, int nrhs, const double
   const int lane = threadIdx.x & 63;
   // uniform across a wave; saying so keeps the per-column conditions scalar
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int gl = lane % GW;
+  const int grp = wave * GPW + lane / GW;
   const int64_t MN = (int64_t)m * nc;
 
-  double a[CPW][RPL];
+  double a[S][R];
 #pragma unroll
-  for (int q = 0; q < CPW; ++q) {
-    const int c = wave + 16 * q;
+  for (int s = 0; s < S; ++s) {
+    const int c = grp + NG * s;
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int i = lane + 64 * r;
+    for (int r = 0; r < R; ++r) {
+      const int i = gl + GW * r;
       double x = 0.0;
       if (i < m && c < nc) {
         const int64_t o = i + (int64_t)c * m;
@@ -243,102 +281,142 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, int nrhs, const double
           x = c < n ? W[i + (int64_t)c * ldw] : Bm[i + (int64_t)(c - n) * ldb];
         }
       }
-      a[q][r] = x;
+      a[s][r] = x;
     }
   }
   if (threadIdx.x == 0) s_singular = 0;
 
-  for (int j = 0; j < n; ++j) {
+  auto owner_wave = [&](int j) { return (j % NG) / GPW; };
+  // Reflector j from column j, slot col of the owning wave (every group of
+  // the wave runs the steps on its own column; only the owner publishes and
+  // keeps the result).  With t = |alpha| + ||x||: tau = t / ||x|| and the
+  // scale of v below the diagonal is sign(alpha) / t, from one division.
+  auto build = [&](int j, double(&col)[R]) {
+    const int og = (j % NG) % GPW;
+    const int olane = og * GW;
+    const bool own = lane / GW == og;
+    double p[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) p[q] = 0.0;
+    double av = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = gl + GW * r;
+      if (i > j) p[r % NP] += col[r] * col[r];
+      if (r == j / GW) av = col[r];
+    }
+    double ps = p[0];
+#pragma unroll
+    for (int q = 1; q < NP; ++q) ps += p[q];
+    const double xn2 = read_lane(group_allsum<GW>(ps), olane);
+    const double alpha = read_lane(av, olane + j % GW);
+    double tau = 0.0, beta = alpha, scal = 0.0;
+    if (xn2 != 0.0) {
+      const double nrm = sqrt(alpha * alpha + xn2);
+      const double tt = fabs(alpha) + nrm;
+      const double qq = 1.0 / (nrm * tt);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = tt * tt * qq;
+      scal = (alpha >= 0.0 ? nrm : -nrm) * qq;
+    }
     const int buf = j & 1;
-    if (wave == (j & 15)) {
-      const int qj = j >> 4;
-      double col[RPL];
+    // branch-free: with x = 0 (tau = 0, beta = alpha) the column keeps its
+    // values (scale 1) and v is never used
+    const double sv = xn2 != 0.0 ? scal : 1.0;
+    if (own) {
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) col[r] = 0.0;
-#pragma unroll
-      for (int q = 0; q < CPW; ++q)
-        if (q == qj)
-#pragma unroll
-          for (int r = 0; r < RPL; ++r) col[r] = a[q][r];
-      double p2 = 0.0, av = 0.0;
-#pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        const int i = lane + 64 * r;
-        if (i > j) p2 += col[r] * col[r];
-        if (r == (j >> 6)) av = col[r];
+      for (int r = 0; r < R; ++r) {
+        const int i = gl + GW * r;
+        const double vi = col[r] * sv;
+        vbuf[buf][i] = i > j ? vi : (i == j ? 1.0 : 0.0);
+        col[r] = i > j ? vi : (i == j ? beta : col[r]);
       }
-      const double xn2 = wave_allsum(p2);
-      const double alpha = read_lane(av, j & 63);
-      double tau = 0.0, beta = alpha, scal = 0.0;
-      if (xn2 != 0.0) {
-        const double nrm = sqrt(alpha * alpha + xn2);
-        beta = alpha >= 0.0 ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scal = 1.0 / (alpha - beta);
-      }
-#pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        const int i = lane + 64 * r;
-        const double v = i > j ? col[r] * scal : (i == j ? 1.0 : 0.0);
-        vbuf[buf][i] = v;
-        if (xn2 != 0.0) col[r] = i > j ? v : (i == j ? beta : col[r]);
-      }
-#pragma unroll
-      for (int q = 0; q < CPW; ++q)
-        if (q == qj)
-#pragma unroll
-          for (int r = 0; r < RPL; ++r) a[q][r] = col[r];
-      if (lane == 0) {
+      if (gl == 0) {
         taubuf[buf] = tau;
         if (tau_out) tau_out[j] = tau;
       }
     }
+  };
+  // whether slot s of this wave holds a column after j (and before nc)
+  auto active = [&](int j, int s) {
+    const int cw = wave * GPW + NG * s;  // first column of the wave's slot
+    return cw + GPW - 1 > j && cw < nc;
+  };
+  // Reflector j (v, tau) applied to slot s of this wave.
+  auto apply = [&](int j, double(&col)[R], int s, const double(&v)[R], double tau) {
+    if (!active(j, s)) return;
+    double p[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) p[q] = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) p[r % NP] += v[r] * col[r];
+    double dot = p[0];
+#pragma unroll
+    for (int q = 1; q < NP; ++q) dot += p[q];
+    dot = group_allsum<GW>(dot);
+    const int c = grp + NG * s;
+    const double w = (c > j && c < nc) ? tau * dot : 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) col[r] -= w * v[r];
+  };
+
+  if (n > 0 && wave == owner_wave(0)) build(0, a[0]);
+  for (int j = 0; j < n; ++j) {
     __syncthreads();
-    const double tau = taubuf[buf];
-    if (tau != 0.0) {
-      double v[RPL];
+    const int jn = j + 1;
+    const bool la = jn < n && wave == owner_wave(jn);
+    const int sn = jn / NG;
+    auto load_v = [&](double(&v)[R]) {
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) v[r] = vbuf[buf][lane + 64 * r];
-      double dots[CPW];
+      for (int r = 0; r < R; ++r) v[r] = vbuf[j & 1][gl + GW * r];
+    };
+    if (la) {
+      // the look-ahead is the serial part of the step: let it issue first
+      __builtin_amdgcn_s_setprio(2);
 #pragma unroll
-      for (int q = 0; q < CPW; ++q) {
-        dots[q] = 0.0;
-        const int c = wave + 16 * q;
-        if (c > j && c < nc)
-#pragma unroll
-          for (int r = 0; r < RPL; ++r) dots[q] += v[r] * a[q][r];
-      }
-#pragma unroll
-      for (int q = 0; q < CPW; ++q) {
-        const int c = wave + 16 * q;
-        if (c > j && c < nc) dots[q] = wave_allsum(dots[q]);
-      }
-#pragma unroll
-      for (int q = 0; q < CPW; ++q) {
-        const int c = wave + 16 * q;
-        if (c > j && c < nc) {
-          const double w = tau * dots[q];
-#pragma unroll
-          for (int r = 0; r < RPL; ++r) a[q][r] -= w * v[r];
+      for (int s = 0; s < S; ++s)
+        if (s == sn) {
+          // v and tau in one LDS round trip
+          double v[R];
+          load_v(v);
+          const double tau = taubuf[j & 1];
+          if (tau != 0.0) apply(j, a[s], s, v, tau);
+          build(jn, a[s]);
         }
+      __builtin_amdgcn_s_setprio(0);
+      // v is read again below rather than kept live through the build
+      asm volatile("" ::: "memory");
+    }
+    // waves with no column after j read nothing
+    bool more = false;
+#pragma unroll
+    for (int s = 0; s < S; ++s) more |= (!la || s != sn) && active(j, s);
+    if (more) {
+      double v[R];
+      load_v(v);
+      const double tau = taubuf[j & 1];
+      if (tau != 0.0) {
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+          if (!la || s != sn) apply(j, a[s], s, v, tau);
       }
     }
   }
 
   // outputs of the factorisation, and the top n rows to LDS
 #pragma unroll
-  for (int q = 0; q < CPW; ++q) {
-    const int c = wave + 16 * q;
+  for (int s = 0; s < S; ++s) {
+    const int c = grp + NG * s;
     if (c >= nc) continue;
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int i = lane + 64 * r;
+    for (int r = 0; r < R; ++r) {
+      const int i = gl + GW * r;
       if (i >= m) continue;
-      if (fact_out && c < n) fact_out[i + (int64_t)c * m] = a[q][r];
+      if (fact_out && c < n) fact_out[i + (int64_t)c * m] = a[s][r];
       if (i < n) {
-        rs[i + c * n] = a[q][r];
-        if (R && c < n) R[i + (int64_t)c * ldr] = i <= c ? a[q][r] : 0.0;
-        if (i == c && (a[q][r] == 0.0 || !isfinite(a[q][r]))) s_singular = 1;
+        rs[i + c * n] = a[s][r];
+        if (Rout && c < n) Rout[i + (int64_t)c * ldr] = i <= c ? a[s][r] : 0.0;
+        if (i == c && (a[s][r] == 0.0 || !isfinite(a[s][r]))) s_singular = 1;
       }
     }
   }
@@ -354,35 +432,38 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, int nrhs, const double
     }
     return;
   }
-  for (int c = wave; c < nrhs; c += 16)
-    wave_back_substitute_reg<RPL>(n, rs, n, rs + (int64_t)(n + c) * n, X + (int64_t)c * ldx);
+  // n <= m <= GW R, so a wave holds y in (GW R + 63) / 64 registers per lane
+  for (int c = wave; c < nrhs; c += NW)
+    wave_back_substitute_reg<(GW * R + 63) / 64>(n, rs, n, rs + (int64_t)(n + c) * n,
+                                                 X + (int64_t)c * ldx);
 }
 
-template <int RPL, int CPW>
-__global__ __launch_bounds__(1024) void k_qr_reg(int m, int n, int nrhs, const double *__restrict__ W,
+template <int NW, int GW, int R, int S>
+__global__ __launch_bounds__(NW * 64) void k_qr_reg(int m, int n, int nrhs, const double *__restrict__ W,
                                                  int64_t ldw, const double *__restrict__ Bm,
                                                  int64_t ldb, const double *__restrict__ part,
                                                  const float *__restrict__ part32, int nsplit,
                                                  double *__restrict__ X, int64_t ldx,
-                                                 double *__restrict__ R, int64_t ldr,
+                                                 double *__restrict__ Rm, int64_t ldr,
                                                  double *__restrict__ tau_out,
                                                  double *__restrict__ fact_out, int *status) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ QrShared<RPL> sh;
-  qr_reg_body<RPL, CPW>(m, n, nrhs, W, ldw, Bm, ldb, part, part32, nsplit, X, ldx, R, ldr, tau_out,
+  __shared__ QrShared<GW * R> sh;
+  qr_reg_body<NW, GW, R, S>(m, n, nrhs, W, ldw, Bm, ldb, part, part32, nsplit, X, ldx, Rm, ldr,
+                            tau_out,
                         fact_out, status, nullptr, reinterpret_cast<double *>(smem_raw), sh);
 }
 
 // One workgroup per problem of a batch: Z_p (FP64, k2 x (n + nrhs)) -> X_p.
-template <int RPL, int CPW>
-__global__ __launch_bounds__(1024) void k_batch_qr(int count, const ms_problem *__restrict__ P,
+template <int NW, int GW, int R, int S>
+__global__ __launch_bounds__(NW * 64) void k_batch_qr(int count, const ms_problem *__restrict__ P,
                                                    const BatchEntry *__restrict__ E,
                                                    const unsigned char *__restrict__ zarea,
                                                    unsigned char *__restrict__ farea,
                                                    int *__restrict__ pstatus, int *status,
                                                    int64_t lds_doubles) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ QrShared<RPL> sh;
+  __shared__ QrShared<GW * R> sh;
   const int p = blockIdx.x;
   const BatchEntry &e = E[p];
   if (!e.valid) return;
@@ -390,7 +471,7 @@ __global__ __launch_bounds__(1024) void k_batch_qr(int count, const ms_problem *
   const double *Z = reinterpret_cast<const double *>(zarea + e.z_off);
   const int m = (int)Q.k2, n = (int)Q.n;
   // descriptors rewritten after the launch shape was chosen must still fit it
-  if (m > 64 * RPL || e.nc > 16 * CPW || (int64_t)n * e.nc > lds_doubles) {
+  if (m > GW * R || e.nc > (NW * 64 / GW) * S || (int64_t)n * e.nc > lds_doubles) {
     if (threadIdx.x == 0) {
       record_status(&pstatus[p], MS_ERR_NOMEM);
       record_status(status, MS_ERR_NOMEM);
@@ -399,40 +480,52 @@ __global__ __launch_bounds__(1024) void k_batch_qr(int count, const ms_problem *
   }
   double *fact = batch_ref(e) ? reinterpret_cast<double *>(farea + e.f_off) : nullptr;
   double *tau = fact ? fact + (int64_t)m * n : nullptr;
-  qr_reg_body<RPL, CPW>(m, n, (int)Q.nrhs, Z, m, Z + (int64_t)n * m, m, nullptr, nullptr, 0, Q.X,
+  qr_reg_body<NW, GW, R, S>(m, n, (int)Q.nrhs, Z, m, Z + (int64_t)n * m, m, nullptr, nullptr, 0, Q.X,
                         Q.ldx, nullptr, 0, tau, fact, &pstatus[p], status,
                         reinterpret_cast<double *>(smem_raw), sh);
 }
 
 struct QrRegShape {
-  int rpl, cpw;
+  int nw, gw, r, s;  // waves, group width, rows per lane (m <= gw r), slots (nc <= groups s)
 };
-// the register-resident instantiations, smallest first
-constexpr QrRegShape kQrShapes[] = {{1, 1}, {1, 2}, {1, 5}, {2, 2}, {2, 5}, {2, 9}, {4, 5}, {4, 9}};
+// the register-resident instantiations, cheapest first.  Sixteen waves: with
+// fewer (more slots per group) the column updates of the owning wave lengthen
+// every step, which measured slower at every shape tried.
+constexpr QrRegShape kQrShapes[] = {
+    {16, 16, 1, 1}, {16, 16, 2, 1}, {16, 16, 4, 1}, {16, 16, 2, 2}, {16, 16, 8, 1}, {16, 16, 4, 2},
+    {16, 16, 8, 2}, {16, 16, 8, 3}, {16, 32, 8, 2}, {16, 32, 8, 3}, {16, 32, 8, 4}, {16, 32, 8, 5}};
+#define MS_QR_SHAPES(X)                                                                \
+  X(16, 16, 1, 1) X(16, 16, 2, 1) X(16, 16, 4, 1) X(16, 16, 2, 2) X(16, 16, 8, 1)     \
+  X(16, 16, 4, 2) X(16, 16, 8, 2) X(16, 16, 8, 3) X(16, 32, 8, 2) X(16, 32, 8, 3)     \
+  X(16, 32, 8, 4) X(16, 32, 8, 5)
 
-template <int RPL, int CPW>
+static bool shape_fits(const QrRegShape &s, int64_t m, int64_t nc) {
+  return s.gw * s.r >= m && (s.nw * 64 / s.gw) * s.s >= nc;
+}
+
+template <int NW, int GW, int R, int S>
 static hipError_t launch_qr_reg_t(int64_t m, int64_t n, int64_t nrhs, const double *W,
                                   int64_t ldw, const double *Bm, int64_t ldb, const double *part,
                                   const float *part32, int nsplit, double *X, int64_t ldx,
-                                  double *R, int64_t ldr,
+                                  double *Rm, int64_t ldr,
                                   double *tau_out, double *fact_out, int *status,
                                   hipStream_t st) {
   const size_t lds = (size_t)n * (size_t)(n + nrhs) * sizeof(double);
-  hipError_t e = allow_dynamic_lds((const void *)k_qr_reg<RPL, CPW>, (int)lds);
+  hipError_t e = allow_dynamic_lds((const void *)k_qr_reg<NW, GW, R, S>, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_qr_reg<RPL, CPW>), dim3(1), dim3(1024), lds, st, (int)m, (int)n, (int)nrhs,
-                     W, ldw, Bm, ldb, part, part32, nsplit, X, ldx, R, ldr, tau_out, fact_out,
-                     status);
+  hipLaunchKernelGGL((k_qr_reg<NW, GW, R, S>), dim3(1), dim3(NW * 64), lds, st, (int)m, (int)n,
+                     (int)nrhs, W, ldw, Bm, ldb, part, part32, nsplit, X, ldx, Rm, ldr, tau_out,
+                     fact_out, status);
   return hipGetLastError();
 }
 
 // Returns hipErrorNotSupported when no register-resident shape fits.
 bool qr_reg_fits(int64_t m, int64_t n, int64_t nrhs) {
   const int64_t nc = n + nrhs;
-  const size_t lds = (size_t)n * (size_t)nc * sizeof(double) + 2 * 64 * 4 * 8 + 64;
+  const size_t lds = (size_t)n * (size_t)nc * sizeof(double) + 2 * 256 * 8 + 64;
   if (lds > (size_t)dev_info().lds_per_block) return false;
   for (const QrRegShape &s : kQrShapes)
-    if (64 * s.rpl >= m && 16 * s.cpw >= nc) return true;
+    if (shape_fits(s, m, nc)) return true;
   return false;
 }
 
@@ -441,22 +534,14 @@ hipError_t launch_qr_reg(int64_t m, int64_t n, int64_t nrhs, const double *W, in
                          int nsplit, double *X, int64_t ldx, double *R, int64_t ldr,
                          double *tau_out, double *fact_out, int *status, hipStream_t st) {
   const int64_t nc = n + nrhs;
-  const size_t lds = (size_t)n * (size_t)nc * sizeof(double) + 2 * 64 * 4 * 8 + 64;
-  if (lds > (size_t)dev_info().lds_per_block) return hipErrorNotSupported;
+  if (!qr_reg_fits(m, n, nrhs)) return hipErrorNotSupported;
   for (const QrRegShape &s : kQrShapes) {
-    if (64 * s.rpl < m || 16 * s.cpw < nc) continue;
-#define MS_QR_CASE(R_, C_)                                                                     \
-  if (s.rpl == R_ && s.cpw == C_)                                                              \
-    return launch_qr_reg_t<R_, C_>(m, n, nrhs, W, ldw, Bm, ldb, part, part32, nsplit, X, ldx, R, \
-                                   ldr, tau_out, fact_out, status, st);
-    MS_QR_CASE(1, 1)
-    MS_QR_CASE(1, 2)
-    MS_QR_CASE(1, 5)
-    MS_QR_CASE(2, 2)
-    MS_QR_CASE(2, 5)
-    MS_QR_CASE(2, 9)
-    MS_QR_CASE(4, 5)
-    MS_QR_CASE(4, 9)
+    if (!shape_fits(s, m, nc)) continue;
+#define MS_QR_CASE(W_, G_, R_, S_)                                                             \
+  if (s.nw == W_ && s.gw == G_ && s.r == R_ && s.s == S_)                                      \
+    return launch_qr_reg_t<W_, G_, R_, S_>(m, n, nrhs, W, ldw, Bm, ldb, part, part32, nsplit, X, \
+                                           ldx, R, ldr, tau_out, fact_out, status, st);
+    MS_QR_SHAPES(MS_QR_CASE)
 #undef MS_QR_CASE
   }
   return hipErrorNotSupported;
@@ -714,23 +799,17 @@ hipError_t launch_batch_qr(int count, int max_k2, int max_n, int max_nc, const m
                            int *pstatus, int *status, hipStream_t st) {
   const size_t lds = (size_t)max_n * (size_t)max_nc * sizeof(double);
   for (const QrRegShape &s : kQrShapes) {
-    if (64 * s.rpl < max_k2 || 16 * s.cpw < max_nc) continue;
-#define MS_BQR_CASE(R_, C_)                                                                    \
-  if (s.rpl == R_ && s.cpw == C_) {                                                           \
-    hipError_t e = allow_dynamic_lds((const void *)k_batch_qr<R_, C_>, (int)lds);            \
+    if (!shape_fits(s, max_k2, max_nc)) continue;
+#define MS_BQR_CASE(W_, G_, R_, S_)                                                            \
+  if (s.nw == W_ && s.gw == G_ && s.r == R_ && s.s == S_) {                                   \
+    hipError_t e = allow_dynamic_lds((const void *)k_batch_qr<W_, G_, R_, S_>, (int)lds);    \
     if (e != hipSuccess) return e;                                                            \
-    hipLaunchKernelGGL((k_batch_qr<R_, C_>), dim3(count), dim3(1024), lds, st, count, P, E,  \
+    hipLaunchKernelGGL((k_batch_qr<W_, G_, R_, S_>), dim3(count), dim3(W_ * 64), lds, st,     \
+                       count, P, E,                                                           \
                        zarea, farea, pstatus, status, (int64_t)max_n * max_nc);               \
     return hipGetLastError();                                                                 \
   }
-    MS_BQR_CASE(1, 1)
-    MS_BQR_CASE(1, 2)
-    MS_BQR_CASE(1, 5)
-    MS_BQR_CASE(2, 2)
-    MS_BQR_CASE(2, 5)
-    MS_BQR_CASE(2, 9)
-    MS_BQR_CASE(4, 5)
-    MS_BQR_CASE(4, 9)
+    MS_QR_SHAPES(MS_BQR_CASE)
 #undef MS_BQR_CASE
   }
   return hipErrorNotSupported;

@@ -11,12 +11,14 @@
 
 namespace ms {
 
-// Four consecutive rows of a column, promoted to FP64 (16-byte aligned).
+// Four consecutive rows of a column, promoted to FP64.  The vector loads are
+// aligned to the element only (a dword-aligned multi-dword global load is
+// legal on CDNA), so a column may start at any element.
 template <typename TA>
 struct Rows4 {
   static __device__ __forceinline__ void load(const TA *p, double v[4]) {
-    typedef TA V __attribute__((ext_vector_type(4)));
-    const V a = *reinterpret_cast<const V *>(p);
+    typedef TA V __attribute__((ext_vector_type(4), aligned(sizeof(TA))));
+    const V a = gload(reinterpret_cast<const V *>(p));
     v[0] = (double)a.x;
     v[1] = (double)a.y;
     v[2] = (double)a.z;
@@ -26,9 +28,9 @@ struct Rows4 {
 template <>
 struct Rows4<double> {
   static __device__ __forceinline__ void load(const double *p, double v[4]) {
-    typedef double V __attribute__((ext_vector_type(2)));
-    const V a = *reinterpret_cast<const V *>(p);
-    const V b = *reinterpret_cast<const V *>(p + 2);
+    typedef double V __attribute__((ext_vector_type(2), aligned(8)));
+    const V a = gload(reinterpret_cast<const V *>(p));
+    const V b = gload(reinterpret_cast<const V *>(p + 2));
     v[0] = a.x;
     v[1] = a.y;
     v[2] = b.x;
@@ -54,10 +56,9 @@ __global__ __launch_bounds__(256) void k_residual(int64_t d, int n, int nrhs,
     __syncthreads();
   }
   auto xv = [&](int j, int c) { return XLDS ? xs[j * RH + c] : X[j + (int64_t)c * ldx]; };
-  const bool aligned = ((lda | ldb) & 3) == 0 && (((uintptr_t)A | (uintptr_t)B) & 15) == 0;
   for (int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i0 < d;
        i0 += (int64_t)gridDim.x * blockDim.x * 4) {
-    const bool vec = aligned && i0 + 4 <= d;
+    const bool vec = i0 + 4 <= d;
     const int rows = (int)min((int64_t)4, d - i0);
     double acc[4][RH];
 #pragma unroll
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(256) void k_batch_residual(
     __syncthreads();  // the previous item's reads of xs are done
     for (int t = threadIdx.x; t < n * nrhs; t += blockDim.x) {
       const int c = t / n, j = t - c * n;
-      xs[j * RH + c] = Q.X[j + (int64_t)c * Q.ldx];
+      xs[j * RH + c] = gload(Q.X + j + (int64_t)c * Q.ldx);
     }
     __syncthreads();
     for (int64_t sub = 0; sub < kBatchResRows; sub += 4 * (int64_t)blockDim.x) {
@@ -175,8 +176,7 @@ __global__ __launch_bounds__(256) void k_batch_residual(
       const TA *A = static_cast<const TA *>(Q.A);
       const TA *B = static_cast<const TA *>(Q.B);
       double *r = reinterpret_cast<double *>(rarea + e.r_off);
-      const bool vec = i0 + 4 <= Q.d && ((Q.lda | Q.ldb) & 3) == 0 &&
-                       (((uintptr_t)A | (uintptr_t)B) & 15) == 0;
+      const bool vec = i0 + 4 <= Q.d;
       const int rows = (int)min((int64_t)4, Q.d - i0);
       double acc[4][RH];
 #pragma unroll
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void k_batch_residual(
 #pragma unroll
           for (int q = 0; q < 4; ++q)
             if (q < rows) {
-              const double a = (double)A[i0 + q + (int64_t)j * Q.lda];
+              const double a = (double)gload(A + i0 + q + (int64_t)j * Q.lda);
 #pragma unroll
               for (int c = 0; c < RH; ++c)
                 if (c < nrhs) acc[q][c] += a * xs[j * RH + c];
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(256) void k_batch_residual(
 #pragma unroll
             for (int q = 0; q < 4; ++q)
               if (q < rows)
-                r[i0 + q + (int64_t)c * Q.d] = (double)B[i0 + q + (int64_t)c * Q.ldb] - acc[q][c];
+                r[i0 + q + (int64_t)c * Q.d] = (double)gload(B + i0 + q + (int64_t)c * Q.ldb) - acc[q][c];
       }
     }
   }
