@@ -717,13 +717,17 @@ __global__ __launch_bounds__(1024) void k_batch_cs(int count, const ms_problem *
                                                    const BatchTotals *__restrict__ tot,
                                                    const unsigned char *__restrict__ rarea,
                                                    unsigned char *__restrict__ yarea,
-                                                   int *__restrict__ pstatus, int *status) {
+                                                   int *__restrict__ pstatus, int *status,
+                                                   int dies) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double *acc = reinterpret_cast<double *>(smem_raw);
   for (int t = threadIdx.x; t < kBatchLdsSlots; t += blockDim.x) acc[t] = 0.0;
   __syncthreads();
   const int64_t total = RES ? tot->rcs_items : tot->cs_items;
-  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+  const DieOrder ord(dies);
+  for (int64_t rr = 0;; ++rr) {
+    const int64_t it = ord.item(rr);
+    if (it >= total) break;
     const int p = RES ? batch_find_m<&BatchEntry::rcs_start>(E, count, it)
                       : batch_find_m<&BatchEntry::cs_start>(E, count, it);
     const ms_problem &Q = P[p];
@@ -813,7 +817,8 @@ hipError_t launch_batch_cs(int count, const ms_problem *P, const BatchEntry *E,
   hipError_t e = allow_dynamic_lds((const void *)k_batch_cs<T, false>, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_batch_cs<T, false>), dim3(grid), dim3(1024), lds, st, count, P, E, tot,
-                     (const unsigned char *)nullptr, yarea, pstatus, status);
+                     (const unsigned char *)nullptr, yarea, pstatus, status,
+                     grid_dies(grid, dev_info().xcds));
   return hipGetLastError();
 }
 template hipError_t launch_batch_cs<double>(int, const ms_problem *, const BatchEntry *,
@@ -831,7 +836,7 @@ hipError_t launch_batch_cs_res(int count, const ms_problem *P, const BatchEntry 
   hipError_t e = allow_dynamic_lds((const void *)k_batch_cs<double, true>, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_batch_cs<double, true>), dim3(grid), dim3(1024), lds, st, count, P, E,
-                     tot, rarea, yrarea, pstatus, status);
+                     tot, rarea, yrarea, pstatus, status, grid_dies(grid, dev_info().xcds));
   return hipGetLastError();
 }
 

@@ -25,6 +25,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef unsigned short v8u16 __attribute__((ext_vector_type(8)));
+typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
 
 // FP32 -> BF16 bits, round to nearest, ties to even (NaN kept quiet).
 __device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
@@ -33,6 +34,15 @@ __device__ __forceinline__ unsigned short f32_to_bf16_rne(float f) {
     return (unsigned short)((u | 0x00400000u) >> 16);
   u += 0x7fffu + ((u >> 16) & 1u);
   return (unsigned short)(u >> 16);
+}
+
+// Two FP32 values rounded to nearest-even BF16, packed (first in the low
+// half): the hardware conversion, which agrees with f32_to_bf16_rne on
+// every finite value.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16x2_rne(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t));
 }
 
 enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
@@ -217,28 +227,31 @@ __device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int m0 = m_tile * 64, n0 = n_tile * 64;
-  // global-load roles: G column kk, rows gr .. gr+15; Y column yc, k yk .. yk+15
-  const int kk = tid >> 2, gr = (tid & 3) * 16;
+  // global-load roles: G columns (k) 2 gp and 2 gp + 1, rows 8 g8 .. 8 g8 + 7,
+  // written to LDS as one dword (the two k of a row) per row; Y column yc,
+  // k yk .. yk + 15, rounded to BF16 in pairs by the hardware conversion
+  const int g8 = tid & 7, gp = tid >> 3;
   const int yc = tid >> 2, yk = (tid & 3) * 16;
-  const bool gvec = (ldg & 7) == 0 && ((uintptr_t)G & 15) == 0 && m0 + gr + 16 <= M;
+  const int rb = m0 + 8 * g8;
+  const bool gvec = (ldg & 7) == 0 && ((uintptr_t)G & 15) == 0 && rb + 8 <= M;
   const bool yvec = (ldy & 3) == 0 && ((uintptr_t)Y & 15) == 0 && n0 + yc < N;
-  unsigned short gv[16];
+  uint32_t gw[8];
   float yv[16];
   auto fetch = [&](int64_t k0) {
-    const int64_t kc = k0 + kk;
-    if (kc < ke && gvec) {
-      const v8u16 a = gload(reinterpret_cast<const v8u16 *>(G + (m0 + gr) + kc * ldg));
-      const v8u16 b = gload(reinterpret_cast<const v8u16 *>(G + (m0 + gr + 8) + kc * ldg));
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        gv[r] = a[r];
-        gv[8 + r] = b[r];
-      }
+    const int64_t kc = k0 + 2 * gp;
+    v8u16 c0 = {}, c1 = {};
+    if (gvec) {
+      if (kc < ke) c0 = gload(reinterpret_cast<const v8u16 *>(G + rb + kc * ldg));
+      if (kc + 1 < ke) c1 = gload(reinterpret_cast<const v8u16 *>(G + rb + (kc + 1) * ldg));
     } else {
 #pragma unroll
-      for (int r = 0; r < 16; ++r)
-        gv[r] = (kc < ke && m0 + gr + r < M) ? gload(G + (m0 + gr + r) + kc * ldg) : (unsigned short)0;
+      for (int r = 0; r < 8; ++r) {
+        c0[r] = (kc < ke && rb + r < M) ? gload(G + rb + r + kc * ldg) : (unsigned short)0;
+        c1[r] = (kc + 1 < ke && rb + r < M) ? gload(G + rb + r + (kc + 1) * ldg) : (unsigned short)0;
+      }
     }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) gw[r] = (uint32_t)c0[r] | ((uint32_t)c1[r] << 16);
     const int64_t kq = k0 + yk;
     if (yvec && kq + 16 <= ke) {
 #pragma unroll
@@ -257,15 +270,16 @@ __device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned 
   };
   auto lstore = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) As[buf][(gr + r) * kStPad + kk] = gv[r];
-    v8u16 b0, b1;
+    for (int r = 0; r < 8; ++r)
+      *reinterpret_cast<uint32_t *>(&As[buf][(8 * g8 + r) * kStPad + 2 * gp]) = gw[r];
+    v4u32 b0, b1;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      b0[u] = f32_to_bf16_rne(yv[u]);
-      b1[u] = f32_to_bf16_rne(yv[8 + u]);
+    for (int u = 0; u < 4; ++u) {
+      b0[u] = bf16x2_rne(yv[2 * u], yv[2 * u + 1]);
+      b1[u] = bf16x2_rne(yv[8 + 2 * u], yv[8 + 2 * u + 1]);
     }
-    *reinterpret_cast<v8u16 *>(&Bs[buf][yc * kStPad + yk]) = b0;
-    *reinterpret_cast<v8u16 *>(&Bs[buf][yc * kStPad + yk + 8]) = b1;
+    *reinterpret_cast<v4u32 *>(&Bs[buf][yc * kStPad + yk]) = b0;
+    *reinterpret_cast<v4u32 *>(&Bs[buf][yc * kStPad + yk + 8]) = b1;
   };
   const int m_base = (wave & 1) * 32, n_base = (wave >> 1) * 32;
   v4f acc[2][2];

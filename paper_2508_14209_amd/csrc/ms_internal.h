@@ -179,6 +179,21 @@ hipError_t launch_qr_apply_solve(int64_t m, int64_t n, int64_t nrhs, const doubl
                                  int *status, hipStream_t st);
 
 // ---------------------------------------------------------------- batched
+// Item order of a persistent grid that keeps runs of consecutive items on
+// one die: workgroup g runs on die g % dies (the dispatcher's round-robin),
+// and with w = grid / dies workgroups per die, item (r dies + die) w + q goes
+// to the q-th workgroup of that die.  Items that share data sit next to each
+// other in every item order here, so they are fetched through the same L2.
+// dies = 1 (grid not a multiple of the die count) is the plain order.
+struct DieOrder {
+  int64_t dies, die, q, wpd;
+  __device__ explicit DieOrder(int ndies)
+      : dies(ndies), die(blockIdx.x % ndies), q(blockIdx.x / ndies), wpd(gridDim.x / ndies) {}
+  __device__ int64_t item(int64_t r) const { return (r * dies + die) * wpd + q; }
+};
+// the die count for a persistent grid of `grid` workgroups
+inline int grid_dies(int grid, int xcds) { return xcds > 0 && grid % xcds == 0 ? xcds : 1; }
+
 // Per-problem plan of a batched call, computed identically on the host (to
 // size the workspace) and on the device (so graph replays with rewritten
 // descriptors need no host work).
