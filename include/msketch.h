@@ -272,8 +272,10 @@ typedef struct {
  * Workspace bytes of sketch_lstsq_batched for these problems (host array).
  * 0 for invalid arguments.  A workspace sized for one set of problems serves
  * any other set with the same count whose problems are no larger in k,
- * k2 and n + nrhs (and, with refinement, in d * nrhs): d does not enter
- * without refinement.
+ * k2 and n + nrhs (and, with refinement, in d * nrhs).  Without refinement
+ * d enters only through the packed bucket words (4 bytes per row, written
+ * once per call): a set with more rows in total than the sizing set still
+ * runs, reading h and s in every CountSketch work item instead (slower).
  */
 size_t ms_batch_workspace_size(int count, const ms_problem *probs,
                                ms_dtype a_dtype, ms_dtype g_dtype,
@@ -283,7 +285,7 @@ size_t ms_batch_workspace_size(int count, const ms_problem *probs,
  * Batched multisketch sketch-and-solve: every problem p is solved as
  * sketch_lstsq would solve it (same association G (C [A | B]), same
  * Householder QR and back substitution, same FP64-residual refinement), all
- * problems together in a fixed sequence of launches (six, plus five per
+ * problems together in a fixed sequence of launches (seven, plus five per
  * refinement step) whose grids do not depend on the problems' contents -- so
  * the sequence can be captured once in a HIP graph and replayed after the
  * descriptors in device memory are rewritten.

@@ -27,12 +27,14 @@ namespace {
 constexpr int kSetupThreads = 1024;
 
 struct BatchCaps {
+  int64_t code_bytes;                         // packed bucket/sign words
   int64_t y_bytes, part_bytes, z_bytes;       // first pass
   int64_t f_bytes, r_bytes, yr_bytes, gv_bytes;  // refinement (0 without)
 };
 
 struct BatchLayout {
-  size_t pstatus, entries, totals, yarea, parea, zarea, farea, rarea, yrarea, gvarea, total;
+  size_t pstatus, entries, totals, codearea, yarea, parea, zarea, farea, rarea, yrarea, gvarea,
+      total;
 };
 
 BatchLayout batch_layout(int count, const BatchCaps &caps) {
@@ -41,6 +43,7 @@ BatchLayout batch_layout(int count, const BatchCaps &caps) {
   L.pstatus = cv.take((size_t)count * sizeof(int));
   L.entries = cv.take((size_t)count * sizeof(BatchEntry));
   L.totals = cv.take(sizeof(BatchTotals));
+  L.codearea = cv.take((size_t)caps.code_bytes);
   L.yarea = cv.take((size_t)caps.y_bytes);
   L.parea = cv.take((size_t)caps.part_bytes);
   L.zarea = cv.take((size_t)caps.z_bytes);
@@ -54,7 +57,7 @@ BatchLayout batch_layout(int count, const BatchCaps &caps) {
 
 // The per-problem quantities the setup scans: work items of each persistent
 // launch and bytes of each workspace area.
-enum BatchQ { QCS, QGEMM, QRES, QRCS, QGV, QY, QPART, QZ, QF, QR, QYR, QGVB, NQ };
+enum BatchQ { QCS, QGEMM, QRES, QRCS, QGV, QCODE, QY, QPART, QZ, QF, QR, QYR, QGVB, NQ };
 
 __host__ __device__ inline void batch_quantities(const ms_problem &P, const BatchEntry &e,
                                                  int wdata, int accw, int64_t q[NQ]) {
@@ -63,6 +66,7 @@ __host__ __device__ inline void batch_quantities(const ms_problem &P, const Batc
   q[QRES] = batch_res_items(P, e);
   q[QRCS] = batch_rcs_items(e);
   q[QGV] = batch_gv_items(e);
+  q[QCODE] = batch_code_bytes(P, e);
   q[QY] = batch_y_bytes(P, e, wdata);
   q[QPART] = batch_part_bytes(P, e, accw);
   q[QZ] = batch_z_bytes(P, e);
@@ -125,6 +129,9 @@ __global__ __launch_bounds__(kSetupThreads) void k_batch_setup(
   for (int j = 0; j < NQ; ++j) off[j] = block_excl_scan64(sum[j], sh, total[j]);
   // the workspace areas were sized on the host; descriptors rewritten for a
   // graph replay must not need more
+  // packed bucket words only when the capacity's rows cover the batch's (a
+  // replay with more rows reads h and s in every item instead)
+  const bool codes = total[QCODE] <= caps.code_bytes;
   const bool fits = total[QY] <= caps.y_bytes && total[QPART] <= caps.part_bytes &&
                     total[QZ] <= caps.z_bytes && total[QF] <= caps.f_bytes &&
                     total[QR] <= caps.r_bytes && total[QYR] <= caps.yr_bytes &&
@@ -141,6 +148,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_batch_setup(
     e.res_start = off[QRES];
     e.rcs_start = off[QRCS];
     e.gv_start = off[QGV];
+    e.code_off = codes && batch_packs(e) ? off[QCODE] : -1;
     e.y_off = off[QY];
     e.part_off = off[QPART];
     e.z_off = off[QZ];
@@ -226,7 +234,7 @@ bool valid_batch_opts(const ms_opts *o) {
 // Host pass over the descriptors: validity, area sizes and launch maxima.
 struct HostBatch {
   bool ok = true, refine_rhs_ok = true;
-  BatchCaps caps{0, 0, 0, 0, 0, 0, 0};
+  BatchCaps caps{0, 0, 0, 0, 0, 0, 0, 0};
   int max_k2 = 1, max_n = 1, max_nc = 2;
   int64_t max_mn = 1;
 };
@@ -250,6 +258,7 @@ HostBatch host_batch(int count, const ms_problem *probs, ms_dtype a, ms_dtype g,
     }
     int64_t q[NQ];
     batch_quantities(probs[p], e, wdata, accw, q);
+    H.caps.code_bytes += q[QCODE];
     H.caps.y_bytes += q[QY];
     H.caps.part_bytes += q[QPART];
     H.caps.z_bytes += q[QZ];
@@ -302,6 +311,7 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
   BatchEntry *E = reinterpret_cast<BatchEntry *>(base + L.entries);
   BatchTotals *tot = reinterpret_cast<BatchTotals *>(base + L.totals);
   unsigned char *yarea = base + L.yarea, *parea = base + L.parea, *zarea = base + L.zarea;
+  unsigned char *codearea = base + L.codearea;
   unsigned char *farea = base + L.farea, *rarea = base + L.rarea, *yrarea = base + L.yrarea,
                 *gvarea = base + L.gvarea;
   const DevInfo &di = dev_info();
@@ -319,11 +329,14 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
     return hipGetLastError();
   };
   if (e == hipSuccess) e = zero(0, yarea);
+  if (e == hipSuccess) e = launch_batch_pack(count, probs_dev, E, codearea, pstatus, status, st);
   if (e == hipSuccess) {
     const int grid = di.cus;  // one 1024-thread workgroup per CU (128 KB of LDS each)
     e = a_dtype == MS_F64
-            ? launch_batch_cs<double>(count, probs_dev, E, tot, yarea, pstatus, status, grid, st)
-            : launch_batch_cs<float>(count, probs_dev, E, tot, yarea, pstatus, status, grid, st);
+            ? launch_batch_cs<double>(count, probs_dev, E, tot, codearea, yarea, pstatus, status,
+                                      grid, st)
+            : launch_batch_cs<float>(count, probs_dev, E, tot, codearea, yarea, pstatus, status,
+                                     grid, st);
   }
   if (e == hipSuccess)
     e = launch_batch_gemm(count, g_dtype, probs_dev, E, tot, yarea, parea, di.cus * 4, st);
@@ -340,8 +353,8 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
               ? launch_batch_residual<double>(count, probs_dev, E, tot, rarea, di.cus * 8, st)
               : launch_batch_residual<float>(count, probs_dev, E, tot, rarea, di.cus * 8, st);
     if (e == hipSuccess)
-      e = launch_batch_cs_res(count, probs_dev, E, tot, rarea, yrarea, pstatus, status, di.cus,
-                              st);
+      e = launch_batch_cs_res(count, probs_dev, E, tot, codearea, rarea, yrarea, pstatus, status,
+                              di.cus, st);
     if (e == hipSuccess)
       e = launch_batch_gemv(count, g_dtype, probs_dev, E, tot, yrarea, gvarea, di.cus * 4, st);
     if (e == hipSuccess)

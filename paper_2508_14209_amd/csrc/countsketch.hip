@@ -715,6 +715,7 @@ template <typename T, bool RES>
 __global__ __launch_bounds__(1024) void k_batch_cs(int count, const ms_problem *__restrict__ P,
                                                    const BatchEntry *__restrict__ E,
                                                    const BatchTotals *__restrict__ tot,
+                                                   const unsigned char *__restrict__ codearea,
                                                    const unsigned char *__restrict__ rarea,
                                                    unsigned char *__restrict__ yarea,
                                                    int *__restrict__ pstatus, int *status,
@@ -747,20 +748,22 @@ __global__ __launch_bounds__(1024) void k_batch_cs(int count, const ms_problem *
     const int64_t b0 = (int64_t)bt * ktile;
     const uint32_t kt = (uint32_t)min(ktile, Q.k - b0);
     Cols<T> cols;
-    bool vec;
     T *Y;
-    const int32_t *hq = Q.h;
-    const int8_t *sq = Q.s;
+    // the packed words of the problem's rows (256-byte aligned: the vector
+    // path), or, for problems swept only a few times (and in a replay with
+    // more rows than the capacity), h and s read and checked by every item
+    const bool packed = e.code_off >= 0;
+    const bool vec = ((uintptr_t)Q.h & 15) == 0 &&
+                     ((uintptr_t)Q.s & (uintptr_t)(16 / sizeof(T) - 1)) == 0;
+    const uint32_t *code =
+        packed ? reinterpret_cast<const uint32_t *>(codearea + e.code_off) : nullptr;
     if (RES) {
       const T *r = reinterpret_cast<const T *>(rarea + e.r_off);
       cols = Cols<T>{r, Q.d, nullptr, 0, (int)Q.nrhs, (int)Q.nrhs};
-      vec = ((uintptr_t)Q.h & 15) == 0 &&
-            ((uintptr_t)Q.s & (uintptr_t)(16 / sizeof(T) - 1)) == 0;
       Y = reinterpret_cast<T *>(yarea + e.yr_off);
     } else {
       cols = Cols<T>{static_cast<const T *>(Q.A), Q.lda, static_cast<const T *>(Q.B), Q.ldb,
                      (int)Q.n, e.nc};
-      vec = e.vec != 0;
       Y = reinterpret_cast<T *>(yarea + e.y_off);
     }
     const int c0 = tile * nt;
@@ -768,16 +771,19 @@ __global__ __launch_bounds__(1024) void k_batch_cs(int count, const ms_problem *
     bool bad = false;
     // the tile width is a template argument, so narrow tiles issue no
     // loads for columns they do not have
-#define MS_BCS_W(NT_, UNR_, NTL_, PST_)                                                          \
-  if (vec)                                                                                        \
-    cs_segment<T, NT_, true, false, UNR_, NTL_, PST_>(acc, cols, c0, ncur, nullptr, hq, sq, Q.k,   \
-                                                      b0, kt, r0, r1, Y, Q.k, bad);               \
-  else                                                                                            \
-    cs_segment<T, NT_, false, false, UNR_, false, PST_>(acc, cols, c0, ncur, nullptr, hq, sq,      \
+#define MS_BCS_W(NT_, UNR_, NTL_, PST_)                                                      \
+  if (packed)                                                                                      \
+    cs_segment<T, NT_, true, true, UNR_, NTL_, PST_>(acc, cols, c0, ncur, code, nullptr, nullptr,  \
+                                                     Q.k, b0, kt, r0, r1, Y, Q.k, bad);            \
+  else if (vec)                                                                                    \
+    cs_segment<T, NT_, true, false, UNR_, NTL_, PST_>(acc, cols, c0, ncur, nullptr, Q.h, Q.s, Q.k, \
+                                                      b0, kt, r0, r1, Y, Q.k, bad);                \
+  else                                                                                             \
+    cs_segment<T, NT_, false, false, UNR_, false, PST_>(acc, cols, c0, ncur, nullptr, Q.h, Q.s,    \
                                                         Q.k, b0, kt, r0, r1, Y, Q.k, bad);
     // with one bucket tile each column value is read once: nontemporal loads
-    // keep it from evicting the h and s of the segment, which the other
-    // column tiles read from L2.  With one row segment the item is the only
+    // keep it from evicting the codes of the segment, which the other column
+    // tiles read from L2.  With one row segment the item is the only
     // writer of its tile of the output: plain stores, and the output needs
     // no clearing beforehand.
 #define MS_BCS_V(NT_, UNR_, NTL_)         \
@@ -809,34 +815,73 @@ __global__ __launch_bounds__(1024) void k_batch_cs(int count, const ms_problem *
   }
 }
 
+// The packed words of the rows of every problem that packs them (grid x
+// over rows, four per thread with 16-byte loads of h when aligned; y over
+// problems).
+__global__ void k_batch_pack(int count, const ms_problem *__restrict__ P,
+                             const BatchEntry *__restrict__ E, unsigned char *__restrict__ codearea,
+                             int *__restrict__ pstatus, int *status) {
+  for (int p = blockIdx.y; p < count; p += gridDim.y) {
+    const BatchEntry &e = E[p];
+    if (!e.valid || e.code_off < 0) continue;
+    const ms_problem &Q = P[p];
+    uint32_t *code = reinterpret_cast<uint32_t *>(codearea + e.code_off);
+    const bool vec = ((uintptr_t)Q.h & 15) == 0 && ((uintptr_t)Q.s & 3) == 0;
+    bool bad = false;
+    for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4; i < Q.d;
+         i += (int64_t)gridDim.x * blockDim.x * 4) {
+      if (vec && i + 4 <= Q.d) {
+        uint32_t w[4];
+        row_words<false, 4>(nullptr, Q.h, Q.s, i, Q.k, w, bad);
+        *reinterpret_cast<uvec4 *>(code + i) = uvec4{w[0], w[1], w[2], w[3]};
+      } else {
+        for (int64_t r = i; r < min(Q.d, i + 4); ++r) code[r] = row_word<false>(nullptr, Q.h, Q.s, r, Q.k, bad);
+      }
+    }
+    if (bad) {
+      record_status(&pstatus[p], MS_ERR_RANGE);
+      record_status(status, MS_ERR_RANGE);
+    }
+  }
+}
+
+hipError_t launch_batch_pack(int count, const ms_problem *P, const BatchEntry *E,
+                             unsigned char *codearea, int *pstatus, int *status, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_pack, dim3(128, (unsigned)std::min(count, 1024)), dim3(256), 0, st,
+                     count, P, E, codearea, pstatus, status);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_batch_cs(int count, const ms_problem *P, const BatchEntry *E,
-                           const BatchTotals *tot, unsigned char *yarea, int *pstatus, int *status,
-                           int grid, hipStream_t st) {
+                           const BatchTotals *tot, const unsigned char *codearea,
+                           unsigned char *yarea, int *pstatus, int *status, int grid,
+                           hipStream_t st) {
   const size_t lds = (size_t)kBatchLdsSlots * sizeof(double);
   hipError_t e = allow_dynamic_lds((const void *)k_batch_cs<T, false>, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_batch_cs<T, false>), dim3(grid), dim3(1024), lds, st, count, P, E, tot,
-                     (const unsigned char *)nullptr, yarea, pstatus, status,
+                     codearea, (const unsigned char *)nullptr, yarea, pstatus, status,
                      grid_dies(grid, dev_info().xcds));
   return hipGetLastError();
 }
 template hipError_t launch_batch_cs<double>(int, const ms_problem *, const BatchEntry *,
-                                            const BatchTotals *, unsigned char *, int *, int *,
-                                            int, hipStream_t);
+                                            const BatchTotals *, const unsigned char *,
+                                            unsigned char *, int *, int *, int, hipStream_t);
 template hipError_t launch_batch_cs<float>(int, const ms_problem *, const BatchEntry *,
-                                           const BatchTotals *, unsigned char *, int *, int *, int,
-                                           hipStream_t);
+                                           const BatchTotals *, const unsigned char *,
+                                           unsigned char *, int *, int *, int, hipStream_t);
 
 hipError_t launch_batch_cs_res(int count, const ms_problem *P, const BatchEntry *E,
-                               const BatchTotals *tot, const unsigned char *rarea,
-                               unsigned char *yrarea, int *pstatus, int *status, int grid,
-                               hipStream_t st) {
+                               const BatchTotals *tot, const unsigned char *codearea,
+                               const unsigned char *rarea, unsigned char *yrarea, int *pstatus,
+                               int *status, int grid, hipStream_t st) {
   const size_t lds = (size_t)kBatchLdsSlots * sizeof(double);
   hipError_t e = allow_dynamic_lds((const void *)k_batch_cs<double, true>, (int)lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_batch_cs<double, true>), dim3(grid), dim3(1024), lds, st, count, P, E,
-                     tot, rarea, yrarea, pstatus, status, grid_dies(grid, dev_info().xcds));
+                     tot, codearea, rarea, yrarea, pstatus, status,
+                     grid_dies(grid, dev_info().xcds));
   return hipGetLastError();
 }
 

@@ -206,8 +206,9 @@ struct BatchEntry {
   int64_t rows;        // rows per CountSketch item
   int64_t kchunk;      // K per Gaussian-stage item
   int64_t ktile;       // buckets per LDS tile
+  int64_t code_off;    // byte offset of the packed bucket/sign words (d x 4 bytes), or -1
   int32_t nc, nt, ntiles, nsegs, nbt, tiles_m, tiles_n, nsplit;
-  int32_t valid, vec, refine, pad0;
+  int32_t valid, pad2, refine, pad0;
   // refinement (refine != 0): residual r = B - A X (FP64, d x nrhs), its
   // CountSketch Yr (k x nrhs, FP64), G Yr split-K partials, and the QR
   // factors (k2 x n reflectors and R, then n values of tau)
@@ -266,9 +267,6 @@ __host__ __device__ inline void batch_entry(const ms_problem &P, int wdata, int 
   E.tiles_n = (E.nc + 63) / 64;
   E.kchunk = kchunk;
   E.nsplit = (int32_t)((P.k + kchunk - 1) / kchunk);
-  // data columns need element alignment only; h and s are loaded 16 / wdata
-  // rows at a time
-  E.vec = ((uintptr_t)P.h & 15) == 0 && ((uintptr_t)P.s & (uintptr_t)(16 / wdata - 1)) == 0;
 }
 
 __host__ __device__ inline int64_t batch_cs_items(const BatchEntry &E) {
@@ -279,6 +277,16 @@ __host__ __device__ inline int64_t batch_gemm_items(const BatchEntry &E) {
 }
 __host__ __device__ inline int64_t batch_y_bytes(const ms_problem &P, const BatchEntry &E, int wdata) {
   return E.valid ? batch_align(P.k * E.nc * wdata) : 0;
+}
+// Rows are packed into bucket/sign words only when the CountSketch sweeps
+// them at least kBatchPackSweeps times (column tiles x bucket tiles): the
+// pack pass (9 bytes per row) pays for itself from there.
+constexpr int kBatchPackSweeps = 8;
+__host__ __device__ inline bool batch_packs(const BatchEntry &E) {
+  return E.valid && (int64_t)E.ntiles * E.nbt >= kBatchPackSweeps;
+}
+__host__ __device__ inline int64_t batch_code_bytes(const ms_problem &P, const BatchEntry &E) {
+  return batch_packs(E) ? batch_align(P.d * 4) : 0;
 }
 __host__ __device__ inline int64_t batch_part_bytes(const ms_problem &P, const BatchEntry &E, int accw) {
   return E.valid ? batch_align((int64_t)E.nsplit * P.k2 * E.nc * accw) : 0;
@@ -334,10 +342,15 @@ __device__ __forceinline__ int batch_find_m(const BatchEntry *__restrict__ E, in
 }
 
 // countsketch.hip / gemm.hip / qr.hip batched launchers
+// packed words h | sign << 31 of every problem's rows into the code area
+// (invalid rows: 0xffffffff and MS_ERR_RANGE for the problem)
+hipError_t launch_batch_pack(int count, const ms_problem *P, const BatchEntry *E,
+                             unsigned char *codearea, int *pstatus, int *status, hipStream_t st);
 template <typename T>
 hipError_t launch_batch_cs(int count, const ms_problem *P, const BatchEntry *E,
-                           const BatchTotals *tot, unsigned char *yarea, int *pstatus,
-                           int *status, int grid, hipStream_t st);
+                           const BatchTotals *tot, const unsigned char *codearea,
+                           unsigned char *yarea, int *pstatus, int *status, int grid,
+                           hipStream_t st);
 hipError_t launch_batch_gemm(int count, ms_dtype g_dtype, const ms_problem *P,
                              const BatchEntry *E, const BatchTotals *tot,
                              const unsigned char *yarea, unsigned char *parea, int grid,
@@ -354,9 +367,9 @@ hipError_t launch_batch_residual(int count, const ms_problem *P, const BatchEntr
                                  const BatchTotals *tot, unsigned char *rarea, int grid,
                                  hipStream_t st);
 hipError_t launch_batch_cs_res(int count, const ms_problem *P, const BatchEntry *E,
-                               const BatchTotals *tot, const unsigned char *rarea,
-                               unsigned char *yrarea, int *pstatus, int *status, int grid,
-                               hipStream_t st);
+                               const BatchTotals *tot, const unsigned char *codearea,
+                               const unsigned char *rarea, unsigned char *yrarea, int *pstatus,
+                               int *status, int grid, hipStream_t st);
 hipError_t launch_batch_gemv(int count, ms_dtype g_dtype, const ms_problem *P,
                              const BatchEntry *E, const BatchTotals *tot,
                              const unsigned char *yrarea, unsigned char *gvarea, int grid,

@@ -58,12 +58,13 @@ class Request:
 def footprint_bytes(d: int, n: int, nrhs: int, k: int, k2: int, w: int = 4,
                     refine: bool = False) -> int:
     """HBM a request holds while in flight: its inputs and output plus its
-    share of the batched workspace (sketch, split-K partials, Z; with
-    refinement also the QR factors, the FP64 residual, its sketch and the
-    Gaussian-stage partials of the residual)."""
+    share of the batched workspace (packed bucket/sign words, sketch,
+    split-K partials, Z; with refinement also the QR factors, the FP64
+    residual, its sketch and the Gaussian-stage partials of the residual)."""
     data = d * (n + nrhs) * w + d * 5 + k2 * k * w + n * nrhs * 8
     nsplit = (k + 1023) // 1024
-    work = k * (n + nrhs) * w + nsplit * k2 * (n + nrhs) * 4 + k2 * (n + nrhs) * 8 + 1024
+    work = (d * 4 + k * (n + nrhs) * w + nsplit * k2 * (n + nrhs) * 4 + k2 * (n + nrhs) * 8
+            + 1280)
     if refine:
         work += (k2 * n + n) * 8 + d * nrhs * 8 + k * nrhs * 8 + nsplit * k2 * nrhs * 8 + 1024
     return data + work

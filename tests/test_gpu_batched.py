@@ -71,7 +71,10 @@ def test_batched_fp32(ms, orc, gd):
 
 
 def test_batched_graph_replay_with_new_problems(ms, orc):
-    shapes = [(20000, 8, 2), (30000, 16, 1), (10000, 8, 3)]
+    # n = 32 (33 columns in 9 column tiles) packs its rows into bucket words;
+    # the second set has more rows than the captured capacity, so its replays
+    # read h and s in every work item instead
+    shapes = [(20000, 8, 2), (30000, 16, 1), (10000, 8, 3), (12000, 32, 1)]
     set1 = [make_problem(ms, d, n, r, seed=300 + i) for i, (d, n, r) in enumerate(shapes)]
     set2 = [make_problem(ms, d + 777, n, r, seed=400 + i) for i, (d, n, r) in enumerate(shapes)]
     runner = ms.BatchRunner([p[1] for p in set1])
