@@ -118,25 +118,48 @@ SERVE_WORKLOAD = ("Poisson arrivals at 2,000/s; d log-uniform in [2^14, 2^20], n
 
 def serving_leg(ms, torch, np, count, seed, refine, dev):
     """Continuous-batching serving loop over the request stream: open loop at
-    2,000 requests/s and closed loop (all requests at t = 0, saturation)."""
+    2,000 requests/s and closed loop (all requests at t = 0, saturation), for
+    the mixed-precision batched solver with `refine` steps (top-level keys)
+    and, under "variants", for every path: the plain FP64 multisketch one
+    request per call (the paper's path) and batched, and the mixed-precision
+    batched solver with 0..3 refinement steps."""
     from paper_2508_14209_amd import serve
     out = {"workload": SERVE_WORKLOAD, "requests": count, "g_dtype": "bf16",
            "refine_steps": refine, "max_batch": 64, "streams": 4}
-    # warm-up: load every kernel of the batched path once
-    warm = serve.make_requests(16, 0.0, seed=seed + 7)
-    serve.Server(max_batch=8, streams=2, g_dtype="bf16", refine_steps=refine, device=dev).run(warm)
-    for name, rate in (("open_loop_2000_per_s", 2000.0), ("closed_loop", 0.0)):
-        reqs = serve.make_requests(count, rate, seed=seed)
-        srv = serve.Server(hbm_budget=96 << 30, max_inflight=512, max_batch=64, streams=4,
-                           g_dtype="bf16", refine_steps=refine, device=dev)
-        t0 = time.perf_counter()
-        done = srv.run(reqs)
-        wall = time.perf_counter() - t0
-        summ = serve.summarize(done, wall)
-        summ.update({"wall_s": wall, "batches": srv.nbatches,
-                     "peak_inflight_bytes": srv.admission.peak_bytes,
-                     "failed": sum(1 for r in done if r.status != ms.MS_OK)})
-        out[name] = summ
+
+    def run_variant(g_dtype, a_dtype, single, rsteps):
+        # each variant starts from an empty allocator cache: the previous
+        # variant's closed loop leaves tens of GB of blocks of other sizes
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        # warm-up: load every kernel of the path once
+        warm = serve.make_requests(16, 0.0, seed=seed + 7)
+        serve.Server(max_batch=8, streams=2, g_dtype=g_dtype, a_dtype=a_dtype, single=single,
+                     refine_steps=rsteps, device=dev).run(warm)
+        res = {}
+        for name, rate in (("open_loop_2000_per_s", 2000.0), ("closed_loop", 0.0)):
+            reqs = serve.make_requests(count, rate, seed=seed)
+            srv = serve.Server(hbm_budget=96 << 30, max_inflight=512, max_batch=64,
+                               streams=1 if single else 4, g_dtype=g_dtype, a_dtype=a_dtype,
+                               single=single, refine_steps=rsteps, device=dev)
+            t0 = time.perf_counter()
+            done = srv.run(reqs)
+            wall = time.perf_counter() - t0
+            summ = serve.summarize(done, wall)
+            summ.update({"wall_s": wall, "batches": srv.nbatches,
+                         "peak_inflight_bytes": srv.admission.peak_bytes,
+                         "failed": sum(1 for r in done if r.status != ms.MS_OK)})
+            res[name] = summ
+        return res
+
+    main = run_variant("bf16", "f32", False, refine)
+    out.update(main)
+    variants = {"plain_fp64_one_per_call": run_variant("f64", "f64", True, 0),
+                "plain_fp64_batched": run_variant("f64", "f64", False, 0)}
+    for r in range(4):
+        variants["mixed_bf16_batched_refine%d" % r] = (main if r == refine
+                                                        else run_variant("bf16", "f32", False, r))
+    out["variants"] = variants
     return out
 
 

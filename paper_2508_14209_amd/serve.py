@@ -70,8 +70,10 @@ def footprint_bytes(d: int, n: int, nrhs: int, k: int, k2: int, w: int = 4,
     return data + work
 
 
-def generate(req: Request, device, g_dtype: str = "f32") -> dict:
-    """Seeded synthetic inputs of one request, on the current stream."""
+def generate(req: Request, device, g_dtype: str = "f32", a_dtype: str = "f32") -> dict:
+    """Seeded synthetic inputs of one request, on the current stream.  A and B
+    are drawn in FP32; a_dtype "f64" promotes them exactly (and g_dtype "f64"
+    promotes G) for the plain FP64 path."""
     g = torch.Generator(device=device)
     g.manual_seed(int(req.seed))
     d, n, nrhs, k, k2 = req.d, req.n, req.nrhs, req.k, req.k2
@@ -90,6 +92,16 @@ def generate(req: Request, device, g_dtype: str = "f32") -> dict:
         Gb = torch.empty((k, k2), device=device, dtype=torch.bfloat16).t()
         Gb.copy_(Gm)
         Gm = Gb
+    elif g_dtype == "f64":
+        G64 = ms.empty_colmajor(k2, k, torch.float64, device)
+        G64.copy_(Gm)
+        Gm = G64
+    if a_dtype == "f64":
+        A64 = ms.empty_colmajor(d, n, torch.float64, device)
+        A64.copy_(A)
+        B64 = ms.empty_colmajor(d, nrhs, torch.float64, device)
+        B64.copy_(B)
+        A, B = A64, B64
     X = ms.empty_colmajor(n, nrhs, torch.float64, device)
     return dict(A=A, B=B, h=h, s=s.to(torch.int8), G=Gm, X=X, k=k, xstar=xs)
 
@@ -133,7 +145,7 @@ class Server:
     def __init__(self, hbm_budget: int = 64 << 30, max_inflight: int = 256, max_batch: int = 64,
                  streams: int = 4, g_dtype: str = "f32", rows_log2: int = 0,
                  kchunk_log2: int = 0, refine_steps: int = 0, tuned: bool = False,
-                 device="cuda"):
+                 a_dtype: str = "f32", single: bool = False, device="cuda"):
         self.device = torch.device(device)
         self.admission = Admission(hbm_budget, max_inflight)
         self.max_batch = max_batch
@@ -142,6 +154,8 @@ class Server:
         self.kchunk_log2 = kchunk_log2
         self.refine_steps = refine_steps
         self.tuned = tuned              # take rows/K per item from the autotuner's cache
+        self.a_dtype = a_dtype          # "f64": A, B promoted exactly (the plain FP64 path)
+        self.single = single            # one request per call of the single-problem solver
         self.gen_stream = torch.cuda.Stream(device=self.device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self.busy = {}                # stream index -> (event, runner, requests)
@@ -157,6 +171,7 @@ class Server:
     # -- arrivals and admission ------------------------------------------------
     def arrive(self, req: Request):
         req.footprint = footprint_bytes(req.d, req.n, req.nrhs, req.k, req.k2,
+                                        w=8 if self.a_dtype == "f64" else 4,
                                         refine=self.refine_steps > 0)
         self.waiting.append(req)
         self._admit()
@@ -169,7 +184,7 @@ class Server:
             self.waiting.popleft()
             req.t_admit = self.now()
             with torch.cuda.stream(self.gen_stream):
-                req.tensors = generate(req, self.device, self.g_dtype)
+                req.tensors = generate(req, self.device, self.g_dtype, self.a_dtype)
                 ev = torch.cuda.Event()
                 ev.record(self.gen_stream)
             req.gen_event = ev
@@ -181,23 +196,34 @@ class Server:
             if si in self.busy or not self.ready:
                 continue
             batch = []
-            while self.ready and len(batch) < self.max_batch:
+            cap = 1 if self.single else self.max_batch
+            while self.ready and len(batch) < cap:
                 batch.append(self.ready.popleft())
             probs = [r.tensors for r in batch]
             st.wait_stream(self.gen_stream)     # inputs generated before the solve
             for pr in probs:                    # memory of the generator stream used here
                 for key in ("A", "B", "h", "s", "G", "X"):
                     pr[key].record_stream(st)
-            rl, kl = self.rows_log2, self.kchunk_log2
-            if self.tuned and not (rl or kl):
-                from paper_2508_14209_amd import autotune
-                rl, kl = autotune.batch_params(probs, self.device)
-            with torch.cuda.stream(st):
-                runner = ms.BatchRunner(probs, rows_log2=rl, kchunk_log2=kl,
-                                        refine_steps=self.refine_steps)
-                runner.launch(st)
-                ev = torch.cuda.Event()
-                ev.record(st)
+            if self.single:
+                # the paper's path: one sketch_lstsq call per request
+                pr = probs[0]
+                with torch.cuda.stream(st):
+                    _, ws = ms.sketch_lstsq(pr["A"], pr["B"], pr["h"], pr["s"], pr["G"], pr["k"],
+                                            refine_steps=self.refine_steps, X=pr["X"], stream=st)
+                    ev = torch.cuda.Event()
+                    ev.record(st)
+                runner = ("single", ws)
+            else:
+                rl, kl = self.rows_log2, self.kchunk_log2
+                if self.tuned and not (rl or kl):
+                    from paper_2508_14209_amd import autotune
+                    rl, kl = autotune.batch_params(probs, self.device)
+                with torch.cuda.stream(st):
+                    runner = ms.BatchRunner(probs, rows_log2=rl, kchunk_log2=kl,
+                                            refine_steps=self.refine_steps)
+                    runner.launch(st)
+                    ev = torch.cuda.Event()
+                    ev.record(st)
             tl = self.now()
             for r in batch:
                 r.t_launch = tl
@@ -211,7 +237,14 @@ class Server:
             if not ev.query():
                 continue
             t = self.now()
-            st, per = runner.status(self.streams[si])
+            if isinstance(runner, tuple):
+                try:
+                    ms.check_status(runner[1], self.streams[si])
+                    per = [ms.MS_OK]
+                except ms.MsketchError as e:
+                    per = [e.code]
+            else:
+                st, per = runner.status(self.streams[si])
             for r, code in zip(batch, per):
                 r.t_done = t
                 r.status = code

@@ -68,3 +68,30 @@ def test_serving_respects_hbm_budget(ms):
     assert len(done) == 24 and all(r.status == ms.MS_OK for r in done)
     assert srv.admission.peak_bytes <= budget
     assert srv.nbatches >= 3
+
+
+@pytest.mark.parametrize("single", [True, False])
+def test_serving_plain_fp64_paths(ms, orc, single):
+    # the plain FP64 comparators of the serving measurement: A, B and G
+    # promoted exactly to FP64, solved one request per sketch_lstsq call (the
+    # paper's path) or in batches; every request against the oracle at the
+    # FP64 bar on the same (promoted) inputs
+    # (condition numbers up to 10, so the association-order differences stay
+    # well inside the FP64 bar)
+    from paper_2508_14209_amd import serve
+    reqs = serve.make_requests(12, 4000.0, seed=5, d_lo=1 << 12, d_hi=1 << 15, ns=(8, 16, 32),
+                               nrhs_max=4, kappa_lo=1.0, kappa_hi=10.0)
+    for r in reqs:
+        r.extra["kept"] = True
+    srv = serve.Server(hbm_budget=1 << 30, max_inflight=16, max_batch=4, streams=2,
+                       g_dtype="f64", a_dtype="f64", single=single)
+    done = srv.run(reqs, keep_tensors=True)
+    assert len(done) == len(reqs) and all(r.status == ms.MS_OK for r in done)
+    if single:
+        assert srv.nbatches == len(reqs)
+    for r in done:
+        T = r.tensors
+        assert T["A"].dtype == torch.float64 and T["G"].dtype == torch.float64
+        Xr, _, _ = orc.sketch_lstsq(to_host(T["A"]), to_host(T["B"]), to_host(T["h"]),
+                                    to_host(T["s"]), to_host(T["G"]), T["k"])
+        assert rel(to_host(T["X"]), Xr) <= 1e-12, (r.id, single)
