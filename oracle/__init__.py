@@ -73,6 +73,8 @@ def _load():
                                     _i64, _p, _p],
             "or_round_bf16": [ctypes.c_float],
             "or_round_bf16_array": [_i64, _p, _p],
+            "or_rand_cholqr_from_sketch": [_i64, _i64, _i64, _i64, _p, _i64, _p, _i64,
+                                           _p, _i64, _p, _i64, _p, _i64],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -312,6 +314,47 @@ def sketch_lstsq(A, B, h, s, G, k: int, y_bf16: bool = False):
         return X, Y, Z
     _check(rc, "sketch_lstsq")
     return X, Y, Z
+
+
+# --------------------------------------------------------------------------
+# rand_cholQR least squares (Alg. 5) with the multisketch S = G C
+# --------------------------------------------------------------------------
+
+def rand_cholqr_from_sketch(SA, A, B):
+    """Alg. 5 steps 2-8 given the sketch SA = S A (m x n): R0 from the
+    Householder QR of SA, Q0 = A R0^{-1} row by row, Gm = Q0^T Q0 and
+    z = Q0^T B, R1 = chol(Gm), R = R1 R0, y = R1^{-T} z, x = R^{-1} y, all in
+    FP64 (an FP32 A or B is promoted exactly).  Returns (X, R)."""
+    SA = _fortran(SA, np.float64)
+    A = _fortran(A, np.float64)
+    B = _fortran(B, np.float64)
+    m, n = SA.shape
+    d = A.shape[0]
+    nrhs = B.shape[1]
+    X = np.zeros((n, nrhs), dtype=np.float64, order="F")
+    R = np.zeros((n, n), dtype=np.float64, order="F")
+    rc = _load().or_rand_cholqr_from_sketch(d, n, nrhs, m, _ptr(SA), _ld(SA), _ptr(A), _ld(A),
+                                            _ptr(B), _ld(B), _ptr(X), max(1, n), _ptr(R),
+                                            max(1, n))
+    _check(rc, "rand_cholqr")
+    return X, R
+
+
+def rand_cholqr_lstsq(A, B, h, s, G, k: int, y_bf16: bool = False):
+    """x = argmin ||B - A x|| by rand_cholQR least squares (Alg. 5) with the
+    multisketch S = G C as the sketch operator (step 1: the CountSketch of A
+    in A's precision, optionally rounded to BF16 for an FP32 A, then the
+    Gaussian stage in FP64 on the stored values of G).  Returns (X, R, SA)."""
+    A = np.asarray(A)
+    Gd = _fortran(G, np.float64)
+    if Gd.shape[1] != k:
+        raise ValueError("G must be k2 x k")
+    Y = countsketch(A, h, s, k)
+    if A.dtype == np.float32 and y_bf16:
+        Y = round_bf16(Y)
+    SA = gemm(Gd, np.asarray(Y, dtype=np.float64))
+    X, R = rand_cholqr_from_sketch(SA, A, B)
+    return X, R, SA
 
 
 def round_bf16(x) -> np.ndarray:

@@ -437,3 +437,111 @@ int or_sketch_lstsq_f32(int64_t d, int64_t n, int64_t nrhs, int64_t k,
   free(Z);
   return st;
 }
+
+/* ------------------------------------------------------------------------ */
+/* rand_cholQR least squares (Alg. 5, Sec. 6.3) with the multisketch S = G C */
+/* as the sketch operator.  The steps in the paper's order:                 */
+/*   1. Y = S A                 (CountSketch of A, then the Gaussian stage)  */
+/*   2. R0 = R factor of the economy QR of Y (Householder)                   */
+/*   3. Q0 = A R0^{-1}          (each row q of Q0 solves q R0 = a)           */
+/*   4. Gm = Q0^T Q0, z = Q0^T B                                             */
+/*   5. R1 = chol(Gm)           (upper, Gm = R1^T R1)                        */
+/*   6. R = R1 R0                                                            */
+/*   7. y = R1^{-T} z                                                        */
+/*   8. x = R^{-1} y                                                         */
+/* Q0 is never stored: each row is solved and folded into Gm and z in       */
+/* ascending row order.  Y_f64 holds S A in FP64 (the caller's sketch of A  */
+/* in whatever precision it was formed, promoted); A and B are FP64 (FP32   */
+/* data promoted exactly by the caller).  R (n x n, upper, zeros below) is   */
+/* written when Rout is not NULL.                                            */
+/* ------------------------------------------------------------------------ */
+int or_rand_cholqr_from_sketch(int64_t d, int64_t n, int64_t nrhs, int64_t m,
+                               const double *SA, int64_t lds, const double *A,
+                               int64_t lda, const double *B, int64_t ldb, double *X,
+                               int64_t ldx, double *Rout, int64_t ldr) {
+  if (m < n || n < 1) return ORACLE_ERR_ARG;
+  double *W = (double *)malloc((size_t)(m * n) * sizeof(double));
+  double *tau = (double *)malloc((size_t)n * sizeof(double));
+  double *Gm = (double *)calloc((size_t)(n * n), sizeof(double));
+  double *z = (double *)calloc((size_t)(n * (nrhs > 0 ? nrhs : 1)), sizeof(double));
+  double *q = (double *)malloc((size_t)n * sizeof(double));
+  double *R = (double *)calloc((size_t)(n * n), sizeof(double));
+  int st = ORACLE_OK;
+  if (!W || !tau || !Gm || !z || !q || !R) {
+    st = ORACLE_ERR_NOMEM;
+    goto done;
+  }
+  /* step 2: R0 in the upper triangle of W */
+  for (int64_t c = 0; c < n; ++c)
+    for (int64_t i = 0; i < m; ++i) W[i + c * m] = SA[i + c * lds];
+  or_householder_qr(m, n, W, m, tau);
+  for (int64_t j = 0; j < n; ++j)
+    if (W[j + j * m] == 0.0 || !isfinite(W[j + j * m])) {
+      st = ORACLE_ERR_SINGULAR;
+      goto done;
+    }
+  /* steps 3-4: row i of Q0 by forward substitution, folded into Gm and z */
+  for (int64_t i = 0; i < d; ++i) {
+    for (int64_t j = 0; j < n; ++j) {
+      double acc = A[i + j * lda];
+      for (int64_t l = 0; l < j; ++l) acc = acc - q[l] * W[l + j * m];
+      q[j] = acc / W[j + j * m];
+    }
+    for (int64_t c2 = 0; c2 < n; ++c2)
+      for (int64_t p = 0; p < n; ++p) Gm[p + c2 * n] = Gm[p + c2 * n] + q[p] * q[c2];
+    for (int64_t c = 0; c < nrhs; ++c)
+      for (int64_t p = 0; p < n; ++p) z[p + c * n] = z[p + c * n] + q[p] * B[i + c * ldb];
+  }
+  /* step 5: Cholesky Gm = R1^T R1, R1 in the upper triangle of Gm */
+  for (int64_t j = 0; j < n; ++j) {
+    double diag = Gm[j + j * n];
+    for (int64_t t = 0; t < j; ++t) diag = diag - Gm[t + j * n] * Gm[t + j * n];
+    if (!(diag > 0.0) || !isfinite(diag)) {
+      st = ORACLE_ERR_SINGULAR;
+      goto done;
+    }
+    const double rjj = sqrt(diag);
+    Gm[j + j * n] = rjj;
+    for (int64_t c2 = j + 1; c2 < n; ++c2) {
+      double acc = Gm[j + c2 * n];
+      for (int64_t t = 0; t < j; ++t) acc = acc - Gm[t + j * n] * Gm[t + c2 * n];
+      Gm[j + c2 * n] = acc / rjj;
+    }
+  }
+  /* step 6: R = R1 R0 (both upper triangular) */
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t i = 0; i <= j; ++i) {
+      double acc = 0.0;
+      for (int64_t t = i; t <= j; ++t) acc = acc + Gm[i + t * n] * W[t + j * m];
+      R[i + j * n] = acc;
+    }
+  /* steps 7-8: R1^T y = z (forward), then R x = y (backward) */
+  for (int64_t c = 0; c < nrhs; ++c) {
+    double *y = z + c * n;
+    for (int64_t i = 0; i < n; ++i) {
+      double acc = y[i];
+      for (int64_t t = 0; t < i; ++t) acc = acc - Gm[t + i * n] * y[t];
+      y[i] = acc / Gm[i + i * n];
+    }
+    double *x = X + c * ldx;
+    for (int64_t i = n - 1; i >= 0; --i) {
+      double acc = y[i];
+      for (int64_t t = i + 1; t < n; ++t) acc = acc - R[i + t * n] * x[t];
+      x[i] = acc / R[i + i * n];
+    }
+  }
+  if (Rout)
+    for (int64_t j = 0; j < n; ++j)
+      for (int64_t i = 0; i < n; ++i) Rout[i + j * ldr] = i <= j ? R[i + j * n] : 0.0;
+done:
+  if (st != ORACLE_OK && st != ORACLE_ERR_NOMEM)
+    for (int64_t c = 0; c < nrhs; ++c)
+      for (int64_t p = 0; p < n; ++p) X[p + c * ldx] = NAN;
+  free(W);
+  free(tau);
+  free(Gm);
+  free(z);
+  free(q);
+  free(R);
+  return st;
+}

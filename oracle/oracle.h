@@ -52,5 +52,9 @@ int or_sketch_lstsq_f32(int64_t d, int64_t n, int64_t nrhs, int64_t k,
                         const int8_t *s, const double *G, int64_t ldg,
                         int y_bf16, double *X, int64_t ldx, float *Ys,
                         double *Zs);
+int or_rand_cholqr_from_sketch(int64_t d, int64_t n, int64_t nrhs, int64_t m,
+                               const double *SA, int64_t lds, const double *A,
+                               int64_t lda, const double *B, int64_t ldb, double *X,
+                               int64_t ldx, double *Rout, int64_t ldr);
 
 #endif

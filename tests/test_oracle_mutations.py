@@ -46,6 +46,15 @@ MUTANTS = [
     ("composite_rhs_offset", "st = or_countsketch_f64(d, nrhs, k, B, ldb, h, s, Y + n * k, k);",
      "st = or_countsketch_f64(d, nrhs, k, B, ldb, h, s, Y + (n - 1) * k, k);", 0),
     ("bf16_ties_away", "u = u + 0x7fffu + lsb;", "u = u + 0x8000u + 0 * lsb;", 0),
+    # rand_cholQR least squares (Alg. 5)
+    ("rcq_no_cholesky_correction", "for (int64_t t = i; t <= j; ++t) acc = acc + Gm[i + t * n] * W[t + j * m];",
+     "acc = W[i + j * m];", 0),
+    ("rcq_r1_not_transposed", "for (int64_t t = 0; t < i; ++t) acc = acc - Gm[t + i * n] * y[t];",
+     "for (int64_t t = 0; t < i; ++t) acc = acc - Gm[i + t * n] * y[t];", 0),
+    ("rcq_q0_times_r0", "for (int64_t l = 0; l < j; ++l) acc = acc - q[l] * W[l + j * m];\n      q[j] = acc / W[j + j * m];",
+     "for (int64_t l = 0; l < j; ++l) acc = acc - q[l] * W[l + j * m];\n      q[j] = acc * W[j + j * m];", 0),
+    ("rcq_rhs_skips_first_row", "for (int64_t p = 0; p < n; ++p) z[p + c * n] = z[p + c * n] + q[p] * B[i + c * ldb];",
+     "if (i > 0) for (int64_t p = 0; p < n; ++p) z[p + c * n] = z[p + c * n] + q[p] * B[i + c * ldb];", 0),
 ]
 
 
@@ -73,7 +82,8 @@ def _run_mutant(args):
     env = dict(os.environ, MSKETCH_ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_countsketch.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_solve.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_solve.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_rcq.py")],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     return name, r.returncode, r.stdout[-600:]
 
