@@ -98,6 +98,7 @@ typedef struct {
 #define MS_OP_MULTISKETCH 3
 #define MS_OP_QR_SOLVE 4
 #define MS_OP_LSTSQ 5
+#define MS_OP_RAND_CHOLQR 6
 
 /*
  * Bytes of workspace the operation needs (a multiple of 256, at least 256).
@@ -244,6 +245,34 @@ ms_status sketch_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k,
                        int64_t ldg, double *X, int64_t ldx,
                        const ms_opts *opts, void *ws, size_t ws_bytes,
                        void *stream);
+
+/*
+ * rand_cholQR least squares (Alg. 5, Sec. 6.3) with the multisketch S = G C
+ * as the sketch operator: X = argmin ||B - A X||, the least-squares optimum
+ * itself (the sketch only preconditions; no O(1) distortion as in
+ * sketch_lstsq).  Steps: Y = S A (CountSketch of A in its precision, then
+ * the Gaussian stage), R0 = the R factor of the Householder QR of Y,
+ * Q0 = A R0^{-1}, Q0^T Q0 and Q0^T B in FP64 in one pass over A and B
+ * (FP32 data promoted exactly; Q0 is not stored), R1 = chol(Q0^T Q0),
+ * R = R1 R0, y = R1^{-T} Q0^T B, X = R^{-1} y.  Stable for kappa(A) < 1/u
+ * (Sec. 6.3); the FP32 / BF16 sketch of an FP32 A changes only the
+ * preconditioner, so X is the FP64 optimum for the stored data.
+ *   Arguments as for sketch_lstsq, plus R (may be NULL): n x n (ld ldr >= n),
+ *   receives R (upper triangular, zeros below; A = Q R with Q = A R^{-1}).
+ *   opts->refine_steps must be 0.
+ * Limits: n <= 64, nrhs <= 16 (else MS_ERR_UNSUPPORTED).  Device status:
+ * MS_ERR_SINGULAR (X = NaN) when R0 or the Cholesky factor breaks down,
+ * MS_ERR_RANGE for h or s out of range.
+ * ws: ms_workspace_size(MS_OP_RAND_CHOLQR, d, n, nrhs, k, k2, a_dtype,
+ * g_dtype, opts) bytes.
+ */
+ms_status rand_cholqr_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k,
+                            int64_t k2, ms_dtype a_dtype, const void *A,
+                            int64_t lda, const void *B, int64_t ldb,
+                            const int32_t *h, const int8_t *s, ms_dtype g_dtype,
+                            const void *G, int64_t ldg, double *X, int64_t ldx,
+                            double *R, int64_t ldr, const ms_opts *opts, void *ws,
+                            size_t ws_bytes, void *stream);
 
 /*
  * One problem of a batched multisketch sketch-and-solve (all device

@@ -23,7 +23,8 @@ __all__ = [
     "MS_ERR_DEVICE", "MS_ERR_UNSUPPORTED", "MsketchError", "LIB_PATH",
     "empty_colmajor", "colmajor", "workspace", "workspace_size", "check_status",
     "bucket_plan", "pack_sketch", "countsketch_accumulate", "countsketch_apply",
-    "gaussian_apply", "multisketch_apply", "qr_solve", "sketch_lstsq", "MsProblem",
+    "gaussian_apply", "multisketch_apply", "qr_solve", "sketch_lstsq", "rand_cholqr_lstsq",
+    "MsProblem",
     "batch_workspace_size", "sketch_lstsq_batched", "batch_status", "BatchRunner",
 ]
 
@@ -35,7 +36,7 @@ MS_OK, MS_ERR_ARG, MS_ERR_RANGE, MS_ERR_NOMEM, MS_ERR_SINGULAR, MS_ERR_DEVICE, \
 MS_F64, MS_F32, MS_BF16 = 0, 1, 2
 MODES = {"auto": 0, "atomic": 1, "lds": 2, "sorted": 3}
 OPS = {"bucket_plan": 0, "countsketch": 1, "gaussian": 2, "multisketch": 3,
-       "qr_solve": 4, "lstsq": 5}
+       "qr_solve": 4, "lstsq": 5, "rand_cholqr": 6}
 MS_SORTED_MAX_SEGMENT = 16384
 
 if not os.path.exists(LIB_PATH):
@@ -82,6 +83,8 @@ _SIGS = {
                      _p], _i32),
     "sketch_lstsq": ([_i64, _i64, _i64, _i64, _i64, _i32, _p, _i64, _p, _i64, _p, _p,
                       _i32, _p, _i64, _p, _i64, _p, _p, _sz, _p], _i32),
+    "rand_cholqr_lstsq": ([_i64, _i64, _i64, _i64, _i64, _i32, _p, _i64, _p, _i64, _p, _p,
+                           _i32, _p, _i64, _p, _i64, _p, _i64, _p, _p, _sz, _p], _i32),
     "ms_batch_workspace_size": ([_i32, _p, _i32, _i32, _p], _sz),
     "sketch_lstsq_batched": ([_i32, _p, _p, _i32, _i32, _p, _p, _sz, _p], _i32),
     "ms_batch_status": ([_p, _i32, _p, _p], _i32),
@@ -356,6 +359,39 @@ def sketch_lstsq(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torch.Ten
                           _vec(s, torch.int8, "s"), g_dt, Gp, ldg, Xp, ldx, ctypes.byref(o), wp,
                           have, _stream(stream)), "sketch_lstsq")
     return X, ws
+
+
+def rand_cholqr_lstsq(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torch.Tensor,
+                      G: torch.Tensor, k: int, mode: str = "auto", X: torch.Tensor | None = None,
+                      R: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None):
+    """X = argmin ||B - A X|| by rand_cholQR least squares with the multisketch
+    G C as the sketch operator (n x nrhs, FP64; the least-squares optimum, no
+    sketch distortion).  R (optional, n x n FP64) receives the R factor of A.
+    Returns (X, R, ws)."""
+    d, n = A.shape
+    if B.dim() == 1:
+        B = B.unsqueeze(1)
+    nrhs = B.shape[1]
+    k2 = G.shape[0]
+    a_dt, g_dt = _dt(A), _dt(G)
+    if B.dtype != A.dtype:
+        raise ValueError("B must have A's dtype")
+    if X is None:
+        X = empty_colmajor(n, nrhs, torch.float64, A.device)
+    Ap, lda = colmajor(A, "A")
+    Bp, ldb = colmajor(B, "B")
+    Gp, ldg = colmajor(G, "G")
+    Xp, ldx = colmajor(X, "X")
+    Rp, ldr = colmajor(R, "R") if R is not None else (None, n)
+    need = workspace_size("rand_cholqr", d=d, n=n, nrhs=nrhs, k=k, k2=k2, a_dtype=a_dt,
+                          g_dtype=g_dt, mode=mode)
+    ws = workspace(need, A.device) if ws is None else ws
+    wp, have = _ws_ptr(ws, need)
+    o = _opts(mode, 0)
+    _ok(_lib.rand_cholqr_lstsq(d, n, nrhs, k, k2, a_dt, Ap, lda, Bp, ldb, _vec(h, torch.int32, "h"),
+                               _vec(s, torch.int8, "s"), g_dt, Gp, ldg, Xp, ldx, Rp, ldr,
+                               ctypes.byref(o), wp, have, _stream(stream)), "rand_cholqr_lstsq")
+    return X, R, ws
 
 
 # --------------------------------------------------------------------------

@@ -130,6 +130,33 @@ LstsqLayout lstsq_layout(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64_t 
   return L;
 }
 
+// rand_cholQR least squares: the multisketch of A alone, its QR (R0 kept),
+// R0^{-1}, the fused pass's per-workgroup partials and their sum.
+struct RcqLayout {
+  CsLayout cs;
+  size_t y = 0, partials = 0, z64 = 0, qr = 0, fact = 0, tau = 0;
+  size_t r0 = 0, rinv = 0, part = 0, w = 0, total = 0;
+};
+
+RcqLayout rcq_layout(int64_t d, int64_t n, int64_t k, int64_t k2, ms_dtype a_dtype,
+                     ms_dtype g_dtype, int mode) {
+  RcqLayout L;
+  Carve cv;
+  carve_cs(cv, L.cs, d, k, mode, n, dtype_size(a_dtype));
+  L.y = cv.take((size_t)k * n * dtype_size(a_dtype));
+  L.partials = cv.take(plan_gemm(k2, n, k, g_dtype).partial_bytes);
+  L.z64 = cv.take((size_t)k2 * n * 8);
+  L.qr = cv.take(qr_workspace_bytes(k2, n, 0));
+  L.fact = cv.take((size_t)k2 * n * 8);
+  L.tau = cv.take((size_t)n * 8);
+  L.r0 = cv.take((size_t)kRcqMaxN * kRcqMaxN * 8);
+  L.rinv = cv.take((size_t)kRcqMaxN * kRcqMaxN * 8);
+  L.part = cv.take(rcq_partial_bytes(rcq_grid()));
+  L.w = cv.take((size_t)kRcqMaxN * kRcqMaxCols * 8);
+  L.total = cv.off;
+  return L;
+}
+
 template <typename P>
 P *at(void *ws, size_t off) {
   return reinterpret_cast<P *>(static_cast<unsigned char *>(ws) + off);
@@ -252,6 +279,8 @@ size_t ms_workspace_size(int op, int64_t d, int64_t n, int64_t nrhs, int64_t k, 
       const int refine = opts ? opts->refine_steps : 0;
       return lstsq_layout(d, n, nrhs, k, k2, a_dtype, g_dtype, mode, refine).total;
     }
+    case MS_OP_RAND_CHOLQR:
+      return rcq_layout(d, n, k, k2, a_dtype, g_dtype, mode).total;
     default:
       return 0;
   }
@@ -517,6 +546,67 @@ ms_status sketch_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64_t k2
     if (e != hipSuccess) break;
     e = launch_axpy_update(n, nrhs, at<double>(ws, L.dx), X, ldx, st);
   }
+  return from_hip(e);
+}
+
+ms_status rand_cholqr_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64_t k2,
+                            ms_dtype a_dtype, const void *A, int64_t lda, const void *B,
+                            int64_t ldb, const int32_t *h, const int8_t *s, ms_dtype g_dtype,
+                            const void *G, int64_t ldg, double *X, int64_t ldx, double *R,
+                            int64_t ldr, const ms_opts *opts, void *ws, size_t ws_bytes,
+                            void *stream) {
+  if (d < 1 || n < 1 || nrhs < 1 || k < 1 || k > kMax31 || k2 < n || k2 > (1 << 24))
+    return MS_ERR_ARG;
+  const bool ok = (a_dtype == MS_F64 && g_dtype == MS_F64) ||
+                  (a_dtype == MS_F32 && (g_dtype == MS_F32 || g_dtype == MS_BF16));
+  if (!ok || !valid_mode(opts)) return MS_ERR_ARG;
+  if (opts && opts->refine_steps != 0) return MS_ERR_ARG;
+  if (n > kRcqMaxN || nrhs > kRcqMaxRhs || n + nrhs > kRcqMaxCols) return MS_ERR_UNSUPPORTED;
+  const int mode = resolve_mode(opts);
+  if (mode == MS_CS_SORTED && d > kMax31) return MS_ERR_UNSUPPORTED;
+  if (lda < d || ldb < d || ldg < k2 || ldx < n || (R && ldr < n)) return MS_ERR_ARG;
+  if (!A || !B || !h || !s || !G || !X || !ws) return MS_ERR_ARG;
+  const RcqLayout L = rcq_layout(d, n, k, k2, a_dtype, g_dtype, mode);
+  if (ws_bytes < L.total) return MS_ERR_NOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  int *status = static_cast<int *>(ws);
+  hipError_t e;
+  // 1. Y = S A (CountSketch of A, then the Gaussian stage into an FP64 Z)
+  if (a_dtype == MS_F64) {
+    Cols<double> c{static_cast<const double *>(A), lda, nullptr, 0, (int)n, (int)n};
+    e = run_countsketch<double>(d, k, c, h, s, at<double>(ws, L.y), k, mode, ws, L.cs, status,
+                                st, tuning_of(opts));
+  } else {
+    Cols<float> c{static_cast<const float *>(A), lda, nullptr, 0, (int)n, (int)n};
+    e = run_countsketch<float>(d, k, c, h, s, at<float>(ws, L.y), k, mode, ws, L.cs, status, st,
+                               tuning_of(opts));
+  }
+  const GemmPlan p = plan_gemm(k2, n, k, g_dtype);
+  double *z64 = at<double>(ws, L.z64);
+  if (e == hipSuccess)
+    e = launch_gemm(p, g_dtype, G, ldg, at<void>(ws, L.y), k, nullptr, k2, z64,
+                    at<void>(ws, L.partials), nullptr, st);
+  // 2. R0 of the Householder QR of S A (no right-hand side)
+  double *r0 = at<double>(ws, L.r0);
+  if (e == hipSuccess)
+    e = launch_qr_solve(k2, n, 0, z64, k2, nullptr, k2, X, ldx, r0, kRcqMaxN,
+                        at<double>(ws, L.tau), at<double>(ws, L.fact), at<void>(ws, L.qr), status,
+                        st);
+  // 3-4. R0^{-1}; one pass: Q0 = A R0^{-1}, per-workgroup Q0^T [Q0 | B]
+  double *rinv = at<double>(ws, L.rinv), *part = at<double>(ws, L.part);
+  const int grid = rcq_grid();
+  if (e == hipSuccess) e = launch_rcq_trinv((int)n, r0, kRcqMaxN, rinv, status, st);
+  if (e == hipSuccess)
+    e = a_dtype == MS_F64
+            ? launch_rcq_gram<double>(d, (int)n, (int)nrhs, static_cast<const double *>(A), lda,
+                                      static_cast<const double *>(B), ldb, rinv, part, grid, st)
+            : launch_rcq_gram<float>(d, (int)n, (int)nrhs, static_cast<const float *>(A), lda,
+                                     static_cast<const float *>(B), ldb, rinv, part, grid, st);
+  // 5-8. the partials' sum, R1 = chol(Q0^T Q0), R = R1 R0, y = R1^{-T} Q0^T B,
+  // x = R^{-1} y
+  if (e == hipSuccess)
+    e = launch_rcq_finish((int)n, (int)nrhs, grid, part, at<double>(ws, L.w), r0, kRcqMaxN, X, ldx,
+                          R, ldr, status, st);
   return from_hip(e);
 }
 

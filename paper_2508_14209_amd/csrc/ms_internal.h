@@ -178,6 +178,24 @@ hipError_t launch_qr_apply_solve(int64_t m, int64_t n, int64_t nrhs, const doubl
                                  const double *tau, double *Bm, double *X, int64_t ldx,
                                  int *status, hipStream_t st);
 
+// rand_cholQR least squares (randcholqr.hip): R0^{-1} of the sketch's R
+// factor, the fused pass Q0 = A R0^{-1} -> Q0^T [Q0 | B] (per-workgroup
+// partials), then the ordered sum, Cholesky and the two triangular solves.
+constexpr int kRcqMaxN = 64;     // columns of A
+constexpr int kRcqMaxRhs = 16;   // right-hand sides
+constexpr int kRcqMaxCols = 80;  // n + nrhs (the partial's row length)
+size_t rcq_partial_bytes(int grid);
+int rcq_grid();
+hipError_t launch_rcq_trinv(int n, const double *R0, int ldr0, double *Rinv, int *status,
+                            hipStream_t st);
+template <typename TA>
+hipError_t launch_rcq_gram(int64_t d, int n, int nrhs, const TA *A, int64_t lda, const TA *B,
+                           int64_t ldb, const double *Rinv, double *part, int grid,
+                           hipStream_t st);
+hipError_t launch_rcq_finish(int n, int nrhs, int nparts, const double *part, double *W,
+                             const double *R0, int ldr0, double *X, int64_t ldx, double *R,
+                             int64_t ldr, int *status, hipStream_t st);
+
 // ---------------------------------------------------------------- batched
 // Item order of a persistent grid that keeps runs of consecutive items on
 // one die: workgroup g runs on die g % dies (the dispatcher's round-robin),

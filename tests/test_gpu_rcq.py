@@ -1,0 +1,125 @@
+"""GPU parity of rand_cholQR least squares (Alg. 5 with the multisketch as
+sketch operator) against the oracle, through the C ABI.
+
+Bar: FP64 normwise relative 1e-12 against the oracle on the same inputs.
+Both are within about kappa * u * n of the least-squares optimum for the
+condition numbers used here (kappa <= 1e2), so the bar holds although the
+device forms Q0 = A R0^{-1} with the explicit inverse of R0 and the oracle
+by forward substitution.  FP32 data: the same bar against the oracle on the
+promoted data (the FP32 / BF16 sketch only changes the preconditioner).
+At the full 4,194,304 x 64 size (oracle too slow) the least-squares
+optimality A^T (B - A X) = 0 is checked instead, in FP64.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import bf16_dev, rel, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ms():
+    import paper_2508_14209_amd as ms
+    return ms
+
+
+def _problem(d, n, nrhs, kappa, seed, dtype=np.float64, noise=1e-2):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((d, n)) * np.logspace(0, -np.log10(kappa), n)
+    B = A @ rng.standard_normal((n, nrhs)) + noise * rng.standard_normal((d, nrhs))
+    k, k2 = 2 * n * n, 2 * n
+    h = synth.bucket_map(d, k, seed=seed)
+    s = synth.signs(d, seed=seed)
+    G = synth.gaussian_sketch(k2, k, seed=seed, dtype="f64")
+    return (np.asfortranarray(A, dtype=dtype), np.asfortranarray(B, dtype=dtype), h, s, G, k)
+
+
+CASES = [(1000, 3, 1, 1.0), (12345, 8, 2, 1e2), (65537, 16, 3, 10.0), (100000, 33, 1, 1e2),
+         (200003, 64, 1, 1e2), (5000, 60, 16, 10.0)]
+
+
+@pytest.mark.parametrize("d,n,nrhs,kappa", CASES)
+def test_rand_cholqr_fp64_parity(ms, orc, d, n, nrhs, kappa):
+    print("rand_cholqr f64 d=%d n=%d nrhs=%d kappa=%g" % (d, n, nrhs, kappa), flush=True)
+    A, B, h, s, G, k = _problem(d, n, nrhs, kappa, seed=d + n)
+    R = ms.empty_colmajor(n, n, torch.float64, "cuda")
+    X, _, ws = ms.rand_cholqr_lstsq(to_dev(A), to_dev(B), to_dev(h), to_dev(s), to_dev(G), k, R=R)
+    ms.check_status(ws)
+    Xr, Rr, _ = orc.rand_cholqr_lstsq(A, B, h, s, G, k)
+    assert rel(to_host(X), Xr) <= 1e-12
+    # R is unique up to the signs of its rows: compare R^T R
+    Rg = to_host(R)
+    assert np.all(np.tril(Rg, -1) == 0.0)
+    assert rel(Rg.T @ Rg, Rr.T @ Rr) <= 1e-12
+
+
+@pytest.mark.parametrize("gd", ["f32", "bf16"])
+def test_rand_cholqr_fp32_parity(ms, orc, gd):
+    d, n, nrhs = 70001, 16, 2
+    A, B, h, s, G, k = _problem(d, n, nrhs, 1e2, seed=7, dtype=np.float32)
+    Gq = np.asarray(G, dtype=np.float32)
+    Gdev = bf16_dev(Gq) if gd == "bf16" else to_dev(Gq)
+    X, _, ws = ms.rand_cholqr_lstsq(to_dev(A), to_dev(B), to_dev(h), to_dev(s), Gdev, k)
+    ms.check_status(ws)
+    Gvals = to_host(Gdev.float()).astype(np.float64)
+    Xr, _, _ = orc.rand_cholqr_lstsq(A, B, h, s, Gvals, k, y_bf16=(gd == "bf16"))
+    assert rel(to_host(X), Xr) <= 1e-12
+
+
+def test_rand_cholqr_does_not_depend_on_the_sketch(ms):
+    d, n = 50000, 16
+    A, B, _, _, _, k = _problem(d, n, 2, 1e2, seed=3)
+    xs = []
+    for seed in (10, 11):
+        h = synth.bucket_map(d, k, seed=seed)
+        s = synth.signs(d, seed=seed)
+        G = synth.gaussian_sketch(2 * n, k, seed=seed, dtype="f64")
+        X, _, ws = ms.rand_cholqr_lstsq(to_dev(A), to_dev(B), to_dev(h), to_dev(s), to_dev(G), k)
+        ms.check_status(ws)
+        xs.append(to_host(X))
+    assert rel(xs[0], xs[1]) <= 1e-12
+
+
+def test_rand_cholqr_full_size_optimality(ms):
+    # the 4,194,304 x 64 FP64 workload: A^T (B - A X) = 0 up to rounding
+    d, n, k, k2 = 4194304, 64, 8192, 128
+    g = torch.Generator(device="cuda")
+    g.manual_seed(14209)
+    A = torch.randn((n, d), generator=g, device="cuda", dtype=torch.float64).t()
+    xs = torch.randn((n, 1), generator=g, device="cuda", dtype=torch.float64)
+    B = ms.empty_colmajor(d, 1, torch.float64, "cuda")
+    B.copy_(A @ xs + 1e-2 * torch.randn((d, 1), generator=g, device="cuda", dtype=torch.float64))
+    h = torch.randint(0, k, (d,), generator=g, device="cuda", dtype=torch.int32)
+    s = (torch.randint(0, 2, (d,), generator=g, device="cuda", dtype=torch.int8) * 2 - 1)
+    G = ms.empty_colmajor(k2, k, torch.float64, "cuda")
+    G.copy_(torch.randn((k, k2), generator=g, device="cuda", dtype=torch.float64).t() / np.sqrt(k2))
+    X, _, ws = ms.rand_cholqr_lstsq(A, B, h, s, G, k)
+    ms.check_status(ws)
+    r = B - A @ X
+    grad = (A.t() @ r).norm().item()
+    scale = (A.norm() * r.norm()).item()
+    assert grad / scale <= 1e-13, grad / scale
+
+
+def test_rand_cholqr_errors(ms):
+    A, B, h, s, G, k = _problem(3000, 8, 1, 1.0, seed=5)
+    Ad = to_dev(A)
+    Ad[:, 3] = 0.0  # rank deficient: R0 (or the Cholesky factor) breaks down
+    X, _, ws = ms.rand_cholqr_lstsq(Ad, to_dev(B), to_dev(h), to_dev(s), to_dev(G), k)
+    with pytest.raises(ms.MsketchError) as e:
+        ms.check_status(ws)
+    assert e.value.code == ms.MS_ERR_SINGULAR
+    assert np.all(np.isnan(to_host(X)))
+    hb = h.copy()
+    hb[11] = k
+    X, _, ws = ms.rand_cholqr_lstsq(to_dev(A), to_dev(B), to_dev(hb), to_dev(s), to_dev(G), k)
+    with pytest.raises(ms.MsketchError) as e:
+        ms.check_status(ws)
+    assert e.value.code == ms.MS_ERR_RANGE
+    A65, B65, h65, s65, G65, k65 = _problem(2000, 65, 1, 1.0, seed=6)
+    with pytest.raises(ms.MsketchError) as e:
+        ms.rand_cholqr_lstsq(to_dev(A65), to_dev(B65), to_dev(h65), to_dev(s65), to_dev(G65), k65)
+    assert e.value.code == ms.MS_ERR_UNSUPPORTED
