@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--only", default=None,
                     choices=["countsketch", "countsketch_f32_k32768", "countsketch_f32_k131072",
                              "copy", "gaussian_f64", "gaussian_bf16", "batched_mixed",
-                             "solve_fp32", "solve_mixed"],
+                             "solve_fp32", "solve_mixed", "rand_cholqr"],
                     help="profiling runs: launch only the LDS CountSketch of [A | b] (--steps "
                          "times), only a plain device copy of 1 GiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters), or only the Gaussian stage of the "
@@ -255,6 +255,56 @@ def mixed_vs_fp64_leg(ms, torch, np, count, seed, refine, dev, reps=3):
     res.update({"problems": count, "refine_steps": refine, "workload": SERVE_WORKLOAD,
                 "g_dtype_mixed": "bf16", "reps": reps})
     return res
+
+
+def rcq_leg(ms, torch, np, A, B, h, s, G, k, mode, X_ss, reps, A_host=None, B_host=None,
+            h_host=None, s_host=None, G_host=None, cpu=True):
+    """rand_cholQR least squares (Alg. 5) on the headline problem: solves/s
+    and how close it and the sketch-and-solve x come to the least-squares
+    optimum, measured by ||A^T r|| / (||A||_F ||r||) (zero at the optimum;
+    the sketch-and-solve x carries the sketch's distortion).  With cpu, the
+    oracle's rand_cholQR solve of the same arrays is timed once beside it."""
+    X, R, ws = ms.rand_cholqr_lstsq(A, B, h, s, G, k, mode=mode)
+    for _ in range(3):
+        ms.rand_cholqr_lstsq(A, B, h, s, G, k, mode=mode, X=X, ws=ws)
+    ms.check_status(ws)
+    evs = [event_pair(torch) for _ in range(reps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record()
+        ms.rand_cholqr_lstsq(A, B, h, s, G, k, mode=mode, X=X, ws=ws)
+        e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms.check_status(ws)
+    lat = np.array([a.elapsed_time(b) for a, b in evs])
+    anorm = float(torch.linalg.norm(A))
+
+    def optimality(Xv):
+        r = B - A @ Xv
+        return float(torch.linalg.norm(A.t() @ r) / (anorm * torch.linalg.norm(r)))
+
+    out = {"solves_per_s": reps / wall, "ms_per_solve": 1e3 * wall / reps,
+           "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                          "p99": float(np.percentile(lat, 99))},
+           "optimality_rand_cholqr": optimality(X),
+           "optimality_sketch_and_solve": optimality(X_ss),
+           "gram_pass_flops": 2 * A.shape[0] * A.shape[1] * (A.shape[1] + 1)
+                              + 2 * A.shape[0] * A.shape[1] * B.shape[1],
+           "gram_pass_bytes": A.shape[0] * (A.shape[1] + B.shape[1]) * A.element_size()}
+    if cpu and A_host is not None:
+        import oracle
+        c0 = time.perf_counter()
+        Xo, _, _ = oracle.rand_cholqr_lstsq(A_host, B_host, h_host, s_host, G_host, k)
+        tc = time.perf_counter() - c0
+        Xh = X.cpu().numpy()
+        out["cpu_oracle"] = {"value": 1.0 / tc, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                             "sample": "1 full rand_cholQR solve of the same problem (%.1f s)"
+                                       % tc,
+                             "rel_err_gpu_vs_oracle":
+                                 float(np.linalg.norm(Xh - Xo) / np.linalg.norm(Xo))}
+    return out
 
 
 def other_configs_leg(ms, torch, np, seed, dev, reps=10, only=None):
@@ -456,6 +506,16 @@ def main():
     ws = ms.workspace(ms.workspace_size("lstsq", d=d, n=n, nrhs=nrhs, k=k, k2=k2,
                                         mode=args.mode), dev)
     torch.cuda.synchronize()
+    if args.only == "rand_cholqr":
+        # rand_cholQR least squares of the headline problem alone
+        Xr, _, rws = ms.rand_cholqr_lstsq(Ad, Bd, hd, sd, Gd, k, mode=args.mode)
+        for _ in range(args.steps):
+            ms.rand_cholqr_lstsq(Ad, Bd, hd, sd, Gd, k, mode=args.mode, X=Xr, ws=rws)
+        ms.check_status(rws)
+        print(json.dumps({"only": args.only, "kernel": "k_rcq_gram", "launches": args.steps + 1,
+                          "flops_per_launch": 2 * d * n * (n + 1) + 2 * d * n * nrhs,
+                          "bytes_per_launch": d * nc * 8}))
+        return
     if args.only == "countsketch":
         # the step's CountSketch kernel alone: codes packed once, then
         # args.steps launches of the LDS kernel over [A | b]
@@ -526,6 +586,13 @@ def main():
     gs_ms = time_calls(lambda: ms.gaussian_apply(Gd, Y, Z=Z, ws=gws), reps)
     gs_flops = 2.0 * k2 * k * nc
 
+    # ---- rand_cholQR least squares on the same problem (its own leg)
+    try:
+        rcq = rcq_leg(ms, torch, np, Ad, Bd, hd, sd, Gd, k, args.mode, X, max(10, args.steps // 5),
+                      A, B, h, s, G, cpu=args.cpu_seconds > 0)
+    except Exception as e:  # reported in the line, not hidden
+        rcq = {"error": repr(e)}
+
     # ---- CPU baseline: the oracle on this host, same arrays
     cpu = None
     if args.cpu_seconds > 0:
@@ -570,6 +637,7 @@ def main():
         "roofline": {"bound": "hbm", "achieved": cs_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": cs_gbps / HBM_PEAK_GBPS, "traffic": measured_traffic()},
         "cpu_baseline": cpu,
+        "rand_cholqr": rcq,
     }
     # beyond the headline: the serving loop and the batched mixed-precision
     # solver against the plain FP64 one (each leg reports its own error)

@@ -396,4 +396,42 @@ hipError_t launch_batch_apply_solve(int count, const ms_problem *P, const BatchE
                                     const unsigned char *gvarea, const unsigned char *farea,
                                     int *pstatus, int *status, hipStream_t st);
 
+// ------------------------------------------------------------------ wave helpers
+// Wave-wide sum with DPP: quad swaps, half-row and row mirrors give every
+// lane its 16-lane row sum, two row broadcasts (lane 15 into rows 1 and 3,
+// lane 31 into rows 2 and 3) leave the total in lane 63, and one lane read
+// (a pair, for the two halves of the double) hands it to every lane.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long u = __double_as_longlong(v);
+  int lo = (int)(u & 0xffffffffLL), hi = (int)(u >> 32);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(u & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(u >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+// DPP broadcast into the rows selected by ROWMASK; other rows get 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_bcast(double v) {
+  const long long u = __double_as_longlong(v);
+  int lo = (int)(u & 0xffffffffLL), hi = (int)(u >> 32);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, ROWMASK, 0xf, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, ROWMASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_allsum(double v) {
+  v += dpp_move<0xb1>(v);        // quad_perm [1,0,3,2]
+  v += dpp_move<0x4e>(v);        // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);       // row_half_mirror
+  v += dpp_move<0x140>(v);       // row_mirror: every lane holds its 16-lane row sum
+  v += dpp_bcast<0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3: rows (0+1), (2+3)
+  v += dpp_bcast<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3: lane 63 holds the total
+  return read_lane(v, 63);
+}
+
 }  // namespace ms

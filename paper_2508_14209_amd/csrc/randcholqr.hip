@@ -32,239 +32,320 @@ __device__ __forceinline__ v4d mma64(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// R0^{-1} (64 x 64, column-major, zero below the diagonal and outside n x n)
-// by back substitution, one thread per column: R0 Rinv = I.
+// R0^{-1} (64 x 64, row-major, zero outside the leading n x n block) by one
+// wave: lane j solves R0 x = e_j by back substitution, x in registers, step i
+// (from 63 down) x_i = (delta_ij - sum_{l > i} R0[i][l] x_l) / R0[i][i].  Row i
+// of R0 is read from LDS at one address by every lane (a broadcast).  Entries
+// x_l with l > j stay zero, so every lane runs the same 64 steps.
 __global__ __launch_bounds__(64) void k_rcq_trinv(int n, const double *__restrict__ R0, int ldr0,
                                                   double *__restrict__ Rinv, int *status) {
-  __shared__ double r0[kRcqMaxN * (kRcqMaxN + 1)];
-  __shared__ double ri[kRcqMaxN * (kRcqMaxN + 1)];
   constexpr int L = kRcqMaxN + 1;
-  for (int t = threadIdx.x; t < kRcqMaxN * kRcqMaxN; t += blockDim.x) {
-    const int i = t % kRcqMaxN, j = t / kRcqMaxN;
-    r0[i + j * L] = (i < n && j < n && i <= j) ? R0[i + (int64_t)j * ldr0] : 0.0;
-    ri[i + j * L] = 0.0;
-  }
+  __shared__ double r0[kRcqMaxN * L];  // row-major: r0[i L + l] = R0[i][l]
+  __shared__ double dinv[kRcqMaxN];
+  const int lane = threadIdx.x;
+  // coalesced column reads (lane = row i), transposed into LDS
+  for (int l = 0; l < kRcqMaxN; ++l)
+    r0[lane * L + l] =
+        (lane < n && l < n && lane <= l) ? R0[lane + (int64_t)l * ldr0] : 0.0;
+  const double dii = lane < n ? R0[lane + (int64_t)lane * ldr0] : 1.0;
+  const bool bad = lane < n && (!(dii != 0.0) || !isfinite(dii));
+  dinv[lane] = lane < n ? 1.0 / dii : 0.0;
+  if (__any(bad) && lane == 0) record_status(status, MS_ERR_SINGULAR);
   __syncthreads();
-  const int j = threadIdx.x;
-  bool bad = false;
-  if (j < n) {
-    const double djj = r0[j + j * L];
-    bad = !(djj != 0.0) || !isfinite(djj);
-    ri[j + j * L] = 1.0 / djj;
-    for (int i = j - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int l = i + 1; l <= j; ++l) acc += r0[i + l * L] * ri[l + j * L];
-      ri[i + j * L] = -acc / r0[i + i * L];
-    }
+  double x[kRcqMaxN];
+#pragma unroll
+  for (int i = kRcqMaxN - 1; i >= 0; --i) {
+    // four partial sums over l = i + 1 + 4 m + u, added in a fixed order
+    double acc[4] = {i == lane ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int l = i + 1; l < kRcqMaxN; ++l) acc[(l - i - 1) & 3] -= r0[i * L + l] * x[l];
+    x[i] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) * dinv[i];
   }
-  if (bad) record_status(status, MS_ERR_SINGULAR);
-  __syncthreads();
-  for (int t = threadIdx.x; t < kRcqMaxN * kRcqMaxN; t += blockDim.x) {
-    const int i = t % kRcqMaxN, jj = t / kRcqMaxN;
-    Rinv[t] = ri[i + jj * L];
-  }
+#pragma unroll
+  for (int i = 0; i < kRcqMaxN; ++i) Rinv[i * kRcqMaxN + lane] = x[i];
 }
 
-// The fused pass.  NTI = column tiles of Q0 (n <= 16 NTI).  Partial of the
-// workgroup: part[blockIdx.x] (64 x 80, row-major) holds the upper tiles of
-// Q0^T [Q0 | B] over its blocks (tile (it, ct) for it <= ct; the lower
-// off-diagonal tiles are not written).
-template <typename TA, int NTI>
-__global__ __launch_bounds__(256) void k_rcq_gram(int64_t d, int n, int nrhs,
-                                                  const TA *__restrict__ A, int64_t lda,
-                                                  const TA *__restrict__ B, int64_t ldb,
-                                                  const double *__restrict__ Rinv,
-                                                  double *__restrict__ part) {
-  __shared__ double rinv[kRcqMaxN * kLdr];
-  __shared__ double qb[kRows * kLdq];
+// The fused pass.  NTI = column tiles of Q0 (n <= 16 NTI).  The columns of
+// B that do not fit in Q0's last tile (nx = n + nrhs - 16 NTI of them) are
+// handled by EXTRA: 0 (none), 1 (one more 16-column MFMA tile), 2 (nx = 1:
+// vector FMAs, since a tile with one column in use would cost 4 NTI
+// matrix-core instructions per slab).
+//
+// Each wave takes slabs of 16 rows of A (grid-stride over all waves).  For a
+// slab it forms the 16 x 16 NTI block of Q0 = A R0^{-1} on the f64 matrix
+// cores: the A operand of k-step ks is A[row li][4 ks + lk] (lane li + 16 lk),
+// the B operand R0^{-1}[4 ks + lk][16 jt + li] from LDS, and the result
+// register r of column tile jt is Q0[lk + 4 r][16 jt + li].  That is exactly
+// the operand layout of the Gram products over the slab's 16 rows
+// (k = row): A operand Q0[4 r + lk][16 it + li], B operand
+// V[4 r + lk][16 ct + li] with V = [Q0 | B], so the tiles (it, ct), it <= ct,
+// of V^T V accumulate from registers with no data exchange between lanes.
+// B's columns enter V's tiles from the lanes whose column is >= n (R0^{-1}
+// is zero there, so those lanes' Q0 values are zero).  After its last slab
+// each wave holds the sum over its slabs; the waves are added in wave order
+// through LDS and the workgroup's partial (row-major 64 x 80: entry (i, j) at
+// i 80 + j; upper tiles only) goes to part[blockIdx.x].  Eight waves (two per
+// SIMD) keep the matrix cores busy while a wave waits for its slab.
+constexpr int kGramWaves = 8;
+template <typename TA, int NTI, int EXTRA>
+__global__ __launch_bounds__(64 * kGramWaves) void k_rcq_gram(int64_t d, int n, int nrhs,
+                                                              const TA *__restrict__ A,
+                                                              int64_t lda,
+                                                              const TA *__restrict__ B,
+                                                              int64_t ldb,
+                                                              const double *__restrict__ Rinv,
+                                                              double *__restrict__ part) {
+  constexpr int NCT = NTI + (EXTRA == 1);
+  constexpr int NT = NTI * NCT - NTI * (NTI - 1) / 2;  // tiles (it, ct), it <= ct
+  constexpr int NZ = EXTRA == 2 ? 1 : 0;                // vector columns of B
+  constexpr int NB = EXTRA == 1 ? 2 : 1;                // B fragments in MFMA tiles
+  __shared__ double rinv[kRcqMaxN * kLdr];             // rinv[k kLdr + j] = R0^{-1}[k][j]
+  __shared__ double wsum[kRcqMaxN * kRcqMaxCols];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  const int nc = n + nrhs;
-  const int nct = (nc + 15) / 16;
-  for (int t = tid; t < kRcqMaxN * kRcqMaxN; t += 256) {
-    const int kk = t % kRcqMaxN, j = t / kRcqMaxN;
-    rinv[kk * kLdr + j] = Rinv[t];
-  }
-  for (int t = tid; t < kRows * kLdq; t += 256) qb[t] = 0.0;
+  for (int t = tid; t < kRcqMaxN * kRcqMaxN; t += 64 * kGramWaves)
+    rinv[(t >> 6) * kLdr + (t & 63)] = Rinv[t];
   __syncthreads();
 
-  // this wave's tiles of Q0^T [Q0 | B]: (it, ct), it < NTI, it <= ct < nct,
-  // numbered it-major; tile u goes to wave u % 4
-  constexpr int kMaxTiles = 4;  // ceil(15 / 4): NTI <= 4 and nct <= 5
-  int tit[kMaxTiles], tct[kMaxTiles];
-  int ntile = 0;
-  {
-    int u = 0;
-    for (int it = 0; it < NTI; ++it)
-      for (int ct = it; ct < nct; ++ct, ++u)
-        if (u % 4 == wave && ntile < kMaxTiles) {
-          tit[ntile] = it;
-          tct[ntile] = ct;
-          ++ntile;
-        }
-  }
-  v4d w[kMaxTiles];
+  v4d w[NT];
 #pragma unroll
-  for (int u = 0; u < kMaxTiles; ++u) w[u] = v4d{0.0, 0.0, 0.0, 0.0};
+  for (int u = 0; u < NT; ++u) w[u] = v4d{0.0, 0.0, 0.0, 0.0};
+  double z[NTI][NZ > 0 ? NZ : 1];
+#pragma unroll
+  for (int it = 0; it < NTI; ++it)
+#pragma unroll
+    for (int c = 0; c < (NZ > 0 ? NZ : 1); ++c) z[it][c] = 0.0;
+  const int zc0 = 16 * NTI - n;                  // first B column outside Q0's tiles
+  const int nx = EXTRA == 2 ? nrhs - zc0 : 0;    // vector columns in use
 
-  const int64_t nblk = (d + kRows - 1) / kRows;
-  // A fragments of a block for this wave: rows 16 wave + li, k = 4 ks + lk
-  auto load_a = [&](int64_t blk, double(&fa)[4 * NTI]) {
-    const int64_t row = blk * kRows + 16 * wave + li;
+  const int64_t nslab = (d + 15) >> 4;
+  const int64_t stride = (int64_t)gridDim.x * kGramWaves;
+  // per-lane bases; the per-k-step offsets 4 ks lda are wave-uniform
+  const TA *const Al = A + li + (int64_t)lk * lda;
+  const int64_t lda4 = 4 * lda;
+  for (int64_t sl = (int64_t)blockIdx.x * kGramWaves + wave; sl < nslab; sl += stride) {
+    const int64_t r0 = sl * 16;
+    const bool rin = r0 + li < d;
+    const TA *const As = Al + r0;
+    double a[4 * NTI];
 #pragma unroll
-    for (int ks = 0; ks < 4 * NTI; ++ks) {
-      const int kk = 4 * ks + lk;
-      fa[ks] = (row < d && kk < n) ? (double)gload(A + row + (int64_t)kk * lda) : 0.0;
-    }
-  };
-  double a[4 * NTI];
-  int64_t blk = blockIdx.x;
-  if (blk < nblk) load_a(blk, a);
-  for (; blk < nblk; blk += gridDim.x) {
-    const int64_t nb = blk + gridDim.x;
-    double an[4 * NTI];
-    if (nb < nblk) load_a(nb, an);
-    // Q0 tile of this wave: rows 16 wave .. + 15, all columns; R0^{-1} is
-    // upper triangular, so column tile jt needs k < 16 (jt + 1) only
+    for (int ks = 0; ks < 4 * NTI; ++ks)
+      a[ks] = (rin && 4 * ks + lk < n) ? (double)gload(As + ks * lda4) : 0.0;
+    // fb[e][r] = B[r0 + lk + 4 r][c], c = 16 (NTI - 1 + e) + li - n (zero
+    // outside 0 <= c < nrhs); zb[c][r] = B[r0 + lk + 4 r][zc0 + c]
+    double fb[NB][4];
 #pragma unroll
-    for (int jt = 0; jt < NTI; ++jt) {
-      v4d q = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int e = 0; e < NB; ++e) {
+      const int c = 16 * (NTI - 1 + e) + li - n;
 #pragma unroll
-      for (int ks = 0; ks < 4 * (jt + 1); ++ks)
-        q = mma64(a[ks], rinv[(4 * ks + lk) * kLdr + 16 * jt + li], q);
-      const int col = 16 * jt + li;
-      if (col < n)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) qb[(16 * wave + lk + 4 * r) * kLdq + col] = q[r];
-    }
-    for (int t = tid; t < kRows * nrhs; t += 256) {
-      const int row = t % kRows, c = t / kRows;
-      const int64_t grow = blk * kRows + row;
-      qb[row * kLdq + n + c] = grow < d ? (double)gload(B + grow + (int64_t)c * ldb) : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < kMaxTiles; ++u)
-      if (u < ntile) {
-        const int ci = 16 * tit[u] + li, cc = 16 * tct[u] + li;
-#pragma unroll
-        for (int ks = 0; ks < kRows / 4; ++ks) {
-          const int row = 4 * ks + lk;
-          w[u] = mma64(qb[row * kLdq + ci], qb[row * kLdq + cc], w[u]);
-        }
+      for (int r = 0; r < 4; ++r) {
+        const int64_t rw = r0 + lk + 4 * r;
+        fb[e][r] = (c >= 0 && c < nrhs && rw < d) ? (double)gload(B + rw + (int64_t)c * ldb) : 0.0;
       }
-    __syncthreads();
-    if (nb < nblk)
+    }
+    double zb[NZ > 0 ? NZ : 1][4];
 #pragma unroll
-      for (int ks = 0; ks < 4 * NTI; ++ks) a[ks] = an[ks];
+    for (int c = 0; c < NZ; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t rw = r0 + lk + 4 * r;
+        zb[c][r] = (c < nx && rw < d) ? (double)gload(B + rw + (int64_t)(zc0 + c) * ldb) : 0.0;
+      }
+    // R0^{-1} is re-read from LDS in every slab: the empty asm keeps the
+    // compiler from hoisting its 4 NTI (NTI + 1) / 2 fragments into registers
+    // for the whole loop (which would leave too few for two waves per SIMD)
+    int roff = lk * kLdr + li;
+    asm volatile("" : "+v"(roff));
+    v4d q[NCT];
+#pragma unroll
+    for (int jt = 0; jt < NCT; ++jt) q[jt] = v4d{0.0, 0.0, 0.0, 0.0};
+    // Q0 tile jt: R0^{-1} is upper triangular, so k-step ks enters the tiles
+    // jt >= ks / 4 only (k-step outer: each A fragment is used, then dead)
+#pragma unroll
+    for (int ks = 0; ks < 4 * NTI; ++ks)
+#pragma unroll
+      for (int jt = ks / 4; jt < NTI; ++jt)
+        q[jt] = mma64(a[ks], rinv[roff + 4 * ks * kLdr + 16 * jt], q[jt]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      q[NTI - 1][r] += fb[0][r];
+      if (EXTRA == 1) q[NCT - 1][r] = fb[NB - 1][r];
+    }
+    int u = 0;
+#pragma unroll
+    for (int it = 0; it < NTI; ++it)
+#pragma unroll
+      for (int ct = it; ct < NCT; ++ct, ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w[u] = mma64(q[it][r], q[ct][r], w[u]);
+    // vector columns: z[it][c] += sum_r Q0[lk + 4 r][16 it + li] B[lk + 4 r][zc0 + c]
+#pragma unroll
+    for (int c = 0; c < NZ; ++c)
+      if (c < nx)
+#pragma unroll
+        for (int it = 0; it < NTI; ++it)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) z[it][c] += q[it][r] * zb[c][r];
   }
+  // vector columns: sum over the four lane rows lk (xor 16, then xor 32)
+#pragma unroll
+  for (int c = 0; c < NZ; ++c)
+#pragma unroll
+    for (int it = 0; it < NTI; ++it) {
+      z[it][c] += __shfl_xor(z[it][c], 16);
+      z[it][c] += __shfl_xor(z[it][c], 32);
+    }
+  // the waves' sums, added in wave order
   double *P = part + (int64_t)blockIdx.x * kPart;
+  for (int wv = 0; wv < kGramWaves; ++wv) {
+    if (wave == wv) {
+      const bool first = wv == 0, last = wv == kGramWaves - 1;
+      int u = 0;
 #pragma unroll
-  for (int u = 0; u < kMaxTiles; ++u)
-    if (u < ntile)
+      for (int it = 0; it < NTI; ++it)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        P[(16 * tit[u] + lk + 4 * r) * kRcqMaxCols + 16 * tct[u] + li] = w[u][r];
+        for (int ct = it; ct < NCT; ++ct, ++u)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int idx = (16 * it + lk + 4 * r) * kRcqMaxCols + 16 * ct + li;
+            const double v = first ? w[u][r] : wsum[idx] + w[u][r];
+            if (last)
+              P[idx] = v;
+            else
+              wsum[idx] = v;
+          }
+#pragma unroll
+      for (int c = 0; c < NZ; ++c)
+        if (c < nx && lk == 0)
+#pragma unroll
+          for (int it = 0; it < NTI; ++it) {
+            const int idx = (16 * it + li) * kRcqMaxCols + 16 * NTI + c;
+            const double v = first ? z[it][c] : wsum[idx] + z[it][c];
+            if (last)
+              P[idx] = v;
+            else
+              wsum[idx] = v;
+          }
+    }
+    if (wv < kGramWaves - 1) __syncthreads();
+  }
 }
 
 // W = the sum of the nparts partials, element by element: wave q of a
-// workgroup sums partials q, q + 4, ... of 64 consecutive elements, and the
-// four sums are added in wave order (a fixed association).
+// workgroup sums partials q, q + 4, ... of 64 consecutive elements in four
+// interleaved running sums (fixed association), and the four waves' sums are
+// added in wave order.
 __global__ __launch_bounds__(256) void k_rcq_reduce(int nparts, const double *__restrict__ part,
                                                     double *__restrict__ W) {
   __shared__ double sh[4][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int e = blockIdx.x * 64 + lane;
-  double s = 0.0;
-  for (int p = wave; p < nparts; p += 4) s += part[(int64_t)p * kPart + e];
-  sh[wave][lane] = s;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  int p = wave;
+  for (; p + 12 < nparts; p += 16)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s[u] += part[(int64_t)(p + 4 * u) * kPart + e];
+  for (int u = 0; p < nparts; p += 4, ++u) s[u] += part[(int64_t)p * kPart + e];
+  sh[wave][lane] = (s[0] + s[1]) + (s[2] + s[3]);
   __syncthreads();
   if (wave == 0) W[e] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
 }
 
-// One workgroup: R1 = chol(G) (G = Q0^T Q0, upper part of W), R = R1 R0,
-// y = R1^{-T} z (z = Q0^T B, columns n .. n + nrhs of W), x = R^{-1} y.
-__global__ __launch_bounds__(256) void k_rcq_solve(int n, int nrhs, const double *__restrict__ W,
-                                                   const double *__restrict__ R0, int ldr0,
-                                                   double *__restrict__ X, int64_t ldx,
-                                                   double *__restrict__ Rout, int64_t ldr,
-                                                   int *status) {
-  constexpr int L = kRcqMaxN + 1;
-  __shared__ double g[kRcqMaxN * L];   // g[i + j L]: R1 in the upper triangle
-  __shared__ double r0[kRcqMaxN * L];
-  __shared__ double rr[kRcqMaxN * L];  // R = R1 R0
-  __shared__ double z[kRcqMaxN * 16];
-  __shared__ int bad;
-  const int tid = threadIdx.x;
-  if (tid == 0) bad = 0;
-  for (int t = tid; t < n * n; t += blockDim.x) {
-    const int i = t % n, j = t / n;
-    // the upper triangle of Q0^T Q0 (row i, column j of the row-major W)
-    g[i + j * L] = i <= j ? W[i * kRcqMaxCols + j] : 0.0;
-    r0[i + j * L] = i <= j ? R0[i + (int64_t)j * ldr0] : 0.0;
-  }
-  for (int t = tid; t < n * nrhs; t += blockDim.x) {
-    const int i = t % n, c = t / n;
-    z[i + c * kRcqMaxN] = W[i * kRcqMaxCols + n + c];
-  }
-  __syncthreads();
-  // right-looking Cholesky, one barrier per column: step j updates the
-  // trailing rows with the undivided row j, and row j is scaled at step j + 1
-  for (int j = 0; j < n; ++j) {
-    const double djj = g[j + j * L];
-    if (!(djj > 0.0) || !isfinite(djj)) {
-      if (tid == 0) bad = 1;
+// One wave: R1 = chol(G) (G = Q0^T Q0, the upper part of W), y = R1^{-T} z
+// (z = Q0^T B, columns n .. n + nrhs of W), R = R1 R0 and x = R^{-1} y.
+// Lane l holds column l of the working matrix in registers (g[i] = entry
+// (i, l)); matrices of order n < 64 are padded to 64 with the identity, so
+// every lane runs the same fully unrolled steps.
+__global__ __launch_bounds__(64) void k_rcq_solve(int n, int nrhs, const double *__restrict__ W,
+                                                  const double *__restrict__ R0, int ldr0,
+                                                  double *__restrict__ X, int64_t ldx,
+                                                  double *__restrict__ Rout, int64_t ldr,
+                                                  int *status) {
+  constexpr int N = kRcqMaxN, L = kRcqMaxN + 1;
+  __shared__ double r1[N * L];   // R1, row-major: r1[i L + l]
+  __shared__ double rm[N * L];   // R0 staging, then R column-major: rm[i + j L]
+  __shared__ double zs[kRcqMaxRhs * N];
+  const int lane = threadIdx.x;
+  double g[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    g[i] = lane < n ? (i <= lane ? W[i * kRcqMaxCols + lane] : 0.0) : (i == lane ? 1.0 : 0.0);
+  for (int c = 0; c < nrhs; ++c) zs[c * N + lane] = lane < n ? W[lane * kRcqMaxCols + n + c] : 0.0;
+  // R0 (padded with the identity), staged column by column (lane = row)
+  for (int j = 0; j < N; ++j)
+    rm[lane + j * L] = (lane < n && j < n) ? (lane <= j ? R0[lane + (int64_t)j * ldr0] : 0.0)
+                                           : (lane == j ? 1.0 : 0.0);
+
+  // right-looking Cholesky: at step j lane l forms R1[j][l] (l >= j), row j
+  // goes to LDS, and every lane updates its column with it
+  bool bad = false;
+  double mydiag = 1.0;
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const double djj = read_lane(g[j], j);
+    if (j < n && (!(djj > 0.0) || !isfinite(djj))) {
+      bad = true;
       break;
     }
-    const double inv = 1.0 / djj;
-    const int m = n - 1 - j;  // trailing order
-    for (int t = tid; t < m * m; t += blockDim.x) {
-      const int i = j + 1 + t % m, c = j + 1 + t / m;
-      if (i <= c) g[i + c * L] -= g[j + i * L] * g[j + c * L] * inv;
-    }
-    __syncthreads();
     const double rjj = sqrt(djj);
-    for (int c = j + tid; c < n; c += blockDim.x) g[j + c * L] = c == j ? rjj : g[j + c * L] / rjj;
-    __syncthreads();
+    const double rl = lane > j ? g[j] / rjj : (lane == j ? rjj : 0.0);
+    g[j] = rl;
+    if (lane == j) mydiag = rjj;
+    r1[j * L + lane] = rl;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+    for (int i = j + 1; i < N; ++i) g[i] -= r1[j * L + i] * rl;
   }
   if (bad) {
-    for (int t = tid; t < n * nrhs; t += blockDim.x)
-      X[t % n + (int64_t)(t / n) * ldx] = __longlong_as_double(0x7ff8000000000000LL);
-    if (tid == 0) record_status(status, MS_ERR_SINGULAR);
+    for (int c = 0; c < nrhs; ++c)
+      if (lane < n) X[lane + (int64_t)c * ldx] = __longlong_as_double(0x7ff8000000000000LL);
+    if (lane == 0) record_status(status, MS_ERR_SINGULAR);
     return;
   }
-  // R = R1 R0
-  for (int t = tid; t < n * n; t += blockDim.x) {
-    const int i = t % n, j = t / n;
-    double acc = 0.0;
-    if (i <= j)
-      for (int q = i; q <= j; ++q) acc += g[i + q * L] * r0[q + j * L];
-    rr[i + j * L] = acc;
-    if (Rout) Rout[i + (int64_t)j * ldr] = acc;
+  // R1^T y = z, column oriented: y_i = z_i / R1[i][i], then lanes t > i
+  // subtract R1[i][t] y_i (lane t's g[i])
+  for (int c = 0; c < nrhs; ++c) {
+    double y = zs[c * N + lane];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const double yi = read_lane(y, i) / read_lane(mydiag, i);
+      y = lane == i ? yi : (lane > i ? y - g[i] * yi : y);
+    }
+    zs[c * N + lane] = y;
+  }
+  // R = R1 R0, column lane in place of R0's: R[i][l] = sum_{q >= i} R1[i][q] R0[q][l]
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < N; ++i) g[i] = rm[i + lane * L];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    double acc[2] = {0.0, 0.0};
+#pragma unroll
+    for (int q = i; q < N; ++q) acc[(q - i) & 1] += r1[i * L + q] * g[q];
+    g[i] = acc[0] + acc[1];
+  }
+  double rdiag = 1.0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (lane == i) rdiag = g[i];
+    rm[i + lane * L] = g[i];
   }
   __syncthreads();
-  // per right-hand side, one wave: R1^T y = z (forward), then R x = y
-  const int lane = tid & 63, wave = tid >> 6;
-  for (int c = wave; c < nrhs; c += 4) {
-    double *y = z + c * kRcqMaxN;
-    for (int i = 0; i < n; ++i) {
-      const double yi = y[i] / g[i + i * L];
-      if (lane == 0) y[i] = yi;
-      for (int t = i + 1 + lane; t < n; t += 64) y[t] -= g[i + t * L] * yi;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  if (Rout)
+    for (int j = 0; j < n; ++j)
+      if (lane < n) Rout[lane + (int64_t)j * ldr] = rm[lane + j * L];
+  // R x = y, column oriented: x_i = y_i / R[i][i], then lanes t < i subtract
+  // R[t][i] x_i
+  for (int c = 0; c < nrhs; ++c) {
+    double y = zs[c * N + lane];
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i) {
+      const double xi = read_lane(y, i) / read_lane(rdiag, i);
+      y = lane == i ? xi : (lane < i ? y - rm[lane + i * L] * xi : y);
     }
-    for (int i = n - 1; i >= 0; --i) {
-      const double xi = y[i] / rr[i + i * L];
-      if (lane == 0) {
-        y[i] = xi;
-        X[i + (int64_t)c * ldx] = xi;
-      }
-      for (int t = lane; t < i; t += 64) y[t] -= rr[t + i * L] * xi;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    }
+    if (lane < n) X[lane + (int64_t)c * ldx] = y;
   }
 }
 
@@ -284,17 +365,27 @@ hipError_t launch_rcq_gram(int64_t d, int n, int nrhs, const TA *A, int64_t lda,
                            int64_t ldb, const double *Rinv, double *part, int grid,
                            hipStream_t st) {
   if (n < 1 || n > kRcqMaxN || nrhs < 0 || n + nrhs > kRcqMaxCols) return hipErrorInvalidValue;
-  const int nti = (n + 15) / 16;
-#define MS_RCQ_CASE(T_)                                                                      \
-  case T_:                                                                                   \
-    hipLaunchKernelGGL((k_rcq_gram<TA, T_>), dim3(grid), dim3(256), 0, st, d, n, nrhs, A, lda, \
-                       B, ldb, Rinv, part);                                                  \
+  const int nti = (n + 15) / 16, nx = n + nrhs - 16 * nti;
+  const int extra = nx <= 0 ? 0 : (nx == 1 ? 2 : 1);
+  if (nx > 16) return hipErrorInvalidValue;
+#define MS_RCQ_CASE(T_, E_)                                                                  \
+  case 3 * T_ + E_:                                                                          \
+    hipLaunchKernelGGL((k_rcq_gram<TA, T_, E_>), dim3(grid), dim3(64 * kGramWaves), 0, st, d, \
+                       n, nrhs, A, lda, B, ldb, Rinv, part);                                 \
     break;
-  switch (nti) {
-    MS_RCQ_CASE(1)
-    MS_RCQ_CASE(2)
-    MS_RCQ_CASE(3)
-    MS_RCQ_CASE(4)
+  switch (3 * nti + extra) {
+    MS_RCQ_CASE(1, 0)
+    MS_RCQ_CASE(1, 1)
+    MS_RCQ_CASE(1, 2)
+    MS_RCQ_CASE(2, 0)
+    MS_RCQ_CASE(2, 1)
+    MS_RCQ_CASE(2, 2)
+    MS_RCQ_CASE(3, 0)
+    MS_RCQ_CASE(3, 1)
+    MS_RCQ_CASE(3, 2)
+    MS_RCQ_CASE(4, 0)
+    MS_RCQ_CASE(4, 1)
+    MS_RCQ_CASE(4, 2)
   }
 #undef MS_RCQ_CASE
   return hipGetLastError();
@@ -312,7 +403,7 @@ hipError_t launch_rcq_finish(int n, int nrhs, int nparts, const double *part, do
   hipLaunchKernelGGL(k_rcq_reduce, dim3(kPart / 64), dim3(256), 0, st, nparts, part, W);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_rcq_solve, dim3(1), dim3(256), 0, st, n, nrhs, W, R0, ldr0, X, ldx, R,
+  hipLaunchKernelGGL(k_rcq_solve, dim3(1), dim3(64), 0, st, n, nrhs, W, R0, ldr0, X, ldx, R,
                      ldr, status);
   return hipGetLastError();
 }
