@@ -63,7 +63,8 @@ def parse():
     ap.add_argument("--only", default=None,
                     choices=["countsketch", "countsketch_f32_k32768", "countsketch_f32_k131072",
                              "copy", "gaussian_f64", "gaussian_bf16", "batched_mixed",
-                             "solve_fp32", "solve_mixed", "rand_cholqr"],
+                             "solve_fp32", "solve_mixed", "rand_cholqr",
+                             "normal_equations"],
                     help="profiling runs: launch only the LDS CountSketch of [A | b] (--steps "
                          "times), only a plain device copy of 1 GiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters), or only the Gaussian stage of the "
@@ -285,9 +286,34 @@ def rcq_leg(ms, torch, np, A, B, h, s, G, k, mode, X_ss, reps, A_host=None, B_ho
         r = B - A @ Xv
         return float(torch.linalg.norm(A.t() @ r) / (anorm * torch.linalg.norm(r)))
 
+    # the normal equations (Sec. 6.3's comparator) on the same problem
+    Xn, _, nws = ms.normal_equations_lstsq(A, B)
+    for _ in range(3):
+        ms.normal_equations_lstsq(A, B, X=Xn, ws=nws)
+    ms.check_status(nws)
+    nevs = [event_pair(torch) for _ in range(reps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in nevs:
+        e0.record()
+        ms.normal_equations_lstsq(A, B, X=Xn, ws=nws)
+        e1.record()
+    torch.cuda.synchronize()
+    nwall = time.perf_counter() - t0
+    ms.check_status(nws)
+    nlat = np.array([a.elapsed_time(b) for a, b in nevs])
     out = {"solves_per_s": reps / wall, "ms_per_solve": 1e3 * wall / reps,
            "latency_ms": {"p50": float(np.percentile(lat, 50)),
                           "p99": float(np.percentile(lat, 99))},
+           "normal_equations": {"solves_per_s": reps / nwall, "ms_per_solve": 1e3 * nwall / reps,
+                                "latency_ms_p50": float(np.percentile(nlat, 50)),
+                                "optimality": optimality(Xn),
+                                "rel_diff_vs_rand_cholqr":
+                                    float(torch.linalg.norm(Xn - X) / torch.linalg.norm(X))},
+           "optimality_note": "||A^T r|| / (||A||_F ||r||); with b = A x* + 1e-6 N(0,1) the "
+                              "rounding of r alone gives about u ||b|| / ||r|| = 1e-9",
+           "residual_ratio_sketch_and_solve": float(torch.linalg.norm(B - A @ X_ss)
+                                                    / torch.linalg.norm(B - A @ X)),
            "optimality_rand_cholqr": optimality(X),
            "optimality_sketch_and_solve": optimality(X_ss),
            "gram_pass_flops": 2 * A.shape[0] * A.shape[1] * (A.shape[1] + 1)
@@ -506,6 +532,17 @@ def main():
     ws = ms.workspace(ms.workspace_size("lstsq", d=d, n=n, nrhs=nrhs, k=k, k2=k2,
                                         mode=args.mode), dev)
     torch.cuda.synchronize()
+    if args.only == "normal_equations":
+        # the normal equations of the headline problem alone
+        Xn, _, nws = ms.normal_equations_lstsq(Ad, Bd)
+        for _ in range(args.steps):
+            ms.normal_equations_lstsq(Ad, Bd, X=Xn, ws=nws)
+        ms.check_status(nws)
+        print(json.dumps({"only": args.only, "kernel": "k_rcq_gram (plain)",
+                          "launches": args.steps + 1,
+                          "flops_per_launch": d * n * (n + 1) + 2 * d * n * nrhs,
+                          "bytes_per_launch": d * nc * 8}))
+        return
     if args.only == "rand_cholqr":
         # rand_cholQR least squares of the headline problem alone
         Xr, _, rws = ms.rand_cholqr_lstsq(Ad, Bd, hd, sd, Gd, k, mode=args.mode)

@@ -99,6 +99,7 @@ typedef struct {
 #define MS_OP_QR_SOLVE 4
 #define MS_OP_LSTSQ 5
 #define MS_OP_RAND_CHOLQR 6
+#define MS_OP_NORMAL_EQUATIONS 7
 
 /*
  * Bytes of workspace the operation needs (a multiple of 256, at least 256).
@@ -273,6 +274,29 @@ ms_status rand_cholqr_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k,
                             const void *G, int64_t ldg, double *X, int64_t ldx,
                             double *R, int64_t ldr, const ms_opts *opts, void *ws,
                             size_t ws_bytes, void *stream);
+
+/*
+ * Least squares by the normal equations (Sec. 6.3: the deterministic solver
+ * the paper measures sketch-and-solve against): W = [A | B]^T [A | B] in
+ * FP64 in one pass over A and B (FP32 data promoted exactly; a fixed
+ * summation order, so results repeat bit for bit), R = chol(A^T A),
+ * R^T y = A^T B, X = R^{-1} y.  Accurate only while kappa(A) is well below
+ * u^{-1/2} (the Gram matrix squares the condition number; Sec. 6.3).
+ *   d x n A (a_dtype MS_F64 or MS_F32, column-major, lda >= d), d x nrhs B
+ *   (A's dtype, ldb >= d), X n x nrhs FP64 (ldx >= n); R (may be NULL):
+ *   n x n (ldr >= n), receives R (upper triangular, zeros below).
+ *   opts is unused (may be NULL).
+ * Limits: n <= 64, nrhs <= 16 (else MS_ERR_UNSUPPORTED).  Device status:
+ * MS_ERR_SINGULAR (X = NaN) when the Cholesky factorisation breaks down.
+ * ws: ms_workspace_size(MS_OP_NORMAL_EQUATIONS, d, n, nrhs, 0, 0, a_dtype,
+ * 0, NULL) bytes.
+ */
+ms_status normal_equations_lstsq(int64_t d, int64_t n, int64_t nrhs,
+                                 ms_dtype a_dtype, const void *A, int64_t lda,
+                                 const void *B, int64_t ldb, double *X,
+                                 int64_t ldx, double *R, int64_t ldr,
+                                 const ms_opts *opts, void *ws, size_t ws_bytes,
+                                 void *stream);
 
 /*
  * One problem of a batched multisketch sketch-and-solve (all device

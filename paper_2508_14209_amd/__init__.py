@@ -24,7 +24,7 @@ __all__ = [
     "empty_colmajor", "colmajor", "workspace", "workspace_size", "check_status",
     "bucket_plan", "pack_sketch", "countsketch_accumulate", "countsketch_apply",
     "gaussian_apply", "multisketch_apply", "qr_solve", "sketch_lstsq", "rand_cholqr_lstsq",
-    "MsProblem",
+    "normal_equations_lstsq", "MsProblem",
     "batch_workspace_size", "sketch_lstsq_batched", "batch_status", "BatchRunner",
 ]
 
@@ -36,7 +36,8 @@ MS_OK, MS_ERR_ARG, MS_ERR_RANGE, MS_ERR_NOMEM, MS_ERR_SINGULAR, MS_ERR_DEVICE, \
 MS_F64, MS_F32, MS_BF16 = 0, 1, 2
 MODES = {"auto": 0, "atomic": 1, "lds": 2, "sorted": 3}
 OPS = {"bucket_plan": 0, "countsketch": 1, "gaussian": 2, "multisketch": 3,
-       "qr_solve": 4, "lstsq": 5, "rand_cholqr": 6}
+       "qr_solve": 4, "lstsq": 5, "rand_cholqr": 6,
+       "normal_equations": 7}
 MS_SORTED_MAX_SEGMENT = 16384
 
 if not os.path.exists(LIB_PATH):
@@ -85,6 +86,8 @@ _SIGS = {
                       _i32, _p, _i64, _p, _i64, _p, _p, _sz, _p], _i32),
     "rand_cholqr_lstsq": ([_i64, _i64, _i64, _i64, _i64, _i32, _p, _i64, _p, _i64, _p, _p,
                            _i32, _p, _i64, _p, _i64, _p, _i64, _p, _p, _sz, _p], _i32),
+    "normal_equations_lstsq": ([_i64, _i64, _i64, _i32, _p, _i64, _p, _i64, _p, _i64, _p, _i64,
+                                _p, _p, _sz, _p], _i32),
     "ms_batch_workspace_size": ([_i32, _p, _i32, _i32, _p], _sz),
     "sketch_lstsq_batched": ([_i32, _p, _p, _i32, _i32, _p, _p, _sz, _p], _i32),
     "ms_batch_status": ([_p, _i32, _p, _p], _i32),
@@ -391,6 +394,34 @@ def rand_cholqr_lstsq(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torc
     _ok(_lib.rand_cholqr_lstsq(d, n, nrhs, k, k2, a_dt, Ap, lda, Bp, ldb, _vec(h, torch.int32, "h"),
                                _vec(s, torch.int8, "s"), g_dt, Gp, ldg, Xp, ldx, Rp, ldr,
                                ctypes.byref(o), wp, have, _stream(stream)), "rand_cholqr_lstsq")
+    return X, R, ws
+
+
+def normal_equations_lstsq(A: torch.Tensor, B: torch.Tensor, X: torch.Tensor | None = None,
+                           R: torch.Tensor | None = None, ws: torch.Tensor | None = None,
+                           stream=None):
+    """X = argmin ||B - A X|| by the normal equations: [A | B]^T [A | B] in
+    FP64 in one pass, R = chol(A^T A), R^T y = A^T B, X = R^{-1} y (n x nrhs,
+    FP64).  R (optional, n x n FP64) receives the Cholesky factor.
+    Returns (X, R, ws)."""
+    d, n = A.shape
+    if B.dim() == 1:
+        B = B.unsqueeze(1)
+    nrhs = B.shape[1]
+    a_dt = _dt(A)
+    if B.dtype != A.dtype:
+        raise ValueError("B must have A's dtype")
+    if X is None:
+        X = empty_colmajor(n, nrhs, torch.float64, A.device)
+    Ap, lda = colmajor(A, "A")
+    Bp, ldb = colmajor(B, "B")
+    Xp, ldx = colmajor(X, "X")
+    Rp, ldr = colmajor(R, "R") if R is not None else (None, n)
+    need = workspace_size("normal_equations", d=d, n=n, nrhs=nrhs, a_dtype=a_dt)
+    ws = workspace(need, A.device) if ws is None else ws
+    wp, have = _ws_ptr(ws, need)
+    _ok(_lib.normal_equations_lstsq(d, n, nrhs, a_dt, Ap, lda, Bp, ldb, Xp, ldx, Rp, ldr, None,
+                                    wp, have, _stream(stream)), "normal_equations_lstsq")
     return X, R, ws
 
 

@@ -157,6 +157,20 @@ RcqLayout rcq_layout(int64_t d, int64_t n, int64_t k, int64_t k2, ms_dtype a_dty
   return L;
 }
 
+// Normal equations: the fused pass's per-workgroup partials and their sum.
+struct NeLayout {
+  size_t part = 0, w = 0, total = 0;
+};
+
+NeLayout ne_layout() {
+  NeLayout L;
+  Carve cv;
+  L.part = cv.take(rcq_partial_bytes(rcq_grid()));
+  L.w = cv.take((size_t)kRcqMaxN * kRcqMaxCols * 8);
+  L.total = cv.off;
+  return L;
+}
+
 template <typename P>
 P *at(void *ws, size_t off) {
   return reinterpret_cast<P *>(static_cast<unsigned char *>(ws) + off);
@@ -281,6 +295,8 @@ size_t ms_workspace_size(int op, int64_t d, int64_t n, int64_t nrhs, int64_t k, 
     }
     case MS_OP_RAND_CHOLQR:
       return rcq_layout(d, n, k, k2, a_dtype, g_dtype, mode).total;
+    case MS_OP_NORMAL_EQUATIONS:
+      return ne_layout().total;
     default:
       return 0;
   }
@@ -606,6 +622,38 @@ ms_status rand_cholqr_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64
   // x = R^{-1} y
   if (e == hipSuccess)
     e = launch_rcq_finish((int)n, (int)nrhs, grid, part, at<double>(ws, L.w), r0, kRcqMaxN, X, ldx,
+                          R, ldr, status, st);
+  return from_hip(e);
+}
+
+ms_status normal_equations_lstsq(int64_t d, int64_t n, int64_t nrhs, ms_dtype a_dtype,
+                                 const void *A, int64_t lda, const void *B, int64_t ldb,
+                                 double *X, int64_t ldx, double *R, int64_t ldr,
+                                 const ms_opts *opts, void *ws, size_t ws_bytes, void *stream) {
+  (void)opts;
+  if (d < 1 || n < 1 || nrhs < 1) return MS_ERR_ARG;
+  if (a_dtype != MS_F64 && a_dtype != MS_F32) return MS_ERR_ARG;
+  if (n > kRcqMaxN || nrhs > kRcqMaxRhs || n + nrhs > kRcqMaxCols) return MS_ERR_UNSUPPORTED;
+  if (lda < d || ldb < d || ldx < n || (R && ldr < n)) return MS_ERR_ARG;
+  if (!A || !B || !X || !ws) return MS_ERR_ARG;
+  const NeLayout L = ne_layout();
+  if (ws_bytes < L.total) return MS_ERR_NOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  int *status = static_cast<int *>(ws);
+  double *part = at<double>(ws, L.part);
+  const int grid = rcq_grid();
+  hipError_t e = launch_zero_status(status, st);
+  // one pass: per-workgroup [A | B]^T [A | B] (FP64), then the ordered sum,
+  // R = chol(A^T A), R^T y = A^T B, X = R^{-1} y
+  if (e == hipSuccess)
+    e = a_dtype == MS_F64
+            ? launch_rcq_gram<double>(d, (int)n, (int)nrhs, static_cast<const double *>(A), lda,
+                                      static_cast<const double *>(B), ldb, nullptr, part, grid,
+                                      st)
+            : launch_rcq_gram<float>(d, (int)n, (int)nrhs, static_cast<const float *>(A), lda,
+                                     static_cast<const float *>(B), ldb, nullptr, part, grid, st);
+  if (e == hipSuccess)
+    e = launch_rcq_finish((int)n, (int)nrhs, grid, part, at<double>(ws, L.w), nullptr, 0, X, ldx,
                           R, ldr, status, st);
   return from_hip(e);
 }

@@ -181,6 +181,8 @@ hipError_t launch_qr_apply_solve(int64_t m, int64_t n, int64_t nrhs, const doubl
 // rand_cholQR least squares (randcholqr.hip): R0^{-1} of the sketch's R
 // factor, the fused pass Q0 = A R0^{-1} -> Q0^T [Q0 | B] (per-workgroup
 // partials), then the ordered sum, Cholesky and the two triangular solves.
+// With Rinv and R0 null the same kernels solve the normal equations
+// (W = [A | B]^T [A | B], R = chol(A^T A)).
 constexpr int kRcqMaxN = 64;     // columns of A
 constexpr int kRcqMaxRhs = 16;   // right-hand sides
 constexpr int kRcqMaxCols = 80;  // n + nrhs (the partial's row length)

@@ -22,6 +22,37 @@ namespace ms {
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+// four consecutive elements at element alignment (a dword-aligned multi-dword
+// global load is legal)
+typedef double dvec4e __attribute__((ext_vector_type(4), aligned(8)));
+typedef float fvec4e __attribute__((ext_vector_type(4), aligned(4)));
+template <typename T>
+struct Four;
+template <>
+struct Four<double> {
+  typedef dvec4e type;
+};
+template <>
+struct Four<float> {
+  typedef fvec4e type;
+};
+
+// Rows row .. row + 3 of the column at p (zero past row d, or for p null),
+// promoted to FP64.
+template <typename T>
+__device__ __forceinline__ v4d load_rows4(const T *p, int64_t row, int64_t d) {
+  v4d v = v4d{0.0, 0.0, 0.0, 0.0};
+  if (p == nullptr) return v;
+  if (row + 4 <= d) {
+    const typename Four<T>::type x = gload((const typename Four<T>::type *)(p + row));
+    v = v4d{(double)x[0], (double)x[1], (double)x[2], (double)x[3]};
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (row + r < d) v[r] = (double)gload(p + row + r);
+  }
+  return v;
+}
 
 constexpr int kLdr = 68;   // LDS row stride of R0^{-1} (doubles)
 constexpr int kLdq = 84;   // LDS row stride of a [Q0 | B] block (doubles)
@@ -69,7 +100,8 @@ __global__ __launch_bounds__(64) void k_rcq_trinv(int n, const double *__restric
 // B that do not fit in Q0's last tile (nx = n + nrhs - 16 NTI of them) are
 // handled by EXTRA: 0 (none), 1 (one more 16-column MFMA tile), 2 (nx = 1:
 // vector FMAs, since a tile with one column in use would cost 4 NTI
-// matrix-core instructions per slab).
+// matrix-core instructions per slab).  PLAIN: no R0 (the normal equations,
+// Sec. 6.3): V = [A | B] itself, W = V^T V.
 //
 // Each wave takes slabs of 16 rows of A (grid-stride over all waves).  For a
 // slab it forms the 16 x 16 NTI block of Q0 = A R0^{-1} on the f64 matrix
@@ -86,8 +118,13 @@ __global__ __launch_bounds__(64) void k_rcq_trinv(int n, const double *__restric
 // through LDS and the workgroup's partial (row-major 64 x 80: entry (i, j) at
 // i 80 + j; upper tiles only) goes to part[blockIdx.x].  Eight waves (two per
 // SIMD) keep the matrix cores busy while a wave waits for its slab.
+//
+// In the PLAIN form the operands come from memory directly: the Gram
+// product only needs both operands to map the k index to the same row, so
+// lane (li, lk) takes rows 4 lk .. 4 lk + 3 of column 16 ct + li with one
+// vector load (register r = row 4 lk + r).
 constexpr int kGramWaves = 8;
-template <typename TA, int NTI, int EXTRA>
+template <typename TA, int NTI, int EXTRA, bool PLAIN>
 __global__ __launch_bounds__(64 * kGramWaves) void k_rcq_gram(int64_t d, int n, int nrhs,
                                                               const TA *__restrict__ A,
                                                               int64_t lda,
@@ -104,9 +141,11 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_rcq_gram(int64_t d, int n, 
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int li = lane & 15, lk = lane >> 4;
-  for (int t = tid; t < kRcqMaxN * kRcqMaxN; t += 64 * kGramWaves)
-    rinv[(t >> 6) * kLdr + (t & 63)] = Rinv[t];
-  __syncthreads();
+  if (!PLAIN) {
+    for (int t = tid; t < kRcqMaxN * kRcqMaxN; t += 64 * kGramWaves)
+      rinv[(t >> 6) * kLdr + (t & 63)] = Rinv[t];
+    __syncthreads();
+  }
 
   v4d w[NT];
 #pragma unroll
@@ -124,7 +163,34 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_rcq_gram(int64_t d, int n, 
   // per-lane bases; the per-k-step offsets 4 ks lda are wave-uniform
   const TA *const Al = A + li + (int64_t)lk * lda;
   const int64_t lda4 = 4 * lda;
-  for (int64_t sl = (int64_t)blockIdx.x * kGramWaves + wave; sl < nslab; sl += stride) {
+  // PLAIN: the column each lane reads in tile ct (A's, B's, or none)
+  const TA *vcol[NCT];
+#pragma unroll
+  for (int ct = 0; ct < NCT; ++ct) {
+    const int c = 16 * ct + li;
+    vcol[ct] = c < n ? A + (int64_t)c * lda : (c - n < nrhs ? B + (int64_t)(c - n) * ldb : nullptr);
+  }
+  const TA *const zcol = NZ > 0 ? B + (int64_t)zc0 * ldb : nullptr;
+  for (int64_t sl = (int64_t)blockIdx.x * kGramWaves + wave; PLAIN && sl < nslab; sl += stride) {
+    const int64_t rr = sl * 16 + 4 * lk;
+    v4d q[NCT];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) q[ct] = load_rows4(vcol[ct], rr, d);
+    v4d zb = NZ > 0 && nx > 0 ? load_rows4(zcol, rr, d) : v4d{0.0, 0.0, 0.0, 0.0};
+    int u = 0;
+#pragma unroll
+    for (int it = 0; it < NTI; ++it)
+#pragma unroll
+      for (int ct = it; ct < NCT; ++ct, ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w[u] = mma64(q[it][r], q[ct][r], w[u]);
+    if (NZ > 0)
+#pragma unroll
+      for (int it = 0; it < NTI; ++it)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) z[it][0] += q[it][r] * zb[r];
+  }
+  for (int64_t sl = (int64_t)blockIdx.x * kGramWaves + wave; !PLAIN && sl < nslab; sl += stride) {
     const int64_t r0 = sl * 16;
     const bool rin = r0 + li < d;
     const TA *const As = Al + r0;
@@ -254,6 +320,7 @@ __global__ __launch_bounds__(256) void k_rcq_reduce(int nparts, const double *__
 
 // One wave: R1 = chol(G) (G = Q0^T Q0, the upper part of W), y = R1^{-T} z
 // (z = Q0^T B, columns n .. n + nrhs of W), R = R1 R0 and x = R^{-1} y.
+// R0 null: R0 = I (the normal equations: G = A^T A, z = A^T B, R = R1).
 // Lane l holds column l of the working matrix in registers (g[i] = entry
 // (i, l)); matrices of order n < 64 are padded to 64 with the identity, so
 // every lane runs the same fully unrolled steps.
@@ -274,8 +341,9 @@ __global__ __launch_bounds__(64) void k_rcq_solve(int n, int nrhs, const double 
   for (int c = 0; c < nrhs; ++c) zs[c * N + lane] = lane < n ? W[lane * kRcqMaxCols + n + c] : 0.0;
   // R0 (padded with the identity), staged column by column (lane = row)
   for (int j = 0; j < N; ++j)
-    rm[lane + j * L] = (lane < n && j < n) ? (lane <= j ? R0[lane + (int64_t)j * ldr0] : 0.0)
-                                           : (lane == j ? 1.0 : 0.0);
+    rm[lane + j * L] = (R0 && lane < n && j < n)
+                           ? (lane <= j ? R0[lane + (int64_t)j * ldr0] : 0.0)
+                           : (lane == j ? 1.0 : 0.0);
 
   // right-looking Cholesky: at step j lane l forms R1[j][l] (l >= j), row j
   // goes to LDS, and every lane updates its column with it
@@ -368,10 +436,14 @@ hipError_t launch_rcq_gram(int64_t d, int n, int nrhs, const TA *A, int64_t lda,
   const int nti = (n + 15) / 16, nx = n + nrhs - 16 * nti;
   const int extra = nx <= 0 ? 0 : (nx == 1 ? 2 : 1);
   if (nx > 16) return hipErrorInvalidValue;
-#define MS_RCQ_CASE(T_, E_)                                                                  \
-  case 3 * T_ + E_:                                                                          \
-    hipLaunchKernelGGL((k_rcq_gram<TA, T_, E_>), dim3(grid), dim3(64 * kGramWaves), 0, st, d, \
-                       n, nrhs, A, lda, B, ldb, Rinv, part);                                 \
+#define MS_RCQ_CASE(T_, E_)                                                                 \
+  case 3 * T_ + E_:                                                                         \
+    if (Rinv)                                                                               \
+      hipLaunchKernelGGL((k_rcq_gram<TA, T_, E_, false>), dim3(grid), dim3(64 * kGramWaves), \
+                         0, st, d, n, nrhs, A, lda, B, ldb, Rinv, part);                    \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_rcq_gram<TA, T_, E_, true>), dim3(grid), dim3(64 * kGramWaves),  \
+                         0, st, d, n, nrhs, A, lda, B, ldb, Rinv, part);                    \
     break;
   switch (3 * nti + extra) {
     MS_RCQ_CASE(1, 0)
