@@ -75,6 +75,8 @@ def _load():
             "or_round_bf16_array": [_i64, _p, _p],
             "or_rand_cholqr_from_sketch": [_i64, _i64, _i64, _i64, _p, _i64, _p, _i64,
                                            _p, _i64, _p, _i64, _p, _i64],
+            "or_splitmix64": [ctypes.c_uint64, _i64, _p],
+            "or_hash_sketch": [_i64, _i64, ctypes.c_uint64, _p, _p],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -85,6 +87,7 @@ def _load():
         lib.or_apply_qt.restype = None
         lib.or_round_bf16.restype = ctypes.c_float
         lib.or_round_bf16_array.restype = None
+        lib.or_splitmix64.restype = None
         _lib = lib
     return _lib
 
@@ -355,6 +358,37 @@ def rand_cholqr_lstsq(A, B, h, s, G, k: int, y_bf16: bool = False):
     SA = gemm(Gd, np.asarray(Y, dtype=np.float64))
     X, R = rand_cholqr_from_sketch(SA, A, B)
     return X, R, SA
+
+
+# --------------------------------------------------------------------------
+# Hash-generated CountSketch (Sec. 8, future work): (h, s) from SplitMix64
+# --------------------------------------------------------------------------
+
+def splitmix64(seed: int, count: int) -> np.ndarray:
+    """``count`` successive outputs of SplitMix64 started at state ``seed``
+    (Steele, Lea and Flood, OOPSLA 2014), as uint64."""
+    out = np.zeros(int(count), dtype=np.uint64)
+    _load().or_splitmix64(ctypes.c_uint64(int(seed) & (2**64 - 1)), int(count), _ptr(out))
+    return out
+
+
+def hash_sketch(d: int, k: int, seed: int):
+    """Bucket map h (int32) and signs s (int8) of the hash-generated
+    CountSketch: row i takes u = the (i+1)-th SplitMix64 output from state
+    ``seed``; h = floor((u >> 32) k / 2^32), s = -1 if bit 0 of u else +1."""
+    h = np.zeros(int(d), dtype=np.int32)
+    s = np.zeros(int(d), dtype=np.int8)
+    _check(_load().or_hash_sketch(int(d), int(k), ctypes.c_uint64(int(seed) & (2**64 - 1)),
+                                  _ptr(h), _ptr(s)), "hash_sketch")
+    return h, s
+
+
+def countsketch_hashed(A, k: int, seed: int, acc: str | None = None) -> np.ndarray:
+    """Y = C A for the CountSketch C whose (h, s) are ``hash_sketch(d, k,
+    seed)`` (Def. 3 with generated instead of stored vectors)."""
+    A = np.asarray(A)
+    h, s = hash_sketch(A.shape[0], k, seed)
+    return countsketch(A, h, s, k, acc=acc)
 
 
 def round_bf16(x) -> np.ndarray:

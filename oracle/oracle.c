@@ -545,3 +545,42 @@ done:
   free(R);
   return st;
 }
+
+/* ------------------------------------------------------------------------
+ * Hash-generated CountSketch (Sec. 8 names it future work: the bucket and
+ * sign of each row come from a hash of the row index instead of stored
+ * vectors).  The hash is SplitMix64 (Steele, Lea and Flood, "Fast splittable
+ * pseudorandom number generators", OOPSLA 2014): the state advances by the
+ * odd constant gamma = 0x9E3779B97F4A7C15 and each output is the state passed
+ * through the finaliser mix64.  Row i (0-based) takes the (i+1)-th output of
+ * the generator started at state `seed`:
+ *   u_i = mix64(seed + (i + 1) gamma)   (mod 2^64)
+ *   h_i = floor((u_i >> 32) k / 2^32)  (multiply-shift: 0 <= h_i < k)
+ *   s_i = +1 if bit 0 of u_i is 0, else -1.
+ * ------------------------------------------------------------------------ */
+static uint64_t or_mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * UINT64_C(0xBF58476D1CE4E5B9);
+  z = (z ^ (z >> 27)) * UINT64_C(0x94D049BB133111EB);
+  return z ^ (z >> 31);
+}
+
+/* `count` successive SplitMix64 outputs from state `seed`. */
+void or_splitmix64(uint64_t seed, int64_t count, uint64_t *out) {
+  uint64_t state = seed;
+  for (int64_t t = 0; t < count; ++t) {
+    state = state + UINT64_C(0x9E3779B97F4A7C15);
+    out[t] = or_mix64(state);
+  }
+}
+
+/* h and s of rows 0 .. d-1 for k buckets (1 <= k <= 2^31). */
+int or_hash_sketch(int64_t d, int64_t k, uint64_t seed, int32_t *h, int8_t *s) {
+  if (d < 0 || k < 1 || k > (INT64_C(1) << 31)) return ORACLE_ERR_ARG;
+  for (int64_t i = 0; i < d; ++i) {
+    const uint64_t u = or_mix64(seed + (uint64_t)(i + 1) * UINT64_C(0x9E3779B97F4A7C15));
+    h[i] = (int32_t)(((u >> 32) * (uint64_t)k) >> 32);
+    s[i] = (u & 1) ? (int8_t)-1 : (int8_t)1;
+  }
+  return ORACLE_OK;
+}
+

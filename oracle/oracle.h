@@ -57,4 +57,7 @@ int or_rand_cholqr_from_sketch(int64_t d, int64_t n, int64_t nrhs, int64_t m,
                                int64_t lda, const double *B, int64_t ldb, double *X,
                                int64_t ldx, double *Rout, int64_t ldr);
 
+void or_splitmix64(uint64_t seed, int64_t count, uint64_t *out);
+int or_hash_sketch(int64_t d, int64_t k, uint64_t seed, int32_t *h, int8_t *s);
+
 #endif

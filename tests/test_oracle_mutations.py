@@ -55,6 +55,12 @@ MUTANTS = [
      "for (int64_t l = 0; l < j; ++l) acc = acc - q[l] * W[l + j * m];\n      q[j] = acc * W[j + j * m];", 0),
     ("rcq_rhs_skips_first_row", "for (int64_t p = 0; p < n; ++p) z[p + c * n] = z[p + c * n] + q[p] * B[i + c * ldb];",
      "if (i > 0) for (int64_t p = 0; p < n; ++p) z[p + c * n] = z[p + c * n] + q[p] * B[i + c * ldb];", 0),
+    ("mix64_wrong_shift", "z = (z ^ (z >> 30)) * UINT64_C(0xBF58476D1CE4E5B9);",
+     "z = (z ^ (z >> 31)) * UINT64_C(0xBF58476D1CE4E5B9);", 0),
+    ("hash_bucket_low_bits", "h[i] = (int32_t)(((u >> 32) * (uint64_t)k) >> 32);",
+     "h[i] = (int32_t)(((u & 0xffffffffu) * (uint64_t)k) >> 32);", 0),
+    ("hash_row_off_by_one", "or_mix64(seed + (uint64_t)(i + 1) * UINT64_C(0x9E3779B97F4A7C15));",
+     "or_mix64(seed + (uint64_t)i * UINT64_C(0x9E3779B97F4A7C15));", 0),
 ]
 
 
@@ -83,7 +89,8 @@ def _run_mutant(args):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_countsketch.py"),
                         os.path.join(ROOT, "tests", "test_oracle_solve.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_rcq.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_rcq.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_hash.py")],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     return name, r.returncode, r.stdout[-600:]
 
