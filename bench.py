@@ -64,7 +64,7 @@ def parse():
                     choices=["countsketch", "countsketch_f32_k32768", "countsketch_f32_k131072",
                              "copy", "gaussian_f64", "gaussian_bf16", "batched_mixed",
                              "solve_fp32", "solve_mixed", "rand_cholqr",
-                             "normal_equations"],
+                             "normal_equations", "countsketch_hashed"],
                     help="profiling runs: launch only the LDS CountSketch of [A | b] (--steps "
                          "times), only a plain device copy of 1 GiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters), or only the Gaussian stage of the "
@@ -333,6 +333,50 @@ def rcq_leg(ms, torch, np, A, B, h, s, G, k, mode, X_ss, reps, A_host=None, B_ho
     return out
 
 
+def hashed_leg(ms, torch, seed, dev, reps=20):
+    """The hash-generated CountSketch (Sec. 8's future-work variant) on the
+    narrow workload where stored (h, s) matter most: A 16,777,216 x 8 FP32,
+    k = 2 n^2 = 128.  Times the LDS CountSketch with stored packed codes
+    (4 bytes per row), with stored h and s (5 bytes per row, checked in the
+    kernel) and with generated ones (0 bytes per row)."""
+    d, n, k = 1 << 24, 8, 128
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    A = torch.randn((n, d), generator=gen, device=dev, dtype=torch.float32).t()
+    h, s = ms.hash_sketch(d, k, seed)
+    code, _ = ms.pack_sketch(h, s, k)
+    Y = ms.empty_colmajor(k, n, torch.float32, dev)
+    cws = ms.workspace(ms.workspace_size("countsketch", d=d, n=n, k=k, a_dtype=ms.MS_F32), dev)
+    hws = ms.workspace(ms.workspace_size("countsketch_hashed", d=d, n=n, k=k, a_dtype=ms.MS_F32),
+                       dev)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        a, b = event_pair(torch)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps * 1e3  # us
+
+    t_code = timed(lambda: ms.countsketch_accumulate(A, code, k, Y, mode="lds", ws=cws))
+    t_hs = timed(lambda: ms.countsketch_apply(A, h, s, k, Y=Y, mode="lds", ws=cws))
+    t_hash = timed(lambda: ms.countsketch_hashed(A, k, seed, Y=Y, ws=hws))
+    ms.check_status(hws)
+    base = d * n * 4 + k * n * 4
+    out = {"workload": "countsketch_f32_16777216x8_k128", "bytes_A_and_Y": base}
+    for name, t, extra in (("stored_packed_codes", t_code, 4 * d),
+                           ("stored_h_s", t_hs, 5 * d),
+                           ("hash_generated", t_hash, 0)):
+        out[name] = {"avg_us": t, "algorithmic_bytes": base + extra,
+                     "GBps": (base + extra) / (t * 1e-6) / 1e9,
+                     "pct_hbm_peak": 100.0 * (base + extra) / (t * 1e-6) / 1e9 / HBM_PEAK_GBPS}
+    out["speedup_vs_packed_codes"] = t_code / t_hash
+    return out
+
+
 def other_configs_leg(ms, torch, np, seed, dev, reps=10, only=None):
     """The FP32 and mixed-precision least-squares workloads: full solves
     (sketch_lstsq) and their CountSketch kernel alone, inputs generated on
@@ -447,6 +491,19 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"only": "copy", "bytes_read_per_launch": nbytes,
                           "bytes_written_per_launch": nbytes, "launches": args.steps}))
+        return
+    if args.only == "countsketch_hashed":
+        # the hash-generated CountSketch of A 16,777,216 x 8 FP32 (k = 128) alone
+        d_, n_, k_ = 1 << 24, 8, 128
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(args.seed)
+        Ax = torch.randn((n_, d_), generator=gen, device=dev, dtype=torch.float32).t()
+        Yx, hws = ms.countsketch_hashed(Ax, k_, args.seed)
+        for _ in range(args.steps):
+            ms.countsketch_hashed(Ax, k_, args.seed, Y=Yx, ws=hws)
+        ms.check_status(hws)
+        print(json.dumps({"only": args.only, "kernel": "k_cs_lds_xcd (hashed)",
+                          "launches": args.steps + 1, "bytes_per_launch": d_ * n_ * 4 + k_ * n_ * 4}))
         return
     if args.only in ("solve_fp32", "solve_mixed"):
         # one of the FP32 / mixed-precision solves alone (3 timed solves)
@@ -691,6 +748,10 @@ def main():
             out["other_configs"] = other_configs_leg(ms, torch, np, seed + 2, dev)
         except Exception as e:
             out["other_configs"] = {"error": repr(e)}
+    try:
+        out["hashed_countsketch"] = hashed_leg(ms, torch, seed, dev)
+    except Exception as e:
+        out["hashed_countsketch"] = {"error": repr(e)}
     if args.compare_problems > 0:
         try:
             out["batched_mixed_vs_plain_fp64"] = mixed_vs_fp64_leg(

@@ -100,6 +100,7 @@ typedef struct {
 #define MS_OP_LSTSQ 5
 #define MS_OP_RAND_CHOLQR 6
 #define MS_OP_NORMAL_EQUATIONS 7
+#define MS_OP_COUNTSKETCH_HASHED 8
 
 /*
  * Bytes of workspace the operation needs (a multiple of 256, at least 256).
@@ -274,6 +275,36 @@ ms_status rand_cholqr_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k,
                             const void *G, int64_t ldg, double *X, int64_t ldx,
                             double *R, int64_t ldr, const ms_opts *opts, void *ws,
                             size_t ws_bytes, void *stream);
+
+/*
+ * Hash-generated CountSketch (Sec. 8 names it future work): Y = C A with the
+ * bucket and sign of each row computed from (seed, row) instead of read from
+ * stored h and s, which removes their 5 bytes per row of traffic and the
+ * packing pass.  Row i (0-based) takes u = the (i+1)-th output of SplitMix64
+ * started at state `seed` (Steele, Lea and Flood, OOPSLA 2014: the state
+ * advances by 0x9E3779B97F4A7C15, the output is the state through its
+ * finaliser); h_i = floor((u >> 32) k / 2^32), s_i = -1 if bit 0 of u is 1,
+ * else +1.  ms_hash_sketch writes the same h and s, so
+ * countsketch_apply(..., h, s, ...) computes the same sketch.
+ *   d x n A (a_dtype MS_F64 or MS_F32, column-major, lda >= d), Y k x n of
+ *   A's dtype (ldy >= k), overwritten.  1 <= k <= 2^31 - 2.
+ *   opts: cs_mode MS_CS_AUTO or MS_CS_LDS and cs_schedule 0 only (else
+ *   MS_ERR_UNSUPPORTED); cs_tile_cols as for countsketch_apply.
+ *   Accumulation order as MS_CS_LDS (FP64 partial sums; not bit-stable).
+ * ws: ms_workspace_size(MS_OP_COUNTSKETCH_HASHED, d, n, 0, k, 0, a_dtype,
+ * a_dtype, opts) bytes.
+ */
+ms_status countsketch_hashed(int64_t d, int64_t n, int64_t k, uint64_t seed,
+                             ms_dtype a_dtype, const void *A, int64_t lda,
+                             void *Y, int64_t ldy, const ms_opts *opts,
+                             void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * h (d int32) and s (d int8) of the hash-generated CountSketch with this
+ * seed and k (see countsketch_hashed); device pointers, written on `stream`.
+ */
+ms_status ms_hash_sketch(int64_t d, int64_t k, uint64_t seed, int32_t *h,
+                         int8_t *s, void *stream);
 
 /*
  * Least squares by the normal equations (Sec. 6.3: the deterministic solver

@@ -24,7 +24,7 @@ __all__ = [
     "empty_colmajor", "colmajor", "workspace", "workspace_size", "check_status",
     "bucket_plan", "pack_sketch", "countsketch_accumulate", "countsketch_apply",
     "gaussian_apply", "multisketch_apply", "qr_solve", "sketch_lstsq", "rand_cholqr_lstsq",
-    "normal_equations_lstsq", "MsProblem",
+    "normal_equations_lstsq", "countsketch_hashed", "hash_sketch", "MsProblem",
     "batch_workspace_size", "sketch_lstsq_batched", "batch_status", "BatchRunner",
 ]
 
@@ -37,7 +37,7 @@ MS_F64, MS_F32, MS_BF16 = 0, 1, 2
 MODES = {"auto": 0, "atomic": 1, "lds": 2, "sorted": 3}
 OPS = {"bucket_plan": 0, "countsketch": 1, "gaussian": 2, "multisketch": 3,
        "qr_solve": 4, "lstsq": 5, "rand_cholqr": 6,
-       "normal_equations": 7}
+       "normal_equations": 7, "countsketch_hashed": 8}
 MS_SORTED_MAX_SEGMENT = 16384
 
 if not os.path.exists(LIB_PATH):
@@ -88,6 +88,9 @@ _SIGS = {
                            _i32, _p, _i64, _p, _i64, _p, _i64, _p, _p, _sz, _p], _i32),
     "normal_equations_lstsq": ([_i64, _i64, _i64, _i32, _p, _i64, _p, _i64, _p, _i64, _p, _i64,
                                 _p, _p, _sz, _p], _i32),
+    "countsketch_hashed": ([_i64, _i64, _i64, ctypes.c_uint64, _i32, _p, _i64, _p, _i64, _p, _p,
+                            _sz, _p], _i32),
+    "ms_hash_sketch": ([_i64, _i64, ctypes.c_uint64, _p, _p, _p], _i32),
     "ms_batch_workspace_size": ([_i32, _p, _i32, _i32, _p], _sz),
     "sketch_lstsq_batched": ([_i32, _p, _p, _i32, _i32, _p, _p, _sz, _p], _i32),
     "ms_batch_status": ([_p, _i32, _p, _p], _i32),
@@ -263,6 +266,37 @@ def countsketch_apply(A: torch.Tensor, h: torch.Tensor, s: torch.Tensor, k: int,
                                _vec(s, torch.int8, "s") if d else None, Yp, ldy,
                                ctypes.byref(o), wp, have, _stream(stream)), "countsketch_apply")
     return Y, ws
+
+
+def countsketch_hashed(A: torch.Tensor, k: int, seed: int, Y: torch.Tensor | None = None,
+                       ws: torch.Tensor | None = None, stream=None, tile_cols: int = 0):
+    """Y = C A (k x n, A's dtype) for the hash-generated CountSketch: row i's
+    bucket and sign come from SplitMix64's (i+1)-th output from state
+    ``seed`` (no stored h, s).  Returns (Y, ws)."""
+    d, n = A.shape
+    a_dt = _dt(A)
+    Ap, lda = colmajor(A, "A")
+    if Y is None:
+        Y = empty_colmajor(k, n, A.dtype, A.device)
+    Yp, ldy = colmajor(Y, "Y")
+    if Y.shape != (k, n) or Y.dtype != A.dtype:
+        raise ValueError("Y must be k x n with A's dtype")
+    need = workspace_size("countsketch_hashed", d=d, n=n, k=k, a_dtype=a_dt)
+    ws = workspace(need, A.device) if ws is None else ws
+    wp, have = _ws_ptr(ws, need)
+    o = _opts("auto", 0, tile_cols, 0)
+    _ok(_lib.countsketch_hashed(d, n, k, int(seed) & (2**64 - 1), a_dt, Ap, lda, Yp, ldy,
+                                ctypes.byref(o), wp, have, _stream(stream)), "countsketch_hashed")
+    return Y, ws
+
+
+def hash_sketch(d: int, k: int, seed: int, device="cuda", stream=None):
+    """h (int32) and s (int8) of the hash-generated CountSketch, on the device."""
+    h = torch.empty(d, dtype=torch.int32, device=device)
+    s = torch.empty(d, dtype=torch.int8, device=device)
+    _ok(_lib.ms_hash_sketch(d, k, int(seed) & (2**64 - 1), h.data_ptr() if d else None,
+                            s.data_ptr() if d else None, _stream(stream)), "ms_hash_sketch")
+    return h, s
 
 
 def gaussian_apply(G: torch.Tensor, Y: torch.Tensor, Z: torch.Tensor | None = None,

@@ -297,6 +297,11 @@ size_t ms_workspace_size(int op, int64_t d, int64_t n, int64_t nrhs, int64_t k, 
       return rcq_layout(d, n, k, k2, a_dtype, g_dtype, mode).total;
     case MS_OP_NORMAL_EQUATIONS:
       return ne_layout().total;
+    case MS_OP_COUNTSKETCH_HASHED: {
+      const size_t pb = cs_part_bytes(d, k, n, dtype_size(a_dtype));
+      if (pb) cv.take(pb);
+      return cv.off;
+    }
     default:
       return 0;
   }
@@ -624,6 +629,50 @@ ms_status rand_cholqr_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64
     e = launch_rcq_finish((int)n, (int)nrhs, grid, part, at<double>(ws, L.w), r0, kRcqMaxN, X, ldx,
                           R, ldr, status, st);
   return from_hip(e);
+}
+
+ms_status countsketch_hashed(int64_t d, int64_t n, int64_t k, uint64_t seed, ms_dtype a_dtype,
+                             const void *A, int64_t lda, void *Y, int64_t ldy,
+                             const ms_opts *opts, void *ws, size_t ws_bytes, void *stream) {
+  if (d < 0 || n < 0 || k < 1 || k > kMax31 || n > (int64_t)1 << 30) return MS_ERR_ARG;
+  if (a_dtype != MS_F64 && a_dtype != MS_F32) return MS_ERR_ARG;
+  if (!valid_mode(opts)) return MS_ERR_ARG;
+  const int m = opts ? opts->cs_mode : MS_CS_AUTO;
+  if ((m != MS_CS_AUTO && m != MS_CS_LDS) || (opts && opts->cs_schedule != 0))
+    return MS_ERR_UNSUPPORTED;
+  if (lda < (d > 1 ? d : 1) || ldy < k) return MS_ERR_ARG;
+  if (!ws || (n > 0 && !Y) || (d > 0 && n > 0 && !A)) return MS_ERR_ARG;
+  const size_t need = ms_workspace_size(MS_OP_COUNTSKETCH_HASHED, d, n, 0, k, 0, a_dtype, a_dtype,
+                                        opts);
+  if (ws_bytes < need) return MS_ERR_NOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  int *status = static_cast<int *>(ws);
+  if (n == 0) return from_hip(launch_zero_status(status, st));
+  Carve cv;
+  const size_t pbytes = cs_part_bytes(d, k, n, dtype_size(a_dtype));
+  void *part = pbytes ? at<void>(ws, cv.take(pbytes)) : nullptr;
+  const CsTuning tune = tuning_of(opts);
+  hipError_t e;
+  if (a_dtype == MS_F64) {
+    Cols<double> c{static_cast<const double *>(A), lda, nullptr, 0, (int)n, (int)n, 1, seed};
+    e = launch_prologue<double>(status, static_cast<double *>(Y), k, n, ldy, st);
+    if (e == hipSuccess)
+      e = launch_cs_lds<double>(d, k, c, nullptr, nullptr, nullptr, static_cast<double *>(Y), ldy,
+                                false, status, st, &tune, part, pbytes);
+  } else {
+    Cols<float> c{static_cast<const float *>(A), lda, nullptr, 0, (int)n, (int)n, 1, seed};
+    e = launch_prologue<float>(status, static_cast<float *>(Y), k, n, ldy, st);
+    if (e == hipSuccess)
+      e = launch_cs_lds<float>(d, k, c, nullptr, nullptr, nullptr, static_cast<float *>(Y), ldy,
+                               false, status, st, &tune, part, pbytes);
+  }
+  return from_hip(e);
+}
+
+ms_status ms_hash_sketch(int64_t d, int64_t k, uint64_t seed, int32_t *h, int8_t *s,
+                         void *stream) {
+  if (d < 0 || k < 1 || k > kMax31 || (d > 0 && (!h || !s))) return MS_ERR_ARG;
+  return from_hip(launch_hash_sketch(d, k, seed, h, s, (hipStream_t)stream));
 }
 
 ms_status normal_equations_lstsq(int64_t d, int64_t n, int64_t nrhs, ms_dtype a_dtype,

@@ -355,15 +355,35 @@ __device__ __forceinline__ uint32_t code_of(const CV &v, int q) {
   return v[q];
 }
 
-// The bucket/sign word of row i: either a packed code (CODES) or built from
-// h and s, in which case a row with h outside [0,k) or s not +-1 yields an
-// invalid word (bucket field 0x7fffffff, never inside a tile) and sets bad.
-template <bool CODES>
+// Where a row's bucket and sign come from (the SRC template argument).
+constexpr int kSrcHS = 0;    // stored h and s, checked per row
+constexpr int kSrcCode = 1;  // packed 4-byte words (ms_pack_sketch)
+constexpr int kSrcHash = 2;  // generated from (key, row): the hash-generated sketch
+
+// The hash-generated sketch's word of row i: u = SplitMix64's (i+1)-th output
+// from state key (Steele, Lea and Flood, OOPSLA 2014: state += 0x9E3779B97F4A7C15,
+// output = the state through its finaliser); bucket = the top 32 bits of u
+// times k, shifted down 32 (multiply-shift, < k); sign bit = bit 0 of u.
+__device__ __forceinline__ uint32_t hash_word(uint64_t key, int64_t i, int64_t k) {
+  uint64_t z = key + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  const uint32_t b = (uint32_t)(((z >> 32) * (uint64_t)k) >> 32);
+  return b | ((uint32_t)z << 31);
+}
+
+// The bucket/sign word of row i: a packed code (kSrcCode), a generated word
+// (kSrcHash, always valid), or built from h and s (kSrcHS), in which case a
+// row with h outside [0,k) or s not +-1 yields an invalid word (bucket field
+// 0x7fffffff, never inside a tile) and sets bad.
+template <int SRC>
 __device__ __forceinline__ uint32_t row_word(const uint32_t *__restrict__ code,
                                              const int32_t *__restrict__ h,
                                              const int8_t *__restrict__ s, int64_t i, int64_t k,
-                                             bool &bad) {
-  if (CODES) {
+                                             bool &bad, uint64_t key = 0) {
+  if (SRC == kSrcHash) return hash_word(key, i, k);
+  if (SRC == kSrcCode) {
     const uint32_t e = gload(code + i);
     bad |= (int64_t)(e & kIdxMask) >= k;
     return e;
@@ -396,12 +416,15 @@ struct HsVec<4> {
 
 // W consecutive words starting at row i (i a multiple of W; 16/8/4/2-byte
 // aligned loads).
-template <bool CODES, int W>
+template <int SRC, int W>
 __device__ __forceinline__ void row_words(const uint32_t *__restrict__ code,
                                           const int32_t *__restrict__ h,
                                           const int8_t *__restrict__ s, int64_t i, int64_t k,
-                                          uint32_t (&e)[W], bool &bad) {
-  if (CODES) {
+                                          uint32_t (&e)[W], bool &bad, uint64_t key = 0) {
+  if (SRC == kSrcHash) {
+#pragma unroll
+    for (int q = 0; q < W; ++q) e[q] = hash_word(key, i + q, k);
+  } else if (SRC == kSrcCode) {
     using CV = typename Vec16<typename std::conditional<W == 2, double, float>::type>::code_t;
     const CV v = gload(reinterpret_cast<const CV *>(code + i));
 #pragma unroll
@@ -428,7 +451,7 @@ __device__ __forceinline__ void row_words(const uint32_t *__restrict__ code,
 // acc[b + j*kt]; rows whose bucket is outside the tile are skipped (only
 // when the buckets of a column do not fit in LDS at once).  Y += the
 // partials, one atomic add per non-zero partial.
-template <typename T, int NT, bool VEC, bool CODES>
+template <typename T, int NT, bool VEC, int SRC>
 __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
                                                  const uint32_t *__restrict__ code,
                                                  const int32_t *__restrict__ h,
@@ -459,8 +482,8 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
     // two vectors in flight per thread per iteration
     for (; i + step + W <= r1; i += 2 * step) {
       uint32_t e0[W], e1[W];
-      row_words<CODES, W>(code, h, s, i, k, e0, bad);
-      row_words<CODES, W>(code, h, s, i + step, k, e1, bad);
+      row_words<SRC, W>(code, h, s, i, k, e0, bad, cols.key);
+      row_words<SRC, W>(code, h, s, i + step, k, e1, bad, cols.key);
       V a0[NT], a1[NT];
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
@@ -483,7 +506,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
     for (; i < r1; i += step) {
       if (i + W <= r1) {
         uint32_t e0[W];
-        row_words<CODES, W>(code, h, s, i, k, e0, bad);
+        row_words<SRC, W>(code, h, s, i, k, e0, bad, cols.key);
         V a0[NT];
 #pragma unroll
         for (int j = 0; j < NT; ++j) a0[j] = gload(reinterpret_cast<const V *>(cp[j] + i));
@@ -496,7 +519,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
         }
       } else {
         for (int64_t r = i; r < r1; ++r) {
-          const uint32_t e0 = row_word<CODES>(code, h, s, r, k, bad);
+          const uint32_t e0 = row_word<SRC>(code, h, s, r, k, bad, cols.key);
           const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
 #pragma unroll
           for (int j = 0; j < NT; ++j)
@@ -506,7 +529,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
     }
   } else {
     for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-      const uint32_t e0 = row_word<CODES>(code, h, s, r, k, bad);
+      const uint32_t e0 = row_word<SRC>(code, h, s, r, k, bad, cols.key);
       const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
 #pragma unroll
       for (int j = 0; j < NT; ++j)
@@ -528,7 +551,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds(int64_t d, Cols<T> cols,
 // [b0, b0 + kt): accumulate into LDS (zero on entry), then add the non-zero
 // partials to Y (PST: store every partial, zeros included, into a buffer the
 // workgroup owns) and leave LDS zero again.  UNR vectors in flight per thread.
-template <typename T, int NT, bool VEC, bool CODES, int UNR, bool NTL, bool PST = false>
+template <typename T, int NT, bool VEC, int SRC, int UNR, bool NTL, bool PST = false>
 __device__ __forceinline__ void cs_segment(double *acc, const Cols<T> &cols, int c0, int nc,
                                            const uint32_t *__restrict__ code,
                                            const int32_t *__restrict__ h,
@@ -539,7 +562,7 @@ __device__ __forceinline__ void cs_segment(double *acc, const Cols<T> &cols, int
 #pragma unroll
   for (int j = 0; j < NT; ++j) cp[j] = col_ptr(cols, min(c0 + j, cols.ncols - 1));
   auto scalar_row = [&](int64_t r) {
-    const uint32_t e0 = row_word<CODES>(code, h, s, r, k, bad);
+    const uint32_t e0 = row_word<SRC>(code, h, s, r, k, bad, cols.key);
     const uint32_t l0 = (e0 & kIdxMask) - (uint32_t)b0;
 #pragma unroll
     for (int j = 0; j < NT; ++j)
@@ -557,7 +580,7 @@ __device__ __forceinline__ void cs_segment(double *acc, const Cols<T> &cols, int
       uint32_t e[UNR][W];
       V a[UNR][NT];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) row_words<CODES, W>(code, h, s, i + u * step, k, e[u], bad);
+      for (int u = 0; u < UNR; ++u) row_words<SRC, W>(code, h, s, i + u * step, k, e[u], bad, cols.key);
 #pragma unroll
       for (int u = 0; u < UNR; ++u)
 #pragma unroll
@@ -577,7 +600,7 @@ __device__ __forceinline__ void cs_segment(double *acc, const Cols<T> &cols, int
     for (; i < r1; i += step) {
       if (i + W <= r1) {
         uint32_t e0[W];
-        row_words<CODES, W>(code, h, s, i, k, e0, bad);
+        row_words<SRC, W>(code, h, s, i, k, e0, bad, cols.key);
         V a0[NT];
 #pragma unroll
         for (int j = 0; j < NT; ++j) a0[j] = gload(reinterpret_cast<const V *>(cp[j] + i));
@@ -620,7 +643,7 @@ __device__ __forceinline__ void cs_segment(double *acc, const Cols<T> &cols, int
 // which stores its partial sum into the die's slice of a partial buffer (Y,
 // ld k, slices of k x ncols) with plain stores; k_cs_part_reduce adds the
 // slices to the output.
-template <typename T, int NT, bool VEC, bool CODES, int UNR, bool NTL, bool PART>
+template <typename T, int NT, bool VEC, int SRC, int UNR, bool NTL, bool PART>
 __global__ __launch_bounds__(1024) void k_cs_lds_xcd(int64_t d, Cols<T> cols,
                                                      const uint32_t *__restrict__ code,
                                                      const int32_t *__restrict__ h,
@@ -649,7 +672,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds_xcd(int64_t d, Cols<T> cols,
     for (int ct = ct0; ct < ct1; ++ct) {
       const int c0 = ct * NT;
       const int nc = min(NT, cols.ncols - c0);
-      cs_segment<T, NT, VEC, CODES, UNR, NTL, true>(acc, cols, c0, nc, code, h, s, k, b0, kt, R0,
+      cs_segment<T, NT, VEC, SRC, UNR, NTL, true>(acc, cols, c0, nc, code, h, s, k, b0, kt, R0,
                                                     R1, Px, k, bad);
     }
     if (bad) record_status(status, MS_ERR_RANGE);
@@ -664,7 +687,7 @@ __global__ __launch_bounds__(1024) void k_cs_lds_xcd(int64_t d, Cols<T> cols,
     const int64_t rhi = min(len, rlo + (u1 - u0));
     const int c0 = ct * NT;
     const int nc = min(NT, cols.ncols - c0);
-    cs_segment<T, NT, VEC, CODES, UNR, NTL>(acc, cols, c0, nc, code, h, s, k, b0, kt, R0 + rlo,
+    cs_segment<T, NT, VEC, SRC, UNR, NTL>(acc, cols, c0, nc, code, h, s, k, b0, kt, R0 + rlo,
                                             R0 + rhi, Y, ldy, bad);
     u0 += rhi - rlo;
   }
@@ -885,15 +908,15 @@ hipError_t launch_batch_cs_res(int count, const ms_problem *P, const BatchEntry 
   return hipGetLastError();
 }
 
-template <typename T, int NT, bool VEC, bool CODES, int UNR, bool NTL, bool PART>
+template <typename T, int NT, bool VEC, int SRC, int UNR, bool NTL, bool PART>
 static hipError_t launch_cs_xcd_k(int grid, size_t lds, hipStream_t st, int64_t d,
                                   const Cols<T> &c, const uint32_t *code, const int32_t *h,
                                   const int8_t *s, int64_t k, int64_t ktile, int nct, int nbt,
                                   int xcds, int spx, int64_t rpx, T *Y, int64_t ldy, int *status) {
-  const void *fn = (const void *)k_cs_lds_xcd<T, NT, VEC, CODES, UNR, NTL, PART>;
+  const void *fn = (const void *)k_cs_lds_xcd<T, NT, VEC, SRC, UNR, NTL, PART>;
   hipError_t e = allow_dynamic_lds(fn, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_cs_lds_xcd<T, NT, VEC, CODES, UNR, NTL, PART>), dim3(grid), dim3(1024),
+  hipLaunchKernelGGL((k_cs_lds_xcd<T, NT, VEC, SRC, UNR, NTL, PART>), dim3(grid), dim3(1024),
                      lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy,
                      status);
   return hipGetLastError();
@@ -902,7 +925,7 @@ static hipError_t launch_cs_xcd_k(int grid, size_t lds, hipStream_t st, int64_t 
 // part (may be null): per-die partial buffer of xcds * k * ncols elements;
 // when given (one column per tile only), the PART schedule stores into it and
 // k_cs_part_reduce adds it to Y.
-template <typename T, int NT, bool CODES>
+template <typename T, int NT, int SRC>
 static hipError_t launch_cs_xcd_v(bool vec, int grid, size_t lds, hipStream_t st, int64_t d,
                                   const Cols<T> &c, const uint32_t *code, const int32_t *h,
                                   const int8_t *s, int64_t k, int64_t ktile, int nct, int nbt,
@@ -913,10 +936,10 @@ static hipError_t launch_cs_xcd_v(bool vec, int grid, size_t lds, hipStream_t st
   if constexpr (NT == 1) {
   if (part && nbt > 1) {
     hipError_t e =
-        vec ? launch_cs_xcd_k<T, NT, true, CODES, UNR, false, true>(
+        vec ? launch_cs_xcd_k<T, NT, true, SRC, UNR, false, true>(
                   grid, lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, part, k,
                   status)
-            : launch_cs_xcd_k<T, NT, false, CODES, UNR, false, true>(
+            : launch_cs_xcd_k<T, NT, false, SRC, UNR, false, true>(
                   grid, lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, part, k,
                   status);
     if (e != hipSuccess) return e;
@@ -929,34 +952,34 @@ static hipError_t launch_cs_xcd_v(bool vec, int grid, size_t lds, hipStream_t st
   }
   }
   if (nbt > 1)  // bucket tiles re-read A: ordinary loads, so the die's L2 keeps it
-    return vec ? launch_cs_xcd_k<T, NT, true, CODES, UNR, false, false>(
+    return vec ? launch_cs_xcd_k<T, NT, true, SRC, UNR, false, false>(
                      grid, lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy,
                      status)
-               : launch_cs_xcd_k<T, NT, false, CODES, UNR, false, false>(
+               : launch_cs_xcd_k<T, NT, false, SRC, UNR, false, false>(
                      grid, lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy,
                      status);
-  return vec ? launch_cs_xcd_k<T, NT, true, CODES, UNR, true, false>(
+  return vec ? launch_cs_xcd_k<T, NT, true, SRC, UNR, true, false>(
                    grid, lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy,
                    status)
-             : launch_cs_xcd_k<T, NT, false, CODES, UNR, true, false>(
+             : launch_cs_xcd_k<T, NT, false, SRC, UNR, true, false>(
                    grid, lds, st, d, c, code, h, s, k, ktile, nct, nbt, xcds, spx, rpx, Y, ldy,
                    status);
 }
 
-template <typename T, int NT, bool CODES>
+template <typename T, int NT, int SRC>
 static hipError_t launch_cs_lds_v(bool vec, dim3 grid, size_t lds, hipStream_t st, int64_t d,
                                   const Cols<T> &c, const uint32_t *code, const int32_t *h,
                                   const int8_t *s, int64_t k, int64_t ktile, int64_t rows, T *Y,
                                   int64_t ldy, int *status) {
-  const void *fn = vec ? (const void *)k_cs_lds<T, NT, true, CODES>
-                       : (const void *)k_cs_lds<T, NT, false, CODES>;
+  const void *fn = vec ? (const void *)k_cs_lds<T, NT, true, SRC>
+                       : (const void *)k_cs_lds<T, NT, false, SRC>;
   hipError_t e = allow_dynamic_lds(fn, (int)lds);
   if (e != hipSuccess) return e;
   if (vec)
-    hipLaunchKernelGGL((k_cs_lds<T, NT, true, CODES>), grid, dim3(1024), lds, st, d, c, code, h, s,
+    hipLaunchKernelGGL((k_cs_lds<T, NT, true, SRC>), grid, dim3(1024), lds, st, d, c, code, h, s,
                        k, ktile, rows, Y, ldy, status);
   else
-    hipLaunchKernelGGL((k_cs_lds<T, NT, false, CODES>), grid, dim3(1024), lds, st, d, c, code, h,
+    hipLaunchKernelGGL((k_cs_lds<T, NT, false, SRC>), grid, dim3(1024), lds, st, d, c, code, h,
                        s, k, ktile, rows, Y, ldy, status);
   return hipGetLastError();
 }
@@ -966,11 +989,31 @@ static hipError_t launch_cs_lds_nt(bool vec, dim3 grid, size_t lds, hipStream_t 
                                    const Cols<T> &c, const uint32_t *code, const int32_t *h,
                                    const int8_t *s, int64_t k, int64_t ktile, int64_t rows, T *Y,
                                    int64_t ldy, int *status) {
+  if (c.hashed) return hipErrorNotSupported;  // the persistent schedule only
   if (code)
-    return launch_cs_lds_v<T, NT, true>(vec, grid, lds, st, d, c, code, h, s, k, ktile, rows, Y,
+    return launch_cs_lds_v<T, NT, kSrcCode>(vec, grid, lds, st, d, c, code, h, s, k, ktile, rows,
+                                            Y, ldy, status);
+  return launch_cs_lds_v<T, NT, kSrcHS>(vec, grid, lds, st, d, c, code, h, s, k, ktile, rows, Y,
                                         ldy, status);
-  return launch_cs_lds_v<T, NT, false>(vec, grid, lds, st, d, c, code, h, s, k, ktile, rows, Y,
-                                       ldy, status);
+}
+
+// h and s of the hash-generated sketch, materialised (rows i of [0, d)).
+__global__ void k_hash_sketch(int64_t d, int64_t k, uint64_t key, int32_t *__restrict__ h,
+                              int8_t *__restrict__ s) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < d;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t w = hash_word(key, i, k);
+    h[i] = (int32_t)(w & kIdxMask);
+    s[i] = (w & kSignBit) ? (int8_t)-1 : (int8_t)1;
+  }
+}
+
+hipError_t launch_hash_sketch(int64_t d, int64_t k, uint64_t key, int32_t *h, int8_t *s,
+                              hipStream_t st) {
+  if (d <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)std::min<int64_t>((d + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_hash_sketch, dim3(blocks), dim3(256), 0, st, d, k, key, h, s);
+  return hipGetLastError();
 }
 
 // LDS CountSketch.  Default: the persistent die-aware schedule; the earlier
@@ -1029,12 +1072,15 @@ hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t 
                 : nullptr;
 #define MS_XCD_CASE(NT_)                                                                         \
   if (nt == NT_)                                                                                 \
-    return code ? launch_cs_xcd_v<T, NT_, true>(vec, grid, lds, st, d, c, code, h, s, k, ktile,   \
-                                                (int)nct, (int)nbt, xcds, spx, rpx, Y, ldy, pb,  \
-                                                status)                                          \
-                : launch_cs_xcd_v<T, NT_, false>(vec, grid, lds, st, d, c, code, h, s, k, ktile,  \
-                                                 (int)nct, (int)nbt, xcds, spx, rpx, Y, ldy, pb, \
-                                                 status);
+    return c.hashed ? launch_cs_xcd_v<T, NT_, kSrcHash>(vec, grid, lds, st, d, c, code, h, s, k,  \
+                                                        ktile, (int)nct, (int)nbt, xcds, spx,    \
+                                                        rpx, Y, ldy, pb, status)                 \
+           : code   ? launch_cs_xcd_v<T, NT_, kSrcCode>(vec, grid, lds, st, d, c, code, h, s, k,  \
+                                                        ktile, (int)nct, (int)nbt, xcds, spx,    \
+                                                        rpx, Y, ldy, pb, status)                 \
+                    : launch_cs_xcd_v<T, NT_, kSrcHS>(vec, grid, lds, st, d, c, code, h, s, k,    \
+                                                      ktile, (int)nct, (int)nbt, xcds, spx, rpx, \
+                                                      Y, ldy, pb, status);
     MS_XCD_CASE(8)
     MS_XCD_CASE(4)
     MS_XCD_CASE(2)

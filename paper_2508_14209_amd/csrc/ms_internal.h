@@ -92,6 +92,10 @@ struct Cols {
   int64_t ldb;
   int n_a;
   int ncols;
+  // the hash-generated sketch: rows' buckets and signs come from (key, row)
+  // instead of stored vectors (LDS CountSketch only)
+  int hashed = 0;
+  uint64_t key = 0;
 };
 
 // countsketch.hip
@@ -128,6 +132,9 @@ hipError_t launch_cs_lds(int64_t d, int64_t k, const Cols<T> &c, const uint32_t 
                          const int32_t *h, const int8_t *s, T *Y, int64_t ldy, bool zero_first,
                          int *status, hipStream_t st, const CsTuning *tune = nullptr,
                          void *part = nullptr, size_t part_bytes = 0);
+// h and s of the hash-generated sketch with key `key` (see hash_word).
+hipError_t launch_hash_sketch(int64_t d, int64_t k, uint64_t key, int32_t *h, int8_t *s,
+                              hipStream_t st);
 // Bytes of the optional per-die partial buffer of launch_cs_lds (0 when the
 // per-die partial schedule does not pay for this shape); wd = element bytes.
 size_t cs_part_bytes(int64_t d, int64_t k, int64_t ncols, int64_t wd);
