@@ -77,6 +77,7 @@ def _load():
                                            _p, _i64, _p, _i64, _p, _i64],
             "or_splitmix64": [ctypes.c_uint64, _i64, _p],
             "or_hash_sketch": [_i64, _i64, ctypes.c_uint64, _p, _p],
+            "or_srht": [_i64, _i64, _i64, _p, _i64, _p, _p, _p, _i64],
         }
         for name, args in sig.items():
             fn = getattr(lib, name)
@@ -389,6 +390,48 @@ def countsketch_hashed(A, k: int, seed: int, acc: str | None = None) -> np.ndarr
     A = np.asarray(A)
     h, s = hash_sketch(A.shape[0], k, seed)
     return countsketch(A, h, s, k, acc=acc)
+
+
+# --------------------------------------------------------------------------
+# SRHT (Sec. 5) and the Count + SRHT multisketch (Sec. 8, future work)
+# --------------------------------------------------------------------------
+
+def srht(X, dsign, r) -> np.ndarray:
+    """Y = k^{-1/2} P H_m D X (k x ncols, FP64) by the SRHT's definition:
+    H_m[a][b] = (-1)^popcount(a & b), m = the smallest power of two >= the
+    rows of X (zero rows appended), D = diag(dsign) (+-1, one per row of X),
+    P taking rows r (k int32 in [0, m)) of H_m D X."""
+    X = _fortran(X, np.float64)
+    if X.ndim == 1:
+        X = X.reshape(-1, 1, order="F")
+    mx, nc = X.shape
+    dsign = np.ascontiguousarray(dsign, dtype=np.int8)
+    r = np.ascontiguousarray(r, dtype=np.int32)
+    k = r.shape[0]
+    Y = np.zeros((k, nc), dtype=np.float64, order="F")
+    _check(_load().or_srht(mx, nc, k, _ptr(X), _ld(X), _ptr(dsign), _ptr(r), _ptr(Y),
+                           max(1, k)), "srht")
+    return Y
+
+
+def count_srht_sketch(A, h, s, k1: int, dsign, r, acc: str | None = None) -> np.ndarray:
+    """The Count + SRHT multisketch S2 (C A): the CountSketch of A (k1
+    buckets, A's precision) followed by the SRHT (FP64) of its k1 rows."""
+    Y = countsketch(A, h, s, k1, acc=acc)
+    return srht(np.asarray(Y, dtype=np.float64), dsign, r)
+
+
+def count_srht_lstsq(A, B, h, s, k1: int, dsign, r):
+    """Alg. 1 with the Count + SRHT multisketch as S: Z = S [A | B] (C in A's
+    precision, the SRHT and the QR least squares in FP64).  Returns X."""
+    A = np.asarray(A)
+    B = np.asarray(B)
+    if B.ndim == 1:
+        B = B[:, None]
+    n = A.shape[1]
+    AB = np.asfortranarray(np.concatenate([A, B.astype(A.dtype)], axis=1))
+    Z = count_srht_sketch(AB, h, s, k1, dsign, r)
+    return qr_solve(Z[:, :n], Z[:, n:])
 
 
 def round_bf16(x) -> np.ndarray:

@@ -584,3 +584,46 @@ int or_hash_sketch(int64_t d, int64_t k, uint64_t seed, int32_t *h, int8_t *s) {
   return ORACLE_OK;
 }
 
+/* ------------------------------------------------------------------------
+ * SRHT (Sec. 5, its definition): S = k^{-1/2} P H_m D with H_m the Hadamard
+ * matrix of the recursive definition, whose entries are
+ *   H_m[a][b] = (-1)^{popcount(a AND b)}
+ * (the block rule [[H, H], [H, -H]] adds one bit to both indices, and the
+ * sign flips exactly when both new bits are 1), D = diag(dsign) and P
+ * taking rows r_0 .. r_{k-1} of H_m D X.  m is the smallest power of two
+ * >= the row count mx of X, which is padded with zero rows (the definition
+ * needs log2 m integral).  Each output is that sum written out, accumulated
+ * in long double, then scaled and rounded once:
+ *   Y[j][c] = k^{-1/2} sum_{i < mx} (-1)^{popcount(r_j AND i)} dsign_i X[i][c].
+ * ------------------------------------------------------------------------ */
+static int or_parity64(uint64_t v) {
+  int p = 0;
+  while (v) {
+    p ^= 1;
+    v &= v - 1;
+  }
+  return p;
+}
+
+int or_srht(int64_t mx, int64_t ncols, int64_t k, const double *X, int64_t ldx,
+            const int8_t *dsign, const int32_t *r, double *Y, int64_t ldy) {
+  if (mx < 1 || ncols < 0 || k < 1 || ldx < mx || ldy < k) return ORACLE_ERR_ARG;
+  int64_t m = 1;
+  while (m < mx) m *= 2;
+  for (int64_t i = 0; i < mx; ++i)
+    if (dsign[i] != 1 && dsign[i] != -1) return ORACLE_ERR_RANGE;
+  for (int64_t j = 0; j < k; ++j)
+    if (r[j] < 0 || r[j] >= m) return ORACLE_ERR_RANGE;
+  const long double scale = 1.0L / sqrtl((long double)k);
+  for (int64_t c = 0; c < ncols; ++c)
+    for (int64_t j = 0; j < k; ++j) {
+      long double acc = 0.0L;
+      for (int64_t i = 0; i < mx; ++i) {
+        const long double v = (long double)dsign[i] * (long double)X[i + c * ldx];
+        acc = or_parity64((uint64_t)r[j] & (uint64_t)i) ? acc - v : acc + v;
+      }
+      Y[j + c * ldy] = (double)(acc * scale);
+    }
+  return ORACLE_OK;
+}
+

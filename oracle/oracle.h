@@ -60,4 +60,7 @@ int or_rand_cholqr_from_sketch(int64_t d, int64_t n, int64_t nrhs, int64_t m,
 void or_splitmix64(uint64_t seed, int64_t count, uint64_t *out);
 int or_hash_sketch(int64_t d, int64_t k, uint64_t seed, int32_t *h, int8_t *s);
 
+int or_srht(int64_t mx, int64_t ncols, int64_t k, const double *X, int64_t ldx,
+            const int8_t *dsign, const int32_t *r, double *Y, int64_t ldy);
+
 #endif

@@ -59,6 +59,12 @@ MUTANTS = [
      "z = (z ^ (z >> 31)) * UINT64_C(0xBF58476D1CE4E5B9);", 0),
     ("hash_bucket_low_bits", "h[i] = (int32_t)(((u >> 32) * (uint64_t)k) >> 32);",
      "h[i] = (int32_t)(((u & 0xffffffffu) * (uint64_t)k) >> 32);", 0),
+    ("srht_sign_from_or", "acc = or_parity64((uint64_t)r[j] & (uint64_t)i) ? acc - v : acc + v;",
+     "acc = or_parity64((uint64_t)r[j] | (uint64_t)i) ? acc - v : acc + v;", 0),
+    ("srht_dsign_dropped", "const long double v = (long double)dsign[i] * (long double)X[i + c * ldx];",
+     "const long double v = (long double)X[i + c * ldx];", 0),
+    ("srht_scale_one_over_k", "const long double scale = 1.0L / sqrtl((long double)k);",
+     "const long double scale = 1.0L / (long double)k;", 0),
     ("hash_row_off_by_one", "or_mix64(seed + (uint64_t)(i + 1) * UINT64_C(0x9E3779B97F4A7C15));",
      "or_mix64(seed + (uint64_t)i * UINT64_C(0x9E3779B97F4A7C15));", 0),
 ]
@@ -90,7 +96,8 @@ def _run_mutant(args):
                         os.path.join(ROOT, "tests", "test_oracle_countsketch.py"),
                         os.path.join(ROOT, "tests", "test_oracle_solve.py"),
                         os.path.join(ROOT, "tests", "test_oracle_rcq.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_hash.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_hash.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_srht.py")],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     return name, r.returncode, r.stdout[-600:]
 
