@@ -101,6 +101,8 @@ typedef struct {
 #define MS_OP_RAND_CHOLQR 6
 #define MS_OP_NORMAL_EQUATIONS 7
 #define MS_OP_COUNTSKETCH_HASHED 8
+#define MS_OP_SRHT 9
+#define MS_OP_COUNT_SRHT_LSTSQ 10
 
 /*
  * Bytes of workspace the operation needs (a multiple of 256, at least 256).
@@ -305,6 +307,44 @@ ms_status countsketch_hashed(int64_t d, int64_t n, int64_t k, uint64_t seed,
  */
 ms_status ms_hash_sketch(int64_t d, int64_t k, uint64_t seed, int32_t *h,
                          int8_t *s, void *stream);
+
+/*
+ * SRHT (Sec. 5): Y = k^{-1/2} P H_m D X, with H_m the Hadamard matrix of the
+ * recursive definition (entries (-1)^popcount(a AND b)), m the smallest power
+ * of two >= the m rows of X (X padded with zero rows; the definition needs
+ * log2 m integral), D = diag(dsign) and P taking rows r[0..k-1] of H_m D X.
+ *   X: m x ncols (x_dtype MS_F64 or MS_F32, column-major, ldx >= m);
+ *   dsign: m int8, each +1 or -1; r: k int32, each in [0, padded m) (rows may
+ *   repeat: P samples with replacement); Y: k x ncols FP64 (ldy >= k),
+ *   overwritten.  1 <= m <= 2^31 - 2, ncols <= 65535, 1 <= k <= 2^24.
+ * Device status MS_ERR_RANGE for a sign not +-1 or a row index out of range
+ * (the offending entries then contribute zero).  One pass over X; the sum
+ * over 8192-row blocks is taken in block order (repeatable bits).
+ * ws: ms_workspace_size(MS_OP_SRHT, m, ncols, 0, k, 0, x_dtype, 0, NULL).
+ */
+ms_status srht_apply(int64_t m, int64_t ncols, int64_t k, ms_dtype x_dtype,
+                     const void *X, int64_t ldx, const int8_t *dsign,
+                     const int32_t *r, double *Y, int64_t ldy, void *ws,
+                     size_t ws_bytes, void *stream);
+
+/*
+ * Sketch-and-solve (Alg. 1) with the Count + SRHT multisketch (Sec. 8 names
+ * it future work): Z = S2 (C [A | B]) with C the CountSketch (h, s; k1
+ * buckets, accumulated in A's precision as in sketch_lstsq) and S2 the SRHT
+ * of its k1 rows (dsign: k1 int8; r: k2 int32 in [0, padded k1)), in FP64;
+ * then the Householder QR of Z's first n columns and X = R^{-1} (Q^T Z_B).
+ *   Other arguments as for sketch_lstsq; k2 >= n; opts->refine_steps must
+ *   be 0.  Device status as for sketch_lstsq and srht_apply.
+ * ws: ms_workspace_size(MS_OP_COUNT_SRHT_LSTSQ, d, n, nrhs, k1, k2, a_dtype,
+ * 0, opts) bytes.
+ */
+ms_status count_srht_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k1,
+                           int64_t k2, ms_dtype a_dtype, const void *A,
+                           int64_t lda, const void *B, int64_t ldb,
+                           const int32_t *h, const int8_t *s,
+                           const int8_t *dsign, const int32_t *r, double *X,
+                           int64_t ldx, const ms_opts *opts, void *ws,
+                           size_t ws_bytes, void *stream);
 
 /*
  * Least squares by the normal equations (Sec. 6.3: the deterministic solver

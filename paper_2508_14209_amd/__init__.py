@@ -24,7 +24,8 @@ __all__ = [
     "empty_colmajor", "colmajor", "workspace", "workspace_size", "check_status",
     "bucket_plan", "pack_sketch", "countsketch_accumulate", "countsketch_apply",
     "gaussian_apply", "multisketch_apply", "qr_solve", "sketch_lstsq", "rand_cholqr_lstsq",
-    "normal_equations_lstsq", "countsketch_hashed", "hash_sketch", "MsProblem",
+    "normal_equations_lstsq", "countsketch_hashed", "hash_sketch", "srht_apply",
+    "count_srht_lstsq", "MsProblem",
     "batch_workspace_size", "sketch_lstsq_batched", "batch_status", "BatchRunner",
 ]
 
@@ -37,7 +38,8 @@ MS_F64, MS_F32, MS_BF16 = 0, 1, 2
 MODES = {"auto": 0, "atomic": 1, "lds": 2, "sorted": 3}
 OPS = {"bucket_plan": 0, "countsketch": 1, "gaussian": 2, "multisketch": 3,
        "qr_solve": 4, "lstsq": 5, "rand_cholqr": 6,
-       "normal_equations": 7, "countsketch_hashed": 8}
+       "normal_equations": 7, "countsketch_hashed": 8, "srht": 9,
+       "count_srht_lstsq": 10}
 MS_SORTED_MAX_SEGMENT = 16384
 
 if not os.path.exists(LIB_PATH):
@@ -91,6 +93,9 @@ _SIGS = {
     "countsketch_hashed": ([_i64, _i64, _i64, ctypes.c_uint64, _i32, _p, _i64, _p, _i64, _p, _p,
                             _sz, _p], _i32),
     "ms_hash_sketch": ([_i64, _i64, ctypes.c_uint64, _p, _p, _p], _i32),
+    "srht_apply": ([_i64, _i64, _i64, _i32, _p, _i64, _p, _p, _p, _i64, _p, _sz, _p], _i32),
+    "count_srht_lstsq": ([_i64, _i64, _i64, _i64, _i64, _i32, _p, _i64, _p, _i64, _p, _p, _p, _p,
+                          _p, _i64, _p, _p, _sz, _p], _i32),
     "ms_batch_workspace_size": ([_i32, _p, _i32, _i32, _p], _sz),
     "sketch_lstsq_batched": ([_i32, _p, _p, _i32, _i32, _p, _p, _sz, _p], _i32),
     "ms_batch_status": ([_p, _i32, _p, _p], _i32),
@@ -297,6 +302,60 @@ def hash_sketch(d: int, k: int, seed: int, device="cuda", stream=None):
     _ok(_lib.ms_hash_sketch(d, k, int(seed) & (2**64 - 1), h.data_ptr() if d else None,
                             s.data_ptr() if d else None, _stream(stream)), "ms_hash_sketch")
     return h, s
+
+
+def srht_apply(X: torch.Tensor, dsign: torch.Tensor, r: torch.Tensor,
+               Y: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None):
+    """Y = k^{-1/2} P H_m D X (k x ncols, FP64): the SRHT with D = diag(dsign)
+    and P taking rows r of H_m D X (m = X's rows rounded up to a power of
+    two).  Returns (Y, ws)."""
+    if X.dim() == 1:
+        X = X.unsqueeze(1)
+    m, nc = X.shape
+    k = r.shape[0]
+    x_dt = _dt(X)
+    if Y is None:
+        Y = empty_colmajor(k, nc, torch.float64, X.device)
+    Xp, ldx = colmajor(X, "X")
+    Yp, ldy = colmajor(Y, "Y")
+    need = workspace_size("srht", d=m, n=nc, k=k, a_dtype=x_dt)
+    ws = workspace(need, X.device) if ws is None else ws
+    wp, have = _ws_ptr(ws, need)
+    _ok(_lib.srht_apply(m, nc, k, x_dt, Xp, ldx, _vec(dsign, torch.int8, "dsign"),
+                        _vec(r, torch.int32, "r"), Yp, ldy, wp, have, _stream(stream)),
+        "srht_apply")
+    return Y, ws
+
+
+def count_srht_lstsq(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torch.Tensor,
+                     k1: int, dsign: torch.Tensor, r: torch.Tensor, mode: str = "auto",
+                     X: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None):
+    """Sketch-and-solve with the Count + SRHT multisketch: Z = S2 (C [A | B])
+    (C: h, s, k1 buckets; S2: the SRHT with dsign, r), then QR least
+    squares in FP64.  Returns (X, ws)."""
+    d, n = A.shape
+    if B.dim() == 1:
+        B = B.unsqueeze(1)
+    nrhs = B.shape[1]
+    k2 = r.shape[0]
+    a_dt = _dt(A)
+    if B.dtype != A.dtype:
+        raise ValueError("B must have A's dtype")
+    if X is None:
+        X = empty_colmajor(n, nrhs, torch.float64, A.device)
+    Ap, lda = colmajor(A, "A")
+    Bp, ldb = colmajor(B, "B")
+    Xp, ldx = colmajor(X, "X")
+    need = workspace_size("count_srht_lstsq", d=d, n=n, nrhs=nrhs, k=k1, k2=k2, a_dtype=a_dt,
+                          mode=mode)
+    ws = workspace(need, A.device) if ws is None else ws
+    wp, have = _ws_ptr(ws, need)
+    o = _opts(mode, 0)
+    _ok(_lib.count_srht_lstsq(d, n, nrhs, k1, k2, a_dt, Ap, lda, Bp, ldb,
+                              _vec(h, torch.int32, "h"), _vec(s, torch.int8, "s"),
+                              _vec(dsign, torch.int8, "dsign"), _vec(r, torch.int32, "r"), Xp, ldx,
+                              ctypes.byref(o), wp, have, _stream(stream)), "count_srht_lstsq")
+    return X, ws
 
 
 def gaussian_apply(G: torch.Tensor, Y: torch.Tensor, Z: torch.Tensor | None = None,

@@ -157,6 +157,29 @@ RcqLayout rcq_layout(int64_t d, int64_t n, int64_t k, int64_t k2, ms_dtype a_dty
   return L;
 }
 
+// Count + SRHT multisketch least squares: the CountSketch of [A | B], its
+// SRHT (per-block partials when k1 > 8192), the FP64 sketch and the QR.
+struct CsrLayout {
+  CsLayout cs;
+  size_t y = 0, spart = 0, z64 = 0, qr = 0, fact = 0, tau = 0, total = 0;
+};
+
+CsrLayout csr_layout(int64_t d, int64_t n, int64_t nrhs, int64_t k1, int64_t k2,
+                     ms_dtype a_dtype, int mode) {
+  CsrLayout L;
+  Carve cv;
+  const int64_t nc = n + nrhs;
+  carve_cs(cv, L.cs, d, k1, mode, nc, dtype_size(a_dtype));
+  L.y = cv.take((size_t)k1 * nc * dtype_size(a_dtype));
+  L.spart = cv.take(srht_workspace_bytes(k1, nc, k2));
+  L.z64 = cv.take((size_t)k2 * nc * 8);
+  L.qr = cv.take(qr_workspace_bytes(k2, n, nrhs));
+  L.fact = cv.take((size_t)k2 * n * 8);
+  L.tau = cv.take((size_t)n * 8);
+  L.total = cv.off;
+  return L;
+}
+
 // Normal equations: the fused pass's per-workgroup partials and their sum.
 struct NeLayout {
   size_t part = 0, w = 0, total = 0;
@@ -297,6 +320,11 @@ size_t ms_workspace_size(int op, int64_t d, int64_t n, int64_t nrhs, int64_t k, 
       return rcq_layout(d, n, k, k2, a_dtype, g_dtype, mode).total;
     case MS_OP_NORMAL_EQUATIONS:
       return ne_layout().total;
+    case MS_OP_SRHT:
+      cv.take(srht_workspace_bytes(d, n, k));
+      return cv.off;
+    case MS_OP_COUNT_SRHT_LSTSQ:
+      return csr_layout(d, n, nrhs, k, k2, a_dtype, mode).total;
     case MS_OP_COUNTSKETCH_HASHED: {
       const size_t pb = cs_part_bytes(d, k, n, dtype_size(a_dtype));
       if (pb) cv.take(pb);
@@ -666,6 +694,77 @@ ms_status countsketch_hashed(int64_t d, int64_t n, int64_t k, uint64_t seed, ms_
       e = launch_cs_lds<float>(d, k, c, nullptr, nullptr, nullptr, static_cast<float *>(Y), ldy,
                                false, status, st, &tune, part, pbytes);
   }
+  return from_hip(e);
+}
+
+ms_status srht_apply(int64_t m, int64_t ncols, int64_t k, ms_dtype x_dtype, const void *X,
+                     int64_t ldx, const int8_t *dsign, const int32_t *r, double *Y, int64_t ldy,
+                     void *ws, size_t ws_bytes, void *stream) {
+  if (m < 1 || m > kMax31 || ncols < 0 || ncols > 65535 || k < 1 || k > (1 << 24))
+    return MS_ERR_ARG;
+  if (x_dtype != MS_F64 && x_dtype != MS_F32) return MS_ERR_ARG;
+  if (ldx < m || ldy < k || !ws || (ncols > 0 && (!X || !dsign || !r || !Y))) return MS_ERR_ARG;
+  Carve cv;
+  const size_t pbytes = srht_workspace_bytes(m, ncols, k);
+  void *part = pbytes ? at<void>(ws, cv.take(pbytes)) : nullptr;
+  if (ws_bytes < cv.off) return MS_ERR_NOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  int *status = static_cast<int *>(ws);
+  hipError_t e = launch_zero_status(status, st);
+  if (e == hipSuccess && ncols > 0)
+    e = x_dtype == MS_F64
+            ? launch_srht<double>(m, ncols, k, static_cast<const double *>(X), ldx, dsign, r, Y,
+                                  ldy, part, status, st)
+            : launch_srht<float>(m, ncols, k, static_cast<const float *>(X), ldx, dsign, r, Y, ldy,
+                                 part, status, st);
+  return from_hip(e);
+}
+
+ms_status count_srht_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k1, int64_t k2,
+                           ms_dtype a_dtype, const void *A, int64_t lda, const void *B,
+                           int64_t ldb, const int32_t *h, const int8_t *s, const int8_t *dsign,
+                           const int32_t *r, double *X, int64_t ldx, const ms_opts *opts, void *ws,
+                           size_t ws_bytes, void *stream) {
+  if (d < 1 || n < 1 || nrhs < 1 || k1 < 1 || k1 > kMax31 || k2 < n || k2 > (1 << 24))
+    return MS_ERR_ARG;
+  if (a_dtype != MS_F64 && a_dtype != MS_F32) return MS_ERR_ARG;
+  if (!valid_mode(opts) || (opts && opts->refine_steps != 0)) return MS_ERR_ARG;
+  if (n + nrhs > 65535) return MS_ERR_UNSUPPORTED;
+  const int mode = resolve_mode(opts);
+  if (mode == MS_CS_SORTED && d > kMax31) return MS_ERR_UNSUPPORTED;
+  if (lda < d || ldb < d || ldx < n) return MS_ERR_ARG;
+  if (!A || !B || !h || !s || !dsign || !r || !X || !ws) return MS_ERR_ARG;
+  const CsrLayout L = csr_layout(d, n, nrhs, k1, k2, a_dtype, mode);
+  if (ws_bytes < L.total) return MS_ERR_NOMEM;
+  hipStream_t st = (hipStream_t)stream;
+  int *status = static_cast<int *>(ws);
+  const int64_t nc = n + nrhs;
+  double *z64 = at<double>(ws, L.z64);
+  void *sp = L.spart ? at<void>(ws, L.spart) : nullptr;
+  hipError_t e;
+  // 1. Y = C [A | B] (k1 x nc, A's precision); 2. Z = SRHT(Y) (k2 x nc, FP64)
+  if (a_dtype == MS_F64) {
+    Cols<double> c{static_cast<const double *>(A), lda, static_cast<const double *>(B), ldb,
+                   (int)n, (int)nc};
+    e = run_countsketch<double>(d, k1, c, h, s, at<double>(ws, L.y), k1, mode, ws, L.cs, status,
+                                st, tuning_of(opts));
+    if (e == hipSuccess)
+      e = launch_srht<double>(k1, nc, k2, at<double>(ws, L.y), k1, dsign, r, z64, k2, sp, status,
+                              st);
+  } else {
+    Cols<float> c{static_cast<const float *>(A), lda, static_cast<const float *>(B), ldb, (int)n,
+                  (int)nc};
+    e = run_countsketch<float>(d, k1, c, h, s, at<float>(ws, L.y), k1, mode, ws, L.cs, status, st,
+                               tuning_of(opts));
+    if (e == hipSuccess)
+      e = launch_srht<float>(k1, nc, k2, at<float>(ws, L.y), k1, dsign, r, z64, k2, sp, status,
+                             st);
+  }
+  // 3. Householder QR of Z_A, Q^T Z_B, back substitution (FP64)
+  if (e == hipSuccess)
+    e = launch_qr_solve(k2, n, nrhs, z64, k2, z64 + n * k2, k2, X, ldx, nullptr, 0,
+                        at<double>(ws, L.tau), at<double>(ws, L.fact), at<void>(ws, L.qr), status,
+                        st);
   return from_hip(e);
 }
 

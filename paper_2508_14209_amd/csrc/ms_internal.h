@@ -205,6 +205,16 @@ hipError_t launch_rcq_finish(int n, int nrhs, int nparts, const double *part, do
                              const double *R0, int ldr0, double *X, int64_t ldx, double *R,
                              int64_t ldr, int *status, hipStream_t st);
 
+// SRHT (srht.hip): Y = k^{-1/2} P H_m D X for an mx x ncols X (FP64 or FP32),
+// m = the smallest power of two >= mx; Y k x ncols FP64.  part: the
+// per-block partials (srht_workspace_bytes; none when m <= 8192).
+int64_t srht_padded_rows(int64_t mx);
+size_t srht_workspace_bytes(int64_t mx, int64_t ncols, int64_t k);
+template <typename TX>
+hipError_t launch_srht(int64_t mx, int64_t ncols, int64_t k, const TX *X, int64_t ldx,
+                       const int8_t *dsign, const int32_t *r, double *Y, int64_t ldy, void *part,
+                       int *status, hipStream_t st);
+
 // ---------------------------------------------------------------- batched
 // Item order of a persistent grid that keeps runs of consecutive items on
 // one die: workgroup g runs on die g % dies (the dispatcher's round-robin),

@@ -1,0 +1,231 @@
+// srht.hip -- the SRHT S = k^{-1/2} P H_m D (Sec. 5) of a column-major m x
+// ncols operand X, and through it the second stage of the Count + SRHT
+// multisketch (Sec. 8's future-work variant).
+//
+// H_m (m the smallest power of two >= the rows of X, X padded with zero
+// rows) factors over blocks of B = 8192 rows: H_m = (H_{m/B} (x) I_B)
+// (I_{m/B} (x) H_B).  Row r of H_m D X is therefore
+//   sum over blocks q of (-1)^{popcount((r >> 13) AND q)} (H_B D_q X_q)[r mod B],
+// so one pass over X suffices: each workgroup transforms one block of one
+// column in place (D, then the 13 butterfly stages of H_B), keeps only the k
+// sampled rows with their block sign, and the per-block values are summed
+// over blocks in block order afterwards.  Only the sampled rows leave the
+// workgroup: X is read once and nothing of its size is written.
+//
+// Inside a block each of 256 threads holds 32 elements in registers.  The
+// butterfly stages on the 5 index bits a thread holds run in registers; the
+// 13 bits are covered by three such sets (bits 8-12, 0-4, 5-7) with two
+// exchanges through LDS in between, instead of one LDS round trip per stage
+// as in the stage-by-stage FWHT (Alg. 3 processes two bits per stage).
+// Blocks of fewer than 8192 rows (m < 8192) use a plain stage-by-stage LDS
+// transform.
+#include "ms_internal.h"
+
+namespace ms {
+
+namespace {
+
+constexpr int kLogB = 13;
+constexpr int kB = 1 << kLogB;
+constexpr int kThreads = 256;      // 32 elements per thread
+constexpr int kPer = kB / kThreads;
+
+// LDS slot of block element e: one pad slot per 32 elements keeps the three
+// exchange patterns free of bank conflicts beyond the 64-bit pairs
+__device__ __forceinline__ int pad(int e) { return e + (e >> 5); }
+
+__device__ __forceinline__ double block_sign(int64_t r, int64_t q) {
+  return (__popcll((uint64_t)(r >> kLogB) & (uint64_t)q) & 1) ? -1.0 : 1.0;
+}
+
+// butterflies of the stages on the register-index bits in [lo, lo + nb)
+template <int LO, int NB>
+__device__ __forceinline__ void reg_stages(double (&x)[kPer]) {
+#pragma unroll
+  for (int b = LO; b < LO + NB; ++b)
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+      if (!(u & (1 << b))) {
+        const double a = x[u], c = x[u | (1 << b)];
+        x[u] = a + c;
+        x[u | (1 << b)] = a - c;
+      }
+}
+
+// One workgroup per (block q, column c).  out: with one block, Y (scaled);
+// else part[(q ncols + c) k + j] (unscaled, summed by k_srht_reduce).
+template <typename TX>
+__global__ __launch_bounds__(kThreads) void k_srht_block(int64_t mx, int ncols, int k, int nblk,
+                                                         const TX *__restrict__ X, int64_t ldx,
+                                                         const int8_t *__restrict__ dsign,
+                                                         const int32_t *__restrict__ r,
+                                                         int64_t m, double scale,
+                                                         double *__restrict__ out, int64_t ldo,
+                                                         int *status) {
+  __shared__ double lds[kB + kB / 32];
+  const int t = threadIdx.x;
+  const int64_t q = blockIdx.x;
+  const int c = blockIdx.y;
+  const int64_t base = q * kB;
+  const TX *xc = X + (int64_t)c * ldx;
+  double x[kPer];
+  bool bad = false;
+  // element e = t + 256 u: the stages on bits 8..12 are in registers
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int64_t i = base + t + kThreads * u;
+    double v = 0.0;
+    if (i < mx) {
+      const int8_t sg = gload(dsign + i);
+      bad |= !(sg == 1 || sg == -1);
+      const double a = (double)gload(xc + i);
+      v = sg < 0 ? -a : a;
+    }
+    x[u] = v;
+  }
+  reg_stages<0, 5>(x);
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) lds[pad(t + kThreads * u)] = x[u];
+  __syncthreads();
+  // e = 32 t + u: bits 0..4
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) x[u] = lds[pad(32 * t + u)];
+  reg_stages<0, 5>(x);
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) lds[pad(32 * t + u)] = x[u];
+  __syncthreads();
+  // e = (t & 31) | (u & 7) << 5 | (t >> 5) << 8 | (u >> 3) << 11: bits 5..7
+  auto e3 = [&](int u) { return (t & 31) | ((u & 7) << 5) | ((t >> 5) << 8) | ((u >> 3) << 11); };
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) x[u] = lds[pad(e3(u))];
+  reg_stages<0, 3>(x);
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) lds[pad(e3(u))] = x[u];
+  __syncthreads();
+  // the sampled rows of this block's share
+  for (int j = t; j < k; j += kThreads) {
+    const int32_t rj = gload(r + j);
+    const bool ok = rj >= 0 && (int64_t)rj < m;
+    bad |= !ok;
+    const double v = ok ? block_sign(rj, q) * lds[pad(rj & (kB - 1))] : 0.0;
+    if (nblk == 1)
+      out[j + (int64_t)c * ldo] = v * scale;
+    else
+      out[((int64_t)q * ncols + c) * k + j] = v;
+  }
+  if (bad) record_status(status, MS_ERR_RANGE);
+}
+
+// m < 8192: one workgroup per column, the whole transform in LDS, one
+// butterfly stage at a time.
+template <typename TX>
+__global__ __launch_bounds__(kThreads) void k_srht_small(int64_t mx, int logm, int k,
+                                                         const TX *__restrict__ X, int64_t ldx,
+                                                         const int8_t *__restrict__ dsign,
+                                                         const int32_t *__restrict__ r,
+                                                         double scale, double *__restrict__ Y,
+                                                         int64_t ldy, int *status) {
+  __shared__ double lds[kB];
+  const int t = threadIdx.x;
+  const int c = blockIdx.x;
+  const int m = 1 << logm;
+  const TX *xc = X + (int64_t)c * ldx;
+  bool bad = false;
+  for (int i = t; i < m; i += kThreads) {
+    double v = 0.0;
+    if (i < mx) {
+      const int8_t sg = gload(dsign + i);
+      bad |= !(sg == 1 || sg == -1);
+      const double a = (double)gload(xc + i);
+      v = sg < 0 ? -a : a;
+    }
+    lds[i] = v;
+  }
+  __syncthreads();
+  for (int b = 0; b < logm; ++b) {
+    for (int p = t; p < m / 2; p += kThreads) {
+      const int i0 = ((p >> b) << (b + 1)) | (p & ((1 << b) - 1));
+      const int i1 = i0 | (1 << b);
+      const double a = lds[i0], cc = lds[i1];
+      lds[i0] = a + cc;
+      lds[i1] = a - cc;
+    }
+    __syncthreads();
+  }
+  for (int j = t; j < k; j += kThreads) {
+    const int32_t rj = gload(r + j);
+    const bool ok = rj >= 0 && rj < m;
+    bad |= !ok;
+    Y[j + (int64_t)c * ldy] = ok ? lds[rj] * scale : 0.0;
+  }
+  if (bad) record_status(status, MS_ERR_RANGE);
+}
+
+// Y[j][c] = scale * sum over blocks q (ascending) of part[(q ncols + c) k + j].
+__global__ void k_srht_reduce(int ncols, int k, int nblk, const double *__restrict__ part,
+                              double scale, double *__restrict__ Y, int64_t ldy) {
+  const int64_t total = (int64_t)ncols * k;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e % k), c = (int)(e / k);
+    double s = 0.0;
+    for (int q = 0; q < nblk; ++q) s += part[((int64_t)q * ncols + c) * k + j];
+    Y[j + (int64_t)c * ldy] = s * scale;
+  }
+}
+
+}  // namespace
+
+int64_t srht_padded_rows(int64_t mx) {
+  int64_t m = 1;
+  while (m < mx) m *= 2;
+  return m;
+}
+
+size_t srht_workspace_bytes(int64_t mx, int64_t ncols, int64_t k) {
+  const int64_t m = srht_padded_rows(mx);
+  const int64_t nblk = m > kB ? m / kB : 1;
+  return nblk > 1 ? (size_t)nblk * ncols * k * 8 : 0;
+}
+
+template <typename TX>
+hipError_t launch_srht(int64_t mx, int64_t ncols, int64_t k, const TX *X, int64_t ldx,
+                       const int8_t *dsign, const int32_t *r, double *Y, int64_t ldy, void *part,
+                       int *status, hipStream_t st) {
+  if (mx < 1 || ncols < 1 || k < 1) return hipSuccess;
+  if (ncols > 65535) return hipErrorInvalidValue;
+  const int64_t m = srht_padded_rows(mx);
+  const double scale = 1.0 / sqrt((double)k);
+  if (m < kB) {
+    int logm = 0;
+    while ((int64_t)1 << logm < m) ++logm;
+    hipLaunchKernelGGL((k_srht_small<TX>), dim3((unsigned)ncols), dim3(kThreads), 0, st, mx, logm,
+                       (int)k, X, ldx, dsign, r, scale, Y, ldy, status);
+    return hipGetLastError();
+  }
+  const int64_t nblk = m / kB;
+  if (nblk == 1) {
+    hipLaunchKernelGGL((k_srht_block<TX>), dim3(1, (unsigned)ncols), dim3(kThreads), 0, st, mx,
+                       (int)ncols, (int)k, 1, X, ldx, dsign, r, m, scale, Y, ldy, status);
+    return hipGetLastError();
+  }
+  if (!part) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_srht_block<TX>), dim3((unsigned)nblk, (unsigned)ncols), dim3(kThreads), 0,
+                     st, mx, (int)ncols, (int)k, (int)nblk, X, ldx, dsign, r, m, scale,
+                     static_cast<double *>(part), (int64_t)0, status);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = ncols * k;
+  const unsigned rb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_srht_reduce, dim3(rb), dim3(256), 0, st, (int)ncols, (int)k, (int)nblk,
+                     static_cast<const double *>(part), scale, Y, ldy);
+  return hipGetLastError();
+}
+template hipError_t launch_srht<double>(int64_t, int64_t, int64_t, const double *, int64_t,
+                                        const int8_t *, const int32_t *, double *, int64_t, void *,
+                                        int *, hipStream_t);
+template hipError_t launch_srht<float>(int64_t, int64_t, int64_t, const float *, int64_t,
+                                       const int8_t *, const int32_t *, double *, int64_t, void *,
+                                       int *, hipStream_t);
+
+}  // namespace ms
