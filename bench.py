@@ -64,7 +64,7 @@ def parse():
                     choices=["countsketch", "countsketch_f32_k32768", "countsketch_f32_k131072",
                              "copy", "gaussian_f64", "gaussian_bf16", "batched_mixed",
                              "solve_fp32", "solve_mixed", "rand_cholqr",
-                             "normal_equations", "countsketch_hashed"],
+                             "normal_equations", "countsketch_hashed", "srht"],
                     help="profiling runs: launch only the LDS CountSketch of [A | b] (--steps "
                          "times), only a plain device copy of 1 GiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters), or only the Gaussian stage of the "
@@ -377,6 +377,55 @@ def hashed_leg(ms, torch, seed, dev, reps=20):
     return out
 
 
+def srht_leg(ms, torch, np, A, B, h, s, G, k, mode, X_ss, seed, reps=10):
+    """The SRHT (Sec. 5) of the headline A (k = 2n rows, the paper's choice)
+    against the CountSketch of the same A, and sketch-and-solve with the
+    Count + SRHT multisketch against the Count + Gaussian one (same C,
+    k2 = 2n), on the same problem."""
+    d, n = A.shape
+    k2 = G.shape[0]
+    gen = torch.Generator(device=A.device)
+    gen.manual_seed(seed)
+    dsign = (torch.randint(0, 2, (d,), generator=gen, device=A.device, dtype=torch.int8) * 2 - 1)
+    r = torch.randint(0, d, (2 * n,), generator=gen, device=A.device, dtype=torch.int32)
+    Y, sws = ms.srht_apply(A, dsign, r)
+
+    def timed(fn, nrep=reps):
+        for _ in range(3):
+            fn()
+        a, b = event_pair(torch)
+        a.record()
+        for _ in range(nrep):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / nrep * 1e3  # us
+
+    t_srht = timed(lambda: ms.srht_apply(A, dsign, r, Y=Y, ws=sws))
+    ms.check_status(sws)
+    bytes_srht = d * n * 8 + d + 2 * n * 4 + 2 * n * n * 8
+    k1 = k
+    m1 = 1 << (k1 - 1).bit_length()
+    ds2 = (torch.randint(0, 2, (k1,), generator=gen, device=A.device, dtype=torch.int8) * 2 - 1)
+    r2 = torch.randint(0, m1, (k2,), generator=gen, device=A.device, dtype=torch.int32)
+    Xs, cws = ms.count_srht_lstsq(A, B, h, s, k1, ds2, r2, mode=mode)
+    t_cs = timed(lambda: ms.count_srht_lstsq(A, B, h, s, k1, ds2, r2, mode=mode, X=Xs, ws=cws))
+    ms.check_status(cws)
+    Xg, gws = ms.sketch_lstsq(A, B, h, s, G, k, mode=mode)
+    t_cg = timed(lambda: ms.sketch_lstsq(A, B, h, s, G, k, mode=mode, X=Xg, ws=gws))
+    Xo, _, ows = ms.rand_cholqr_lstsq(A, B, h, s, G, k)  # the optimum (its residual)
+    ms.check_status(ows)
+    ropt = float(torch.linalg.norm(B - A @ Xo))
+    return {"srht_4194304x64_k128": {"avg_us": t_srht, "algorithmic_bytes": bytes_srht,
+                                     "GBps": bytes_srht / (t_srht * 1e-6) / 1e9,
+                                     "pct_hbm_peak": 100.0 * bytes_srht / (t_srht * 1e-6) / 1e9
+                                     / HBM_PEAK_GBPS},
+            "count_srht_lstsq": {"avg_us": t_cs, "solves_per_s": 1e6 / t_cs,
+                                 "rho": float(torch.linalg.norm(B - A @ Xs)) / ropt},
+            "count_gaussian_lstsq": {"avg_us": t_cg, "solves_per_s": 1e6 / t_cg,
+                                     "rho": float(torch.linalg.norm(B - A @ Xg)) / ropt}}
+
+
 def other_configs_leg(ms, torch, np, seed, dev, reps=10, only=None):
     """The FP32 and mixed-precision least-squares workloads: full solves
     (sketch_lstsq) and their CountSketch kernel alone, inputs generated on
@@ -491,6 +540,21 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"only": "copy", "bytes_read_per_launch": nbytes,
                           "bytes_written_per_launch": nbytes, "launches": args.steps}))
+        return
+    if args.only == "srht":
+        # the SRHT of A 4,194,304 x 64 FP64 (k = 128 sampled rows) alone
+        d_, n_, k_ = 4194304, 64, 128
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(args.seed)
+        Ax = torch.randn((n_, d_), generator=gen, device=dev, dtype=torch.float64).t()
+        dx = (torch.randint(0, 2, (d_,), generator=gen, device=dev, dtype=torch.int8) * 2 - 1)
+        rx = torch.randint(0, d_, (k_,), generator=gen, device=dev, dtype=torch.int32)
+        Yx, sws = ms.srht_apply(Ax, dx, rx)
+        for _ in range(args.steps):
+            ms.srht_apply(Ax, dx, rx, Y=Yx, ws=sws)
+        ms.check_status(sws)
+        print(json.dumps({"only": args.only, "kernel": "k_srht_block", "launches": args.steps + 1,
+                          "bytes_per_launch": d_ * n_ * 8 + d_ + k_ * 4 + k_ * n_ * 8}))
         return
     if args.only == "countsketch_hashed":
         # the hash-generated CountSketch of A 16,777,216 x 8 FP32 (k = 128) alone
@@ -687,6 +751,12 @@ def main():
     except Exception as e:  # reported in the line, not hidden
         rcq = {"error": repr(e)}
 
+    # ---- SRHT and the Count + SRHT multisketch on the same problem
+    try:
+        srht = srht_leg(ms, torch, np, Ad, Bd, hd, sd, Gd, k, args.mode, X, seed + 3)
+    except Exception as e:
+        srht = {"error": repr(e)}
+
     # ---- CPU baseline: the oracle on this host, same arrays
     cpu = None
     if args.cpu_seconds > 0:
@@ -732,6 +802,7 @@ def main():
                      "frac": cs_gbps / HBM_PEAK_GBPS, "traffic": measured_traffic()},
         "cpu_baseline": cpu,
         "rand_cholqr": rcq,
+        "srht": srht,
     }
     # beyond the headline: the serving loop and the batched mixed-precision
     # solver against the plain FP64 one (each leg reports its own error)

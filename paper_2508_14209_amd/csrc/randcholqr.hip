@@ -37,6 +37,13 @@ struct Four<float> {
   typedef fvec4e type;
 };
 
+// Rows row .. row + 3 of the column at p (all inside the column), FP64.
+template <typename T>
+__device__ __forceinline__ v4d load_rows4_full(const T *p, int64_t row) {
+  const typename Four<T>::type x = gload((const typename Four<T>::type *)(p + row));
+  return v4d{(double)x[0], (double)x[1], (double)x[2], (double)x[3]};
+}
+
 // Rows row .. row + 3 of the column at p (zero past row d, or for p null),
 // promoted to FP64.
 template <typename T>
@@ -171,12 +178,29 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_rcq_gram(int64_t d, int n, 
     vcol[ct] = c < n ? A + (int64_t)c * lda : (c - n < nrhs ? B + (int64_t)(c - n) * ldb : nullptr);
   }
   const TA *const zcol = NZ > 0 ? B + (int64_t)zc0 * ldb : nullptr;
+  // Full slabs (all 16 rows inside A) load without any branch: a load
+  // behind a per-lane branch is waited for at the branch's end, which
+  // serialises the slab's loads.  A lane without a column reads A's first
+  // column and masks the value; only the last, ragged slab takes the
+  // guarded path.
+  const int64_t nfull = d >> 4;
   for (int64_t sl = (int64_t)blockIdx.x * kGramWaves + wave; PLAIN && sl < nslab; sl += stride) {
     const int64_t rr = sl * 16 + 4 * lk;
     v4d q[NCT];
+    v4d zb = v4d{0.0, 0.0, 0.0, 0.0};
+    if (sl < nfull) {
 #pragma unroll
-    for (int ct = 0; ct < NCT; ++ct) q[ct] = load_rows4(vcol[ct], rr, d);
-    v4d zb = NZ > 0 && nx > 0 ? load_rows4(zcol, rr, d) : v4d{0.0, 0.0, 0.0, 0.0};
+      for (int ct = 0; ct < NCT; ++ct) q[ct] = load_rows4_full(vcol[ct] ? vcol[ct] : A, rr);
+      if (NZ > 0) zb = load_rows4_full(zcol, rr);
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct)
+        if (!vcol[ct]) q[ct] = v4d{0.0, 0.0, 0.0, 0.0};
+      if (NZ > 0 && nx <= 0) zb = v4d{0.0, 0.0, 0.0, 0.0};
+    } else {
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) q[ct] = load_rows4(vcol[ct], rr, d);
+      if (NZ > 0 && nx > 0) zb = load_rows4(zcol, rr, d);
+    }
     int u = 0;
 #pragma unroll
     for (int it = 0; it < NTI; ++it)
@@ -190,34 +214,75 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_rcq_gram(int64_t d, int n, 
 #pragma unroll
         for (int r = 0; r < 4; ++r) z[it][0] += q[it][r] * zb[r];
   }
+  // B columns of this lane in the tiles NTI - 1 .. (clamped into [0, nrhs))
+  const TA *fbcol[NB];
+  bool fbok[NB];
+#pragma unroll
+  for (int e = 0; e < NB; ++e) {
+    const int c = 16 * (NTI - 1 + e) + li - n;
+    fbok[e] = c >= 0 && c < nrhs;
+    fbcol[e] = B + (int64_t)(c < 0 ? 0 : (c < nrhs ? c : nrhs - 1)) * ldb;
+  }
   for (int64_t sl = (int64_t)blockIdx.x * kGramWaves + wave; !PLAIN && sl < nslab; sl += stride) {
     const int64_t r0 = sl * 16;
-    const bool rin = r0 + li < d;
-    const TA *const As = Al + r0;
     double a[4 * NTI];
-#pragma unroll
-    for (int ks = 0; ks < 4 * NTI; ++ks)
-      a[ks] = (rin && 4 * ks + lk < n) ? (double)gload(As + ks * lda4) : 0.0;
     // fb[e][r] = B[r0 + lk + 4 r][c], c = 16 (NTI - 1 + e) + li - n (zero
     // outside 0 <= c < nrhs); zb[c][r] = B[r0 + lk + 4 r][zc0 + c]
     double fb[NB][4];
-#pragma unroll
-    for (int e = 0; e < NB; ++e) {
-      const int c = 16 * (NTI - 1 + e) + li - n;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t rw = r0 + lk + 4 * r;
-        fb[e][r] = (c >= 0 && c < nrhs && rw < d) ? (double)gload(B + rw + (int64_t)c * ldb) : 0.0;
-      }
-    }
     double zb[NZ > 0 ? NZ : 1][4];
+    if (sl < nfull) {
+      // no branch around any load (see the PLAIN loop): columns past n read
+      // column n - 1 and B columns outside [0, nrhs) read a clamped one, and
+      // the values are masked afterwards
 #pragma unroll
-    for (int c = 0; c < NZ; ++c)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t rw = r0 + lk + 4 * r;
-        zb[c][r] = (c < nx && rw < d) ? (double)gload(B + rw + (int64_t)(zc0 + c) * ldb) : 0.0;
+      for (int ks = 0; ks < 4 * NTI; ++ks) {
+        const int kk = 4 * ks + lk;
+        a[ks] = (double)gload(A + li + r0 + (int64_t)min(kk, n - 1) * lda);
       }
+#pragma unroll
+      for (int e = 0; e < NB; ++e)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) fb[e][r] = (double)gload(fbcol[e] + r0 + lk + 4 * r);
+#pragma unroll
+      for (int c = 0; c < NZ; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) zb[c][r] = (double)gload(zcol + r0 + lk + 4 * r);
+#pragma unroll
+      for (int ks = 0; ks < 4 * NTI; ++ks)
+        if (4 * ks + lk >= n) a[ks] = 0.0;
+#pragma unroll
+      for (int e = 0; e < NB; ++e)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (!fbok[e]) fb[e][r] = 0.0;
+#pragma unroll
+      for (int c = 0; c < NZ; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (c >= nx) zb[c][r] = 0.0;
+    } else {
+      const bool rin = r0 + li < d;
+      const TA *const As = Al + r0;
+#pragma unroll
+      for (int ks = 0; ks < 4 * NTI; ++ks)
+        a[ks] = (rin && 4 * ks + lk < n) ? (double)gload(As + ks * lda4) : 0.0;
+#pragma unroll
+      for (int e = 0; e < NB; ++e) {
+        const int c = 16 * (NTI - 1 + e) + li - n;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t rw = r0 + lk + 4 * r;
+          fb[e][r] = (c >= 0 && c < nrhs && rw < d) ? (double)gload(B + rw + (int64_t)c * ldb) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < NZ; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t rw = r0 + lk + 4 * r;
+          zb[c][r] = (c < nx && rw < d) ? (double)gload(B + rw + (int64_t)(zc0 + c) * ldb) : 0.0;
+        }
+    }
     // R0^{-1} is re-read from LDS in every slab: the empty asm keeps the
     // compiler from hoisting its 4 NTI (NTI + 1) / 2 fragments into registers
     // for the whole loop (which would leave too few for two waves per SIMD)

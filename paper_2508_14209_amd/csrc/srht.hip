@@ -29,6 +29,7 @@ constexpr int kLogB = 13;
 constexpr int kB = 1 << kLogB;
 constexpr int kThreads = 256;      // 32 elements per thread
 constexpr int kPer = kB / kThreads;
+constexpr int kRCache = 1024;      // sampled row indices kept in LDS
 
 // LDS slot of block element e: one pad slot per 32 elements keeps the three
 // exchange patterns free of bank conflicts beyond the 64-bit pairs
@@ -52,8 +53,49 @@ __device__ __forceinline__ void reg_stages(double (&x)[kPer]) {
       }
 }
 
-// One workgroup per (block q, column c).  out: with one block, Y (scaled);
-// else part[(q ncols + c) k + j] (unscaled, summed by k_srht_reduce).
+// Persistent: workgroup g takes items g, g + grid, ... (item = c nblk + q:
+// block q of column c), and loads the next item's 32 values per thread into
+// registers before it transforms the current one, so a block's HBM reads
+// overlap the previous block's butterflies and LDS exchanges.  out: with one
+// block, Y (scaled); else part[(q ncols + c) k + j] (unscaled, summed by
+// k_srht_reduce).
+// Raw loads of one item's 32 values and signs per thread (element e = t +
+// 256 u).  Rows past mx load row mx - 1 (in bounds) and are zeroed later by
+// srht_signed: nothing here uses the loaded data, so the loads stay in
+// flight while the previous item is transformed (a load behind a branch, or
+// a use right after it, would make the wave wait for it there).
+template <typename TX>
+__device__ __forceinline__ void srht_load(int64_t item, int nblk, int64_t mx,
+                                          const TX *__restrict__ X, int64_t ldx,
+                                          const int8_t *__restrict__ dsign, int t,
+                                          TX (&xa)[kPer], int8_t (&sg)[kPer]) {
+  const int64_t q = item % nblk, c = item / nblk;
+  const int64_t base = q * kB;
+  const TX *xc = X + c * ldx;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int64_t i = base + t + kThreads * u;
+    const int64_t ic = i < mx ? i : mx - 1;
+    sg[u] = gload(dsign + ic);
+    xa[u] = gload(xc + ic);
+  }
+}
+
+// D applied to the loaded values (FP64), rows past mx zeroed; a sign other
+// than +-1 sets bad.
+template <typename TX>
+__device__ __forceinline__ void srht_signed(int64_t base, int64_t mx, int t,
+                                            const TX (&xa)[kPer], const int8_t (&sg)[kPer],
+                                            double (&x)[kPer], bool &bad) {
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const bool in = base + t + kThreads * u < mx;
+    bad |= in & !(sg[u] == 1 || sg[u] == -1);
+    const double a = (double)xa[u];
+    x[u] = in ? (sg[u] < 0 ? -a : a) : 0.0;
+  }
+}
+
 template <typename TX>
 __global__ __launch_bounds__(kThreads) void k_srht_block(int64_t mx, int ncols, int k, int nblk,
                                                          const TX *__restrict__ X, int64_t ldx,
@@ -63,55 +105,63 @@ __global__ __launch_bounds__(kThreads) void k_srht_block(int64_t mx, int ncols, 
                                                          double *__restrict__ out, int64_t ldo,
                                                          int *status) {
   __shared__ double lds[kB + kB / 32];
+  // the sampled rows, the same for every item: read from LDS, so that the
+  // sampling does not wait behind the next item's loads
+  __shared__ int32_t rs[kRCache];
   const int t = threadIdx.x;
-  const int64_t q = blockIdx.x;
-  const int c = blockIdx.y;
-  const int64_t base = q * kB;
-  const TX *xc = X + (int64_t)c * ldx;
-  double x[kPer];
+  const int64_t items = (int64_t)nblk * ncols;
+  for (int j = t; j < k && j < kRCache; j += kThreads) rs[j] = gload(r + j);
   bool bad = false;
-  // element e = t + 256 u: the stages on bits 8..12 are in registers
+  TX xa[kPer];
+  int8_t sg[kPer];
+  int64_t item = blockIdx.x;
+  if (item < items) srht_load(item, nblk, mx, X, ldx, dsign, t, xa, sg);
+  for (; item < items; item += gridDim.x) {
+    const int64_t q = item % nblk, c = item / nblk;
+    double x[kPer];
+    srht_signed(q * kB, mx, t, xa, sg, x, bad);
+    const int64_t next = item + gridDim.x;
+    if (next < items) srht_load(next, nblk, mx, X, ldx, dsign, t, xa, sg);
+    // bits 8..12 (element e = t + 256 u) in registers
+    reg_stages<0, 5>(x);
+    __syncthreads();  // the previous item's sampling reads are done
 #pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int64_t i = base + t + kThreads * u;
-    double v = 0.0;
-    if (i < mx) {
-      const int8_t sg = gload(dsign + i);
-      bad |= !(sg == 1 || sg == -1);
-      const double a = (double)gload(xc + i);
-      v = sg < 0 ? -a : a;
+    for (int u = 0; u < kPer; ++u) lds[pad(t + kThreads * u)] = x[u];
+    __syncthreads();
+    // e = 32 t + u: bits 0..4
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) x[u] = lds[pad(32 * t + u)];
+    reg_stages<0, 5>(x);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) lds[pad(32 * t + u)] = x[u];
+    __syncthreads();
+    // e = (t & 31) | (u & 7) << 5 | (t >> 5) << 8 | (u >> 3) << 11: bits 5..7
+    auto e3 = [&](int u) {
+      return (t & 31) | ((u & 7) << 5) | ((t >> 5) << 8) | ((u >> 3) << 11);
+    };
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) x[u] = lds[pad(e3(u))];
+    reg_stages<0, 3>(x);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) lds[pad(e3(u))] = x[u];
+    __syncthreads();
+    // the sampled rows of this block's share
+    auto sample = [&](int j, int32_t rj) {
+      const bool ok = rj >= 0 && (int64_t)rj < m;
+      bad |= !ok;
+      const double v = ok ? block_sign(rj, q) * lds[pad(rj & (kB - 1))] : 0.0;
+      if (nblk == 1)
+        out[j + c * ldo] = v * scale;
+      else
+        out[(q * ncols + c) * k + j] = v;
+    };
+    // two uniform paths: a global load on the same path as the LDS read
+    // would make the LDS path wait for every outstanding load too
+    if (k <= kRCache) {
+      for (int j = t; j < k; j += kThreads) sample(j, rs[j]);
+    } else {
+      for (int j = t; j < k; j += kThreads) sample(j, gload(r + j));
     }
-    x[u] = v;
-  }
-  reg_stages<0, 5>(x);
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) lds[pad(t + kThreads * u)] = x[u];
-  __syncthreads();
-  // e = 32 t + u: bits 0..4
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) x[u] = lds[pad(32 * t + u)];
-  reg_stages<0, 5>(x);
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) lds[pad(32 * t + u)] = x[u];
-  __syncthreads();
-  // e = (t & 31) | (u & 7) << 5 | (t >> 5) << 8 | (u >> 3) << 11: bits 5..7
-  auto e3 = [&](int u) { return (t & 31) | ((u & 7) << 5) | ((t >> 5) << 8) | ((u >> 3) << 11); };
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) x[u] = lds[pad(e3(u))];
-  reg_stages<0, 3>(x);
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) lds[pad(e3(u))] = x[u];
-  __syncthreads();
-  // the sampled rows of this block's share
-  for (int j = t; j < k; j += kThreads) {
-    const int32_t rj = gload(r + j);
-    const bool ok = rj >= 0 && (int64_t)rj < m;
-    bad |= !ok;
-    const double v = ok ? block_sign(rj, q) * lds[pad(rj & (kB - 1))] : 0.0;
-    if (nblk == 1)
-      out[j + (int64_t)c * ldo] = v * scale;
-    else
-      out[((int64_t)q * ncols + c) * k + j] = v;
   }
   if (bad) record_status(status, MS_ERR_RANGE);
 }
@@ -161,16 +211,39 @@ __global__ __launch_bounds__(kThreads) void k_srht_small(int64_t mx, int logm, i
   if (bad) record_status(status, MS_ERR_RANGE);
 }
 
-// Y[j][c] = scale * sum over blocks q (ascending) of part[(q ncols + c) k + j].
-__global__ void k_srht_reduce(int ncols, int k, int nblk, const double *__restrict__ part,
-                              double scale, double *__restrict__ Y, int64_t ldy) {
-  const int64_t total = (int64_t)ncols * k;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int j = (int)(e % k), c = (int)(e / k);
-    double s = 0.0;
-    for (int q = 0; q < nblk; ++q) s += part[((int64_t)q * ncols + c) * k + j];
-    Y[j + (int64_t)c * ldy] = s * scale;
+// Y[j][c] = scale * the sum over blocks q of part[(q ncols + c) k + j]: a
+// workgroup takes 64 consecutive outputs (one column); wave w sums the
+// blocks of its contiguous share in ascending order (four interleaved
+// running sums, added pairwise), and the 16 waves' sums are added in wave
+// order -- a fixed association, so repeated calls give the same bits.
+constexpr int kRedWaves = 16;
+__global__ __launch_bounds__(64 * kRedWaves) void k_srht_reduce(int ncols, int k, int nblk,
+                                                                const double *__restrict__ part,
+                                                                double scale,
+                                                                double *__restrict__ Y,
+                                                                int64_t ldy) {
+  __shared__ double sh[kRedWaves][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tiles = (k + 63) / 64;
+  const int c = blockIdx.x / tiles;
+  const int j = (blockIdx.x % tiles) * 64 + lane;
+  const int q0 = (int)((int64_t)nblk * w / kRedWaves), q1 = (int)((int64_t)nblk * (w + 1) / kRedWaves);
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  if (j < k) {
+    const double *p = part + (int64_t)c * k + j;
+    const int64_t step = (int64_t)ncols * k;
+    int q = q0;
+    for (; q + 4 <= q1; q += 4)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s[u] += p[(int64_t)(q + u) * step];
+    for (int u = 0; q < q1; ++q, ++u) s[u] += p[(int64_t)q * step];
+  }
+  sh[w][lane] = (s[0] + s[1]) + (s[2] + s[3]);
+  __syncthreads();
+  if (w == 0 && j < k) {
+    double t = 0.0;
+    for (int v = 0; v < kRedWaves; ++v) t += sh[v][lane];
+    Y[j + (int64_t)c * ldy] = t * scale;
   }
 }
 
@@ -204,21 +277,23 @@ hipError_t launch_srht(int64_t mx, int64_t ncols, int64_t k, const TX *X, int64_
     return hipGetLastError();
   }
   const int64_t nblk = m / kB;
+  // persistent grid: two workgroups per CU (the LDS of a block allows two)
+  const int64_t items = nblk * ncols;
+  const unsigned grid = (unsigned)std::min<int64_t>(items, 2 * (int64_t)dev_info().cus);
   if (nblk == 1) {
-    hipLaunchKernelGGL((k_srht_block<TX>), dim3(1, (unsigned)ncols), dim3(kThreads), 0, st, mx,
-                       (int)ncols, (int)k, 1, X, ldx, dsign, r, m, scale, Y, ldy, status);
+    hipLaunchKernelGGL((k_srht_block<TX>), dim3(grid), dim3(kThreads), 0, st, mx, (int)ncols,
+                       (int)k, 1, X, ldx, dsign, r, m, scale, Y, ldy, status);
     return hipGetLastError();
   }
   if (!part) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_srht_block<TX>), dim3((unsigned)nblk, (unsigned)ncols), dim3(kThreads), 0,
-                     st, mx, (int)ncols, (int)k, (int)nblk, X, ldx, dsign, r, m, scale,
-                     static_cast<double *>(part), (int64_t)0, status);
+  hipLaunchKernelGGL((k_srht_block<TX>), dim3(grid), dim3(kThreads), 0, st, mx, (int)ncols,
+                     (int)k, (int)nblk, X, ldx, dsign, r, m, scale, static_cast<double *>(part),
+                     (int64_t)0, status);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t total = ncols * k;
-  const unsigned rb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 4096));
-  hipLaunchKernelGGL(k_srht_reduce, dim3(rb), dim3(256), 0, st, (int)ncols, (int)k, (int)nblk,
-                     static_cast<const double *>(part), scale, Y, ldy);
+  const unsigned rb = (unsigned)(ncols * ((k + 63) / 64));
+  hipLaunchKernelGGL(k_srht_reduce, dim3(rb), dim3(64 * kRedWaves), 0, st, (int)ncols, (int)k,
+                     (int)nblk, static_cast<const double *>(part), scale, Y, ldy);
   return hipGetLastError();
 }
 template hipError_t launch_srht<double>(int64_t, int64_t, int64_t, const double *, int64_t,
