@@ -58,6 +58,10 @@ def parse():
     ap.add_argument("--other-configs", type=int, default=1,
                     help="also time the FP32 16,777,216 x 128 and the mixed-precision "
                          "8,388,608 x 256 solves (0 skips them)")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="1: also measure rand_cholQR / normal equations, the SRHT and the "
+                         "hash-generated CountSketch (0 skips them, e.g. to profile the headline "
+                         "solve alone)")
     ap.add_argument("--refine", type=int, default=2,
                     help="FP64-residual refinement steps of the mixed-precision legs")
     ap.add_argument("--only", default=None,
@@ -745,15 +749,21 @@ def main():
     gs_flops = 2.0 * k2 * k * nc
 
     # ---- rand_cholQR least squares on the same problem (its own leg)
+    rcq = srht = None
     try:
+        if not args.extras:
+            raise StopIteration
         rcq = rcq_leg(ms, torch, np, Ad, Bd, hd, sd, Gd, k, args.mode, X, max(10, args.steps // 5),
                       A, B, h, s, G, cpu=args.cpu_seconds > 0)
+    except StopIteration:
+        pass
     except Exception as e:  # reported in the line, not hidden
         rcq = {"error": repr(e)}
 
     # ---- SRHT and the Count + SRHT multisketch on the same problem
     try:
-        srht = srht_leg(ms, torch, np, Ad, Bd, hd, sd, Gd, k, args.mode, X, seed + 3)
+        if args.extras:
+            srht = srht_leg(ms, torch, np, Ad, Bd, hd, sd, Gd, k, args.mode, X, seed + 3)
     except Exception as e:
         srht = {"error": repr(e)}
 
@@ -820,7 +830,8 @@ def main():
         except Exception as e:
             out["other_configs"] = {"error": repr(e)}
     try:
-        out["hashed_countsketch"] = hashed_leg(ms, torch, seed, dev)
+        if args.extras:
+            out["hashed_countsketch"] = hashed_leg(ms, torch, seed, dev)
     except Exception as e:
         out["hashed_countsketch"] = {"error": repr(e)}
     if args.compare_problems > 0:
