@@ -654,8 +654,8 @@ ms_status rand_cholqr_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64
   // 5-8. the partials' sum, R1 = chol(Q0^T Q0), R = R1 R0, y = R1^{-T} Q0^T B,
   // x = R^{-1} y
   if (e == hipSuccess)
-    e = launch_rcq_finish((int)n, (int)nrhs, grid, part, at<double>(ws, L.w), r0, kRcqMaxN, X, ldx,
-                          R, ldr, status, st);
+    e = launch_rcq_finish((int)n, (int)nrhs, grid, part, at<double>(ws, L.w), r0, kRcqMaxN, rinv,
+                          X, ldx, R, ldr, status, st);
   return from_hip(e);
 }
 
@@ -801,8 +801,8 @@ ms_status normal_equations_lstsq(int64_t d, int64_t n, int64_t nrhs, ms_dtype a_
             : launch_rcq_gram<float>(d, (int)n, (int)nrhs, static_cast<const float *>(A), lda,
                                      static_cast<const float *>(B), ldb, nullptr, part, grid, st);
   if (e == hipSuccess)
-    e = launch_rcq_finish((int)n, (int)nrhs, grid, part, at<double>(ws, L.w), nullptr, 0, X, ldx,
-                          R, ldr, status, st);
+    e = launch_rcq_finish((int)n, (int)nrhs, grid, part, at<double>(ws, L.w), nullptr, 0, nullptr,
+                          X, ldx, R, ldr, status, st);
   return from_hip(e);
 }
 

@@ -202,8 +202,8 @@ hipError_t launch_rcq_gram(int64_t d, int n, int nrhs, const TA *A, int64_t lda,
                            int64_t ldb, const double *Rinv, double *part, int grid,
                            hipStream_t st);
 hipError_t launch_rcq_finish(int n, int nrhs, int nparts, const double *part, double *W,
-                             const double *R0, int ldr0, double *X, int64_t ldx, double *R,
-                             int64_t ldr, int *status, hipStream_t st);
+                             const double *R0, int ldr0, const double *Rinv, double *X,
+                             int64_t ldx, double *R, int64_t ldr, int *status, hipStream_t st);
 
 // SRHT (srht.hip): Y = k^{-1/2} P H_m D X for an mx x ncols X (FP64 or FP32),
 // m = the smallest power of two >= mx; Y k x ncols FP64.  part: the

@@ -62,8 +62,6 @@ __device__ __forceinline__ v4d load_rows4(const T *p, int64_t row, int64_t d) {
 }
 
 constexpr int kLdr = 68;   // LDS row stride of R0^{-1} (doubles)
-constexpr int kLdq = 84;   // LDS row stride of a [Q0 | B] block (doubles)
-constexpr int kRows = 64;  // rows of A per block
 constexpr int kPart = kRcqMaxN * kRcqMaxCols;  // doubles of one partial (64 x 80, row-major)
 
 __device__ __forceinline__ v4d mma64(double a, double b, v4d c) {
@@ -384,19 +382,21 @@ __global__ __launch_bounds__(256) void k_rcq_reduce(int nparts, const double *__
 }
 
 // One wave: R1 = chol(G) (G = Q0^T Q0, the upper part of W), y = R1^{-T} z
-// (z = Q0^T B, columns n .. n + nrhs of W), R = R1 R0 and x = R^{-1} y.
-// R0 null: R0 = I (the normal equations: G = A^T A, z = A^T B, R = R1).
+// (z = Q0^T B, columns n .. n + nrhs of W), x = R^{-1} y with R = R1 R0.
+// R0 and Rinv null: R0 = I (the normal equations: G = A^T A, z = A^T B,
+// R = R1).
 // Lane l holds column l of the working matrix in registers (g[i] = entry
 // (i, l)); matrices of order n < 64 are padded to 64 with the identity, so
 // every lane runs the same fully unrolled steps.
 __global__ __launch_bounds__(64) void k_rcq_solve(int n, int nrhs, const double *__restrict__ W,
                                                   const double *__restrict__ R0, int ldr0,
+                                                  const double *__restrict__ Rinv,
                                                   double *__restrict__ X, int64_t ldx,
                                                   double *__restrict__ Rout, int64_t ldr,
                                                   int *status) {
   constexpr int N = kRcqMaxN, L = kRcqMaxN + 1;
   __shared__ double r1[N * L];   // R1, row-major: r1[i L + l]
-  __shared__ double rm[N * L];   // R0 staging, then R column-major: rm[i + j L]
+  __shared__ double rm[N * L];   // R0^{-1} staging, row-major: rm[i L + j]
   __shared__ double zs[kRcqMaxRhs * N];
   const int lane = threadIdx.x;
   double g[N];
@@ -404,11 +404,6 @@ __global__ __launch_bounds__(64) void k_rcq_solve(int n, int nrhs, const double 
   for (int i = 0; i < N; ++i)
     g[i] = lane < n ? (i <= lane ? W[i * kRcqMaxCols + lane] : 0.0) : (i == lane ? 1.0 : 0.0);
   for (int c = 0; c < nrhs; ++c) zs[c * N + lane] = lane < n ? W[lane * kRcqMaxCols + n + c] : 0.0;
-  // R0 (padded with the identity), staged column by column (lane = row)
-  for (int j = 0; j < N; ++j)
-    rm[lane + j * L] = (R0 && lane < n && j < n)
-                           ? (lane <= j ? R0[lane + (int64_t)j * ldr0] : 0.0)
-                           : (lane == j ? 1.0 : 0.0);
 
   // right-looking Cholesky: at step j lane l forms R1[j][l] (l >= j), row j
   // goes to LDS, and every lane updates its column with it
@@ -448,37 +443,50 @@ __global__ __launch_bounds__(64) void k_rcq_solve(int n, int nrhs, const double 
     }
     zs[c * N + lane] = y;
   }
-  // R = R1 R0, column lane in place of R0's: R[i][l] = sum_{q >= i} R1[i][q] R0[q][l]
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < N; ++i) g[i] = rm[i + lane * L];
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    double acc[2] = {0.0, 0.0};
-#pragma unroll
-    for (int q = i; q < N; ++q) acc[(q - i) & 1] += r1[i * L + q] * g[q];
-    g[i] = acc[0] + acc[1];
-  }
-  double rdiag = 1.0;
-#pragma unroll
-  for (int i = 0; i < N; ++i) {
-    if (lane == i) rdiag = g[i];
-    rm[i + lane * L] = g[i];
-  }
-  __syncthreads();
-  if (Rout)
-    for (int j = 0; j < n; ++j)
-      if (lane < n) Rout[lane + (int64_t)j * ldr] = rm[lane + j * L];
-  // R x = y, column oriented: x_i = y_i / R[i][i], then lanes t < i subtract
-  // R[t][i] x_i
+  // x = R^{-1} y with R = R1 R0, taken as R0^{-1} (R1^{-1} y): first the
+  // back substitution with R1 (lanes t < i subtract R1[t][i] w_i), then the
+  // product with R0^{-1} (Rinv, from the triangular inverse); without R0
+  // (the normal equations) x = R1^{-1} y.  The straight-line product
+  // R = R1 R0 is formed only when the caller asks for R.
   for (int c = 0; c < nrhs; ++c) {
     double y = zs[c * N + lane];
 #pragma unroll
     for (int i = N - 1; i >= 0; --i) {
-      const double xi = read_lane(y, i) / read_lane(rdiag, i);
-      y = lane == i ? xi : (lane < i ? y - rm[lane + i * L] * xi : y);
+      const double xi = read_lane(y, i) / read_lane(mydiag, i);
+      y = lane == i ? xi : (lane < i ? y - r1[lane * L + i] * xi : y);
     }
-    if (lane < n) X[lane + (int64_t)c * ldx] = y;
+    zs[c * N + lane] = y;
+  }
+  if (Rout) {
+    // R0 (padded with the identity) column lane in registers, then
+    // R[i][lane] = sum_{q >= i} R1[i][q] R0[q][lane] in place
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      g[i] = (R0 && lane < n && i < n) ? (i <= lane ? R0[i + (int64_t)lane * ldr0] : 0.0)
+                                       : (lane == i ? 1.0 : 0.0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double acc[2] = {0.0, 0.0};
+#pragma unroll
+      for (int q = i; q < N; ++q) acc[(q - i) & 1] += r1[i * L + q] * g[q];
+      g[i] = acc[0] + acc[1];
+    }
+    if (lane < n)
+      for (int i = 0; i < n; ++i) Rout[i + (int64_t)lane * ldr] = g[i];
+  }
+  if (Rinv) {
+    // R0^{-1} staged row-major (lane = column), then x_t = sum_q Rinv[t][q] w_q
+    for (int i = 0; i < N; ++i) rm[i * L + lane] = Rinv[i * N + lane];
+    __syncthreads();
+    for (int c = 0; c < nrhs; ++c) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < N; ++q) acc[q & 3] += rm[lane * L + q] * zs[c * N + q];
+      if (lane < n) X[lane + (int64_t)c * ldx] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    }
+  } else {
+    for (int c = 0; c < nrhs; ++c)
+      if (lane < n) X[lane + (int64_t)c * ldx] = zs[c * N + lane];
   }
 }
 
@@ -535,13 +543,13 @@ template hipError_t launch_rcq_gram<float>(int64_t, int, int, const float *, int
                                            hipStream_t);
 
 hipError_t launch_rcq_finish(int n, int nrhs, int nparts, const double *part, double *W,
-                             const double *R0, int ldr0, double *X, int64_t ldx, double *R,
-                             int64_t ldr, int *status, hipStream_t st) {
+                             const double *R0, int ldr0, const double *Rinv, double *X,
+                             int64_t ldx, double *R, int64_t ldr, int *status, hipStream_t st) {
   hipLaunchKernelGGL(k_rcq_reduce, dim3(kPart / 64), dim3(256), 0, st, nparts, part, W);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_rcq_solve, dim3(1), dim3(64), 0, st, n, nrhs, W, R0, ldr0, X, ldx, R,
-                     ldr, status);
+  hipLaunchKernelGGL(k_rcq_solve, dim3(1), dim3(64), 0, st, n, nrhs, W, R0, ldr0, Rinv, X, ldx,
+                     R, ldr, status);
   return hipGetLastError();
 }
 

@@ -59,25 +59,74 @@ __device__ __forceinline__ void reg_stages(double (&x)[kPer]) {
 // overlap the previous block's butterflies and LDS exchanges.  out: with one
 // block, Y (scaled); else part[(q ncols + c) k + j] (unscaled, summed by
 // k_srht_reduce).
-// Raw loads of one item's 32 values and signs per thread (element e = t +
-// 256 u).  Rows past mx load row mx - 1 (in bounds) and are zeroed later by
-// srht_signed: nothing here uses the loaded data, so the loads stay in
-// flight while the previous item is transformed (a load behind a branch, or
-// a use right after it, would make the wave wait for it there).
+// Element maps of the three register phases (t: thread, u: register):
+//   phase 1  e = (u & 3) | t << 2 | (u >> 2) << 10        bits 0,1,10,11,12 in registers
+//   phase 2  e = (t & 3) | u << 2 | (t >> 2) << 7         bits 2..6
+//   phase 3  e = (t & 127) | (u & 7) << 7 | (t >> 7) << 10 | (u >> 3) << 11   bits 7,8,9
+// Phase 1 gives each thread 8 groups of 4 consecutive rows: one 32-byte load
+// and one 4-byte sign word per group (16 load instructions per thread), so a
+// wave stays well under its limit of 63 outstanding loads and the next
+// block's loads are all in flight while the current block is transformed.
+// With the one pad slot per 32 elements, every exchange reaches each LDS
+// bank pair at most twice per 64 lanes.
+// pad(e_k(t, u)) = p_k(t) + c_k(u): a per-thread base plus a compile-time
+// offset (at most 59 KB, inside the LDS instruction's immediate), so each
+// exchange keeps one address register instead of 32.
+__device__ __forceinline__ int p1(int t) { return 4 * t + (t >> 3); }
+constexpr int c1(int u) { return (u & 3) + 1056 * (u >> 2); }
+__device__ __forceinline__ int p2(int t) { return (t & 3) + 132 * (t >> 2); }
+constexpr int c2(int u) { return 4 * u + (u >> 3); }
+__device__ __forceinline__ int p3(int t) { return (t & 127) + ((t & 127) >> 5) + 1056 * (t >> 7); }
+constexpr int c3(int u) { return 132 * (u & 7) + 2112 * (u >> 3); }
+__device__ __forceinline__ int e1(int t, int u) { return (u & 3) | (t << 2) | ((u >> 2) << 10); }
+
+typedef double dv4e __attribute__((ext_vector_type(4), aligned(8)));
+typedef float fv4e __attribute__((ext_vector_type(4), aligned(4)));
+template <typename T>
+struct V4;
+template <>
+struct V4<double> {
+  typedef dv4e type;
+};
+template <>
+struct V4<float> {
+  typedef fv4e type;
+};
+
+// Raw loads of one item (block q of column c) in the phase-1 map; nothing
+// here uses the data, so the loads stay in flight.  Full blocks (all 8192
+// rows inside X) with a 4-byte aligned dsign take vector loads; the ragged
+// last block reads clamped rows one by one (zeroed by srht_signed).
 template <typename TX>
 __device__ __forceinline__ void srht_load(int64_t item, int nblk, int64_t mx,
                                           const TX *__restrict__ X, int64_t ldx,
-                                          const int8_t *__restrict__ dsign, int t,
-                                          TX (&xa)[kPer], int8_t (&sg)[kPer]) {
+                                          const int8_t *__restrict__ dsign, bool svec, int t,
+                                          TX (&xa)[kPer], uint32_t (&sw)[kPer / 4]) {
   const int64_t q = item % nblk, c = item / nblk;
   const int64_t base = q * kB;
   const TX *xc = X + c * ldx;
+  if (svec && base + kB <= mx) {
 #pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int64_t i = base + t + kThreads * u;
-    const int64_t ic = i < mx ? i : mx - 1;
-    sg[u] = gload(dsign + ic);
-    xa[u] = gload(xc + ic);
+    for (int g = 0; g < kPer / 4; ++g) {
+      const int64_t i = base + e1(t, 4 * g);
+      const typename V4<TX>::type v = gload((const typename V4<TX>::type *)(xc + i));
+#pragma unroll
+      for (int r = 0; r < 4; ++r) xa[4 * g + r] = v[r];
+      sw[g] = gload((const uint32_t *)(dsign + i));
+    }
+  } else {
+#pragma unroll
+    for (int g = 0; g < kPer / 4; ++g) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = base + e1(t, 4 * g + r);
+        const int64_t ic = i < mx ? i : mx - 1;
+        xa[4 * g + r] = gload(xc + ic);
+        w |= (uint32_t)(uint8_t)gload(dsign + ic) << (8 * r);
+      }
+      sw[g] = w;
+    }
   }
 }
 
@@ -85,14 +134,15 @@ __device__ __forceinline__ void srht_load(int64_t item, int nblk, int64_t mx,
 // than +-1 sets bad.
 template <typename TX>
 __device__ __forceinline__ void srht_signed(int64_t base, int64_t mx, int t,
-                                            const TX (&xa)[kPer], const int8_t (&sg)[kPer],
+                                            const TX (&xa)[kPer], const uint32_t (&sw)[kPer / 4],
                                             double (&x)[kPer], bool &bad) {
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
-    const bool in = base + t + kThreads * u < mx;
-    bad |= in & !(sg[u] == 1 || sg[u] == -1);
+    const bool in = base + e1(t, u) < mx;
+    const int8_t sg = (int8_t)(sw[u >> 2] >> (8 * (u & 3)));
+    bad |= in & !(sg == 1 || sg == -1);
     const double a = (double)xa[u];
-    x[u] = in ? (sg[u] < 0 ? -a : a) : 0.0;
+    x[u] = in ? (sg < 0 ? -a : a) : 0.0;
   }
 }
 
@@ -110,40 +160,38 @@ __global__ __launch_bounds__(kThreads) void k_srht_block(int64_t mx, int ncols, 
   __shared__ int32_t rs[kRCache];
   const int t = threadIdx.x;
   const int64_t items = (int64_t)nblk * ncols;
+  const bool svec = (reinterpret_cast<uintptr_t>(dsign) & 3) == 0;
   for (int j = t; j < k && j < kRCache; j += kThreads) rs[j] = gload(r + j);
   bool bad = false;
   TX xa[kPer];
-  int8_t sg[kPer];
+  uint32_t sw[kPer / 4];
   int64_t item = blockIdx.x;
-  if (item < items) srht_load(item, nblk, mx, X, ldx, dsign, t, xa, sg);
+  if (item < items) srht_load(item, nblk, mx, X, ldx, dsign, svec, t, xa, sw);
   for (; item < items; item += gridDim.x) {
     const int64_t q = item % nblk, c = item / nblk;
     double x[kPer];
-    srht_signed(q * kB, mx, t, xa, sg, x, bad);
+    srht_signed(q * kB, mx, t, xa, sw, x, bad);
     const int64_t next = item + gridDim.x;
-    if (next < items) srht_load(next, nblk, mx, X, ldx, dsign, t, xa, sg);
-    // bits 8..12 (element e = t + 256 u) in registers
-    reg_stages<0, 5>(x);
-    __syncthreads();  // the previous item's sampling reads are done
+    if (next < items) srht_load(next, nblk, mx, X, ldx, dsign, svec, t, xa, sw);
+    reg_stages<0, 5>(x);  // bits 0, 1, 10, 11, 12
+    __syncthreads();      // the previous item's sampling reads are done
+    double *const l1 = lds + p1(t);
+    double *const l2 = lds + p2(t);
+    double *const l3 = lds + p3(t);
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) lds[pad(t + kThreads * u)] = x[u];
+    for (int u = 0; u < kPer; ++u) l1[c1(u)] = x[u];
     __syncthreads();
-    // e = 32 t + u: bits 0..4
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) x[u] = lds[pad(32 * t + u)];
-    reg_stages<0, 5>(x);
+    for (int u = 0; u < kPer; ++u) x[u] = l2[c2(u)];
+    reg_stages<0, 5>(x);  // bits 2..6
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) lds[pad(32 * t + u)] = x[u];
+    for (int u = 0; u < kPer; ++u) l2[c2(u)] = x[u];
     __syncthreads();
-    // e = (t & 31) | (u & 7) << 5 | (t >> 5) << 8 | (u >> 3) << 11: bits 5..7
-    auto e3 = [&](int u) {
-      return (t & 31) | ((u & 7) << 5) | ((t >> 5) << 8) | ((u >> 3) << 11);
-    };
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) x[u] = lds[pad(e3(u))];
-    reg_stages<0, 3>(x);
+    for (int u = 0; u < kPer; ++u) x[u] = l3[c3(u)];
+    reg_stages<0, 3>(x);  // bits 7, 8, 9
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) lds[pad(e3(u))] = x[u];
+    for (int u = 0; u < kPer; ++u) l3[c3(u)] = x[u];
     __syncthreads();
     // the sampled rows of this block's share
     auto sample = [&](int j, int32_t rj) {
