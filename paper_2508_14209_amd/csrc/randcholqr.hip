@@ -457,23 +457,20 @@ __global__ __launch_bounds__(64) void k_rcq_solve(int n, int nrhs, const double 
     }
     zs[c * N + lane] = y;
   }
-  if (Rout) {
-    // R0 (padded with the identity) column lane in registers, then
-    // R[i][lane] = sum_{q >= i} R1[i][q] R0[q][lane] in place
-#pragma unroll
-    for (int i = 0; i < N; ++i)
-      g[i] = (R0 && lane < n && i < n) ? (i <= lane ? R0[i + (int64_t)lane * ldr0] : 0.0)
-                                       : (lane == i ? 1.0 : 0.0);
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-      double acc[2] = {0.0, 0.0};
-#pragma unroll
-      for (int q = i; q < N; ++q) acc[(q - i) & 1] += r1[i * L + q] * g[q];
-      g[i] = acc[0] + acc[1];
+  if (Rout && lane < n) {
+    // R[i][lane] = sum_{q = i .. lane} R1[i][q] R0[q][lane] (rolled, from LDS
+    // and R0 itself: an array indexed at run time must not share the
+    // factorisation's registers, or all of them would live in scratch memory)
+    for (int i = 0; i < n; ++i) {
+      double acc = 0.0;
+      if (R0)
+        for (int q = i; q <= lane; ++q) acc += r1[i * L + q] * R0[q + (int64_t)lane * ldr0];
+      else
+        acc = i <= lane ? r1[i * L + lane] : 0.0;
+      Rout[i + (int64_t)lane * ldr] = i <= lane ? acc : 0.0;
     }
-    if (lane < n)
-      for (int i = 0; i < n; ++i) Rout[i + (int64_t)lane * ldr] = g[i];
   }
+  __syncthreads();
   if (Rinv) {
     // R0^{-1} staged row-major (lane = column), then x_t = sum_q Rinv[t][q] w_q
     for (int i = 0; i < N; ++i) rm[i * L + lane] = Rinv[i * N + lane];
