@@ -99,13 +99,13 @@ def measured_traffic():
 
 
 def countsketch_source_hash():
-    """sha256 of the single-problem CountSketch sources: countsketch.hip and
-    ms_internal.h up to their batched sections (which the profiled kernel
-    does not use)."""
+    """sha256 of the single-problem CountSketch sources: countsketch.hip up
+    to its batched section and ms_internal.h up to the rand_cholQR
+    declarations (what follows there is not used by the profiled kernel)."""
     import hashlib
     h = hashlib.sha256()
     for f, mark in (("countsketch.hip", "// " + "-" * 66 + " batched"),
-                    ("ms_internal.h", "// " + "-" * 64 + " batched")):
+                    ("ms_internal.h", "// rand_cholQR least squares (randcholqr.hip)")):
         with open(os.path.join(ROOT, "paper_2508_14209_amd", "csrc", f)) as fh:
             text = fh.read()
         h.update(text[:text.index(mark)].encode())
