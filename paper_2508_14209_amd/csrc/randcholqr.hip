@@ -182,14 +182,28 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_rcq_gram(int64_t d, int n, 
   // column and masks the value; only the last, ragged slab takes the
   // guarded path.
   const int64_t nfull = d >> 4;
+  // full slabs: the next slab's operands are loaded into registers while the
+  // current one is multiplied (one slab ahead)
+  v4d qn[NCT], zn = v4d{0.0, 0.0, 0.0, 0.0};
+  auto load_full = [&](int64_t sl_) {
+    const int64_t rr_ = sl_ * 16 + 4 * lk;
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) qn[ct] = load_rows4_full(vcol[ct] ? vcol[ct] : A, rr_);
+    if (NZ > 0) zn = load_rows4_full(zcol, rr_);
+  };
+  {
+    const int64_t sl0 = (int64_t)blockIdx.x * kGramWaves + wave;
+    if (PLAIN && sl0 < nfull) load_full(sl0);
+  }
   for (int64_t sl = (int64_t)blockIdx.x * kGramWaves + wave; PLAIN && sl < nslab; sl += stride) {
     const int64_t rr = sl * 16 + 4 * lk;
     v4d q[NCT];
     v4d zb = v4d{0.0, 0.0, 0.0, 0.0};
     if (sl < nfull) {
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct) q[ct] = load_rows4_full(vcol[ct] ? vcol[ct] : A, rr);
-      if (NZ > 0) zb = load_rows4_full(zcol, rr);
+      for (int ct = 0; ct < NCT; ++ct) q[ct] = qn[ct];
+      if (NZ > 0) zb = zn;
+      if (sl + stride < nfull) load_full(sl + stride);
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct)
         if (!vcol[ct]) q[ct] = v4d{0.0, 0.0, 0.0, 0.0};
