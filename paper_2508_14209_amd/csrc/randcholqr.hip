@@ -3,16 +3,17 @@
 // QR), form Q0 = A R0^{-1}, the Gram matrix Q0^T Q0 and Q0^T B in one pass
 // over A and B, then R1 = chol(Q0^T Q0), R = R1 R0, y = R1^{-T} Q0^T B and
 // x = R^{-1} y.  The result is the least-squares optimum of min ||B - A x||:
-// the sketch only preconditions.
+// the sketch only preconditions.  Without R0 the same kernels solve the
+// normal equations (Sec. 6.3's comparator).
 //
-// The pass over A is the dominant cost (2 d n^2 flops for Q0 and about as
-// much for the Gram matrix, FP64): each persistent workgroup (4 waves) takes
-// blocks of 64 rows; wave w forms the 16-row tile of Q0 = A R0^{-1} on the
-// f64 matrix cores (R0^{-1} staged in LDS, its zero lower blocks skipped),
-// the block [Q0 | B] goes to LDS, and the upper tiles of Q0^T [Q0 | B] are
-// accumulated in registers across all the workgroup's blocks.  Q0 never
-// reaches HBM: A and B are read once.  The workgroups' partial products are
-// summed in a fixed order, then one workgroup factors and solves.
+// The pass over A is the dominant cost (n(n+1) flops per row for Q0 and as
+// many for the upper Gram matrix, FP64): persistent workgroups of eight
+// waves; each wave takes 16-row slabs, forms the slab's Q0 tiles on the f64
+// matrix cores (R0^{-1} staged in LDS, its zero lower blocks skipped) and
+// accumulates the upper tiles of Q0^T [Q0 | B] straight from those result
+// registers (see k_rcq_gram).  Q0 never leaves the registers: A and B are
+// read once.  The waves' and then the workgroups' partial products are
+// summed in a fixed order, then one wave factors and solves.
 #include <algorithm>
 
 #include "ms_internal.h"
