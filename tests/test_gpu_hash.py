@@ -71,6 +71,18 @@ def test_hashed_full_size_fp32(ms, orc):
     assert rel(to_host(Y), Yr) <= 1e-5
 
 
+def test_countsketch_hashed_empty(ms):
+    # no rows: Y is all zero; no columns: nothing to do
+    A = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    Y, ws = ms.countsketch_hashed(A, 16, 5)
+    ms.check_status(ws)
+    assert torch.count_nonzero(Y).item() == 0
+    A = torch.zeros((100, 0), dtype=torch.float64, device="cuda")
+    Y, ws = ms.countsketch_hashed(A, 16, 5)
+    ms.check_status(ws)
+    assert Y.shape == (16, 0)
+
+
 def test_hash_sketch_k_limit(ms):
     # k <= 2^31 - 2, as for every entry point (bucket field 0x7fffffff marks
     # an invalid row)

@@ -38,7 +38,7 @@ def _problem(d, n, nrhs, kappa, seed, dtype=np.float64, noise=1e-2):
 # path) and n + nrhs > 16 NTI + 1 (one more matrix-core tile)
 CASES = [(1000, 3, 1, 1.0), (12345, 8, 2, 10.0), (65537, 16, 3, 10.0), (100003, 33, 1, 10.0),
          (200003, 64, 1, 10.0), (5000, 60, 16, 10.0), (4099, 64, 2, 1.0), (7777, 48, 1, 10.0),
-         (30001, 20, 12, 10.0), (17, 5, 1, 1.0)]
+         (30001, 20, 12, 10.0), (17, 5, 1, 1.0), (10, 3, 2, 1.0)]
 
 
 @pytest.mark.parametrize("d,n,nrhs,kappa", CASES)

@@ -37,7 +37,7 @@ def _problem(d, n, nrhs, kappa, seed, dtype=np.float64, noise=1e-2):
     return (np.asfortranarray(A, dtype=dtype), np.asfortranarray(B, dtype=dtype), h, s, G, k)
 
 
-CASES = [(1000, 3, 1, 1.0), (12345, 8, 2, 1e2), (65537, 16, 3, 10.0), (100000, 33, 1, 1e2),
+CASES = [(10, 3, 1, 1.0), (1000, 3, 1, 1.0), (12345, 8, 2, 1e2), (65537, 16, 3, 10.0), (100000, 33, 1, 1e2),
          (200003, 64, 1, 1e2), (5000, 60, 16, 10.0)]
 
 

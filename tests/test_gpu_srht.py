@@ -47,6 +47,23 @@ def test_srht_parity(ms, orc, m, nc, k, dtype):
     assert rel(to_host(Y), Yr) <= 1e-12
 
 
+def test_srht_many_sampled_rows(ms, orc):
+    # k above the 1024 sampled rows kept in LDS: the indices are read from memory
+    X, dsign, r = _srht_inputs(40000, 3, 1500, seed=11)
+    Y, ws = ms.srht_apply(to_dev(X), to_dev(dsign), to_dev(r))
+    ms.check_status(ws)
+    assert rel(to_host(Y), orc.srht(X, dsign, r)) <= 1e-12
+
+
+def test_srht_no_columns(ms):
+    X = torch.zeros((1000, 0), dtype=torch.float64, device="cuda")
+    dsign = torch.ones(1000, dtype=torch.int8, device="cuda")
+    r = torch.zeros(4, dtype=torch.int32, device="cuda")
+    Y, ws = ms.srht_apply(X, dsign, r)
+    ms.check_status(ws)
+    assert Y.shape == (4, 0)
+
+
 def test_srht_repeatable(ms):
     X, dsign, r = _srht_inputs(300000, 6, 100, seed=5)
     Xd, dd, rd = to_dev(X), to_dev(dsign), to_dev(r)
@@ -105,8 +122,9 @@ def _lstsq_problem(d, n, nrhs, seed, dtype=np.float64):
             dsign, r)
 
 
+# n = 66: k1 = 2 n^2 = 8712 rows, so the second stage spans two 8192-row blocks
 @pytest.mark.parametrize("d,n,nrhs", [(5000, 4, 1), (65537, 16, 2), (200003, 64, 1),
-                                      (100000, 33, 3)])
+                                      (100000, 33, 3), (60000, 66, 1)])
 def test_count_srht_lstsq_parity(ms, orc, d, n, nrhs):
     print("count_srht_lstsq d=%d n=%d nrhs=%d" % (d, n, nrhs), flush=True)
     A, B, h, s, k1, dsign, r = _lstsq_problem(d, n, nrhs, seed=d + n)
