@@ -69,37 +69,53 @@ __device__ __forceinline__ v4d mma64(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// R0^{-1} (64 x 64, row-major, zero outside the leading n x n block) by one
-// wave: lane j solves R0 x = e_j by back substitution, x in registers, step i
-// (from 63 down) x_i = (delta_ij - sum_{l > i} R0[i][l] x_l) / R0[i][i].  Row i
-// of R0 is read from LDS at one address by every lane (a broadcast).  Entries
-// x_l with l > j stay zero, so every lane runs the same 64 steps.
-__global__ __launch_bounds__(64) void k_rcq_trinv(int n, const double *__restrict__ R0, int ldr0,
-                                                  double *__restrict__ Rinv, int *status) {
-  constexpr int L = kRcqMaxN + 1;
-  __shared__ double r0[kRcqMaxN * L];  // row-major: r0[i L + l] = R0[i][l]
-  __shared__ double dinv[kRcqMaxN];
-  const int lane = threadIdx.x;
-  // coalesced column reads (lane = row i), transposed into LDS
-  for (int l = 0; l < kRcqMaxN; ++l)
-    r0[lane * L + l] =
-        (lane < n && l < n && lane <= l) ? R0[lane + (int64_t)l * ldr0] : 0.0;
-  const double dii = lane < n ? R0[lane + (int64_t)lane * ldr0] : 1.0;
-  const bool bad = lane < n && (!(dii != 0.0) || !isfinite(dii));
-  dinv[lane] = lane < n ? 1.0 / dii : 0.0;
-  if (__any(bad) && lane == 0) record_status(status, MS_ERR_SINGULAR);
+// R0^{-1} (64 x 64, row-major, zero outside the leading n x n block) by
+// back substitution, R0 x = e_j for every column j, on four waves: wave w
+// takes columns 16 w .. 16 w + 15 (lane & 15), and the four 16-lane groups
+// g = lane >> 4 of a wave split each step's sum by row residue:
+//   x_i = (delta_ij - sum_{l > i} R0[i][l] x_l) / R0[i][i],
+// group g adding the terms l = g (mod 4) from its 16 registers
+// (x[m] = x_{4m+g}), two xor shuffles giving every group the whole sum.  A
+// wave skips the steps below its columns' rows (x_i = 0 for i > j).
+__global__ __launch_bounds__(256) void k_rcq_trinv(int n, const double *__restrict__ R0, int ldr0,
+                                                   double *__restrict__ Rinv, int *status) {
+  constexpr int N = kRcqMaxN, L = kRcqMaxN + 1;
+  __shared__ double r0[N * L];  // row-major: r0[i L + l] = R0[i][l], zero elsewhere
+  __shared__ double dinv[N];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  for (int t = tid; t < N * N; t += 256) {
+    const int i = t & (N - 1), l = t >> 6;  // coalesced along the column
+    r0[i * L + l] = (i < n && l < n && i <= l) ? R0[i + (int64_t)l * ldr0] : 0.0;
+  }
+  if (tid < N) {
+    const double dii = tid < n ? R0[tid + (int64_t)tid * ldr0] : 1.0;
+    const bool bad = tid < n && (!(dii != 0.0) || !isfinite(dii));
+    dinv[tid] = tid < n ? 1.0 / dii : 0.0;
+    if (__any(bad) && tid == 0) record_status(status, MS_ERR_SINGULAR);
+  }
   __syncthreads();
-  double x[kRcqMaxN];
+  const int j = 16 * w + (lane & 15), g = lane >> 4;
+  double x[N / 4];
 #pragma unroll
-  for (int i = kRcqMaxN - 1; i >= 0; --i) {
-    // four partial sums over l = i + 1 + 4 m + u, added in a fixed order
-    double acc[4] = {i == lane ? 1.0 : 0.0, 0.0, 0.0, 0.0};
+  for (int m = 0; m < N / 4; ++m) x[m] = 0.0;
 #pragma unroll
-    for (int l = i + 1; l < kRcqMaxN; ++l) acc[(l - i - 1) & 3] -= r0[i * L + l] * x[l];
-    x[i] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) * dinv[i];
+  for (int i = N - 1; i >= 0; --i) {
+    if (i > 16 * w + 15) continue;  // wave-uniform: every column of this wave is left of row i
+    double acc[2] = {0.0, 0.0};
+    // terms l = 4 m + g > i; entries at l <= i are zero (r0's lower part, or
+    // the not yet computed x_i), so the static range may start early
+#pragma unroll
+    for (int m = (i + 1) / 4 > 0 ? ((i + 1) / 4 - 1 > 0 ? (i + 1) / 4 - 1 : 0) : 0; m < N / 4; ++m)
+      acc[m & 1] += r0[i * L + 4 * m + g] * x[m];
+    double sum = acc[0] + acc[1];
+    sum += __shfl_xor(sum, 16);
+    sum += __shfl_xor(sum, 32);
+    const double xi = ((i == j) ? 1.0 : 0.0) - sum;
+    if (g == (i & 3)) x[i >> 2] = xi * dinv[i];
   }
 #pragma unroll
-  for (int i = 0; i < kRcqMaxN; ++i) Rinv[i * kRcqMaxN + lane] = x[i];
+  for (int m = 0; m < N / 4; ++m) Rinv[(4 * m + g) * N + j] = x[m];
 }
 
 // The fused pass.  NTI = column tiles of Q0 (n <= 16 NTI).  The columns of
@@ -509,7 +525,7 @@ int rcq_grid() { return dev_info().cus; }
 
 hipError_t launch_rcq_trinv(int n, const double *R0, int ldr0, double *Rinv, int *status,
                             hipStream_t st) {
-  hipLaunchKernelGGL(k_rcq_trinv, dim3(1), dim3(64), 0, st, n, R0, ldr0, Rinv, status);
+  hipLaunchKernelGGL(k_rcq_trinv, dim3(1), dim3(256), 0, st, n, R0, ldr0, Rinv, status);
   return hipGetLastError();
 }
 
