@@ -393,23 +393,29 @@ __global__ __launch_bounds__(64 * kGramWaves) void k_rcq_gram(int64_t d, int n, 
 }
 
 // W = the sum of the nparts partials, element by element: wave q of a
-// workgroup sums partials q, q + 4, ... of 64 consecutive elements in four
-// interleaved running sums (fixed association), and the four waves' sums are
-// added in wave order.
-__global__ __launch_bounds__(256) void k_rcq_reduce(int nparts, const double *__restrict__ part,
-                                                    double *__restrict__ W) {
-  __shared__ double sh[4][64];
+// workgroup (16 waves) sums partials q, q + 16, ... of 64 consecutive
+// elements in four interleaved running sums (added pairwise), and the 16
+// waves' sums are added in wave order -- a fixed association.
+constexpr int kRedW = 16;
+__global__ __launch_bounds__(64 * kRedW) void k_rcq_reduce(int nparts,
+                                                           const double *__restrict__ part,
+                                                           double *__restrict__ W) {
+  __shared__ double sh[kRedW][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int e = blockIdx.x * 64 + lane;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   int p = wave;
-  for (; p + 12 < nparts; p += 16)
+  for (; p + 3 * kRedW < nparts; p += 4 * kRedW)
 #pragma unroll
-    for (int u = 0; u < 4; ++u) s[u] += part[(int64_t)(p + 4 * u) * kPart + e];
-  for (int u = 0; p < nparts; p += 4, ++u) s[u] += part[(int64_t)p * kPart + e];
+    for (int u = 0; u < 4; ++u) s[u] += part[(int64_t)(p + u * kRedW) * kPart + e];
+  for (int u = 0; p < nparts; p += kRedW, ++u) s[u] += part[(int64_t)p * kPart + e];
   sh[wave][lane] = (s[0] + s[1]) + (s[2] + s[3]);
   __syncthreads();
-  if (wave == 0) W[e] = ((sh[0][lane] + sh[1][lane]) + sh[2][lane]) + sh[3][lane];
+  if (wave == 0) {
+    double t = 0.0;
+    for (int v = 0; v < kRedW; ++v) t += sh[v][lane];
+    W[e] = t;
+  }
 }
 
 // One wave: R1 = chol(G) (G = Q0^T Q0, the upper part of W), y = R1^{-T} z
@@ -573,7 +579,7 @@ template hipError_t launch_rcq_gram<float>(int64_t, int, int, const float *, int
 hipError_t launch_rcq_finish(int n, int nrhs, int nparts, const double *part, double *W,
                              const double *R0, int ldr0, const double *Rinv, double *X,
                              int64_t ldx, double *R, int64_t ldr, int *status, hipStream_t st) {
-  hipLaunchKernelGGL(k_rcq_reduce, dim3(kPart / 64), dim3(256), 0, st, nparts, part, W);
+  hipLaunchKernelGGL(k_rcq_reduce, dim3(kPart / 64), dim3(64 * kRedW), 0, st, nparts, part, W);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_rcq_solve, dim3(1), dim3(64), 0, st, n, nrhs, W, R0, ldr0, Rinv, X, ldx,
