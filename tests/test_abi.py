@@ -147,3 +147,59 @@ def test_batch_workspace_size_host_only(ms):
     assert ms._lib.ms_batch_workspace_size(1, (ms.MsProblem * 1)(P), 1, 1, ctypes.byref(bad)) == 0
     assert ms._lib.sketch_lstsq_batched(0, arr, arr, 1, 1, None, ctypes.c_void_p(0x1000), 1 << 30,
                                         None) == ms.MS_ERR_ARG
+
+
+def test_workspace_sizes_of_the_later_rows(ms):
+    # rand_cholQR, normal equations, hash-generated CountSketch, SRHT, Count + SRHT
+    for op, kw in [("rand_cholqr", dict(d=4194304, n=64, nrhs=1, k=8192, k2=128)),
+                   ("normal_equations", dict(d=4194304, n=64, nrhs=1)),
+                   ("countsketch_hashed", dict(d=1 << 24, n=8, k=128, a_dtype=1)),
+                   ("srht", dict(d=4194304, n=64, k=128)),
+                   ("srht", dict(d=5000, n=3, k=16)),
+                   ("count_srht_lstsq", dict(d=4194304, n=64, nrhs=1, k=8192, k2=128))]:
+        sz = ms.workspace_size(op, **kw)
+        assert sz >= 256 and sz % 256 == 0, (op, kw, sz)
+    # the SRHT keeps per-block partials only past one 8192-row block:
+    # 512 blocks x 64 columns x 128 rows x 8 bytes for 4,194,304 rows
+    assert ms.workspace_size("srht", d=4194304, n=64, k=128) >= 512 * 64 * 128 * 8
+    assert ms.workspace_size("srht", d=8192, n=64, k=128) < 4096
+
+
+def test_later_rows_reject_invalid_arguments_on_host(ms):
+    lib = ms._lib
+    ws = ctypes.c_void_p(0x1000)  # never dereferenced: every call below fails validation first
+    P = ctypes.c_void_p(0x2000)
+    o = ms.MsOpts(0, 0, 0, 0, 0, 0, 0, 0)
+    refine = ms.MsOpts(0, 1, 0, 0, 0, 0, 0, 0)
+    sorted_ = ms.MsOpts(3, 0, 0, 0, 0, 0, 0, 0)
+    big = 1 << 30
+    # normal equations: n > 64, nrhs > 16 unsupported; nrhs = 0 invalid
+    assert lib.normal_equations_lstsq(100, 65, 1, 0, P, 100, P, 100, P, 65, None, 65, None, ws,
+                                      big, None) == ms.MS_ERR_UNSUPPORTED
+    assert lib.normal_equations_lstsq(100, 8, 17, 0, P, 100, P, 100, P, 8, None, 8, None, ws,
+                                      big, None) == ms.MS_ERR_UNSUPPORTED
+    assert lib.normal_equations_lstsq(100, 8, 0, 0, P, 100, P, 100, P, 8, None, 8, None, ws,
+                                      big, None) == ms.MS_ERR_ARG
+    # rand_cholQR: no refinement steps; k2 >= n
+    assert lib.rand_cholqr_lstsq(100, 8, 1, 128, 16, 0, P, 100, P, 100, P, P, 0, P, 16, P, 8,
+                                 None, 8, ctypes.byref(refine), ws, big, None) == ms.MS_ERR_ARG
+    assert lib.rand_cholqr_lstsq(100, 8, 1, 128, 4, 0, P, 100, P, 100, P, P, 0, P, 4, P, 8,
+                                 None, 8, ctypes.byref(o), ws, big, None) == ms.MS_ERR_ARG
+    # hash-generated CountSketch: LDS schedule only; k in [1, 2^31 - 2]
+    assert lib.countsketch_hashed(100, 2, 16, 7, 0, P, 100, P, 16, ctypes.byref(sorted_), ws, big,
+                                  None) == ms.MS_ERR_UNSUPPORTED
+    assert lib.countsketch_hashed(100, 2, 0, 7, 0, P, 100, P, 16, ctypes.byref(o), ws, big,
+                                  None) == ms.MS_ERR_ARG
+    assert lib.ms_hash_sketch(10, 0, 1, P, P, None) == ms.MS_ERR_ARG
+    assert lib.ms_hash_sketch(10, (1 << 31) - 1, 1, P, P, None) == ms.MS_ERR_ARG
+    assert lib.ms_hash_sketch(10, 16, 1, None, P, None) == ms.MS_ERR_ARG
+    # SRHT: m >= 1, k >= 1, at most 65535 columns, FP64 or FP32 data
+    assert lib.srht_apply(0, 2, 4, 0, P, 1, P, P, P, 4, ws, big, None) == ms.MS_ERR_ARG
+    assert lib.srht_apply(100, 2, 0, 0, P, 100, P, P, P, 4, ws, big, None) == ms.MS_ERR_ARG
+    assert lib.srht_apply(100, 70000, 4, 0, P, 100, P, P, P, 4, ws, big, None) == ms.MS_ERR_ARG
+    assert lib.srht_apply(100, 2, 4, 2, P, 100, P, P, P, 4, ws, big, None) == ms.MS_ERR_ARG
+    # Count + SRHT least squares: k2 >= n, no refinement
+    assert lib.count_srht_lstsq(100, 8, 1, 128, 4, 0, P, 100, P, 100, P, P, P, P, P, 8,
+                                ctypes.byref(o), ws, big, None) == ms.MS_ERR_ARG
+    assert lib.count_srht_lstsq(100, 8, 1, 128, 16, 0, P, 100, P, 100, P, P, P, P, P, 8,
+                                ctypes.byref(refine), ws, big, None) == ms.MS_ERR_ARG
