@@ -204,3 +204,46 @@ def test_bucket_uniformity_chi2():
     assert 255 - 6 * 22.6 < chi2 < 255 + 6 * 22.6
     s = synth.signs(d, seed=14)
     assert set(np.unique(s)) == {-1, 1} and abs(int(s.astype(np.int64).sum())) < 6 * np.sqrt(d)
+
+
+# --- FP32 data folded in FP64 (the "plain FP64" reading of an FP32 matrix) ---
+
+def test_f32_acc64_equals_f64_fold_of_promoted_data(orc):
+    # Promoting FP32 to FP64 is exact, so Def. 3 folded in FP64 over the FP32
+    # values and over their FP64 images is the same computation: bit-equal.
+    d, n, k = 6000, 5, 96
+    h = synth.bucket_map(d, k, seed=21)
+    s = synth.signs(d, seed=21)
+    A32 = synth.normal_matrix(d, n, seed=21).astype(np.float32)
+    Y = orc.countsketch(A32, h, s, k, acc="f64")
+    assert Y.dtype == np.float64
+    ref = orc.countsketch(A32.astype(np.float64), h, s, k)
+    assert np.array_equal(Y.view(np.uint64), ref.view(np.uint64))
+
+
+def test_f32_acc64_dense_brute_force_beyond_float_precision(orc):
+    # Integer-valued FP32 entries near 2^23: every partial sum of a bucket is
+    # an integer below 2^53, so the FP64 fold is exact and must equal the dense
+    # S of Def. 3 times A; the same sums overflow FP32's 24-bit significand, so
+    # a fold in float (or a dropped or flipped sign) cannot match.
+    d, n, k = 4096, 3, 8
+    h = synth.bucket_map(d, k, seed=22)
+    s = synth.signs(d, seed=22)
+    g = np.random.default_rng(22)
+    A = ((1 << 23) + g.integers(0, 1 << 20, size=(d, n))).astype(np.float32)
+    Y = orc.countsketch(A, h, s, k, acc="f64")
+    exact = dense_sketch(h, s, k).astype(np.int64) @ A.astype(np.int64)
+    assert np.array_equal(Y, exact.astype(np.float64))
+    Y32 = orc.countsketch(A, h, s, k).astype(np.float64)
+    assert not np.array_equal(Y32, Y)   # the float fold does round here
+
+
+def test_f32_acc64_keeps_small_terms(orc):
+    # 1 + 2^-30 - 1 in one bucket: FP64 keeps 2^-30 (an FP32 fold would give
+    # 0); the rows of the other bucket, signs included, give -(3 + 2^-29).
+    A = np.array([[1.0], [2.0 ** -30], [3.0], [-1.0], [2.0 ** -29]], np.float32)
+    h = np.array([0, 0, 1, 0, 1], np.int32)
+    s = np.array([1, 1, -1, 1, -1], np.int8)
+    Y = orc.countsketch(A, h, s, 2, acc="f64")
+    assert Y[0, 0] == 2.0 ** -30
+    assert Y[1, 0] == -(3.0 + 2.0 ** -29)

@@ -25,6 +25,11 @@ MUTANTS = [
      "Y[m + c * ldy] = Y[m + c * ldy] + (s[i] < 0 ? a : -a);", 1),
     ("cs64_fold_reversed", "for (int64_t i = 0; i < d; ++i) {\n    const int64_t m = h[i];",
      "for (int64_t i = d - 1; i >= 0; --i) {\n    const int64_t m = h[i];", 0),
+    # FP32 data folded in FP64: a float fold and a flipped sign
+    ("cs32acc64_float_fold", "const double a = (double)A[i + c * lda];\n      Y[m + c * ldy] = Y[m + c * ldy] + (s[i] > 0 ? a : -a);",
+     "const float a = A[i + c * lda];\n      Y[m + c * ldy] = (float)((float)Y[m + c * ldy] + (s[i] > 0 ? a : -a));", 0),
+    ("cs32acc64_sign_flipped", "Y[m + c * ldy] = Y[m + c * ldy] + (s[i] > 0 ? a : -a);",
+     "Y[m + c * ldy] = Y[m + c * ldy] + (s[i] < 0 ? a : -a);", 2),
     ("cs64_bucket_shift", "const int64_t m = h[i];", "const int64_t m = (h[i] + 1) % k;", 0),
     ("cs64_init_neg_zero", "for (int64_t m = 0; m < k; ++m) Y[m + c * ldy] = +0.0;",
      "for (int64_t m = 0; m < k; ++m) Y[m + c * ldy] = -0.0;", 0),
