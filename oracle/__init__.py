@@ -271,12 +271,14 @@ def normal_equations(A, B) -> np.ndarray:
 # Composite multisketch sketch-and-solve (Alg. 1 with S = G C)
 # --------------------------------------------------------------------------
 
-def sketch_lstsq(A, B, h, s, G, k: int, y_bf16: bool = False):
+def sketch_lstsq(A, B, h, s, G, k: int, y_bf16: bool = False, y_acc64: bool = False):
     """X = argmin ||G C (B - A X)|| via Alg. 1 with the multisketch S = G C.
 
-    FP64 A: CountSketch in FP64.  FP32 A: CountSketch in FP32, optional RNE
-    rounding of the sketch to BF16 (``y_bf16``), Gaussian stage and QR in
-    FP64 on the exact FP64 images of the stored values.  G is passed as its
+    FP64 A: CountSketch in FP64.  FP32 A: CountSketch in FP32 (folded in FP32
+    in the canonical order, or with ``y_acc64`` Def. 3's sums taken in FP64
+    and rounded once to FP32), optional RNE rounding of the sketch to BF16
+    (``y_bf16``), Gaussian stage and QR in FP64 on the exact FP64 images of
+    the stored values.  G is passed as its
     stored values (float64, float32 or BF16 values held in float32/float64).
     Returns (X, Y, Z): solution n x nrhs, CountSketch k x (n+nrhs) and the
     Gaussian-stage output k2 x (n+nrhs).
@@ -310,7 +312,8 @@ def sketch_lstsq(A, B, h, s, G, k: int, y_bf16: bool = False):
         Z = np.zeros((k2, n + nrhs), dtype=np.float64, order="F")
         rc = lib.or_sketch_lstsq_f32(d, n, nrhs, k, k2, _ptr(A), _ld(A), _ptr(B),
                                      _ld(B), _ptr(h), _ptr(s), _ptr(Gd), _ld(Gd),
-                                     1 if y_bf16 else 0, _ptr(X), max(1, n),
+                                     (1 if y_bf16 else 0) | (2 if y_acc64 else 0),
+                                     _ptr(X), max(1, n),
                                      _ptr(Y), _ptr(Z))
     else:
         raise TypeError("sketch_lstsq oracle takes float64 or float32 A")

@@ -421,12 +421,24 @@ int or_sketch_lstsq_f32(int64_t d, int64_t n, int64_t nrhs, int64_t k,
     free(Z);
     return ORACLE_ERR_NOMEM;
   }
-  int st = or_countsketch_f32(d, n, k, A, lda, h, s, Y, k);
-  if (st == ORACLE_OK)
-    st = or_countsketch_f32(d, nrhs, k, B, ldb, h, s, Y + n * k, k);
+  int st;
+  if (y_bf16 & ORACLE_Y_ACC64) {
+    /* Def. 3's sums taken in FP64 (exact for these FP32 terms up to FP64
+     * rounding) and rounded once to FP32: the FP32 sketch closest to the
+     * exact one */
+    st = or_countsketch_f32_acc64(d, n, k, A, lda, h, s, Yd, k);
+    if (st == ORACLE_OK)
+      st = or_countsketch_f32_acc64(d, nrhs, k, B, ldb, h, s, Yd + n * k, k);
+    if (st == ORACLE_OK)
+      for (int64_t t = 0; t < k * nc; ++t) Y[t] = (float)Yd[t];
+  } else {
+    st = or_countsketch_f32(d, n, k, A, lda, h, s, Y, k);
+    if (st == ORACLE_OK)
+      st = or_countsketch_f32(d, nrhs, k, B, ldb, h, s, Y + n * k, k);
+  }
   if (st == ORACLE_OK) {
     for (int64_t t = 0; t < k * nc; ++t)
-      Yd[t] = (double)(y_bf16 ? or_round_bf16(Y[t]) : Y[t]);
+      Yd[t] = (double)((y_bf16 & ORACLE_Y_BF16) ? or_round_bf16(Y[t]) : Y[t]);
     or_gemm_f64(k2, nc, k, G, ldg, Yd, k, Z, k2);
     st = or_qr_solve(k2, n, nrhs, Z, k2, Z + n * k2, k2, X, ldx);
   }

@@ -46,6 +46,11 @@ int or_sketch_lstsq_f64(int64_t d, int64_t n, int64_t nrhs, int64_t k,
                         double *X, int64_t ldx, double *Ys, double *Zs);
 float or_round_bf16(float x);
 void or_round_bf16_array(int64_t count, const float *x, float *out);
+/* flags of or_sketch_lstsq_f32: round the FP32 sketch to BF16 before the
+ * Gaussian stage; form the FP32 sketch as Def. 3's sums in FP64 rounded once
+ * to FP32 (else folded in FP32, the canonical order) */
+#define ORACLE_Y_BF16 1
+#define ORACLE_Y_ACC64 2
 int or_sketch_lstsq_f32(int64_t d, int64_t n, int64_t nrhs, int64_t k,
                         int64_t k2, const float *A, int64_t lda,
                         const float *B, int64_t ldb, const int32_t *h,

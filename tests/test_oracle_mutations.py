@@ -50,6 +50,11 @@ MUTANTS = [
     ("ne_forward_wrong_index", "acc = acc - Gm[t + i * n] * x[t];", "acc = acc - Gm[i + t * n] * x[t];", 0),
     ("composite_rhs_offset", "st = or_countsketch_f64(d, nrhs, k, B, ldb, h, s, Y + n * k, k);",
      "st = or_countsketch_f64(d, nrhs, k, B, ldb, h, s, Y + (n - 1) * k, k);", 0),
+    # the FP64-fold FP32 sketch of the FP32 least-squares path
+    ("acc64_rhs_offset", "st = or_countsketch_f32_acc64(d, nrhs, k, B, ldb, h, s, Yd + n * k, k);",
+     "st = or_countsketch_f32_acc64(d, nrhs, k, B, ldb, h, s, Yd + (n - 1) * k, k);", 0),
+    ("acc64_rounds_to_bf16", "for (int64_t t = 0; t < k * nc; ++t) Y[t] = (float)Yd[t];",
+     "for (int64_t t = 0; t < k * nc; ++t) Y[t] = or_round_bf16((float)Yd[t]);", 0),
     ("bf16_ties_away", "u = u + 0x7fffu + lsb;", "u = u + 0x8000u + 0 * lsb;", 0),
     # rand_cholQR least squares (Alg. 5)
     ("rcq_no_cholesky_correction", "for (int64_t t = i; t <= j; ++t) acc = acc + Gm[i + t * n] * W[t + j * m];",

@@ -253,3 +253,30 @@ def test_lstsq_tsqr_matches_lapack_and_exact_cases(orc):
     b = q[:, -1:]
     X3, res3 = orc.lstsq_tsqr(A, b, block_rows=300)
     assert np.abs(X3).max() <= 1e-10 and abs(res3[0] - 1.0) <= 1e-12
+
+
+def test_fp32_path_acc64_sketch_is_correctly_rounded_exact_sum(orc):
+    # With y_acc64 the FP32 sketch is Def. 3's exact bucket sum rounded once
+    # to FP32: math.fsum gives the correctly rounded FP64 value of each exact
+    # sum (A's and B's columns alike), which then rounds to the same FP32.
+    import math
+    d, n, nrhs, k, k2 = 3000, 3, 2, 48, 8
+    A = synth.normal_matrix(d, n, seed=31, dtype=np.float32)
+    B = synth.normal_matrix(d, nrhs, seed=32, dtype=np.float32)
+    h = synth.bucket_map(d, k, seed=31)
+    s = synth.signs(d, seed=31)
+    G = synth.gaussian_sketch(k2, k, seed=31)
+    X, Y, Z = orc.sketch_lstsq(A, B, h, s, G, k, y_acc64=True)
+    AB = np.hstack([A, B]).astype(np.float64)
+    expect = np.zeros((k, n + nrhs), np.float32)
+    for m in range(k):
+        rows = np.nonzero(h == m)[0]
+        for c in range(n + nrhs):
+            expect[m, c] = np.float32(math.fsum(float(s[i]) * AB[i, c] for i in rows))
+    assert np.array_equal(Y, expect)
+    # the rest of the path takes those values: Z = G Y in FP64
+    assert np.allclose(Z, G @ Y.astype(np.float64), rtol=0, atol=1e-12 * np.abs(Z).max())
+    # the FP32 fold of the same data is a different (less accurate) sketch
+    _, Y32, _ = orc.sketch_lstsq(A, B, h, s, G, k)
+    assert not np.array_equal(Y32, Y)
+    assert np.abs(Y32.astype(np.float64) - expect).max() < 1e-5 * np.abs(expect).max()
