@@ -58,6 +58,8 @@ def _load():
             "or_countsketch_f64": [_i64, _i64, _i64, _p, _i64, _p, _p, _p, _i64],
             "or_countsketch_f32": [_i64, _i64, _i64, _p, _i64, _p, _p, _p, _i64],
             "or_countsketch_f32_acc64": [_i64, _i64, _i64, _p, _i64, _p, _p, _p, _i64],
+            "or_countsketch_f64_cols": [_i64, _i64, _i64, _p, _i64, _p, _p, _p, _i64,
+                                        ctypes.c_int],
             "or_bucket_hist": [_i64, _i64, _p, _p],
             "or_bucket_plan": [_i64, _i64, _p, _p, _p],
             "or_gemm_f64": [_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64],
@@ -123,13 +125,14 @@ def _check(code: int, what: str):
 # CountSketch: Def. 3, Eq. (2), Alg. 2
 # --------------------------------------------------------------------------
 
-def countsketch(A, h, s, k: int, acc: str | None = None) -> np.ndarray:
+def countsketch(A, h, s, k: int, acc: str | None = None, threads: int = 1) -> np.ndarray:
     """Y = S A, S the CountSketch with buckets h (0-based) and signs s (+-1).
 
     Canonical fold: for each bucket, rows are added in ascending row order
     starting from +0.0, in the accumulation precision (A's own precision unless
     ``acc='f64'`` for an FP32 A).  Def. 3 and Eq. (2); the add-or-subtract form
-    of Alg. 2.
+    of Alg. 2.  ``threads`` > 1 (FP64 A): the same fold with the columns split
+    over that many host threads (bit-identical; for timing on all cores).
     """
     A = np.asarray(A)
     lib = _load()
@@ -139,8 +142,12 @@ def countsketch(A, h, s, k: int, acc: str | None = None) -> np.ndarray:
         A = _fortran(A, np.float64)
         d, n = A.shape
         Y = np.zeros((k, n), dtype=np.float64, order="F")
-        rc = lib.or_countsketch_f64(d, n, k, _ptr(A), _ld(A), _ptr(h), _ptr(s),
-                                    _ptr(Y), max(1, k))
+        if threads > 1:
+            rc = lib.or_countsketch_f64_cols(d, n, k, _ptr(A), _ld(A), _ptr(h), _ptr(s),
+                                             _ptr(Y), max(1, k), int(threads))
+        else:
+            rc = lib.or_countsketch_f64(d, n, k, _ptr(A), _ld(A), _ptr(h), _ptr(s),
+                                        _ptr(Y), max(1, k))
     elif A.dtype == np.float32 and acc == "f64":
         A = _fortran(A, np.float32)
         d, n = A.shape

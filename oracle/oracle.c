@@ -24,6 +24,7 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <pthread.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -93,6 +94,68 @@ int or_countsketch_f32_acc64(int64_t d, int64_t n, int64_t k, const float *A,
       Y[m + c * ldy] = Y[m + c * ldy] + (s[i] > 0 ? a : -a);
     }
   }
+  return ORACLE_OK;
+}
+
+/* The same FP64 fold on several host threads, split by column: each column
+ * is folded by one thread in exactly the canonical order above (ascending
+ * rows from +0.0), and columns do not interact, so the result is bit for bit
+ * that of or_countsketch_f64.  Used to time the oracle on all host cores. */
+typedef struct {
+  int64_t d, k, c0, c1, lda, ldy;
+  const double *A;
+  const int32_t *h;
+  const int8_t *s;
+  double *Y;
+} or_cs_cols_job;
+
+static void *or_cs_cols_run(void *arg) {
+  const or_cs_cols_job *j = (const or_cs_cols_job *)arg;
+  for (int64_t c = j->c0; c < j->c1; ++c)
+    for (int64_t m = 0; m < j->k; ++m) j->Y[m + c * j->ldy] = +0.0;
+  for (int64_t i = 0; i < j->d; ++i) {
+    const int64_t m = j->h[i];
+    for (int64_t c = j->c0; c < j->c1; ++c) {
+      const double a = j->A[i + c * j->lda];
+      j->Y[m + c * j->ldy] = j->Y[m + c * j->ldy] + (j->s[i] > 0 ? a : -a);
+    }
+  }
+  return NULL;
+}
+
+int or_countsketch_f64_cols(int64_t d, int64_t n, int64_t k, const double *A,
+                            int64_t lda, const int32_t *h, const int8_t *s,
+                            double *Y, int64_t ldy, int nthreads) {
+  for (int64_t i = 0; i < d; ++i)
+    if (h[i] < 0 || h[i] >= k || (s[i] != 1 && s[i] != -1))
+      return ORACLE_ERR_RANGE;
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > n) nthreads = n > 0 ? (int)n : 1;
+  pthread_t *th = (pthread_t *)malloc((size_t)nthreads * sizeof(pthread_t));
+  int *live = (int *)calloc((size_t)nthreads, sizeof(int));
+  or_cs_cols_job *jobs = (or_cs_cols_job *)malloc((size_t)nthreads * sizeof(or_cs_cols_job));
+  if (!th || !live || !jobs) {
+    free(th);
+    free(live);
+    free(jobs);
+    return ORACLE_ERR_NOMEM;
+  }
+  for (int t = 0; t < nthreads; ++t) {
+    or_cs_cols_job j = {d, k, n * t / nthreads, n * (t + 1) / nthreads, lda, ldy, A, h, s, Y};
+    jobs[t] = j;
+  }
+  for (int t = 1; t < nthreads; ++t)
+    live[t] = pthread_create(&th[t], NULL, or_cs_cols_run, &jobs[t]) == 0;
+  or_cs_cols_run(&jobs[0]);
+  for (int t = 1; t < nthreads; ++t) {
+    if (live[t])
+      pthread_join(th[t], NULL);
+    else
+      or_cs_cols_run(&jobs[t]); /* no thread could start: fold those columns here */
+  }
+  free(th);
+  free(live);
+  free(jobs);
   return ORACLE_OK;
 }
 

@@ -22,6 +22,11 @@ int or_countsketch_f32(int64_t d, int64_t n, int64_t k, const float *A,
 int or_countsketch_f32_acc64(int64_t d, int64_t n, int64_t k, const float *A,
                              int64_t lda, const int32_t *h, const int8_t *s,
                              double *Y, int64_t ldy);
+/* or_countsketch_f64 with its columns split over nthreads host threads
+ * (bit-identical: each column is folded in the canonical order) */
+int or_countsketch_f64_cols(int64_t d, int64_t n, int64_t k, const double *A,
+                            int64_t lda, const int32_t *h, const int8_t *s,
+                            double *Y, int64_t ldy, int nthreads);
 int or_bucket_hist(int64_t d, int64_t k, const int32_t *h, int64_t *cnt);
 int or_bucket_plan(int64_t d, int64_t k, const int32_t *h, int64_t *off,
                    int64_t *perm);

@@ -247,3 +247,21 @@ def test_f32_acc64_keeps_small_terms(orc):
     Y = orc.countsketch(A, h, s, 2, acc="f64")
     assert Y[0, 0] == 2.0 ** -30
     assert Y[1, 0] == -(3.0 + 2.0 ** -29)
+
+
+@pytest.mark.parametrize("threads", [2, 3, 8, 64])
+def test_column_parallel_fold_bit_identical(orc, threads):
+    # the all-cores timing variant folds each column on one thread in the
+    # canonical order: bit for bit the sequential fold (including with more
+    # threads than columns, and for rounding-sensitive data)
+    d, n, k = 20000, 7, 300
+    h = synth.bucket_map(d, k, seed=41)
+    s = synth.signs(d, seed=41)
+    A = synth.normal_matrix(d, n, seed=41) * np.logspace(0, 12, n)[None, :]
+    ref = orc.countsketch(A, h, s, k)
+    Y = orc.countsketch(A, h, s, k, threads=threads)
+    assert np.array_equal(Y.view(np.uint64), ref.view(np.uint64))
+    hb = h.copy()
+    hb[5] = k
+    with pytest.raises(orc.OracleError):
+        orc.countsketch(A, hb, s, k, threads=threads)

@@ -30,6 +30,10 @@ MUTANTS = [
      "const float a = A[i + c * lda];\n      Y[m + c * ldy] = (float)((float)Y[m + c * ldy] + (s[i] > 0 ? a : -a));", 0),
     ("cs32acc64_sign_flipped", "Y[m + c * ldy] = Y[m + c * ldy] + (s[i] > 0 ? a : -a);",
      "Y[m + c * ldy] = Y[m + c * ldy] + (s[i] < 0 ? a : -a);", 2),
+    ("cols_fold_sign_dropped", "j->Y[m + c * j->ldy] = j->Y[m + c * j->ldy] + (j->s[i] > 0 ? a : -a);",
+     "j->Y[m + c * j->ldy] = j->Y[m + c * j->ldy] + a;", 0),
+    ("cols_split_skips_last_column", "or_cs_cols_job j = {d, k, n * t / nthreads, n * (t + 1) / nthreads,",
+     "or_cs_cols_job j = {d, k, n * t / nthreads, n * (t + 1) / nthreads - (t + 1 == nthreads),", 0),
     ("cs64_bucket_shift", "const int64_t m = h[i];", "const int64_t m = (h[i] + 1) % k;", 0),
     ("cs64_init_neg_zero", "for (int64_t m = 0; m < k; ++m) Y[m + c * ldy] = +0.0;",
      "for (int64_t m = 0; m < k; ++m) Y[m + c * ldy] = -0.0;", 0),
