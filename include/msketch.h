@@ -87,7 +87,15 @@ typedef struct {
   int32_t batch_kchunk_log2; /* sketch_lstsq_batched tuning: K per Gaussian-
                                 stage work item = 2^x (0 = automatic, else
                                 5..20) */
-  int32_t reserved0;
+  int32_t gauss_y_terms;     /* BF16 Gaussian stage (multisketch_apply,
+                                sketch_lstsq, rand_cholqr_lstsq,
+                                sketch_lstsq_batched): 1 = Y rounded to BF16
+                                (nearest even); 3 = Y split into three BF16
+                                terms hi + mid + lo that sum to Y exactly, so
+                                G Y is formed from the exact Y with FP32
+                                accumulation (three matrix-core products per
+                                step, G read once); 0 = 3.  Other values:
+                                MS_ERR_ARG. */
   int32_t reserved1;
 } ms_opts;
 
@@ -357,7 +365,11 @@ ms_status count_srht_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k1,
  *   (A's dtype, ldb >= d), X n x nrhs FP64 (ldx >= n); R (may be NULL):
  *   n x n (ldr >= n), receives R (upper triangular, zeros below).
  *   opts is unused (may be NULL).
- * Limits: n <= 64, nrhs <= 16 (else MS_ERR_UNSUPPORTED).  Device status:
+ * Limits: n <= 256, nrhs <= 16, n + nrhs <= 272 (else MS_ERR_UNSUPPORTED).
+ * Up to 64 columns (n + nrhs <= 80) one fused pass accumulates the Gram
+ * matrix in registers; wider problems take a tiled Gram pass (per-chunk
+ * partials of its upper 16 x 16 tiles, summed in chunk order) and a blocked
+ * Cholesky (64 x 64 blocks).  Device status:
  * MS_ERR_SINGULAR (X = NaN) when the Cholesky factorisation breaks down.
  * ws: ms_workspace_size(MS_OP_NORMAL_EQUATIONS, d, n, nrhs, 0, 0, a_dtype,
  * 0, NULL) bytes.

@@ -55,7 +55,7 @@ class MsOpts(ctypes.Structure):
     _fields_ = [("cs_mode", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
                 ("cs_tile_cols", ctypes.c_int32), ("cs_schedule", ctypes.c_int32),
                 ("batch_rows_log2", ctypes.c_int32), ("batch_kchunk_log2", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("gauss_y_terms", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 
 
 class MsProblem(ctypes.Structure):
@@ -164,9 +164,9 @@ def _stream(stream):
 
 
 def _opts(mode: str = "auto", refine_steps: int = 0, tile_cols: int = 0, schedule: int = 0,
-          rows_log2: int = 0, kchunk_log2: int = 0):
+          rows_log2: int = 0, kchunk_log2: int = 0, y_terms: int = 0):
     return MsOpts(MODES[mode], int(refine_steps), int(tile_cols), int(schedule), int(rows_log2),
-                  int(kchunk_log2), 0, 0)
+                  int(kchunk_log2), int(y_terms), 0)
 
 
 def workspace_size(op: str, d=0, n=0, nrhs=0, k=0, k2=0, a_dtype=MS_F64, g_dtype=MS_F64,
@@ -382,8 +382,9 @@ def gaussian_apply(G: torch.Tensor, Y: torch.Tensor, Z: torch.Tensor | None = No
 
 def multisketch_apply(A: torch.Tensor, h: torch.Tensor, s: torch.Tensor, G: torch.Tensor,
                       k: int, Z: torch.Tensor | None = None, mode: str = "auto",
-                      ws: torch.Tensor | None = None, stream=None):
-    """Z = G (S A) (k2 x n).  Returns (Z, ws)."""
+                      ws: torch.Tensor | None = None, stream=None, y_terms: int = 0):
+    """Z = G (S A) (k2 x n).  y_terms (BF16 G): 1 = S A rounded to BF16, 3 (or
+    0, the default) = S A as three exact BF16 terms.  Returns (Z, ws)."""
     d, n = A.shape
     k2 = G.shape[0]
     a_dt, g_dt = _dt(A), _dt(G)
@@ -397,7 +398,7 @@ def multisketch_apply(A: torch.Tensor, h: torch.Tensor, s: torch.Tensor, G: torc
                           mode=mode)
     ws = workspace(need, A.device) if ws is None else ws
     wp, have = _ws_ptr(ws, need)
-    o = _opts(mode)
+    o = _opts(mode, y_terms=y_terms)
     _ok(_lib.multisketch_apply(d, n, k, k2, a_dt, Ap, lda,
                                _vec(h, torch.int32, "h") if d else None,
                                _vec(s, torch.int8, "s") if d else None, g_dt, Gp, ldg, Zp, ldz,
@@ -430,7 +431,7 @@ def qr_solve(W: torch.Tensor, B: torch.Tensor, X: torch.Tensor | None = None,
 def sketch_lstsq(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torch.Tensor,
                  G: torch.Tensor, k: int, refine_steps: int = 0, mode: str = "auto",
                  X: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None,
-                 tile_cols: int = 0, schedule: int = 0):
+                 tile_cols: int = 0, schedule: int = 0, y_terms: int = 0):
     """X = argmin || G C (B - A X) || (n x nrhs, FP64).  Returns (X, ws)."""
     d, n = A.shape
     if B.dim() == 1:
@@ -450,7 +451,7 @@ def sketch_lstsq(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torch.Ten
                           g_dtype=g_dt, mode=mode, refine_steps=refine_steps)
     ws = workspace(need, A.device) if ws is None else ws
     wp, have = _ws_ptr(ws, need)
-    o = _opts(mode, refine_steps, tile_cols, schedule)
+    o = _opts(mode, refine_steps, tile_cols, schedule, y_terms=y_terms)
     _ok(_lib.sketch_lstsq(d, n, nrhs, k, k2, a_dt, Ap, lda, Bp, ldb, _vec(h, torch.int32, "h"),
                           _vec(s, torch.int8, "s"), g_dt, Gp, ldg, Xp, ldx, ctypes.byref(o), wp,
                           have, _stream(stream)), "sketch_lstsq")
@@ -459,7 +460,8 @@ def sketch_lstsq(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torch.Ten
 
 def rand_cholqr_lstsq(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torch.Tensor,
                       G: torch.Tensor, k: int, mode: str = "auto", X: torch.Tensor | None = None,
-                      R: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None):
+                      R: torch.Tensor | None = None, ws: torch.Tensor | None = None, stream=None,
+                      y_terms: int = 0):
     """X = argmin ||B - A X|| by rand_cholQR least squares with the multisketch
     G C as the sketch operator (n x nrhs, FP64; the least-squares optimum, no
     sketch distortion).  R (optional, n x n FP64) receives the R factor of A.
@@ -483,7 +485,7 @@ def rand_cholqr_lstsq(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torc
                           g_dtype=g_dt, mode=mode)
     ws = workspace(need, A.device) if ws is None else ws
     wp, have = _ws_ptr(ws, need)
-    o = _opts(mode, 0)
+    o = _opts(mode, 0, y_terms=y_terms)
     _ok(_lib.rand_cholqr_lstsq(d, n, nrhs, k, k2, a_dt, Ap, lda, Bp, ldb, _vec(h, torch.int32, "h"),
                                _vec(s, torch.int8, "s"), g_dt, Gp, ldg, Xp, ldx, Rp, ldr,
                                ctypes.byref(o), wp, have, _stream(stream)), "rand_cholqr_lstsq")
@@ -537,16 +539,26 @@ def _describe(prob: dict) -> MsProblem:
 
 
 def _host_array(problems):
+    """ms_problem array of problem dicts, or of (d, n, nrhs, k, k2) shape
+    tuples (capacity sets only: the host-side descriptors that size the
+    workspace and the launch shapes; their pointers are placeholders that no
+    kernel reads -- the kernels read the device descriptors of the problems
+    being solved)."""
     arr = (MsProblem * len(problems))()
     for i, pr in enumerate(problems):
-        arr[i] = _describe(pr)
+        if isinstance(pr, tuple):
+            d, n, nrhs, k, k2 = (int(v) for v in pr)
+            ph = 256
+            arr[i] = MsProblem(d, n, nrhs, k, k2, ph, d, ph, d, ph, ph, ph, k2, ph, n)
+        else:
+            arr[i] = _describe(pr)
     return arr
 
 
 def batch_workspace_size(problems, a_dtype: int, g_dtype: int, rows_log2: int = 0,
-                         kchunk_log2: int = 0, refine_steps: int = 0) -> int:
+                         kchunk_log2: int = 0, refine_steps: int = 0, y_terms: int = 0) -> int:
     arr = _host_array(problems)
-    o = _opts("auto", refine_steps, 0, 0, rows_log2, kchunk_log2)
+    o = _opts("auto", refine_steps, 0, 0, rows_log2, kchunk_log2, y_terms)
     sz = _lib.ms_batch_workspace_size(len(problems), arr, a_dtype, g_dtype, ctypes.byref(o))
     if sz == 0:
         raise MsketchError(MS_ERR_ARG, "ms_batch_workspace_size")
@@ -567,20 +579,20 @@ class BatchRunner:
 
     ``problems``: list of dicts with device tensors A (d x n), B (d x nrhs),
     h (int32, d), s (int8, d), G (k2 x k), X (n x nrhs, FP64) and int k.
-    ``capacity``: problems that bound later ones (same count, each no larger
-    in k, k2, n + nrhs, and with refinement in d * nrhs); defaults to
-    ``problems``.  ``refine_steps``: FP64-residual refinement steps (each
+    ``capacity``: problems that bound later ones (same count; the later
+    sets' totals of sketch, partial, factor and residual sizes no larger);
+    problem dicts or (d, n, nrhs, k, k2) tuples; defaults to ``problems``.  ``refine_steps``: FP64-residual refinement steps (each
     problem then needs nrhs <= 8).
     """
 
     def __init__(self, problems, capacity=None, rows_log2: int = 0, kchunk_log2: int = 0,
-                 refine_steps: int = 0):
+                 refine_steps: int = 0, y_terms: int = 0):
         if not problems:
             raise ValueError("empty batch")
         self.count = len(problems)
         self.a_dtype = _dt(problems[0]["A"])
         self.g_dtype = _dt(problems[0]["G"])
-        self.opts = _opts("auto", refine_steps, 0, 0, rows_log2, kchunk_log2)
+        self.opts = _opts("auto", refine_steps, 0, 0, rows_log2, kchunk_log2, y_terms)
         cap = capacity if capacity is not None else problems
         cap_arr = _host_array(cap)
         need = _lib.ms_batch_workspace_size(self.count, cap_arr, self.a_dtype, self.g_dtype,
@@ -592,20 +604,36 @@ class BatchRunner:
         self.ws_ptr, self.ws_bytes = _ws_ptr(self.ws, need)
         self.cap_host = cap_arr          # launch shapes come from the capacity set
         nbytes = ctypes.sizeof(MsProblem) * self.count
-        self.desc_host = torch.empty(nbytes, dtype=torch.uint8).pin_memory()
+        # staging buffers of the descriptor copies, used in turn: a buffer is
+        # rewritten only once the copy that last read it has run (its event),
+        # so set_problems may be called again before earlier work has ended
+        self._stage = [torch.empty(nbytes, dtype=torch.uint8).pin_memory()
+                       for _ in range(self.STAGING)]
+        self._stage_done = [None] * self.STAGING
+        self._next_stage = 0
         self.desc_dev = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         self.graph = None
         self.set_problems(problems)
 
+    STAGING = 3
+
     def set_problems(self, problems, stream=None):
-        """Rewrite the device descriptors (stream-ordered copy)."""
+        """Rewrite the device descriptors (a stream-ordered copy: launches or
+        replays enqueued before it on the stream use the earlier problems)."""
         if len(problems) != self.count:
             raise ValueError("a runner keeps its problem count")
         arr = _host_array(problems)
-        ctypes.memmove(self.desc_host.data_ptr(), arr, ctypes.sizeof(arr))
+        i = self._next_stage
+        self._next_stage = (i + 1) % self.STAGING
+        if self._stage_done[i] is not None:
+            self._stage_done[i].synchronize()
+        ctypes.memmove(self._stage[i].data_ptr(), arr, ctypes.sizeof(arr))
         s = stream if stream is not None else torch.cuda.current_stream()
         with torch.cuda.stream(s):
-            self.desc_dev.copy_(self.desc_host, non_blocking=True)
+            self.desc_dev.copy_(self._stage[i], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        self._stage_done[i] = ev
         self.problems = problems
 
     def launch(self, stream=None):
@@ -639,10 +667,10 @@ class BatchRunner:
 
 
 def sketch_lstsq_batched(problems, rows_log2: int = 0, kchunk_log2: int = 0,
-                         refine_steps: int = 0, stream=None):
+                         refine_steps: int = 0, stream=None, y_terms: int = 0):
     """Solve a list of problems (dicts as for BatchRunner) in one batched call;
     returns the runner (its problems' X tensors hold the solutions)."""
     r = BatchRunner(problems, rows_log2=rows_log2, kchunk_log2=kchunk_log2,
-                    refine_steps=refine_steps)
+                    refine_steps=refine_steps, y_terms=y_terms)
     r.launch(stream)
     return r

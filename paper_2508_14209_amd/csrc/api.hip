@@ -79,8 +79,9 @@ int resolve_mode(const ms_opts *o) {
 }
 
 struct CsLayout {
-  size_t code = 0, cnt = 0, off = 0, cursor = 0, sperm = 0;
+  size_t code = 0, cnt = 0, off = 0, cursor = 0, sperm = 0, tab = 0, tab_bytes = 0;
   size_t part = 0, part_bytes = 0;
+  size_t tplan = 0, tplan_bytes = 0;  // the tiled CountSketch's plan (k > 16384)
 };
 
 // ncols, wd: columns and element bytes of the sketched operand (the LDS
@@ -91,13 +92,28 @@ void carve_cs(Carve &cv, CsLayout &L, int64_t d, int64_t k, int mode, int64_t nc
     L.off = cv.take((size_t)(k + 1) * 4);
     L.cursor = cv.take((size_t)k * 4);
     L.sperm = cv.take((size_t)d * 4);
+    // the blocked plan's count table (k <= 16384)
+    L.tab_bytes = plan_blocked_bytes(d, k);
+    if (L.tab_bytes) L.tab = cv.take(L.tab_bytes);
   } else {
-    L.code = cv.take((size_t)d * 4);
+    // the tiled CountSketch's plan comes first, right after the status block
     if (mode == MS_CS_LDS) {
+      L.tplan_bytes = cs_tile_plan_bytes(d, k);
+      if (L.tplan_bytes) L.tplan = cv.take(L.tplan_bytes);
+    }
+    L.code = cv.take((size_t)d * 4);
+    if (mode == MS_CS_LDS && !L.tplan_bytes) {
       L.part_bytes = cs_part_bytes(d, k, ncols, wd);
       if (L.part_bytes) L.part = cv.take(L.part_bytes);
     }
   }
+}
+
+// The LDS CountSketch of this call runs as the tiled CountSketch: the plan
+// has room in the workspace, the device can run it, and no schedule
+// override of the single-tile kernels was asked for.
+bool use_tiled(const CsLayout &L, int64_t d, int64_t k, const CsTuning &tune) {
+  return L.tplan_bytes && !tune.grid_variant && !tune.cols_per_wg && cs_tiled_supported(d, k);
 }
 
 struct LstsqLayout {
@@ -180,16 +196,31 @@ CsrLayout csr_layout(int64_t d, int64_t n, int64_t nrhs, int64_t k1, int64_t k2,
   return L;
 }
 
-// Normal equations: the fused pass's per-workgroup partials and their sum.
+// Normal equations: the fused pass's per-workgroup partials and their sum
+// (n <= 64); for wider problems the wide Gram pass's per-chunk partials, the
+// Gram matrix and the factorisation's breakdown flag.
 struct NeLayout {
-  size_t part = 0, w = 0, total = 0;
+  size_t part = 0, w = 0, bad = 0, total = 0;
 };
 
-NeLayout ne_layout() {
+bool ne_is_wide(int64_t n, int64_t nrhs) {
+  return n > kRcqMaxN || nrhs > kRcqMaxRhs || n + nrhs > kRcqMaxCols;
+}
+bool ne_fits_wide(int64_t n, int64_t nrhs) {
+  return n <= kWideMaxN && nrhs <= kWideMaxRhs && n + nrhs <= kWideMaxCols;
+}
+
+NeLayout ne_layout(int64_t d, int64_t n, int64_t nrhs) {
   NeLayout L;
   Carve cv;
-  L.part = cv.take(rcq_partial_bytes(rcq_grid()));
-  L.w = cv.take((size_t)kRcqMaxN * kRcqMaxCols * 8);
+  if (ne_is_wide(n, nrhs) && ne_fits_wide(n, nrhs)) {
+    L.part = cv.take(gram_wide_partial_bytes(d, (int)(n + nrhs)));
+    L.w = cv.take(gram_wide_w_bytes((int)(n + nrhs)));
+    L.bad = cv.take(4);
+  } else {
+    L.part = cv.take(rcq_partial_bytes(rcq_grid()));
+    L.w = cv.take((size_t)kRcqMaxN * kRcqMaxCols * 8);
+  }
   L.total = cv.off;
   return L;
 }
@@ -235,12 +266,22 @@ hipError_t run_countsketch(int64_t d, int64_t k, const Cols<T> &c, const int32_t
     e = launch_prologue<int32_t>(status, at<int32_t>(ws, L.cnt), k, 1, k, st);
     if (e == hipSuccess) e = launch_check_signs(d, s, status, st);
     if (e == hipSuccess)
-      e = launch_plan(d, k, h, s, at<int32_t>(ws, L.cnt), at<int32_t>(ws, L.off),
-                      at<int32_t>(ws, L.cursor), at<uint32_t>(ws, L.sperm), status, st);
+      e = L.tab_bytes
+              ? launch_plan_blocked(d, k, h, s, at<int32_t>(ws, L.cnt), at<int32_t>(ws, L.off),
+                                    at<int32_t>(ws, L.cursor), at<void>(ws, L.tab),
+                                    at<uint32_t>(ws, L.sperm), status, st)
+              : launch_plan(d, k, h, s, at<int32_t>(ws, L.cnt), at<int32_t>(ws, L.off),
+                            at<int32_t>(ws, L.cursor), at<uint32_t>(ws, L.sperm), status, st);
     if (e != hipSuccess) return e;
-    return launch_cs_sorted<T>(k, c, at<int32_t>(ws, L.off), at<uint32_t>(ws, L.sperm), Y, ldy, st);
+    return launch_cs_sorted_cols<T>(k, c, at<int32_t>(ws, L.off), at<uint32_t>(ws, L.sperm), Y,
+                                    ldy, st);
   }
   e = launch_prologue<T>(status, Y, k, c.ncols, ldy, st);
+  if (e == hipSuccess && mode == MS_CS_LDS && use_tiled(L, d, k, tune)) {
+    e = launch_tile_plan(d, k, nullptr, h, s, at<void>(ws, L.tplan), status, st);
+    if (e == hipSuccess) e = launch_cs_tiled<T>(d, k, c, at<void>(ws, L.tplan), Y, ldy, st);
+    return e;
+  }
   if (e == hipSuccess) e = launch_pack_codes(d, k, h, s, at<uint32_t>(ws, L.code), status, st);
   if (e != hipSuccess) return e;
   if (mode == MS_CS_ATOMIC)
@@ -255,8 +296,13 @@ bool valid_mode(const ms_opts *o) {
   if (!(m >= MS_CS_AUTO && m <= MS_CS_SORTED)) return false;
   if (o && (o->cs_tile_cols < 0 || o->cs_tile_cols > 64 || o->cs_schedule < 0 || o->cs_schedule > 1))
     return false;
+  if (o && !(o->gauss_y_terms == 0 || o->gauss_y_terms == 1 || o->gauss_y_terms == 3))
+    return false;
   return true;
 }
+
+// BF16 terms of Y in the Gaussian stage (default: the exact three-term split)
+int yterms_of(const ms_opts *o) { return (o && o->gauss_y_terms == 1) ? 1 : 3; }
 
 CsTuning tuning_of(const ms_opts *o) {
   CsTuning t{0, 0};
@@ -297,6 +343,7 @@ size_t ms_workspace_size(int op, int64_t d, int64_t n, int64_t nrhs, int64_t k, 
     case MS_OP_BUCKET_PLAN:
       cv.take((size_t)k * 4);
       cv.take((size_t)d * 4);
+      if (plan_blocked_bytes(d, k)) cv.take(plan_blocked_bytes(d, k));
       return cv.off;
     case MS_OP_COUNTSKETCH:
       carve_cs(cv, L, d, k, mode, n, dtype_size(a_dtype));
@@ -319,7 +366,7 @@ size_t ms_workspace_size(int op, int64_t d, int64_t n, int64_t nrhs, int64_t k, 
     case MS_OP_RAND_CHOLQR:
       return rcq_layout(d, n, k, k2, a_dtype, g_dtype, mode).total;
     case MS_OP_NORMAL_EQUATIONS:
-      return ne_layout().total;
+      return ne_layout(d, n, nrhs).total;
     case MS_OP_SRHT:
       cv.take(srht_workspace_bytes(d, n, k));
       return cv.off;
@@ -355,11 +402,15 @@ ms_status ms_bucket_plan(int64_t d, int64_t k, const int32_t *h, int32_t *cnt, i
   Carve cv;
   const size_t o_cursor = cv.take((size_t)k * 4);
   const size_t o_sperm = cv.take((size_t)d * 4);
+  const size_t tab_bytes = d > 0 ? plan_blocked_bytes(d, k) : 0;
+  const size_t o_tab = tab_bytes ? cv.take(tab_bytes) : 0;
   int *status = static_cast<int *>(ws);
   hipError_t e = launch_prologue<int32_t>(status, cnt, k, 1, k, st);
   if (e == hipSuccess)
-    e = launch_plan(d, k, h, nullptr, cnt, off, at<int32_t>(ws, o_cursor),
-                    at<uint32_t>(ws, o_sperm), status, st);
+    e = tab_bytes ? launch_plan_blocked(d, k, h, nullptr, cnt, off, at<int32_t>(ws, o_cursor),
+                                        at<void>(ws, o_tab), at<uint32_t>(ws, o_sperm), status, st)
+                  : launch_plan(d, k, h, nullptr, cnt, off, at<int32_t>(ws, o_cursor),
+                                at<uint32_t>(ws, o_sperm), status, st);
   if (e == hipSuccess) e = launch_strip_sign(d, at<uint32_t>(ws, o_sperm), perm, st);
   return from_hip(e);
 }
@@ -391,7 +442,24 @@ ms_status countsketch_accumulate(int64_t d, int64_t n, int64_t k, ms_dtype a_dty
   hipError_t e = launch_zero_status(status, st);
   if (e != hipSuccess || n == 0 || d == 0) return from_hip(e);
   const CsTuning tune = tuning_of(opts);
-  // a workspace beyond the status block holds the per-die partial buffer
+  // a workspace beyond the status block holds the tiled CountSketch's plan
+  // (k > 16384), built here from the codes
+  const size_t tneed = cs_tile_plan_bytes(d, k);
+  if (mode == MS_CS_LDS && tneed && ws_bytes >= kAlign + tneed && !tune.grid_variant &&
+      !tune.cols_per_wg && cs_tiled_supported(d, k)) {
+    void *plan = at<void>(ws, kAlign);
+    e = launch_tile_plan(d, k, code, nullptr, nullptr, plan, status, st);
+    if (e != hipSuccess) return from_hip(e);
+    if (a_dtype == MS_F64) {
+      Cols<double> c{static_cast<const double *>(A), lda, nullptr, 0, (int)n, (int)n};
+      e = launch_cs_tiled<double>(d, k, c, plan, static_cast<double *>(Y), ldy, st);
+    } else {
+      Cols<float> c{static_cast<const float *>(A), lda, nullptr, 0, (int)n, (int)n};
+      e = launch_cs_tiled<float>(d, k, c, plan, static_cast<float *>(Y), ldy, st);
+    }
+    return from_hip(e);
+  }
+  // else a workspace beyond the status block holds the per-die partial buffer
   const size_t pneed = cs_part_bytes(d, k, n, dtype_size(a_dtype));
   void *part = (pneed && ws_bytes >= kAlign + pneed) ? at<void>(ws, kAlign) : nullptr;
   if (a_dtype == MS_F64) {
@@ -497,7 +565,7 @@ ms_status multisketch_apply(int64_t d, int64_t n, int64_t k, int64_t k2, ms_dtyp
   }
   if (e == hipSuccess)
     e = launch_gemm(p, g_dtype, G, ldg, at<void>(ws, o_y), k, Z, ldz, nullptr,
-                    at<void>(ws, o_part), nullptr, st);
+                    at<void>(ws, o_part), nullptr, st, yterms_of(opts));
   return from_hip(e);
 }
 
@@ -561,7 +629,7 @@ ms_status sketch_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64_t k2
   double *z64 = at<double>(ws, L.z64);
   if (e == hipSuccess)
     e = launch_gemm(p, g_dtype, G, ldg, at<void>(ws, L.y), k, nullptr, k2, z64,
-                    at<void>(ws, L.partials), nullptr, st);
+                    at<void>(ws, L.partials), nullptr, st, yterms_of(opts));
   if (e == hipSuccess)
     e = launch_qr_solve(k2, n, nrhs, z64, k2, z64 + n * k2, k2, X, ldx, nullptr, 0,
                         at<double>(ws, L.tau), at<double>(ws, L.fact), at<void>(ws, L.qr), status,
@@ -578,12 +646,17 @@ ms_status sketch_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64_t k2
     if (e != hipSuccess) break;
     Cols<double> cr{r, d, nullptr, 0, (int)nrhs, (int)nrhs};
     if (mode == MS_CS_SORTED)
-      e = launch_cs_sorted<double>(k, cr, at<int32_t>(ws, L.cs.off), at<uint32_t>(ws, L.cs.sperm),
+      e = launch_cs_sorted_cols<double>(k, cr, at<int32_t>(ws, L.cs.off), at<uint32_t>(ws, L.cs.sperm),
                                    at<double>(ws, L.yr), k, st);
     else if (mode == MS_CS_ATOMIC)
       e = launch_cs_atomic<double>(d, k, cr, at<uint32_t>(ws, L.cs.code), at<double>(ws, L.yr), k,
                                    true, status, st);
-    else
+    else if (use_tiled(L.cs, d, k, tuning_of(opts))) {
+      e = launch_fill_zero<double>(at<double>(ws, L.yr), k, nrhs, k, st);
+      if (e == hipSuccess)
+        e = launch_cs_tiled<double>(d, k, cr, at<void>(ws, L.cs.tplan), at<double>(ws, L.yr), k,
+                                    st);
+    } else
       e = launch_cs_lds<double>(d, k, cr, at<uint32_t>(ws, L.cs.code), nullptr, nullptr,
                                 at<double>(ws, L.yr), k, true, status, st);
     if (e != hipSuccess) break;
@@ -634,7 +707,7 @@ ms_status rand_cholqr_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64
   double *z64 = at<double>(ws, L.z64);
   if (e == hipSuccess)
     e = launch_gemm(p, g_dtype, G, ldg, at<void>(ws, L.y), k, nullptr, k2, z64,
-                    at<void>(ws, L.partials), nullptr, st);
+                    at<void>(ws, L.partials), nullptr, st, yterms_of(opts));
   // 2. R0 of the Householder QR of S A (no right-hand side)
   double *r0 = at<double>(ws, L.r0);
   if (e == hipSuccess)
@@ -781,16 +854,33 @@ ms_status normal_equations_lstsq(int64_t d, int64_t n, int64_t nrhs, ms_dtype a_
   (void)opts;
   if (d < 1 || n < 1 || nrhs < 1) return MS_ERR_ARG;
   if (a_dtype != MS_F64 && a_dtype != MS_F32) return MS_ERR_ARG;
-  if (n > kRcqMaxN || nrhs > kRcqMaxRhs || n + nrhs > kRcqMaxCols) return MS_ERR_UNSUPPORTED;
+  const bool wide = ne_is_wide(n, nrhs);
+  if (wide && !ne_fits_wide(n, nrhs)) return MS_ERR_UNSUPPORTED;
   if (lda < d || ldb < d || ldx < n || (R && ldr < n)) return MS_ERR_ARG;
   if (!A || !B || !X || !ws) return MS_ERR_ARG;
-  const NeLayout L = ne_layout();
+  const NeLayout L = ne_layout(d, n, nrhs);
   if (ws_bytes < L.total) return MS_ERR_NOMEM;
   hipStream_t st = (hipStream_t)stream;
   int *status = static_cast<int *>(ws);
   double *part = at<double>(ws, L.part);
   const int grid = rcq_grid();
   hipError_t e = launch_zero_status(status, st);
+  if (wide) {
+    // W = [A | B]^T [A | B] by the wide Gram pass (per-chunk partials, then
+    // their ordered sum), then the blocked Cholesky and the two solves
+    const int nc = (int)(n + nrhs);
+    double *W = at<double>(ws, L.w);
+    if (e == hipSuccess)
+      e = a_dtype == MS_F64
+              ? launch_gram_wide<double, double>(d, (int)n, nc, static_cast<const double *>(A), lda,
+                                                 static_cast<const double *>(B), ldb, part, W, st)
+              : launch_gram_wide<float, float>(d, (int)n, nc, static_cast<const float *>(A), lda,
+                                               static_cast<const float *>(B), ldb, part, W, st);
+    if (e == hipSuccess)
+      e = launch_chol_solve_wide((int)n, (int)nrhs, nc, W, nullptr, 0, X, ldx, R, ldr,
+                                 at<int>(ws, L.bad), status, st);
+    return from_hip(e);
+  }
   // one pass: per-workgroup [A | B]^T [A | B] (FP64), then the ordered sum,
   // R = chol(A^T A), R^T y = A^T B, X = R^{-1} y
   if (e == hipSuccess)

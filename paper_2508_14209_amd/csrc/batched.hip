@@ -228,6 +228,7 @@ bool valid_batch_opts(const ms_opts *o) {
   if (o->batch_rows_log2 != 0 && (o->batch_rows_log2 < 8 || o->batch_rows_log2 > 24)) return false;
   if (o->batch_kchunk_log2 != 0 && (o->batch_kchunk_log2 < 5 || o->batch_kchunk_log2 > 20))
     return false;
+  if (!(o->gauss_y_terms == 0 || o->gauss_y_terms == 1 || o->gauss_y_terms == 3)) return false;
   return true;
 }
 
@@ -339,7 +340,8 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
                                      grid, st);
   }
   if (e == hipSuccess)
-    e = launch_batch_gemm(count, g_dtype, probs_dev, E, tot, yarea, parea, di.cus * 4, st);
+    e = launch_batch_gemm(count, g_dtype, probs_dev, E, tot, yarea, parea, di.cus * 4, st,
+                          (opts && opts->gauss_y_terms == 1) ? 1 : 3);
   if (e == hipSuccess)
     e = launch_batch_reduce(count, g_dtype, probs_dev, E, parea, zarea, (int)H.max_mn, st);
   if (e == hipSuccess)

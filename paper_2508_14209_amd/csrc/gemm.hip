@@ -212,24 +212,39 @@ __device__ __forceinline__ void gemm_tile(int M, int N, const typename Mf<DT>::T
 // matrix-core fragment holds 8 consecutive k of one row, so G's tile (64 rows
 // x 64 k) is loaded with 16-byte loads along the rows and written to LDS
 // transposed (row-major, k contiguous); Y's tile (64 k x 64 columns, FP32,
-// k contiguous) is rounded to BF16 and written as is.  Two LDS buffers: the
+// k contiguous) is converted to BF16 and written as is.  Two LDS buffers: the
 // next stage's global loads are in flight while the current stage runs on
 // the matrix cores.  The k steps (32 each) run in the same order as in
 // gemm_tile, so the partial sums are the same.
+//
+// YT = 1: Y rounded to BF16 (nearest even).  YT = 3: Y as the sum of three
+// BF16 terms, hi = bf16(y), mid = bf16(y - hi), lo = bf16(y - hi - mid);
+// each remainder is exact in FP32 and the last one fits BF16's 8 bits, so
+// hi + mid + lo = y exactly for every normal FP32 y, and G Y is formed from
+// the exact Y (G's values are BF16 data) with three matrix-core products per
+// step and FP32 accumulation: FP32-level accuracy at BF16 instruction rate,
+// with G read once.
 constexpr int kStK = 64, kStPad = 72;  // k per stage; LDS row stride (BF16 elements)
 
+// y -> (hi, mid, lo) BF16 bit patterns, two values at a time
+__device__ __forceinline__ float bf16_lo_as_f32(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi_as_f32(uint32_t w) {
+  return __uint_as_float(w & 0xffff0000u);
+}
+
+template <int YT>
 __device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned short *__restrict__ G,
                                                    int64_t ldg, const float *__restrict__ Y,
                                                    int64_t ldy, float *__restrict__ P, int64_t kb,
                                                    int64_t ke, int m_tile, int n_tile) {
   __shared__ __align__(16) unsigned short As[2][64 * kStPad];
-  __shared__ __align__(16) unsigned short Bs[2][64 * kStPad];
+  __shared__ __align__(16) unsigned short Bs[2][YT][64 * kStPad];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int m0 = m_tile * 64, n0 = n_tile * 64;
   // global-load roles: G columns (k) 2 gp and 2 gp + 1, rows 8 g8 .. 8 g8 + 7,
   // written to LDS as one dword (the two k of a row) per row; Y column yc,
-  // k yk .. yk + 15, rounded to BF16 in pairs by the hardware conversion
+  // k yk .. yk + 15, converted to BF16 in pairs by the hardware conversion
   const int g8 = tid & 7, gp = tid >> 3;
   const int yc = tid >> 2, yk = (tid & 3) * 16;
   const int rb = m0 + 8 * g8;
@@ -272,14 +287,26 @@ __device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned 
 #pragma unroll
     for (int r = 0; r < 8; ++r)
       *reinterpret_cast<uint32_t *>(&As[buf][(8 * g8 + r) * kStPad + 2 * gp]) = gw[r];
-    v4u32 b0, b1;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      b0[u] = bf16x2_rne(yv[2 * u], yv[2 * u + 1]);
-      b1[u] = bf16x2_rne(yv[8 + 2 * u], yv[8 + 2 * u + 1]);
+    for (int h = 0; h < 2; ++h) {
+      v4u32 bt[YT];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        float y0 = yv[8 * h + 2 * u], y1 = yv[8 * h + 2 * u + 1];
+#pragma unroll
+        for (int tt = 0; tt < YT; ++tt) {
+          const uint32_t w = bf16x2_rne(y0, y1);
+          bt[tt][u] = w;
+          if (tt + 1 < YT) {
+            y0 -= bf16_lo_as_f32(w);
+            y1 -= bf16_hi_as_f32(w);
+          }
+        }
+      }
+#pragma unroll
+      for (int tt = 0; tt < YT; ++tt)
+        *reinterpret_cast<v4u32 *>(&Bs[buf][tt][yc * kStPad + yk + 8 * h]) = bt[tt];
     }
-    *reinterpret_cast<v4u32 *>(&Bs[buf][yc * kStPad + yk]) = b0;
-    *reinterpret_cast<v4u32 *>(&Bs[buf][yc * kStPad + yk + 8]) = b1;
   };
   const int m_base = (wave & 1) * 32, n_base = (wave >> 1) * 32;
   v4f acc[2][2];
@@ -296,18 +323,24 @@ __device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned 
     if (more) fetch(k0 + kStK);
 #pragma unroll
     for (int ks = 0; ks < kStK / 32; ++ks) {
-      v8bf a[2], b[2];
+      v8bf a[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
         a[i] = *reinterpret_cast<const v8bf *>(&As[buf][(m_base + 16 * i + li) * kStPad + ks * 32 + lk * 8]);
+      // the small terms first (each enters the same FP32 accumulators)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        b[j] = *reinterpret_cast<const v8bf *>(&Bs[buf][(n_base + 16 * j + li) * kStPad + ks * 32 + lk * 8]);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int tt = YT - 1; tt >= 0; --tt) {
+        v8bf b[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+          b[j] = *reinterpret_cast<const v8bf *>(
+              &Bs[buf][tt][(n_base + 16 * j + li) * kStPad + ks * 32 + lk * 8]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
     }
     if (more) lstore(buf ^ 1);
     __syncthreads();
@@ -327,18 +360,19 @@ __device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned 
 }
 
 // The tile of either kind: LDS-staged for BF16, direct fragment loads else.
-template <int DT>
+// YT: BF16 terms of Y (1 or 3; the other dtypes ignore it).
+template <int DT, int YT = 1>
 __device__ __forceinline__ void gemm_tile_any(int M, int N, const typename Mf<DT>::TG *__restrict__ G,
                                               int64_t ldg, const typename Mf<DT>::TY *__restrict__ Y,
                                               int64_t ldy, typename Mf<DT>::Acc *__restrict__ P,
                                               int64_t kb, int64_t ke, int m_tile, int n_tile) {
   if constexpr (DT == DT_BF16)
-    gemm_tile_lds_bf16(M, N, G, ldg, Y, ldy, P, kb, ke, m_tile, n_tile);
+    gemm_tile_lds_bf16<YT>(M, N, G, ldg, Y, ldy, P, kb, ke, m_tile, n_tile);
   else
     gemm_tile<DT>(M, N, G, ldg, Y, ldy, P, kb, ke, m_tile, n_tile);
 }
 
-template <int DT>
+template <int DT, int YT = 1>
 __global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
                                                      const typename Mf<DT>::TG *__restrict__ G,
                                                      int64_t ldg,
@@ -348,8 +382,8 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
                                                      int64_t kchunk) {
   const int64_t kb = (int64_t)blockIdx.z * kchunk;
   const int64_t ke = min(K, kb + kchunk);
-  gemm_tile_any<DT>(M, N, G, ldg, Y, ldy, part + (int64_t)blockIdx.z * M * N, kb, ke, blockIdx.x,
-                    blockIdx.y);
+  gemm_tile_any<DT, YT>(M, N, G, ldg, Y, ldy, part + (int64_t)blockIdx.z * M * N, kb, ke,
+                        blockIdx.x, blockIdx.y);
 }
 
 // Z[p, c] = sum over splits (in split order) of the partials; written to Z
@@ -382,7 +416,7 @@ __global__ void k_reduce_splits(int M, int N, int nsplit, const Acc *__restrict_
 // Persistent workgroups over the Gaussian-stage items of all problems: item
 // = (problem, 64-row tile, 64-column tile, K split); each writes its partial
 // block into the problem's partials area.
-template <int DT>
+template <int DT, int YT = 1>
 __global__ __launch_bounds__(256) void k_batch_gemm(int count, const ms_problem *__restrict__ P,
                                                     const BatchEntry *__restrict__ E,
                                                     const BatchTotals *__restrict__ tot,
@@ -403,14 +437,14 @@ __global__ __launch_bounds__(256) void k_batch_gemm(int count, const ms_problem 
     const int64_t kb = (int64_t)split * e.kchunk, ke = min(Q.k, kb + e.kchunk);
     const auto *Y = reinterpret_cast<const typename F::TY *>(yarea + e.y_off);
     auto *Pz = reinterpret_cast<typename F::Acc *>(parea + e.part_off) + (int64_t)split * M * N;
-    gemm_tile_any<DT>(M, N, static_cast<const typename F::TG *>(Q.G), Q.ldg, Y, Q.k, Pz, kb, ke, tm,
-                      tn);
+    gemm_tile_any<DT, YT>(M, N, static_cast<const typename F::TG *>(Q.G), Q.ldg, Y, Q.k, Pz, kb,
+                          ke, tm, tn);
   }
 }
 
 hipError_t launch_batch_gemm(int count, ms_dtype g_dtype, const ms_problem *P, const BatchEntry *E,
                              const BatchTotals *tot, const unsigned char *yarea,
-                             unsigned char *parea, int grid, hipStream_t st) {
+                             unsigned char *parea, int grid, hipStream_t st, int yterms) {
   switch (g_dtype) {
     case MS_F64:
       hipLaunchKernelGGL(k_batch_gemm<DT_F64>, dim3(grid), dim3(256), 0, st, count, P, E, tot,
@@ -421,8 +455,12 @@ hipError_t launch_batch_gemm(int count, ms_dtype g_dtype, const ms_problem *P, c
                          yarea, parea);
       break;
     case MS_BF16:
-      hipLaunchKernelGGL(k_batch_gemm<DT_BF16>, dim3(grid), dim3(256), 0, st, count, P, E, tot,
-                         yarea, parea);
+      if (yterms == 3)
+        hipLaunchKernelGGL((k_batch_gemm<DT_BF16, 3>), dim3(grid), dim3(256), 0, st, count, P, E,
+                           tot, yarea, parea);
+      else
+        hipLaunchKernelGGL((k_batch_gemm<DT_BF16, 1>), dim3(grid), dim3(256), 0, st, count, P, E,
+                           tot, yarea, parea);
       break;
     default:
       return hipErrorInvalidValue;
@@ -495,7 +533,7 @@ GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K, ms_dtype g_dtype) {
 
 hipError_t launch_gemm(const GemmPlan &p, ms_dtype g_dtype, const void *G, int64_t ldg,
                        const void *Y, int64_t ldy, void *Z, int64_t ldz, double *z64,
-                       void *partials, void *ybf16, hipStream_t st) {
+                       void *partials, void *ybf16, hipStream_t st, int yterms) {
   (void)ybf16;
   if (p.M <= 0 || p.N <= 0) return hipSuccess;
   const int64_t MN = (int64_t)p.M * p.N;
@@ -521,9 +559,14 @@ hipError_t launch_gemm(const GemmPlan &p, ms_dtype g_dtype, const void *G, int64
                            p.N, p.nsplit, (const float *)partials, (float *)Z, ldz, z64);
       break;
     case MS_BF16:
-      hipLaunchKernelGGL(k_gemm_splitk<DT_BF16>, grid, dim3(256), 0, st, p.M, p.N, p.K,
-                         (const unsigned short *)G, ldg, (const float *)Y, ldy, (float *)partials,
-                         p.kchunk);
+      if (yterms == 3)
+        hipLaunchKernelGGL((k_gemm_splitk<DT_BF16, 3>), grid, dim3(256), 0, st, p.M, p.N, p.K,
+                           (const unsigned short *)G, ldg, (const float *)Y, ldy,
+                           (float *)partials, p.kchunk);
+      else
+        hipLaunchKernelGGL((k_gemm_splitk<DT_BF16, 1>), grid, dim3(256), 0, st, p.M, p.N, p.K,
+                           (const unsigned short *)G, ldg, (const float *)Y, ldy,
+                           (float *)partials, p.kchunk);
       if (reduce)
         hipLaunchKernelGGL((k_reduce_splits<float, float>), dim3(rblocks), dim3(256), 0, st, p.M,
                            p.N, p.nsplit, (const float *)partials, (float *)Z, ldz, z64);

@@ -153,9 +153,11 @@ struct GemmPlan {
 };
 GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K, ms_dtype g_dtype);
 // z64 (optional) receives an FP64 copy of Z (ldz64 = M).
+// yterms: for a BF16 G, Y enters as 1 BF16 term (rounded) or as 3 BF16
+// terms whose sum is Y exactly.
 hipError_t launch_gemm(const GemmPlan &p, ms_dtype g_dtype, const void *G, int64_t ldg,
                        const void *Y, int64_t ldy, void *Z, int64_t ldz, double *z64,
-                       void *partials, void *ybf16, hipStream_t st);
+                       void *partials, void *ybf16, hipStream_t st, int yterms = 1);
 
 // Z64 (M x N, ld M) = G Y64 in FP64 for N <= 8 (refinement correction).
 size_t gemv64_partial_bytes(int64_t M, int64_t N, int64_t K);
@@ -391,7 +393,7 @@ hipError_t launch_batch_cs(int count, const ms_problem *P, const BatchEntry *E,
 hipError_t launch_batch_gemm(int count, ms_dtype g_dtype, const ms_problem *P,
                              const BatchEntry *E, const BatchTotals *tot,
                              const unsigned char *yarea, unsigned char *parea, int grid,
-                             hipStream_t st);
+                             hipStream_t st, int yterms = 1);
 hipError_t launch_batch_reduce(int count, ms_dtype g_dtype, const ms_problem *P,
                                const BatchEntry *E, const unsigned char *parea,
                                unsigned char *zarea, int max_mn, hipStream_t st);
@@ -452,5 +454,53 @@ __device__ __forceinline__ double wave_allsum(double v) {
   v += dpp_bcast<0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3: lane 63 holds the total
   return read_lane(v, 63);
 }
+
+// cs_tiled.hip -- the CountSketch for bucket counts beyond one workgroup's
+// LDS (k > 16384): a per-call plan grouping each 8192-row block's rows by
+// bucket tile, then one pass in which each tile's workgroups visit only
+// their own rows.
+// Bytes of the plan (0 when the tiled CountSketch does not apply to d, k).
+size_t cs_tile_plan_bytes(int64_t d, int64_t k);
+// The current device can run the tiled CountSketch for (d, k).
+bool cs_tiled_supported(int64_t d, int64_t k);
+// Build the plan from packed codes (code non-null) or from h and s (checked:
+// MS_ERR_RANGE for a bad row, which the plan then leaves out).
+hipError_t launch_tile_plan(int64_t d, int64_t k, const uint32_t *code, const int32_t *h,
+                            const int8_t *s, void *plan, int *status, hipStream_t st);
+// Y += C [A | B] from the plan (Y is not cleared).
+template <typename T>
+hipError_t launch_cs_tiled(int64_t d, int64_t k, const Cols<T> &c, const void *plan, T *Y,
+                           int64_t ldy, hipStream_t st);
+
+// ne_wide.hip -- the normal equations / rand_cholQR's Cholesky stage for
+// wide problems (n <= 256, nrhs <= 16, n + nrhs <= 272): the Gram product
+// W = [X | B]^T [X | B] of a tall V in FP64 (per-chunk partials of upper
+// tiles, summed in chunk order), then R1 = chol(W_XX), y = R1^{-T} W_XB,
+// x = R1^{-1} y (and x = R0^{-1} x when fact holds rand_cholQR's R0).
+constexpr int kWideMaxN = 256;
+constexpr int kWideMaxRhs = 16;
+constexpr int kWideMaxCols = 272;
+int gram_wide_chunks(int64_t d, int nc);
+size_t gram_wide_partial_bytes(int64_t d, int nc);
+size_t gram_wide_w_bytes(int nc);
+template <typename TX, typename TB>
+hipError_t launch_gram_wide(int64_t d, int nx, int nc, const TX *X, int64_t ldx, const TB *B,
+                            int64_t ldb, double *part, double *W, hipStream_t st);
+// bad: one int of workspace (breakdown flag between the launches)
+hipError_t launch_chol_solve_wide(int n, int nrhs, int nc, double *W, const double *fact,
+                                  int64_t ldf, double *X, int64_t ldx, double *R, int64_t ldr,
+                                  int *bad, int *status, hipStream_t st);
+
+// plan_blocked.hip -- the sketch plan by 4096-row blocks with LDS counts (k <=
+// 16384; no global atomics, stable without a per-bucket sort), and the
+// deterministic fold launched a few columns at a time.
+// Bytes of the blocks x k count table (0 when the blocked plan does not apply).
+size_t plan_blocked_bytes(int64_t d, int64_t k);
+hipError_t launch_plan_blocked(int64_t d, int64_t k, const int32_t *h, const int8_t *s,
+                               int32_t *cnt, int32_t *off, int32_t *cursor, void *tab_ws,
+                               uint32_t *sperm, int *status, hipStream_t st);
+template <typename T>
+hipError_t launch_cs_sorted_cols(int64_t k, const Cols<T> &c, const int32_t *off,
+                                 const uint32_t *sperm, T *Y, int64_t ldy, hipStream_t st);
 
 }  // namespace ms

@@ -14,8 +14,9 @@ scheduled arrival to the moment the host observes its batch's completion
 event.
 
 The solver is the library's; this module only schedules.  Inputs follow the
-serving workload: A = Z diag(logspace(0, -log10 kappa, n)) (FP32), B = A x* +
-1e-6 N(0,1), h uniform, s Rademacher, G ~ N(0, 1/k2), k = 2 n^2, k2 = 2 n.
+serving workload: A = Z diag(logspace(0, -log10 kappa, n)) Q (FP32; Q
+orthogonal), B = A x* + 1e-6 N(0,1), h uniform, s Rademacher,
+G ~ N(0, 1/k2), k = 2 n^2, k2 = 2 n.
 """
 from __future__ import annotations
 
@@ -77,9 +78,15 @@ def generate(req: Request, device, g_dtype: str = "f32", a_dtype: str = "f32") -
     g = torch.Generator(device=device)
     g.manual_seed(int(req.seed))
     d, n, nrhs, k, k2 = req.d, req.n, req.nrhs, req.k, req.k2
-    scales = torch.logspace(0.0, -math.log10(req.kappa), n, device=device, dtype=torch.float32)
-    A = torch.randn((n, d), generator=g, device=device, dtype=torch.float32).t()
-    A.mul_(scales)                                   # column scaling: condition ~ kappa
+    scales = torch.logspace(0.0, -math.log10(req.kappa), n, device=device, dtype=torch.float64)
+    # A = Z diag(scales) Q: Z N(0,1), Q orthogonal (QR of an n x n Gaussian),
+    # the n x n factor formed in FP64, the product in FP32; condition ~ kappa
+    q, _ = torch.linalg.qr(torch.randn((n, n), generator=g, device=device, dtype=torch.float64))
+    M = (scales[:, None] * q).to(torch.float32)
+    Z = torch.randn((d, n), generator=g, device=device, dtype=torch.float32)
+    A = ms.empty_colmajor(d, n, torch.float32, device)
+    A.copy_(Z @ M)
+    del Z
     xs = torch.randn((n, nrhs), generator=g, device=device, dtype=torch.float32)
     B = ms.empty_colmajor(d, nrhs, torch.float32, device)
     B.copy_(A @ xs)
@@ -145,7 +152,8 @@ class Server:
     def __init__(self, hbm_budget: int = 64 << 30, max_inflight: int = 256, max_batch: int = 64,
                  streams: int = 4, g_dtype: str = "f32", rows_log2: int = 0,
                  kchunk_log2: int = 0, refine_steps: int = 0, tuned: bool = False,
-                 a_dtype: str = "f32", single: bool = False, device="cuda"):
+                 a_dtype: str = "f32", single: bool = False, device="cuda",
+                 persistent: bool = False, graphs: bool = True, max_shape=None):
         self.device = torch.device(device)
         self.admission = Admission(hbm_budget, max_inflight)
         self.max_batch = max_batch
@@ -156,6 +164,16 @@ class Server:
         self.tuned = tuned              # take rows/K per item from the autotuner's cache
         self.a_dtype = a_dtype          # "f64": A, B promoted exactly (the plain FP64 path)
         self.single = single            # one request per call of the single-problem solver
+        # persistent: one BatchRunner per solver stream, its workspace sized
+        # once for max_batch requests of the largest shape (d, n, nrhs) the
+        # stream can send; a batch of fewer requests is padded with a 1-row
+        # placeholder problem, so every call has the runner's count and its
+        # launch sequence is captured once in a graph and replayed
+        self.persistent = persistent and not single
+        self.graphs = graphs
+        self.max_shape = max_shape or (1 << 20, 128, 8)
+        self.runners = {}
+        self._pad = None
         self.gen_stream = torch.cuda.Stream(device=self.device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self.busy = {}                # stream index -> (event, runner, requests)
@@ -213,6 +231,17 @@ class Server:
                     ev = torch.cuda.Event()
                     ev.record(st)
                 runner = ("single", ws)
+            elif self.persistent:
+                runner = self._stream_runner(si, st, probs)
+                padded = probs + [self._pad_problem()] * (self.max_batch - len(probs))
+                with torch.cuda.stream(st):
+                    runner.set_problems(padded, stream=st)
+                    if self.graphs:
+                        runner.replay()
+                    else:
+                        runner.launch(st)
+                    ev = torch.cuda.Event()
+                    ev.record(st)
             else:
                 rl, kl = self.rows_log2, self.kchunk_log2
                 if self.tuned and not (rl or kl):
@@ -230,6 +259,64 @@ class Server:
                 r.batch = self.nbatches
             self.nbatches += 1
             self.busy[si] = (ev, runner, batch)
+
+    def _pad_problem(self) -> dict:
+        """A 1-row, 1-column problem (k = k2 = 1) that fills unused batch slots."""
+        if self._pad is None:
+            dev = self.device
+            adt = torch.float64 if self.a_dtype == "f64" else torch.float32
+            gdt = {"f64": torch.float64, "bf16": torch.bfloat16}.get(self.g_dtype, torch.float32)
+            A = ms.empty_colmajor(1, 1, adt, dev)
+            A.fill_(1.0)
+            B = ms.empty_colmajor(1, 1, adt, dev)
+            B.fill_(1.0)
+            G = ms.empty_colmajor(1, 1, gdt, dev)
+            G.fill_(1.0)
+            self._pad = dict(A=A, B=B, h=torch.zeros(1, dtype=torch.int32, device=dev),
+                             s=torch.ones(1, dtype=torch.int8, device=dev), G=G,
+                             X=ms.empty_colmajor(1, 1, torch.float64, dev), k=1)
+        return self._pad
+
+    def _capacity(self) -> list:
+        """Shapes the persistent runners are sized for: max_batch copies of
+        the largest request (d, n, nrhs, k, k2)."""
+        d, n, nrhs = self.max_shape
+        return [(d, n, nrhs, 2 * n * n, 2 * n)] * self.max_batch
+
+    def _stream_runner(self, si, st, probs):
+        r = self.runners.get(si)
+        if r is None:
+            rl, kl = self.rows_log2, self.kchunk_log2
+            if self.tuned and not (rl or kl):
+                from paper_2508_14209_amd import autotune
+                rl, kl = autotune.batch_params(probs, self.device)
+            padded = probs + [self._pad_problem()] * (self.max_batch - len(probs))
+            with torch.cuda.stream(st):
+                r = ms.BatchRunner(padded, capacity=self._capacity(), rows_log2=rl,
+                                   kchunk_log2=kl, refine_steps=self.refine_steps)
+            if self.graphs:
+                with torch.cuda.stream(st):
+                    r.capture()
+            self.runners[si] = r
+        return r
+
+    def warm_runners(self, requests):
+        """Build every stream's persistent runner (workspace, graph capture)
+        before a timed run, tuned for the shape class of ``requests``."""
+        if not self.persistent:
+            return
+        probs = [generate(r, self.device, self.g_dtype, self.a_dtype) for r in requests]
+        probs = probs[:self.max_batch]
+        for si, st in enumerate(self.streams):
+            runner = self._stream_runner(si, st, probs)
+            padded = probs + [self._pad_problem()] * (self.max_batch - len(probs))
+            with torch.cuda.stream(st):
+                runner.set_problems(padded, stream=st)
+                if self.graphs:
+                    runner.replay()
+                else:
+                    runner.launch(st)
+        torch.cuda.synchronize(self.device)
 
     def _complete(self):
         for si in list(self.busy):

@@ -173,8 +173,8 @@ def test_later_rows_reject_invalid_arguments_on_host(ms):
     refine = ms.MsOpts(0, 1, 0, 0, 0, 0, 0, 0)
     sorted_ = ms.MsOpts(3, 0, 0, 0, 0, 0, 0, 0)
     big = 1 << 30
-    # normal equations: n > 64, nrhs > 16 unsupported; nrhs = 0 invalid
-    assert lib.normal_equations_lstsq(100, 65, 1, 0, P, 100, P, 100, P, 65, None, 65, None, ws,
+    # normal equations: n > 256, nrhs > 16 unsupported; nrhs = 0 invalid
+    assert lib.normal_equations_lstsq(300, 257, 1, 0, P, 300, P, 300, P, 257, None, 257, None, ws,
                                       big, None) == ms.MS_ERR_UNSUPPORTED
     assert lib.normal_equations_lstsq(100, 8, 17, 0, P, 100, P, 100, P, 8, None, 8, None, ws,
                                       big, None) == ms.MS_ERR_UNSUPPORTED

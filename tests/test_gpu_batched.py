@@ -3,10 +3,10 @@ mixed batch against the oracle, each result the same alone and in the mix,
 HIP-graph capture and replay with rewritten descriptors, per-problem errors.
 
 Bar: FP64 problems 1e-12 normwise relative against the oracle (and against
-the same problem solved alone); FP32 problems 1e-4 (well-conditioned, FP32
-sketch); BF16 Gaussian stage against the oracle's BF16 path 1e-2 (the
-sketch's last-bit differences may move entries across a BF16 rounding
-boundary, each such entry changing by 2^-8 relative).
+the same problem solved alone); FP32 problems 1e-5 (well-conditioned, FP32
+sketch, against the exact-sum FP32 sketch); BF16 Gaussian stage against the
+oracle's BF16 path 1e-2 (the sketch's last-bit differences may move entries
+across a BF16 rounding boundary, each such entry changing by 2^-8 relative).
 """
 import numpy as np
 import pytest
@@ -65,9 +65,15 @@ def test_batched_fp32(ms, orc, gd):
     st, per = runner.status()
     assert st == ms.MS_OK
     for host, dev in probs:
+        # reference sketch: Def. 3's exact sums rounded once to FP32 (the
+        # batched kernel sums each item's rows in FP64); the BF16 Gaussian
+        # stage takes the sketch as three BF16 terms that sum to it exactly
+        # (the default), so both G dtypes meet the FP32 bar
         Xr, _, _ = orc.sketch_lstsq(host["A"], host["B"], host["h"], host["s"], host["G"],
-                                    host["k"], y_bf16=(gd == "bf16"))
-        assert rel(to_host(dev["X"]), Xr) <= (1e-4 if gd == "f32" else 1e-2)
+                                    host["k"], y_acc64=True)
+        err = rel(to_host(dev["X"]), Xr)
+        print(gd, host["A"].shape, "err %.3e" % err)
+        assert err <= 1e-5
 
 
 def test_batched_graph_replay_with_new_problems(ms, orc):
@@ -94,6 +100,33 @@ def test_batched_graph_replay_with_new_problems(ms, orc):
                 Xr, _, _ = orc.sketch_lstsq(host["A"], host["B"], host["h"], host["s"],
                                             host["G"], host["k"])
                 assert rel(to_host(dev["X"]), Xr) <= 1e-12
+
+
+def test_batched_pipelined_set_problems_without_host_sync(ms, orc):
+    # set_problems(set1), replay, set_problems(set2), replay, ... enqueued back
+    # to back with no host synchronisation: each replay must solve the set
+    # whose descriptors were written just before it (the staging buffer of a
+    # pending descriptor copy is not rewritten before that copy has run)
+    shapes = [(20000, 8, 2), (30000, 16, 1), (12000, 32, 1)]
+    sets = [[make_problem(ms, d + 101 * j, n, r, seed=800 + 10 * j + i)
+             for i, (d, n, r) in enumerate(shapes)] for j in range(4)]
+    runner = ms.BatchRunner([p[1] for p in sets[0]])
+    runner.capture()
+    for which in sets:
+        for _, dev in which:
+            dev["X"].fill_(float("nan"))
+    torch.cuda.synchronize()
+    for which in sets:
+        runner.set_problems([p[1] for p in which])
+        runner.replay()
+    torch.cuda.synchronize()
+    st, per = runner.status()
+    assert st == ms.MS_OK, (st, per)
+    for j, which in enumerate(sets):
+        for host, dev in which:
+            Xr, _, _ = orc.sketch_lstsq(host["A"], host["B"], host["h"], host["s"], host["G"],
+                                        host["k"])
+            assert rel(to_host(dev["X"]), Xr) <= 1e-12, j
 
 
 def test_batched_per_problem_range_error(ms, orc):
@@ -140,8 +173,9 @@ def make_scaled_problem(ms, d, n, nrhs, seed, gd="bf16", decades=4.0):
 REFINE_SHAPES = [(1 << 17, 8, 1), (100003, 16, 4), (1 << 16, 32, 8)]
 
 
-@pytest.mark.parametrize("refine", [0, 1, 3])
-def test_batched_bf16_refinement(ms, orc, refine):
+@pytest.mark.parametrize("yt", [1, 3])
+@pytest.mark.parametrize("refine", [0, 1, 2, 3])
+def test_batched_bf16_refinement(ms, orc, refine, yt):
     # Mixed precision in one batched call: FP32 CountSketch, BF16 Gaussian
     # stage, FP64 QR, then FP64-residual refinement steps per problem.  Each
     # X's error against the FP64 sketch-and-solve solution for the same
@@ -153,7 +187,7 @@ def test_batched_bf16_refinement(ms, orc, refine):
     # column-equilibrated sketch, ~1e-2 for k2 = 2n).
     probs = [make_scaled_problem(ms, d, n, r, seed=800 + i)
              for i, (d, n, r) in enumerate(REFINE_SHAPES)]
-    runner = ms.sketch_lstsq_batched([p[1] for p in probs], refine_steps=refine)
+    runner = ms.sketch_lstsq_batched([p[1] for p in probs], refine_steps=refine, y_terms=yt)
     st, per = runner.status()
     assert st == ms.MS_OK and all(v == ms.MS_OK for v in per)
     for (host, dev), shape in zip(probs, REFINE_SHAPES):
@@ -163,14 +197,24 @@ def test_batched_bf16_refinement(ms, orc, refine):
                                      host["G"].astype(np.float64), host["k"])
         err = rel(Xb, X64)
         Xa, ws = ms.sketch_lstsq(dev["A"], dev["B"], dev["h"], dev["s"], dev["G"], host["k"],
-                                 refine_steps=refine)
+                                 refine_steps=refine, y_terms=yt)
         ms.check_status(ws)
         ea = rel(to_host(Xa), X64)
-        print(shape, "refine=%d batched %.3e alone %.3e" % (refine, err, ea))
-        assert np.isfinite(Xb).all() and err <= 5.0, (shape, err)
-        assert err <= 1.2 * ea + 1e-7, (shape, err, ea)
-        if refine == 3:
-            assert err <= 1e-4, (shape, err)
+        print(shape, "y_terms=%d refine=%d batched %.3e alone %.3e" % (yt, refine, err, ea))
+        # One BF16 term: the error starts at O(1) and each step contracts
+        # it by c ~ u_bf16 times the conditioning of the column-equilibrated
+        # sketch (1e-2 or less here: e_1 / e_0 measured 1e-2 for n = 8, 2e-3
+        # for n = 32) down to the fixed point's offset (a few 1e-6): bounds
+        # 5, 5e-2, 1e-4, 1e-5 after 0..3 steps; both paths round the same
+        # sketch values to BF16 and agree to the last digits.  Three exact
+        # terms: only the FP32 sketch's rounding remains (a few 1e-4 before,
+        # ~1e-10 after one step); the batched and single sketches differ in
+        # association order, so only the bound is checked.
+        bound = ({0: 5.0, 1: 5e-2, 2: 1e-4, 3: 1e-5} if yt == 1 else
+                 {0: 1e-2, 1: 1e-8, 2: 1e-8, 3: 1e-8})[refine]
+        assert np.isfinite(Xb).all() and err <= bound, (shape, err)
+        if yt == 1:
+            assert err <= 1.2 * ea + 1e-7, (shape, err, ea)
 
 
 def test_batched_fp64_refinement_keeps_parity(ms, orc):

@@ -112,21 +112,63 @@ def test_countsketch_bucket_tiles(ms, orc, dtype, k):
 
 @pytest.mark.parametrize("d,n,k,dtype", [(300001, 20, 65536, np.float32),
                                          (200000, 32, 32768, np.float64),
-                                         (1000, 8, 131072, np.float32)])
-def test_countsketch_die_partials(ms, orc, d, n, k, dtype):
-    # many buckets, few rows per bucket: each die stores its partial sums
-    # (one owner per column and bucket) and a second kernel adds the dies'
-    # slices; with 1000 rows only some dies hold rows
-    wd = np.dtype(dtype).itemsize
+                                         (1000, 8, 131072, np.float32),
+                                         (8192 * 3 + 5, 3, 40000, np.float64),
+                                         (50000, 2, 20000, np.float32),
+                                         (8192, 1, 16385, np.float64)])
+def test_countsketch_tiled_plan(ms, orc, d, n, k, dtype):
+    # more buckets than one workgroup's LDS holds (k > 16384): the rows of
+    # each 8192-row block are grouped by bucket tile first, and each tile's
+    # workgroups visit only their rows.  Ragged shapes: a partial last block,
+    # one block only, bucket counts that are not powers of two, tiles of
+    # unequal length.  The workspace holds the plan (4 bytes per row, block
+    # padded) besides the packed codes.
     a_dt = ms.MS_F64 if dtype == np.float64 else ms.MS_F32
+    nblk = (d + 8191) // 8192
     assert (ms.workspace_size("countsketch", d=d, n=n, k=k, a_dtype=a_dt, mode="lds")
             - ms.workspace_size("countsketch", d=d, n=n, k=k, a_dtype=a_dt, mode="atomic")
-            >= 8 * k * n * wd)
-    print("countsketch die partials d=%d n=%d k=%d" % (d, n, k), flush=True)
+            >= nblk * 8192 * 4)
+    print("countsketch tiled d=%d n=%d k=%d %s" % (d, n, k, np.dtype(dtype)), flush=True)
     A, h, s = _inputs(d, n, k, seed=9, dtype=dtype)
     Y, ws = ms.countsketch_apply(to_dev(A), to_dev(h), to_dev(s), k, mode="lds")
     ms.check_status(ws)
     assert rel(to_host(Y), orc.countsketch(A, h, s, k)) <= (1e-12 if dtype == np.float64 else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_countsketch_tiled_accumulate_row_blocks(ms, orc, dtype):
+    # Y += C A over two row blocks (the streaming form of Sec. 7) through the
+    # packed codes, with the tiled plan built from the codes in the workspace
+    import torch
+    d, n, k, split = 150001, 5, 65536, 70001
+    a_dt = ms.MS_F64 if dtype == np.float64 else ms.MS_F32
+    A, h, s = _inputs(d, n, k, seed=19, dtype=dtype)
+    Y = ms.empty_colmajor(k, n, torch.float64 if dtype == np.float64 else torch.float32, "cuda")
+    Y.zero_()
+    for r0, r1 in ((0, split), (split, d)):
+        print("accumulate rows %d..%d" % (r0, r1), flush=True)
+        code, _ = ms.pack_sketch(to_dev(h[r0:r1]), to_dev(s[r0:r1]), k)
+        ws = ms.workspace(ms.workspace_size("countsketch", d=r1 - r0, n=n, k=k, a_dtype=a_dt), "cuda")
+        ms.countsketch_accumulate(to_dev(A[r0:r1]), code, k, Y, mode="lds", ws=ws)
+        ms.check_status(ws)
+    assert rel(to_host(Y), orc.countsketch(A, h, s, k)) <= (1e-12 if dtype == np.float64 else 1e-5)
+
+
+def test_countsketch_tiled_range_errors(ms):
+    d, n, k = 20000, 2, 32768
+    A, h, s = _inputs(d, n, k, seed=3)
+    hb = h.copy()
+    hb[12345] = k
+    Y, ws = ms.countsketch_apply(to_dev(A), to_dev(hb), to_dev(s), k, mode="lds")
+    with pytest.raises(ms.MsketchError) as e:
+        ms.check_status(ws)
+    assert e.value.code == ms.MS_ERR_RANGE
+    sb = s.copy()
+    sb[9000] = 0
+    Y, ws = ms.countsketch_apply(to_dev(A), to_dev(h), to_dev(sb), k, mode="lds")
+    with pytest.raises(ms.MsketchError) as e:
+        ms.check_status(ws)
+    assert e.value.code == ms.MS_ERR_RANGE
 
 
 @pytest.mark.parametrize("mode", ["sorted", "lds", "atomic"])

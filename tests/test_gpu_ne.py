@@ -106,6 +106,51 @@ def test_normal_equations_full_size(ms):
     assert rel(to_host(X), to_host(Xq)) <= 1e-12
 
 
+# Wide problems (n > 64, up to 256 columns and 16 right-hand sides): the
+# tiled Gram pass and the blocked Cholesky.  Ragged shapes: a partial last
+# 64-column block, n + nrhs not a multiple of 16, d not a multiple of 16,
+# d barely above n.  Bar: the two sides sum the Gram matrix in different
+# orders, and the normal equations amplify such differences by kappa(A)^2,
+# so X agrees to about n kappa(A)^2 u (times a small factor); never looser
+# than the FP64 bar of 1e-12 where that product is below 1e-13.
+WIDE_CASES = [(20011, 65, 1, 10.0), (50000, 100, 3, 10.0), (100003, 128, 1, 10.0),
+              (30000, 200, 16, 10.0), (70001, 256, 16, 10.0), (400, 256, 1, 1.0),
+              (65536, 250, 7, 1.0)]
+
+
+@pytest.mark.parametrize("d,n,nrhs,kappa", WIDE_CASES)
+def test_normal_equations_wide_parity(ms, orc, d, n, nrhs, kappa):
+    print("normal_equations wide d=%d n=%d nrhs=%d kappa=%g" % (d, n, nrhs, kappa), flush=True)
+    A, B = _problem(d, n, nrhs, kappa, seed=d + n)
+    R = ms.empty_colmajor(n, n, torch.float64, "cuda")
+    X, _, ws = ms.normal_equations_lstsq(to_dev(A), to_dev(B), R=R)
+    ms.check_status(ws)
+    Xr = orc.normal_equations(A, B)
+    ka = np.linalg.cond(A)
+    tol = max(1e-12, 10 * n * ka ** 2 * 2.0 ** -53)
+    err = rel(to_host(X), Xr)
+    print("  kappa(A) %.3g err %.3e tol %.3e" % (ka, err, tol))
+    assert err <= tol
+    Rg = to_host(R)
+    assert np.all(np.tril(Rg, -1) == 0.0) and np.all(np.diag(Rg) > 0.0)
+    assert rel(Rg.T @ Rg, A.T @ A) <= 1e-13
+
+
+def test_normal_equations_wide_fp32_and_singular(ms, orc):
+    A, B = _problem(70001, 128, 2, 10.0, seed=8, dtype=np.float32)
+    X, _, ws = ms.normal_equations_lstsq(to_dev(A), to_dev(B))
+    ms.check_status(ws)
+    Xr = orc.normal_equations(A.astype(np.float64), B.astype(np.float64))
+    assert rel(to_host(X), Xr) <= 1e-11
+    A2, B2 = _problem(5000, 150, 1, 1.0, seed=9)
+    A2[:, 130] = 0.0   # breakdown in the third diagonal block
+    X2, _, ws2 = ms.normal_equations_lstsq(to_dev(A2), to_dev(B2))
+    with pytest.raises(ms.MsketchError) as e:
+        ms.check_status(ws2)
+    assert e.value.code == ms.MS_ERR_SINGULAR
+    assert np.all(np.isnan(to_host(X2)))
+
+
 def test_normal_equations_errors(ms):
     A, B = _problem(3000, 8, 1, 1.0, seed=5)
     Ad = to_dev(A)
@@ -115,7 +160,7 @@ def test_normal_equations_errors(ms):
         ms.check_status(ws)
     assert e.value.code == ms.MS_ERR_SINGULAR
     assert np.all(np.isnan(to_host(X)))
-    for n, nrhs in ((65, 1), (8, 17)):
+    for n, nrhs in ((257, 1), (8, 17), (260, 16)):
         A2, B2 = _problem(500, n, nrhs, 1.0, seed=6)
         with pytest.raises(ms.MsketchError) as e:
             ms.normal_equations_lstsq(to_dev(A2), to_dev(B2))
