@@ -26,7 +26,8 @@
  *    and runs asynchronously.  Argument errors are returned before anything
  *    is enqueued.  Errors found on the device (a bucket index outside [0,k),
  *    a sign that is not +-1, a zero or non-finite diagonal of R, a sorted-mode
- *    bucket longer than MS_SORTED_MAX_SEGMENT rows) are recorded in a status
+ *    bucket longer than MS_SORTED_MAX_SEGMENT rows when k >
+ *    MS_SORTED_BLOCKED_MAX_K) are recorded in a status
  *    word at the start of `ws` and returned by ms_check_status().  After such
  *    an error the outputs' contents are unspecified, except that a singular
  *    R leaves X filled with NaN.
@@ -70,8 +71,12 @@ typedef enum {
                        Alg. 2 */
 } ms_cs_mode;
 
-/* Longest bucket (rows sharing one h value) MS_CS_SORTED accepts. */
+/* Longest bucket (rows sharing one h value) MS_CS_SORTED and ms_bucket_plan
+   accept when k > MS_SORTED_BLOCKED_MAX_K (then each bucket is sorted on its
+   own in LDS).  Up to MS_SORTED_BLOCKED_MAX_K buckets the plan is a blocked
+   stable counting sort and a bucket may hold every row. */
 #define MS_SORTED_MAX_SEGMENT 16384
+#define MS_SORTED_BLOCKED_MAX_K 16384
 
 typedef struct {
   int32_t cs_mode;      /* ms_cs_mode */
@@ -139,7 +144,9 @@ const char *ms_status_string(ms_status st);
  *   perm    = the rows of bucket 0, then of bucket 1, ..., each group in
  *             ascending row order                  (d entries, int32)
  * Requires 0 <= d < 2^31, 1 <= k < 2^31.  h out of range -> MS_ERR_RANGE on
- * the device.  ws: ms_workspace_size(MS_OP_BUCKET_PLAN, d, 0, 0, k, ...).
+ * the device.  For k > MS_SORTED_BLOCKED_MAX_K a bucket longer than
+ * MS_SORTED_MAX_SEGMENT rows records MS_ERR_UNSUPPORTED (its rows are then
+ * left unsorted).  ws: ms_workspace_size(MS_OP_BUCKET_PLAN, d, 0, 0, k, ...).
  */
 ms_status ms_bucket_plan(int64_t d, int64_t k, const int32_t *h, int32_t *cnt,
                          int32_t *off, int32_t *perm, void *ws, size_t ws_bytes,

@@ -41,6 +41,7 @@ OPS = {"bucket_plan": 0, "countsketch": 1, "gaussian": 2, "multisketch": 3,
        "normal_equations": 7, "countsketch_hashed": 8, "srht": 9,
        "count_srht_lstsq": 10}
 MS_SORTED_MAX_SEGMENT = 16384
+MS_SORTED_BLOCKED_MAX_K = 16384
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(

@@ -24,7 +24,7 @@ namespace {
 
 constexpr int kPbRows = 4096;  // rows per block
 constexpr int kPbT = 1024;     // threads
-constexpr int64_t kPbMaxK = 16384;
+constexpr int64_t kPbMaxK = MS_SORTED_BLOCKED_MAX_K;
 
 // 1. LDS histogram of block b's buckets, stored as row b of cnt_tab (k
 // ints); rows with h outside [0, k) are left out and reported.

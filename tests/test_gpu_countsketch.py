@@ -44,11 +44,26 @@ def test_bucket_plan_bit_exact(ms, orc, d, k):
     assert np.array_equal(to_host(perm).astype(np.int64), perm_ref)
 
 
-def test_bucket_plan_segment_limit_reported(ms):
-    # one bucket longer than the sorted-mode limit: reported, not mis-sorted
-    d, k = 3 * ms.MS_SORTED_MAX_SEGMENT, 2
+def test_bucket_plan_long_bucket_blocked(ms, orc):
+    # up to MS_SORTED_BLOCKED_MAX_K buckets the plan is a blocked stable
+    # counting sort: a bucket holding most rows is planned exactly
+    d, k = 3 * ms.MS_SORTED_MAX_SEGMENT + 5, 2
     h = np.zeros(d, np.int32)
     h[::7] = 1
+    cnt, off, perm, ws = ms.bucket_plan(to_dev(h), k)
+    ms.check_status(ws)
+    off_ref, perm_ref = orc.bucket_plan(h, k)
+    assert np.array_equal(to_host(off).astype(np.int64), off_ref)
+    assert np.array_equal(to_host(perm).astype(np.int64), perm_ref)
+
+
+def test_bucket_plan_segment_limit_reported(ms):
+    # beyond MS_SORTED_BLOCKED_MAX_K buckets each bucket is sorted in LDS: one
+    # longer than the limit is reported, not mis-sorted
+    k = ms.MS_SORTED_BLOCKED_MAX_K + 1
+    d = 3 * ms.MS_SORTED_MAX_SEGMENT
+    h = (np.arange(d, dtype=np.int64) % k).astype(np.int32)
+    h[::2] = 0
     cnt, off, perm, ws = ms.bucket_plan(to_dev(h), k)
     with pytest.raises(ms.MsketchError) as e:
         ms.check_status(ws)
