@@ -266,6 +266,34 @@ ms_status sketch_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k,
                        void *stream);
 
 /*
+ * sketch_lstsq for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation):
+ * the same computation, arguments and limits as sketch_lstsq, with no
+ * workspace argument.  Its scratch space is a static device array of
+ * MS_NOALLOC_SCRATCH_BYTES bytes per GPU, created with the library's code
+ * object on each device it runs on and held until the process ends; the call
+ * allocates nothing.
+ *   status: optional device pointer (may be NULL) that receives, in stream
+ *   order after the solve, the device-side status that ms_check_status would
+ *   report for sketch_lstsq (MS_ERR_RANGE, MS_ERR_SINGULAR, ...).
+ * Returns MS_ERR_NOMEM, before anything is enqueued, when the problem needs
+ * more scratch than that (ms_workspace_size(MS_OP_LSTSQ, ...) >
+ * MS_NOALLOC_SCRATCH_BYTES; e.g. 4,194,304 x 64 FP64 with k = 8192 and no
+ * refinement needs 24.3 MiB), and MS_ERR_DEVICE when the array's device
+ * address cannot be obtained.  Every call on a GPU uses that GPU's one array:
+ * calls that overlap on the same GPU (streams not ordered with each other)
+ * race and give undefined results; order them.
+ */
+#define MS_NOALLOC_SCRATCH_BYTES (32 << 20)
+ms_status sketch_lstsq_noalloc(int64_t d, int64_t n, int64_t nrhs, int64_t k,
+                               int64_t k2, ms_dtype a_dtype, const void *A,
+                               int64_t lda, const void *B, int64_t ldb,
+                               const int32_t *h, const int8_t *s,
+                               ms_dtype g_dtype, const void *G, int64_t ldg,
+                               double *X, int64_t ldx, int32_t *status,
+                               const ms_opts *opts, void *stream);
+
+/*
  * rand_cholQR least squares (Alg. 5, Sec. 6.3) with the multisketch S = G C
  * as the sketch operator: X = argmin ||B - A X||, the least-squares optimum
  * itself (the sketch only preconditions; no O(1) distortion as in

@@ -23,7 +23,8 @@ __all__ = [
     "MS_ERR_DEVICE", "MS_ERR_UNSUPPORTED", "MsketchError", "LIB_PATH",
     "empty_colmajor", "colmajor", "workspace", "workspace_size", "check_status",
     "bucket_plan", "pack_sketch", "countsketch_accumulate", "countsketch_apply",
-    "gaussian_apply", "multisketch_apply", "qr_solve", "sketch_lstsq", "rand_cholqr_lstsq",
+    "gaussian_apply", "multisketch_apply", "qr_solve", "sketch_lstsq", "sketch_lstsq_noalloc",
+    "NOALLOC_SCRATCH_BYTES", "rand_cholqr_lstsq",
     "normal_equations_lstsq", "countsketch_hashed", "hash_sketch", "srht_apply",
     "count_srht_lstsq", "MsProblem",
     "batch_workspace_size", "sketch_lstsq_batched", "batch_status", "BatchRunner",
@@ -42,6 +43,7 @@ OPS = {"bucket_plan": 0, "countsketch": 1, "gaussian": 2, "multisketch": 3,
        "count_srht_lstsq": 10}
 MS_SORTED_MAX_SEGMENT = 16384
 MS_SORTED_BLOCKED_MAX_K = 16384
+NOALLOC_SCRATCH_BYTES = 32 << 20   # MS_NOALLOC_SCRATCH_BYTES of msketch.h
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
@@ -87,6 +89,8 @@ _SIGS = {
                      _p], _i32),
     "sketch_lstsq": ([_i64, _i64, _i64, _i64, _i64, _i32, _p, _i64, _p, _i64, _p, _p,
                       _i32, _p, _i64, _p, _i64, _p, _p, _sz, _p], _i32),
+    "sketch_lstsq_noalloc": ([_i64, _i64, _i64, _i64, _i64, _i32, _p, _i64, _p, _i64, _p, _p,
+                              _i32, _p, _i64, _p, _i64, _p, _p, _p], _i32),
     "rand_cholqr_lstsq": ([_i64, _i64, _i64, _i64, _i64, _i32, _p, _i64, _p, _i64, _p, _p,
                            _i32, _p, _i64, _p, _i64, _p, _i64, _p, _p, _sz, _p], _i32),
     "normal_equations_lstsq": ([_i64, _i64, _i64, _i32, _p, _i64, _p, _i64, _p, _i64, _p, _i64,
@@ -457,6 +461,40 @@ def sketch_lstsq(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torch.Ten
                           _vec(s, torch.int8, "s"), g_dt, Gp, ldg, Xp, ldx, ctypes.byref(o), wp,
                           have, _stream(stream)), "sketch_lstsq")
     return X, ws
+
+
+def sketch_lstsq_noalloc(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torch.Tensor,
+                         G: torch.Tensor, k: int, X: torch.Tensor, status: torch.Tensor | None = None,
+                         refine_steps: int = 0, mode: str = "auto", stream=None,
+                         y_terms: int = 0):
+    """sketch_lstsq with the library's static per-device scratch array instead
+    of a workspace: the caller passes the inputs and the outputs X (n x nrhs,
+    FP64, column-major) and optionally ``status`` (a 1-element int32 device
+    tensor receiving the device-side status).  Allocates nothing.  Returns X."""
+    d, n = A.shape
+    if B.dim() == 1:
+        B = B.unsqueeze(1)
+    nrhs = B.shape[1]
+    k2 = G.shape[0]
+    a_dt, g_dt = _dt(A), _dt(G)
+    if B.dtype != A.dtype:
+        raise ValueError("B must have A's dtype")
+    Ap, lda = colmajor(A, "A")
+    Bp, ldb = colmajor(B, "B")
+    Gp, ldg = colmajor(G, "G")
+    Xp, ldx = colmajor(X, "X")
+    Xs = X if X.dim() == 2 else X.unsqueeze(1)
+    if X.dtype != torch.float64 or tuple(Xs.shape) != (n, nrhs):
+        raise ValueError("X must be an n x nrhs FP64 tensor")
+    sp = None
+    if status is not None:
+        sp = _vec(status.view(-1), torch.int32, "status")
+    o = _opts(mode, refine_steps, y_terms=y_terms)
+    _ok(_lib.sketch_lstsq_noalloc(d, n, nrhs, k, k2, a_dt, Ap, lda, Bp, ldb,
+                                  _vec(h, torch.int32, "h"), _vec(s, torch.int8, "s"), g_dt, Gp,
+                                  ldg, Xp, ldx, sp, ctypes.byref(o), _stream(stream)),
+        "sketch_lstsq_noalloc")
+    return X
 
 
 def rand_cholqr_lstsq(A: torch.Tensor, B: torch.Tensor, h: torch.Tensor, s: torch.Tensor,
