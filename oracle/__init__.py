@@ -75,6 +75,9 @@ def _load():
                                     _i64, _p, _p],
             "or_round_bf16": [ctypes.c_float],
             "or_round_bf16_array": [_i64, _p, _p],
+            "or_round_f16": [ctypes.c_float],
+            "or_f16_col_exp": [_i64, _p],
+            "or_round_f16_colscaled": [_i64, _i64, _p, _i64, _p, _i64],
             "or_rand_cholqr_from_sketch": [_i64, _i64, _i64, _i64, _p, _i64, _p, _i64,
                                            _p, _i64, _p, _i64, _p, _i64],
             "or_splitmix64": [ctypes.c_uint64, _i64, _p],
@@ -90,6 +93,8 @@ def _load():
         lib.or_apply_qt.restype = None
         lib.or_round_bf16.restype = ctypes.c_float
         lib.or_round_bf16_array.restype = None
+        lib.or_round_f16.restype = ctypes.c_float
+        lib.or_round_f16_colscaled.restype = None
         lib.or_splitmix64.restype = None
         _lib = lib
     return _lib
@@ -278,14 +283,16 @@ def normal_equations(A, B) -> np.ndarray:
 # Composite multisketch sketch-and-solve (Alg. 1 with S = G C)
 # --------------------------------------------------------------------------
 
-def sketch_lstsq(A, B, h, s, G, k: int, y_bf16: bool = False, y_acc64: bool = False):
+def sketch_lstsq(A, B, h, s, G, k: int, y_bf16: bool = False, y_acc64: bool = False,
+                 y_f16: bool = False):
     """X = argmin ||G C (B - A X)|| via Alg. 1 with the multisketch S = G C.
 
     FP64 A: CountSketch in FP64.  FP32 A: CountSketch in FP32 (folded in FP32
     in the canonical order, or with ``y_acc64`` Def. 3's sums taken in FP64
     and rounded once to FP32), optional RNE rounding of the sketch to BF16
-    (``y_bf16``), Gaussian stage and QR in FP64 on the exact FP64 images of
-    the stored values.  G is passed as its
+    (``y_bf16``) or to FP16 after the FP16 stage's per-column power-of-two
+    scale (``y_f16``, see ``round_f16_colscaled``), Gaussian stage and QR in
+    FP64 on the exact FP64 images of the stored values.  G is passed as its
     stored values (float64, float32 or BF16 values held in float32/float64).
     Returns (X, Y, Z): solution n x nrhs, CountSketch k x (n+nrhs) and the
     Gaussian-stage output k2 x (n+nrhs).
@@ -319,7 +326,8 @@ def sketch_lstsq(A, B, h, s, G, k: int, y_bf16: bool = False, y_acc64: bool = Fa
         Z = np.zeros((k2, n + nrhs), dtype=np.float64, order="F")
         rc = lib.or_sketch_lstsq_f32(d, n, nrhs, k, k2, _ptr(A), _ld(A), _ptr(B),
                                      _ld(B), _ptr(h), _ptr(s), _ptr(Gd), _ld(Gd),
-                                     (1 if y_bf16 else 0) | (2 if y_acc64 else 0),
+                                     (1 if y_bf16 else 0) | (2 if y_acc64 else 0) |
+                                     (4 if y_f16 else 0),
                                      _ptr(X), max(1, n),
                                      _ptr(Y), _ptr(Z))
     else:
@@ -354,7 +362,7 @@ def rand_cholqr_from_sketch(SA, A, B):
     return X, R
 
 
-def rand_cholqr_lstsq(A, B, h, s, G, k: int, y_bf16: bool = False):
+def rand_cholqr_lstsq(A, B, h, s, G, k: int, y_bf16: bool = False, y_f16: bool = False):
     """x = argmin ||B - A x|| by rand_cholQR least squares (Alg. 5) with the
     multisketch S = G C as the sketch operator (step 1: the CountSketch of A
     in A's precision, optionally rounded to BF16 for an FP32 A, then the
@@ -366,6 +374,8 @@ def rand_cholqr_lstsq(A, B, h, s, G, k: int, y_bf16: bool = False):
     Y = countsketch(A, h, s, k)
     if A.dtype == np.float32 and y_bf16:
         Y = round_bf16(Y)
+    elif A.dtype == np.float32 and y_f16:
+        Y = round_f16_colscaled(Y)
     SA = gemm(Gd, np.asarray(Y, dtype=np.float64))
     X, R = rand_cholqr_from_sketch(SA, A, B)
     return X, R, SA
@@ -453,6 +463,40 @@ def round_bf16(x) -> np.ndarray:
     out = np.empty_like(flat)
     lib.or_round_bf16_array(flat.shape[0], _ptr(flat), _ptr(out))
     return out.reshape(x.shape, order=order)
+
+
+def round_f16(x) -> np.ndarray:
+    """Round FP32 values to FP16 (IEEE binary16, RNE, subnormals kept,
+    overflow to infinity), returned as the FP32 values they are."""
+    lib = _load()
+    x = np.asarray(x, dtype=np.float32)
+    out = np.empty(x.shape, dtype=np.float32)
+    flat_in = x.reshape(-1)
+    flat_out = out.reshape(-1)
+    for i in range(flat_in.shape[0]):
+        flat_out[i] = lib.or_round_f16(float(flat_in[i]))
+    return out
+
+
+def f16_col_exp(y) -> int:
+    """The FP16 Gaussian stage's scale exponent of one FP32 column:
+    floor(log2 max |y|) - 14 held in [-112, 112]; 0 for a zero or
+    non-finite column."""
+    y = np.ascontiguousarray(y, dtype=np.float32).reshape(-1)
+    return int(_load().or_f16_col_exp(y.shape[0], _ptr(y)))
+
+
+def round_f16_colscaled(Y) -> np.ndarray:
+    """Y (k x nc, FP32) as the FP16 Gaussian stage reads it: column c scaled
+    by 2^-e_c (e_c = f16_col_exp of the column; an FP32 product), rounded to
+    FP16 (RNE) and scaled back by 2^e_c.  Returns FP64 (exact values)."""
+    Y = _fortran(Y, np.float32)
+    if Y.ndim == 1:
+        Y = Y.reshape(-1, 1, order="F")
+    k, nc = Y.shape
+    out = np.zeros((k, nc), dtype=np.float64, order="F")
+    _load().or_round_f16_colscaled(k, nc, _ptr(Y), _ld(Y), _ptr(out), max(1, k))
+    return out
 
 
 def lstsq_tsqr(A, B, block_rows: int = 1 << 18):

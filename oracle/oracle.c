@@ -460,9 +460,66 @@ void or_round_bf16_array(int64_t count, const float *x, float *out) {
   for (int64_t i = 0; i < count; ++i) out[i] = or_round_bf16(x[i]);
 }
 
+/* ------------------------------------------------------------------------ */
+/* FP16 rounding (IEEE binary16: 11-bit significand, exponents -14..15,     */
+/* subnormals spaced 2^-24, largest finite 65504), round to nearest, ties to */
+/* even, of an FP32 value, returned as the FP32 value it denotes.  The      */
+/* spacing of binary16 numbers around |x| in [2^(E-1), 2^E) is 2^(E-11),    */
+/* never below 2^-24; |x| is rounded to a multiple of that spacing (exact   */
+/* in FP64) and a result of 2^16 or more overflows to infinity.             */
+/* ------------------------------------------------------------------------ */
+
+float or_round_f16(float x) {
+  if (isnan(x) || isinf(x)) return x;
+  const double a = fabs((double)x);
+  if (a == 0.0) return x;
+  int E;
+  frexp(a, &E); /* a = m 2^E, m in [0.5, 1) */
+  int q = E - 11;
+  if (q < -24) q = -24;
+  const double r = ldexp(nearbyint(ldexp(a, -q)), q); /* ties to even */
+  const float v = r >= 65536.0 ? INFINITY : (float)r;
+  return x < 0.0f ? -v : v;
+}
+
+/* The FP16 Gaussian stage's column exponent: e = floor(log2 max_i |y_i|) -
+ * 14 held in [-112, 112], so that 2^-e y has its largest magnitude in
+ * [2^14, 2^15); 0 for a zero column or one holding a NaN or an infinity. */
+int or_f16_col_exp(int64_t k, const float *y) {
+  double m = 0.0;
+  for (int64_t i = 0; i < k; ++i) {
+    if (!isfinite(y[i])) return 0;
+    const double a = fabs((double)y[i]);
+    if (a > m) m = a;
+  }
+  if (m == 0.0) return 0;
+  int E;
+  frexp(m, &E); /* floor(log2 m) = E - 1 */
+  int e = E - 1 - 14;
+  if (e < -112) e = -112;
+  if (e > 112) e = 112;
+  return e;
+}
+
+/* Y (k x nc, FP32) as the FP16 Gaussian stage reads it: column c scaled by
+ * 2^-e_c (an FP32 product), rounded to FP16, scaled back by 2^e_c (exact in
+ * FP64).  out: k x nc FP64. */
+void or_round_f16_colscaled(int64_t k, int64_t nc, const float *Y, int64_t ldy,
+                            double *out, int64_t ldo) {
+  for (int64_t c = 0; c < nc; ++c) {
+    const float *y = Y + c * ldy;
+    const int e = or_f16_col_exp(k, y);
+    const float down = ldexpf(1.0f, -e);
+    for (int64_t i = 0; i < k; ++i)
+      out[i + c * ldo] = ldexp((double)or_round_f16(y[i] * down), e);
+  }
+}
+
 /*
  * FP32 data path of the same composite: Y = C [A | B] folded in FP32; when
- * y_bf16 is non-zero Y is rounded to BF16 (RNE) before the Gaussian stage;
+ * y_bf16 has ORACLE_Y_BF16 Y is rounded to BF16 (RNE) before the Gaussian
+ * stage, with ORACLE_Y_F16 to FP16 after the column scaling of the FP16
+ * stage (or_round_f16_colscaled);
  * Z = G Y is then formed in FP64 from the exact FP64 images of the FP32 (or
  * BF16) values and of G (G is passed as the FP64 images of its stored
  * values); QR and solve are FP64.
@@ -500,8 +557,11 @@ int or_sketch_lstsq_f32(int64_t d, int64_t n, int64_t nrhs, int64_t k,
       st = or_countsketch_f32(d, nrhs, k, B, ldb, h, s, Y + n * k, k);
   }
   if (st == ORACLE_OK) {
-    for (int64_t t = 0; t < k * nc; ++t)
-      Yd[t] = (double)((y_bf16 & ORACLE_Y_BF16) ? or_round_bf16(Y[t]) : Y[t]);
+    if (y_bf16 & ORACLE_Y_F16)
+      or_round_f16_colscaled(k, nc, Y, k, Yd, k);
+    else
+      for (int64_t t = 0; t < k * nc; ++t)
+        Yd[t] = (double)((y_bf16 & ORACLE_Y_BF16) ? or_round_bf16(Y[t]) : Y[t]);
     or_gemm_f64(k2, nc, k, G, ldg, Yd, k, Z, k2);
     st = or_qr_solve(k2, n, nrhs, Z, k2, Z + n * k2, k2, X, ldx);
   }

@@ -56,6 +56,7 @@ void or_round_bf16_array(int64_t count, const float *x, float *out);
  * to FP32 (else folded in FP32, the canonical order) */
 #define ORACLE_Y_BF16 1
 #define ORACLE_Y_ACC64 2
+#define ORACLE_Y_F16 4
 int or_sketch_lstsq_f32(int64_t d, int64_t n, int64_t nrhs, int64_t k,
                         int64_t k2, const float *A, int64_t lda,
                         const float *B, int64_t ldb, const int32_t *h,
@@ -72,5 +73,10 @@ int or_hash_sketch(int64_t d, int64_t k, uint64_t seed, int32_t *h, int8_t *s);
 
 int or_srht(int64_t mx, int64_t ncols, int64_t k, const double *X, int64_t ldx,
             const int8_t *dsign, const int32_t *r, double *Y, int64_t ldy);
+
+float or_round_f16(float x);
+int or_f16_col_exp(int64_t k, const float *y);
+void or_round_f16_colscaled(int64_t k, int64_t nc, const float *Y, int64_t ldy,
+                            double *out, int64_t ldo);
 
 #endif

@@ -81,6 +81,14 @@ MUTANTS = [
      "const long double scale = 1.0L / (long double)k;", 0),
     ("hash_row_off_by_one", "or_mix64(seed + (uint64_t)(i + 1) * UINT64_C(0x9E3779B97F4A7C15));",
      "or_mix64(seed + (uint64_t)i * UINT64_C(0x9E3779B97F4A7C15));", 0),
+    # FP16 Gaussian-stage reference: rounding and the per-column scale
+    ("f16_ties_away", "const double r = ldexp(nearbyint(ldexp(a, -q)), q);",
+     "const double r = ldexp(round(ldexp(a, -q)), q);", 0),
+    ("f16_no_subnormals", "if (q < -24) q = -24;", "if (q < -14) q = -14;", 0),
+    ("f16_overflow_late", "r >= 65536.0 ? INFINITY", "r > 65536.0 ? INFINITY", 0),
+    ("f16_colexp_off_by_one", "int e = E - 1 - 14;", "int e = E - 14;", 0),
+    ("f16_scale_not_restored", "out[i + c * ldo] = ldexp((double)or_round_f16(y[i] * down), e);",
+     "out[i + c * ldo] = (double)or_round_f16(y[i] * down);", 0),
 ]
 
 
@@ -111,7 +119,8 @@ def _run_mutant(args):
                         os.path.join(ROOT, "tests", "test_oracle_solve.py"),
                         os.path.join(ROOT, "tests", "test_oracle_rcq.py"),
                         os.path.join(ROOT, "tests", "test_oracle_hash.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_srht.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_srht.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_f16.py")],
                        env=env, cwd=ROOT, capture_output=True, text=True, timeout=600)
     return name, r.returncode, r.stdout[-600:]
 
