@@ -69,7 +69,7 @@ def parse():
                              "copy", "gaussian_f64", "gaussian_bf16", "batched_mixed",
                              "solve_fp32", "solve_mixed", "rand_cholqr",
                              "normal_equations", "countsketch_hashed", "srht",
-                             "paper_comparison"],
+                             "paper_comparison", "countsketch_sorted"],
                     help="profiling runs: launch only the LDS CountSketch of [A | b] (--steps "
                          "times), only a plain device copy of 1 GiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters), or only the Gaussian stage of the "
@@ -795,8 +795,31 @@ def main():
         for _ in range(args.steps):
             ms.countsketch_accumulate(ABx, code, k_, Yx, mode="lds", ws=cws)
         ms.check_status(cws)
-        print(json.dumps({"only": args.only, "kernel": "k_cs_lds_xcd", "launches": args.steps,
+        print(json.dumps({"only": args.only, "kernel": "k_cs_tiled", "launches": args.steps,
                           "bytes_per_launch": d_ * nc_ * 4 + d_ * 4 + k_ * nc_ * 4}))
+        return
+    if args.only == "countsketch_sorted":
+        # the deterministic CountSketch of [A | b] (4,194,304 x 65 FP64, k =
+        # 8192): blocked stable plan, then the fold of each bucket in
+        # ascending row order; and the plan alone (ms_bucket_plan)
+        d_, nc_, k_ = 4194304, 65, 8192
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(args.seed)
+        ABx = torch.randn((nc_, d_), generator=gen, device=dev, dtype=torch.float64).t()
+        hx = torch.randint(0, k_, (d_,), generator=gen, device=dev, dtype=torch.int32)
+        sx = (torch.randint(0, 2, (d_,), generator=gen, device=dev, dtype=torch.int8) * 2 - 1)
+        Yx, sws = ms.countsketch_apply(ABx, hx, sx, k_, mode="sorted")
+        cnt, off, perm, pws = ms.bucket_plan(hx, k_)
+        torch.cuda.synchronize()
+        for _ in range(args.steps):
+            ms.countsketch_apply(ABx, hx, sx, k_, mode="sorted", Y=Yx, ws=sws)
+            ms.bucket_plan(hx, k_, ws=pws)
+        ms.check_status(sws)
+        ms.check_status(pws)
+        print(json.dumps({"only": args.only, "kernels": "k_pb_* (plan), k_cs_sorted_cols (fold)",
+                          "launches": args.steps + 1,
+                          "bytes_per_launch": {"fold": d_ * nc_ * 8 + d_ * 4 + k_ * nc_ * 8,
+                                               "plan": d_ * 4 + d_ * 4 + 2 * k_ * 4}}))
         return
     if args.only in ("gaussian_f64", "gaussian_bf16"):
         # Gaussian stage alone on device-generated inputs of the workload's shape

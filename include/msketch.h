@@ -55,7 +55,8 @@ typedef enum {
   MS_ERR_UNSUPPORTED = 6  /* valid but unsupported combination or size */
 } ms_status;
 
-typedef enum { MS_F64 = 0, MS_F32 = 1, MS_BF16 = 2 } ms_dtype;
+/* MS_BF16 and MS_F16 are passed as their 16-bit patterns (G only). */
+typedef enum { MS_F64 = 0, MS_F32 = 1, MS_BF16 = 2, MS_F16 = 3 } ms_dtype;
 
 /* How the CountSketch sum of Eq. (2) is formed on the device. */
 typedef enum {
@@ -92,15 +93,17 @@ typedef struct {
   int32_t batch_kchunk_log2; /* sketch_lstsq_batched tuning: K per Gaussian-
                                 stage work item = 2^x (0 = automatic, else
                                 5..20) */
-  int32_t gauss_y_terms;     /* BF16 Gaussian stage (multisketch_apply,
-                                sketch_lstsq, rand_cholqr_lstsq,
-                                sketch_lstsq_batched): 1 = Y rounded to BF16
-                                (nearest even); 3 = Y split into three BF16
-                                terms hi + mid + lo that sum to Y exactly, so
-                                G Y is formed from the exact Y with FP32
-                                accumulation (three matrix-core products per
-                                step, G read once); 0 = 3.  Other values:
-                                MS_ERR_ARG. */
+  int32_t gauss_y_terms;     /* BF16 / FP16 Gaussian stage
+                                (multisketch_apply, sketch_lstsq,
+                                rand_cholqr_lstsq, sketch_lstsq_batched):
+                                1 = Y rounded to G's 16-bit format (nearest
+                                even); 3 = Y split into three such terms
+                                hi + mid + lo that sum to Y exactly (FP16:
+                                down to 2^-40 of the column's largest
+                                magnitude), so G Y is formed from the exact
+                                Y with FP32 accumulation (three matrix-core
+                                products per step, G read once); 0 = 3.
+                                Other values: MS_ERR_ARG. */
   int32_t reserved1;
 } ms_opts;
 
@@ -208,7 +211,14 @@ ms_status countsketch_apply(int64_t d, int64_t n, int64_t k, ms_dtype a_dtype,
  *                        (F32, F32): FP32 MFMA, Z is FP32.
  *                        (BF16, F32): Y rounded to BF16 (round to nearest
  *                        even), BF16 MFMA with FP32 accumulation, Z is FP32.
- *   G: k2 x k (BF16 is passed as its 16-bit patterns), ldg >= k2.
+ *                        (F16, F32): column c of Y scaled by 2^-e_c,
+ *                        e_c = floor(log2 max_i |Y[i,c]|) - 14 held in
+ *                        [-112, 112] (0 for a zero or non-finite column),
+ *                        rounded to FP16 (nearest even), FP16 MFMA with
+ *                        FP32 accumulation, column c of the product
+ *                        multiplied by 2^e_c; Z is FP32.
+ *   G: k2 x k (BF16 and FP16 are passed as their 16-bit patterns),
+ *   ldg >= k2.
  *   Y: k x ncols, ldy >= k.   Z: k2 x ncols, ldz >= k2.
  */
 ms_status ms_gaussian_apply(int64_t k, int64_t ncols, int64_t k2,
@@ -220,7 +230,8 @@ ms_status ms_gaussian_apply(int64_t k, int64_t ncols, int64_t k2,
 /*
  * Multisketch Z = G (S A) (Sec. 1; Table 1 "MultiSketch"), always in that
  * association: the CountSketch first, then the Gaussian stage.
- *   a_dtype F64 -> g_dtype F64, Z FP64;  a_dtype F32 -> g_dtype F32 or BF16,
+ *   a_dtype F64 -> g_dtype F64, Z FP64;  a_dtype F32 -> g_dtype F32, BF16 or
+ *   F16 (the 16-bit stages as in ms_gaussian_apply, with opts->gauss_y_terms),
  *   Z FP32.  Z: k2 x n, ldz >= k2.  Requires k2 >= 1.
  */
 ms_status multisketch_apply(int64_t d, int64_t n, int64_t k, int64_t k2,
@@ -251,7 +262,7 @@ ms_status ms_qr_solve(int64_t m, int64_t n, int64_t nrhs, const double *W,
  * Steps: Y = C [A | B] (CountSketch, A's precision); Z = G Y (Gaussian stage,
  * MFMA in the precision of g_dtype); Householder QR of Z_A (k2 x n, FP64);
  * Q^T applied to Z_B; back substitution.
- *   a_dtype F64: g_dtype F64.   a_dtype F32: g_dtype F32 or BF16.
+ *   a_dtype F64: g_dtype F64.   a_dtype F32: g_dtype F32, BF16 or F16.
  *   Requires d >= 1, n >= 1, nrhs >= 1, k >= 1, k2 >= n.
  * opts->refine_steps > 0 (requires nrhs <= 8) then repeats, in FP64,
  *   r = B - A X;  X += R^{-1} Q^T G (C r)
@@ -300,14 +311,18 @@ ms_status sketch_lstsq_noalloc(int64_t d, int64_t n, int64_t nrhs, int64_t k,
  * sketch_lstsq).  Steps: Y = S A (CountSketch of A in its precision, then
  * the Gaussian stage), R0 = the R factor of the Householder QR of Y,
  * Q0 = A R0^{-1}, Q0^T Q0 and Q0^T B in FP64 in one pass over A and B
- * (FP32 data promoted exactly; Q0 is not stored), R1 = chol(Q0^T Q0),
+ * (FP32 data promoted exactly; Q0 is not stored up to n = 64),
+ * R1 = chol(Q0^T Q0),
  * R = R1 R0, y = R1^{-T} Q0^T B, X = R^{-1} y.  Stable for kappa(A) < 1/u
  * (Sec. 6.3); the FP32 / BF16 sketch of an FP32 A changes only the
  * preconditioner, so X is the FP64 optimum for the stored data.
  *   Arguments as for sketch_lstsq, plus R (may be NULL): n x n (ld ldr >= n),
  *   receives R (upper triangular, zeros below; A = Q R with Q = A R^{-1}).
  *   opts->refine_steps must be 0.
- * Limits: n <= 64, nrhs <= 16 (else MS_ERR_UNSUPPORTED).  Device status:
+ * Limits: n <= 256, nrhs <= 16, n + nrhs <= 272 (else MS_ERR_UNSUPPORTED).
+ * Beyond n = 64 or n + nrhs = 80, Q0 is formed on matrix cores and stored
+ * (d x n FP64 in the workspace) and its Gram product is a second pass.
+ * Device status:
  * MS_ERR_SINGULAR (X = NaN) when R0 or the Cholesky factor breaks down,
  * MS_ERR_RANGE for h or s out of range.
  * ws: ms_workspace_size(MS_OP_RAND_CHOLQR, d, n, nrhs, k, k2, a_dtype,
@@ -464,7 +479,8 @@ size_t ms_batch_workspace_size(int count, const ms_problem *probs,
  *   probs_host host copy of the descriptors: validated, and used for the
  *              launch shapes (LDS size, QR register tile);
  *   probs_dev  the same descriptors in device memory (read by the kernels);
- *   a_dtype    MS_F32 or MS_F64 (all problems); g_dtype as for sketch_lstsq.
+ *   a_dtype    MS_F32 or MS_F64 (all problems); g_dtype as for sketch_lstsq
+ *              except MS_F16 (MS_ERR_UNSUPPORTED).
  * Limits per problem: k2 <= MS_BATCH_MAX_K2, n + nrhs <= MS_BATCH_MAX_COLS,
  * k2 >= n >= 1, nrhs >= 1, 1 <= d < 2^31, 1 <= k < 2^31.  The CountSketch is the
  * LDS variant (opts->cs_mode MS_CS_SORTED or MS_CS_ATOMIC ->

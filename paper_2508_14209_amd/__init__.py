@@ -35,7 +35,7 @@ LIB_PATH = os.path.join(HERE, "libmsketch.so")
 
 MS_OK, MS_ERR_ARG, MS_ERR_RANGE, MS_ERR_NOMEM, MS_ERR_SINGULAR, MS_ERR_DEVICE, \
     MS_ERR_UNSUPPORTED = range(7)
-MS_F64, MS_F32, MS_BF16 = 0, 1, 2
+MS_F64, MS_F32, MS_BF16, MS_F16 = 0, 1, 2, 3
 MODES = {"auto": 0, "atomic": 1, "lds": 2, "sorted": 3}
 OPS = {"bucket_plan": 0, "countsketch": 1, "gaussian": 2, "multisketch": 3,
        "qr_solve": 4, "lstsq": 5, "rand_cholqr": 6,
@@ -130,10 +130,13 @@ def _dt(t: torch.Tensor) -> int:
         return MS_F32
     if t.dtype == torch.bfloat16:
         return MS_BF16
+    if t.dtype == torch.float16:
+        return MS_F16
     raise TypeError("unsupported dtype %s" % t.dtype)
 
 
-_TORCH_DT = {MS_F64: torch.float64, MS_F32: torch.float32, MS_BF16: torch.bfloat16}
+_TORCH_DT = {MS_F64: torch.float64, MS_F32: torch.float32, MS_BF16: torch.bfloat16,
+             MS_F16: torch.float16}
 
 
 def empty_colmajor(rows: int, cols: int, dtype, device="cuda") -> torch.Tensor:
@@ -388,8 +391,9 @@ def gaussian_apply(G: torch.Tensor, Y: torch.Tensor, Z: torch.Tensor | None = No
 def multisketch_apply(A: torch.Tensor, h: torch.Tensor, s: torch.Tensor, G: torch.Tensor,
                       k: int, Z: torch.Tensor | None = None, mode: str = "auto",
                       ws: torch.Tensor | None = None, stream=None, y_terms: int = 0):
-    """Z = G (S A) (k2 x n).  y_terms (BF16 G): 1 = S A rounded to BF16, 3 (or
-    0, the default) = S A as three exact BF16 terms.  Returns (Z, ws)."""
+    """Z = G (S A) (k2 x n).  y_terms (BF16 or FP16 G): 1 = S A rounded to G's
+    16-bit format (FP16: after a power-of-two scale per column), 3 (or 0, the
+    default) = S A as three exact 16-bit terms.  Returns (Z, ws)."""
     d, n = A.shape
     k2 = G.shape[0]
     a_dt, g_dt = _dt(A), _dt(G)

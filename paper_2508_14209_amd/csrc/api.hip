@@ -147,15 +147,26 @@ LstsqLayout lstsq_layout(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64_t 
 }
 
 // rand_cholQR least squares: the multisketch of A alone, its QR (R0 kept),
-// R0^{-1}, the fused pass's per-workgroup partials and their sum.
+// R0^{-1}, the fused pass's per-workgroup partials and their sum; for wide
+// problems (n > 64 or n + nrhs > 80) R0^{-1} of order n, Q0 = A R0^{-1}
+// (d x n FP64), the wide Gram pass's per-chunk partials, the Gram matrix and
+// the factorisation's breakdown flag.
 struct RcqLayout {
   CsLayout cs;
   size_t y = 0, partials = 0, z64 = 0, qr = 0, fact = 0, tau = 0;
-  size_t r0 = 0, rinv = 0, part = 0, w = 0, total = 0;
+  size_t r0 = 0, rinv = 0, part = 0, w = 0, q0 = 0, bad = 0, total = 0;
+  bool wide = false;
 };
 
-RcqLayout rcq_layout(int64_t d, int64_t n, int64_t k, int64_t k2, ms_dtype a_dtype,
-                     ms_dtype g_dtype, int mode) {
+bool rcq_is_wide(int64_t n, int64_t nrhs) {
+  return n > kRcqMaxN || nrhs > kRcqMaxRhs || n + nrhs > kRcqMaxCols;
+}
+bool rcq_fits_wide(int64_t n, int64_t nrhs) {
+  return n <= kWideMaxN && nrhs <= kWideMaxRhs && n + nrhs <= kWideMaxCols;
+}
+
+RcqLayout rcq_layout(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64_t k2,
+                     ms_dtype a_dtype, ms_dtype g_dtype, int mode) {
   RcqLayout L;
   Carve cv;
   carve_cs(cv, L.cs, d, k, mode, n, dtype_size(a_dtype));
@@ -165,10 +176,20 @@ RcqLayout rcq_layout(int64_t d, int64_t n, int64_t k, int64_t k2, ms_dtype a_dty
   L.qr = cv.take(qr_workspace_bytes(k2, n, 0));
   L.fact = cv.take((size_t)k2 * n * 8);
   L.tau = cv.take((size_t)n * 8);
-  L.r0 = cv.take((size_t)kRcqMaxN * kRcqMaxN * 8);
-  L.rinv = cv.take((size_t)kRcqMaxN * kRcqMaxN * 8);
-  L.part = cv.take(rcq_partial_bytes(rcq_grid()));
-  L.w = cv.take((size_t)kRcqMaxN * kRcqMaxCols * 8);
+  L.wide = rcq_is_wide(n, nrhs) && rcq_fits_wide(n, nrhs);
+  if (L.wide) {
+    const int nc = (int)(n + nrhs);
+    L.rinv = cv.take((size_t)n * n * 8);
+    L.q0 = cv.take((size_t)d * n * 8);
+    L.part = cv.take(gram_wide_partial_bytes(d, nc));
+    L.w = cv.take(gram_wide_w_bytes(nc));
+    L.bad = cv.take(4);
+  } else {
+    L.r0 = cv.take((size_t)kRcqMaxN * kRcqMaxN * 8);
+    L.rinv = cv.take((size_t)kRcqMaxN * kRcqMaxN * 8);
+    L.part = cv.take(rcq_partial_bytes(rcq_grid()));
+    L.w = cv.take((size_t)kRcqMaxN * kRcqMaxCols * 8);
+  }
   L.total = cv.off;
   return L;
 }
@@ -203,12 +224,8 @@ struct NeLayout {
   size_t part = 0, w = 0, bad = 0, total = 0;
 };
 
-bool ne_is_wide(int64_t n, int64_t nrhs) {
-  return n > kRcqMaxN || nrhs > kRcqMaxRhs || n + nrhs > kRcqMaxCols;
-}
-bool ne_fits_wide(int64_t n, int64_t nrhs) {
-  return n <= kWideMaxN && nrhs <= kWideMaxRhs && n + nrhs <= kWideMaxCols;
-}
+bool ne_is_wide(int64_t n, int64_t nrhs) { return rcq_is_wide(n, nrhs); }
+bool ne_fits_wide(int64_t n, int64_t nrhs) { return rcq_fits_wide(n, nrhs); }
 
 NeLayout ne_layout(int64_t d, int64_t n, int64_t nrhs) {
   NeLayout L;
@@ -364,7 +381,7 @@ size_t ms_workspace_size(int op, int64_t d, int64_t n, int64_t nrhs, int64_t k, 
       return lstsq_layout(d, n, nrhs, k, k2, a_dtype, g_dtype, mode, refine).total;
     }
     case MS_OP_RAND_CHOLQR:
-      return rcq_layout(d, n, k, k2, a_dtype, g_dtype, mode).total;
+      return rcq_layout(d, n, nrhs, k, k2, a_dtype, g_dtype, mode).total;
     case MS_OP_NORMAL_EQUATIONS:
       return ne_layout(d, n, nrhs).total;
     case MS_OP_SRHT:
@@ -515,7 +532,7 @@ ms_status ms_gaussian_apply(int64_t k, int64_t ncols, int64_t k2, ms_dtype g_dty
   if (k < 1 || ncols < 0 || k2 < 1 || k2 > (1 << 24) || ncols > (1 << 24)) return MS_ERR_ARG;
   const bool ok = (g_dtype == MS_F64 && y_dtype == MS_F64) ||
                   (g_dtype == MS_F32 && y_dtype == MS_F32) ||
-                  (g_dtype == MS_BF16 && y_dtype == MS_F32);
+                  ((g_dtype == MS_BF16 || g_dtype == MS_F16) && y_dtype == MS_F32);
   if (!ok) return MS_ERR_ARG;
   if (ldg < k2 || ldy < k || ldz < k2) return MS_ERR_ARG;
   if (!ws || (ncols > 0 && (!G || !Y || !Z))) return MS_ERR_ARG;
@@ -538,7 +555,8 @@ ms_status multisketch_apply(int64_t d, int64_t n, int64_t k, int64_t k2, ms_dtyp
   if (d < 0 || n < 0 || k < 1 || k > kMax31 || k2 < 1 || k2 > (1 << 24) || n > (1 << 24))
     return MS_ERR_ARG;
   const bool ok = (a_dtype == MS_F64 && g_dtype == MS_F64) ||
-                  (a_dtype == MS_F32 && (g_dtype == MS_F32 || g_dtype == MS_BF16));
+                  (a_dtype == MS_F32 &&
+                   (g_dtype == MS_F32 || g_dtype == MS_BF16 || g_dtype == MS_F16));
   if (!ok || !valid_mode(opts)) return MS_ERR_ARG;
   const int mode = resolve_mode(opts);
   if (mode == MS_CS_SORTED && d > kMax31) return MS_ERR_UNSUPPORTED;
@@ -598,7 +616,8 @@ ms_status sketch_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64_t k2
       n > (1 << 16) || nrhs > (1 << 16))
     return MS_ERR_ARG;
   const bool ok = (a_dtype == MS_F64 && g_dtype == MS_F64) ||
-                  (a_dtype == MS_F32 && (g_dtype == MS_F32 || g_dtype == MS_BF16));
+                  (a_dtype == MS_F32 &&
+                   (g_dtype == MS_F32 || g_dtype == MS_BF16 || g_dtype == MS_F16));
   if (!ok || !valid_mode(opts)) return MS_ERR_ARG;
   const int mode = resolve_mode(opts);
   const int refine = opts ? opts->refine_steps : 0;
@@ -680,15 +699,16 @@ ms_status rand_cholqr_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64
   if (d < 1 || n < 1 || nrhs < 1 || k < 1 || k > kMax31 || k2 < n || k2 > (1 << 24))
     return MS_ERR_ARG;
   const bool ok = (a_dtype == MS_F64 && g_dtype == MS_F64) ||
-                  (a_dtype == MS_F32 && (g_dtype == MS_F32 || g_dtype == MS_BF16));
+                  (a_dtype == MS_F32 &&
+                   (g_dtype == MS_F32 || g_dtype == MS_BF16 || g_dtype == MS_F16));
   if (!ok || !valid_mode(opts)) return MS_ERR_ARG;
   if (opts && opts->refine_steps != 0) return MS_ERR_ARG;
-  if (n > kRcqMaxN || nrhs > kRcqMaxRhs || n + nrhs > kRcqMaxCols) return MS_ERR_UNSUPPORTED;
+  if (rcq_is_wide(n, nrhs) && !rcq_fits_wide(n, nrhs)) return MS_ERR_UNSUPPORTED;
   const int mode = resolve_mode(opts);
   if (mode == MS_CS_SORTED && d > kMax31) return MS_ERR_UNSUPPORTED;
   if (lda < d || ldb < d || ldg < k2 || ldx < n || (R && ldr < n)) return MS_ERR_ARG;
   if (!A || !B || !h || !s || !G || !X || !ws) return MS_ERR_ARG;
-  const RcqLayout L = rcq_layout(d, n, k, k2, a_dtype, g_dtype, mode);
+  const RcqLayout L = rcq_layout(d, n, nrhs, k, k2, a_dtype, g_dtype, mode);
   if (ws_bytes < L.total) return MS_ERR_NOMEM;
   hipStream_t st = (hipStream_t)stream;
   int *status = static_cast<int *>(ws);
@@ -708,14 +728,38 @@ ms_status rand_cholqr_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64
   if (e == hipSuccess)
     e = launch_gemm(p, g_dtype, G, ldg, at<void>(ws, L.y), k, nullptr, k2, z64,
                     at<void>(ws, L.partials), nullptr, st, yterms_of(opts));
+  double *fact = at<double>(ws, L.fact), *rinv = at<double>(ws, L.rinv);
+  if (L.wide) {
+    // 2. R0: the upper part of the QR factors of S A (ld k2)
+    if (e == hipSuccess)
+      e = launch_qr_solve(k2, n, 0, z64, k2, nullptr, k2, X, ldx, nullptr, 0,
+                          at<double>(ws, L.tau), fact, at<void>(ws, L.qr), status, st);
+    // 3. R0^{-1} and Q0 = A R0^{-1}
+    double *q0 = at<double>(ws, L.q0);
+    if (e == hipSuccess)
+      e = launch_rcq_wide_q0(d, (int)n, a_dtype, A, lda, fact, k2, rinv, q0, status, st);
+    // 4. W = [Q0 | B]^T [Q0 | B]
+    const int nc = (int)(n + nrhs);
+    double *part = at<double>(ws, L.part), *W = at<double>(ws, L.w);
+    if (e == hipSuccess)
+      e = a_dtype == MS_F64
+              ? launch_gram_wide<double, double>(d, (int)n, nc, q0, d,
+                                                 static_cast<const double *>(B), ldb, part, W, st)
+              : launch_gram_wide<double, float>(d, (int)n, nc, q0, d,
+                                                static_cast<const float *>(B), ldb, part, W, st);
+    // 5-8. R1 = chol(Q0^T Q0), y = R1^{-T} Q0^T B, x = R0^{-1} R1^{-1} y, R = R1 R0
+    if (e == hipSuccess)
+      e = launch_chol_solve_wide((int)n, (int)nrhs, nc, W, fact, k2, X, ldx, R, ldr,
+                                 at<int>(ws, L.bad), status, st);
+    return from_hip(e);
+  }
   // 2. R0 of the Householder QR of S A (no right-hand side)
   double *r0 = at<double>(ws, L.r0);
   if (e == hipSuccess)
     e = launch_qr_solve(k2, n, 0, z64, k2, nullptr, k2, X, ldx, r0, kRcqMaxN,
-                        at<double>(ws, L.tau), at<double>(ws, L.fact), at<void>(ws, L.qr), status,
-                        st);
+                        at<double>(ws, L.tau), fact, at<void>(ws, L.qr), status, st);
   // 3-4. R0^{-1}; one pass: Q0 = A R0^{-1}, per-workgroup Q0^T [Q0 | B]
-  double *rinv = at<double>(ws, L.rinv), *part = at<double>(ws, L.part);
+  double *part = at<double>(ws, L.part);
   const int grid = rcq_grid();
   if (e == hipSuccess) e = launch_rcq_trinv((int)n, r0, kRcqMaxN, rinv, status, st);
   if (e == hipSuccess)

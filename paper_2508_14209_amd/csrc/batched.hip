@@ -296,6 +296,7 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
                                const ms_problem *probs_dev, ms_dtype a_dtype, ms_dtype g_dtype,
                                const ms_opts *opts, void *ws, size_t ws_bytes, void *stream) {
   if (count < 1 || count > 65535 || !probs_host || !probs_dev || !ws) return MS_ERR_ARG;
+  if (a_dtype == MS_F32 && g_dtype == MS_F16) return MS_ERR_UNSUPPORTED;
   if (!valid_dtypes(a_dtype, g_dtype)) return MS_ERR_ARG;
   if (opts && (opts->cs_mode == MS_CS_SORTED || opts->cs_mode == MS_CS_ATOMIC))
     return MS_ERR_UNSUPPORTED;

@@ -11,6 +11,7 @@
 //   FP64: v_mfma_f64_16x16x4_f64       (K step 4)
 //   FP32: v_mfma_f32_16x16x4_f32       (K step 4)
 //   BF16: v_mfma_f32_16x16x32_bf16     (K step 32, FP32 accumulation)
+//   FP16: v_mfma_f32_16x16x32_f16      (K step 32, FP32 accumulation)
 // Operand layout per lane l (64 lanes): A element (row l%16, k-group l/16),
 // B element (k-group l/16, column l%16).  The four accumulator values r of
 // lane l belong to column l%16 and to row 4*(l/16)+r for the FP32 and BF16
@@ -45,7 +46,14 @@ __device__ __forceinline__ uint32_t bf16x2_rne(float lo, float hi) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, bf16x2_t));
 }
 
-enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2 };
+// Two FP32 values rounded to nearest-even FP16, packed (first in the low half).
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 v8h __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ uint32_t f16x2_rne(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{lo, hi}, f16x2_t));
+}
+
+enum { DT_F64 = 0, DT_F32 = 1, DT_BF16 = 2, DT_F16 = 3 };
 
 template <int DT>
 struct Mf;
@@ -87,6 +95,46 @@ struct Mf<DT_BF16> {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
   }
   __device__ static int out_row(int lk, int r) { return 4 * lk + r; }
+};
+
+template <>
+struct Mf<DT_F16> {
+  using TG = _Float16;  // FP16 data
+  using TY = float;     // scaled per column and rounded to FP16 terms on load
+  using Acc = float;
+  using Frag = v8h;
+  using AccV = v4f;
+  static constexpr int KS = 32;
+  __device__ static int out_row(int lk, int r) { return 4 * lk + r; }
+};
+
+// The 16-bit formats of the LDS-staged tile: conversion of FP32 pairs,
+// the value of a converted half as FP32, and the matrix-core product.
+template <int DT>
+struct Half16;
+template <>
+struct Half16<DT_BF16> {
+  using V8 = v8bf;
+  __device__ static uint32_t pack2(float lo, float hi) { return bf16x2_rne(lo, hi); }
+  __device__ static float lo_f32(uint32_t w) { return __uint_as_float(w << 16); }
+  __device__ static float hi_f32(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+  __device__ static v4f mma(V8 a, V8 b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Half16<DT_F16> {
+  using V8 = v8h;
+  __device__ static uint32_t pack2(float lo, float hi) { return f16x2_rne(lo, hi); }
+  __device__ static float lo_f32(uint32_t w) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu));
+  }
+  __device__ static float hi_f32(uint32_t w) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16));
+  }
+  __device__ static v4f mma(V8 a, V8 b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
 };
 
 // A fragment: G rows [row], k-group starting at kq (KS/4 consecutive k).
@@ -208,35 +256,36 @@ __device__ __forceinline__ void gemm_tile(int M, int N, const typename Mf<DT>::T
     }
 }
 
-// BF16 tile staged through LDS.  G is stored with its rows contiguous, but a
-// matrix-core fragment holds 8 consecutive k of one row, so G's tile (64 rows
-// x 64 k) is loaded with 16-byte loads along the rows and written to LDS
-// transposed (row-major, k contiguous); Y's tile (64 k x 64 columns, FP32,
-// k contiguous) is converted to BF16 and written as is.  Two LDS buffers: the
-// next stage's global loads are in flight while the current stage runs on
-// the matrix cores.  The k steps (32 each) run in the same order as in
-// gemm_tile, so the partial sums are the same.
+// BF16 / FP16 tile staged through LDS.  G is stored with its rows
+// contiguous, but a matrix-core fragment holds 8 consecutive k of one row, so
+// G's tile (64 rows x 64 k) is loaded with 16-byte loads along the rows and
+// written to LDS transposed (row-major, k contiguous); Y's tile (64 k x 64
+// columns, FP32, k contiguous) is converted to the 16-bit format and written
+// as is.  Two LDS buffers: the next stage's global loads are in flight while
+// the current stage runs on the matrix cores.  The k steps (32 each) run in
+// the same order as in gemm_tile, so the partial sums are the same.
 //
-// YT = 1: Y rounded to BF16 (nearest even).  YT = 3: Y as the sum of three
-// BF16 terms, hi = bf16(y), mid = bf16(y - hi), lo = bf16(y - hi - mid);
-// each remainder is exact in FP32 and the last one fits BF16's 8 bits, so
-// hi + mid + lo = y exactly for every normal FP32 y, and G Y is formed from
-// the exact Y (G's values are BF16 data) with three matrix-core products per
-// step and FP32 accumulation: FP32-level accuracy at BF16 instruction rate,
-// with G read once.
+// YT = 1: Y rounded to the 16-bit format (nearest even).  YT = 3: Y as the
+// sum of three terms, hi = h(y), mid = h(y - hi), lo = h(y - hi - mid); each
+// remainder is exact in FP32.  For BF16 (8-bit significand, FP32's exponent
+// range) the last remainder fits BF16, so hi + mid + lo = y exactly for every
+// normal FP32 y, and G Y is formed from the exact Y (G's values are BF16
+// data) with three matrix-core products per step and FP32 accumulation:
+// FP32-level accuracy at BF16 instruction rate, with G read once.
+// FP16 (11-bit significand, largest finite 65504) first scales column c of Y
+// by the power of two cs[2c] = 2^-e_c that brings its largest magnitude into
+// [2^14, 2^15), and multiplies the column's result by cs[2c + 1] = 2^e_c;
+// the three terms then hold y exactly down to 2^-40 of the column's largest
+// magnitude (smaller parts of an entry fall below FP16's subnormals).
 constexpr int kStK = 64, kStPad = 72;  // k per stage; LDS row stride (BF16 elements)
 
-// y -> (hi, mid, lo) BF16 bit patterns, two values at a time
-__device__ __forceinline__ float bf16_lo_as_f32(uint32_t w) { return __uint_as_float(w << 16); }
-__device__ __forceinline__ float bf16_hi_as_f32(uint32_t w) {
-  return __uint_as_float(w & 0xffff0000u);
-}
-
-template <int YT>
-__device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned short *__restrict__ G,
-                                                   int64_t ldg, const float *__restrict__ Y,
-                                                   int64_t ldy, float *__restrict__ P, int64_t kb,
-                                                   int64_t ke, int m_tile, int n_tile) {
+template <int DT, int YT>
+__device__ __forceinline__ void gemm_tile_lds_h(int M, int N, const unsigned short *__restrict__ G,
+                                                int64_t ldg, const float *__restrict__ Y,
+                                                int64_t ldy, const float *__restrict__ cs,
+                                                float *__restrict__ P, int64_t kb, int64_t ke,
+                                                int m_tile, int n_tile) {
+  using H = Half16<DT>;
   __shared__ __align__(16) unsigned short As[2][64 * kStPad];
   __shared__ __align__(16) unsigned short Bs[2][YT][64 * kStPad];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -250,6 +299,8 @@ __device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned 
   const int rb = m0 + 8 * g8;
   const bool gvec = (ldg & 7) == 0 && ((uintptr_t)G & 15) == 0 && rb + 8 <= M;
   const bool yvec = (ldy & 3) == 0 && ((uintptr_t)Y & 15) == 0 && n0 + yc < N;
+  // FP16: the scale of this thread's column of Y
+  const float yscale = (DT == DT_F16 && n0 + yc < N) ? cs[2 * (n0 + yc)] : 1.0f;
   uint32_t gw[8];
   float yv[16];
   auto fetch = [&](int64_t k0) {
@@ -293,13 +344,17 @@ __device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned 
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         float y0 = yv[8 * h + 2 * u], y1 = yv[8 * h + 2 * u + 1];
+        if (DT == DT_F16) {
+          y0 *= yscale;
+          y1 *= yscale;
+        }
 #pragma unroll
         for (int tt = 0; tt < YT; ++tt) {
-          const uint32_t w = bf16x2_rne(y0, y1);
+          const uint32_t w = H::pack2(y0, y1);
           bt[tt][u] = w;
           if (tt + 1 < YT) {
-            y0 -= bf16_lo_as_f32(w);
-            y1 -= bf16_hi_as_f32(w);
+            y0 -= H::lo_f32(w);
+            y1 -= H::hi_f32(w);
           }
         }
       }
@@ -323,23 +378,23 @@ __device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned 
     if (more) fetch(k0 + kStK);
 #pragma unroll
     for (int ks = 0; ks < kStK / 32; ++ks) {
-      v8bf a[2];
+      typename H::V8 a[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
-        a[i] = *reinterpret_cast<const v8bf *>(&As[buf][(m_base + 16 * i + li) * kStPad + ks * 32 + lk * 8]);
+        a[i] = *reinterpret_cast<const typename H::V8 *>(
+            &As[buf][(m_base + 16 * i + li) * kStPad + ks * 32 + lk * 8]);
       // the small terms first (each enters the same FP32 accumulators)
 #pragma unroll
       for (int tt = YT - 1; tt >= 0; --tt) {
-        v8bf b[2];
+        typename H::V8 b[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          b[j] = *reinterpret_cast<const v8bf *>(
+          b[j] = *reinterpret_cast<const typename H::V8 *>(
               &Bs[buf][tt][(n_base + 16 * j + li) * kStPad + ks * 32 + lk * 8]);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < 2; ++j) acc[i][j] = H::mma(a[i], b[j], acc[i][j]);
       }
     }
     if (more) lstore(buf ^ 1);
@@ -351,27 +406,35 @@ __device__ __forceinline__ void gemm_tile_lds_bf16(int M, int N, const unsigned 
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int col = n0 + n_base + 16 * j + li;
+      const float back = (DT == DT_F16 && col < N) ? cs[2 * col + 1] : 1.0f;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + m_base + 16 * i + 4 * lk + r;
-        if (row < M && col < N) P[row + (int64_t)col * M] = acc[i][j][r];
+        if (row < M && col < N) P[row + (int64_t)col * M] = DT == DT_F16 ? acc[i][j][r] * back
+                                                                         : acc[i][j][r];
       }
     }
 }
 
-// The tile of either kind: LDS-staged for BF16, direct fragment loads else.
-// YT: BF16 terms of Y (1 or 3; the other dtypes ignore it).
+// The tile of either kind: LDS-staged for BF16 and FP16, direct fragment
+// loads else.  YT: 16-bit terms of Y (1 or 3; the other dtypes ignore it).
+// cs: FP16's column scales (unused for the other dtypes).
 template <int DT, int YT = 1>
 __device__ __forceinline__ void gemm_tile_any(int M, int N, const typename Mf<DT>::TG *__restrict__ G,
                                               int64_t ldg, const typename Mf<DT>::TY *__restrict__ Y,
-                                              int64_t ldy, typename Mf<DT>::Acc *__restrict__ P,
-                                              int64_t kb, int64_t ke, int m_tile, int n_tile) {
-  if constexpr (DT == DT_BF16)
-    gemm_tile_lds_bf16<YT>(M, N, G, ldg, Y, ldy, P, kb, ke, m_tile, n_tile);
+                                              int64_t ldy, const float *__restrict__ cs,
+                                              typename Mf<DT>::Acc *__restrict__ P, int64_t kb,
+                                              int64_t ke, int m_tile, int n_tile) {
+  if constexpr (DT == DT_BF16 || DT == DT_F16)
+    gemm_tile_lds_h<DT, YT>(M, N, reinterpret_cast<const unsigned short *>(G), ldg, Y, ldy, cs, P,
+                            kb, ke, m_tile, n_tile);
   else
     gemm_tile<DT>(M, N, G, ldg, Y, ldy, P, kb, ke, m_tile, n_tile);
 }
 
+// Workgroup g runs on die g % xcds.  All output tiles of one K chunk are
+// given to workgroups of the same die, so that chunk of G and Y is fetched
+// from HBM into one L2 and the other tiles re-read it from there.
 template <int DT, int YT = 1>
 __global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
                                                      const typename Mf<DT>::TG *__restrict__ G,
@@ -379,11 +442,55 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
                                                      const typename Mf<DT>::TY *__restrict__ Y,
                                                      int64_t ldy,
                                                      typename Mf<DT>::Acc *__restrict__ part,
-                                                     int64_t kchunk) {
-  const int64_t kb = (int64_t)blockIdx.z * kchunk;
+                                                     int64_t kchunk, int tiles_m, int tiles,
+                                                     int nsplit, int xcds,
+                                                     const float *__restrict__ cs) {
+  const int g = blockIdx.x;
+  const int x = g % xcds, j = g / xcds;
+  const int split = x + xcds * (j / tiles);
+  if (split >= nsplit) return;
+  const int tile = j % tiles;
+  const int64_t kb = (int64_t)split * kchunk;
   const int64_t ke = min(K, kb + kchunk);
-  gemm_tile_any<DT, YT>(M, N, G, ldg, Y, ldy, part + (int64_t)blockIdx.z * M * N, kb, ke,
-                        blockIdx.x, blockIdx.y);
+  gemm_tile_any<DT, YT>(M, N, G, ldg, Y, ldy, cs, part + (int64_t)split * M * N, kb, ke,
+                        tile % tiles_m, tile / tiles_m);
+}
+
+// FP16 column scales: cs[2c] = 2^-e_c and cs[2c + 1] = 2^e_c with
+// e_c = floor(log2 max_k |Y[k, c]|) - 14, so the scaled column's largest
+// magnitude lies in [2^14, 2^15) (FP16's largest finite value is 65504).
+// e_c is held in [-112, 112] (both factors normal FP32 numbers); a zero
+// column, or one holding a NaN or an infinity, takes e_c = 0.  One workgroup
+// per column.
+__global__ __launch_bounds__(256) void k_f16_col_scale(int64_t K, const float *__restrict__ Y,
+                                                       int64_t ldy, float *__restrict__ cs) {
+  __shared__ float wmax[4];
+  const int c = blockIdx.x;
+  const float *y = Y + (int64_t)c * ldy;
+  float m = 0.0f;
+  bool bad = false;
+  for (int64_t i = threadIdx.x; i < K; i += blockDim.x) {
+    const float v = fabsf(gload(y + i));
+    bad |= !(v <= 3.4028235e38f);   // NaN or infinity
+    m = fmaxf(m, v);
+  }
+  bad = __any(bad);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = bad ? -1.0f : m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float mm = 0.0f;
+    bool anybad = false;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      anybad |= wmax[w] < 0.0f;
+      mm = fmaxf(mm, wmax[w]);
+    }
+    int e = 0;
+    if (!anybad && mm > 0.0f) e = min(112, max(-112, ilogbf(mm) - 14));
+    cs[2 * c] = ldexpf(1.0f, -e);
+    cs[2 * c + 1] = ldexpf(1.0f, e);
+  }
 }
 
 // Z[p, c] = sum over splits (in split order) of the partials; written to Z
@@ -437,8 +544,8 @@ __global__ __launch_bounds__(256) void k_batch_gemm(int count, const ms_problem 
     const int64_t kb = (int64_t)split * e.kchunk, ke = min(Q.k, kb + e.kchunk);
     const auto *Y = reinterpret_cast<const typename F::TY *>(yarea + e.y_off);
     auto *Pz = reinterpret_cast<typename F::Acc *>(parea + e.part_off) + (int64_t)split * M * N;
-    gemm_tile_any<DT, YT>(M, N, static_cast<const typename F::TG *>(Q.G), Q.ldg, Y, Q.k, Pz, kb,
-                          ke, tm, tn);
+    gemm_tile_any<DT, YT>(M, N, static_cast<const typename F::TG *>(Q.G), Q.ldg, Y, Q.k, nullptr,
+                          Pz, kb, ke, tm, tn);
   }
 }
 
@@ -514,7 +621,7 @@ GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K, ms_dtype g_dtype) {
   p.K = K;
   p.tiles_m = (int)((M + 63) / 64);
   p.tiles_n = (int)((N + 63) / 64);
-  const int64_t ks = g_dtype == MS_BF16 ? 32 : 4;
+  const int64_t ks = (g_dtype == MS_BF16 || g_dtype == MS_F16) ? 32 : 4;
   const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
   // aim for ~1024 workgroups but keep at least 128 K values per workgroup
   int64_t ns = std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, (K + 127) / 128));
@@ -527,6 +634,8 @@ GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K, ms_dtype g_dtype) {
   if (p.nsplit < 1) p.nsplit = 1;
   const size_t acc = g_dtype == MS_F64 ? 8 : 4;
   p.partial_bytes = (size_t)p.nsplit * (size_t)M * (size_t)N * acc;
+  // FP16: the column scales follow the partials
+  if (g_dtype == MS_F16) p.partial_bytes = align_up(p.partial_bytes) + (size_t)N * 2 * sizeof(float);
   p.ybf16_bytes = 0;
   return p;
 }
@@ -539,13 +648,15 @@ hipError_t launch_gemm(const GemmPlan &p, ms_dtype g_dtype, const void *G, int64
   const int64_t MN = (int64_t)p.M * p.N;
   const unsigned rblocks = (unsigned)std::min<int64_t>((MN + 255) / 256, 65535);
   if (p.K <= 0) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)p.tiles_m, (unsigned)p.tiles_n, (unsigned)p.nsplit);
+  const int xcds = dev_info().xcds;
+  const int tiles = p.tiles_m * p.tiles_n;
+  const dim3 grid((unsigned)((int64_t)xcds * tiles * ((p.nsplit + xcds - 1) / xcds)));
   const bool reduce = Z != nullptr || z64 != nullptr;  // otherwise the caller consumes the partials
   switch (g_dtype) {
     case MS_F64:
       hipLaunchKernelGGL(k_gemm_splitk<DT_F64>, grid, dim3(256), 0, st, p.M, p.N, p.K,
                          (const double *)G, ldg, (const double *)Y, ldy, (double *)partials,
-                         p.kchunk);
+                         p.kchunk, p.tiles_m, tiles, p.nsplit, xcds, nullptr);
       if (reduce)
         hipLaunchKernelGGL((k_reduce_splits<double, double>), dim3(rblocks), dim3(256), 0, st, p.M,
                            p.N, p.nsplit, (const double *)partials, (double *)Z, ldz, z64);
@@ -553,7 +664,7 @@ hipError_t launch_gemm(const GemmPlan &p, ms_dtype g_dtype, const void *G, int64
     case MS_F32:
       hipLaunchKernelGGL(k_gemm_splitk<DT_F32>, grid, dim3(256), 0, st, p.M, p.N, p.K,
                          (const float *)G, ldg, (const float *)Y, ldy, (float *)partials,
-                         p.kchunk);
+                         p.kchunk, p.tiles_m, tiles, p.nsplit, xcds, nullptr);
       if (reduce)
         hipLaunchKernelGGL((k_reduce_splits<float, float>), dim3(rblocks), dim3(256), 0, st, p.M,
                            p.N, p.nsplit, (const float *)partials, (float *)Z, ldz, z64);
@@ -562,15 +673,33 @@ hipError_t launch_gemm(const GemmPlan &p, ms_dtype g_dtype, const void *G, int64
       if (yterms == 3)
         hipLaunchKernelGGL((k_gemm_splitk<DT_BF16, 3>), grid, dim3(256), 0, st, p.M, p.N, p.K,
                            (const unsigned short *)G, ldg, (const float *)Y, ldy,
-                           (float *)partials, p.kchunk);
+                           (float *)partials, p.kchunk, p.tiles_m, tiles, p.nsplit, xcds, nullptr);
       else
         hipLaunchKernelGGL((k_gemm_splitk<DT_BF16, 1>), grid, dim3(256), 0, st, p.M, p.N, p.K,
                            (const unsigned short *)G, ldg, (const float *)Y, ldy,
-                           (float *)partials, p.kchunk);
+                           (float *)partials, p.kchunk, p.tiles_m, tiles, p.nsplit, xcds, nullptr);
       if (reduce)
         hipLaunchKernelGGL((k_reduce_splits<float, float>), dim3(rblocks), dim3(256), 0, st, p.M,
                            p.N, p.nsplit, (const float *)partials, (float *)Z, ldz, z64);
       break;
+    case MS_F16: {
+      float *cs = reinterpret_cast<float *>(static_cast<unsigned char *>(partials) +
+                                            align_up((size_t)p.nsplit * MN * sizeof(float)));
+      hipLaunchKernelGGL(k_f16_col_scale, dim3((unsigned)p.N), dim3(256), 0, st, p.K,
+                         (const float *)Y, ldy, cs);
+      if (yterms == 3)
+        hipLaunchKernelGGL((k_gemm_splitk<DT_F16, 3>), grid, dim3(256), 0, st, p.M, p.N, p.K,
+                           (const _Float16 *)G, ldg, (const float *)Y, ldy, (float *)partials,
+                           p.kchunk, p.tiles_m, tiles, p.nsplit, xcds, (const float *)cs);
+      else
+        hipLaunchKernelGGL((k_gemm_splitk<DT_F16, 1>), grid, dim3(256), 0, st, p.M, p.N, p.K,
+                           (const _Float16 *)G, ldg, (const float *)Y, ldy, (float *)partials,
+                           p.kchunk, p.tiles_m, tiles, p.nsplit, xcds, (const float *)cs);
+      if (reduce)
+        hipLaunchKernelGGL((k_reduce_splits<float, float>), dim3(rblocks), dim3(256), 0, st, p.M,
+                           p.N, p.nsplit, (const float *)partials, (float *)Z, ldz, z64);
+      break;
+    }
     default:
       return hipErrorInvalidValue;
   }
@@ -592,6 +721,8 @@ template <>
 __device__ __forceinline__ double g_as_f64<unsigned short>(unsigned short v) {
   return (double)__uint_as_float((uint32_t)v << 16);
 }
+template <>
+__device__ __forceinline__ double g_as_f64<_Float16>(_Float16 v) { return (double)v; }
 
 template <typename TG>
 __device__ __forceinline__ void g_rows4(const TG *g, bool vec, int nvalid, double v[4]) {
@@ -793,6 +924,10 @@ hipError_t launch_gemv64(int64_t M, int64_t N, int64_t K, ms_dtype g_dtype, cons
     case MS_BF16:
       hipLaunchKernelGGL(k_gemv64_splitk<unsigned short>, grid, dim3(256), 0, st, (int)M, (int)N,
                          K, (const unsigned short *)G, ldg, Y, ldy, part, kc);
+      break;
+    case MS_F16:
+      hipLaunchKernelGGL(k_gemv64_splitk<_Float16>, grid, dim3(256), 0, st, (int)M, (int)N, K,
+                         (const _Float16 *)G, ldg, Y, ldy, part, kc);
       break;
     default:
       return hipErrorInvalidValue;

@@ -486,6 +486,12 @@ size_t gram_wide_w_bytes(int nc);
 template <typename TX, typename TB>
 hipError_t launch_gram_wide(int64_t d, int nx, int nc, const TX *X, int64_t ldx, const TB *B,
                             int64_t ldb, double *part, double *W, hipStream_t st);
+// rand_cholQR for wide problems (rcq_wide.hip): Rinv (n x n, ld n) = R0^{-1}
+// from the upper part of the QR factors (ld ldf), then Q0 = A Rinv (d x n
+// FP64, ld d).  A zero or non-finite diagonal of R0 records MS_ERR_SINGULAR.
+hipError_t launch_rcq_wide_q0(int64_t d, int n, ms_dtype a_dtype, const void *A, int64_t lda,
+                              const double *fact, int64_t ldf, double *Rinv, double *Q0,
+                              int *status, hipStream_t st);
 // bad: one int of workspace (breakdown flag between the launches)
 hipError_t launch_chol_solve_wide(int n, int nrhs, int nc, double *W, const double *fact,
                                   int64_t ldf, double *X, int64_t ldx, double *R, int64_t ldr,

@@ -16,7 +16,10 @@ event.
 The solver is the library's; this module only schedules.  Inputs follow the
 serving workload: A = Z diag(logspace(0, -log10 kappa, n)) Q (FP32; Q
 orthogonal), B = A x* + 1e-6 N(0,1), h uniform, s Rademacher,
-G ~ N(0, 1/k2), k = 2 n^2, k2 = 2 n.
+G ~ N(0, 1/k2), k = 2 n^2, k2 = 2 n.  Q is taken from a pool of Haar
+orthogonal matrices per n (the QR factor of an n x n Gaussian, drawn once on
+the host from a fixed seed and copied to the device before serving starts):
+a device QR per request would synchronise the device and serialise the loop.
 """
 from __future__ import annotations
 
@@ -25,9 +28,27 @@ import time
 from collections import deque
 from dataclasses import dataclass, field
 
+import numpy as np
 import torch
 
 import paper_2508_14209_amd as ms
+
+Q_POOL = 8                 # orthogonal factors per n
+_q_pool: dict = {}         # (n, device) -> (Q_POOL, n, n) FP64 device tensor
+
+
+def orthogonal_pool(n: int, device) -> torch.Tensor:
+    """Q_POOL Haar orthogonal n x n matrices (QR of Gaussians, LAPACK on the
+    host, fixed seed) resident on ``device``; built on first use."""
+    key = (int(n), str(torch.device(device)))
+    if key not in _q_pool:
+        rng = np.random.default_rng(np.random.SeedSequence([0x51, int(n)]))
+        qs = np.empty((Q_POOL, n, n))
+        for i in range(Q_POOL):
+            q, r = np.linalg.qr(rng.standard_normal((n, n)))
+            qs[i] = q * np.sign(np.diag(r))[None, :]    # Haar: fix the column signs
+        _q_pool[key] = torch.from_numpy(qs).to(device)
+    return _q_pool[key]
 
 
 @dataclass
@@ -81,7 +102,7 @@ def generate(req: Request, device, g_dtype: str = "f32", a_dtype: str = "f32") -
     scales = torch.logspace(0.0, -math.log10(req.kappa), n, device=device, dtype=torch.float64)
     # A = Z diag(scales) Q: Z N(0,1), Q orthogonal (QR of an n x n Gaussian),
     # the n x n factor formed in FP64, the product in FP32; condition ~ kappa
-    q, _ = torch.linalg.qr(torch.randn((n, n), generator=g, device=device, dtype=torch.float64))
+    q = orthogonal_pool(n, device)[int(req.seed) % Q_POOL]
     M = (scales[:, None] * q).to(torch.float32)
     Z = torch.randn((d, n), generator=g, device=device, dtype=torch.float32)
     A = ms.empty_colmajor(d, n, torch.float32, device)
@@ -351,6 +372,10 @@ class Server:
     def run(self, requests, keep_tensors: bool = False):
         """Open loop: request r arrives at r.arrival seconds after the start."""
         pending = deque(sorted(requests, key=lambda r: r.arrival))
+        # the orthogonal factors of the input generator, before the clock starts
+        for n in sorted({r.n for r in requests}):
+            orthogonal_pool(n, self.device)
+        torch.cuda.synchronize(self.device)
         self.t0 = time.perf_counter()
         while pending or not self.idle():
             t = self.now()

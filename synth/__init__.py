@@ -101,7 +101,8 @@ def gaussian_sketch(k2: int, k: int, seed: int, dtype: str = "f64") -> np.ndarra
     """G (k2 x k), entries N(0, 1/k2) (variance 1/k2, Sec. 1), column-major.
 
     dtype 'f64' -> float64; 'f32' -> float32 rounding of the same draw;
-    'bf16' -> BF16 rounding (via FP32, ties to even) held in float32.
+    'bf16' -> BF16 rounding (via FP32, ties to even) held in float32;
+    'f16' -> FP16 rounding (via FP32, NumPy's conversion) held in float32.
     """
     g = normal_matrix(k2, k, seed, stream="G", dtype=np.float64,
                       scale=1.0 / math.sqrt(k2))
@@ -111,6 +112,8 @@ def gaussian_sketch(k2: int, k: int, seed: int, dtype: str = "f64") -> np.ndarra
         return np.asfortranarray(g.astype(np.float32))
     if dtype == "bf16":
         return np.asfortranarray(to_bf16_values(g.astype(np.float32)))
+    if dtype == "f16":
+        return np.asfortranarray(g.astype(np.float32).astype(np.float16).astype(np.float32))
     raise ValueError(dtype)
 
 

@@ -26,6 +26,24 @@ def bf16_dev(values_f32: np.ndarray, device="cuda") -> torch.Tensor:
     return out
 
 
+def f16_dev(values_f32: np.ndarray, device="cuda") -> torch.Tensor:
+    """A column-major torch.float16 device tensor holding FP16-representable
+    float32 values exactly."""
+    t = to_dev(np.asarray(values_f32, dtype=np.float32), device=device)
+    out = torch.empty((t.shape[1], t.shape[0]), dtype=torch.float16, device=device).t()
+    out.copy_(t)  # exact: the values are representable
+    return out
+
+
+def g_dev(G: np.ndarray, gd: str, device="cuda") -> torch.Tensor:
+    """G on the device in the stored format named by gd (f64, f32, bf16, f16)."""
+    if gd == "bf16":
+        return bf16_dev(G, device)
+    if gd == "f16":
+        return f16_dev(G, device)
+    return to_dev(G, device=device)
+
+
 def to_host(t: torch.Tensor) -> np.ndarray:
     if t.dim() == 1:
         return t.detach().cpu().numpy()

@@ -15,7 +15,7 @@ import pytest
 import torch
 
 import synth
-from gpu_util import bf16_dev, rel, to_dev, to_host
+from gpu_util import bf16_dev, g_dev, rel, to_dev, to_host
 
 pytestmark = pytest.mark.gpu
 
@@ -26,11 +26,12 @@ def ms():
     return ms
 
 
-def _problem(d, n, nrhs, kappa, seed, dtype=np.float64, noise=1e-2):
+def _problem(d, n, nrhs, kappa, seed, dtype=np.float64, noise=1e-2, k=None):
     rng = np.random.default_rng(seed)
     A = rng.standard_normal((d, n)) * np.logspace(0, -np.log10(kappa), n)
     B = A @ rng.standard_normal((n, nrhs)) + noise * rng.standard_normal((d, nrhs))
-    k, k2 = 2 * n * n, 2 * n
+    k = 2 * n * n if k is None else k
+    k2 = 2 * n
     h = synth.bucket_map(d, k, seed=seed)
     s = synth.signs(d, seed=seed)
     G = synth.gaussian_sketch(k2, k, seed=seed, dtype="f64")
@@ -56,12 +57,14 @@ def test_rand_cholqr_fp64_parity(ms, orc, d, n, nrhs, kappa):
     assert rel(Rg.T @ Rg, Rr.T @ Rr) <= 1e-12
 
 
-@pytest.mark.parametrize("gd", ["f32", "bf16"])
+@pytest.mark.parametrize("gd", ["f32", "bf16", "f16"])
 def test_rand_cholqr_fp32_parity(ms, orc, gd):
     d, n, nrhs = 70001, 16, 2
     A, B, h, s, G, k = _problem(d, n, nrhs, 1e2, seed=7, dtype=np.float32)
     Gq = np.asarray(G, dtype=np.float32)
-    Gdev = bf16_dev(Gq) if gd == "bf16" else to_dev(Gq)
+    if gd == "f16":
+        Gq = Gq.astype(np.float16).astype(np.float32)
+    Gdev = g_dev(Gq, gd)
     X, _, ws = ms.rand_cholqr_lstsq(to_dev(A), to_dev(B), to_dev(h), to_dev(s), Gdev, k)
     ms.check_status(ws)
     Gvals = to_host(Gdev.float()).astype(np.float64)
@@ -119,7 +122,56 @@ def test_rand_cholqr_errors(ms):
     with pytest.raises(ms.MsketchError) as e:
         ms.check_status(ws)
     assert e.value.code == ms.MS_ERR_RANGE
-    A65, B65, h65, s65, G65, k65 = _problem(2000, 65, 1, 1.0, seed=6)
+    for n_, nrhs_ in ((257, 1), (8, 17), (260, 16)):
+        Aw, Bw, hw, sw, Gw, kw = _problem(2000, n_, nrhs_, 1.0, seed=6, k=4096)
+        with pytest.raises(ms.MsketchError) as e:
+            ms.rand_cholqr_lstsq(to_dev(Aw), to_dev(Bw), to_dev(hw), to_dev(sw), to_dev(Gw), kw)
+        assert e.value.code == ms.MS_ERR_UNSUPPORTED
+
+
+# wide problems (64 < n <= 256 or n + nrhs > 80): Q0 = A R0^{-1} on matrix
+# cores, stored, then the wide Gram pass and blocked Cholesky.  Same 1e-12
+# bar: with kappa(Q0) ~ 1 the solve's error is about kappa(A) u n, below
+# 1e-12 for kappa <= 1e2 and n <= 256.  k = 8192 (any k >= k2 embeds the
+# column space; the oracle's dense Gaussian stage stays small).
+WIDE = [(20000, 65, 1, 1e2), (30001, 100, 3, 10.0), (40000, 128, 2, 1e2), (9000, 70, 16, 1.0),
+        (30000, 256, 16, 10.0)]
+
+
+@pytest.mark.parametrize("d,n,nrhs,kappa", WIDE)
+def test_rand_cholqr_wide_fp64_parity(ms, orc, d, n, nrhs, kappa):
+    print("rand_cholqr wide f64 d=%d n=%d nrhs=%d kappa=%g" % (d, n, nrhs, kappa), flush=True)
+    A, B, h, s, G, k = _problem(d, n, nrhs, kappa, seed=d + n, k=8192)
+    R = ms.empty_colmajor(n, n, torch.float64, "cuda")
+    X, _, ws = ms.rand_cholqr_lstsq(to_dev(A), to_dev(B), to_dev(h), to_dev(s), to_dev(G), k, R=R)
+    ms.check_status(ws)
+    Xr, Rr, _ = orc.rand_cholqr_lstsq(A, B, h, s, G, k)
+    err = rel(to_host(X), Xr)
+    print("  rel err %.3e" % err, flush=True)
+    assert err <= 1e-12
+    Rg = to_host(R)
+    assert np.all(np.tril(Rg, -1) == 0.0)
+    assert rel(Rg.T @ Rg, Rr.T @ Rr) <= 1e-12
+
+
+@pytest.mark.parametrize("gd", ["f32", "bf16"])
+def test_rand_cholqr_wide_fp32_parity(ms, orc, gd):
+    d, n, nrhs = 60001, 128, 4
+    A, B, h, s, G, k = _problem(d, n, nrhs, 1e2, seed=9, dtype=np.float32, k=8192)
+    Gq = np.asarray(G, dtype=np.float32)
+    Gdev = bf16_dev(Gq) if gd == "bf16" else to_dev(Gq)
+    X, _, ws = ms.rand_cholqr_lstsq(to_dev(A), to_dev(B), to_dev(h), to_dev(s), Gdev, k)
+    ms.check_status(ws)
+    Gvals = to_host(Gdev.float()).astype(np.float64)
+    Xr, _, _ = orc.rand_cholqr_lstsq(A, B, h, s, Gvals, k, y_bf16=(gd == "bf16"))
+    assert rel(to_host(X), Xr) <= 1e-12
+
+
+def test_rand_cholqr_wide_singular(ms):
+    A, B, h, s, G, k = _problem(6000, 96, 2, 1.0, seed=12, k=4096)
+    A[:, 70] = 0.0   # rank deficient: R0 (or the Cholesky factor) breaks down
+    X, _, ws = ms.rand_cholqr_lstsq(to_dev(A), to_dev(B), to_dev(h), to_dev(s), to_dev(G), k)
     with pytest.raises(ms.MsketchError) as e:
-        ms.rand_cholqr_lstsq(to_dev(A65), to_dev(B65), to_dev(h65), to_dev(s65), to_dev(G65), k65)
-    assert e.value.code == ms.MS_ERR_UNSUPPORTED
+        ms.check_status(ws)
+    assert e.value.code == ms.MS_ERR_SINGULAR
+    assert np.all(np.isnan(to_host(X)))
