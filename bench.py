@@ -69,7 +69,7 @@ def parse():
                              "copy", "gaussian_f64", "gaussian_bf16", "batched_mixed",
                              "solve_fp32", "solve_mixed", "rand_cholqr",
                              "normal_equations", "countsketch_hashed", "srht",
-                             "paper_comparison", "countsketch_sorted"],
+                             "paper_comparison", "countsketch_sorted", "batched_fp64"],
                     help="profiling runs: launch only the LDS CountSketch of [A | b] (--steps "
                          "times), only a plain device copy of 1 GiB (calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters), or only the Gaussian stage of the "
@@ -241,8 +241,9 @@ def mixed_vs_fp64_leg(ms, torch, np, count, seed, refine, dev, reps=3):
     terms) with 0, 1 and `refine` steps; solves/s of each and the residual
     ratio ||b - A x|| / ||b - A x_opt|| against the FP64 QR optimum x_opt
     (library QR in FP64 on the device, measurement only).  Headline: batched
-    mixed over batched FP64 at the fewest refinement steps whose largest
-    residual ratio is within 2."""
+    mixed over batched FP64 at the fewest refinement steps at which every
+    problem's residual ratio is within max(2, its FP64 sketch-and-solve
+    ratio) (1 + 1e-3)."""
     p64, pbf = compare_problems(ms, torch, count, seed, dev)
     torch.cuda.synchronize()
 
@@ -279,32 +280,51 @@ def mixed_vs_fp64_leg(ms, torch, np, count, seed, refine, dev, reps=3):
         assert rm.status()[0] == ms.MS_OK
         X_m[rs] = [p["X"].clone() for p in pbf]
         del rm
+    # early stop: up to 3 steps, a problem stops once its correction is at
+    # most 2^-30 of its X
+    rm = ms.BatchRunner(pbf, refine_steps=3, refine_tol_log2=30)
+    res["batched_mixed_refine3_stop30_solves_per_s"] = timed(lambda: rm.launch())
+    assert rm.status()[0] == ms.MS_OK
+    X_stop = [p["X"].clone() for p in pbf]
+    del rm
     res["batched_mixed_norefine_solves_per_s"] = res["batched_mixed_refine0_solves_per_s"]
     res["batched_mixed_solves_per_s"] = res["batched_mixed_refine%d_solves_per_s" % refine]
 
-    def rho(Xs):
+    def rhos(Xs):
         vals = []
         for p, X, xo in zip(p64, Xs, x_opt):
             num = torch.linalg.norm(p["B"] - p["A"] @ X)
             den = torch.linalg.norm(p["B"] - p["A"] @ xo)
             vals.append(float(num / den))
-        return {"max": max(vals), "median": float(np.median(vals))}
+        return np.array(vals)
+
+    def summ(v):
+        return {"max": float(v.max()), "median": float(np.median(v)),
+                "fraction_le_2": float(np.mean(v <= 2.0))}
 
     x_opt = []
     for p in p64:
         Q, R = torch.linalg.qr(p["A"], mode="reduced")
         x_opt.append(torch.linalg.solve_triangular(R, Q.t() @ p["B"], upper=True))
         del Q, R
+    rho64 = rhos(X_b64)
+    rho_m = {rs: rhos(X) for rs, X in X_m.items()}
     res["rho_vs_fp64_qr_optimum"] = dict(
-        {"plain_fp64": rho(X_plain), "batched_fp64": rho(X_b64)},
-        **{"batched_mixed_refine%d" % rs: rho(X) for rs, X in X_m.items()})
+        {"plain_fp64": summ(rhos(X_plain)), "batched_fp64": summ(rho64),
+         "batched_mixed_refine3_stop30": summ(rhos(X_stop))},
+        **{"batched_mixed_refine%d" % rs: summ(v) for rs, v in rho_m.items()})
     # the headline ratio: batched mixed precision against batched plain FP64
-    # (the same batching, so the ratio isolates the precision), for the
-    # fewest refinement steps whose largest residual ratio is within 2
-    ok = [rs for rs in sorted(X_m) if res["rho_vs_fp64_qr_optimum"]["batched_mixed_refine%d" % rs]
-          ["max"] <= 2.0]
+    # (the same batching, so the ratio isolates the precision), for the fewest
+    # refinement steps at which every problem's residual ratio is within 2,
+    # or within the FP64 sketch-and-solve's own ratio where that exceeds 2
+    # (the sketch's distortion, which no precision removes), to 1e-3
+    allow = np.maximum(2.0, rho64) * (1.0 + 1e-3)
+    ok = [rs for rs in sorted(rho_m) if np.all(rho_m[rs] <= allow)]
+    ok2 = [rs for rs in sorted(rho_m) if np.all(rho_m[rs] <= 2.0)]
     best = ok[0] if ok else refine
-    res["mixed_refine_steps_for_rho_le_2"] = best if ok else None
+    res["mixed_refine_steps_for_rho_le_max_2_fp64"] = best if ok else None
+    res["mixed_refine_steps_for_rho_le_2"] = ok2[0] if ok2 else None
+    res["fp64_problems_with_rho_above_2"] = int(np.sum(rho64 > 2.0))
     res["ratio_batched_mixed_over_batched_fp64"] = (
         res["batched_mixed_refine%d_solves_per_s" % best] / res["batched_fp64_solves_per_s"])
     res["speedup_batched_mixed_over_plain_fp64"] = (
@@ -599,16 +619,51 @@ def c1_leg(ms, torch, seed, dev, reps=64):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps * 1e-3
 
+    def graphed(pick):
+        # the same calls captured in one HIP graph and replayed: the kernels'
+        # own time, without the host's per-call submission
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for i in range(reps):
+                ms.countsketch_accumulate(pick(i), code, k, Y, mode="lds", ws=cws, stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for i in range(reps):
+                ms.countsketch_accumulate(pick(i), code, k, Y, mode="lds", ws=cws,
+                                          stream=torch.cuda.current_stream())
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = event_pair(torch)
+        e0.record()
+        for _ in range(4):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        del g
+        return e0.elapsed_time(e1) / (4 * reps) * 1e-3
+
     t_warm = timed(lambda i: copies[0])
     t_cold = timed(lambda i: copies[i % 64])
+    g_warm = graphed(lambda i: copies[0])
+    g_cold = graphed(lambda i: copies[i % 64])
     ms.check_status(cws)
     out = {"workload": "countsketch_65536x32_f64_k2048", "bytes_per_call": nbytes,
            "warm": {"avg_us": t_warm * 1e6, "GBps": nbytes / t_warm / 1e9,
                     "pct_hbm_peak": 100.0 * nbytes / t_warm / 1e9 / HBM_PEAK_GBPS},
            "cold_rotating_1GiB": {"avg_us": t_cold * 1e6, "GBps": nbytes / t_cold / 1e9,
                                   "pct_hbm_peak": 100.0 * nbytes / t_cold / 1e9 / HBM_PEAK_GBPS},
-           "note": "one call moves 17.4 MB: the launch and the final flush are a large share "
-                   "of a ~3 us call"}
+           "graph_replay": {
+               "warm": {"avg_us": g_warm * 1e6, "GBps": nbytes / g_warm / 1e9,
+                        "pct_hbm_peak": 100.0 * nbytes / g_warm / 1e9 / HBM_PEAK_GBPS},
+               "cold_rotating_1GiB": {"avg_us": g_cold * 1e6, "GBps": nbytes / g_cold / 1e9,
+                                      "pct_hbm_peak": 100.0 * nbytes / g_cold / 1e9 /
+                                      HBM_PEAK_GBPS}},
+           "note": "one call moves 17.6 MB; called from Python each call waits for its host "
+                   "submission, so the graph replay (64 calls captured once) gives the "
+                   "kernels' own rate"}
     del copies, Y, cws
     return out
 
@@ -763,9 +818,17 @@ def main():
                                 only="fp32" if args.only == "solve_fp32" else "mixed")
         print(json.dumps(res))
         return
-    if args.only == "batched_mixed":
-        # the batched mixed-precision solve of the comparison batch, alone
-        _, pbf = compare_problems(ms, torch, args.compare_problems, args.seed + 1, dev)
+    if args.only in ("batched_mixed", "batched_fp64"):
+        # the batched mixed-precision (or plain FP64) solve of the comparison batch, alone
+        p64, pbf = compare_problems(ms, torch, args.compare_problems, args.seed + 1, dev)
+        if args.only == "batched_fp64":
+            r = ms.BatchRunner(p64)
+            for _ in range(args.steps):
+                r.launch()
+            torch.cuda.synchronize()
+            print(json.dumps({"only": args.only, "problems": len(p64),
+                              "status": r.status()[0], "launches": args.steps}))
+            return
         r = ms.BatchRunner(pbf, refine_steps=args.refine)
         for _ in range(args.steps):
             r.launch()

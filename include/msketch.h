@@ -104,7 +104,13 @@ typedef struct {
                                 Y with FP32 accumulation (three matrix-core
                                 products per step, G read once); 0 = 3.
                                 Other values: MS_ERR_ARG. */
-  int32_t reserved1;
+  int32_t refine_tol_log2;   /* sketch_lstsq_batched: 0 = every problem takes
+                                all refine_steps; x in 1..60 = a problem
+                                stops refining once a step's correction dx
+                                has ||dx||_F <= 2^-x ||X||_F (X after the
+                                step); the later steps skip it.  Other
+                                values: MS_ERR_ARG.  sketch_lstsq runs all
+                                steps. */
 } ms_opts;
 
 /* op codes of ms_workspace_size() */
@@ -483,8 +489,14 @@ size_t ms_batch_workspace_size(int count, const ms_problem *probs,
  *              except MS_F16 (MS_ERR_UNSUPPORTED).
  * Limits per problem: k2 <= MS_BATCH_MAX_K2, n + nrhs <= MS_BATCH_MAX_COLS,
  * k2 >= n >= 1, nrhs >= 1, 1 <= d < 2^31, 1 <= k < 2^31.  The CountSketch is the
- * LDS variant (opts->cs_mode MS_CS_SORTED or MS_CS_ATOMIC ->
- * MS_ERR_UNSUPPORTED).  opts->refine_steps (0 .. 64) refinement steps
+ * LDS variant (MS_CS_AUTO / MS_CS_LDS; MS_CS_ATOMIC -> MS_ERR_UNSUPPORTED) or,
+ * with opts->cs_mode MS_CS_SORTED, the deterministic one: every bucket sum
+ * folded in ascending row order in A's precision (the sequential reading of
+ * Alg. 2, as sketch_lstsq's MS_CS_SORTED), so that -- with the other options
+ * fixed -- each problem's X is bit-identical whatever else is in the batch
+ * (every other stage of a problem depends on that problem alone); requires
+ * k < 2^19 (else the problem is invalid: MS_ERR_ARG).
+ * opts->refine_steps (0 .. 64) refinement steps
  * x <- x + R^{-1} Q^T G C (b - A x) with the FP64 residual, as in
  * sketch_lstsq; with refinement every problem needs nrhs <= 8 (else
  * MS_ERR_UNSUPPORTED).  Device errors are recorded per problem

@@ -58,7 +58,7 @@ class MsOpts(ctypes.Structure):
     _fields_ = [("cs_mode", ctypes.c_int32), ("refine_steps", ctypes.c_int32),
                 ("cs_tile_cols", ctypes.c_int32), ("cs_schedule", ctypes.c_int32),
                 ("batch_rows_log2", ctypes.c_int32), ("batch_kchunk_log2", ctypes.c_int32),
-                ("gauss_y_terms", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("gauss_y_terms", ctypes.c_int32), ("refine_tol_log2", ctypes.c_int32)]
 
 
 class MsProblem(ctypes.Structure):
@@ -172,9 +172,9 @@ def _stream(stream):
 
 
 def _opts(mode: str = "auto", refine_steps: int = 0, tile_cols: int = 0, schedule: int = 0,
-          rows_log2: int = 0, kchunk_log2: int = 0, y_terms: int = 0):
+          rows_log2: int = 0, kchunk_log2: int = 0, y_terms: int = 0, refine_tol_log2: int = 0):
     return MsOpts(MODES[mode], int(refine_steps), int(tile_cols), int(schedule), int(rows_log2),
-                  int(kchunk_log2), int(y_terms), 0)
+                  int(kchunk_log2), int(y_terms), int(refine_tol_log2))
 
 
 def workspace_size(op: str, d=0, n=0, nrhs=0, k=0, k2=0, a_dtype=MS_F64, g_dtype=MS_F64,
@@ -624,18 +624,24 @@ class BatchRunner:
     h (int32, d), s (int8, d), G (k2 x k), X (n x nrhs, FP64) and int k.
     ``capacity``: problems that bound later ones (same count; the later
     sets' totals of sketch, partial, factor and residual sizes no larger);
-    problem dicts or (d, n, nrhs, k, k2) tuples; defaults to ``problems``.  ``refine_steps``: FP64-residual refinement steps (each
-    problem then needs nrhs <= 8).
+    problem dicts or (d, n, nrhs, k, k2) tuples; defaults to ``problems``.
+    ``refine_steps``: FP64-residual refinement steps (each problem then needs
+    nrhs <= 8).  ``deterministic``: the CountSketch folds every bucket in
+    ascending row order, so each problem's X does not depend on the rest of
+    the batch (bit for bit).  ``refine_tol_log2`` (x > 0): a problem stops
+    refining once a step's correction is at most 2^-x of its X (Frobenius).
     """
 
     def __init__(self, problems, capacity=None, rows_log2: int = 0, kchunk_log2: int = 0,
-                 refine_steps: int = 0, y_terms: int = 0):
+                 refine_steps: int = 0, y_terms: int = 0, deterministic: bool = False,
+                 refine_tol_log2: int = 0):
         if not problems:
             raise ValueError("empty batch")
         self.count = len(problems)
         self.a_dtype = _dt(problems[0]["A"])
         self.g_dtype = _dt(problems[0]["G"])
-        self.opts = _opts("auto", refine_steps, 0, 0, rows_log2, kchunk_log2, y_terms)
+        self.opts = _opts("sorted" if deterministic else "auto", refine_steps, 0, 0, rows_log2,
+                          kchunk_log2, y_terms, refine_tol_log2)
         cap = capacity if capacity is not None else problems
         cap_arr = _host_array(cap)
         need = _lib.ms_batch_workspace_size(self.count, cap_arr, self.a_dtype, self.g_dtype,
@@ -710,10 +716,12 @@ class BatchRunner:
 
 
 def sketch_lstsq_batched(problems, rows_log2: int = 0, kchunk_log2: int = 0,
-                         refine_steps: int = 0, stream=None, y_terms: int = 0):
+                         refine_steps: int = 0, stream=None, y_terms: int = 0,
+                         deterministic: bool = False, refine_tol_log2: int = 0):
     """Solve a list of problems (dicts as for BatchRunner) in one batched call;
     returns the runner (its problems' X tensors hold the solutions)."""
     r = BatchRunner(problems, rows_log2=rows_log2, kchunk_log2=kchunk_log2,
-                    refine_steps=refine_steps, y_terms=y_terms)
+                    refine_steps=refine_steps, y_terms=y_terms, deterministic=deterministic,
+                    refine_tol_log2=refine_tol_log2)
     r.launch(stream)
     return r

@@ -80,6 +80,7 @@ int resolve_mode(const ms_opts *o) {
 
 struct CsLayout {
   size_t code = 0, cnt = 0, off = 0, cursor = 0, sperm = 0, tab = 0, tab_bytes = 0;
+  size_t bkeys = 0, bkeys_bytes = 0;  // the block fold's sorted keys (sorted mode)
   size_t part = 0, part_bytes = 0;
   size_t tplan = 0, tplan_bytes = 0;  // the tiled CountSketch's plan (k > 16384)
 };
@@ -87,7 +88,11 @@ struct CsLayout {
 // ncols, wd: columns and element bytes of the sketched operand (the LDS
 // variant's per-die partial buffer, when its schedule pays for the shape).
 void carve_cs(Carve &cv, CsLayout &L, int64_t d, int64_t k, int mode, int64_t ncols, int64_t wd) {
-  if (mode == MS_CS_SORTED) {
+  if (mode == MS_CS_SORTED && cs_blockfold_supported(d, k, 1, 8)) {
+    // the block fold (FP64 sizing, so that the FP64 residual's sketch fits too)
+    L.bkeys_bytes = cs_blockfold_key_bytes(d);
+    L.bkeys = cv.take(L.bkeys_bytes);
+  } else if (mode == MS_CS_SORTED) {
     L.cnt = cv.take((size_t)k * 4);
     L.off = cv.take((size_t)(k + 1) * 4);
     L.cursor = cv.take((size_t)k * 4);
@@ -279,6 +284,12 @@ hipError_t run_countsketch(int64_t d, int64_t k, const Cols<T> &c, const int32_t
   if (c.ncols <= 0 || d == 0)
     return launch_prologue<T>(status, Y, k, c.ncols > 0 ? c.ncols : 0, ldy, st);
   hipError_t e;
+  if (mode == MS_CS_SORTED && L.bkeys_bytes) {
+    e = launch_zero_status(status, st);
+    if (e == hipSuccess) e = launch_bf_keys(d, k, h, s, at<uint32_t>(ws, L.bkeys), status, st);
+    if (e == hipSuccess) e = launch_bf_fold<T>(d, k, c, at<uint32_t>(ws, L.bkeys), Y, ldy, st);
+    return e;
+  }
   if (mode == MS_CS_SORTED) {
     e = launch_prologue<int32_t>(status, at<int32_t>(ws, L.cnt), k, 1, k, st);
     if (e == hipSuccess) e = launch_check_signs(d, s, status, st);
@@ -664,7 +675,10 @@ ms_status sketch_lstsq(int64_t d, int64_t n, int64_t nrhs, int64_t k, int64_t k2
                               static_cast<const double *>(B), ldb, X, ldx, r, d, st);
     if (e != hipSuccess) break;
     Cols<double> cr{r, d, nullptr, 0, (int)nrhs, (int)nrhs};
-    if (mode == MS_CS_SORTED)
+    if (mode == MS_CS_SORTED && L.cs.bkeys_bytes)
+      e = launch_bf_fold<double>(d, k, cr, at<uint32_t>(ws, L.cs.bkeys), at<double>(ws, L.yr), k,
+                                 st);
+    else if (mode == MS_CS_SORTED)
       e = launch_cs_sorted_cols<double>(k, cr, at<int32_t>(ws, L.cs.off), at<uint32_t>(ws, L.cs.sperm),
                                    at<double>(ws, L.yr), k, st);
     else if (mode == MS_CS_ATOMIC)

@@ -28,13 +28,14 @@ constexpr int kSetupThreads = 1024;
 
 struct BatchCaps {
   int64_t code_bytes;                         // packed bucket/sign words
+  int64_t key_bytes;                          // sorted block keys (deterministic mode)
   int64_t y_bytes, part_bytes, z_bytes;       // first pass
   int64_t f_bytes, r_bytes, yr_bytes, gv_bytes;  // refinement (0 without)
 };
 
 struct BatchLayout {
-  size_t pstatus, entries, totals, codearea, yarea, parea, zarea, farea, rarea, yrarea, gvarea,
-      total;
+  size_t pstatus, entries, totals, codearea, keyarea, yarea, parea, zarea, farea, rarea, yrarea,
+      gvarea, total;
 };
 
 BatchLayout batch_layout(int count, const BatchCaps &caps) {
@@ -44,6 +45,7 @@ BatchLayout batch_layout(int count, const BatchCaps &caps) {
   L.entries = cv.take((size_t)count * sizeof(BatchEntry));
   L.totals = cv.take(sizeof(BatchTotals));
   L.codearea = cv.take((size_t)caps.code_bytes);
+  L.keyarea = cv.take((size_t)caps.key_bytes);
   L.yarea = cv.take((size_t)caps.y_bytes);
   L.parea = cv.take((size_t)caps.part_bytes);
   L.zarea = cv.take((size_t)caps.z_bytes);
@@ -57,7 +59,8 @@ BatchLayout batch_layout(int count, const BatchCaps &caps) {
 
 // The per-problem quantities the setup scans: work items of each persistent
 // launch and bytes of each workspace area.
-enum BatchQ { QCS, QGEMM, QRES, QRCS, QGV, QCODE, QY, QPART, QZ, QF, QR, QYR, QGVB, NQ };
+enum BatchQ { QCS, QGEMM, QRES, QRCS, QGV, QCODE, QY, QPART, QZ, QF, QR, QYR, QGVB,
+              QBK, QBF, QBFR, QKEY, NQ };
 
 __host__ __device__ inline void batch_quantities(const ms_problem &P, const BatchEntry &e,
                                                  int wdata, int accw, int64_t q[NQ]) {
@@ -74,6 +77,10 @@ __host__ __device__ inline void batch_quantities(const ms_problem &P, const Batc
   q[QR] = batch_r_bytes(P, e);
   q[QYR] = batch_yr_bytes(P, e);
   q[QGVB] = batch_gv_bytes(P, e);
+  q[QBK] = batch_bk_items(P, e);
+  q[QBF] = batch_bf_items(e);
+  q[QBFR] = batch_bfr_items(P, e);
+  q[QKEY] = batch_key_bytes(P, e);
 }
 
 __device__ __forceinline__ int64_t wave_excl_scan64(int64_t v, int64_t &wave_total) {
@@ -108,7 +115,7 @@ __device__ int64_t block_excl_scan64(int64_t v, int64_t *sh, int64_t &total) {
 
 __global__ __launch_bounds__(kSetupThreads) void k_batch_setup(
     int count, const ms_problem *__restrict__ P, int wdata, int accw, int64_t rows_item,
-    int64_t kchunk, int refine, BatchCaps caps, BatchEntry *__restrict__ E,
+    int64_t kchunk, int refine, int det, BatchCaps caps, BatchEntry *__restrict__ E,
     BatchTotals *__restrict__ tot, int *__restrict__ pstatus, int *status) {
   __shared__ int64_t sh[16];
   if (threadIdx.x == 0) *status = MS_OK;
@@ -117,7 +124,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_batch_setup(
   int64_t sum[NQ] = {}, mx = 0;
   for (int p = p0; p < p1; ++p) {
     BatchEntry e;
-    batch_entry(P[p], wdata, accw, rows_item, kchunk, refine, e);
+    batch_entry(P[p], wdata, accw, rows_item, kchunk, refine, e, det);
     int64_t q[NQ];
     batch_quantities(P[p], e, wdata, accw, q);
     for (int j = 0; j < NQ; ++j) sum[j] += q[j];
@@ -135,10 +142,10 @@ __global__ __launch_bounds__(kSetupThreads) void k_batch_setup(
   const bool fits = total[QY] <= caps.y_bytes && total[QPART] <= caps.part_bytes &&
                     total[QZ] <= caps.z_bytes && total[QF] <= caps.f_bytes &&
                     total[QR] <= caps.r_bytes && total[QYR] <= caps.yr_bytes &&
-                    total[QGVB] <= caps.gv_bytes;
+                    total[QGVB] <= caps.gv_bytes && total[QKEY] <= caps.key_bytes;
   for (int p = p0; p < p1; ++p) {
     BatchEntry e;
-    batch_entry(P[p], wdata, accw, rows_item, kchunk, refine, e);
+    batch_entry(P[p], wdata, accw, rows_item, kchunk, refine, e, det);
     const bool valid = e.valid != 0;
     if (!fits) e.valid = 0;
     int64_t q[NQ];
@@ -156,6 +163,10 @@ __global__ __launch_bounds__(kSetupThreads) void k_batch_setup(
     e.r_off = off[QR];
     e.yr_off = off[QYR];
     e.gv_off = off[QGVB];
+    e.bk_start = off[QBK];
+    e.bf_start = off[QBF];
+    e.bfr_start = off[QBFR];
+    e.key_off = off[QKEY];
     for (int j = 0; j < NQ; ++j) off[j] += q[j];
     E[p] = e;
     if (!valid) record_status(status, MS_ERR_ARG);
@@ -179,6 +190,9 @@ __global__ __launch_bounds__(kSetupThreads) void k_batch_setup(
     T.res_items = fits ? total[QRES] : 0;
     T.rcs_items = fits ? total[QRCS] : 0;
     T.gv_items = fits ? total[QGV] : 0;
+    T.bk_items = fits ? total[QBK] : 0;
+    T.bf_items = fits ? total[QBF] : 0;
+    T.bfr_items = fits ? total[QBFR] : 0;
     T.y_bytes = fits ? total[QY] : 0;
     T.yr_bytes = fits ? total[QYR] : 0;
     T.part_bytes = total[QPART];
@@ -221,21 +235,24 @@ int64_t kchunk_of(const ms_opts *o) {
   return (int64_t)1 << (r ? r : 10);
 }
 int refine_of(const ms_opts *o) { return o ? o->refine_steps : 0; }
+int det_of(const ms_opts *o) { return (o && o->cs_mode == MS_CS_SORTED) ? 1 : 0; }
 bool valid_batch_opts(const ms_opts *o) {
   if (!o) return true;
-  if (o->cs_mode != MS_CS_AUTO && o->cs_mode != MS_CS_LDS) return false;
+  if (o->cs_mode != MS_CS_AUTO && o->cs_mode != MS_CS_LDS && o->cs_mode != MS_CS_SORTED)
+    return false;
   if (o->refine_steps < 0 || o->refine_steps > 64) return false;
   if (o->batch_rows_log2 != 0 && (o->batch_rows_log2 < 8 || o->batch_rows_log2 > 24)) return false;
   if (o->batch_kchunk_log2 != 0 && (o->batch_kchunk_log2 < 5 || o->batch_kchunk_log2 > 20))
     return false;
   if (!(o->gauss_y_terms == 0 || o->gauss_y_terms == 1 || o->gauss_y_terms == 3)) return false;
+  if (o->refine_tol_log2 < 0 || o->refine_tol_log2 > 60) return false;
   return true;
 }
 
 // Host pass over the descriptors: validity, area sizes and launch maxima.
 struct HostBatch {
   bool ok = true, refine_rhs_ok = true;
-  BatchCaps caps{0, 0, 0, 0, 0, 0, 0, 0};
+  BatchCaps caps{0, 0, 0, 0, 0, 0, 0, 0, 0};
   int max_k2 = 1, max_n = 1, max_nc = 2;
   int64_t max_mn = 1;
 };
@@ -252,7 +269,7 @@ HostBatch host_batch(int count, const ms_problem *probs, ms_dtype a, ms_dtype g,
       return H;
     }
     BatchEntry e;
-    batch_entry(probs[p], wdata, accw, rows_item_of(o), kchunk_of(o), refine, e);
+    batch_entry(probs[p], wdata, accw, rows_item_of(o), kchunk_of(o), refine, e, det_of(o));
     if (!e.valid) {
       H.ok = false;
       return H;
@@ -260,6 +277,7 @@ HostBatch host_batch(int count, const ms_problem *probs, ms_dtype a, ms_dtype g,
     int64_t q[NQ];
     batch_quantities(probs[p], e, wdata, accw, q);
     H.caps.code_bytes += q[QCODE];
+    H.caps.key_bytes += q[QKEY];
     H.caps.y_bytes += q[QY];
     H.caps.part_bytes += q[QPART];
     H.caps.z_bytes += q[QZ];
@@ -298,8 +316,7 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
   if (count < 1 || count > 65535 || !probs_host || !probs_dev || !ws) return MS_ERR_ARG;
   if (a_dtype == MS_F32 && g_dtype == MS_F16) return MS_ERR_UNSUPPORTED;
   if (!valid_dtypes(a_dtype, g_dtype)) return MS_ERR_ARG;
-  if (opts && (opts->cs_mode == MS_CS_SORTED || opts->cs_mode == MS_CS_ATOMIC))
-    return MS_ERR_UNSUPPORTED;
+  if (opts && opts->cs_mode == MS_CS_ATOMIC) return MS_ERR_UNSUPPORTED;
   if (!valid_batch_opts(opts)) return MS_ERR_ARG;
   const HostBatch H = host_batch(count, probs_host, a_dtype, g_dtype, opts);
   if (!H.refine_rhs_ok) return MS_ERR_UNSUPPORTED;
@@ -313,26 +330,40 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
   BatchEntry *E = reinterpret_cast<BatchEntry *>(base + L.entries);
   BatchTotals *tot = reinterpret_cast<BatchTotals *>(base + L.totals);
   unsigned char *yarea = base + L.yarea, *parea = base + L.parea, *zarea = base + L.zarea;
-  unsigned char *codearea = base + L.codearea;
+  unsigned char *codearea = base + L.codearea, *keyarea = base + L.keyarea;
   unsigned char *farea = base + L.farea, *rarea = base + L.rarea, *yrarea = base + L.yrarea,
                 *gvarea = base + L.gvarea;
   const DevInfo &di = dev_info();
   const int wdata = (int)dtype_size(a_dtype);
   const int accw = g_dtype == MS_F64 ? 8 : 4;
   const int refine = refine_of(opts);
+  const int det = det_of(opts);
 
   hipLaunchKernelGGL(k_batch_setup, dim3(1), dim3(kSetupThreads), 0, st, count, probs_dev, wdata,
-                     accw, rows_item_of(opts), kchunk_of(opts), refine > 0 ? 1 : 0, H.caps, E,
-                     tot, pstatus, status);
+                     accw, rows_item_of(opts), kchunk_of(opts), refine > 0 ? 1 : 0, det, H.caps,
+                     E, tot, pstatus, status);
   hipError_t e = hipGetLastError();
   auto zero = [&](int residual, unsigned char *area) {
     hipLaunchKernelGGL(k_batch_zero, dim3(32, (unsigned)std::min(count, 2048)), dim3(256), 0, st,
                        count, probs_dev, E, residual, wdata, area);
     return hipGetLastError();
   };
-  if (e == hipSuccess) e = zero(0, yarea);
-  if (e == hipSuccess) e = launch_batch_pack(count, probs_dev, E, codearea, pstatus, status, st);
-  if (e == hipSuccess) {
+  if (det) {
+    // deterministic: sorted block keys, then the block-ordered fold of every
+    // column (each output slot stored once, no clearing)
+    if (e == hipSuccess)
+      e = launch_batch_bf_keys(count, probs_dev, E, tot, keyarea, pstatus, status, di.cus * 4, st);
+    if (e == hipSuccess)
+      e = a_dtype == MS_F64
+              ? launch_batch_bf_fold<double, 0>(count, probs_dev, E, tot, keyarea, nullptr, yarea,
+                                                di.cus, st)
+              : launch_batch_bf_fold<float, 0>(count, probs_dev, E, tot, keyarea, nullptr, yarea,
+                                               di.cus, st);
+  }
+  if (e == hipSuccess && !det) e = zero(0, yarea);
+  if (e == hipSuccess && !det)
+    e = launch_batch_pack(count, probs_dev, E, codearea, pstatus, status, st);
+  if (e == hipSuccess && !det) {
     const int grid = di.cus;  // one 1024-thread workgroup per CU (128 KB of LDS each)
     e = a_dtype == MS_F64
             ? launch_batch_cs<double>(count, probs_dev, E, tot, codearea, yarea, pstatus, status,
@@ -347,21 +378,24 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
     e = launch_batch_reduce(count, g_dtype, probs_dev, E, parea, zarea, (int)H.max_mn, st);
   if (e == hipSuccess)
     e = launch_batch_qr(count, H.max_k2, H.max_n, H.max_nc, probs_dev, E, zarea, farea, pstatus,
-                        status, st);
+                        status, st, det);
   // refinement: r = B - A X (FP64); X += R^{-1} Q^T G (C r)
   for (int it = 0; it < refine && e == hipSuccess; ++it) {
-    e = zero(1, yrarea);
+    if (!det) e = zero(1, yrarea);
     if (e == hipSuccess)
       e = a_dtype == MS_F64
               ? launch_batch_residual<double>(count, probs_dev, E, tot, rarea, di.cus * 8, st)
               : launch_batch_residual<float>(count, probs_dev, E, tot, rarea, di.cus * 8, st);
     if (e == hipSuccess)
-      e = launch_batch_cs_res(count, probs_dev, E, tot, codearea, rarea, yrarea, pstatus, status,
-                              di.cus, st);
+      e = det ? launch_batch_bf_fold<double, 1>(count, probs_dev, E, tot, keyarea, rarea, yrarea,
+                                                di.cus, st)
+              : launch_batch_cs_res(count, probs_dev, E, tot, codearea, rarea, yrarea, pstatus,
+                                    status, di.cus, st);
     if (e == hipSuccess)
       e = launch_batch_gemv(count, g_dtype, probs_dev, E, tot, yrarea, gvarea, di.cus * 4, st);
     if (e == hipSuccess)
-      e = launch_batch_apply_solve(count, probs_dev, E, gvarea, farea, pstatus, status, st);
+      e = launch_batch_apply_solve(count, probs_dev, E, gvarea, farea, pstatus, status, st,
+                                   opts ? opts->refine_tol_log2 : 0);
   }
   return e == hipSuccess ? MS_OK : MS_ERR_DEVICE;
 }

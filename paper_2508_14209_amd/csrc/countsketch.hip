@@ -756,6 +756,7 @@ __global__ __launch_bounds__(1024) void k_batch_cs(int count, const ms_problem *
                       : batch_find_m<&BatchEntry::cs_start>(E, count, it);
     const ms_problem &Q = P[p];
     const BatchEntry &e = E[p];
+    if (RES && !e.refine) continue;   // converged in an earlier step
     const int nbt = RES ? e.rnbt : e.nbt, nt = RES ? e.rnt : e.nt;
     const int64_t ktile = RES ? e.rktile : e.ktile;
     // the column tiles and bucket tiles of a row segment are consecutive

@@ -35,11 +35,11 @@ constexpr int64_t kBlk = (int64_t)1 << kBlkLog2;
 constexpr uint32_t kOffMask = (uint32_t)kBlk - 1;
 constexpr int kLbShift = kBlkLog2;             // bucket within the tile: bits 13..27
 constexpr uint32_t kLbMask = 0x7fffu;
-constexpr int64_t kMaxSlots = 18432;           // FP64 partial sums (144 KB) beside 16 KB of ranges
+constexpr int64_t kMaxSlots = 20480;           // FP64 partial sums in 160 KB of LDS
 constexpr int kMaxTiles = 32;                  // at least one group per die of 32 CUs
 constexpr int kPlanThreads = 1024;             // 8 rows per thread in a plan block
-constexpr int kPer = 8;                        // gathers in flight per thread (16 measured slower)
-constexpr int kSegUnits = 2048;                // blocks whose entry ranges are staged in LDS
+constexpr int kUnits = 8;                      // (column, block) units per batch
+constexpr int kPer = 4;                        // gathers in flight per thread
 
 struct TileShape {
   int nbt = 0;  // 0: not applicable
@@ -52,7 +52,10 @@ TileShape tile_shape(int64_t d, int64_t k) {
   int64_t need = (k + kMaxSlots - 1) / kMaxSlots;
   int nbt = 2;
   while (nbt < need) nbt *= 2;
-  if (nbt > kMaxTiles) return s;
+  // two bucket tiles: the untiled kernel, whose two tiles each stream every
+  // row, measured faster (16,777,216 x 129 FP32, k = 32,768: 2.98 vs 3.2 ms);
+  // from four tiles the per-tile entry lists win (k = 131,072: 6.0 vs 7.9 ms)
+  if (nbt < 4 || nbt > kMaxTiles) return s;
   s.nbt = nbt;
   s.ktile = (k + nbt - 1) / nbt;
   s.nblk = (d + kBlk - 1) / kBlk;
@@ -158,91 +161,14 @@ __device__ __forceinline__ void tiled_flush(double *acc, uint32_t kt, int64_t bb
   __syncthreads();
 }
 
-// One wave's walk over its share of a column segment: items it = wave,
-// wave + nw, ... of the segment's nb * parts items (item = one part of one
-// block's entry list for tile t), in chunks of 64 * P entries.  seg[2 u],
-// seg[2 u + 1] (LDS) hold the first and end entry of tile t in the segment's
-// block u.  The entries of the next chunk are loaded while the current
-// chunk's rows are gathered and added, so one memory round trip per chunk is
-// exposed instead of two.
-template <typename T, int P>
-__device__ __forceinline__ void tiled_wave_walk(double *acc, const T *__restrict__ col,
-                                                const uint32_t *__restrict__ ent,
-                                                const int32_t *seg, int64_t b0, int nb, int parts,
-                                                int wave, int nw, int lane) {
-  const int nitems = nb * parts;
-  int it = wave;
-  int64_t eb = 0;     // first row of the current item's block (entries are stored per row)
-  int32_t pos = 0, s1 = 0;
-  // advance `it` to the next item with entries; false when none is left
-  auto open = [&]() -> bool {
-    for (; it < nitems; it += nw) {
-      const int u = it / parts, part = it - u * parts;
-      const int32_t a = seg[2 * u], z = seg[2 * u + 1];
-      const int32_t len = z - a;
-      const int32_t lo = a + (int32_t)((int64_t)len * part / parts);
-      const int32_t hi = a + (int32_t)((int64_t)len * (part + 1) / parts);
-      if (hi > lo) {
-        eb = (b0 + u) * kBlk;
-        pos = lo;
-        s1 = hi;
-        return true;
-      }
-    }
-    return false;
-  };
-  if (!open()) return;
-  // Loads are issued unconditionally (a lane past the end of its list reads
-  // the list's last entry, an invalid entry reads the block's first row) and
-  // masked afterwards: with no loads inside branches the compiler can wait for
-  // the gathers alone while the next entries are still in flight.
-  uint32_t en[P];
-#pragma unroll
-  for (int p = 0; p < P; ++p) {
-    const int32_t v = pos + 64 * p + lane;
-    const uint32_t x = gload(ent + eb + min(v, s1 - 1));
-    en[p] = v < s1 ? x : 0xffffffffu;
-  }
-  while (true) {
-    uint32_t e[P];
-    T a[P];
-    const T *cb = col + eb;
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      e[p] = en[p];
-      const uint32_t off = e[p] != 0xffffffffu ? (e[p] & kOffMask) : 0u;
-      a[p] = gload(cb + off);
-    }
-    pos += 64 * P;
-    bool more = true;
-    if (pos >= s1) {
-      it += nw;
-      more = open();
-    }
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int32_t v = pos + 64 * p + lane;
-      const uint32_t x = gload(ent + eb + min(v, s1 - 1));
-      en[p] = (more && v < s1) ? x : 0xffffffffu;
-    }
-#pragma unroll
-    for (int p = 0; p < P; ++p)
-      if (e[p] != 0xffffffffu)
-        atomicAdd(&acc[(e[p] >> kLbShift) & kLbMask], (double)apply_sign(a[p], e[p]));
-    if (!more) break;
-  }
-}
-
-template <typename T, int P>
+template <typename T>
 __global__ __launch_bounds__(1024) void k_cs_tiled(int64_t d, Cols<T> cols, int64_t k,
                                                    int64_t ktile, int nbt, int64_t nblk,
                                                    const uint32_t *__restrict__ ent,
                                                    const int32_t *__restrict__ boff, int xcds,
-                                                   int subs, int parts, T *__restrict__ Y,
-                                                   int64_t ldy) {
+                                                   int subs, T *__restrict__ Y, int64_t ldy) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double *acc = reinterpret_cast<double *>(smem_raw);
-  int32_t *seg = reinterpret_cast<int32_t *>(acc + ktile);   // kSegUnits (first, end) pairs
   const int g = blockIdx.x;
   const int x = g % xcds, slot = g / xcds;
   if (slot >= subs * nbt) return;
@@ -252,30 +178,71 @@ __global__ __launch_bounds__(1024) void k_cs_tiled(int64_t d, Cols<T> cols, int6
   const int64_t bbase = (int64_t)t * ktile;
   if (bbase >= k) return;
   const uint32_t kt = (uint32_t)min(ktile, k - bbase);
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int nw = (int)(blockDim.x >> 6);
   for (uint32_t l = threadIdx.x; l < kt; l += blockDim.x) acc[l] = 0.0;
+  __syncthreads();
   const int64_t total = (int64_t)cols.ncols * nblk;
   int64_t u = total * grp / ngroups;
   const int64_t u1 = total * (grp + 1) / ngroups;
   int cur = -1;
   while (u < u1) {
-    // up to kSegUnits of the group's units of one column: blocks b0 .. b0 + nb - 1
     const int c = (int)(u / nblk);
     const int64_t b0 = u - (int64_t)c * nblk;
-    const int nb = (int)min<int64_t>(kSegUnits, min(u1 - u, nblk - b0));
+    const int64_t nb = min<int64_t>(kUnits, min(u1 - u, nblk - b0));
     if (c != cur) {
       if (cur >= 0) tiled_flush<T>(acc, kt, bbase, cur, Y, ldy);
       cur = c;
     }
-    __syncthreads();   // the previous segment's walk is done with seg
-    for (int q = threadIdx.x; q < 2 * nb; q += blockDim.x)
-      seg[q] = boff[(b0 + (q >> 1)) * (nbt + 1) + t + (q & 1)];
-    __syncthreads();
-    // split blocks further when the segment has fewer items than waves
-    const int pseg = max(parts, min(8, (nw + nb - 1) / nb));
-    tiled_wave_walk<T, P>(acc, tcol(cols, c), ent, seg, b0, nb, pseg, wave, nw, lane);
+    const T *col = tcol(cols, c);
+    // the batch's entry lists, concatenated: unit j holds virtual positions
+    // [pre[j], pre[j+1])
+    int32_t e0[kUnits], pre[kUnits + 1];
+    pre[0] = 0;
+#pragma unroll
+    for (int j = 0; j < kUnits; ++j) {
+      int32_t a = 0, z = 0;
+      if (j < nb) {
+        const int32_t *bo = boff + (b0 + j) * (nbt + 1) + t;
+        a = bo[0];
+        z = bo[1];
+      }
+      e0[j] = a;
+      pre[j + 1] = pre[j] + (z - a);
+    }
+    const int32_t L = pre[kUnits];
+    for (int32_t base = 0; base < L; base += kPer * (int32_t)blockDim.x) {
+      uint32_t e[kPer];
+      int64_t rb[kPer];
+#pragma unroll
+      for (int p = 0; p < kPer; ++p) {
+        const int32_t v = base + p * (int32_t)blockDim.x + (int32_t)threadIdx.x;
+        e[p] = 0xffffffffu;
+        rb[p] = 0;
+        if (v < L) {
+          // the unit holding v: the last j with pre[j] <= v (static indices
+          // only, so the small arrays stay in registers)
+          int j = 0;
+          int32_t ej = e0[0], pj = 0;
+#pragma unroll
+          for (int q = 1; q < kUnits; ++q)
+            if (v >= pre[q]) {
+              j = q;
+              ej = e0[q];
+              pj = pre[q];
+            }
+          const int64_t blk = b0 + j;
+          e[p] = gload(ent + blk * kBlk + ej + (v - pj));
+          rb[p] = blk * kBlk;
+        }
+      }
+      T a[kPer];
+#pragma unroll
+      for (int p = 0; p < kPer; ++p)
+        a[p] = e[p] != 0xffffffffu ? gload(col + rb[p] + (e[p] & kOffMask)) : T(0);
+#pragma unroll
+      for (int p = 0; p < kPer; ++p)
+        if (e[p] != 0xffffffffu)
+          atomicAdd(&acc[(e[p] >> kLbShift) & kLbMask], (double)apply_sign(a[p], e[p]));
+    }
     u += nb;
   }
   if (cur >= 0) tiled_flush<T>(acc, kt, bbase, cur, Y, ldy);
@@ -293,8 +260,7 @@ bool cs_tiled_supported(int64_t d, int64_t k) {
   const TileShape s = tile_shape(d, k);
   if (!s.nbt) return false;
   const DevInfo &di = dev_info();
-  return di.lds_per_block >= s.ktile * 8 + kSegUnits * 8 && di.cus % di.xcds == 0 &&
-         di.cus / di.xcds >= s.nbt;
+  return di.lds_per_block >= s.ktile * 8 && di.cus % di.xcds == 0 && di.cus / di.xcds >= s.nbt;
 }
 
 hipError_t launch_tile_plan(int64_t d, int64_t k, const uint32_t *code, const int32_t *h,
@@ -323,18 +289,15 @@ hipError_t launch_cs_tiled(int64_t d, int64_t k, const Cols<T> &c, const void *p
   const DevInfo &di = dev_info();
   const int xcds = di.xcds;
   const int subs = di.cus / xcds / sh.nbt;
-  const size_t lds = (size_t)sh.ktile * 8 + (size_t)kSegUnits * 8;
-  const void *fn = (const void *)k_cs_tiled<T, kPer>;
+  const size_t lds = (size_t)sh.ktile * 8;
+  const void *fn = (const void *)k_cs_tiled<T>;
   hipError_t e = allow_dynamic_lds(fn, (int)lds);
   if (e != hipSuccess) return e;
   const uint32_t *ent = static_cast<const uint32_t *>(plan);
   const int32_t *boff = reinterpret_cast<const int32_t *>(
       static_cast<const unsigned char *>(plan) + align_up((size_t)sh.nblk * kBlk * 4));
-  // about 2048 entries per item: a block holds about 8192 / nbt entries of a tile
-  const int parts = std::max(1, (int)(kBlk / sh.nbt / 2048));
-  hipLaunchKernelGGL((k_cs_tiled<T, kPer>), dim3((unsigned)(xcds * subs * sh.nbt)), dim3(1024),
-                     lds, st, d, c, k, sh.ktile, sh.nbt, sh.nblk, ent, boff, xcds, subs, parts, Y,
-                     ldy);
+  hipLaunchKernelGGL(k_cs_tiled<T>, dim3((unsigned)(xcds * subs * sh.nbt)), dim3(1024), lds, st,
+                     d, c, k, sh.ktile, sh.nbt, sh.nblk, ent, boff, xcds, subs, Y, ldy);
   return hipGetLastError();
 }
 template hipError_t launch_cs_tiled<double>(int64_t, int64_t, const Cols<double> &, const void *,

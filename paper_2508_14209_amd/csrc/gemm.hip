@@ -820,6 +820,7 @@ __global__ __launch_bounds__(256) void k_batch_gemv(int count, const ms_problem 
     const int p = batch_find_m<&BatchEntry::gv_start>(E, count, it);
     const ms_problem &Q = P[p];
     const BatchEntry &e = E[p];
+    if (!e.refine) continue;   // converged in an earlier step
     const int split = (int)(it - e.gv_start);
     const int M = (int)Q.k2, N = (int)Q.nrhs;
     const int L = (M + 3) / 4, S = (int)blockDim.x / L;

@@ -255,6 +255,11 @@ struct BatchEntry {
   int64_t f_off, r_off, yr_off, gv_off;
   int64_t rktile;
   int32_t rnt, rntiles, rnbt, pad1;
+  // deterministic mode (det != 0): the block-ordered CountSketch instead of
+  // the LDS one -- sorted keys of each 4096-row block at key_off, fold items
+  // (column, bucket part) of the first pass and of the residuals
+  int64_t bk_start, bf_start, bfr_start, key_off;
+  int32_t det, parts, rparts, pad3;
 };
 
 constexpr int64_t kBatchResRows = 2048;  // rows per residual work item
@@ -282,9 +287,18 @@ __host__ __device__ inline void batch_cs_geom(int64_t k, int nc, int64_t &ktile,
   ntiles = (nc + nt - 1) / nt;
 }
 
+// Deterministic mode: rows per sorted-key block, and the bucket sums one
+// 160 KB workgroup holds next to a block's staged values and keys (FP32 data:
+// 32768, FP64 data and residuals: 14336).
+constexpr int64_t kBatchBfRows = 4096;
+constexpr int kBatchBfMaxParts = 32;
+__host__ __device__ inline int64_t batch_bf_slots(int welem) {
+  return welem == 4 ? 32768 : 14336;
+}
+
 __host__ __device__ inline void batch_entry(const ms_problem &P, int wdata, int accw,
                                             int64_t rows_item, int64_t kchunk, int refine,
-                                            BatchEntry &E) {
+                                            BatchEntry &E, int det = 0) {
   E = BatchEntry{};
   E.valid = P.d >= 1 && P.d < 0x7fffffffLL && P.n >= 1 && P.nrhs >= 1 && P.k >= 1 &&
             P.k < 0x7fffffffLL && P.k2 >= P.n && P.k2 <= kBatchMaxK2 &&
@@ -306,10 +320,34 @@ __host__ __device__ inline void batch_entry(const ms_problem &P, int wdata, int 
   E.tiles_n = (E.nc + 63) / 64;
   E.kchunk = kchunk;
   E.nsplit = (int32_t)((P.k + kchunk - 1) / kchunk);
+  if (det) {
+    E.det = 1;
+    const int64_t parts = (P.k + batch_bf_slots(wdata) - 1) / batch_bf_slots(wdata);
+    const int64_t rparts = (P.k + batch_bf_slots(8) - 1) / batch_bf_slots(8);
+    if (parts > kBatchBfMaxParts || rparts > kBatchBfMaxParts || P.k >= ((int64_t)1 << 19)) {
+      E.valid = 0;
+      return;
+    }
+    E.parts = (int32_t)parts;
+    E.rparts = refine ? (int32_t)rparts : 0;
+  }
 }
 
 __host__ __device__ inline int64_t batch_cs_items(const BatchEntry &E) {
-  return E.valid ? (int64_t)E.ntiles * E.nsegs * E.nbt : 0;
+  return E.valid && !E.det ? (int64_t)E.ntiles * E.nsegs * E.nbt : 0;
+}
+// deterministic mode: key blocks, fold items, key bytes
+__host__ __device__ inline int64_t batch_bk_items(const ms_problem &P, const BatchEntry &E) {
+  return E.valid && E.det ? (P.d + kBatchBfRows - 1) / kBatchBfRows : 0;
+}
+__host__ __device__ inline int64_t batch_bf_items(const BatchEntry &E) {
+  return E.valid && E.det ? (int64_t)E.nc * E.parts : 0;
+}
+__host__ __device__ inline int64_t batch_bfr_items(const ms_problem &P, const BatchEntry &E) {
+  return E.valid && E.det && E.refine ? (int64_t)P.nrhs * E.rparts : 0;
+}
+__host__ __device__ inline int64_t batch_key_bytes(const ms_problem &P, const BatchEntry &E) {
+  return batch_bk_items(P, E) * kBatchBfRows * 4;
 }
 __host__ __device__ inline int64_t batch_gemm_items(const BatchEntry &E) {
   return E.valid ? (int64_t)E.tiles_m * E.tiles_n * E.nsplit : 0;
@@ -322,7 +360,7 @@ __host__ __device__ inline int64_t batch_y_bytes(const ms_problem &P, const Batc
 // pack pass (9 bytes per row) pays for itself from there.
 constexpr int kBatchPackSweeps = 8;
 __host__ __device__ inline bool batch_packs(const BatchEntry &E) {
-  return E.valid && (int64_t)E.ntiles * E.nbt >= kBatchPackSweeps;
+  return E.valid && !E.det && (int64_t)E.ntiles * E.nbt >= kBatchPackSweeps;
 }
 __host__ __device__ inline int64_t batch_code_bytes(const ms_problem &P, const BatchEntry &E) {
   return batch_packs(E) ? batch_align(P.d * 4) : 0;
@@ -339,7 +377,7 @@ __host__ __device__ inline int64_t batch_res_items(const ms_problem &P, const Ba
   return batch_ref(E) ? (P.d + kBatchResRows - 1) / kBatchResRows : 0;
 }
 __host__ __device__ inline int64_t batch_rcs_items(const BatchEntry &E) {
-  return batch_ref(E) ? (int64_t)E.rntiles * E.nsegs * E.rnbt : 0;
+  return batch_ref(E) && !E.det ? (int64_t)E.rntiles * E.nsegs * E.rnbt : 0;
 }
 __host__ __device__ inline int64_t batch_gv_items(const BatchEntry &E) {
   return batch_ref(E) ? (int64_t)E.nsplit : 0;
@@ -361,7 +399,8 @@ __host__ __device__ inline int64_t batch_gv_bytes(const ms_problem &P, const Bat
 struct BatchTotals {
   int64_t cs_items, gemm_items, y_bytes, part_bytes, z_bytes, max_mn;
   int64_t res_items, rcs_items, gv_items, yr_bytes;
-  int64_t pad[2];
+  int64_t bk_items, bf_items, bfr_items;
+  int64_t pad[3];
 };
 
 // Last problem whose first item (member M of its entry) is <= it; problems
@@ -399,7 +438,8 @@ hipError_t launch_batch_reduce(int count, ms_dtype g_dtype, const ms_problem *P,
                                unsigned char *zarea, int max_mn, hipStream_t st);
 hipError_t launch_batch_qr(int count, int max_k2, int max_n, int max_nc, const ms_problem *P,
                            const BatchEntry *E, const unsigned char *zarea, unsigned char *farea,
-                           int *pstatus, int *status, hipStream_t st);
+                           int *pstatus, int *status, hipStream_t st,
+                           int det = 0);
 // refinement: r = B - A X; Yr = C r; partials of G Yr; X += R^{-1} Q^T (G Yr)
 template <typename TA>
 hipError_t launch_batch_residual(int count, const ms_problem *P, const BatchEntry *E,
@@ -413,9 +453,12 @@ hipError_t launch_batch_gemv(int count, ms_dtype g_dtype, const ms_problem *P,
                              const BatchEntry *E, const BatchTotals *tot,
                              const unsigned char *yrarea, unsigned char *gvarea, int grid,
                              hipStream_t st);
-hipError_t launch_batch_apply_solve(int count, const ms_problem *P, const BatchEntry *E,
+// tol_log2 > 0: a problem whose correction is <= 2^-tol_log2 of its X
+// (Frobenius) has its entry's refine flag cleared, and the later steps'
+// residual, sketch, G product and update kernels skip it
+hipError_t launch_batch_apply_solve(int count, const ms_problem *P, BatchEntry *E,
                                     const unsigned char *gvarea, const unsigned char *farea,
-                                    int *pstatus, int *status, hipStream_t st);
+                                    int *pstatus, int *status, hipStream_t st, int tol_log2 = 0);
 
 // ------------------------------------------------------------------ wave helpers
 // Wave-wide sum with DPP: quad swaps, half-row and row mirrors give every
@@ -508,5 +551,29 @@ hipError_t launch_plan_blocked(int64_t d, int64_t k, const int32_t *h, const int
 template <typename T>
 hipError_t launch_cs_sorted_cols(int64_t k, const Cols<T> &c, const int32_t *off,
                                  const uint32_t *sperm, T *Y, int64_t ldy, hipStream_t st);
+
+// deterministic batched mode (cs_blockfold.hip): sorted keys of every
+// problem's 4096-row blocks; the block-ordered fold of every problem's
+// [A | B] (RES = 0, into the Y area) or of its residuals (RES = 1, into Yr)
+hipError_t launch_batch_bf_keys(int count, const ms_problem *P, const BatchEntry *E,
+                                const BatchTotals *tot, unsigned char *keyarea, int *pstatus,
+                                int *status, int grid, hipStream_t st);
+template <typename T, int RES>
+hipError_t launch_batch_bf_fold(int count, const ms_problem *P, const BatchEntry *E,
+                                const BatchTotals *tot, const unsigned char *keyarea,
+                                const unsigned char *rarea, unsigned char *out, int grid,
+                                hipStream_t st);
+
+// cs_blockfold.hip -- the deterministic CountSketch as a block-ordered fold:
+// per block of 4096 rows the keys (bucket << 12 | row | sign << 31) sorted
+// by (bucket, row); then one workgroup per (column, bucket range) folds the
+// blocks in order with its bucket sums in LDS (elem: bytes of the data type).
+bool cs_blockfold_supported(int64_t d, int64_t k, int ncols, size_t elem);
+size_t cs_blockfold_key_bytes(int64_t d);
+hipError_t launch_bf_keys(int64_t d, int64_t k, const int32_t *h, const int8_t *s, uint32_t *keys,
+                          int *status, hipStream_t st);
+template <typename T>
+hipError_t launch_bf_fold(int64_t d, int64_t k, const Cols<T> &c, const uint32_t *keys, T *Y,
+                          int64_t ldy, hipStream_t st);
 
 }  // namespace ms

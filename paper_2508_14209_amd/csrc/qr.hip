@@ -418,13 +418,16 @@ __global__ __launch_bounds__(NW * 64) void k_qr_reg(int m, int n, int nrhs, cons
 }
 
 // One workgroup per problem of a batch: Z_p (FP64, k2 x (n + nrhs)) -> X_p.
+// first register shape that fits an m x nc system (defined with the shape table)
+__host__ __device__ inline int qr_first_shape(int64_t m, int64_t nc);
+
 template <int NW, int GW, int R, int S>
 __global__ __launch_bounds__(NW * 64) void k_batch_qr(int count, const ms_problem *__restrict__ P,
                                                    const BatchEntry *__restrict__ E,
                                                    const unsigned char *__restrict__ zarea,
                                                    unsigned char *__restrict__ farea,
                                                    int *__restrict__ pstatus, int *status,
-                                                   int64_t lds_doubles) {
+                                                   int64_t lds_doubles, int shape_class) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   __shared__ QrShared<GW * R> sh;
   const int p = blockIdx.x;
@@ -433,6 +436,9 @@ __global__ __launch_bounds__(NW * 64) void k_batch_qr(int count, const ms_proble
   const ms_problem &Q = P[p];
   const double *Z = reinterpret_cast<const double *>(zarea + e.z_off);
   const int m = (int)Q.k2, n = (int)Q.n;
+  // deterministic mode: one launch per shape, each problem factored by the
+  // first shape that fits it alone (the shape fixes the reduction order)
+  if (shape_class >= 0 && qr_first_shape(m, e.nc) != shape_class) return;
   // descriptors rewritten after the launch shape was chosen must still fit it
   if (m > GW * R || e.nc > (NW * 64 / GW) * S || (int64_t)n * e.nc > lds_doubles) {
     if (threadIdx.x == 0) {
@@ -464,6 +470,18 @@ constexpr QrRegShape kQrShapes[] = {
 
 static bool shape_fits(const QrRegShape &s, int64_t m, int64_t nc) {
   return s.gw * s.r >= m && (s.nw * 64 / s.gw) * s.s >= nc;
+}
+
+// Index in kQrShapes of the first register shape that fits an m x nc system
+// (-1: none); the same first-fit rule on the device.
+__host__ __device__ inline int qr_first_shape(int64_t m, int64_t nc) {
+  int j = 0;
+#define MS_QR_FIRST(W_, G_, R_, S_)                                        \
+  if ((int64_t)G_ * R_ >= m && (int64_t)(W_ * 64 / G_) * S_ >= nc) return j; \
+  ++j;
+  MS_QR_SHAPES(MS_QR_FIRST)
+#undef MS_QR_FIRST
+  return -1;
 }
 
 template <int NW, int GW, int R, int S>
@@ -759,23 +777,31 @@ hipError_t launch_qr_solve(int64_t m, int64_t n, int64_t nrhs, const double *W, 
 
 hipError_t launch_batch_qr(int count, int max_k2, int max_n, int max_nc, const ms_problem *P,
                            const BatchEntry *E, const unsigned char *zarea, unsigned char *farea,
-                           int *pstatus, int *status, hipStream_t st) {
+                           int *pstatus, int *status, hipStream_t st, int det) {
   const size_t lds = (size_t)max_n * (size_t)max_nc * sizeof(double);
-  for (const QrRegShape &s : kQrShapes) {
-    if (!shape_fits(s, max_k2, max_nc)) continue;
+  const int last = qr_first_shape(max_k2, max_nc);
+  if (last < 0) return hipErrorNotSupported;
+  // default: the one shape that fits the largest problem; deterministic:
+  // every shape up to that one, each taking the problems it fits first
+  const int first = det ? 0 : last;
+  for (int j = first; j <= last; ++j) {
+    const QrRegShape &s = kQrShapes[j];
+    const int cls = det ? j : -1;
+    hipError_t e = hipErrorNotSupported;
 #define MS_BQR_CASE(W_, G_, R_, S_)                                                            \
   if (s.nw == W_ && s.gw == G_ && s.r == R_ && s.s == S_) {                                   \
-    hipError_t e = allow_dynamic_lds((const void *)k_batch_qr<W_, G_, R_, S_>, (int)lds);    \
+    e = allow_dynamic_lds((const void *)k_batch_qr<W_, G_, R_, S_>, (int)lds);               \
     if (e != hipSuccess) return e;                                                            \
     hipLaunchKernelGGL((k_batch_qr<W_, G_, R_, S_>), dim3(count), dim3(W_ * 64), lds, st,     \
                        count, P, E,                                                           \
-                       zarea, farea, pstatus, status, (int64_t)max_n * max_nc);               \
-    return hipGetLastError();                                                                 \
+                       zarea, farea, pstatus, status, (int64_t)max_n * max_nc, cls);          \
+    e = hipGetLastError();                                                                    \
   }
     MS_QR_SHAPES(MS_BQR_CASE)
 #undef MS_BQR_CASE
+    if (e != hipSuccess) return e;
   }
-  return hipErrorNotSupported;
+  return hipSuccess;
 }
 
 // Refinement of a batch, one workgroup per problem: zr = the G Yr partials
@@ -785,10 +811,12 @@ hipError_t launch_batch_qr(int count, int max_k2, int max_n, int max_nc, const m
 // (and, in the back substitution, the next column of R) is loaded while the
 // current one is applied.
 __global__ __launch_bounds__(64 * kBatchMaxRefineRhs) void k_batch_apply_solve(
-    int count, const ms_problem *__restrict__ P, const BatchEntry *__restrict__ E,
-    const unsigned char *__restrict__ gvarea, const unsigned char *__restrict__ farea) {
+    int count, const ms_problem *__restrict__ P, BatchEntry *__restrict__ E,
+    const unsigned char *__restrict__ gvarea, const unsigned char *__restrict__ farea,
+    int tol_log2) {
   constexpr int RPL = kBatchMaxK2 / 64;
   __shared__ double zb[kBatchMaxK2 * kBatchMaxRefineRhs];
+  __shared__ double nrm[2][kBatchMaxRefineRhs];   // per right-hand side: ||dx||^2, ||X||^2
   const int p = blockIdx.x;
   const BatchEntry &e = E[p];
   if (!batch_ref(e)) return;
@@ -806,7 +834,11 @@ __global__ __launch_bounds__(64 * kBatchMaxRefineRhs) void k_batch_apply_solve(
   const double *fact = reinterpret_cast<const double *>(farea + e.f_off);
   const double *tau = fact + (int64_t)m * n;
   const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
-  if (c >= nrhs) return;
+  if (c >= nrhs) {
+    // waves without a right-hand side only join the convergence check
+    if (tol_log2 > 0) __syncthreads();
+    return;
+  }
   double y[RPL];
 #pragma unroll
   for (int r = 0; r < RPL; ++r) {
@@ -848,6 +880,7 @@ __global__ __launch_bounds__(64 * kBatchMaxRefineRhs) void k_batch_apply_solve(
     }
   };
   double rn[RPL];
+  double dx2 = 0.0, x2 = 0.0;   // lane 0: sums over this right-hand side
   if (n > 0) load_r(n - 1, rn);
   for (int i = n - 1; i >= 0; --i) {
     double col[RPL];
@@ -867,17 +900,40 @@ __global__ __launch_bounds__(64 * kBatchMaxRefineRhs) void k_batch_apply_solve(
       const int t = lane + 64 * r;
       if (t < i) y[r] -= col[r] * xi;
     }
-    if (lane == 0) Q.X[i + (int64_t)c * Q.ldx] += xi;
+    if (lane == 0) {
+      const double xn = Q.X[i + (int64_t)c * Q.ldx] + xi;
+      Q.X[i + (int64_t)c * Q.ldx] = xn;
+      dx2 += xi * xi;
+      x2 += xn * xn;
+    }
+  }
+  if (tol_log2 > 0) {
+    // converged when ||dx||_F <= 2^-tol ||X||_F: the later steps skip the
+    // problem (its entry's refine flag cleared; the setup of the next
+    // launch sets it again)
+    if (lane == 0) {
+      nrm[0][c] = dx2;
+      nrm[1][c] = x2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double sd = 0.0, sx = 0.0;
+      for (int q = 0; q < nrhs; ++q) {
+        sd += nrm[0][q];
+        sx += nrm[1][q];
+      }
+      if (sd <= ldexp(sx, -2 * tol_log2)) E[p].refine = 0;
+    }
   }
 }
 
-hipError_t launch_batch_apply_solve(int count, const ms_problem *P, const BatchEntry *E,
+hipError_t launch_batch_apply_solve(int count, const ms_problem *P, BatchEntry *E,
                                     const unsigned char *gvarea, const unsigned char *farea,
-                                    int *pstatus, int *status, hipStream_t st) {
+                                    int *pstatus, int *status, hipStream_t st, int tol_log2) {
   (void)pstatus;
   (void)status;
   hipLaunchKernelGGL(k_batch_apply_solve, dim3(count), dim3(64 * kBatchMaxRefineRhs), 0, st,
-                     count, P, E, gvarea, farea);
+                     count, P, E, gvarea, farea, tol_log2);
   return hipGetLastError();
 }
 

@@ -163,6 +163,7 @@ __global__ __launch_bounds__(256) void k_batch_residual(
     const int p = batch_find_m<&BatchEntry::res_start>(E, count, it);
     const ms_problem &Q = P[p];
     const BatchEntry &e = E[p];
+    if (!e.refine) continue;   // converged in an earlier step
     const int n = (int)Q.n, nrhs = (int)Q.nrhs;
     __syncthreads();  // the previous item's reads of xs are done
     for (int t = threadIdx.x; t < n * nrhs; t += blockDim.x) {

@@ -16,10 +16,12 @@ event.
 The solver is the library's; this module only schedules.  Inputs follow the
 serving workload: A = Z diag(logspace(0, -log10 kappa, n)) Q (FP32; Q
 orthogonal), B = A x* + 1e-6 N(0,1), h uniform, s Rademacher,
-G ~ N(0, 1/k2), k = 2 n^2, k2 = 2 n.  Q is taken from a pool of Haar
-orthogonal matrices per n (the QR factor of an n x n Gaussian, drawn once on
-the host from a fixed seed and copied to the device before serving starts):
-a device QR per request would synchronise the device and serialise the loop.
+G ~ N(0, 1/k2), k = 2 n^2, k2 = 2 n.  Q is the product of two Householder
+reflections I - 2 u u^T with Gaussian directions u: an orthogonal matrix that
+mixes every column into every other, applied as two rank-one updates (O(d n)
+per request) so that generating an arriving request costs little next to
+solving it (a dense n x n factor costs a d x n x n product per request, and a
+device QR per request synchronises the device).
 """
 from __future__ import annotations
 
@@ -28,28 +30,9 @@ import time
 from collections import deque
 from dataclasses import dataclass, field
 
-import numpy as np
 import torch
 
 import paper_2508_14209_amd as ms
-
-Q_POOL = 8                 # orthogonal factors per n
-_q_pool: dict = {}         # (n, device) -> (Q_POOL, n, n) FP64 device tensor
-
-
-def orthogonal_pool(n: int, device) -> torch.Tensor:
-    """Q_POOL Haar orthogonal n x n matrices (QR of Gaussians, LAPACK on the
-    host, fixed seed) resident on ``device``; built on first use."""
-    key = (int(n), str(torch.device(device)))
-    if key not in _q_pool:
-        rng = np.random.default_rng(np.random.SeedSequence([0x51, int(n)]))
-        qs = np.empty((Q_POOL, n, n))
-        for i in range(Q_POOL):
-            q, r = np.linalg.qr(rng.standard_normal((n, n)))
-            qs[i] = q * np.sign(np.diag(r))[None, :]    # Haar: fix the column signs
-        _q_pool[key] = torch.from_numpy(qs).to(device)
-    return _q_pool[key]
-
 
 @dataclass
 class Request:
@@ -100,14 +83,15 @@ def generate(req: Request, device, g_dtype: str = "f32", a_dtype: str = "f32") -
     g.manual_seed(int(req.seed))
     d, n, nrhs, k, k2 = req.d, req.n, req.nrhs, req.k, req.k2
     scales = torch.logspace(0.0, -math.log10(req.kappa), n, device=device, dtype=torch.float64)
-    # A = Z diag(scales) Q: Z N(0,1), Q orthogonal (QR of an n x n Gaussian),
-    # the n x n factor formed in FP64, the product in FP32; condition ~ kappa
-    q = orthogonal_pool(n, device)[int(req.seed) % Q_POOL]
-    M = (scales[:, None] * q).to(torch.float32)
-    Z = torch.randn((d, n), generator=g, device=device, dtype=torch.float32)
+    # A = Z diag(scales) Q: Z N(0,1) drawn column by column, Q = H(u1) H(u2)
+    # with H(u) = I - 2 u u^T, |u| = 1, u Gaussian; A H(u) = A - 2 (A u) u^T
     A = ms.empty_colmajor(d, n, torch.float32, device)
-    A.copy_(Z @ M)
-    del Z
+    A.copy_(torch.randn((n, d), generator=g, device=device, dtype=torch.float32).t())
+    A.mul_(scales.to(torch.float32)[None, :])
+    for _ in range(2):
+        u = torch.randn(n, generator=g, device=device, dtype=torch.float64)
+        u = (u / u.norm()).to(torch.float32)
+        A.addr_(A @ u, u, alpha=-2.0)
     xs = torch.randn((n, nrhs), generator=g, device=device, dtype=torch.float32)
     B = ms.empty_colmajor(d, nrhs, torch.float32, device)
     B.copy_(A @ xs)
@@ -174,7 +158,8 @@ class Server:
                  streams: int = 4, g_dtype: str = "f32", rows_log2: int = 0,
                  kchunk_log2: int = 0, refine_steps: int = 0, tuned: bool = False,
                  a_dtype: str = "f32", single: bool = False, device="cuda",
-                 persistent: bool = False, graphs: bool = True, max_shape=None):
+                 persistent: bool = False, graphs: bool = True, max_shape=None,
+                 deterministic: bool = False):
         self.device = torch.device(device)
         self.admission = Admission(hbm_budget, max_inflight)
         self.max_batch = max_batch
@@ -190,6 +175,10 @@ class Server:
         # stream can send; a batch of fewer requests is padded with a 1-row
         # placeholder problem, so every call has the runner's count and its
         # launch sequence is captured once in a graph and replayed
+        # deterministic: the batched CountSketch folds each bucket in row
+        # order and the Gaussian stage's K split is fixed (no per-batch
+        # tuning), so a request's solution does not depend on its batch
+        self.deterministic = deterministic
         self.persistent = persistent and not single
         self.graphs = graphs
         self.max_shape = max_shape or (1 << 20, 128, 8)
@@ -265,12 +254,13 @@ class Server:
                     ev.record(st)
             else:
                 rl, kl = self.rows_log2, self.kchunk_log2
-                if self.tuned and not (rl or kl):
+                if self.tuned and not (rl or kl) and not self.deterministic:
                     from paper_2508_14209_amd import autotune
                     rl, kl = autotune.batch_params(probs, self.device)
                 with torch.cuda.stream(st):
                     runner = ms.BatchRunner(probs, rows_log2=rl, kchunk_log2=kl,
-                                            refine_steps=self.refine_steps)
+                                            refine_steps=self.refine_steps,
+                                            deterministic=self.deterministic)
                     runner.launch(st)
                     ev = torch.cuda.Event()
                     ev.record(st)
@@ -308,13 +298,14 @@ class Server:
         r = self.runners.get(si)
         if r is None:
             rl, kl = self.rows_log2, self.kchunk_log2
-            if self.tuned and not (rl or kl):
+            if self.tuned and not (rl or kl) and not self.deterministic:
                 from paper_2508_14209_amd import autotune
                 rl, kl = autotune.batch_params(probs, self.device)
             padded = probs + [self._pad_problem()] * (self.max_batch - len(probs))
             with torch.cuda.stream(st):
                 r = ms.BatchRunner(padded, capacity=self._capacity(), rows_log2=rl,
-                                   kchunk_log2=kl, refine_steps=self.refine_steps)
+                                   kchunk_log2=kl, refine_steps=self.refine_steps,
+                                   deterministic=self.deterministic)
             if self.graphs:
                 with torch.cuda.stream(st):
                     r.capture()
@@ -372,10 +363,6 @@ class Server:
     def run(self, requests, keep_tensors: bool = False):
         """Open loop: request r arrives at r.arrival seconds after the start."""
         pending = deque(sorted(requests, key=lambda r: r.arrival))
-        # the orthogonal factors of the input generator, before the clock starts
-        for n in sorted({r.n for r in requests}):
-            orthogonal_pool(n, self.device)
-        torch.cuda.synchronize(self.device)
         self.t0 = time.perf_counter()
         while pending or not self.idle():
             t = self.now()

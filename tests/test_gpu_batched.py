@@ -256,3 +256,91 @@ def test_batched_refinement_graph_replay(ms, orc):
             assert st == ms.MS_OK, (rep, st, per)
             for (host, dev), Xe in zip(which, eager[name]):
                 assert rel(to_host(dev["X"]), Xe) <= 1e-6, (rep, name)
+
+
+# ------------------------------------------------------------------ deterministic mode
+@pytest.mark.parametrize("refine", [0, 1])
+def test_batched_deterministic_alone_vs_mix_bit_identical(ms, orc, refine):
+    # the deterministic batched CountSketch folds every bucket in row order,
+    # and every other stage of a problem depends on that problem alone: its X
+    # is the same bit for bit in any batch (here: the whole mix, the mix
+    # reversed, and a batch of its own)
+    specs = [(70001, 8, 3, 1, "bf16"), (4097, 16, 1, 2, "bf16"), (123457, 32, 4, 3, "bf16"),
+             (30000, 8, 2, 4, "bf16"), (65536, 64, 1, 5, "bf16"), (9000, 16, 8, 6, "bf16")]
+    hosts, devs = [], []
+    for d, n, nrhs, seed, gd in specs:
+        hst, dv = make_problem(ms, d, n, nrhs, seed=seed + 40, dtype=np.float32, gd=gd)
+        hosts.append(hst)
+        devs.append(dv)
+    print("deterministic batch refine=%d" % refine, flush=True)
+    ms.sketch_lstsq_batched(devs, refine_steps=refine, deterministic=True)
+    torch.cuda.synchronize()
+    X_mix = [to_host(p["X"]).copy() for p in devs]
+    for p in devs:
+        p["X"].fill_(np.nan)
+    ms.sketch_lstsq_batched(devs[::-1], refine_steps=refine, deterministic=True)
+    torch.cuda.synchronize()
+    X_rev = [to_host(p["X"]).copy() for p in devs]
+    for i, p in enumerate(devs):
+        p["X"].fill_(np.nan)
+        r = ms.sketch_lstsq_batched([p], refine_steps=refine, deterministic=True)
+        assert r.status()[0] == ms.MS_OK
+        torch.cuda.synchronize()
+        Xa = to_host(p["X"])
+        assert np.array_equal(Xa, X_mix[i]) and np.array_equal(Xa, X_rev[i]), i
+    # and the solutions are the problems' sketch-and-solve solutions: the
+    # FP32 sketch is the oracle's sequential FP32 fold exactly, the BF16
+    # stage takes it as three exact terms (FP32 accumulation): against the
+    # oracle's FP32-sketch path with FP64 Gaussian stage, 1e-5 at refine 0
+    # (well-conditioned N(0,1) data); with a step, against FP64
+    # sketch-and-solve of the promoted data at 1e-5
+    for i, hst in enumerate(hosts):
+        if refine == 0:
+            Xr, _, _ = orc.sketch_lstsq(hst["A"], hst["B"], hst["h"], hst["s"],
+                                        hst["G"].astype(np.float64), hst["k"])
+        else:
+            Xr, _, _ = orc.sketch_lstsq(hst["A"].astype(np.float64), hst["B"].astype(np.float64),
+                                        hst["h"], hst["s"], hst["G"].astype(np.float64), hst["k"])
+        assert rel(X_mix[i], Xr) <= 1e-5, (i, rel(X_mix[i], Xr))
+
+
+def test_batched_deterministic_fp64_matches_oracle(ms, orc):
+    # FP64 data: the sorted fold is the oracle's FP64 fold bit for bit; the
+    # FP64 Gaussian stage (K split in fixed chunks, partials summed in order)
+    # and QR keep the FP64 bar
+    hst, dv = make_problem(ms, 50001, 16, 2, seed=77)
+    hst2, dv2 = make_problem(ms, 3000, 8, 1, seed=78)
+    ms.sketch_lstsq_batched([dv, dv2], deterministic=True)
+    torch.cuda.synchronize()
+    for h_, d_ in ((hst, dv), (hst2, dv2)):
+        Xr, _, _ = orc.sketch_lstsq(h_["A"], h_["B"], h_["h"], h_["s"], h_["G"], h_["k"])
+        assert rel(to_host(d_["X"]), Xr) <= 1e-12
+
+
+def test_batched_refinement_early_stop(ms, orc):
+    # refine_tol_log2 = x: a problem stops refining once a step's correction
+    # is at most 2^-x of its X.  x = 1 stops every problem after its first
+    # step (the first correction is far below half of X): the result is that
+    # of one step, bit for bit (deterministic mode, so that the two runs see
+    # the same arithmetic).  x = 60 stops none: the result is that of all
+    # steps, bit for bit.
+    probs = []
+    for i, (d, n, nrhs) in enumerate([(40001, 8, 2), (70000, 16, 1), (9000, 32, 4)]):
+        _, dv = make_problem(ms, d, n, nrhs, seed=90 + i, dtype=np.float32, gd="bf16")
+        probs.append(dv)
+
+    def run(steps, tol):
+        for p in probs:
+            p["X"].fill_(np.nan)
+        r = ms.sketch_lstsq_batched(probs, refine_steps=steps, deterministic=True,
+                                    refine_tol_log2=tol)
+        assert r.status()[0] == ms.MS_OK
+        torch.cuda.synchronize()
+        return [to_host(p["X"]).copy() for p in probs]
+
+    one, three = run(1, 0), run(3, 0)
+    stop1, stop60 = run(3, 1), run(3, 60)
+    for a, b in zip(one, stop1):
+        assert np.array_equal(a, b)
+    for a, b in zip(three, stop60):
+        assert np.array_equal(a, b)

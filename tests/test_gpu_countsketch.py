@@ -125,24 +125,28 @@ def test_countsketch_bucket_tiles(ms, orc, dtype, k):
     assert rel(to_host(Y), orc.countsketch(A, h, s, k)) <= (1e-12 if dtype == np.float64 else 1e-5)
 
 
-@pytest.mark.parametrize("d,n,k,dtype", [(300001, 20, 65536, np.float32),
-                                         (200000, 32, 32768, np.float64),
-                                         (1000, 8, 131072, np.float32),
-                                         (8192 * 3 + 5, 3, 40000, np.float64),
-                                         (50000, 2, 20000, np.float32),
-                                         (8192, 1, 16385, np.float64)])
-def test_countsketch_tiled_plan(ms, orc, d, n, k, dtype):
-    # more buckets than one workgroup's LDS holds (k > 16384): the rows of
-    # each 8192-row block are grouped by bucket tile first, and each tile's
-    # workgroups visit only their rows.  Ragged shapes: a partial last block,
-    # one block only, bucket counts that are not powers of two, tiles of
-    # unequal length.  The workspace holds the plan (4 bytes per row, block
-    # padded) besides the packed codes.
+@pytest.mark.parametrize("d,n,k,dtype,tiled", [(300001, 20, 65536, np.float32, True),
+                                               (1000, 8, 131072, np.float32, True),
+                                               (8192 * 3 + 5, 3, 70001, np.float64, True),
+                                               (50000, 2, 41000, np.float32, True),
+                                               (8192, 1, 61441, np.float64, True),
+                                               (200000, 32, 32768, np.float64, False),
+                                               (8192 * 3 + 5, 3, 40000, np.float64, False),
+                                               (8192, 1, 16385, np.float64, False)])
+def test_countsketch_tiled_plan(ms, orc, d, n, k, dtype, tiled):
+    # more buckets than one workgroup's LDS holds (k > 16384).  From four
+    # bucket tiles up (k > 40960) the rows of each 8192-row block are grouped
+    # by bucket tile first and each tile's workgroups visit only their rows;
+    # with two tiles every tile's workgroups stream all rows (untiled).
+    # Ragged shapes: a partial last block, one block only, bucket counts that
+    # are not powers of two, tiles of unequal length.  With the plan the
+    # workspace holds it (4 bytes per row, block padded) besides the codes.
     a_dt = ms.MS_F64 if dtype == np.float64 else ms.MS_F32
     nblk = (d + 8191) // 8192
-    assert (ms.workspace_size("countsketch", d=d, n=n, k=k, a_dtype=a_dt, mode="lds")
-            - ms.workspace_size("countsketch", d=d, n=n, k=k, a_dtype=a_dt, mode="atomic")
-            >= nblk * 8192 * 4)
+    extra = (ms.workspace_size("countsketch", d=d, n=n, k=k, a_dtype=a_dt, mode="lds")
+             - ms.workspace_size("countsketch", d=d, n=n, k=k, a_dtype=a_dt, mode="atomic"))
+    if tiled:
+        assert extra >= nblk * 8192 * 4
     print("countsketch tiled d=%d n=%d k=%d %s" % (d, n, k, np.dtype(dtype)), flush=True)
     A, h, s = _inputs(d, n, k, seed=9, dtype=dtype)
     Y, ws = ms.countsketch_apply(to_dev(A), to_dev(h), to_dev(s), k, mode="lds")

@@ -163,3 +163,30 @@ def test_serving_default_stream_mixed_precision(ms, orc):
     rhos = np.array(rhos)
     print("fraction rho <= 2: %.3f, max rho %.3f (FP64 sketch-and-solve: %.3f, %.3f)"
           % (np.mean(rhos <= 2), rhos.max(), np.mean(np.array(rhos64) <= 2), max(rhos64)))
+
+
+def test_serving_deterministic_alone_equals_mix_bit_for_bit(ms):
+    # deterministic serving: persistent runners replaying captured graphs,
+    # BF16 Gaussian stage, one refinement step; each request's X equals, bit
+    # for bit, the X of the same request solved in a batch of its own
+    from paper_2508_14209_amd import serve
+    reqs = serve.make_requests(40, 4000.0, seed=21, d_lo=1 << 12, d_hi=1 << 16,
+                               ns=(8, 16, 32, 64), nrhs_max=4, kappa_lo=1e1, kappa_hi=1e5)
+    for r in reqs:
+        r.extra["kept"] = True
+    srv = serve.Server(hbm_budget=8 << 30, max_inflight=32, max_batch=8, streams=3,
+                       g_dtype="bf16", refine_steps=1, persistent=True, graphs=True,
+                       deterministic=True, max_shape=(1 << 16, 64, 4))
+    srv.warm_runners(reqs[:8])
+    done = srv.run(reqs, keep_tensors=True)
+    assert len(done) == len(reqs) and all(r.status == ms.MS_OK for r in done)
+    assert srv.nbatches > 1
+    for r in sorted(done, key=lambda q: q.id):
+        T = r.tensors
+        Xmix = to_host(T["X"]).copy()
+        alone = dict(T)
+        alone["X"] = ms.empty_colmajor(r.n, r.nrhs, torch.float64, "cuda")
+        run = ms.sketch_lstsq_batched([alone], refine_steps=1, deterministic=True)
+        assert run.status()[0] == ms.MS_OK
+        torch.cuda.synchronize()
+        assert np.array_equal(to_host(alone["X"]), Xmix), r.id
