@@ -863,8 +863,9 @@ def main():
         return
     if args.only == "countsketch_sorted":
         # the deterministic CountSketch of [A | b] (4,194,304 x 65 FP64, k =
-        # 8192): blocked stable plan, then the fold of each bucket in
-        # ascending row order; and the plan alone (ms_bucket_plan)
+        # 8192): per-block sorted keys, then the block-ordered fold (each
+        # bucket summed in ascending row order); and the bucket plan alone
+        # (ms_bucket_plan)
         d_, nc_, k_ = 4194304, 65, 8192
         gen = torch.Generator(device=dev)
         gen.manual_seed(args.seed)
@@ -879,7 +880,7 @@ def main():
             ms.bucket_plan(hx, k_, ws=pws)
         ms.check_status(sws)
         ms.check_status(pws)
-        print(json.dumps({"only": args.only, "kernels": "k_pb_* (plan), k_cs_sorted_cols (fold)",
+        print(json.dumps({"only": args.only, "kernels": "k_bf_keys + k_bf_fold (sketch), k_pb_* (plan)",
                           "launches": args.steps + 1,
                           "bytes_per_launch": {"fold": d_ * nc_ * 8 + d_ * 4 + k_ * nc_ * 8,
                                                "plan": d_ * 4 + d_ * 4 + 2 * k_ * 4}}))

@@ -512,6 +512,32 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
 ms_status ms_batch_status(const void *ws, int count, int32_t *status_host,
                           void *stream);
 
+/*
+ * Synthetic least-squares request generated on the device from a seed: a
+ * matrix of prescribed condition number, as in the experiments of Sec. 6.3
+ * (there kappa(A) = 1e2, or swept), for the serving workload, whose inputs
+ * arrive faster than a host could upload them.  Not a step of the method.
+ *   A (d x n FP32, column-major, lda >= d) = Z diag(D) Q: Z with independent
+ *     N(0,1) entries, D_j = kappa^(-j/(n-1)) (D_0 = 1), Q = (I - 2 u1 u1^T)
+ *     (I - 2 u2 u2^T) with unit Gaussian directions u1, u2;
+ *   xstar (n x nrhs FP32, ld n) N(0,1);
+ *   B (d x nrhs FP32, ldb >= d) = A xstar + noise * N(0,1) (needs A);
+ *   h (d int32) uniform in [0, k), s (d int8) uniform in {-1, +1} (both or
+ *     neither);
+ *   G (k2 x k, column-major, ld k2; g_dtype MS_F32, MS_BF16 (rounded to
+ *     nearest even) or MS_F64 (exact)) = N(0,1) / sqrt(k2) drawn in FP32.
+ * Device pointers, written on `stream`; any output may be NULL (not made).
+ * Limits: d >= 1, 1 <= n <= 128, 1 <= nrhs <= 8, 1 <= k, k2 <= 2^31 - 2,
+ * kappa >= 1 and finite (else MS_ERR_ARG).  Each value depends only on the
+ * seed and its position (counter-based SplitMix64 words, Box-Muller normals),
+ * so a seed gives the same request on any device or stream.
+ */
+ms_status ms_gen_lstsq_request(uint64_t seed, int64_t d, int64_t n, int64_t nrhs,
+                               double kappa, double noise, int64_t k, int64_t k2,
+                               ms_dtype g_dtype, float *A, int64_t lda, float *B,
+                               int64_t ldb, float *xstar, int32_t *h, int8_t *s,
+                               void *G, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,6 +28,7 @@ __all__ = [
     "normal_equations_lstsq", "countsketch_hashed", "hash_sketch", "srht_apply",
     "count_srht_lstsq", "MsProblem",
     "batch_workspace_size", "sketch_lstsq_batched", "batch_status", "BatchRunner",
+    "gen_lstsq_request",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -104,6 +105,8 @@ _SIGS = {
     "ms_batch_workspace_size": ([_i32, _p, _i32, _i32, _p], _sz),
     "sketch_lstsq_batched": ([_i32, _p, _p, _i32, _i32, _p, _p, _sz, _p], _i32),
     "ms_batch_status": ([_p, _i32, _p, _p], _i32),
+    "ms_gen_lstsq_request": ([ctypes.c_uint64, _i64, _i64, _i64, ctypes.c_double, ctypes.c_double,
+                              _i64, _i64, _i32, _p, _i64, _p, _i64, _p, _p, _p, _p, _p], _i32),
 }
 for _name, (_args, _ret) in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -301,6 +304,38 @@ def countsketch_hashed(A: torch.Tensor, k: int, seed: int, Y: torch.Tensor | Non
     _ok(_lib.countsketch_hashed(d, n, k, int(seed) & (2**64 - 1), a_dt, Ap, lda, Yp, ldy,
                                 ctypes.byref(o), wp, have, _stream(stream)), "countsketch_hashed")
     return Y, ws
+
+
+def gen_lstsq_request(seed: int, d: int, n: int, nrhs: int, kappa: float, k: int, k2: int,
+                      g_dtype=MS_F32, noise: float = 1e-6, device="cuda", stream=None,
+                      want=("A", "B", "xstar", "h", "s", "G")) -> dict:
+    """A seeded synthetic request generated on the device by
+    ms_gen_lstsq_request: A = Z diag(kappa^(-j/(n-1))) Q (FP32, column-major),
+    B = A xstar + noise N(0,1), h, s, G (k2 x k, column-major, dtype g_dtype)
+    = N(0,1)/sqrt(k2).  Only the parts named in `want` are made."""
+    out = {}
+    if "A" in want or "B" in want:
+        out["A"] = empty_colmajor(d, n, torch.float32, device)
+    if "B" in want:
+        out["B"] = empty_colmajor(d, nrhs, torch.float32, device)
+    if "xstar" in want:
+        out["xstar"] = empty_colmajor(n, nrhs, torch.float32, device)
+    if "h" in want or "s" in want:
+        out["h"] = torch.empty(d, dtype=torch.int32, device=device)
+        out["s"] = torch.empty(d, dtype=torch.int8, device=device)
+    if "G" in want:
+        gt = {MS_F32: torch.float32, MS_BF16: torch.bfloat16, MS_F64: torch.float64}[g_dtype]
+        out["G"] = empty_colmajor(k2, k, gt, device)
+
+    def ptr(name):
+        t = out.get(name)
+        return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+    _ok(_lib.ms_gen_lstsq_request(int(seed) & (2**64 - 1), d, n, nrhs, float(kappa), float(noise),
+                                  k, k2, int(g_dtype), ptr("A"), d, ptr("B"), d, ptr("xstar"),
+                                  ptr("h"), ptr("s"), ptr("G"), _stream(stream)),
+        "ms_gen_lstsq_request")
+    return out
 
 
 def hash_sketch(d: int, k: int, seed: int, device="cuda", stream=None):

@@ -18,10 +18,10 @@ serving workload: A = Z diag(logspace(0, -log10 kappa, n)) Q (FP32; Q
 orthogonal), B = A x* + 1e-6 N(0,1), h uniform, s Rademacher,
 G ~ N(0, 1/k2), k = 2 n^2, k2 = 2 n.  Q is the product of two Householder
 reflections I - 2 u u^T with Gaussian directions u: an orthogonal matrix that
-mixes every column into every other, applied as two rank-one updates (O(d n)
-per request) so that generating an arriving request costs little next to
-solving it (a dense n x n factor costs a d x n x n product per request, and a
-device QR per request synchronises the device).
+mixes every column into every other.  The library's device generator makes a
+request in one write pass over each input (a row of A is formed in registers
+and both reflections applied there), so that generating an arriving request
+costs little next to solving it.
 """
 from __future__ import annotations
 
@@ -76,38 +76,15 @@ def footprint_bytes(d: int, n: int, nrhs: int, k: int, k2: int, w: int = 4,
 
 
 def generate(req: Request, device, g_dtype: str = "f32", a_dtype: str = "f32") -> dict:
-    """Seeded synthetic inputs of one request, on the current stream.  A and B
-    are drawn in FP32; a_dtype "f64" promotes them exactly (and g_dtype "f64"
-    promotes G) for the plain FP64 path."""
-    g = torch.Generator(device=device)
-    g.manual_seed(int(req.seed))
+    """Seeded synthetic inputs of one request, on the current stream, made by
+    the library's device generator (ms_gen_lstsq_request: A = Z diag(D) Q with
+    Q two Householder reflections, B = A x* + 1e-6 N(0,1), h, s, G in one
+    write pass each).  A and B are FP32; a_dtype "f64" promotes them exactly
+    for the plain FP64 path."""
     d, n, nrhs, k, k2 = req.d, req.n, req.nrhs, req.k, req.k2
-    scales = torch.logspace(0.0, -math.log10(req.kappa), n, device=device, dtype=torch.float64)
-    # A = Z diag(scales) Q: Z N(0,1) drawn column by column, Q = H(u1) H(u2)
-    # with H(u) = I - 2 u u^T, |u| = 1, u Gaussian; A H(u) = A - 2 (A u) u^T
-    A = ms.empty_colmajor(d, n, torch.float32, device)
-    A.copy_(torch.randn((n, d), generator=g, device=device, dtype=torch.float32).t())
-    A.mul_(scales.to(torch.float32)[None, :])
-    for _ in range(2):
-        u = torch.randn(n, generator=g, device=device, dtype=torch.float64)
-        u = (u / u.norm()).to(torch.float32)
-        A.addr_(A @ u, u, alpha=-2.0)
-    xs = torch.randn((n, nrhs), generator=g, device=device, dtype=torch.float32)
-    B = ms.empty_colmajor(d, nrhs, torch.float32, device)
-    B.copy_(A @ xs)
-    B.add_(torch.randn((nrhs, d), generator=g, device=device, dtype=torch.float32).t(), alpha=1e-6)
-    h = torch.randint(0, k, (d,), generator=g, device=device, dtype=torch.int32)
-    s = (torch.randint(0, 2, (d,), generator=g, device=device, dtype=torch.int8) * 2 - 1)
-    Gm = torch.randn((k, k2), generator=g, device=device, dtype=torch.float32).t()
-    Gm.mul_(1.0 / math.sqrt(k2))
-    if g_dtype == "bf16":
-        Gb = torch.empty((k, k2), device=device, dtype=torch.bfloat16).t()
-        Gb.copy_(Gm)
-        Gm = Gb
-    elif g_dtype == "f64":
-        G64 = ms.empty_colmajor(k2, k, torch.float64, device)
-        G64.copy_(Gm)
-        Gm = G64
+    gdt = {"f32": ms.MS_F32, "bf16": ms.MS_BF16, "f64": ms.MS_F64}[g_dtype]
+    t = ms.gen_lstsq_request(req.seed, d, n, nrhs, req.kappa, k, k2, g_dtype=gdt, device=device)
+    A, B = t["A"], t["B"]
     if a_dtype == "f64":
         A64 = ms.empty_colmajor(d, n, torch.float64, device)
         A64.copy_(A)
@@ -115,7 +92,7 @@ def generate(req: Request, device, g_dtype: str = "f32", a_dtype: str = "f32") -
         B64.copy_(B)
         A, B = A64, B64
     X = ms.empty_colmajor(n, nrhs, torch.float64, device)
-    return dict(A=A, B=B, h=h, s=s.to(torch.int8), G=Gm, X=X, k=k, xstar=xs)
+    return dict(A=A, B=B, h=t["h"], s=t["s"], G=t["G"], X=X, k=k, xstar=t["xstar"])
 
 
 class Admission:

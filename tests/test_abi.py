@@ -203,3 +203,29 @@ def test_later_rows_reject_invalid_arguments_on_host(ms):
                                 ctypes.byref(o), ws, big, None) == ms.MS_ERR_ARG
     assert lib.count_srht_lstsq(100, 8, 1, 128, 16, 0, P, 100, P, 100, P, P, P, P, P, 8,
                                 ctypes.byref(refine), ws, big, None) == ms.MS_ERR_ARG
+
+
+def test_request_generator_rejects_invalid_arguments_on_host(ms):
+    lib = ms._lib
+    P = ctypes.c_void_p(0x2000)  # never dereferenced: every call below fails validation first
+    F32, BF16, F16 = ms.MS_F32, ms.MS_BF16, ms.MS_F16
+
+    def gen(d=100, n=8, nrhs=2, kappa=10.0, k=128, k2=16, gdt=F32, A=P, lda=100, B=P, ldb=100,
+            h=P, s=P, G=P):
+        return lib.ms_gen_lstsq_request(1, d, n, nrhs, kappa, 1e-6, k, k2, gdt, A, lda, B, ldb, P,
+                                        h, s, G, None)
+    assert gen(n=0) == ms.MS_ERR_ARG
+    assert gen(n=129) == ms.MS_ERR_ARG            # rows are formed in registers: n <= 128
+    assert gen(nrhs=0) == ms.MS_ERR_ARG
+    assert gen(nrhs=9) == ms.MS_ERR_ARG
+    assert gen(d=0) == ms.MS_ERR_ARG
+    assert gen(kappa=0.5) == ms.MS_ERR_ARG
+    assert gen(kappa=float("inf")) == ms.MS_ERR_ARG
+    assert gen(kappa=float("nan")) == ms.MS_ERR_ARG
+    assert gen(k=0) == ms.MS_ERR_ARG
+    assert gen(k2=(1 << 31) - 1) == ms.MS_ERR_ARG
+    assert gen(lda=99) == ms.MS_ERR_ARG
+    assert gen(ldb=99) == ms.MS_ERR_ARG
+    assert gen(A=None) == ms.MS_ERR_ARG            # B is formed from A's rows
+    assert gen(h=None) == ms.MS_ERR_ARG            # h and s come together
+    assert gen(gdt=F16) == ms.MS_ERR_ARG
