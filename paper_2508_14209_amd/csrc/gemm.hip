@@ -416,6 +416,319 @@ __device__ __forceinline__ void gemm_tile_lds_h(int M, int N, const unsigned sho
     }
 }
 
+// ------------------------------------------------------------ wide 16-bit tiles
+// The BF16 / FP16 stage with 256 x 144 output tiles: four waves (one per
+// SIMD), wave w owning rows 64 w .. 64 w + 63 of the tile and all 144 columns
+// (4 x 9 blocks of 16 x 16, 144 accumulator registers).  K advances in stages
+// of 32: per stage the workgroup stages G's 256 x 32 tile (loaded as 16-byte
+// runs of 8 rows at one k, written to LDS k-contiguous per row) and Y's
+// 32 x 144 tile (FP32, split into YT 16-bit terms on the way in); two stages
+// of global loads are in flight while a third is on the matrix cores.  With
+// 64 x 64 tiles every element of G was fetched by ceil(N/64) workgroups and
+// every element of Y by ceil(M/64); here by ceil(N/144) and ceil(M/256)
+// (once each for M <= 256 and N <= 144: every sketch of the serving
+// workload).  The k steps of a K chunk run in ascending order and the terms
+// of a step small first, as in the 64 x 64 tile.
+//
+// LDS: G's tile row R starts at element 40 R + 32 (R / 8): rows padded to 40
+// elements (fragment reads of 16 lanes hit distinct banks), and each 8-row
+// group shifted by 16 banks so that the transposing 4-byte writes of a wave
+// (16 k pairs x 4 row groups) cost two passes, not four.
+constexpr int kWTM = 256, kWTN = 144, kWKS = 32, kWPad = 40, kWThreads = 256;
+constexpr int kWNB = kWTN / 16;                       // column blocks per tile
+constexpr int kWAElems = kWTM * kWPad + (kWTM / 8) * 32;  // G tile incl. group shifts
+
+__device__ __forceinline__ int wide_arow(int r) { return r * kWPad + (r >> 3) * 32; }
+
+template <int YT>
+constexpr int wide_stage_elems() {
+  return kWAElems + YT * kWTN * kWPad;
+}
+template <int YT>
+constexpr int wide_lds_bytes() {
+  return 2 * wide_stage_elems<YT>() * 2;
+}
+
+// One stage's global loads held in registers: for G tasks v = 0, 1 the rows
+// 8 g .. 8 g + 7 at k 2 kp and 2 kp + 1; Y columns and k octets of up to
+// three tasks.
+struct WideRegs {
+  v8u16 g[2][2];
+  float y[3][8];
+};
+
+// FAST: G's leading dimension a multiple of 8 and G 16-byte aligned, M a
+// multiple of 8 (each 8-row group of a tile wholly inside or outside), Y's
+// leading dimension a multiple of 4 and Y 16-byte aligned, K a multiple of
+// 32 (every stage wholly inside K).  Then every load is a 16-byte load from a
+// running pointer with no per-load condition: a row group or column outside
+// the tile reads row 0 or column n0 instead (its products land in rows or
+// columns that are never stored), and the fetches past the chunk's last stage
+// re-read that stage (their stages are never computed).  Else every element
+// is loaded alone, guarded, zero outside.
+template <int DT, int YT, bool FAST>
+__device__ __forceinline__ void gemm_tile_wide(int M, int N, const unsigned short *__restrict__ G,
+                                               int64_t ldg, const float *__restrict__ Y,
+                                               int64_t ldy, const float *__restrict__ cs,
+                                               float *__restrict__ P, int64_t kb, int64_t ke,
+                                               int64_t kstride, int m0, int n0,
+                                               unsigned short *lds) {
+  using H = Half16<DT>;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // G task v: k pair kp (fastest), row group g
+  const int kp = tid & 15;
+  // Y task u (tid + 256 u): column / 4, k octet % 4; the third task for the
+  // first wave only (a wave-uniform condition)
+  const int ny = wave == 0 ? 3 : 2;
+  const int64_t klen = ke - kb;
+  float ysc[3] = {1.0f, 1.0f, 1.0f};
+  if (DT == DT_F16) {
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int c = (tid + u * kWThreads) >> 2;
+      if (u < ny && n0 + c < N) ysc[u] = cs[2 * (n0 + c)];
+    }
+  }
+  const unsigned short *gp[2];
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    const int rb = m0 + 8 * ((tid + v * kWThreads) >> 4);
+    gp[v] = G + (rb < M ? rb : 0) + (kb + 2 * kp) * ldg;
+  }
+  const int64_t gstep = kstride * ldg;
+  const float *yp[3];
+  int ykq[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int t = tid + u * kWThreads;
+    const int c = t >> 2;
+    const bool cv = t < kWTN * 4 && n0 + c < N;
+    ykq[u] = 8 * (t & 3);
+    yp[u] = Y + kb + ykq[u] + (int64_t)(cv ? n0 + c : n0) * ldy;
+  }
+  int64_t krel = 0;  // start of the next stage to fetch, relative to kb
+  auto fetch = [&](WideRegs &R) {
+    if constexpr (FAST) {
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        R.g[v][0] = gload(reinterpret_cast<const v8u16 *>(gp[v]));
+        R.g[v][1] = gload(reinterpret_cast<const v8u16 *>(gp[v] + ldg));
+      }
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        if (u >= ny) break;
+        const v4f a = gload(reinterpret_cast<const v4f *>(yp[u]));
+        const v4f b = gload(reinterpret_cast<const v4f *>(yp[u] + 4));
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          R.y[u][e] = a[e];
+          R.y[u][4 + e] = b[e];
+        }
+      }
+      if (krel + kstride < klen) {  // the next stage exists (uniform)
+#pragma unroll
+        for (int v = 0; v < 2; ++v) gp[v] += gstep;
+#pragma unroll
+        for (int u = 0; u < 3; ++u) yp[u] += kstride;
+      }
+    } else {
+      const int64_t k0 = kb + krel;
+#pragma unroll
+      for (int v = 0; v < 2; ++v) {
+        const int rb = m0 + 8 * ((tid + v * kWThreads) >> 4);
+        const int64_t kc = k0 + 2 * kp;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          R.g[v][0][r] = (kc < ke && rb + r < M) ? gload(G + rb + r + kc * ldg) : (unsigned short)0;
+          R.g[v][1][r] = (kc + 1 < ke && rb + r < M) ? gload(G + rb + r + (kc + 1) * ldg)
+                                                     : (unsigned short)0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        if (u >= ny) break;
+        const int t = tid + u * kWThreads;
+        const int c = t >> 2;
+        const int64_t kq = k0 + ykq[u];
+        const bool cv = t < kWTN * 4 && n0 + c < N;
+        const float *q = Y + kq + (int64_t)(cv ? n0 + c : n0) * ldy;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) R.y[u][e] = (cv && kq + e < ke) ? gload(q + e) : 0.0f;
+      }
+    }
+    krel += kstride;
+  };
+  auto lstore = [&](const WideRegs &R, int buf) {
+    unsigned short *As = lds + buf * wide_stage_elems<YT>();
+    unsigned short *Bs = As + kWAElems;
+#pragma unroll
+    for (int v = 0; v < 2; ++v) {
+      // row r's word: its k = 2 kp value in the low half, k = 2 kp + 1 in the
+      // high half; one byte permute per word (rows 2i and 2i + 1 share the
+      // loaded words i)
+      const int g = (tid + v * kWThreads) >> 4;
+      const v4u32 w0 = __builtin_bit_cast(v4u32, R.g[v][0]);
+      const v4u32 w1 = __builtin_bit_cast(v4u32, R.g[v][1]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        *reinterpret_cast<uint32_t *>(&As[wide_arow(8 * g + 2 * i) + 2 * kp]) =
+            __builtin_amdgcn_perm(w1[i], w0[i], 0x05040100u);
+        *reinterpret_cast<uint32_t *>(&As[wide_arow(8 * g + 2 * i + 1) + 2 * kp]) =
+            __builtin_amdgcn_perm(w1[i], w0[i], 0x07060302u);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      if (u >= ny) break;
+      const int t = tid + u * kWThreads;
+      if (t >= kWTN * 4) break;
+      const int c = t >> 2, q8 = 8 * (t & 3);
+      v4u32 bt[YT];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        float y0 = R.y[u][2 * p], y1 = R.y[u][2 * p + 1];
+        if (DT == DT_F16) {
+          y0 *= ysc[u];
+          y1 *= ysc[u];
+        }
+#pragma unroll
+        for (int tt = 0; tt < YT; ++tt) {
+          const uint32_t w = H::pack2(y0, y1);
+          bt[tt][p] = w;
+          if (tt + 1 < YT) {
+            y0 -= H::lo_f32(w);
+            y1 -= H::hi_f32(w);
+          }
+        }
+      }
+#pragma unroll
+      for (int tt = 0; tt < YT; ++tt)
+        *reinterpret_cast<v4u32 *>(&Bs[(tt * kWTN + c) * kWPad + q8]) = bt[tt];
+    }
+  };
+  // the wave's rows and the tile's block count are wave-uniform
+  const int wrow = 64 * wave;
+  const int nrow = min(4, (M - m0 - wrow + 15) / 16);  // 16-row blocks of the wave with rows
+  const int nb = __builtin_amdgcn_readfirstlane(min(kWNB, (N - n0 + 15) / 16));
+  v4f acc[4][kWNB];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < kWNB; ++j) acc[i][j] = v4f{};
+  auto compute = [&](int buf) {
+    if (nrow <= 0) return;
+    const unsigned short *As = lds + buf * wide_stage_elems<YT>();
+    const unsigned short *Bs = As + kWAElems;
+    typename H::V8 a[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      a[i] = *reinterpret_cast<const typename H::V8 *>(&As[wide_arow(wrow + 16 * i + li) + lk * 8]);
+    // the stage's YT x 9 fragments of Y (small terms first, blocks in
+    // order) in chunks of three: the next chunk's LDS reads are issued before
+    // the current chunk's twelve products, and scheduling barriers keep that
+    // order (unpinned, the compiler hoists every read and runs out of
+    // registers)
+    constexpr int kNF = YT * kWNB, kCH = 3;
+    typename H::V8 bq[2][kCH];
+    auto rd = [&](int f, typename H::V8 &dst) {
+      const int tt = YT - 1 - f / kWNB, j = f % kWNB;
+      dst = *reinterpret_cast<const typename H::V8 *>(
+          &Bs[(tt * kWTN + 16 * j + li) * kWPad + lk * 8]);
+    };
+#pragma unroll
+    for (int e = 0; e < kCH; ++e) rd(e, bq[0][e]);
+#pragma unroll
+    for (int c = 0; c < kNF / kCH; ++c) {
+      if (c + 1 < kNF / kCH) {
+#pragma unroll
+        for (int e = 0; e < kCH; ++e) rd((c + 1) * kCH + e, bq[(c + 1) & 1][e]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int e = 0; e < kCH; ++e) {
+        const int j = (c * kCH + e) % kWNB;
+        if (j < nb) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[i][j] = H::mma(a[i], bq[c & 1][e], acc[i][j]);
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  // Stages in pairs with no data-dependent condition around the loads (so
+  // that the compiler keeps the younger stage's loads in flight across the
+  // older one's LDS store): the fetches past the last stage load in-range
+  // addresses, and a stage past the last is not computed.
+  // NS register sets: NS - 1 stages of loads in flight (three on the fast
+  // path, whose loads need few registers); stage s is in register set s % NS
+  // and, once stored, in LDS buffer s % 2.
+  constexpr int NS = FAST ? 4 : 2;
+  const int64_t nst = (klen + kstride - 1) / kstride, ngroups = (nst + NS - 1) / NS;
+  WideRegs R[NS];
+#pragma unroll
+  for (int i = 0; i < NS - 1; ++i) fetch(R[i]);
+  lstore(R[0], 0);
+  __syncthreads();
+  for (int64_t q = 0; q < ngroups; ++q) {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      fetch(R[(i + NS - 1) % NS]);           // stage q NS + i + NS - 1
+      if (q * NS + i < nst) compute(i & 1);  // stage q NS + i
+      lstore(R[(i + 1) % NS], (i + 1) & 1);  // stage q NS + i + 1
+      __syncthreads();
+    }
+  }
+  if (nrow <= 0) return;
+#pragma unroll
+  for (int j = 0; j < kWNB; ++j) {
+    const int col = n0 + 16 * j + li;
+    if (j >= nb || col >= N) continue;
+    const float back = DT == DT_F16 ? cs[2 * col + 1] : 1.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row0 = m0 + wrow + 16 * i + 4 * lk;
+      if (row0 >= M) continue;
+      float *dst = P + row0 + (int64_t)col * M;
+      v4f v = acc[i][j];
+      if (DT == DT_F16) v = v * back;
+      if ((M & 3) == 0 && row0 + 4 <= M) {
+        *reinterpret_cast<v4f *>(dst) = v;
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (row0 + r < M) dst[r] = v[r];
+      }
+    }
+  }
+}
+
+// Workgroup g runs on die g % xcds; the tiles of one K chunk go to one die.
+template <int DT, int YT, bool FAST>
+__global__ __launch_bounds__(kWThreads) void k_gemm_wide(int M, int N, int64_t K,
+                                                         const unsigned short *__restrict__ G,
+                                                         int64_t ldg, const float *__restrict__ Y,
+                                                         int64_t ldy, float *__restrict__ part,
+                                                         int64_t kchunk, int tiles_m, int tiles,
+                                                         int nsplit, int xcds,
+                                                         const float *__restrict__ cs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int g = blockIdx.x;
+  const int x = g % xcds, j = g / xcds;
+  const int split = x + xcds * (j / tiles);
+  if (split >= nsplit) return;
+  const int tile = j % tiles;
+  // contiguous K chunks (kchunk > 0) or, with kchunk = 0, K stages dealt
+  // out in turn: split s takes stages s, s + nsplit, s + 2 nsplit, ...
+  const int64_t kb = kchunk > 0 ? (int64_t)split * kchunk : (int64_t)split * kWKS;
+  const int64_t ke = kchunk > 0 ? min(K, kb + kchunk) : K;
+  const int64_t kstride = kchunk > 0 ? (int64_t)kWKS : (int64_t)kWKS * nsplit;
+  gemm_tile_wide<DT, YT, FAST>(M, N, G, ldg, Y, ldy, cs, part + (int64_t)split * M * N, kb, ke,
+                               kstride, (tile % tiles_m) * kWTM, (tile / tiles_m) * kWTN,
+                               reinterpret_cast<unsigned short *>(smem_raw));
+}
+
 // The tile of either kind: LDS-staged for BF16 and FP16, direct fragment
 // loads else.  YT: 16-bit terms of Y (1 or 3; the other dtypes ignore it).
 // cs: FP16's column scales (unused for the other dtypes).
@@ -619,12 +932,18 @@ GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K, ms_dtype g_dtype) {
   p.M = (int)M;
   p.N = (int)N;
   p.K = K;
-  p.tiles_m = (int)((M + 63) / 64);
-  p.tiles_n = (int)((N + 63) / 64);
-  const int64_t ks = (g_dtype == MS_BF16 || g_dtype == MS_F16) ? 32 : 4;
+  const bool h16 = g_dtype == MS_BF16 || g_dtype == MS_F16;
+  // 16-bit G: 256 x 144 tiles of 512 threads, about one workgroup per
+  // compute unit, at least 512 K values per workgroup (so the partials stay
+  // small next to the chunk of G and Y each workgroup reads); else 64 x 64
+  // tiles, ~1024 workgroups, at least 128 K values each
+  p.tiles_m = (int)(h16 ? (M + kWTM - 1) / kWTM : (M + 63) / 64);
+  p.tiles_n = (int)(h16 ? (N + kWTN - 1) / kWTN : (N + 63) / 64);
+  const int64_t ks = h16 ? kWKS : 4;
   const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n;
-  // aim for ~1024 workgroups but keep at least 128 K values per workgroup
-  int64_t ns = std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, (K + 127) / 128));
+  const int64_t target = h16 ? 256 : 1024, kmin = h16 ? 512 : 128;
+  int64_t ns = std::max<int64_t>(1, std::min<int64_t>((target + tiles - 1) / tiles,
+                                                      (K + kmin - 1) / kmin));
   ns = std::min<int64_t>(ns, 65535);
   int64_t kc = (K + ns - 1) / ns;
   kc = (kc + ks - 1) / ks * ks;
@@ -638,6 +957,34 @@ GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K, ms_dtype g_dtype) {
   if (g_dtype == MS_F16) p.partial_bytes = align_up(p.partial_bytes) + (size_t)N * 2 * sizeof(float);
   p.ybf16_bytes = 0;
   return p;
+}
+
+// The wide 16-bit kernel over a plan's tiles and K splits (dynamic LDS:
+// two stages of G's and Y's tiles).
+template <int DT, int YT>
+hipError_t launch_wide(const GemmPlan &p, const void *G, int64_t ldg, const void *Y, int64_t ldy,
+                       void *partials, const float *cs, hipStream_t st) {
+  const int xcds = dev_info().xcds;
+  const int tiles = p.tiles_m * p.tiles_n;
+  const dim3 grid((unsigned)((int64_t)xcds * tiles * ((p.nsplit + xcds - 1) / xcds)));
+  constexpr int lds = wide_lds_bytes<YT>();
+  const bool fast = (ldg & 7) == 0 && ((uintptr_t)G & 15) == 0 && (p.M & 7) == 0 &&
+                    (ldy & 3) == 0 && ((uintptr_t)Y & 15) == 0 && (p.K % kWKS) == 0;
+  const void *fn = fast ? (const void *)k_gemm_wide<DT, YT, true>
+                        : (const void *)k_gemm_wide<DT, YT, false>;
+  hipError_t e = allow_dynamic_lds(fn, lds);
+  if (e != hipSuccess) return e;
+  if (fast)
+    hipLaunchKernelGGL((k_gemm_wide<DT, YT, true>), grid, dim3(kWThreads), lds, st, p.M, p.N,
+                       p.K, static_cast<const unsigned short *>(G), ldg,
+                       static_cast<const float *>(Y), ldy, static_cast<float *>(partials),
+                       p.kchunk, p.tiles_m, tiles, p.nsplit, xcds, cs);
+  else
+    hipLaunchKernelGGL((k_gemm_wide<DT, YT, false>), grid, dim3(kWThreads), lds, st, p.M, p.N,
+                       p.K, static_cast<const unsigned short *>(G), ldg,
+                       static_cast<const float *>(Y), ldy, static_cast<float *>(partials),
+                       p.kchunk, p.tiles_m, tiles, p.nsplit, xcds, cs);
+  return hipGetLastError();
 }
 
 hipError_t launch_gemm(const GemmPlan &p, ms_dtype g_dtype, const void *G, int64_t ldg,
@@ -669,32 +1016,25 @@ hipError_t launch_gemm(const GemmPlan &p, ms_dtype g_dtype, const void *G, int64
         hipLaunchKernelGGL((k_reduce_splits<float, float>), dim3(rblocks), dim3(256), 0, st, p.M,
                            p.N, p.nsplit, (const float *)partials, (float *)Z, ldz, z64);
       break;
-    case MS_BF16:
-      if (yterms == 3)
-        hipLaunchKernelGGL((k_gemm_splitk<DT_BF16, 3>), grid, dim3(256), 0, st, p.M, p.N, p.K,
-                           (const unsigned short *)G, ldg, (const float *)Y, ldy,
-                           (float *)partials, p.kchunk, p.tiles_m, tiles, p.nsplit, xcds, nullptr);
-      else
-        hipLaunchKernelGGL((k_gemm_splitk<DT_BF16, 1>), grid, dim3(256), 0, st, p.M, p.N, p.K,
-                           (const unsigned short *)G, ldg, (const float *)Y, ldy,
-                           (float *)partials, p.kchunk, p.tiles_m, tiles, p.nsplit, xcds, nullptr);
+    case MS_BF16: {
+      const hipError_t e = yterms == 3
+                               ? launch_wide<DT_BF16, 3>(p, G, ldg, Y, ldy, partials, nullptr, st)
+                               : launch_wide<DT_BF16, 1>(p, G, ldg, Y, ldy, partials, nullptr, st);
+      if (e != hipSuccess) return e;
       if (reduce)
         hipLaunchKernelGGL((k_reduce_splits<float, float>), dim3(rblocks), dim3(256), 0, st, p.M,
                            p.N, p.nsplit, (const float *)partials, (float *)Z, ldz, z64);
       break;
+    }
     case MS_F16: {
       float *cs = reinterpret_cast<float *>(static_cast<unsigned char *>(partials) +
                                             align_up((size_t)p.nsplit * MN * sizeof(float)));
       hipLaunchKernelGGL(k_f16_col_scale, dim3((unsigned)p.N), dim3(256), 0, st, p.K,
                          (const float *)Y, ldy, cs);
-      if (yterms == 3)
-        hipLaunchKernelGGL((k_gemm_splitk<DT_F16, 3>), grid, dim3(256), 0, st, p.M, p.N, p.K,
-                           (const _Float16 *)G, ldg, (const float *)Y, ldy, (float *)partials,
-                           p.kchunk, p.tiles_m, tiles, p.nsplit, xcds, (const float *)cs);
-      else
-        hipLaunchKernelGGL((k_gemm_splitk<DT_F16, 1>), grid, dim3(256), 0, st, p.M, p.N, p.K,
-                           (const _Float16 *)G, ldg, (const float *)Y, ldy, (float *)partials,
-                           p.kchunk, p.tiles_m, tiles, p.nsplit, xcds, (const float *)cs);
+      const hipError_t e = yterms == 3
+                               ? launch_wide<DT_F16, 3>(p, G, ldg, Y, ldy, partials, cs, st)
+                               : launch_wide<DT_F16, 1>(p, G, ldg, Y, ldy, partials, cs, st);
+      if (e != hipSuccess) return e;
       if (reduce)
         hipLaunchKernelGGL((k_reduce_splits<float, float>), dim3(rblocks), dim3(256), 0, st, p.M,
                            p.N, p.nsplit, (const float *)partials, (float *)Z, ldz, z64);

@@ -32,6 +32,8 @@ GEMM_CASES = [
     (128, 8192, 65),    # the 128 x 8192 stage of the FP64 workload
     (64, 2048, 1),
     (256, 32768, 129),  # the 256 x 32768 stage of the FP32 workload
+    (300, 4100, 150),   # two row tiles and two column tiles of the 16-bit kernel, ragged
+    (257, 777, 145),    # second row tile of one row, second column tile of one column
 ]
 
 
