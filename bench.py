@@ -167,6 +167,16 @@ def serving_leg(ms, torch, np, count, seed, refine, dev):
                      refine_steps=rsteps, device=dev).run(warm)
         res = {}
         for name, rate in (("open_loop_2000_per_s", 2000.0), ("closed_loop", 0.0)):
+            if rate == 0.0:
+                # an untimed closed loop first: the allocator then holds the
+                # blocks of the loop's footprint (tens of GB), as a serving
+                # process in steady state does, instead of mapping them during
+                # the timed loop
+                serve.Server(hbm_budget=96 << 30, max_inflight=512, max_batch=64,
+                             streams=1 if single else 4, g_dtype=g_dtype, a_dtype=a_dtype,
+                             single=single, refine_steps=rsteps, device=dev,
+                             persistent=False).run(serve.make_requests(count, 0.0,
+                                                                       seed=seed + 11))
             reqs = serve.make_requests(count, rate, seed=seed)
             if name.startswith("open"):
                 for r in reqs[::32]:
