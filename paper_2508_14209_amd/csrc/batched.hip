@@ -115,7 +115,7 @@ __device__ int64_t block_excl_scan64(int64_t v, int64_t *sh, int64_t &total) {
 
 __global__ __launch_bounds__(kSetupThreads) void k_batch_setup(
     int count, const ms_problem *__restrict__ P, int wdata, int accw, int64_t rows_item,
-    int64_t kchunk, int refine, int det, BatchCaps caps, BatchEntry *__restrict__ E,
+    int64_t kchunk, int refine, int det, int g16, BatchCaps caps, BatchEntry *__restrict__ E,
     BatchTotals *__restrict__ tot, int *__restrict__ pstatus, int *status) {
   __shared__ int64_t sh[16];
   if (threadIdx.x == 0) *status = MS_OK;
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_batch_setup(
   int64_t sum[NQ] = {}, mx = 0;
   for (int p = p0; p < p1; ++p) {
     BatchEntry e;
-    batch_entry(P[p], wdata, accw, rows_item, kchunk, refine, e, det);
+    batch_entry(P[p], wdata, accw, rows_item, kchunk, refine, e, det, g16);
     int64_t q[NQ];
     batch_quantities(P[p], e, wdata, accw, q);
     for (int j = 0; j < NQ; ++j) sum[j] += q[j];
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kSetupThreads) void k_batch_setup(
                     total[QGVB] <= caps.gv_bytes && total[QKEY] <= caps.key_bytes;
   for (int p = p0; p < p1; ++p) {
     BatchEntry e;
-    batch_entry(P[p], wdata, accw, rows_item, kchunk, refine, e, det);
+    batch_entry(P[p], wdata, accw, rows_item, kchunk, refine, e, det, g16);
     const bool valid = e.valid != 0;
     if (!fits) e.valid = 0;
     int64_t q[NQ];
@@ -269,7 +269,8 @@ HostBatch host_batch(int count, const ms_problem *probs, ms_dtype a, ms_dtype g,
       return H;
     }
     BatchEntry e;
-    batch_entry(probs[p], wdata, accw, rows_item_of(o), kchunk_of(o), refine, e, det_of(o));
+    batch_entry(probs[p], wdata, accw, rows_item_of(o), kchunk_of(o), refine, e, det_of(o),
+                g == MS_BF16 ? 1 : 0);
     if (!e.valid) {
       H.ok = false;
       return H;
@@ -340,7 +341,8 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
   const int det = det_of(opts);
 
   hipLaunchKernelGGL(k_batch_setup, dim3(1), dim3(kSetupThreads), 0, st, count, probs_dev, wdata,
-                     accw, rows_item_of(opts), kchunk_of(opts), refine > 0 ? 1 : 0, det, H.caps,
+                     accw, rows_item_of(opts), kchunk_of(opts), refine > 0 ? 1 : 0, det,
+                     g_dtype == MS_BF16 ? 1 : 0, H.caps,
                      E, tot, pstatus, status);
   hipError_t e = hipGetLastError();
   auto zero = [&](int residual, unsigned char *area) {
@@ -372,7 +374,8 @@ ms_status sketch_lstsq_batched(int count, const ms_problem *probs_host,
                                      grid, st);
   }
   if (e == hipSuccess)
-    e = launch_batch_gemm(count, g_dtype, probs_dev, E, tot, yarea, parea, di.cus * 4, st,
+    e = launch_batch_gemm(count, g_dtype, probs_dev, E, tot, yarea, parea,
+                          g_dtype == MS_BF16 ? di.cus : di.cus * 4, st,
                           (opts && opts->gauss_y_terms == 1) ? 1 : 3);
   if (e == hipSuccess)
     e = launch_batch_reduce(count, g_dtype, probs_dev, E, parea, zarea, (int)H.max_mn, st);

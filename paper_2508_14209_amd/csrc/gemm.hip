@@ -4,8 +4,11 @@
 //
 // Shapes are short and wide in K: M = k2 (2n), N = n + nrhs, K = k (2n^2).
 // The K dimension is split across workgroups; each writes a partial M x N
-// block and a second kernel adds the partials in split order (fixed, so the
-// result does not depend on scheduling).
+// block and a second kernel adds the partials in a fixed order (four
+// consecutive runs of splits, each in split order, then the four run sums in
+// order), so the result does not depend on scheduling.  A 16-bit G uses
+// 256 x 144 output tiles staged through LDS; FP64 and FP32 use 64 x 64 tiles
+// with fragments loaded straight from memory.
 //
 // Matrix-core instructions (one 16x16 output block per instruction):
 //   FP64: v_mfma_f64_16x16x4_f64       (K step 4)
@@ -83,31 +86,6 @@ struct Mf<DT_F32> {
   }
   __device__ static int out_row(int lk, int r) { return 4 * lk + r; }
 };
-template <>
-struct Mf<DT_BF16> {
-  using TG = unsigned short;  // BF16 bit patterns
-  using TY = float;           // rounded to BF16 on load
-  using Acc = float;
-  using Frag = v8bf;
-  using AccV = v4f;
-  static constexpr int KS = 32;
-  __device__ static AccV mma(Frag a, Frag b, AccV c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-  }
-  __device__ static int out_row(int lk, int r) { return 4 * lk + r; }
-};
-
-template <>
-struct Mf<DT_F16> {
-  using TG = _Float16;  // FP16 data
-  using TY = float;     // scaled per column and rounded to FP16 terms on load
-  using Acc = float;
-  using Frag = v8h;
-  using AccV = v4f;
-  static constexpr int KS = 32;
-  __device__ static int out_row(int lk, int r) { return 4 * lk + r; }
-};
-
 // The 16-bit formats of the LDS-staged tile: conversion of FP32 pairs,
 // the value of a converted half as FP32, and the matrix-core product.
 template <int DT>
@@ -151,14 +129,6 @@ __device__ __forceinline__ float load_a<DT_F32>(const float *G, int64_t ldg, int
                                                 int64_t kq, int64_t ke) {
   return (row < M && kq < ke) ? gload(G + row + kq * ldg) : 0.0f;
 }
-template <>
-__device__ __forceinline__ v8bf load_a<DT_BF16>(const unsigned short *G, int64_t ldg, int M,
-                                                int row, int64_t kq, int64_t ke) {
-  v8u16 u;
-#pragma unroll
-  for (int t = 0; t < 8; ++t) u[t] = (row < M && kq + t < ke) ? gload(G + row + (kq + t) * ldg) : 0;
-  return __builtin_bit_cast(v8bf, u);
-}
 
 // B fragment: Y column [col], k-group starting at kq.
 template <int DT>
@@ -174,23 +144,10 @@ __device__ __forceinline__ float load_b<DT_F32>(const float *Y, int64_t ldy, int
                                                 int64_t kq, int64_t ke) {
   return (col < N && kq < ke) ? Y[kq + (int64_t)col * ldy] : 0.0f;
 }
-template <>
-__device__ __forceinline__ v8bf load_b<DT_BF16>(const float *Y, int64_t ldy, int N, int col,
-                                                int64_t kq, int64_t ke) {
-  v8u16 u;
-#pragma unroll
-  for (int t = 0; t < 8; ++t)
-    u[t] = (col < N && kq + t < ke) ? f32_to_bf16_rne(Y[kq + t + (int64_t)col * ldy]) : 0;
-  return __builtin_bit_cast(v8bf, u);
-}
 
 // Workgroup = 4 waves over a 64 x 64 output tile (each wave 32 x 32, i.e.
 // 2 x 2 matrix-core blocks), one K chunk per workgroup.  Fragments are loaded U instructions ahead: the loads of the next batch are
 // in flight while the current batch runs on the matrix cores.
-template <int DT>
-struct Unroll {
-  static constexpr int U = DT == DT_BF16 ? 2 : 8;
-};
 
 // One 64 x 64 output tile (m_tile, n_tile) of G[:, kb:ke] Y[kb:ke, :], written
 // to P (ld M) -- the body shared by the single-problem and batched kernels.
@@ -200,7 +157,7 @@ __device__ __forceinline__ void gemm_tile(int M, int N, const typename Mf<DT>::T
                                           int64_t ldy, typename Mf<DT>::Acc *__restrict__ P,
                                           int64_t kb, int64_t ke, int m_tile, int n_tile) {
   using F = Mf<DT>;
-  constexpr int U = Unroll<DT>::U;
+  constexpr int U = 8;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int m_base = m_tile * 64 + (wave & 1) * 32;
@@ -256,14 +213,24 @@ __device__ __forceinline__ void gemm_tile(int M, int N, const typename Mf<DT>::T
     }
 }
 
-// BF16 / FP16 tile staged through LDS.  G is stored with its rows
-// contiguous, but a matrix-core fragment holds 8 consecutive k of one row, so
-// G's tile (64 rows x 64 k) is loaded with 16-byte loads along the rows and
-// written to LDS transposed (row-major, k contiguous); Y's tile (64 k x 64
-// columns, FP32, k contiguous) is converted to the 16-bit format and written
-// as is.  Two LDS buffers: the next stage's global loads are in flight while
-// the current stage runs on the matrix cores.  The k steps (32 each) run in
-// the same order as in gemm_tile, so the partial sums are the same.
+// ------------------------------------------------------------ wide 16-bit tiles
+// The BF16 / FP16 stage with 256 x 144 output tiles: four waves (one per
+// SIMD), wave w owning rows 64 w .. 64 w + 63 of the tile and all 144 columns
+// (4 x 9 blocks of 16 x 16, 144 accumulator registers).  K advances in stages
+// of 32: per stage the workgroup stages G's 256 x 32 tile (loaded as 16-byte
+// runs of 8 rows at one k, written to LDS k-contiguous per row) and Y's
+// 32 x 144 tile (FP32, split into YT 16-bit terms on the way in); up to three
+// stages of global loads are in flight while one is on the matrix cores.
+// With 64 x 64 tiles every element of G would be fetched by ceil(N/64)
+// workgroups and every element of Y by ceil(M/64); here by ceil(N/144) and
+// ceil(M/256) (once each for M <= 256 and N <= 144: every sketch of the
+// serving workload).  The k steps of a K chunk run in ascending order and
+// the terms of a step small first.
+//
+// LDS: G's tile row R starts at element 40 R + 32 (R / 8): rows padded to 40
+// elements (fragment reads of 16 lanes hit distinct banks), and each 8-row
+// group shifted by 16 banks so that the transposing 4-byte writes of a wave
+// (16 k pairs x 4 row groups) cost two passes, not four.
 //
 // YT = 1: Y rounded to the 16-bit format (nearest even).  YT = 3: Y as the
 // sum of three terms, hi = h(y), mid = h(y - hi), lo = h(y - hi - mid); each
@@ -277,163 +244,6 @@ __device__ __forceinline__ void gemm_tile(int M, int N, const typename Mf<DT>::T
 // [2^14, 2^15), and multiplies the column's result by cs[2c + 1] = 2^e_c;
 // the three terms then hold y exactly down to 2^-40 of the column's largest
 // magnitude (smaller parts of an entry fall below FP16's subnormals).
-constexpr int kStK = 64, kStPad = 72;  // k per stage; LDS row stride (BF16 elements)
-
-template <int DT, int YT>
-__device__ __forceinline__ void gemm_tile_lds_h(int M, int N, const unsigned short *__restrict__ G,
-                                                int64_t ldg, const float *__restrict__ Y,
-                                                int64_t ldy, const float *__restrict__ cs,
-                                                float *__restrict__ P, int64_t kb, int64_t ke,
-                                                int m_tile, int n_tile) {
-  using H = Half16<DT>;
-  __shared__ __align__(16) unsigned short As[2][64 * kStPad];
-  __shared__ __align__(16) unsigned short Bs[2][YT][64 * kStPad];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int m0 = m_tile * 64, n0 = n_tile * 64;
-  // global-load roles: G columns (k) 2 gp and 2 gp + 1, rows 8 g8 .. 8 g8 + 7,
-  // written to LDS as one dword (the two k of a row) per row; Y column yc,
-  // k yk .. yk + 15, converted to BF16 in pairs by the hardware conversion
-  const int g8 = tid & 7, gp = tid >> 3;
-  const int yc = tid >> 2, yk = (tid & 3) * 16;
-  const int rb = m0 + 8 * g8;
-  const bool gvec = (ldg & 7) == 0 && ((uintptr_t)G & 15) == 0 && rb + 8 <= M;
-  const bool yvec = (ldy & 3) == 0 && ((uintptr_t)Y & 15) == 0 && n0 + yc < N;
-  // FP16: the scale of this thread's column of Y
-  const float yscale = (DT == DT_F16 && n0 + yc < N) ? cs[2 * (n0 + yc)] : 1.0f;
-  uint32_t gw[8];
-  float yv[16];
-  auto fetch = [&](int64_t k0) {
-    const int64_t kc = k0 + 2 * gp;
-    v8u16 c0 = {}, c1 = {};
-    if (gvec) {
-      if (kc < ke) c0 = gload(reinterpret_cast<const v8u16 *>(G + rb + kc * ldg));
-      if (kc + 1 < ke) c1 = gload(reinterpret_cast<const v8u16 *>(G + rb + (kc + 1) * ldg));
-    } else {
-#pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        c0[r] = (kc < ke && rb + r < M) ? gload(G + rb + r + kc * ldg) : (unsigned short)0;
-        c1[r] = (kc + 1 < ke && rb + r < M) ? gload(G + rb + r + (kc + 1) * ldg) : (unsigned short)0;
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 8; ++r) gw[r] = (uint32_t)c0[r] | ((uint32_t)c1[r] << 16);
-    const int64_t kq = k0 + yk;
-    if (yvec && kq + 16 <= ke) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const v4f v = gload(reinterpret_cast<const v4f *>(Y + kq + 4 * q + (int64_t)(n0 + yc) * ldy));
-        yv[4 * q] = v[0];
-        yv[4 * q + 1] = v[1];
-        yv[4 * q + 2] = v[2];
-        yv[4 * q + 3] = v[3];
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        yv[u] = (n0 + yc < N && kq + u < ke) ? gload(Y + kq + u + (int64_t)(n0 + yc) * ldy) : 0.0f;
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int r = 0; r < 8; ++r)
-      *reinterpret_cast<uint32_t *>(&As[buf][(8 * g8 + r) * kStPad + 2 * gp]) = gw[r];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      v4u32 bt[YT];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        float y0 = yv[8 * h + 2 * u], y1 = yv[8 * h + 2 * u + 1];
-        if (DT == DT_F16) {
-          y0 *= yscale;
-          y1 *= yscale;
-        }
-#pragma unroll
-        for (int tt = 0; tt < YT; ++tt) {
-          const uint32_t w = H::pack2(y0, y1);
-          bt[tt][u] = w;
-          if (tt + 1 < YT) {
-            y0 -= H::lo_f32(w);
-            y1 -= H::hi_f32(w);
-          }
-        }
-      }
-#pragma unroll
-      for (int tt = 0; tt < YT; ++tt)
-        *reinterpret_cast<v4u32 *>(&Bs[buf][tt][yc * kStPad + yk + 8 * h]) = bt[tt];
-    }
-  };
-  const int m_base = (wave & 1) * 32, n_base = (wave >> 1) * 32;
-  v4f acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{};
-  fetch(kb);
-  lstore(0);
-  __syncthreads();
-  int buf = 0;
-  for (int64_t k0 = kb; k0 < ke; k0 += kStK) {
-    const bool more = k0 + kStK < ke;
-    if (more) fetch(k0 + kStK);
-#pragma unroll
-    for (int ks = 0; ks < kStK / 32; ++ks) {
-      typename H::V8 a[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-        a[i] = *reinterpret_cast<const typename H::V8 *>(
-            &As[buf][(m_base + 16 * i + li) * kStPad + ks * 32 + lk * 8]);
-      // the small terms first (each enters the same FP32 accumulators)
-#pragma unroll
-      for (int tt = YT - 1; tt >= 0; --tt) {
-        typename H::V8 b[2];
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          b[j] = *reinterpret_cast<const typename H::V8 *>(
-              &Bs[buf][tt][(n_base + 16 * j + li) * kStPad + ks * 32 + lk * 8]);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) acc[i][j] = H::mma(a[i], b[j], acc[i][j]);
-      }
-    }
-    if (more) lstore(buf ^ 1);
-    __syncthreads();
-    buf ^= 1;
-  }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int col = n0 + n_base + 16 * j + li;
-      const float back = (DT == DT_F16 && col < N) ? cs[2 * col + 1] : 1.0f;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + m_base + 16 * i + 4 * lk + r;
-        if (row < M && col < N) P[row + (int64_t)col * M] = DT == DT_F16 ? acc[i][j][r] * back
-                                                                         : acc[i][j][r];
-      }
-    }
-}
-
-// ------------------------------------------------------------ wide 16-bit tiles
-// The BF16 / FP16 stage with 256 x 144 output tiles: four waves (one per
-// SIMD), wave w owning rows 64 w .. 64 w + 63 of the tile and all 144 columns
-// (4 x 9 blocks of 16 x 16, 144 accumulator registers).  K advances in stages
-// of 32: per stage the workgroup stages G's 256 x 32 tile (loaded as 16-byte
-// runs of 8 rows at one k, written to LDS k-contiguous per row) and Y's
-// 32 x 144 tile (FP32, split into YT 16-bit terms on the way in); two stages
-// of global loads are in flight while a third is on the matrix cores.  With
-// 64 x 64 tiles every element of G was fetched by ceil(N/64) workgroups and
-// every element of Y by ceil(M/64); here by ceil(N/144) and ceil(M/256)
-// (once each for M <= 256 and N <= 144: every sketch of the serving
-// workload).  The k steps of a K chunk run in ascending order and the terms
-// of a step small first, as in the 64 x 64 tile.
-//
-// LDS: G's tile row R starts at element 40 R + 32 (R / 8): rows padded to 40
-// elements (fragment reads of 16 lanes hit distinct banks), and each 8-row
-// group shifted by 16 banks so that the transposing 4-byte writes of a wave
-// (16 k pairs x 4 row groups) cost two passes, not four.
 constexpr int kWTM = 256, kWTN = 144, kWKS = 32, kWPad = 40, kWThreads = 256;
 constexpr int kWNB = kWTN / 16;                       // column blocks per tile
 constexpr int kWAElems = kWTM * kWPad + (kWTM / 8) * 32;  // G tile incl. group shifts
@@ -729,26 +539,10 @@ __global__ __launch_bounds__(kWThreads) void k_gemm_wide(int M, int N, int64_t K
                                reinterpret_cast<unsigned short *>(smem_raw));
 }
 
-// The tile of either kind: LDS-staged for BF16 and FP16, direct fragment
-// loads else.  YT: 16-bit terms of Y (1 or 3; the other dtypes ignore it).
-// cs: FP16's column scales (unused for the other dtypes).
-template <int DT, int YT = 1>
-__device__ __forceinline__ void gemm_tile_any(int M, int N, const typename Mf<DT>::TG *__restrict__ G,
-                                              int64_t ldg, const typename Mf<DT>::TY *__restrict__ Y,
-                                              int64_t ldy, const float *__restrict__ cs,
-                                              typename Mf<DT>::Acc *__restrict__ P, int64_t kb,
-                                              int64_t ke, int m_tile, int n_tile) {
-  if constexpr (DT == DT_BF16 || DT == DT_F16)
-    gemm_tile_lds_h<DT, YT>(M, N, reinterpret_cast<const unsigned short *>(G), ldg, Y, ldy, cs, P,
-                            kb, ke, m_tile, n_tile);
-  else
-    gemm_tile<DT>(M, N, G, ldg, Y, ldy, P, kb, ke, m_tile, n_tile);
-}
-
 // Workgroup g runs on die g % xcds.  All output tiles of one K chunk are
 // given to workgroups of the same die, so that chunk of G and Y is fetched
 // from HBM into one L2 and the other tiles re-read it from there.
-template <int DT, int YT = 1>
+template <int DT>
 __global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
                                                      const typename Mf<DT>::TG *__restrict__ G,
                                                      int64_t ldg,
@@ -756,8 +550,7 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
                                                      int64_t ldy,
                                                      typename Mf<DT>::Acc *__restrict__ part,
                                                      int64_t kchunk, int tiles_m, int tiles,
-                                                     int nsplit, int xcds,
-                                                     const float *__restrict__ cs) {
+                                                     int nsplit, int xcds) {
   const int g = blockIdx.x;
   const int x = g % xcds, j = g / xcds;
   const int split = x + xcds * (j / tiles);
@@ -765,8 +558,8 @@ __global__ __launch_bounds__(256) void k_gemm_splitk(int M, int N, int64_t K,
   const int tile = j % tiles;
   const int64_t kb = (int64_t)split * kchunk;
   const int64_t ke = min(K, kb + kchunk);
-  gemm_tile_any<DT, YT>(M, N, G, ldg, Y, ldy, cs, part + (int64_t)split * M * N, kb, ke,
-                        tile % tiles_m, tile / tiles_m);
+  gemm_tile<DT>(M, N, G, ldg, Y, ldy, part + (int64_t)split * M * N, kb, ke, tile % tiles_m,
+                tile / tiles_m);
 }
 
 // FP16 column scales: cs[2c] = 2^-e_c and cs[2c + 1] = 2^e_c with
@@ -810,33 +603,54 @@ __global__ __launch_bounds__(256) void k_f16_col_scale(int64_t K, const float *_
 // (its own dtype and leading dimension) and/or to an FP64 copy z64 (ld = M).
 // Loads are issued eight splits ahead of the (ordered) adds.
 template <typename Acc, typename TZ>
-__global__ void k_reduce_splits(int M, int N, int nsplit, const Acc *__restrict__ part,
-                                TZ *__restrict__ Z, int64_t ldz, double *__restrict__ z64) {
+__global__ __launch_bounds__(256) void k_reduce_splits(int M, int N, int nsplit,
+                                                       const Acc *__restrict__ part,
+                                                       TZ *__restrict__ Z, int64_t ldz,
+                                                       double *__restrict__ z64) {
+  // 64 outputs per workgroup, one per lane; wave w sums splits
+  // [w q, (w + 1) q) of them in split order (q = ceil(nsplit / 4)), and the
+  // four segment sums are added in segment order: a fixed order, with four
+  // times the loads in flight of one lane walking all the splits
+  __shared__ Acc seg[4][64];
   const int64_t MN = (int64_t)M * N;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < MN;
-       t += (int64_t)gridDim.x * blockDim.x) {
-    Acc s = part[t];
-    int z = 1;
-    for (; z + 8 <= nsplit; z += 8) {
-      Acc v[8];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int q = (nsplit + 3) / 4;
+  const int z0 = min(nsplit, w * q), z1 = min(nsplit, z0 + q);
+  for (int64_t base = (int64_t)blockIdx.x * 64; base < MN; base += (int64_t)gridDim.x * 64) {
+    const int64_t t = base + lane;
+    Acc s = Acc(0);
+    if (t < MN && z0 < z1) {
+      s = part[t + (int64_t)z0 * MN];
+      int z = z0 + 1;
+      for (; z + 8 <= z1; z += 8) {
+        Acc v[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = part[t + (int64_t)(z + u) * MN];
+        for (int u = 0; u < 8; ++u) v[u] = part[t + (int64_t)(z + u) * MN];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) s = s + v[u];
+        for (int u = 0; u < 8; ++u) s = s + v[u];
+      }
+      for (; z < z1; ++z) s = s + part[t + (int64_t)z * MN];
     }
-    for (; z < nsplit; ++z) s = s + part[t + (int64_t)z * MN];
-    const int64_t c = t / M, p = t - c * M;
-    if (Z) Z[p + c * ldz] = (TZ)s;
-    if (z64) z64[t] = (double)s;
+    seg[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && t < MN) {
+      Acc r = seg[0][lane];
+      for (int v = 1; v < 4; ++v)
+        if (v * q < nsplit) r = r + seg[v][lane];
+      const int64_t c = t / M, p = t - c * M;
+      if (Z) Z[p + c * ldz] = (TZ)r;
+      if (z64) z64[t] = (double)r;
+    }
+    __syncthreads();
   }
 }
 
 // ------------------------------------------------------------------ batched
 
-// Persistent workgroups over the Gaussian-stage items of all problems: item
-// = (problem, 64-row tile, 64-column tile, K split); each writes its partial
-// block into the problem's partials area.
-template <int DT, int YT = 1>
+// Persistent workgroups over the Gaussian-stage items of all problems (FP64
+// and FP32 G): item = (problem, 64-row tile, 64-column tile, K split); each
+// writes its partial block into the problem's partials area.
+template <int DT>
 __global__ __launch_bounds__(256) void k_batch_gemm(int count, const ms_problem *__restrict__ P,
                                                     const BatchEntry *__restrict__ E,
                                                     const BatchTotals *__restrict__ tot,
@@ -857,8 +671,51 @@ __global__ __launch_bounds__(256) void k_batch_gemm(int count, const ms_problem 
     const int64_t kb = (int64_t)split * e.kchunk, ke = min(Q.k, kb + e.kchunk);
     const auto *Y = reinterpret_cast<const typename F::TY *>(yarea + e.y_off);
     auto *Pz = reinterpret_cast<typename F::Acc *>(parea + e.part_off) + (int64_t)split * M * N;
-    gemm_tile_any<DT, YT>(M, N, static_cast<const typename F::TG *>(Q.G), Q.ldg, Y, Q.k, nullptr,
-                          Pz, kb, ke, tm, tn);
+    gemm_tile<DT>(M, N, static_cast<const typename F::TG *>(Q.G), Q.ldg, Y, Q.k, Pz, kb, ke, tm,
+                  tn);
+  }
+}
+
+// The 16-bit stage of a batch on the wide tiles: item = (problem, 256 x 144
+// output tile, K split), one 256-thread workgroup per item at a time with
+// the tile's two LDS stages.  The fast path is taken per problem (G aligned
+// with a leading dimension a multiple of 8, k2 a multiple of 8, k a
+// multiple of 32; Y, the batch's sketch area, is 256-byte aligned with
+// leading dimension k).
+static_assert(kBatchWideTM == kWTM && kBatchWideTN == kWTN, "batched wide tile shape");
+
+template <int DT, int YT>
+__global__ __launch_bounds__(kWThreads) void k_batch_gemm_wide(
+    int count, const ms_problem *__restrict__ P, const BatchEntry *__restrict__ E,
+    const BatchTotals *__restrict__ tot, const unsigned char *__restrict__ yarea,
+    unsigned char *__restrict__ parea) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  unsigned short *lds = reinterpret_cast<unsigned short *>(smem_raw);
+  const int64_t total = tot->gemm_items;
+  for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
+    const int p = batch_find_m<&BatchEntry::gemm_start>(E, count, it);
+    const ms_problem &Q = P[p];
+    const BatchEntry &e = E[p];
+    int64_t local = it - e.gemm_start;
+    const int split = (int)(local % e.nsplit);
+    local /= e.nsplit;
+    const int tn = (int)(local % e.tiles_n);
+    const int tm = (int)(local / e.tiles_n);
+    const int M = (int)Q.k2, N = e.nc;
+    const int64_t kb = (int64_t)split * e.kchunk, ke = min(Q.k, kb + e.kchunk);
+    const float *Y = reinterpret_cast<const float *>(yarea + e.y_off);
+    float *Pz = reinterpret_cast<float *>(parea + e.part_off) + (int64_t)split * M * N;
+    const unsigned short *G = static_cast<const unsigned short *>(Q.G);
+    const bool fast = (Q.ldg & 7) == 0 && ((uintptr_t)G & 15) == 0 && (M & 7) == 0 &&
+                      (Q.k & 3) == 0 && ((uintptr_t)Y & 15) == 0 && (Q.k % kWKS) == 0 &&
+                      (e.kchunk % kWKS) == 0;
+    if (fast)
+      gemm_tile_wide<DT, YT, true>(M, N, G, Q.ldg, Y, Q.k, nullptr, Pz, kb, ke, (int64_t)kWKS,
+                                   tm * kWTM, tn * kWTN, lds);
+    else
+      gemm_tile_wide<DT, YT, false>(M, N, G, Q.ldg, Y, Q.k, nullptr, Pz, kb, ke, (int64_t)kWKS,
+                                    tm * kWTM, tn * kWTN, lds);
+    __syncthreads();  // the next item's first stage overwrites the LDS
   }
 }
 
@@ -875,12 +732,19 @@ hipError_t launch_batch_gemm(int count, ms_dtype g_dtype, const ms_problem *P, c
                          yarea, parea);
       break;
     case MS_BF16:
-      if (yterms == 3)
-        hipLaunchKernelGGL((k_batch_gemm<DT_BF16, 3>), dim3(grid), dim3(256), 0, st, count, P, E,
-                           tot, yarea, parea);
-      else
-        hipLaunchKernelGGL((k_batch_gemm<DT_BF16, 1>), dim3(grid), dim3(256), 0, st, count, P, E,
-                           tot, yarea, parea);
+      if (yterms == 3) {
+        const hipError_t e =
+            allow_dynamic_lds((const void *)k_batch_gemm_wide<DT_BF16, 3>, wide_lds_bytes<3>());
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_batch_gemm_wide<DT_BF16, 3>), dim3(grid), dim3(kWThreads),
+                           wide_lds_bytes<3>(), st, count, P, E, tot, yarea, parea);
+      } else {
+        const hipError_t e =
+            allow_dynamic_lds((const void *)k_batch_gemm_wide<DT_BF16, 1>, wide_lds_bytes<1>());
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_batch_gemm_wide<DT_BF16, 1>), dim3(grid), dim3(kWThreads),
+                           wide_lds_bytes<1>(), st, count, P, E, tot, yarea, parea);
+      }
       break;
     default:
       return hipErrorInvalidValue;
@@ -933,10 +797,10 @@ GemmPlan plan_gemm(int64_t M, int64_t N, int64_t K, ms_dtype g_dtype) {
   p.N = (int)N;
   p.K = K;
   const bool h16 = g_dtype == MS_BF16 || g_dtype == MS_F16;
-  // 16-bit G: 256 x 144 tiles of 512 threads, about one workgroup per
-  // compute unit, at least 512 K values per workgroup (so the partials stay
-  // small next to the chunk of G and Y each workgroup reads); else 64 x 64
-  // tiles, ~1024 workgroups, at least 128 K values each
+  // 16-bit G: 256 x 144 tiles, about one workgroup per compute unit, at
+  // least 512 K values per workgroup (so the partials stay small next to the
+  // chunk of G and Y each workgroup reads); else 64 x 64 tiles, ~1024
+  // workgroups, at least 128 K values each
   p.tiles_m = (int)(h16 ? (M + kWTM - 1) / kWTM : (M + 63) / 64);
   p.tiles_n = (int)(h16 ? (N + kWTN - 1) / kWTN : (N + 63) / 64);
   const int64_t ks = h16 ? kWKS : 4;
@@ -993,7 +857,7 @@ hipError_t launch_gemm(const GemmPlan &p, ms_dtype g_dtype, const void *G, int64
   (void)ybf16;
   if (p.M <= 0 || p.N <= 0) return hipSuccess;
   const int64_t MN = (int64_t)p.M * p.N;
-  const unsigned rblocks = (unsigned)std::min<int64_t>((MN + 255) / 256, 65535);
+  const unsigned rblocks = (unsigned)std::min<int64_t>((MN + 63) / 64, 65535);
   if (p.K <= 0) return hipErrorInvalidValue;
   const int xcds = dev_info().xcds;
   const int tiles = p.tiles_m * p.tiles_n;
@@ -1003,7 +867,7 @@ hipError_t launch_gemm(const GemmPlan &p, ms_dtype g_dtype, const void *G, int64
     case MS_F64:
       hipLaunchKernelGGL(k_gemm_splitk<DT_F64>, grid, dim3(256), 0, st, p.M, p.N, p.K,
                          (const double *)G, ldg, (const double *)Y, ldy, (double *)partials,
-                         p.kchunk, p.tiles_m, tiles, p.nsplit, xcds, nullptr);
+                         p.kchunk, p.tiles_m, tiles, p.nsplit, xcds);
       if (reduce)
         hipLaunchKernelGGL((k_reduce_splits<double, double>), dim3(rblocks), dim3(256), 0, st, p.M,
                            p.N, p.nsplit, (const double *)partials, (double *)Z, ldz, z64);
@@ -1011,7 +875,7 @@ hipError_t launch_gemm(const GemmPlan &p, ms_dtype g_dtype, const void *G, int64
     case MS_F32:
       hipLaunchKernelGGL(k_gemm_splitk<DT_F32>, grid, dim3(256), 0, st, p.M, p.N, p.K,
                          (const float *)G, ldg, (const float *)Y, ldy, (float *)partials,
-                         p.kchunk, p.tiles_m, tiles, p.nsplit, xcds, nullptr);
+                         p.kchunk, p.tiles_m, tiles, p.nsplit, xcds);
       if (reduce)
         hipLaunchKernelGGL((k_reduce_splits<float, float>), dim3(rblocks), dim3(256), 0, st, p.M,
                            p.N, p.nsplit, (const float *)partials, (float *)Z, ldz, z64);
@@ -1274,7 +1138,7 @@ hipError_t launch_gemv64(int64_t M, int64_t N, int64_t K, ms_dtype g_dtype, cons
       return hipErrorInvalidValue;
   }
   const int64_t MN = M * N;
-  const unsigned rblocks = (unsigned)std::min<int64_t>((MN + 255) / 256, 4096);
+  const unsigned rblocks = (unsigned)std::min<int64_t>((MN + 63) / 64, 65535);
   hipLaunchKernelGGL((k_reduce_splits<double, double>), dim3(rblocks), dim3(256), 0, st, (int)M,
                      (int)N, (int)ns, (const double *)part, (double *)nullptr, (int64_t)M, z64);
   return hipGetLastError();

@@ -296,9 +296,13 @@ __host__ __device__ inline int64_t batch_bf_slots(int welem) {
   return welem == 4 ? 32768 : 14336;
 }
 
+// Output tile of the Gaussian stage's work items: 256 x 144 for a 16-bit G
+// (the wide matrix-core tile of gemm.hip), 64 x 64 else.
+constexpr int kBatchWideTM = 256, kBatchWideTN = 144;
+
 __host__ __device__ inline void batch_entry(const ms_problem &P, int wdata, int accw,
                                             int64_t rows_item, int64_t kchunk, int refine,
-                                            BatchEntry &E, int det = 0) {
+                                            BatchEntry &E, int det = 0, int g16 = 0) {
   E = BatchEntry{};
   E.valid = P.d >= 1 && P.d < 0x7fffffffLL && P.n >= 1 && P.nrhs >= 1 && P.k >= 1 &&
             P.k < 0x7fffffffLL && P.k2 >= P.n && P.k2 <= kBatchMaxK2 &&
@@ -316,8 +320,8 @@ __host__ __device__ inline void batch_entry(const ms_problem &P, int wdata, int 
   E.rows = rows_item;
   while (E.rows < 8 * P.k && E.rows < ((int64_t)1 << 30)) E.rows *= 2;
   E.nsegs = (int32_t)((P.d + E.rows - 1) / E.rows);
-  E.tiles_m = (int32_t)((P.k2 + 63) / 64);
-  E.tiles_n = (E.nc + 63) / 64;
+  E.tiles_m = (int32_t)(g16 ? (P.k2 + kBatchWideTM - 1) / kBatchWideTM : (P.k2 + 63) / 64);
+  E.tiles_n = g16 ? (E.nc + kBatchWideTN - 1) / kBatchWideTN : (E.nc + 63) / 64;
   E.kchunk = kchunk;
   E.nsplit = (int32_t)((P.k + kchunk - 1) / kchunk);
   if (det) {
