@@ -943,6 +943,79 @@ __device__ __forceinline__ void g_rows4(const TG *g, bool vec, int nvalid, doubl
   }
 }
 
+// buf[m * 8 + c] = Y[m + c * ldy] for m < len, c < N (a chunk of a narrow
+// FP64 right operand), eight loads per thread issued before their LDS
+// stores (indices past the end read the last element and are not stored).
+__device__ __forceinline__ void stage_rhs(const double *__restrict__ Y, int64_t ldy, int len,
+                                          int N, double *buf) {
+  constexpr int U = 8;
+  const int total = len * N, bd = (int)blockDim.x;
+  for (int t0 = threadIdx.x; t0 < total; t0 += U * bd) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = min(t0 + u * bd, total - 1);
+      const int c = t / len, m = t - c * len;
+      v[u] = Y[m + (int64_t)c * ldy];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = t0 + u * bd;
+      if (t < total) {
+        const int c = t / len, m = t - c * len;
+        buf[m * 8 + c] = v[u];
+      }
+    }
+  }
+}
+
+// The columns m = slot, slot + S, ... < len of a staged chunk: acc[q][c] +=
+// G[row q, m] * buf[m * RH + c].  VEC (four aligned rows in range): eight
+// columns' raw 4-row loads are issued before their products, with no
+// condition around them (a column past len reads column len - 1 and is not
+// used) and the conversion to FP64 at the use, so each lane keeps eight
+// loads in flight instead of one.  Else one column at a time, row by row.
+template <typename TG, int RH, bool VEC>
+__device__ __forceinline__ void gemv_cols(const TG *__restrict__ g0, int64_t ldg, int nvalid,
+                                          const double *buf, int slot, int S, int len, int N,
+                                          double (&acc)[4][RH]) {
+  if constexpr (VEC) {
+    constexpr int U = 8;
+    typedef TG V __attribute__((ext_vector_type(4)));
+    for (int m = slot; m < len; m += U * S) {
+      V raw[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        raw[u] = gload(reinterpret_cast<const V *>(g0 + (int64_t)min(m + u * S, len - 1) * ldg));
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int mm = m + u * S;
+        if (mm < len) {
+#pragma unroll
+          for (int c = 0; c < RH; ++c)
+            if (c < N) {
+              const double y = buf[mm * RH + c];
+#pragma unroll
+              for (int q = 0; q < 4; ++q) acc[q][c] += g_as_f64<TG>(raw[u][q]) * y;
+            }
+        }
+      }
+    }
+  } else {
+    for (int m = slot; m < len; m += S) {
+      double g[4];
+      g_rows4<TG>(g0 + (int64_t)m * ldg, false, nvalid, g);
+#pragma unroll
+      for (int c = 0; c < RH; ++c)
+        if (c < N) {
+          const double y = buf[m * RH + c];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) acc[q][c] += g[q] * y;
+        }
+    }
+  }
+}
+
 // Split-K partials of G Y in FP64 for narrow Y (N <= 8 columns; G's values
 // promoted exactly): block (row tile of 256 rows, K split).  Each thread owns
 // four rows; the block's threads form 256 / L slots (L threads per column of
@@ -953,7 +1026,7 @@ __global__ __launch_bounds__(256) void k_gemv64_splitk(int M, int N, int64_t K,
                                                        const TG *__restrict__ G, int64_t ldg,
                                                        const double *__restrict__ Y, int64_t ldy,
                                                        double *__restrict__ part, int64_t kchunk) {
-  constexpr int RH = 8, CH = 1024;
+  constexpr int RH = 8, CH = 1024;  // stage_rhs stores with stride 8
   __shared__ double buf[CH * RH];
   const int mt0 = blockIdx.x * 256;
   const int rows = min(256, M - mt0);
@@ -971,23 +1044,14 @@ __global__ __launch_bounds__(256) void k_gemv64_splitk(int M, int N, int64_t K,
   for (int64_t c0 = kb; c0 < ke; c0 += CH) {
     const int len = (int)min((int64_t)CH, ke - c0);
     __syncthreads();
-    for (int t = threadIdx.x; t < len * N; t += blockDim.x) {
-      const int c = t / len, m = t - c * len;
-      buf[m * RH + c] = Y[c0 + m + (int64_t)c * ldy];
-    }
+    stage_rhs(Y + c0, ldy, len, N, buf);
     __syncthreads();
-    if (active)
-      for (int m = slot; m < len; m += S) {
-        double g[4];
-        g_rows4<TG>(G + row0 + (c0 + m) * ldg, vec, nvalid, g);
-#pragma unroll
-        for (int c = 0; c < RH; ++c)
-          if (c < N) {
-            const double y = buf[m * RH + c];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q][c] += g[q] * y;
-          }
-      }
+    if (active) {
+      if (vec)
+        gemv_cols<TG, RH, true>(G + row0 + c0 * ldg, ldg, nvalid, buf, slot, S, len, N, acc);
+      else
+        gemv_cols<TG, RH, false>(G + row0 + c0 * ldg, ldg, nvalid, buf, slot, S, len, N, acc);
+    }
   }
   __syncthreads();
   if (active)
@@ -1018,6 +1082,7 @@ __global__ __launch_bounds__(256) void k_batch_gemv(int count, const ms_problem 
                                                     const unsigned char *__restrict__ yrarea,
                                                     unsigned char *__restrict__ gvarea) {
   constexpr int RH = kBatchMaxRefineRhs, CH = 1024;
+  static_assert(RH == 8, "stage_rhs stores with stride 8");
   __shared__ double buf[CH * RH];
   const int64_t total = tot->gv_items;
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
@@ -1044,23 +1109,16 @@ __global__ __launch_bounds__(256) void k_batch_gemv(int count, const ms_problem 
     for (int64_t c0 = kb; c0 < ke; c0 += CH) {
       const int len = (int)min((int64_t)CH, ke - c0);
       __syncthreads();  // earlier readers of buf are done
-      for (int t = threadIdx.x; t < len * N; t += blockDim.x) {
-        const int c = t / len, m = t - c * len;
-        buf[m * RH + c] = Yr[c0 + m + (int64_t)c * Q.k];
-      }
+      stage_rhs(Yr + c0, Q.k, len, N, buf);
       __syncthreads();
-      if (active)
-        for (int m = slot; m < len; m += S) {
-          double g[4];
-          g_rows4<TG>(G + row0 + (c0 + m) * Q.ldg, vec, nvalid, g);
-#pragma unroll
-          for (int c = 0; c < RH; ++c)
-            if (c < N) {
-              const double y = buf[m * RH + c];
-#pragma unroll
-              for (int q = 0; q < 4; ++q) acc[q][c] += g[q] * y;
-            }
-        }
+      if (active) {
+        if (vec)
+          gemv_cols<TG, RH, true>(G + row0 + c0 * Q.ldg, Q.ldg, nvalid, buf, slot, S, len, N,
+                                  acc);
+        else
+          gemv_cols<TG, RH, false>(G + row0 + c0 * Q.ldg, Q.ldg, nvalid, buf, slot, S, len, N,
+                                   acc);
+      }
     }
     // slot sums in slot order: buf[(slot * 4L + row) * RH + c]
     __syncthreads();

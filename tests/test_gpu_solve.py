@@ -332,3 +332,24 @@ def test_lstsq_range_error(ms):
     with pytest.raises(ms.MsketchError) as e:
         ms.check_status(ws)
     assert e.value.code == ms.MS_ERR_RANGE
+
+
+@pytest.mark.parametrize("d,n,nrhs,k2", [(5000, 8, 1, 64), (30000, 13, 3, 96),
+                                         (30000, 40, 8, 200), (40000, 64, 2, 512),
+                                         (20000, 20, 1, 520)])
+def test_lstsq_fp64_refinement_fixed_point(ms, orc, d, n, nrhs, k2):
+    # FP64 data and G: the first pass is the FP64 sketch-and-solve solution,
+    # whose sketched residual S r is orthogonal to range(S A), so each
+    # refinement step's correction R^{-1} (Q^T S r)[0:n) is zero up to
+    # rounding and X stays the oracle's solution.  A wrong reflector
+    # application or back substitution in the refinement step moves X by
+    # about ||S r|| / ||R|| (the 1e-6 noise of b): far outside the bar.
+    # Shapes: every register width of the staged refinement kernel (k2 up to
+    # 64, 128, 256, 512), blocks of eight reflectors with a ragged last one,
+    # one to eight right-hand sides, and k2 > 512 (the unstaged kernel).
+    k = 4096
+    print("fp64 refinement d=%d n=%d nrhs=%d k2=%d" % (d, n, nrhs, k2), flush=True)
+    A, B, xs, h, s, G = _lstsq_inputs(d, n, nrhs, k, k2, seed=d + k2)
+    X = _gpu_lstsq(ms, A, B, h, s, G, k, refine_steps=2)
+    Xr, _, _ = orc.sketch_lstsq(A, B, h, s, G, k)
+    assert rel(X, Xr) <= 1e-10
