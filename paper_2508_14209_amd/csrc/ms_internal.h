@@ -469,12 +469,15 @@ hipError_t launch_batch_apply_solve(int count, const ms_problem *P, BatchEntry *
 // lane its 16-lane row sum, two row broadcasts (lane 15 into rows 1 and 3,
 // lane 31 into rows 2 and 3) leave the total in lane 63, and one lane read
 // (a pair, for the two halves of the double) hands it to every lane.
+// Every lane is written (all rows and banks enabled, and each of these
+// patterns reads a lane of its own row), so the move needs no prior value and
+// no zeroed destination register.
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
   const long long u = __double_as_longlong(v);
   int lo = (int)(u & 0xffffffffLL), hi = (int)(u >> 32);
-  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xf, 0xf, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xf, 0xf, false);
+  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xf, 0xf, false);
+  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xf, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 __device__ __forceinline__ double read_lane(double v, int lane) {

@@ -11,6 +11,8 @@
 // Back substitution is one wave per right-hand side.  The system lives in LDS
 // when it fits and in the workspace otherwise.
 #include <algorithm>
+#include <type_traits>
+#include <utility>
 
 #include "ms_internal.h"
 
@@ -172,6 +174,49 @@ __device__ __forceinline__ double group_allsum(double v) {
   return v;
 }
 
+// Square root and reciprocal for the reflector's scalars: a single-precision
+// hardware estimate (v_rsq_f32, v_rcp_f32, relative error near 2^-23; the
+// double-precision estimates have a much longer latency on this chip)
+// refined by Newton's method in double precision: for the reciprocal
+// y <- y + y (1 - x y) twice; for the square root Goldschmidt's coupled
+// iteration g -> sqrt(s), h -> 1 / (2 sqrt(s)) twice, then one residual
+// correction g + h (s - g^2).  Each result is within an ulp or two of the
+// correctly rounded one.  Outside [2^-120, 2^120] (beyond the single-precision
+// range) the library operations are used; the argument is uniform across the
+// wave, so that is a scalar branch.
+__device__ __forceinline__ double qr_sqrt(double s) {
+  if (!(s >= 0x1p-120 && s <= 0x1p120)) return sqrt(s);
+  const double y = (double)__builtin_amdgcn_rsqf((float)s);
+  double g = s * y, h = 0.5 * y;
+  double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  const double d = fma(-g, g, s);
+  return fma(d, h, g);
+}
+__device__ __forceinline__ double qr_rcp(double x) {
+  const double ax = fabs(x);
+  if (!(ax >= 0x1p-120 && ax <= 0x1p120)) return 1.0 / x;
+  double y = (double)__builtin_amdgcn_rcpf((float)x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+
+// f(std::integral_constant<int, I>) for I = 0, ..., N - 1, unrolled.
+template <typename F, int... I>
+__device__ __forceinline__ void qr_static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void qr_static_for(F &&f) {
+  qr_static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
 template <int ROWS>
 struct QrShared {
   double vbuf[2][ROWS];
@@ -253,20 +298,28 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, int nrhs, const double
   // Reflector j from column j, slot col of the owning wave (every group of
   // the wave runs the steps on its own column; only the owner publishes and
   // keeps the result).  With t = |alpha| + ||x||: tau = t / ||x|| and the
-  // scale of v below the diagonal is sign(alpha) / t, from one division.
-  auto build = [&](int j, double(&col)[R]) {
+  // scale of v below the diagonal is sign(alpha) / t, from one product with
+  // the reciprocal of ||x|| t.  Lane gl holds rows gl + GW r: the blocks
+  // r < j / GW lie wholly above row j and r > j / GW wholly below it, so when
+  // the block RJ = j / GW is a compile-time constant only that block needs a
+  // per-lane condition; RJ = -1 is the general form with a condition on every
+  // row.
+  auto build_rows = [&](auto rjc, int j, double(&col)[R]) {
+    constexpr int RJ = decltype(rjc)::value;
     const int og = (j % NG) % GPW;
     const int olane = og * GW;
     const bool own = lane / GW == og;
+    auto below = [&](int r) { return RJ >= 0 ? (r > RJ || (r == RJ && gl + GW * r > j)) : gl + GW * r > j; };
+    auto diag = [&](int r) { return RJ >= 0 ? (r == RJ && gl + GW * r == j) : gl + GW * r == j; };
     double p[NP];
 #pragma unroll
     for (int q = 0; q < NP; ++q) p[q] = 0.0;
     double av = 0.0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const int i = gl + GW * r;
-      if (i > j) p[r % NP] += col[r] * col[r];
-      if (r == j / GW) av = col[r];
+      if (RJ >= 0 && r < RJ) continue;
+      if (below(r)) p[r % NP] += col[r] * col[r];
+      if (RJ >= 0 ? r == RJ : r == j / GW) av = col[r];
     }
     double ps = p[0];
 #pragma unroll
@@ -275,29 +328,46 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, int nrhs, const double
     const double alpha = read_lane(av, olane + j % GW);
     double tau = 0.0, beta = alpha, scal = 0.0;
     if (xn2 != 0.0) {
-      const double nrm = sqrt(alpha * alpha + xn2);
+      const double nrm = qr_sqrt(alpha * alpha + xn2);
       const double tt = fabs(alpha) + nrm;
-      const double qq = 1.0 / (nrm * tt);
+      const double qq = qr_rcp(nrm * tt);
       beta = alpha >= 0.0 ? -nrm : nrm;
       tau = tt * tt * qq;
       scal = (alpha >= 0.0 ? nrm : -nrm) * qq;
     }
     const int buf = j & 1;
     // branch-free: with x = 0 (tau = 0, beta = alpha) the column keeps its
-    // values (scale 1) and v is never used
+    // values (scale 1), and tau = 0 makes every update with v a no-op
     const double sv = xn2 != 0.0 ? scal : 1.0;
     if (own) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int i = gl + GW * r;
+        if (RJ >= 0 && r < RJ) {
+          vbuf[buf][i] = 0.0;
+          continue;
+        }
         const double vi = col[r] * sv;
-        vbuf[buf][i] = i > j ? vi : (i == j ? 1.0 : 0.0);
-        col[r] = i > j ? vi : (i == j ? beta : col[r]);
+        vbuf[buf][i] = below(r) ? vi : (diag(r) ? 1.0 : 0.0);
+        col[r] = below(r) ? vi : (diag(r) ? beta : col[r]);
       }
       if (gl == 0) {
         taubuf[buf] = tau;
         if (tau_out) tau_out[j] = tau;
       }
+    }
+  };
+  // The block index j / GW is uniform across the wave: one compiled form per
+  // block, chosen by a scalar branch, where the look-ahead is unrolled over
+  // few slots.
+  auto build = [&](int j, double(&col)[R]) {
+    if constexpr (S * R <= 16) {
+      const int rj = j / GW;
+      qr_static_for<R>([&](auto rjc) {
+        if (rj == decltype(rjc)::value) build_rows(rjc, j, col);
+      });
+    } else {
+      build_rows(std::integral_constant<int, -1>{}, j, col);
     }
   };
   // whether slot s of this wave holds a column after j (and before nc)
@@ -343,7 +413,7 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, int nrhs, const double
           double v[R];
           load_v(v);
           const double tau = taubuf[j & 1];
-          if (tau != 0.0) apply(j, a[s], s, v, tau);
+          apply(j, a[s], s, v, tau);
           build(jn, a[s]);
         }
       __builtin_amdgcn_s_setprio(0);
@@ -358,11 +428,9 @@ __device__ __forceinline__ void qr_reg_body(int m, int n, int nrhs, const double
       double v[R];
       load_v(v);
       const double tau = taubuf[j & 1];
-      if (tau != 0.0) {
 #pragma unroll
-        for (int s = 0; s < S; ++s)
-          if (!la || s != sn) apply(j, a[s], s, v, tau);
-      }
+      for (int s = 0; s < S; ++s)
+        if (!la || s != sn) apply(j, a[s], s, v, tau);
     }
   }
 
