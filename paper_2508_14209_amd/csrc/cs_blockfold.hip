@@ -82,13 +82,14 @@ __device__ __forceinline__ const T *bf_col(const Cols<T> &c, int j) {
 
 // Fold buckets [m0, m1) of one column col (d rows) into acc (LDS, zero on
 // entry; slot m - m0) over the blocks in order; stage and lkey: LDS for one
-// block's values and keys.  Thread t loads rows 4t .. 4t + 3 of a block (its
+// block's values and keys (two blocks' when DB: the next block is staged while
+// the current one is folded, one barrier per block instead of two).  Thread t loads rows 4t .. 4t + 3 of a block (its
 // values and keys) into registers kBfAhead blocks before the block is folded,
 // so that a block's loads are in flight while the blocks before it are
 // folded.  Ends with the workgroup synchronised.
 constexpr int kBfAhead = 4;
 
-template <typename T>
+template <typename T, bool DB = false>
 __device__ __forceinline__ void bf_fold_column(int64_t d, const T *__restrict__ col,
                                                const uint32_t *__restrict__ keys, uint32_t m0,
                                                uint32_t m1, T *acc, T *stage, uint32_t *lkey) {
@@ -110,80 +111,122 @@ __device__ __forceinline__ void bf_fold_column(int64_t d, const T *__restrict__ 
     }
     kv[j] = gload(reinterpret_cast<const bf_u32x4 *>(keys + r));
   };
+  auto put = [&](int j, T *sg, uint32_t *kg) {
+    *reinterpret_cast<T4 *>(sg + 4 * tid) = v[j];
+    *reinterpret_cast<bf_u32x4 *>(kg + 4 * tid) = kv[j];
+  };
+  // fold the block staged in sg (values) and kg (sorted keys)
+  auto fold = [&](const T *sg, const uint32_t *kg) {
+    // this thread's four positions 4t .. 4t + 3 and the key before them;
+    // the reads of all four runs' sums and first values are issued
+    // together, a run inside the four positions is folded in registers,
+    // and a run that goes on past them continues from LDS
+    const int p0 = 4 * tid;
+    const bf_u32x4 k4 = *reinterpret_cast<const bf_u32x4 *>(kg + p0);
+    const uint32_t kprev = p0 > 0 ? kg[p0 - 1] : kBfPad;
+    uint32_t kq[5] = {kprev, k4[0], k4[1], k4[2], k4[3]};
+    bool start[4];
+    uint32_t mq[4];
+    T a[4], x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      mq[q] = bf_bucket(kq[q + 1]);
+      start[q] = mq[q] >= m0 && mq[q] < m1 && bf_bucket(kq[q]) != mq[q];
+      a[q] = start[q] ? acc[mq[q] - m0] : T(0);
+      x[q] = start[q] ? sg[kq[q + 1] & (kBfRows - 1)] : T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!start[q]) continue;
+      T s = a[q] + apply_sign(x[q], kq[q + 1]);
+      // the run's next rows among this thread's positions (static indices)
+      bool more = true;
+#pragma unroll
+      for (int r = q + 1; r < 4; ++r) {
+        if (more && bf_bucket(kq[r + 1]) == mq[q])
+          s = s + apply_sign(sg[kq[r + 1] & (kBfRows - 1)], kq[r + 1]);
+        else
+          more = false;
+      }
+      if (more) {   // the run may go on into the next threads' positions
+        // four keys per LDS read; their values are read together once the
+        // first of them is known to continue the run, then added in order
+        for (int g = p0 + 4; g < kBfRows; g += 4) {
+          const bf_u32x4 kn = *reinterpret_cast<const bf_u32x4 *>(kg + g);
+          if (bf_bucket(kn[0]) != mq[q]) break;
+          T xn[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) xn[e] = sg[kn[e] & (kBfRows - 1)];
+          bool cont = true;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if (cont && bf_bucket(kn[e]) == mq[q])
+              s = s + apply_sign(xn[e], kn[e]);
+            else
+              cont = false;
+          }
+          if (!cont) break;
+        }
+      }
+      acc[mq[q] - m0] = s;
+    }
+  };
 #pragma unroll
   for (int j = 0; j < kBfAhead; ++j) fetch(j, j);
+  if constexpr (DB) {
+    // two staging buffers: block b + 1 is written while block b is folded,
+    // one barrier per block (the folds of consecutive blocks stay ordered)
+    put(0, stage, lkey);
+    fetch(0, kBfAhead);
+    __syncthreads();   // acc cleared, block 0 staged
+    for (int64_t b0 = 0; b0 < nblk; b0 += kBfAhead) {
+#pragma unroll
+      for (int j = 0; j < kBfAhead; ++j) {
+        const int64_t b = b0 + j;
+        if (b >= nblk) break;
+        const int cur = (int)(b & 1);
+        if (b + 1 < nblk) {
+          const int jn = (j + 1) % kBfAhead;
+          put(jn, stage + (cur ^ 1) * kBfRows, lkey + (cur ^ 1) * kBfRows);
+          fetch(jn, b + 1 + kBfAhead);
+        }
+        fold(stage + cur * kBfRows, lkey + cur * kBfRows);
+        __syncthreads();   // this block folded, the next one staged
+      }
+    }
+    return;
+  }
   for (int64_t b0 = 0; b0 < nblk; b0 += kBfAhead) {
 #pragma unroll
     for (int j = 0; j < kBfAhead; ++j) {
       const int64_t b = b0 + j;
       if (b >= nblk) break;
       __syncthreads();   // acc cleared, or the previous block's runs done with stage and lkey
-      *reinterpret_cast<T4 *>(stage + 4 * tid) = v[j];
-      *reinterpret_cast<bf_u32x4 *>(lkey + 4 * tid) = kv[j];
+      put(j, stage, lkey);
       __syncthreads();
       fetch(j, b + kBfAhead);   // in flight while this block and the next ones are folded
-      // this thread's four positions 4t .. 4t + 3 and the key before them;
-      // the reads of all four runs' sums and first values are issued
-      // together, a run inside the four positions is folded in registers,
-      // and a run that goes on past them continues from LDS
-      const int p0 = 4 * tid;
-      const bf_u32x4 k4 = *reinterpret_cast<const bf_u32x4 *>(lkey + p0);
-      const uint32_t kprev = p0 > 0 ? lkey[p0 - 1] : kBfPad;
-      uint32_t kq[5] = {kprev, k4[0], k4[1], k4[2], k4[3]};
-      bool start[4];
-      uint32_t mq[4];
-      T a[4], x[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        mq[q] = bf_bucket(kq[q + 1]);
-        start[q] = mq[q] >= m0 && mq[q] < m1 && bf_bucket(kq[q]) != mq[q];
-        a[q] = start[q] ? acc[mq[q] - m0] : T(0);
-        x[q] = start[q] ? stage[kq[q + 1] & (kBfRows - 1)] : T(0);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (!start[q]) continue;
-        T s = a[q] + apply_sign(x[q], kq[q + 1]);
-        // the run's next rows among this thread's positions (static indices)
-        bool more = true;
-#pragma unroll
-        for (int r = q + 1; r < 4; ++r) {
-          if (more && bf_bucket(kq[r + 1]) == mq[q])
-            s = s + apply_sign(stage[kq[r + 1] & (kBfRows - 1)], kq[r + 1]);
-          else
-            more = false;
-        }
-        if (more) {   // the run may go on into the next threads' positions
-          int g = p0 + 4;
-          while (g < kBfRows) {
-            const uint32_t kk = lkey[g];
-            if (bf_bucket(kk) != mq[q]) break;
-            s = s + apply_sign(stage[kk & (kBfRows - 1)], kk);
-            ++g;
-          }
-        }
-        acc[mq[q] - m0] = s;
-      }
+      fold(stage, lkey);
     }
   }
   __syncthreads();
 }
 
 // Workgroup (column c, part p) owns buckets [m0, m1) of column c.
-template <typename T>
+template <typename T, bool DB>
 __global__ __launch_bounds__(kBfT) void k_bf_fold(int64_t d, int k, Cols<T> cols, int parts,
                                                   int slots, const uint32_t *__restrict__ keys,
                                                   T *__restrict__ Y, int64_t ldy) {
+  constexpr int NB = DB ? 2 : 1;   // staging buffers
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *acc = reinterpret_cast<T *>(smem_raw);                      // slots
-  T *stage = acc + slots;                                        // kBfRows
-  uint32_t *lkey = reinterpret_cast<uint32_t *>(stage + kBfRows);  // kBfRows
+  T *acc = reinterpret_cast<T *>(smem_raw);                           // slots
+  T *stage = acc + slots;                                             // NB kBfRows
+  uint32_t *lkey = reinterpret_cast<uint32_t *>(stage + NB * kBfRows);  // NB kBfRows
   const int tid = threadIdx.x;
   const int c = blockIdx.x / parts, part = blockIdx.x - (blockIdx.x / parts) * parts;
   const uint32_t m0 = (uint32_t)((int64_t)k * part / parts);
   const uint32_t m1 = (uint32_t)((int64_t)k * (part + 1) / parts);
   for (uint32_t i = tid; i < m1 - m0; i += kBfT) acc[i] = T(0);
-  bf_fold_column<T>(d, bf_col(cols, c), keys, m0, m1, acc, stage, lkey);
+  bf_fold_column<T, DB>(d, bf_col(cols, c), keys, m0, m1, acc, stage, lkey);
   for (uint32_t i = tid; i < m1 - m0; i += kBfT) Y[(m0 + i) + (int64_t)c * ldy] = acc[i];
 }
 
@@ -297,10 +340,10 @@ struct BfShape {
   size_t lds = 0;
 };
 
-BfShape bf_shape(int64_t k, int ncols, size_t elem) {
+BfShape bf_shape(int64_t k, int ncols, size_t elem, int bufs = 1) {
   BfShape s;
   if (k < 1 || k > kBfMaxK || ncols < 1) return s;
-  const size_t fixed = (size_t)kBfRows * (elem + 4);
+  const size_t fixed = (size_t)bufs * kBfRows * (elem + 4);
   const size_t avail = (size_t)dev_info().lds_per_block;
   if (avail <= fixed + 256 * elem) return s;
   const int64_t per = (int64_t)((avail - fixed) / elem);   // bucket sums one workgroup holds
@@ -342,11 +385,20 @@ hipError_t launch_bf_fold(int64_t d, int64_t k, const Cols<T> &c, const uint32_t
                           int64_t ldy, hipStream_t st) {
   const BfShape sh = bf_shape(k, c.ncols, sizeof(T));
   if (!sh.parts) return hipErrorInvalidValue;
-  hipError_t e = allow_dynamic_lds((const void *)k_bf_fold<T>, (int)sh.lds);
+  // two staging buffers when they leave the same workgroup count
+  const BfShape sh2 = bf_shape(k, c.ncols, sizeof(T), 2);
+  const bool db = sh2.parts == sh.parts;
+  const BfShape &u = db ? sh2 : sh;
+  const void *fn = db ? (const void *)k_bf_fold<T, true> : (const void *)k_bf_fold<T, false>;
+  hipError_t e = allow_dynamic_lds(fn, (int)u.lds);
   if (e != hipSuccess) return e;
-  const int64_t grid = (int64_t)c.ncols * sh.parts;
-  hipLaunchKernelGGL(k_bf_fold<T>, dim3((unsigned)grid), dim3(kBfT), sh.lds, st, d, (int)k, c,
-                     sh.parts, sh.slots, keys, Y, ldy);
+  const int64_t grid = (int64_t)c.ncols * u.parts;
+  if (db)
+    hipLaunchKernelGGL((k_bf_fold<T, true>), dim3((unsigned)grid), dim3(kBfT), u.lds, st, d,
+                       (int)k, c, u.parts, u.slots, keys, Y, ldy);
+  else
+    hipLaunchKernelGGL((k_bf_fold<T, false>), dim3((unsigned)grid), dim3(kBfT), u.lds, st, d,
+                       (int)k, c, u.parts, u.slots, keys, Y, ldy);
   return hipGetLastError();
 }
 hipError_t launch_batch_bf_keys(int count, const ms_problem *P, const BatchEntry *E,
