@@ -32,47 +32,61 @@ constexpr uint32_t kBfKeyMask = 0x7fffffffu;  // the (bucket, row) part of a key
 constexpr uint32_t kBfPad = 0x7fffffffu;    // sorts last; its bucket field exceeds every k
 constexpr int64_t kBfMaxK = (int64_t)1 << 19;  // bucket field: bits 12..30
 constexpr int kBfMaxParts = 32;
+static_assert(kBfRows == 4096 && kBfT == 1024, "the key sort (sort4096_lds) takes 4096 keys on 1024 threads");
 
 __device__ __forceinline__ uint32_t bf_bucket(uint32_t key) { return (key & kBfKeyMask) >> 12; }
+
+// Thread t keys rows 4t .. 4t + 3 of the block (q = row within the block):
+// one 16-byte load of h and one 4-byte load of s when the four rows exist
+// and the arrays are aligned for it (vec), else four guarded loads.
+__device__ __forceinline__ void bf_make_keys(int64_t d, int64_t k, const int32_t *__restrict__ h,
+                                             const int8_t *__restrict__ s, int64_t r0, bool vec,
+                                             uint32_t (&v)[4], bool &bad) {
+  const int q0 = 4 * threadIdx.x;
+  const int64_t i0 = r0 + q0;
+  int32_t m[4];
+  int8_t sg[4];
+  if (vec && i0 + 4 <= d) {
+    typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+    const i32x4 hm = gload(reinterpret_cast<const i32x4 *>(h + i0));
+    const int sw = gload(reinterpret_cast<const int *>(s + i0));
+#pragma unroll
+    for (int e = 0; e < 4; ++e) m[e] = hm[e];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sg[e] = (int8_t)(sw >> (8 * e));
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const bool in = i0 + e < d;
+      m[e] = in ? gload(h + i0 + e) : -1;
+      sg[e] = in ? gload(s + i0 + e) : (int8_t)1;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    uint32_t kv = kBfPad;
+    if (i0 + e < d) {
+      const bool ok = ((int64_t)(uint32_t)m[e] < k) & (m[e] >= 0) & ((sg[e] == 1) | (sg[e] == -1));
+      bad |= !ok;
+      if (ok) kv = ((uint32_t)m[e] << 12) | (uint32_t)(q0 + e) | (sg[e] < 0 ? kSignBit : 0u);
+    }
+    v[e] = kv;
+  }
+}
 
 __global__ __launch_bounds__(kBfT) void k_bf_keys(int64_t d, int k, const int32_t *__restrict__ h,
                                                   const int8_t *__restrict__ s,
                                                   uint32_t *__restrict__ keys, int *status) {
-  __shared__ uint32_t key[kBfRows];
-  const int tid = threadIdx.x;
+  __shared__ __align__(16) uint32_t key[kBfRows];
   const int64_t r0 = (int64_t)blockIdx.x * kBfRows;
+  const bool vec = (((uintptr_t)h & 15) | ((uintptr_t)s & 3)) == 0;
   bool bad = false;
-  for (int q = tid; q < kBfRows; q += kBfT) {
-    const int64_t i = r0 + q;
-    uint32_t kv = kBfPad;
-    if (i < d) {
-      const int32_t m = gload(h + i);
-      const int8_t sg = gload(s + i);
-      const bool ok = ((uint32_t)m < (uint32_t)k) & ((sg == 1) | (sg == -1));
-      bad |= !ok;
-      if (ok) kv = ((uint32_t)m << 12) | (uint32_t)q | (sg < 0 ? kSignBit : 0u);
-    }
-    key[q] = kv;
-  }
+  uint32_t v[4];
+  bf_make_keys(d, k, h, s, r0, vec, v, bad);
   if (bad) record_status(status, MS_ERR_RANGE);
-  // bitonic sort of the 4096 keys by their (bucket, row) part
-  for (int size = 2; size <= kBfRows; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      __syncthreads();
-      for (int t = tid; t < kBfRows / 2; t += kBfT) {
-        const int lo = 2 * t - (t & (stride - 1));
-        const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const uint32_t x = key[lo], y = key[hi];
-        if (((x & kBfKeyMask) > (y & kBfKeyMask)) == up) {
-          key[lo] = y;
-          key[hi] = x;
-        }
-      }
-    }
-  }
-  __syncthreads();
-  for (int q = tid; q < kBfRows; q += kBfT) keys[r0 + q] = key[q];
+  // sort the 4096 keys by their (bucket, row) part, store them from registers
+  sort4096_regs(v, key);
+  *reinterpret_cast<uint4 *>(keys + r0 + 4 * threadIdx.x) = make_uint4(v[0], v[1], v[2], v[3]);
 }
 
 template <typename T>
@@ -239,7 +253,7 @@ __global__ __launch_bounds__(kBfT) void k_batch_bf_keys(int count, const ms_prob
                                                         const BatchTotals *__restrict__ tot,
                                                         unsigned char *__restrict__ keyarea,
                                                         int *pstatus, int *status) {
-  __shared__ uint32_t key[kBfRows];
+  __shared__ __align__(16) uint32_t key[kBfRows];
   const int tid = threadIdx.x;
   const int64_t total = tot->bk_items;
   for (int64_t it = blockIdx.x; it < total; it += gridDim.x) {
@@ -249,42 +263,19 @@ __global__ __launch_bounds__(kBfT) void k_batch_bf_keys(int count, const ms_prob
     const int64_t r0 = (it - e.bk_start) * kBfRows;
     const int32_t *h = Q.h;
     const int8_t *s = Q.s;
+    const bool vec = (((uintptr_t)h & 15) | ((uintptr_t)s & 3)) == 0;
     bool bad = false;
-    for (int q = tid; q < kBfRows; q += kBfT) {
-      const int64_t i = r0 + q;
-      uint32_t kv = kBfPad;
-      if (i < Q.d) {
-        const int32_t m = gload(h + i);
-        const int8_t sg = gload(s + i);
-        const bool ok = ((int64_t)(uint32_t)m < Q.k) & (m >= 0) & ((sg == 1) | (sg == -1));
-        bad |= !ok;
-        if (ok) kv = ((uint32_t)m << 12) | (uint32_t)q | (sg < 0 ? kSignBit : 0u);
-      }
-      key[q] = kv;
-    }
+    uint32_t v[4];
+    bf_make_keys(Q.d, Q.k, h, s, r0, vec, v, bad);
     if (bad) {
       record_status(&pstatus[p], MS_ERR_RANGE);
       record_status(status, MS_ERR_RANGE);
     }
-    for (int size = 2; size <= kBfRows; size <<= 1) {
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
-        __syncthreads();
-        for (int t = tid; t < kBfRows / 2; t += kBfT) {
-          const int lo = 2 * t - (t & (stride - 1));
-          const int hi = lo + stride;
-          const bool up = (lo & size) == 0;
-          const uint32_t x = key[lo], y = key[hi];
-          if (((x & kBfKeyMask) > (y & kBfKeyMask)) == up) {
-            key[lo] = y;
-            key[hi] = x;
-          }
-        }
-      }
-    }
-    __syncthreads();
+    // the scratch is reused by the next item: the sort's first LDS phase
+    // stores only each thread's own positions before its barrier
+    sort4096_regs(v, key);
     uint32_t *out = reinterpret_cast<uint32_t *>(keyarea + e.key_off) + r0;
-    for (int q = tid; q < kBfRows; q += kBfT) out[q] = key[q];
-    __syncthreads();   // key is rewritten by the next item
+    *reinterpret_cast<uint4 *>(out + 4 * tid) = make_uint4(v[0], v[1], v[2], v[3]);
   }
 }
 

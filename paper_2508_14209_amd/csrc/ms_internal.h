@@ -505,6 +505,83 @@ __device__ __forceinline__ double wave_allsum(double v) {
   return read_lane(v, 63);
 }
 
+// Ascending sort of 4096 32-bit keys by their low 31 bits (bit 31 is carried
+// along; keys whose low bits are equal must be equal in full, as the padding
+// keys are), by the 1024 threads of a workgroup: a bitonic network run on four
+// keys per thread in registers, thread t holding positions 4t .. 4t + 3 in v
+// on entry and on return.  Strides 1 and 2 stay inside a thread, strides 4 to
+// 128 are exchanges between the lanes of one wave (a wave holds 256
+// consecutive keys), and only strides of 256 and more go through the LDS
+// scratch key (4096 keys, 16-byte aligned), one barrier each.  Every thread
+// reads back only its own positions after the last barrier, so the scratch
+// may be rewritten (own positions first) without another barrier.
+__device__ __forceinline__ void sort4096_regs(uint32_t (&v)[4], uint32_t *key) {
+  constexpr uint32_t M = 0x7fffffffu;
+  const int t = threadIdx.x;
+  for (int size = 2; size <= 4096; size <<= 1) {
+    int stride = size >> 1;
+    if (stride >= 256) {
+      // each thread stores and later reloads only its own four positions, so
+      // the previous phase needs no barrier before the store
+      *reinterpret_cast<uint4 *>(key + 4 * t) = make_uint4(v[0], v[1], v[2], v[3]);
+      __syncthreads();
+      for (; stride >= 256; stride >>= 1) {
+        for (int u = t; u < 2048; u += 1024) {
+          const int lo = 2 * u - (u & (stride - 1));
+          const int hi = lo + stride;
+          const bool up = (lo & size) == 0;
+          const uint32_t x = key[lo], y = key[hi];
+          if (((x & M) > (y & M)) == up) {
+            key[lo] = y;
+            key[hi] = x;
+          }
+        }
+        __syncthreads();
+      }
+      const uint4 q = *reinterpret_cast<const uint4 *>(key + 4 * t);
+      v[0] = q.x;
+      v[1] = q.y;
+      v[2] = q.z;
+      v[3] = q.w;
+    }
+    for (; stride >= 4; stride >>= 1) {
+      const int lm = stride >> 2;   // partner thread t ^ lm, in the same wave
+      const bool lower = (t & lm) == 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const bool up = ((4 * t + i) & size) == 0;
+        const uint32_t o = (uint32_t)__shfl_xor((int)v[i], lm, 64);
+        const bool o_less = (o & M) < (v[i] & M), v_less = (v[i] & M) < (o & M);
+        v[i] = lower == up ? (o_less ? o : v[i]) : (v_less ? o : v[i]);
+      }
+    }
+    for (; stride >= 1; stride >>= 1) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (i & stride) continue;
+        const int j = i | stride;
+        const bool up = ((4 * t + i) & size) == 0;
+        if (((v[i] & M) > (v[j] & M)) == up) {
+          const uint32_t x = v[i];
+          v[i] = v[j];
+          v[j] = x;
+        }
+      }
+    }
+  }
+}
+// The same sort of the 4096 keys held in key (LDS, 16-byte aligned): enter
+// with the workgroup synchronised on key; on return the sorted keys are in
+// key and the workgroup is synchronised.
+__device__ __forceinline__ void sort4096_lds(uint32_t *key) {
+  const int t = threadIdx.x;
+  const uint4 q = *reinterpret_cast<const uint4 *>(key + 4 * t);
+  uint32_t v[4] = {q.x, q.y, q.z, q.w};
+  sort4096_regs(v, key);
+  *reinterpret_cast<uint4 *>(key + 4 * t) = make_uint4(v[0], v[1], v[2], v[3]);
+  __syncthreads();
+}
+
 // cs_tiled.hip -- the CountSketch for bucket counts beyond one workgroup's
 // LDS (k > 16384): a per-call plan grouping each 8192-row block's rows by
 // bucket tile, then one pass in which each tile's workgroups visit only

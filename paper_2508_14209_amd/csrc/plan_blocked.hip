@@ -129,9 +129,10 @@ __global__ __launch_bounds__(kPbT) void k_pb_place(int64_t d, int k, const int32
                                                    const int32_t *__restrict__ off,
                                                    const int32_t *__restrict__ tab,
                                                    uint32_t *__restrict__ sperm) {
-  extern __shared__ int32_t sm[];
+  extern __shared__ __align__(16) int32_t sm[];
   int32_t *lstart = sm;                                          // k
-  uint32_t *key = reinterpret_cast<uint32_t *>(sm + k);          // kPbRows
+  // kPbRows keys, 16-byte aligned (the sort reads and writes four at a time)
+  uint32_t *key = reinterpret_cast<uint32_t *>(sm + ((k + 3) & ~3));
   __shared__ int32_t wsum[16];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t b = blockIdx.x;
@@ -177,23 +178,10 @@ __global__ __launch_bounds__(kPbT) void k_pb_place(int64_t d, int k, const int32
       run += c;
     }
   }
-  // bitonic sort of the 4096 keys (sign bit ignored)
-  for (int size = 2; size <= kPbRows; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      __syncthreads();
-      for (int t = tid; t < kPbRows / 2; t += kPbT) {
-        const int lo = 2 * t - (t & (stride - 1));
-        const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const uint32_t x = key[lo], y = key[hi];
-        if (((x & kPbKeyMask) > (y & kPbKeyMask)) == up) {
-          key[lo] = y;
-          key[hi] = x;
-        }
-      }
-    }
-  }
+  // sort the 4096 keys (sign bit ignored)
+  static_assert(kPbRows == 4096 && kPbT == 1024, "sort4096_lds shape");
   __syncthreads();
+  sort4096_lds(key);
   for (int p = tid; p < kPbRows; p += kPbT) {
     const uint32_t kv = key[p];
     if ((kv & kPbKeyMask) == kPbKeyMask) continue;
@@ -260,7 +248,7 @@ hipError_t launch_plan_blocked(int64_t d, int64_t k, const int32_t *h, const int
   hipLaunchKernelGGL(k_pb_colscan, dim3((unsigned)((k + 63) / 64)), dim3(kPbT), 0, st, nblk, kk,
                      tab, cnt);
   hipLaunchKernelGGL(k_pb_scan, dim3(1), dim3(kPbT), 0, st, kk, (const int32_t *)cnt, off, cursor);
-  const size_t lds4 = (size_t)k * 4 + (size_t)kPbRows * 4;
+  const size_t lds4 = (size_t)((k + 3) & ~3) * 4 + (size_t)kPbRows * 4;
   e = allow_dynamic_lds((const void *)k_pb_place, (int)lds4);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_pb_place, dim3((unsigned)nblk), dim3(kPbT), lds4, st, d, kk, h, s,
