@@ -89,6 +89,97 @@ __global__ __launch_bounds__(kBfT) void k_bf_keys(int64_t d, int k, const int32_
   *reinterpret_cast<uint4 *>(keys + r0 + 4 * threadIdx.x) = make_uint4(v[0], v[1], v[2], v[3]);
 }
 
+// The same keys for k <= kBfCountMaxK, sorted by counting instead of by a
+// network: bucket counts in LDS (the padding keys counted as bucket k), an
+// exclusive scan, each key placed at its bucket's next free slot (an LDS
+// atomic, so equal buckets land in arrival order), then every bucket's few
+// keys put in row order by one thread (insertion sort), which makes the
+// result the same ascending (bucket, row) order as the network's.  A block
+// with a bucket of more than kBfCountMaxRun rows falls back to the network.
+constexpr int kBfCountMaxK = 16384;
+constexpr int kBfCountMaxRun = 64;
+
+size_t bf_count_lds(int64_t k) { return (size_t)(k + 1 + 3) / 4 * 16 + (size_t)kBfRows * 4; }
+
+__global__ __launch_bounds__(kBfT) void k_bf_keys_count(int64_t d, int k,
+                                                        const int32_t *__restrict__ h,
+                                                        const int8_t *__restrict__ s,
+                                                        uint32_t *__restrict__ keys, int *status) {
+  extern __shared__ __align__(16) uint32_t bsm[];
+  __shared__ uint32_t wsum[kBfT / 64];
+  __shared__ int s_long;
+  uint32_t *cnt = bsm;                              // k + 1 counters
+  uint32_t *key = bsm + (k + 1 + 3) / 4 * 4;        // kBfRows keys, 16-byte aligned
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t r0 = (int64_t)blockIdx.x * kBfRows;
+  const bool vec = (((uintptr_t)h & 15) | ((uintptr_t)s & 3)) == 0;
+  for (int m = tid; m <= k; m += kBfT) cnt[m] = 0;
+  if (tid == 0) s_long = 0;
+  bool bad = false;
+  uint32_t v[4];
+  bf_make_keys(d, k, h, s, r0, vec, v, bad);
+  if (bad) record_status(status, MS_ERR_RANGE);
+  auto bucket_of = [&](uint32_t kv) { return min(bf_bucket(kv), (uint32_t)k); };
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 4; ++e) atomicAdd(&cnt[bucket_of(v[e])], 1u);
+  __syncthreads();
+  // exclusive scan of the k + 1 counts, thread t owning a contiguous range
+  const int per = (k + 1 + kBfT - 1) / kBfT;
+  uint32_t loc = 0;
+  for (int q = 0; q < per; ++q) {
+    const int m = tid * per + q;
+    if (m <= k) {
+      loc += cnt[m];
+      if (cnt[m] > (uint32_t)kBfCountMaxRun && m < k) s_long = 1;
+    }
+  }
+  uint32_t incl = loc;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  const bool longrun = s_long != 0;
+  if (longrun) {
+    // a bucket too long for the insertion sort: the network
+    sort4096_regs(v, key);
+    *reinterpret_cast<uint4 *>(keys + r0 + 4 * tid) = make_uint4(v[0], v[1], v[2], v[3]);
+    return;
+  }
+  uint32_t run = incl - loc;
+  for (int u = 0; u < w; ++u) run += wsum[u];
+  for (int q = 0; q < per; ++q) {
+    const int m = tid * per + q;
+    if (m <= k) {
+      const uint32_t c = cnt[m];
+      cnt[m] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 4; ++e) key[atomicAdd(&cnt[bucket_of(v[e])], 1u)] = v[e];
+  __syncthreads();
+  // cnt[m] is now the end of bucket m, cnt[m - 1] its start
+  for (int m = tid; m < k; m += kBfT) {
+    const uint32_t b1 = cnt[m], b0 = m > 0 ? cnt[m - 1] : 0u;
+    for (uint32_t i = b0 + 1; i < b1; ++i) {
+      const uint32_t x = key[i];
+      uint32_t j = i;
+      while (j > b0 && (key[j - 1] & kBfKeyMask) > (x & kBfKeyMask)) {
+        key[j] = key[j - 1];
+        --j;
+      }
+      key[j] = x;
+    }
+  }
+  __syncthreads();
+  *reinterpret_cast<uint4 *>(keys + r0 + 4 * tid) = *reinterpret_cast<const uint4 *>(key + 4 * tid);
+}
+
 template <typename T>
 __device__ __forceinline__ const T *bf_col(const Cols<T> &c, int j) {
   return j < c.n_a ? c.A + (int64_t)j * c.lda : c.B + (int64_t)(j - c.n_a) * c.ldb;
@@ -366,6 +457,14 @@ hipError_t launch_bf_keys(int64_t d, int64_t k, const int32_t *h, const int8_t *
                           int *status, hipStream_t st) {
   if (d < 1 || k < 1 || k > kBfMaxK) return hipErrorInvalidValue;
   const int64_t nblk = (d + kBfRows - 1) / kBfRows;
+  if (k <= kBfCountMaxK) {
+    const size_t lds = bf_count_lds(k);
+    hipError_t e = allow_dynamic_lds((const void *)k_bf_keys_count, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bf_keys_count, dim3((unsigned)nblk), dim3(kBfT), lds, st, d, (int)k, h, s,
+                       keys, status);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_bf_keys, dim3((unsigned)nblk), dim3(kBfT), 0, st, d, (int)k, h, s, keys,
                      status);
   return hipGetLastError();

@@ -9,8 +9,9 @@
 //      first slot each block's rows of that bucket take within the bucket)
 //      and the bucket's total;
 //   3. the exclusive scan of the totals (bucket offsets);
-//   4. per block: its rows sorted by (bucket, row) in LDS (a bitonic
-//      network over 4096 keys), written to offset[bucket] +
+//   4. per block: its rows sorted by (bucket, row) in LDS (counting
+//      placement and a per-bucket insertion sort; a bitonic network over
+//      the 4096 keys when a bucket is long), written to offset[bucket] +
 //      prefix[block][bucket] + rank.
 // Within a bucket, rows of earlier blocks come first and each block's rows
 // ascend: the stable counting sort, with no per-bucket sorting pass.
@@ -120,10 +121,13 @@ __global__ __launch_bounds__(kPbT) void k_pb_scan(int k, const int32_t *__restri
 }
 
 // 4. Block b's rows sorted by (bucket, row) in LDS -- key = bucket << 12 |
-// row offset, the sign in bit 31, absent or invalid rows last -- by a
-// bitonic network over the block's 4096 slots, then each valid row written
-// to off[bucket] + prefix[block][bucket] + its rank within the bucket here.
+// row offset, the sign in bit 31, absent or invalid rows last -- by counting
+// (each key placed at its bucket's next slot, then each bucket's keys put in
+// row order; a block with a bucket of more than kPbMaxRun rows uses a
+// bitonic network instead), then each valid row written to off[bucket] +
+// prefix[block][bucket] + its rank within the bucket here.
 constexpr uint32_t kPbKeyMask = 0x7fffffffu;
+constexpr int kPbMaxRun = 64;   // longest bucket the insertion sort takes
 __global__ __launch_bounds__(kPbT) void k_pb_place(int64_t d, int k, const int32_t *__restrict__ h,
                                                    const int8_t *__restrict__ s,
                                                    const int32_t *__restrict__ off,
@@ -134,12 +138,17 @@ __global__ __launch_bounds__(kPbT) void k_pb_place(int64_t d, int k, const int32
   // kPbRows keys, 16-byte aligned (the sort reads and writes four at a time)
   uint32_t *key = reinterpret_cast<uint32_t *>(sm + ((k + 3) & ~3));
   __shared__ int32_t wsum[16];
+  __shared__ int s_long;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int64_t b = blockIdx.x;
   const int64_t r0 = b * kPbRows, r1 = min(d, r0 + kPbRows);
   for (int m = tid; m < k; m += kPbT) lstart[m] = 0;
+  if (tid == 0) s_long = 0;
   __syncthreads();
-  for (int q = tid; q < kPbRows; q += kPbT) {
+  uint32_t kvr[kPbRows / kPbT];
+#pragma unroll
+  for (int jj = 0; jj < kPbRows / kPbT; ++jj) {
+    const int q = tid + jj * kPbT;
     const int64_t i = r0 + q;
     uint32_t kv = kPbKeyMask;
     if (i < r1) {
@@ -149,6 +158,7 @@ __global__ __launch_bounds__(kPbT) void k_pb_place(int64_t d, int k, const int32
         kv = ((uint32_t)m << 12) | (uint32_t)q | ((s != nullptr && s[i] < 0) ? kSignBit : 0u);
       }
     }
+    kvr[jj] = kv;
     key[q] = kv;
   }
   __syncthreads();
@@ -157,7 +167,10 @@ __global__ __launch_bounds__(kPbT) void k_pb_place(int64_t d, int k, const int32
   int32_t loc = 0;
   for (int q = 0; q < per; ++q) {
     const int m = tid * per + q;
-    if (m < k) loc += lstart[m];
+    if (m < k) {
+      loc += lstart[m];
+      if (lstart[m] > kPbMaxRun) s_long = 1;
+    }
   }
   int32_t incl = loc;
 #pragma unroll
@@ -169,6 +182,7 @@ __global__ __launch_bounds__(kPbT) void k_pb_place(int64_t d, int k, const int32
   __syncthreads();
   int32_t run = incl - loc;
   for (int v = 0; v < w; ++v) run += wsum[v];
+  const bool longrun = s_long != 0;
   __syncthreads();
   for (int q = 0; q < per; ++q) {
     const int m = tid * per + q;
@@ -178,15 +192,48 @@ __global__ __launch_bounds__(kPbT) void k_pb_place(int64_t d, int k, const int32
       run += c;
     }
   }
-  // sort the 4096 keys (sign bit ignored)
   static_assert(kPbRows == 4096 && kPbT == 1024, "sort4096_lds shape");
   __syncthreads();
-  sort4096_lds(key);
+  if (longrun) {
+    // a bucket too long for the insertion sort below: the bitonic network
+    // (sign bit ignored); lstart keeps each bucket's start
+    sort4096_lds(key);
+  } else {
+    // counting placement: each valid key at its bucket's next slot (equal
+    // buckets in arrival order), lstart becoming each bucket's end, then
+    // every bucket's few keys put in row order by one thread; the slots past
+    // the valid keys hold padding
+#pragma unroll
+    for (int jj = 0; jj < kPbRows / kPbT; ++jj) key[tid + jj * kPbT] = kPbKeyMask;
+    __syncthreads();
+#pragma unroll
+    for (int jj = 0; jj < kPbRows / kPbT; ++jj) {
+      const uint32_t kv = kvr[jj];
+      if ((kv & kPbKeyMask) != kPbKeyMask) key[atomicAdd(&lstart[(kv & kPbKeyMask) >> 12], 1)] = kv;
+    }
+    __syncthreads();
+    for (int m = tid; m < k; m += kPbT) {
+      const int b1 = lstart[m], b0 = m > 0 ? lstart[m - 1] : 0;
+      for (int i = b0 + 1; i < b1; ++i) {
+        const uint32_t x = key[i];
+        int jx = i;
+        while (jx > b0 && (key[jx - 1] & kPbKeyMask) > (x & kPbKeyMask)) {
+          key[jx] = key[jx - 1];
+          --jx;
+        }
+        key[jx] = x;
+      }
+    }
+    __syncthreads();
+  }
   for (int p = tid; p < kPbRows; p += kPbT) {
     const uint32_t kv = key[p];
     if ((kv & kPbKeyMask) == kPbKeyMask) continue;
     const int m = (int)((kv & kPbKeyMask) >> 12);
-    const int64_t pos = (int64_t)off[m] + tab[b * k + m] + (p - lstart[m]);
+    // the bucket's first slot in the block: its start (network) or the end
+    // of the bucket before it (counting placement)
+    const int st = longrun ? lstart[m] : (m > 0 ? lstart[m - 1] : 0);
+    const int64_t pos = (int64_t)off[m] + tab[b * k + m] + (p - st);
     sperm[pos] = (uint32_t)(r0 + (kv & 0xfffu)) | (kv & kSignBit);
   }
 }
