@@ -38,6 +38,7 @@ __global__ __launch_bounds__(kPbT) void k_pb_hist(int64_t d, int k, const int32_
   __syncthreads();
   const int64_t r0 = b * kPbRows, r1 = min(d, r0 + kPbRows);
   bool bad = false;
+#pragma unroll 4
   for (int64_t i = r0 + tid; i < r1; i += kPbT) {
     const int32_t m = h[i];
     if ((uint32_t)m < (uint32_t)k)
@@ -59,14 +60,19 @@ __global__ __launch_bounds__(kPbT) void k_pb_colscan(int64_t nblk, int k, int32_
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int m = blockIdx.x * 64 + lane;
   const int64_t b0 = nblk * w / 16, b1 = nblk * (w + 1) / 16;
+  // (the block loops unrolled so that many of their independent loads are
+  // in flight at once)
   int32_t s = 0;
-  if (m < k)
+  if (m < k) {
+#pragma unroll 16
     for (int64_t b = b0; b < b1; ++b) s += tab[b * k + m];
+  }
   ws[w][lane] = s;
   __syncthreads();
   int32_t run = 0;
   for (int v = 0; v < w; ++v) run += ws[v][lane];
   if (m < k) {
+#pragma unroll 16
     for (int64_t b = b0; b < b1; ++b) {
       const int32_t c = tab[b * k + m];
       tab[b * k + m] = run;
