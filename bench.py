@@ -890,7 +890,7 @@ def main():
             ms.bucket_plan(hx, k_, ws=pws)
         ms.check_status(sws)
         ms.check_status(pws)
-        print(json.dumps({"only": args.only, "kernels": "k_bf_keys + k_bf_fold (sketch), k_pb_* (plan)",
+        print(json.dumps({"only": args.only, "kernels": "k_bf_keys_count (k <= 16384; k_bf_keys above) + k_bf_fold (sketch), k_pb_* (plan)",
                           "launches": args.steps + 1,
                           "bytes_per_launch": {"fold": d_ * nc_ * 8 + d_ * 4 + k_ * nc_ * 8,
                                                "plan": d_ * 4 + d_ * 4 + 2 * k_ * 4}}))

@@ -434,11 +434,17 @@ ms_status ms_bucket_plan(int64_t d, int64_t k, const int32_t *h, int32_t *cnt, i
   const size_t o_tab = tab_bytes ? cv.take(tab_bytes) : 0;
   int *status = static_cast<int *>(ws);
   hipError_t e = launch_prologue<int32_t>(status, cnt, k, 1, k, st);
+  if (tab_bytes) {
+    // with no signs given the blocked plan's entries are the row indices
+    // themselves: it writes the permutation in place
+    if (e == hipSuccess)
+      e = launch_plan_blocked(d, k, h, nullptr, cnt, off, at<int32_t>(ws, o_cursor),
+                              at<void>(ws, o_tab), reinterpret_cast<uint32_t *>(perm), status, st);
+    return from_hip(e);
+  }
   if (e == hipSuccess)
-    e = tab_bytes ? launch_plan_blocked(d, k, h, nullptr, cnt, off, at<int32_t>(ws, o_cursor),
-                                        at<void>(ws, o_tab), at<uint32_t>(ws, o_sperm), status, st)
-                  : launch_plan(d, k, h, nullptr, cnt, off, at<int32_t>(ws, o_cursor),
-                                at<uint32_t>(ws, o_sperm), status, st);
+    e = launch_plan(d, k, h, nullptr, cnt, off, at<int32_t>(ws, o_cursor),
+                    at<uint32_t>(ws, o_sperm), status, st);
   if (e == hipSuccess) e = launch_strip_sign(d, at<uint32_t>(ws, o_sperm), perm, st);
   return from_hip(e);
 }
