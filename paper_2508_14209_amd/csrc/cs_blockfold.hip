@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBfT) void k_bf_keys_count(int64_t d, int k,
     const int m = tid * per + q;
     if (m <= k) {
       loc += cnt[m];
-      if (cnt[m] > (uint32_t)kBfCountMaxRun && m < k) s_long = 1;
+      if (cnt[m] > (uint32_t)kBfCountMaxRun && m < k) atomicOr(&s_long, 1);
     }
   }
   uint32_t incl = loc;

@@ -175,7 +175,7 @@ __global__ __launch_bounds__(kPbT) void k_pb_place(int64_t d, int k, const int32
     const int m = tid * per + q;
     if (m < k) {
       loc += lstart[m];
-      if (lstart[m] > kPbMaxRun) s_long = 1;
+      if (lstart[m] > kPbMaxRun) atomicOr(&s_long, 1);
     }
   }
   int32_t incl = loc;
